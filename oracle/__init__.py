@@ -1,0 +1,232 @@
+"""Python front of the FP64 CPU oracle (test infrastructure).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg use
+this package. It compiles ``rod_oracle.cpp`` with g++ (plain C++17, OpenMP over
+independent rows, no FMA contraction) and calls it through ctypes. Nothing here
+is shared with, or imported by, the GPU library.
+
+Arrays cross in the workload's own layout: AoS ``[N, 3]`` / ``[N, 4]`` float64.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rod_oracle.cpp")
+_LIB = os.path.join(_HERE, "librod_oracle.so")
+_lib = None
+
+BOND, DIPOLE, ZEEMAN, CONTACT, DAMP, EXT, ALL = 1, 2, 4, 8, 16, 32, 63
+ENERGY_TERMS = ("stretch", "shear", "twist", "bend", "zeeman", "dipole", "contact",
+                "kinetic", "rotational")
+
+
+def build(force=True):
+    """Compile the oracle library in place."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
+           "-shared", _SRC, "-o", tmp]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _System(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("n_rods", C.c_int32), ("n_members", C.c_int32),
+        ("rod_offset", C.c_void_p), ("rod_member", C.c_void_p),
+        ("rod_params", C.c_void_p), ("x_ref", C.c_void_p), ("bc", C.c_void_p),
+        ("drive_axis", C.c_double * 3), ("drive_period", C.c_int64),
+        ("field_len", C.c_int32), ("ext_force", C.c_void_p), ("ext_torque", C.c_void_p),
+        ("dt", C.c_double), ("damping", C.c_double), ("mu0_4pi", C.c_double),
+        ("k_contact", C.c_double), ("r_contact", C.c_double),
+        ("dipole_on", C.c_int32), ("contact_on", C.c_int32), ("exclude_depth", C.c_int32),
+    ]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = C.CDLL(_LIB)
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+class System:
+    """ctypes view of a workload dict; keeps every array alive while in use."""
+
+    def __init__(self, w):
+        self.w = w
+        self.n = int(w["n"])
+        keep = dict(
+            rod_offset=np.ascontiguousarray(w["rod_offset"], dtype=np.int32),
+            rod_member=np.ascontiguousarray(w["rod_member"], dtype=np.int32),
+            rod_params=_f64(w["rod_params"]),
+            x_ref=_f64(w["x_ref"]),
+            bc=np.ascontiguousarray(w["bc"], dtype=np.int8),
+            field=_f64(w["field"]),
+            ext_force=None if w.get("ext_force") is None else _f64(w["ext_force"]),
+            ext_torque=None if w.get("ext_torque") is None else _f64(w["ext_torque"]),
+        )
+        self.keep = keep
+        s = _System()
+        s.n = self.n
+        s.n_rods = len(keep["rod_member"])
+        s.n_members = int(w["n_members"])
+        s.rod_offset = _p(keep["rod_offset"])
+        s.rod_member = _p(keep["rod_member"])
+        s.rod_params = _p(keep["rod_params"])
+        s.x_ref = _p(keep["x_ref"])
+        s.bc = _p(keep["bc"])
+        s.drive_axis = (C.c_double * 3)(*[float(a) for a in w["drive_axis"]])
+        s.drive_period = int(w["drive_period"])
+        s.field_len = int(keep["field"].shape[0])
+        s.ext_force = _p(keep["ext_force"])
+        s.ext_torque = _p(keep["ext_torque"])
+        s.dt = float(w["dt"]); s.damping = float(w["damping"]); s.mu0_4pi = float(w["mu0_4pi"])
+        s.k_contact = float(w["k_contact"]); s.r_contact = float(w["r_contact"])
+        s.dipole_on = int(bool(w["dipole_on"])); s.contact_on = int(bool(w["contact_on"]))
+        s.exclude_depth = int(w["exclude_depth"])
+        self.s = s
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+    @property
+    def field(self):
+        return self.keep["field"]
+
+
+def bonds(w):
+    """Topology: (ij [B,2] int32, rref [B,3], K [B,4] = K_r, K_s, K_t, K_b)."""
+    lib = _load()
+    sy = System(w)
+    cap = max(sy.n, 1)
+    ij = np.zeros((cap, 2), np.int32)
+    rr = np.zeros((cap, 3))
+    K = np.zeros((cap, 4))
+    lib.orc_bonds.restype = C.c_int
+    B = lib.orc_bonds(sy.ref, _p(ij), _p(rr), _p(K), C.c_int(cap))
+    return ij[:B].copy(), rr[:B].copy(), K[:B].copy()
+
+
+def mass(w):
+    lib = _load()
+    sy = System(w)
+    m = np.zeros(sy.n)
+    I = np.zeros(sy.n)
+    lib.orc_mass(sy.ref, _p(m), _p(I))
+    return m, I
+
+
+def bond_single(x1, x2, q1, q2, rref, K):
+    """One bond: returns (F on particle 1, tau_s, tau_b + tau_t on particle 1, energies[4])."""
+    lib = _load()
+    a = [_f64(v) for v in (x1, x2, q1, q2, rref, K)]
+    F, Ts, Tbt, e = np.zeros(3), np.zeros(3), np.zeros(3), np.zeros(4)
+    lib.orc_bond_single(*[_p(v) for v in a], _p(F), _p(Ts), _p(Tbt), _p(e))
+    return F, Ts, Tbt, e
+
+
+def forces(w, x, q, v=None, om=None, mbody=None, step=0, mask=ALL, with_field=False):
+    """Force and torque [N,3] of the terms in ``mask`` at the given state."""
+    lib = _load()
+    sy = System(w)
+    n = sy.n
+    x = _f64(x, (n, 3)); q = _f64(q, (n, 4))
+    v = np.zeros((n, 3)) if v is None else _f64(v, (n, 3))
+    om = np.zeros((n, 3)) if om is None else _f64(om, (n, 3))
+    mb = _f64(w["m_body"] if mbody is None else mbody, (n, 3))
+    F, T, B = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 3))
+    lib.orc_forces(sy.ref, _p(x), _p(q), _p(v), _p(om), _p(mb), _p(sy.field),
+                   C.c_int64(step), C.c_int32(mask), _p(F), _p(T), _p(B))
+    return (F, T, B) if with_field else (F, T)
+
+
+def energy(w, x, q, v=None, om=None, mbody=None, step=0):
+    """Energies [M, 9] (see ENERGY_TERMS)."""
+    lib = _load()
+    sy = System(w)
+    n = sy.n
+    x = _f64(x, (n, 3)); q = _f64(q, (n, 4))
+    v = np.zeros((n, 3)) if v is None else _f64(v, (n, 3))
+    om = np.zeros((n, 3)) if om is None else _f64(om, (n, 3))
+    mb = _f64(w["m_body"] if mbody is None else mbody, (n, 3))
+    out = np.zeros((int(w["n_members"]), 9))
+    lib.orc_energy(sy.ref, _p(x), _p(q), _p(v), _p(om), _p(mb), _p(sy.field),
+                   C.c_int64(step), _p(out))
+    return out
+
+
+def contact_pairs(w, x):
+    """Sorted contact pairs (i < j) [P, 2] int32 by brute force."""
+    lib = _load()
+    sy = System(w)
+    x = _f64(x, (sy.n, 3))
+    lib.orc_contact_pairs.restype = C.c_int
+    cnt = lib.orc_contact_pairs(sy.ref, _p(x), None, C.c_int(0))
+    out = np.zeros((max(cnt, 1), 2), np.int32)
+    lib.orc_contact_pairs(sy.ref, _p(x), _p(out), C.c_int(cnt))
+    return out[:cnt].copy()
+
+
+def run(w, nsteps, state=None, step0=0, mbody=None):
+    """Advance a workload. ``state`` (dict x, v, q, w, F, T) continues a previous
+    run; otherwise the initial state is prepared from x0, v0, q0, w0.
+    Returns the new state dict (AoS arrays) with its step index."""
+    lib = _load()
+    sy = System(w)
+    n = sy.n
+    if state is None:
+        st = dict(x=_f64(w["x0"]).copy(), v=_f64(w["v0"]).copy(), q=_f64(w["q0"]).copy(),
+                  w=_f64(w["w0"]).copy(), F=np.zeros((n, 3)), T=np.zeros((n, 3)), step=step0)
+        prepared = 0
+    else:
+        st = {k: (np.array(v, dtype=np.float64, copy=True) if k != "step" else v)
+              for k, v in state.items()}
+        prepared = 1
+    mb = _f64(w["m_body"] if mbody is None else mbody, (n, 3))
+    lib.orc_run(sy.ref, _p(st["x"]), _p(st["v"]), _p(st["q"]), _p(st["w"]), _p(st["F"]),
+                _p(st["T"]), _p(mb), _p(sy.field), C.c_int64(int(st["step"])),
+                C.c_int64(int(nsteps)), C.c_int32(prepared))
+    st["step"] = int(st["step"]) + int(nsteps)
+    return st
+
+
+def run_jvp(w, nsteps, tangent, step0=0):
+    """Forward-mode derivative of ``run`` from the raw initial inputs.
+
+    ``tangent`` maps any of x0, v0, q0, w0, m_body, field to a direction array.
+    Returns (final state dict, final tangent dict) with keys x, v, q, w."""
+    lib = _load()
+    sy = System(w)
+    n = sy.n
+    ins = [_f64(w[k]) for k in ("x0", "v0", "q0", "w0", "m_body")] + [sy.field]
+    dins = [None if tangent.get(k) is None else _f64(tangent[k], np.shape(a))
+            for k, a in zip(("x0", "v0", "q0", "w0", "m_body", "field"), ins)]
+    out = [np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 4)), np.zeros((n, 3))]
+    dout = [np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 4)), np.zeros((n, 3))]
+    lib.orc_run_jvp(sy.ref, *[_p(a) for a in ins], *[_p(a) for a in dins],
+                    C.c_int64(step0), C.c_int64(int(nsteps)),
+                    _p(out[0]), _p(out[1]), _p(out[2]), _p(out[3]),
+                    _p(dout[0]), _p(dout[1]), _p(dout[2]), _p(dout[3]))
+    keys = ("x", "v", "q", "w")
+    return dict(zip(keys, out)), dict(zip(keys, dout))
