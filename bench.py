@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Benchmark of the rod force-and-integrate loop on one MI355X.
+
+Default workload: the twisted clamped-clamped rod, N = 4096 particles, driven
+end, Hookean contact through the cell list, all-pairs dipoles, mixed path
+(FP32 pair/bond arithmetic, FP64 state and sums), steps replayed from captured
+HIP graphs. A step is one full pass of the loop (integrate, bonds, dipoles,
+contact, gather and kick) over all particles.
+
+Prints one JSON line: throughput in particle-steps/s (inputs resident in HBM),
+dipole pair-evaluations/s, the roofline of the dominant (dipole) kernel timed
+with HIP events on the library's stream, and the FP64 CPU oracle timed on a
+bounded sample of the same workload on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_PAIR = 67.0        # algorithmic FP32 flops per ordered dipole pair (FMA = 2)
+FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector peak (vendor figure)
+METRIC = "particle-steps/s and dipole pair-evals/s (% FP32 peak); adjoint/forward time"
+
+WORKLOADS = {
+    "twisted_rod": "twisted clamped-clamped rod, N=4096, contact + all-pairs dipoles",
+    "cilia_carpet": "cilia carpet, 1024 rods on 32x32 grid, ~73.7k particles",
+    "rod_array": "rod array, 512 rods x 512 particles = 262,144, field sweep",
+    "ensemble": "ensemble, 64 members x 4096-particle rods",
+    "cantilever": "cantilever, 20 particles, FP64",
+    "adjoint_rod": "adjoint rod, N=256, FP64",
+}
+
+
+def ordered_pairs(w):
+    off = np.asarray(w["rod_offset"])
+    mem = np.asarray(w["rod_member"])
+    sizes = np.zeros(int(w["n_members"]), dtype=np.int64)
+    np.add.at(sizes, mem, np.diff(off))
+    return int(np.sum(sizes * (sizes - 1)))
+
+
+def cpu_baseline(w, target_s=15.0):
+    """The FP64 oracle on a bounded number of steps of the same workload."""
+    import ctypes
+    import oracle
+    lib = oracle._load()
+    n = w["n"]
+    t0 = time.perf_counter()
+    st = oracle.run(w, 0)                   # prepare (includes one force evaluation)
+    t_prep = time.perf_counter() - t0
+    k = int(max(1, min(w["steps"], target_s / max(t_prep, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.run(w, k, state=st)
+    dt = time.perf_counter() - t0
+    lib.orc_threads.restype = ctypes.c_int
+    cores = int(lib.orc_threads())
+    return {"value": n * k / dt, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{k} steps of the same workload (N={n}) from its initial state, FP64, "
+                      f"{dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="twisted_rod", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--graph-steps", type=int, default=50)
+    ap.add_argument("--timing-steps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_2603_27279_amd import RodSim
+
+    w = workloads.make(args.workload)
+    prec = args.precision or w["precision"]
+    n = w["n"]
+    pairs = ordered_pairs(w) if w["dipole_on"] else 0
+
+    sim = RodSim(w, precision=prec, graph_steps=args.graph_steps)
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    secs = t1 - t0
+    ms_step = 1e3 * secs / args.steps
+    value = n * args.steps / secs
+
+    # Kernel durations: HIP events around each launch, on the library's stream.
+    sim.timing(True)
+    sim.step(args.timing_steps)
+    kt = sim.kernel_times()
+    sim.timing(False)
+    sim.sync()
+    kernels_us = {k: (1e3 * ms / c if c else None) for k, (ms, c) in kt.items()}
+    roof = None
+    if pairs and kt["dipole"][1]:
+        t_dip = 1e-3 * kt["dipole"][0] / kt["dipole"][1]
+        achieved = FLOP_PER_PAIR * pairs / t_dip / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                "kernel": "k_dipole<float>" if prec == "mixed" else "k_dipole<double>",
+                "pair_evals_per_s": pairs / t_dip,
+                "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": pairs}
+    sim.free()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_seconds)
+        cpu["value"] = float(cpu["value"])
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair/bond arithmetic, f64 state and sums" if prec == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "n_particles": n,
+                   "ordered_dipole_pairs_per_step": pairs, "precision": prec,
+                   "graph_steps": args.graph_steps},
+        "pair_evals_per_s": pairs * args.steps / secs if pairs else None,
+        "kernel_us": kernels_us,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/* rod.h - C ABI of the MI355X (gfx950) library for the per-timestep
+ * force-and-integrate loop of the bonded-particle model of magneto-elastic rods.
+ *
+ * One time step of the loop (paper, SI "Equations of motion"):
+ *   v(t+dt/2) = v + dt/2 f/m,  x(t+dt) = x + dt v(t+dt/2),
+ *   w(t+dt/2) = w + dt/2 tau/I, q(t+dt) by Richardson extrapolation of
+ *   dq/dt = 1/2 (0, w) q with renormalisation after every substep;
+ *   forces at t+dt; v(t+dt) = v(t+dt/2) + dt/2 f/m, w likewise.
+ * The forces are the sum of
+ *   - bonds: central-frame decomposition into stretch, shear, twist and bend
+ *     (main text eq:bpm-fr, eq:bpm-fst, eq:bpm-tst, eq:bpm-tb, eq:bpm-tt,
+ *     eq:bpm-vector; SI "Symmetric rotational decomposition"), spring
+ *     constants K_r = EA/L, K_s = 12EI/L^3, K_t = GJ/L, K_b = EI/L;
+ *   - dipoles that rotate with their particle (m = R(q) m_body, section on
+ *     magnetised beams): Zeeman force grad(m.B) and torque m x B, and the
+ *     all-pairs dipole-dipole force and torque within an ensemble member
+ *     (Methods, "Magnetic interactions"), open boundaries, no cutoff;
+ *   - Hookean normal contact k (r_c - r) between pairs closer than r_c that
+ *     are not bonded within `exclude_depth` (Methods, "Contact"), found with a
+ *     hashed cell list;
+ *   - global viscous damping -c m v, -c I w with the half-step velocities;
+ *   - optional constant external forces and torques.
+ *
+ * Conventions
+ *   - All device arrays are structure-of-arrays (SoA) planes of length N:
+ *     a "[3N]" vector array holds x-components [0,N), y [N,2N), z [2N,3N);
+ *     quaternions "[4N]" hold the planes w, x, y, z (Hamilton product,
+ *     active rotation v' = q v q*).
+ *   - Particles of a rod are contiguous; consecutive particles of a rod are
+ *     bonded; rods of a member are contiguous; members never interact.
+ *   - Every function returns ROD_OK (0) or a negative error code and never
+ *     throws; rod_last_error() returns a message for the calling thread.
+ *   - Work is enqueued on the stream given to rod_init; functions that return
+ *     host data synchronise that stream first.
+ *   - The library keeps non-owning pointers to the caller's device buffers:
+ *     they must stay valid until rod_free. It allocates its own workspace.
+ */
+#ifndef ROD_H
+#define ROD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ROD_OK = 0,
+  ROD_E_INVALID = -1,   /* bad argument or descriptor */
+  ROD_E_HIP = -2,       /* a HIP runtime call failed */
+  ROD_E_NONFINITE = -3, /* a force, position or quaternion became NaN/inf */
+  ROD_E_NOTAPE = -4,    /* rod_grad without a recorded forward run */
+  ROD_E_OVERFLOW = -5,  /* contact search capacity exceeded */
+  ROD_E_STATE = -6      /* call not valid in the current context state */
+};
+
+enum { ROD_FP64 = 0, ROD_MIXED = 1 };
+
+/* Force terms, as a bitmask for rod_eval_forces. */
+enum {
+  ROD_TERM_BOND = 1, ROD_TERM_DIPOLE = 2, ROD_TERM_ZEEMAN = 4,
+  ROD_TERM_CONTACT = 8, ROD_TERM_DAMP = 16, ROD_TERM_EXT = 32, ROD_TERM_ALL = 63
+};
+
+/* Boundary condition of a particle. */
+enum { ROD_BC_FREE = 0, ROD_BC_CLAMPED = 1, ROD_BC_DRIVEN = 2 };
+
+/* Host-side description; copied by rod_init (the caller may free it after). */
+typedef struct rod_desc {
+  int32_t n_particles;        /* N >= 1 */
+  int32_t n_rods;             /* R >= 1 */
+  int32_t n_members;          /* M >= 1 */
+  const int32_t* rod_offset;  /* host [R+1], strictly increasing, [0] = 0, [R] = N */
+  const int32_t* rod_member;  /* host [R], non-decreasing, values 0..M-1, every member used */
+  const double* rod_params;   /* host [R][4]: diameter d > 0, density > 0, Young E > 0, Poisson nu > -1 */
+  const double* x_ref;        /* host [N][3] (AoS): reference lattice; bond k has r_i = x_ref[k+1]-x_ref[k],
+                                 reference orientations are the identity */
+  const int8_t* bc;           /* host [N]: ROD_BC_* */
+  double drive_axis[3];       /* unit axis of driven particles */
+  int64_t drive_period;       /* steps per turn of driven particles: q(n) = R(axis, 2 pi n / P); 0 = none */
+  int32_t field_len;          /* L >= 1 rows of the field table (row n mod L is used at time level n) */
+  double dt;                  /* time step > 0 */
+  double damping;             /* global viscous damping c >= 0 */
+  double mu0_4pi;             /* dipole prefactor mu0 / 4 pi */
+  double k_contact;           /* contact stiffness */
+  double r_contact;           /* contact distance r_c > 0 (also the cell size) */
+  int32_t dipole_on;          /* 0 / 1 */
+  int32_t contact_on;         /* 0 / 1 */
+  int32_t exclude_depth;      /* same-rod pairs with |i - j| <= depth never contact (>= 0) */
+  int32_t precision;          /* ROD_FP64 or ROD_MIXED (FP32 pair/bond arithmetic, FP64 state and sums) */
+  int64_t step0;              /* time level of the initial state */
+  int32_t graph_steps;        /* steps per captured HIP graph; 0 = launch eagerly */
+  int32_t tape_every;         /* checkpoint interval for rod_grad (0 = no gradient support) */
+  int32_t tape_capacity;      /* maximum number of steps rod_grad can reverse (0 = no tape) */
+} rod_desc;
+
+/* Caller-owned device buffers (SoA, float64). */
+typedef struct rod_buffers {
+  double* x;                  /* [3N] positions, updated in place */
+  double* v;                  /* [3N] velocities */
+  double* q;                  /* [4N] orientations (normalised by rod_init) */
+  double* w;                  /* [3N] angular velocities (space frame) */
+  double* force;              /* [3N] total force of the current time level (part of the state) */
+  double* torque;             /* [3N] total torque of the current time level */
+  const double* m_body;       /* [3N] body-frame dipole moments */
+  const double* field;        /* [L][M][12] rows: B0 (3), G (3x3 row-major); B(x) = B0 + G x */
+  const double* ext_force;    /* [3N] or NULL */
+  const double* ext_torque;   /* [3N] or NULL */
+} rod_buffers;
+
+typedef struct rod_ctx rod_ctx; /* opaque; owned by the library, released by rod_free */
+
+/* Bytes of device workspace rod_init would allocate for this description. */
+int rod_query_workspace(const rod_desc* d, size_t* bytes);
+
+/* Validate `d`, build the topology (bonds, spring constants, masses) and the
+ * workspace, normalise q, impose the boundary conditions of level step0 and,
+ * unless `forces_valid` is non-zero, evaluate force/torque of that level into
+ * the caller's buffers. `hip_stream` is a hipStream_t (NULL = default stream).
+ * On error *out is set to NULL. */
+int rod_init(rod_ctx** out, const rod_desc* d, const rod_buffers* b, void* hip_stream,
+             int32_t forces_valid);
+
+/* Advance n_steps >= 0 time steps (asynchronous on the stream). When the
+ * context records a tape, at most tape_capacity steps may follow rod_tape_begin. */
+int rod_step(rod_ctx* c, int64_t n_steps);
+
+/* Current time level (synchronises). */
+int rod_get_step(rod_ctx* c, int64_t* step);
+
+/* Wait for the stream and report device-side error flags (non-finite state,
+ * contact capacity overflow) raised since the last check. */
+int rod_sync(rod_ctx* c);
+
+/* Evaluate the selected force terms (ROD_TERM_* mask) at the current state
+ * into device buffers F[3N] and T[3N]; damping uses the current v and w; the
+ * field row is that of the current level. Does not change the state.
+ * B_dip (device [3N] or NULL) receives the dipole field at each particle. */
+int rod_eval_forces(rod_ctx* c, int32_t terms, double* F, double* T, double* B_dip);
+
+/* Energies per member, 9 doubles each: stretch, shear, twist, bend
+ * (eq:total-energy), Zeeman -m.B, dipole-dipole, contact 1/2 k (r_c - r)^2,
+ * translational and rotational kinetic energy. `out` is [M][9]; host memory
+ * (synchronises) when out_on_device = 0, device memory otherwise. */
+int rod_energy(rod_ctx* c, double* out, int32_t out_on_device);
+
+/* Bond topology as built (host outputs, each may be NULL): ij [cap][2] particle
+ * pairs, rref [cap][3] reference vectors, K [cap][4] = K_r, K_s, K_t, K_b.
+ * *count receives the number of bonds; at most cap entries are written. */
+int rod_topology(rod_ctx* c, int32_t* ij, double* rref, double* K, int32_t cap, int32_t* count);
+
+/* Contact pairs (i < j, ascending) found by the cell list at the current state
+ * (host output, synchronises); *count receives the total, at most cap written. */
+int rod_contact_pairs(rod_ctx* c, int32_t* pairs, int32_t cap, int32_t* count);
+
+/* Gradient support (reverse mode through recorded steps).
+ * rod_tape_begin marks the current state as the start of the recorded run
+ * (and stores it as the first checkpoint); subsequent rod_step calls record
+ * checkpoints every tape_every steps, up to tape_capacity steps. */
+int rod_tape_begin(rod_ctx* c);
+
+typedef struct rod_cotangent {  /* device [3N]/[4N] cotangents of the final state; NULL = zero */
+  const double* x; const double* v; const double* q; const double* w;
+} rod_cotangent;
+
+typedef struct rod_gradients {  /* device outputs (overwritten); NULL = not wanted */
+  double* m_body;               /* [3N] */
+  double* field;                /* [L][M][12] */
+  double* x0; double* v0; double* q0; double* w0;  /* [3N], [3N], [4N] (raw q0), [3N] */
+} rod_gradients;
+
+/* Reverse the recorded steps: given cotangents of the state at the end of the
+ * recorded run, write the gradients with respect to the body dipoles, the
+ * field table and the state at rod_tape_begin (q0 taken before the
+ * normalisation rod_init applies when the tape starts at rod_init's state).
+ * The forward state is not changed. Returns ROD_E_NOTAPE without a tape. */
+int rod_grad(rod_ctx* c, const rod_cotangent* gy, rod_gradients* gx);
+
+/* Kernel timing with HIP events on the library's own stream.
+ * While enabled (enable != 0), rod_step launches every step eagerly (no graph)
+ * and brackets each kernel launch with a pair of events. rod_kernel_times
+ * synchronises, adds up the elapsed time of all bracketed launches since the
+ * last read per kernel class and resets the sums: ms[ROD_KERNEL_COUNT]
+ * (milliseconds) and launches[ROD_KERNEL_COUNT] (host arrays, may be NULL). */
+enum {
+  ROD_KERNEL_PRE = 0,     /* half-kick, drift, quaternion update, dipole rotation, cell list */
+  ROD_KERNEL_BOND = 1,    /* bond forces and torques */
+  ROD_KERNEL_DIPOLE = 2,  /* all-pairs dipole-dipole */
+  ROD_KERNEL_CONTACT = 3, /* cell-list contact */
+  ROD_KERNEL_POST = 4,    /* force gather, Zeeman, damping, second half-kick */
+  ROD_KERNEL_COUNT = 5
+};
+int rod_timing(rod_ctx* c, int32_t enable);
+int rod_kernel_times(rod_ctx* c, double* ms, int64_t* launches);
+
+/* Release the context and its workspace (synchronises). NULL is accepted. */
+int rod_free(rod_ctx* c);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* rod_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ROD_H */

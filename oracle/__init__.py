@@ -230,3 +230,16 @@ def run_jvp(w, nsteps, tangent, step0=0):
                     _p(dout[0]), _p(dout[1]), _p(dout[2]), _p(dout[3]))
     keys = ("x", "v", "q", "w")
     return dict(zip(keys, out)), dict(zip(keys, dout))
+
+
+def rows(w, x, q, rows, mbody=None):
+    """Dipole force, dipole field and contact force [len(rows), 3] of selected particles."""
+    lib = _load()
+    sy = System(w)
+    n = sy.n
+    x = _f64(x, (n, 3)); q = _f64(q, (n, 4))
+    mb = _f64(w["m_body"] if mbody is None else mbody, (n, 3))
+    r = np.ascontiguousarray(rows, dtype=np.int32)
+    F, B, Fc = np.zeros((len(r), 3)), np.zeros((len(r), 3)), np.zeros((len(r), 3))
+    lib.orc_rows(sy.ref, _p(x), _p(q), _p(mb), _p(r), C.c_int32(len(r)), _p(F), _p(B), _p(Fc))
+    return F, B, Fc

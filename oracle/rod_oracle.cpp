@@ -45,6 +45,9 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace orc {
 
@@ -715,6 +718,53 @@ void orc_run_jvp(const orc_system* s, const double* x0, const double* v0, const 
     wT[k] = st.w[k].v; dwT[k] = st.w[k].d;
   }
   for (int k = 0; k < 4 * N; ++k) { qT[k] = st.q[k].v; dqT[k] = st.q[k].d; }
+}
+
+// Dipole force, dipole field and contact force of selected particles only, by
+// the same direct sums over their member (for spot checks of large systems).
+void orc_rows(const orc_system* s, const double* x, const double* q, const double* mbody,
+              const int32_t* rows, int32_t nrows, double* Fdip, double* Bdip, double* Fc) {
+  Model md = build_model(s);
+  std::vector<double> mu;
+  dipoles(md, q, mbody, mu);
+  const double C = md.C, rc2 = md.rc * md.rc;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k < nrows; ++k) {
+    const int i = rows[k];
+    const int mem = md.member_of[i];
+    V3<double> xi = ld3(x, i), mi = ld3(mu.data(), i);
+    V3<double> Fi{0, 0, 0}, Bi{0, 0, 0}, Fci{0, 0, 0};
+    for (int j = md.member_begin[mem]; j < md.member_end[mem]; ++j) {
+      if (j == i) continue;
+      V3<double> r = xi - ld3(x, j);
+      if (md.dipole_on) {
+        V3<double> mj = ld3(mu.data(), j);
+        double r2 = dot(r, r);
+        double rinv = 1.0 / std::sqrt(r2);
+        double rinv3 = rinv * rinv * rinv, rinv5 = rinv3 * rinv * rinv;
+        double a = dot(mi, r), b = dot(mj, r), cmm = dot(mi, mj);
+        Fi = Fi + (3.0 * C * rinv5) * ((cmm * r + b * mi + a * mj) - (5.0 * a * b * rinv * rinv) * r);
+        Bi = Bi + (3.0 * C * b * rinv5) * r - (C * rinv3) * mj;
+      }
+      if (md.contact_on && !excluded(md, i, j)) {
+        double r2 = (r.x * r.x + r.y * r.y) + r.z * r.z;
+        if (r2 < rc2) {
+          double rr = std::sqrt(r2);
+          Fci = Fci + (md.kc * (md.rc - rr) / rr) * r;
+        }
+      }
+    }
+    st3(Fdip, k, Fi); st3(Bdip, k, Bi); st3(Fc, k, Fci);
+  }
+}
+
+// Threads the OpenMP loops of this library use.
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 }  // extern "C"

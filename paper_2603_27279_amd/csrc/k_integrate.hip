@@ -1,0 +1,264 @@
+// Per-particle kernels of the time step: the first half-kick / drift / Richardson
+// quaternion update with boundary conditions and dipole rotation (pre), and the
+// force gather with Zeeman, damping and external terms followed by the second
+// half-kick (post). SI "Equations of motion"; dipoles rotate with the particle
+// (main text, magnetised beams); Zeeman force and torque (Methods).
+#include "rod_internal.h"
+#include "rod_math.h"
+
+namespace rodmx {
+
+// dq/dt = 1/2 (0, w) q for a space-frame angular velocity w.
+__device__ __forceinline__ Q4<double> q_rate(Q4<double> q, V3<double> w) {
+  return qscale(0.5, qmul(Q4<double>{0.0, w.x, w.y, w.z}, q));
+}
+
+// Richardson extrapolation of one full step against two half steps, each
+// intermediate renormalised: q(t+dt) = N(2 q2 - q1).
+__device__ __forceinline__ Q4<double> richardson(Q4<double> q, V3<double> w, double dt) {
+  Q4<double> rq = q_rate(q, w);
+  Q4<double> q1 = qnormalize(qadd(q, qscale(dt, rq)));
+  Q4<double> qh = qnormalize(qadd(q, qscale(0.5 * dt, rq)));
+  Q4<double> q2 = qnormalize(qadd(qh, qscale(0.5 * dt, q_rate(qh, w))));
+  return qnormalize(qadd(qscale(2.0, q2), qscale(-1.0, q1)));
+}
+
+__device__ __forceinline__ Q4<double> drive_q(const Dev& d, long long lvl) {
+  double phi = 2.0 * 3.14159265358979323846 * (double)lvl / (double)d.period;
+  double s, c;
+  sincos(0.5 * phi, &s, &c);
+  return {c, s * d.axis[0], s * d.axis[1], s * d.axis[2]};
+}
+
+__device__ __forceinline__ int cell_coord(double x, double inv) {
+  double c = floor(x * inv);
+  c = fmin(fmax(c, -1.0e9), 1.0e9);  // keeps runaway coordinates hashable
+  return (int)c;
+}
+
+__device__ __forceinline__ unsigned cell_hash(int cx, int cy, int cz, int mem, unsigned mask) {
+  unsigned h = (unsigned)cx * 73856093u ^ (unsigned)cy * 19349663u ^ (unsigned)cz * 83492791u ^
+               (unsigned)mem * 2654435761u;
+  return h & mask;
+}
+
+__global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const long N = d.n;
+  const long long n = *d.step;
+  const int b = d.bc[i];
+  Q4<double> q = ld4(d.q, N, i);
+  if (mode == PRE_STEP) {
+    if (b == 0) {
+      const double h = 0.5 * d.dt;
+      V3<double> v = ld3(d.v, N, i) + (h * d.minv[i]) * ld3(d.F, N, i);
+      V3<double> x = ld3(d.x, N, i) + d.dt * v;
+      V3<double> w = ld3(d.w, N, i) + (h * d.Iinv[i]) * ld3(d.T, N, i);
+      q = richardson(q, w, d.dt);
+      st3(d.v, N, i, v);
+      st3(d.x, N, i, x);
+      st3(d.w, N, i, w);
+      st4(d.q, N, i, q);
+    } else if (b == 2) {
+      q = drive_q(d, n + 1);
+      st4(d.q, N, i, q);
+    }
+  } else if (mode == PRE_PREPARE) {
+    q = qnormalize(q);
+    if (b != 0) {
+      V3<double> z{0.0, 0.0, 0.0};
+      st3(d.v, N, i, z);
+      st3(d.w, N, i, z);
+    }
+    if (b == 2) {
+      q = drive_q(d, n);
+      double om = 2.0 * 3.14159265358979323846 / ((double)d.period * d.dt);
+      st3(d.w, N, i, V3<double>{om * d.axis[0], om * d.axis[1], om * d.axis[2]});
+    }
+    st4(d.q, N, i, q);
+  }
+  // Dipole moment in the global frame: m = q m_body q*.
+  V3<double> m = qrot(q, ld3(d.mb, N, i));
+  st3(d.mu, N, i, m);
+  if (d.muf) st3(d.muf, N, i, V3<float>{(float)m.x, (float)m.y, (float)m.z});
+  // Hashed cell list insertion for the contact search.
+  if (d.contact_on) {
+    V3<double> x = ld3(d.x, N, i);
+    unsigned key = cell_hash(cell_coord(x.x, d.inv_cell), cell_coord(x.y, d.inv_cell),
+                             cell_coord(x.z, d.inv_cell), d.mem[i], d.cell_mask);
+    int slot = atomicAdd(&d.cell_cnt[key], 1);
+    if (slot < CELL_CAP) {
+      d.cell_slot[(long)key * CELL_CAP + slot] = (int)i;
+    } else {
+      int o = atomicAdd(d.ovf_cnt, 1);
+      if (o < OVF_CAP) d.ovf_list[o] = (int)i;
+      else atomicOr(&d.flags[FLAG_LIST_OVF], 1u);
+    }
+    d.key[i] = (int)key;
+  }
+}
+
+__device__ __forceinline__ bool finite3(V3<double> a) {
+  return isfinite(a.x) && isfinite(a.y) && isfinite(a.z);
+}
+
+__global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double* Fo, double* To,
+                                              double* Bo) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long N = d.n;
+  const long long n = *d.step;
+  if (i < N) {
+    const long long lvl = n + (mode == POST_KICK ? 1 : 0);
+    V3<double> F{0.0, 0.0, 0.0}, T{0.0, 0.0, 0.0};
+    const uint8_t bf = d.bflags[i];
+    if (mask & 1) {  // bonds: +F, tau_s + tau_bt from bond (i, i+1); -F, tau_s - tau_bt from (i-1, i)
+      if (bf & 1) {
+        F = F + ld3(d.bF, N, i);
+        T = T + ld3(d.bTs, N, i) + ld3(d.bTbt, N, i);
+      }
+      if (bf & 2) {
+        F = F - ld3(d.bF, N, i - 1);
+        T = T + ld3(d.bTs, N, i - 1) - ld3(d.bTbt, N, i - 1);
+      }
+    }
+    const V3<double> m = ld3(d.mu, N, i);
+    const int mem = d.mem[i];
+    V3<double> Bd{0.0, 0.0, 0.0};
+    if ((mask & 2) && d.dipole_on) {  // dipole-dipole: sum of the partial slots, torque m x B_dip
+      V3<double> Fd{0.0, 0.0, 0.0};
+      const int S = d.mslots[mem];
+      for (int s = 0; s < S; ++s) {
+        const double* p = d.dpart + (long)s * 6 * N;
+        Fd = Fd + V3<double>{p[i], p[N + i], p[2 * N + i]};
+        Bd = Bd + V3<double>{p[3 * N + i], p[4 * N + i], p[5 * N + i]};
+      }
+      F = F + Fd;
+      T = T + cross(m, Bd);
+    }
+    if (Bo) st3(Bo, N, i, Bd);
+    if (mask & 4) {  // Zeeman: B = B0 + G x, f = G^T m, tau = m x B
+      long long L = d.field_len;
+      long long row = ((lvl % L) + L) % L;
+      const double* f = d.field + (row * d.M + mem) * 12;
+      V3<double> x = ld3(d.x, N, i);
+      V3<double> B{f[0] + f[3] * x.x + f[4] * x.y + f[5] * x.z,
+                   f[1] + f[6] * x.x + f[7] * x.y + f[8] * x.z,
+                   f[2] + f[9] * x.x + f[10] * x.y + f[11] * x.z};
+      F = F + V3<double>{f[3] * m.x + f[6] * m.y + f[9] * m.z,
+                         f[4] * m.x + f[7] * m.y + f[10] * m.z,
+                         f[5] * m.x + f[8] * m.y + f[11] * m.z};
+      T = T + cross(m, B);
+    }
+    if ((mask & 8) && d.contact_on) F = F + ld3(d.cF, N, i);
+    if (mask & 16) {  // global viscous damping with the current (half-step) velocities
+      F = F - (d.damping * d.mass[i]) * ld3(d.v, N, i);
+      T = T - (d.damping * d.inertia[i]) * ld3(d.w, N, i);
+    }
+    if (mask & 32) {
+      if (d.extF) F = F + ld3(d.extF, N, i);
+      if (d.extT) T = T + ld3(d.extT, N, i);
+    }
+    if (mode == POST_EVAL) {
+      st3(Fo, N, i, F);
+      st3(To, N, i, T);
+    } else {
+      st3(d.F, N, i, F);
+      st3(d.T, N, i, T);
+      if (mode == POST_KICK && d.bc[i] == 0) {
+        const double h = 0.5 * d.dt;
+        st3(d.v, N, i, ld3(d.v, N, i) + (h * d.minv[i]) * F);
+        st3(d.w, N, i, ld3(d.w, N, i) + (h * d.Iinv[i]) * T);
+      }
+      if (!finite3(F) || !finite3(T) || !finite3(ld3(d.x, N, i)))
+        atomicOr(&d.flags[FLAG_NONFINITE], 1u);
+    }
+    if (d.contact_on) d.cell_cnt[d.key[i]] = 0;  // empty the cell list for the next build
+  }
+  // The last block to finish advances the time level and resets the overflow list;
+  // every other block has read the level before it counted itself done.
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned t = atomicAdd(d.done, 1u);
+    if (t == gridDim.x - 1) {
+      if (mode == POST_KICK) *d.step = n + 1;
+      *d.ovf_cnt = 0;
+      *d.done = 0;
+      __threadfence();
+    }
+  }
+}
+
+// Per-particle energy terms [9][N]: bond terms attributed to the bond's first
+// particle, Zeeman -m.B, dipole -1/2 m.B_dip, contact (pairs halved), kinetic.
+__global__ __launch_bounds__(256) void k_energy_part(Dev d, const double* Bdip, double* E) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long N = d.n;
+  if (i >= N) return;
+  const long long lvl = *d.step;
+  const bool hb = d.bflags[i] & 1;
+  for (int t = 0; t < 4; ++t) E[t * N + i] = hb ? d.bE[t * N + i] : 0.0;
+  const V3<double> m = ld3(d.mu, N, i);
+  long long L = d.field_len;
+  long long row = ((lvl % L) + L) % L;
+  const double* f = d.field + (row * d.M + d.mem[i]) * 12;
+  V3<double> x = ld3(d.x, N, i);
+  V3<double> B{f[0] + f[3] * x.x + f[4] * x.y + f[5] * x.z,
+               f[1] + f[6] * x.x + f[7] * x.y + f[8] * x.z,
+               f[2] + f[9] * x.x + f[10] * x.y + f[11] * x.z};
+  E[4 * N + i] = -dot(m, B);
+  E[5 * N + i] = d.dipole_on ? -0.5 * dot(m, ld3(Bdip, N, i)) : 0.0;
+  E[6 * N + i] = d.contact_on ? d.cE[i] : 0.0;
+  V3<double> v = ld3(d.v, N, i), w = ld3(d.w, N, i);
+  E[7 * N + i] = 0.5 * d.mass[i] * dot(v, v);
+  E[8 * N + i] = 0.5 * d.inertia[i] * dot(w, w);
+}
+
+// One block per member: fixed-order tree sum of the member's particle range.
+__global__ __launch_bounds__(256) void k_energy_reduce(Dev d, const double* E, double* out) {
+  __shared__ double red[256];
+  const int mem = blockIdx.x;
+  const int b = d.mrange[2 * mem], e = d.mrange[2 * mem + 1];
+  const long N = d.n;
+  for (int t = 0; t < 9; ++t) {
+    double s = 0.0;
+    for (int i = b + threadIdx.x; i < e; i += blockDim.x) s += E[t * N + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[mem * 9 + t] = red[0];
+    __syncthreads();
+  }
+}
+
+static inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_pre(const Dev& d, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_pre, dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_post(const Dev& d, int mode, int mask, double* Fo, double* To, double* Bo,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_post, dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, mode, mask, Fo, To,
+                     Bo);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const Dev& d, double* Epart, double* out, hipStream_t s) {
+  // Epart holds [9][N] energy terms, then [3][N] dipole field, [3][N] and [3][N] scratch.
+  double* Bd = Epart + 9 * d.n;
+  hipError_t e = launch_post(d, POST_EVAL, 2, Bd + 3 * d.n, Bd + 6 * d.n, Bd, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_part, dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d,
+                     (const double*)Bd, Epart);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_reduce, dim3(d.M), dim3(256), 0, s, d, (const double*)Epart, out);
+  return hipGetLastError();
+}
+
+}  // namespace rodmx

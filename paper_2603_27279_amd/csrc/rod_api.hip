@@ -1,0 +1,655 @@
+// Host runtime behind the C ABI of include/rod.h: descriptor validation,
+// topology and constants, workspace, the step schedule (eager launches or a
+// captured HIP graph of several steps), inspection entry points, and the tape
+// used by the reverse pass.
+#include "rod.h"
+#include "rod_internal.h"
+#include "rod_adjoint.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace rodmx;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPC(expr)                                                                        \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      return fail(ROD_E_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),       \
+                  __FILE__, __LINE__);                                                    \
+  } while (0)
+
+#define TRY(expr)                 \
+  do {                            \
+    int _r = (expr);              \
+    if (_r != ROD_OK) return _r;  \
+  } while (0)
+
+struct rod_ctx {
+  rod_desc desc;            // scalar fields (host pointers cleared after init)
+  rod_buffers ub;
+  hipStream_t user = nullptr, s = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  Dev d;
+  std::vector<void*> allocs;
+  DipWork* work = nullptr;
+  int nwork = 0, max_slots = 1, dip_chunk = 0;
+  std::vector<int> mslots_h;
+  double* epart = nullptr;
+  double* eout = nullptr;
+  int* pair_count = nullptr;
+  std::vector<int> rod_offset;
+  std::vector<double> bref_h;  // [4N]
+  std::vector<double> rodK_h;  // [R][4]
+  std::vector<uint8_t> bflags_h;
+  std::vector<int> rod_h;
+  int64_t h_step = 0;
+  hipGraphExec_t gexec = nullptr;
+  int gsteps = 0;
+  Tape tape;
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kernel;  // kernel class of each recorded pair
+  int ev_used = 0;             // pairs recorded since the last read
+  double t_ms[ROD_KERNEL_COUNT] = {0};
+  int64_t t_cnt[ROD_KERNEL_COUNT] = {0};
+};
+
+static int timing_begin(rod_ctx* c, int kid) {
+  if (!c->timing) return ROD_OK;
+  while ((int)c->ev_pool.size() < 2 * (c->ev_used + 1)) {
+    hipEvent_t e;
+    HIPC(hipEventCreate(&e));
+    c->ev_pool.push_back(e);
+  }
+  if ((int)c->ev_kernel.size() < c->ev_used + 1) c->ev_kernel.resize(c->ev_used + 1);
+  c->ev_kernel[c->ev_used] = kid;
+  HIPC(hipEventRecord(c->ev_pool[2 * c->ev_used], c->s));
+  return ROD_OK;
+}
+static int timing_end(rod_ctx* c) {
+  if (!c->timing) return ROD_OK;
+  HIPC(hipEventRecord(c->ev_pool[2 * c->ev_used + 1], c->s));
+  ++c->ev_used;
+  return ROD_OK;
+}
+static int timing_collect(rod_ctx* c) {
+  if (c->ev_used == 0) return ROD_OK;
+  HIPC(hipStreamSynchronize(c->s));
+  for (int k = 0; k < c->ev_used; ++k) {
+    float ms = 0.f;
+    HIPC(hipEventElapsedTime(&ms, c->ev_pool[2 * k], c->ev_pool[2 * k + 1]));
+    c->t_ms[c->ev_kernel[k]] += ms;
+    c->t_cnt[c->ev_kernel[k]] += 1;
+  }
+  c->ev_used = 0;
+  return ROD_OK;
+}
+
+#define TIMED(c, kid, expr)        \
+  do {                             \
+    TRY(timing_begin((c), (kid))); \
+    HIPC(expr);                    \
+    TRY(timing_end(c));            \
+  } while (0)
+
+static size_t next_pow2(size_t v) {
+  size_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+template <class T>
+static int dalloc(rod_ctx* c, T** p, size_t count) {
+  void* q = nullptr;
+  size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+  HIPC(hipMalloc(&q, bytes));
+  c->allocs.push_back(q);
+  HIPC(hipMemset(q, 0, bytes));
+  *p = (T*)q;
+  return ROD_OK;
+}
+
+static int validate(const rod_desc* d) {
+  if (!d) return fail(ROD_E_INVALID, "descriptor is NULL");
+  if (d->n_particles < 1 || d->n_rods < 1 || d->n_members < 1)
+    return fail(ROD_E_INVALID, "need n_particles, n_rods, n_members >= 1 (got %d, %d, %d)",
+                d->n_particles, d->n_rods, d->n_members);
+  if (!d->rod_offset || !d->rod_member || !d->rod_params || !d->x_ref || !d->bc)
+    return fail(ROD_E_INVALID, "rod_offset, rod_member, rod_params, x_ref and bc are required");
+  if (d->rod_offset[0] != 0 || d->rod_offset[d->n_rods] != d->n_particles)
+    return fail(ROD_E_INVALID, "rod_offset must start at 0 and end at n_particles");
+  for (int r = 0; r < d->n_rods; ++r) {
+    if (d->rod_offset[r + 1] <= d->rod_offset[r])
+      return fail(ROD_E_INVALID, "rod_offset must be strictly increasing (rod %d)", r);
+    int m = d->rod_member[r];
+    if (m < 0 || m >= d->n_members || (r > 0 && m < d->rod_member[r - 1]))
+      return fail(ROD_E_INVALID, "rod_member must be non-decreasing in [0, n_members) (rod %d)", r);
+    const double* p = d->rod_params + 4 * r;
+    if (!(p[0] > 0) || !(p[1] > 0) || !(p[2] > 0) || !(p[3] > -1.0))
+      return fail(ROD_E_INVALID, "rod %d: need diameter, density, Young > 0 and Poisson > -1", r);
+  }
+  {
+    std::vector<char> used(d->n_members, 0);
+    for (int r = 0; r < d->n_rods; ++r) used[d->rod_member[r]] = 1;
+    for (int m = 0; m < d->n_members; ++m)
+      if (!used[m]) return fail(ROD_E_INVALID, "member %d has no rod", m);
+  }
+  bool driven = false;
+  for (int i = 0; i < d->n_particles; ++i) {
+    if (d->bc[i] < 0 || d->bc[i] > 2) return fail(ROD_E_INVALID, "bc[%d] = %d is not 0, 1 or 2", i, d->bc[i]);
+    driven |= d->bc[i] == 2;
+  }
+  if (driven) {
+    double a = std::sqrt(d->drive_axis[0] * d->drive_axis[0] + d->drive_axis[1] * d->drive_axis[1] +
+                         d->drive_axis[2] * d->drive_axis[2]);
+    if (d->drive_period <= 0 || !(a > 0))
+      return fail(ROD_E_INVALID, "driven particles need drive_period > 0 and a non-zero axis");
+  }
+  if (!(d->dt > 0) || !std::isfinite(d->dt)) return fail(ROD_E_INVALID, "dt must be > 0");
+  if (!(d->damping >= 0)) return fail(ROD_E_INVALID, "damping must be >= 0");
+  if (d->field_len < 1) return fail(ROD_E_INVALID, "field_len must be >= 1");
+  if (d->precision != ROD_FP64 && d->precision != ROD_MIXED)
+    return fail(ROD_E_INVALID, "precision must be ROD_FP64 or ROD_MIXED");
+  if (d->contact_on && !(d->r_contact > 0)) return fail(ROD_E_INVALID, "r_contact must be > 0");
+  if (d->exclude_depth < 0) return fail(ROD_E_INVALID, "exclude_depth must be >= 0");
+  if (d->graph_steps < 0 || d->tape_every < 0 || d->tape_capacity < 0)
+    return fail(ROD_E_INVALID, "graph_steps, tape_every and tape_capacity must be >= 0");
+  if (d->tape_capacity > 0 && d->tape_every < 1)
+    return fail(ROD_E_INVALID, "a tape needs tape_every >= 1");
+  for (int r = 0; r < d->n_rods; ++r)
+    for (int k = d->rod_offset[r]; k + 1 < d->rod_offset[r + 1]; ++k) {
+      double dx = d->x_ref[3 * (k + 1)] - d->x_ref[3 * k];
+      double dy = d->x_ref[3 * (k + 1) + 1] - d->x_ref[3 * k + 1];
+      double dz = d->x_ref[3 * (k + 1) + 2] - d->x_ref[3 * k + 2];
+      if (!(dx * dx + dy * dy + dz * dz > 0))
+        return fail(ROD_E_INVALID, "zero-length reference bond at particle %d", k);
+    }
+  return ROD_OK;
+}
+
+// Dipole work list: blocks of 256 i against j chunks of the same member; the
+// chunk count per member is chosen so the launch holds at least ~2048 work items.
+static int build_dipole_plan(rod_ctx* c, const std::vector<int>& mrange, int chunk_override) {
+  const int M = c->desc.n_members;
+  long iblocks = 0;
+  for (int m = 0; m < M; ++m) iblocks += (mrange[2 * m + 1] - mrange[2 * m] + 255) / 256;
+  const long target = 2048;
+  std::vector<DipWork> items;
+  c->mslots_h.assign(M, 1);
+  int max_slots = 1;
+  for (int m = 0; m < M; ++m) {
+    const int b = mrange[2 * m], e = mrange[2 * m + 1], nm = e - b;
+    int S;
+    if (chunk_override > 0) S = (nm + chunk_override - 1) / chunk_override;
+    else S = (int)std::min<long>((target + iblocks - 1) / iblocks, (nm + 255) / 256);
+    S = std::max(S, 1);
+    const int len = (nm + S - 1) / S;
+    S = (nm + len - 1) / len;
+    c->mslots_h[m] = S;
+    max_slots = std::max(max_slots, S);
+    for (int i0 = b; i0 < e; i0 += 256)
+      for (int s = 0; s < S; ++s) {
+        DipWork w{};
+        w.i0 = i0; w.i1 = std::min(i0 + 256, e);
+        w.j0 = b + s * len; w.j1 = std::min(e, b + (s + 1) * len);
+        w.slot = s;
+        items.push_back(w);
+      }
+  }
+  c->max_slots = max_slots;
+  c->nwork = (int)items.size();
+  TRY(dalloc(c, &c->work, items.size()));
+  HIPC(hipMemcpy(c->work, items.data(), items.size() * sizeof(DipWork), hipMemcpyHostToDevice));
+  int* ms = nullptr;
+  TRY(dalloc(c, &ms, M));
+  HIPC(hipMemcpy(ms, c->mslots_h.data(), M * sizeof(int), hipMemcpyHostToDevice));
+  c->d.mslots = ms;
+  TRY(dalloc(c, &c->d.dpart, (size_t)max_slots * 6 * c->desc.n_particles));
+  return ROD_OK;
+}
+
+static size_t workspace_bytes(const rod_desc* d, int max_slots) {
+  size_t N = d->n_particles, R = d->n_rods, M = d->n_members;
+  size_t cells = d->contact_on ? next_pow2(std::max<size_t>(1024, 2 * N)) : 1;
+  size_t b = 0;
+  b += N * (1 + 4 + 4 + 1) + 8 * N * 4 + 8 * N * 4 + 8 * R * 4 + 4 * M * 3;  // topology
+  b += 8 * 3 * N + 4 * 3 * N + 8 * 9 * N + 8 * 4 * N;                         // mu, bonds
+  b += 8 * (size_t)max_slots * 6 * N + 8 * 4 * N;                               // dipole, contact
+  b += 4 * cells * (1 + CELL_CAP) + 4 * N + 4 * OVF_CAP;                        // cells
+  b += 8 * 18 * N + 8 * 9 * M;                                                  // energy
+  return b;
+}
+
+// ------------------------------------------------------------------ schedule
+static int force_terms(rod_ctx* c, int want_energy) {
+  TIMED(c, ROD_KERNEL_BOND, launch_bond(c->d, c->desc.precision, want_energy, c->s));
+  if (c->desc.dipole_on)
+    TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole(c->d, c->desc.precision, c->work, c->nwork, c->s));
+  if (c->desc.contact_on) TIMED(c, ROD_KERNEL_CONTACT, launch_contact(c->d, want_energy, c->s));
+  return ROD_OK;
+}
+
+static int enqueue_step(rod_ctx* c) {
+  TIMED(c, ROD_KERNEL_PRE, launch_pre(c->d, PRE_STEP, c->s));
+  TRY(force_terms(c, 0));
+  TIMED(c, ROD_KERNEL_POST,
+        launch_post(c->d, POST_KICK, ROD_TERM_ALL, nullptr, nullptr, nullptr, c->s));
+  return ROD_OK;
+}
+
+static int enqueue_prepare(rod_ctx* c) {
+  HIPC(launch_pre(c->d, PRE_PREPARE, c->s));
+  TRY(force_terms(c, 0));
+  HIPC(launch_post(c->d, POST_PREPARE, ROD_TERM_ALL, nullptr, nullptr, nullptr, c->s));
+  return ROD_OK;
+}
+
+static int enter(rod_ctx* c) {
+  HIPC(hipEventRecord(c->ev_in, c->user));
+  HIPC(hipStreamWaitEvent(c->s, c->ev_in, 0));
+  return ROD_OK;
+}
+static int leave(rod_ctx* c) {
+  HIPC(hipEventRecord(c->ev_out, c->s));
+  HIPC(hipStreamWaitEvent(c->user, c->ev_out, 0));
+  return ROD_OK;
+}
+
+static int capture_graph(rod_ctx* c) {
+  hipGraph_t g = nullptr;
+  HIPC(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
+  int rc = ROD_OK;
+  for (int k = 0; k < c->desc.graph_steps && rc == ROD_OK; ++k) rc = enqueue_step(c);
+  hipError_t e = hipStreamEndCapture(c->s, &g);
+  if (rc != ROD_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+  if (e != hipSuccess) return fail(ROD_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(ROD_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+  c->gsteps = c->desc.graph_steps;
+  return ROD_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* rod_last_error(void) { return g_err.c_str(); }
+
+int rod_query_workspace(const rod_desc* d, size_t* bytes) {
+  TRY(validate(d));
+  if (!bytes) return fail(ROD_E_INVALID, "bytes is NULL");
+  *bytes = workspace_bytes(d, 16);
+  return ROD_OK;
+}
+
+int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip_stream,
+             int32_t forces_valid) {
+  if (!out) return fail(ROD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  TRY(validate(dsc));
+  if (!b || !b->x || !b->v || !b->q || !b->w || !b->force || !b->torque || !b->m_body || !b->field)
+    return fail(ROD_E_INVALID, "x, v, q, w, force, torque, m_body and field buffers are required");
+  rod_ctx* c = new rod_ctx();
+  auto cleanup = [&](int rc) {
+    rod_free(c);
+    return rc;
+  };
+  c->desc = *dsc;
+  c->ub = *b;
+  c->user = (hipStream_t)hip_stream;
+  const int N = dsc->n_particles, R = dsc->n_rods, M = dsc->n_members;
+  c->h_step = dsc->step0;
+  int rc;
+  if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+    return cleanup(fail(ROD_E_HIP, "stream/event creation failed"));
+
+  // ---- topology and constants (host)
+  c->rod_offset.assign(dsc->rod_offset, dsc->rod_offset + R + 1);
+  std::vector<int> rod(N), mem(N);
+  std::vector<uint8_t> bfl(N, 0);
+  std::vector<int8_t> bc(dsc->bc, dsc->bc + N);
+  std::vector<double> minv(N), Iinv(N), mass(N), inertia(N), bref(4 * (size_t)N, 0.0),
+      rodK(4 * (size_t)R);
+  std::vector<int> mrange(2 * M);
+  for (int m = 0; m < M; ++m) { mrange[2 * m] = N; mrange[2 * m + 1] = 0; }
+  const double pi = 3.14159265358979323846;
+  for (int r = 0; r < R; ++r) {
+    const double* p = dsc->rod_params + 4 * r;
+    const double dd = p[0], rho = p[1], E = p[2], nu = p[3];
+    const double A = pi * dd * dd / 4.0, I = pi * dd * dd * dd * dd / 64.0,
+                 J = pi * dd * dd * dd * dd / 32.0, G = E / (2.0 * (1.0 + nu));
+    rodK[4 * r + 0] = E * A;         // K_r = EA / L
+    rodK[4 * r + 1] = 12.0 * E * I;  // K_s = 12 EI / L^3
+    rodK[4 * r + 2] = G * J;         // K_t = GJ / L
+    rodK[4 * r + 3] = E * I;         // K_b = EI / L
+    const double pm = rho * pi * dd * dd * dd / 6.0;           // solid sphere
+    const double pI = 0.4 * pm * (0.5 * dd) * (0.5 * dd);      // 2/5 m R^2
+    const int m = dsc->rod_member[r];
+    for (int i = dsc->rod_offset[r]; i < dsc->rod_offset[r + 1]; ++i) {
+      rod[i] = r; mem[i] = m;
+      mass[i] = pm; inertia[i] = pI; minv[i] = 1.0 / pm; Iinv[i] = 1.0 / pI;
+      if (i + 1 < dsc->rod_offset[r + 1]) {
+        bfl[i] |= 1; bfl[i + 1] |= 2;
+        double rx = dsc->x_ref[3 * (i + 1)] - dsc->x_ref[3 * i];
+        double ry = dsc->x_ref[3 * (i + 1) + 1] - dsc->x_ref[3 * i + 1];
+        double rz = dsc->x_ref[3 * (i + 1) + 2] - dsc->x_ref[3 * i + 2];
+        bref[i] = rx; bref[N + i] = ry; bref[2 * (size_t)N + i] = rz;
+        bref[3 * (size_t)N + i] = std::sqrt(rx * rx + ry * ry + rz * rz);
+      }
+    }
+    mrange[2 * m] = std::min(mrange[2 * m], dsc->rod_offset[r]);
+    mrange[2 * m + 1] = std::max(mrange[2 * m + 1], dsc->rod_offset[r + 1]);
+  }
+  c->bref_h = bref;
+  c->rodK_h = rodK;
+  c->bflags_h = bfl;
+  c->rod_h = rod;
+
+  // ---- device workspace
+  Dev& d = c->d;
+  d = Dev{};
+  d.n = N; d.R = R; d.M = M;
+  d.x = b->x; d.v = b->v; d.q = b->q; d.w = b->w; d.F = b->force; d.T = b->torque;
+  d.mb = b->m_body; d.field = b->field; d.extF = b->ext_force; d.extT = b->ext_torque;
+  uint8_t* bflags; int *rod_d, *mem_d, *mrange_d; int8_t* bc_d;
+  double *minv_d, *Iinv_d, *mass_d, *inertia_d, *bref_d, *rodK_d;
+  if ((rc = dalloc(c, &bflags, N)) || (rc = dalloc(c, &rod_d, N)) || (rc = dalloc(c, &mem_d, N)) ||
+      (rc = dalloc(c, &bc_d, N)) || (rc = dalloc(c, &minv_d, N)) || (rc = dalloc(c, &Iinv_d, N)) ||
+      (rc = dalloc(c, &mass_d, N)) || (rc = dalloc(c, &inertia_d, N)) ||
+      (rc = dalloc(c, &bref_d, 4 * (size_t)N)) || (rc = dalloc(c, &rodK_d, 4 * (size_t)R)) ||
+      (rc = dalloc(c, &mrange_d, 2 * (size_t)M)))
+    return cleanup(rc);
+  struct Up { void* dst; const void* src; size_t bytes; } ups[] = {
+      {bflags, bfl.data(), (size_t)N}, {rod_d, rod.data(), 4 * (size_t)N},
+      {mem_d, mem.data(), 4 * (size_t)N}, {bc_d, bc.data(), (size_t)N},
+      {minv_d, minv.data(), 8 * (size_t)N}, {Iinv_d, Iinv.data(), 8 * (size_t)N},
+      {mass_d, mass.data(), 8 * (size_t)N}, {inertia_d, inertia.data(), 8 * (size_t)N},
+      {bref_d, bref.data(), 32 * (size_t)N}, {rodK_d, rodK.data(), 32 * (size_t)R},
+      {mrange_d, mrange.data(), 8 * (size_t)M}};
+  for (auto& u : ups)
+    if (hipMemcpy(u.dst, u.src, u.bytes, hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(ROD_E_HIP, "upload failed"));
+  d.bflags = bflags; d.rod = rod_d; d.mem = mem_d; d.bc = bc_d;
+  d.minv = minv_d; d.Iinv = Iinv_d; d.mass = mass_d; d.inertia = inertia_d;
+  d.bref = bref_d; d.rodK = rodK_d; d.mrange = mrange_d;
+  float* muf = nullptr;
+  if ((rc = dalloc(c, &d.mu, 3 * (size_t)N)) || (rc = dalloc(c, &muf, 3 * (size_t)N)) ||
+      (rc = dalloc(c, &d.bF, 3 * (size_t)N)) || (rc = dalloc(c, &d.bTs, 3 * (size_t)N)) ||
+      (rc = dalloc(c, &d.bTbt, 3 * (size_t)N)) || (rc = dalloc(c, &d.bE, 4 * (size_t)N)) ||
+      (rc = dalloc(c, &d.cF, 3 * (size_t)N)) || (rc = dalloc(c, &d.cE, (size_t)N)) ||
+      (rc = dalloc(c, &d.key, (size_t)N)) || (rc = dalloc(c, &d.ovf_list, (size_t)OVF_CAP)) ||
+      (rc = dalloc(c, &d.ovf_cnt, 1)) || (rc = dalloc(c, &d.flags, 4)) ||
+      (rc = dalloc(c, &d.step, 1)) || (rc = dalloc(c, &d.done, 1)) ||
+      (rc = dalloc(c, &c->epart, 18 * (size_t)N)) || (rc = dalloc(c, &c->eout, 9 * (size_t)M)) ||
+      (rc = dalloc(c, &c->pair_count, 1)))
+    return cleanup(rc);
+  d.muf = dsc->precision == ROD_MIXED ? muf : nullptr;
+  size_t cells = dsc->contact_on ? next_pow2(std::max<size_t>(1024, 2 * (size_t)N)) : 1;
+  if ((rc = dalloc(c, &d.cell_cnt, cells)) || (rc = dalloc(c, &d.cell_slot, cells * CELL_CAP)))
+    return cleanup(rc);
+  d.cell_mask = (unsigned)(cells - 1);
+  d.dt = dsc->dt; d.damping = dsc->damping; d.C = dsc->mu0_4pi; d.kc = dsc->k_contact;
+  d.rc = dsc->r_contact; d.inv_cell = dsc->contact_on ? 1.0 / dsc->r_contact : 0.0;
+  d.depth = dsc->exclude_depth; d.field_len = dsc->field_len;
+  d.dipole_on = dsc->dipole_on != 0; d.contact_on = dsc->contact_on != 0;
+  {
+    double a = std::sqrt(dsc->drive_axis[0] * dsc->drive_axis[0] +
+                         dsc->drive_axis[1] * dsc->drive_axis[1] +
+                         dsc->drive_axis[2] * dsc->drive_axis[2]);
+    for (int k = 0; k < 3; ++k) d.axis[k] = a > 0 ? dsc->drive_axis[k] / a : 0.0;
+  }
+  d.period = dsc->drive_period > 0 ? dsc->drive_period : 1;
+  long long s0 = dsc->step0;
+  if (hipMemcpy(d.step, &s0, sizeof(s0), hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(fail(ROD_E_HIP, "upload failed"));
+  if ((rc = build_dipole_plan(c, mrange, 0))) return cleanup(rc);
+  // descriptor host pointers are not kept
+  c->desc.rod_offset = nullptr; c->desc.rod_member = nullptr; c->desc.rod_params = nullptr;
+  c->desc.x_ref = nullptr; c->desc.bc = nullptr;
+  if ((rc = tape_init(c->tape, c->d, dsc->tape_every, dsc->tape_capacity, c->allocs))) {
+    return cleanup(fail(rc, "tape allocation failed"));
+  }
+
+  // ---- initial state: normalise q, boundary conditions, forces of level step0
+  if ((rc = enter(c))) return cleanup(rc);
+  if (forces_valid) {
+    if (hipSuccess != launch_pre(c->d, PRE_PREPARE, c->s)) return cleanup(fail(ROD_E_HIP, "launch failed"));
+  } else if ((rc = enqueue_prepare(c))) {
+    return cleanup(rc);
+  }
+  if ((rc = leave(c))) return cleanup(rc);
+  if (forces_valid && d.contact_on) {
+    // pre built the cell list without a force pass; empty it again
+    if (hipStreamSynchronize(c->s) != hipSuccess) return cleanup(fail(ROD_E_HIP, "sync failed"));
+    if (hipMemset(d.cell_cnt, 0, cells * sizeof(int)) != hipSuccess ||
+        hipMemset(d.ovf_cnt, 0, sizeof(int)) != hipSuccess)
+      return cleanup(fail(ROD_E_HIP, "memset failed"));
+  }
+  *out = c;
+  return ROD_OK;
+}
+
+int rod_step(rod_ctx* c, int64_t n) {
+  if (!c) return fail(ROD_E_INVALID, "context is NULL");
+  if (n < 0) return fail(ROD_E_INVALID, "n_steps must be >= 0");
+  if (n == 0) return ROD_OK;
+  TRY(enter(c));
+  if (c->tape.active) {
+    for (int64_t k = 0; k < n; ++k) {
+      TRY(tape_before_step(c->tape, c->d, c->s, c->h_step + k));
+      TRY(enqueue_step(c));
+    }
+  } else {
+    int64_t left = n;
+    if (!c->timing && c->desc.graph_steps > 0 && left >= c->desc.graph_steps) {
+      if (!c->gexec) TRY(capture_graph(c));
+      while (left >= c->gsteps) {
+        HIPC(hipGraphLaunch(c->gexec, c->s));
+        left -= c->gsteps;
+      }
+    }
+    for (int64_t k = 0; k < left; ++k) TRY(enqueue_step(c));
+  }
+  c->h_step += n;
+  TRY(leave(c));
+  return ROD_OK;
+}
+
+int rod_sync(rod_ctx* c) {
+  if (!c) return fail(ROD_E_INVALID, "context is NULL");
+  HIPC(hipStreamSynchronize(c->s));
+  unsigned f[4];
+  HIPC(hipMemcpy(f, c->d.flags, sizeof(f), hipMemcpyDeviceToHost));
+  if (f[0] | f[1] | f[2]) {
+    unsigned z[4] = {0, 0, 0, 0};
+    HIPC(hipMemcpy(c->d.flags, z, sizeof(z), hipMemcpyHostToDevice));
+    if (f[FLAG_NONFINITE]) return fail(ROD_E_NONFINITE, "non-finite force, torque or position");
+    return fail(ROD_E_OVERFLOW, "contact search capacity exceeded (%s)",
+                f[FLAG_CONTACT_OVF] ? "more than 32 contacts on a particle"
+                                    : "overflow list of full cells");
+  }
+  return ROD_OK;
+}
+
+int rod_get_step(rod_ctx* c, int64_t* step) {
+  if (!c || !step) return fail(ROD_E_INVALID, "NULL argument");
+  HIPC(hipStreamSynchronize(c->s));
+  long long s = 0;
+  HIPC(hipMemcpy(&s, c->d.step, sizeof(s), hipMemcpyDeviceToHost));
+  if (s != c->h_step) return fail(ROD_E_STATE, "device step %lld differs from host %lld", s, (long long)c->h_step);
+  *step = s;
+  return ROD_OK;
+}
+
+int rod_eval_forces(rod_ctx* c, int32_t terms, double* F, double* T, double* B) {
+  if (!c || !F || !T) return fail(ROD_E_INVALID, "NULL argument");
+  if (terms < 0 || terms > ROD_TERM_ALL) return fail(ROD_E_INVALID, "bad term mask %d", terms);
+  TRY(enter(c));
+  HIPC(launch_pre(c->d, PRE_EVAL, c->s));
+  TRY(force_terms(c, 0));
+  HIPC(launch_post(c->d, POST_EVAL, terms, F, T, B, c->s));
+  TRY(leave(c));
+  return ROD_OK;
+}
+
+int rod_energy(rod_ctx* c, double* out, int32_t on_device) {
+  if (!c || !out) return fail(ROD_E_INVALID, "NULL argument");
+  TRY(enter(c));
+  HIPC(launch_pre(c->d, PRE_EVAL, c->s));
+  TRY(force_terms(c, 1));
+  HIPC(launch_energy(c->d, c->epart, c->eout, c->s));
+  const size_t bytes = 9 * sizeof(double) * c->d.M;
+  if (on_device) {
+    HIPC(hipMemcpyAsync(out, c->eout, bytes, hipMemcpyDeviceToDevice, c->s));
+    TRY(leave(c));
+  } else {
+    HIPC(hipMemcpyAsync(out, c->eout, bytes, hipMemcpyDeviceToHost, c->s));
+    TRY(leave(c));
+    HIPC(hipStreamSynchronize(c->s));
+  }
+  return ROD_OK;
+}
+
+int rod_topology(rod_ctx* c, int32_t* ij, double* rref, double* K, int32_t cap, int32_t* count) {
+  if (!c || !count) return fail(ROD_E_INVALID, "NULL argument");
+  const long N = c->d.n;
+  int B = 0;
+  for (long k = 0; k < N; ++k) {
+    if (!(c->bflags_h[k] & 1)) continue;
+    if (B < cap) {
+      if (ij) { ij[2 * B] = (int)k; ij[2 * B + 1] = (int)k + 1; }
+      const double r0 = c->bref_h[3 * N + k];
+      if (rref) for (int a = 0; a < 3; ++a) rref[3 * B + a] = c->bref_h[a * N + k];
+      if (K) {
+        const double* k4 = &c->rodK_h[4 * c->rod_h[k]];
+        K[4 * B + 0] = k4[0] / r0;
+        K[4 * B + 1] = k4[1] / (r0 * r0 * r0);
+        K[4 * B + 2] = k4[2] / r0;
+        K[4 * B + 3] = k4[3] / r0;
+      }
+    }
+    ++B;
+  }
+  *count = B;
+  return ROD_OK;
+}
+
+int rod_contact_pairs(rod_ctx* c, int32_t* pairs, int32_t cap, int32_t* count) {
+  if (!c || !count || (cap > 0 && !pairs)) return fail(ROD_E_INVALID, "NULL argument");
+  *count = 0;
+  if (!c->desc.contact_on) return ROD_OK;
+  int32_t* dp = nullptr;
+  const int dcap = std::max(cap, 1);
+  HIPC(hipMalloc(&dp, 2 * sizeof(int32_t) * dcap));
+  int rc = ROD_OK;
+  do {
+    if ((rc = enter(c))) break;
+    if (hipMemsetAsync(c->pair_count, 0, sizeof(int), c->s) != hipSuccess ||
+        launch_pre(c->d, PRE_EVAL, c->s) != hipSuccess ||
+        launch_contact_pairs(c->d, dp, cap, c->pair_count, c->s) != hipSuccess ||
+        launch_clear_cells(c->d, c->s) != hipSuccess) {
+      rc = fail(ROD_E_HIP, "launch failed");
+      break;
+    }
+    if ((rc = leave(c))) break;
+    int cnt = 0;
+    if (hipStreamSynchronize(c->s) != hipSuccess ||
+        hipMemcpy(&cnt, c->pair_count, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+      rc = fail(ROD_E_HIP, "readback failed");
+      break;
+    }
+    int nw = std::min(cnt, cap);
+    if (nw > 0) {
+      if (hipMemcpy(pairs, dp, 2 * sizeof(int32_t) * nw, hipMemcpyDeviceToHost) != hipSuccess) {
+        rc = fail(ROD_E_HIP, "readback failed");
+        break;
+      }
+      std::vector<std::pair<int, int>> v(nw);
+      for (int k = 0; k < nw; ++k) v[k] = {pairs[2 * k], pairs[2 * k + 1]};
+      std::sort(v.begin(), v.end());
+      for (int k = 0; k < nw; ++k) { pairs[2 * k] = v[k].first; pairs[2 * k + 1] = v[k].second; }
+    }
+    *count = cnt;
+  } while (0);
+  (void)hipFree(dp);
+  return rc;
+}
+
+int rod_tape_begin(rod_ctx* c) {
+  if (!c) return fail(ROD_E_INVALID, "context is NULL");
+  if (c->tape.capacity <= 0) return fail(ROD_E_NOTAPE, "context was created without a tape");
+  TRY(enter(c));
+  TRY(enqueue_prepare(c));
+  TRY(tape_start(c->tape, c->d, c->s, c->h_step));
+  TRY(leave(c));
+  return ROD_OK;
+}
+
+int rod_grad(rod_ctx* c, const rod_cotangent* gy, rod_gradients* gx) {
+  if (!c || !gy || !gx) return fail(ROD_E_INVALID, "NULL argument");
+  if (!c->tape.active || c->h_step == c->tape.start_step)
+    return fail(ROD_E_NOTAPE, "no recorded steps: call rod_tape_begin, then rod_step");
+  TRY(enter(c));
+  TRY(adjoint_run(c->tape, c->d, c->desc.precision, c->work, c->nwork, c->s, c->h_step, gy, gx));
+  TRY(leave(c));
+  return ROD_OK;
+}
+
+int rod_timing(rod_ctx* c, int32_t enable) {
+  if (!c) return fail(ROD_E_INVALID, "context is NULL");
+  TRY(timing_collect(c));
+  c->timing = enable != 0;
+  for (int k = 0; k < ROD_KERNEL_COUNT; ++k) { c->t_ms[k] = 0.0; c->t_cnt[k] = 0; }
+  return ROD_OK;
+}
+
+int rod_kernel_times(rod_ctx* c, double* ms, int64_t* launches) {
+  if (!c) return fail(ROD_E_INVALID, "context is NULL");
+  TRY(timing_collect(c));
+  for (int k = 0; k < ROD_KERNEL_COUNT; ++k) {
+    if (ms) ms[k] = c->t_ms[k];
+    if (launches) launches[k] = c->t_cnt[k];
+    c->t_ms[k] = 0.0;
+    c->t_cnt[k] = 0;
+  }
+  return ROD_OK;
+}
+
+int rod_free(rod_ctx* c) {
+  if (!c) return ROD_OK;
+  if (c->s) (void)hipStreamSynchronize(c->s);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  for (void* p : c->allocs) (void)hipFree(p);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+  if (c->s) (void)hipStreamDestroy(c->s);
+  delete c;
+  return ROD_OK;
+}
+
+}  // extern "C"
+
+// Used by the adjoint module to report errors in the same channel.
+int rodmx_fail(int code, const char* msg) { return fail(code, "%s", msg); }

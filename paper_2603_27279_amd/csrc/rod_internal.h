@@ -1,0 +1,74 @@
+// Internal declarations shared by the kernels and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace rodmx {
+
+// Device-side view of one context: every pointer is a device pointer, fixed for
+// the lifetime of the context, so that captured graphs can be replayed.
+struct Dev {
+  long n;           // particles
+  int R, M;         // rods, members
+  // caller-owned state (SoA planes)
+  double *x, *v, *q, *w, *F, *T;
+  const double *mb, *field, *extF, *extT;
+  // topology and constants
+  const uint8_t* bflags;   // bit0: bond (k, k+1); bit1: bond (k-1, k)
+  const int* rod;          // rod of each particle
+  const int* mem;          // member of each particle
+  const int8_t* bc;        // boundary condition of each particle
+  const double *minv, *Iinv, *mass, *inertia;
+  const double* bref;      // [4N]: reference bond vector planes x, y, z and its length r0
+  const double* rodK;      // [R][4]: EA, 12EI, GJ, EI
+  const int* mrange;       // [2M]: member particle range [begin, end)
+  const int* mslots;       // [M]: dipole partial slots used by the member
+  // per-step work buffers
+  double* mu;              // [3N] global dipole moments
+  float* muf;              // [3N] FP32 copy for the mixed dipole kernel
+  double *bF, *bTs, *bTbt; // [3N] per-bond outputs (index = first particle)
+  double* bE;              // [4N] per-bond energies (energy evaluation only)
+  double* dpart;           // [S][6][N] dipole partial sums (F then B)
+  double* cF;              // [3N] contact force
+  double* cE;              // [N] contact energy per particle (energy evaluation only)
+  int* cell_cnt;           // [cells] particles hashed to each cell
+  int* cell_slot;          // [cells][CELL_CAP] particle indices
+  int* key;                // [N] cell of each particle
+  int* ovf_list;           // [OVF_CAP] particles whose cell was full
+  int* ovf_cnt;            // [1]
+  unsigned cell_mask;      // cells - 1 (power of two)
+  unsigned* flags;         // [4]: non-finite, contact overflow, overflow-list overflow
+  long long* step;         // time level of the state
+  unsigned* done;          // block counter for the step advance
+  // parameters
+  double dt, damping, C, kc, rc, inv_cell;
+  int depth, field_len, dipole_on, contact_on;
+  double axis[3];
+  long long period;
+};
+
+constexpr int CELL_CAP = 8;
+constexpr int OVF_CAP = 4096;
+constexpr int CONTACT_MAX = 32;  // contacts per particle
+enum { FLAG_NONFINITE = 0, FLAG_CONTACT_OVF = 1, FLAG_LIST_OVF = 2 };
+
+enum PreMode { PRE_PREPARE = 0, PRE_STEP = 1, PRE_EVAL = 2 };
+enum PostMode { POST_PREPARE = 0, POST_KICK = 1, POST_EVAL = 2 };
+
+// One dipole work item: members' i-block [i0, i0+256) clipped to the member,
+// against j in [j0, j1), written to partial slot `slot`.
+struct DipWork { int i0, i1, j0, j1, slot, pad0, pad1, pad2; };
+
+// Kernel launchers (each enqueues on `s`; return the launch status).
+hipError_t launch_pre(const Dev& d, int mode, hipStream_t s);
+hipError_t launch_bond(const Dev& d, int precision, int want_energy, hipStream_t s);
+hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int nwork,
+                         hipStream_t s);
+hipError_t launch_contact(const Dev& d, int want_energy, hipStream_t s);
+hipError_t launch_post(const Dev& d, int mode, int mask, double* Fout, double* Tout,
+                       double* Bout, hipStream_t s);
+hipError_t launch_energy(const Dev& d, double* Epart, double* out, hipStream_t s);
+hipError_t launch_contact_pairs(const Dev& d, int* pairs, int cap, int* count, hipStream_t s);
+hipError_t launch_clear_cells(const Dev& d, hipStream_t s);
+
+}  // namespace rodmx

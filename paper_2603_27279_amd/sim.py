@@ -1,0 +1,208 @@
+"""Python binding of the rod library: same entry points as the C ABI, with
+torch tensors supplying device memory and the current HIP stream.
+
+Only argument marshalling happens here: every step of the loop runs in the HIP
+kernels of librodmx.so. Device state is SoA: vectors are ``[3, N]`` float64
+tensors, quaternions ``[4, N]``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+_PRECISION = {"fp64": L.ROD_FP64, "mixed": L.ROD_MIXED}
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _soa(torch, a, dev):
+    return torch.as_tensor(np.ascontiguousarray(np.asarray(a, dtype=np.float64).T), device=dev)
+
+
+class RodSim:
+    """One simulation context built from a workload dictionary (see ``workloads``).
+
+    ``precision``: "fp64" or "mixed" (default: the workload's).
+    ``graph_steps``: steps per captured HIP graph (0 = eager launches).
+    ``tape_every`` / ``tape_capacity``: checkpointing for ``grad``.
+    """
+
+    def __init__(self, w, precision=None, graph_steps=0, tape_every=0, tape_capacity=0,
+                 device="cuda", step0=0, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = L.load()
+        self.w = w
+        n = int(w["n"])
+        self.n = n
+        dev = torch.device(device)
+        self.device = dev
+        self.x = _soa(torch, w["x0"], dev)
+        self.v = _soa(torch, w["v0"], dev)
+        self.q = _soa(torch, w["q0"], dev)
+        self.om = _soa(torch, w["w0"], dev)
+        self.F = torch.zeros((3, n), dtype=torch.float64, device=dev)
+        self.T = torch.zeros((3, n), dtype=torch.float64, device=dev)
+        self.m_body = _soa(torch, w["m_body"], dev)
+        self.field = torch.as_tensor(np.ascontiguousarray(w["field"], dtype=np.float64), device=dev)
+        self.ext_force = None if w.get("ext_force") is None else _soa(torch, w["ext_force"], dev)
+        self.ext_torque = None if w.get("ext_torque") is None else _soa(torch, w["ext_torque"], dev)
+        prec = _PRECISION[precision or w.get("precision", "fp64")]
+        self.precision = prec
+        self._host = dict(
+            rod_offset=np.ascontiguousarray(w["rod_offset"], dtype=np.int32),
+            rod_member=np.ascontiguousarray(w["rod_member"], dtype=np.int32),
+            rod_params=np.ascontiguousarray(w["rod_params"], dtype=np.float64),
+            x_ref=np.ascontiguousarray(w["x_ref"], dtype=np.float64),
+            bc=np.ascontiguousarray(w["bc"], dtype=np.int8),
+        )
+        d = L.RodDesc()
+        d.n_particles = n
+        d.n_rods = len(self._host["rod_member"])
+        d.n_members = int(w["n_members"])
+        for k in ("rod_offset", "rod_member", "rod_params", "x_ref", "bc"):
+            setattr(d, k, self._host[k].ctypes.data_as(C.c_void_p))
+        d.drive_axis = (C.c_double * 3)(*[float(a) for a in w["drive_axis"]])
+        d.drive_period = int(w["drive_period"])
+        d.field_len = int(self.field.shape[0])
+        d.dt = float(w["dt"]); d.damping = float(w["damping"]); d.mu0_4pi = float(w["mu0_4pi"])
+        d.k_contact = float(w["k_contact"]); d.r_contact = float(w["r_contact"])
+        d.dipole_on = int(bool(w["dipole_on"])); d.contact_on = int(bool(w["contact_on"]))
+        d.exclude_depth = int(w["exclude_depth"])
+        d.precision = prec
+        d.step0 = int(step0)
+        d.graph_steps = int(graph_steps)
+        d.tape_every = int(tape_every)
+        d.tape_capacity = int(tape_capacity)
+        self.desc = d
+        b = L.RodBuffers()
+        b.x, b.v, b.q, b.w = _ptr(self.x), _ptr(self.v), _ptr(self.q), _ptr(self.om)
+        b.force, b.torque = _ptr(self.F), _ptr(self.T)
+        b.m_body, b.field = _ptr(self.m_body), _ptr(self.field)
+        b.ext_force, b.ext_torque = _ptr(self.ext_force), _ptr(self.ext_torque)
+        self.bufs = b
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.stream = s
+        ctx = C.c_void_p()
+        L.check(self.lib.rod_init(C.byref(ctx), C.byref(d), C.byref(b),
+                                  C.c_void_p(s.cuda_stream), 0))
+        self.ctx = ctx
+
+    # ------------------------------------------------------------------ C ABI
+    def step(self, n=1):
+        L.check(self.lib.rod_step(self.ctx, int(n)))
+
+    def sync(self):
+        L.check(self.lib.rod_sync(self.ctx))
+
+    def get_step(self):
+        s = C.c_int64()
+        L.check(self.lib.rod_get_step(self.ctx, C.byref(s)))
+        return s.value
+
+    def eval_forces(self, terms=L.TERM_ALL, with_field=False):
+        torch = self.torch
+        F = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
+        T = torch.empty_like(F)
+        B = torch.empty_like(F) if with_field else None
+        L.check(self.lib.rod_eval_forces(self.ctx, int(terms), _ptr(F), _ptr(T), _ptr(B)))
+        return (F, T, B) if with_field else (F, T)
+
+    def energy(self):
+        out = np.zeros((int(self.w["n_members"]), 9))
+        L.check(self.lib.rod_energy(self.ctx, out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def topology(self):
+        cnt = C.c_int32()
+        L.check(self.lib.rod_topology(self.ctx, None, None, None, 0, C.byref(cnt)))
+        B = cnt.value
+        ij = np.zeros((max(B, 1), 2), np.int32)
+        rr = np.zeros((max(B, 1), 3))
+        K = np.zeros((max(B, 1), 4))
+        L.check(self.lib.rod_topology(self.ctx, ij.ctypes.data_as(C.c_void_p),
+                                      rr.ctypes.data_as(C.c_void_p),
+                                      K.ctypes.data_as(C.c_void_p), B, C.byref(cnt)))
+        return ij[:B], rr[:B], K[:B]
+
+    def contact_pairs(self):
+        cnt = C.c_int32()
+        L.check(self.lib.rod_contact_pairs(self.ctx, None, 0, C.byref(cnt)))
+        P = cnt.value
+        out = np.zeros((max(P, 1), 2), np.int32)
+        L.check(self.lib.rod_contact_pairs(self.ctx, out.ctypes.data_as(C.c_void_p), P,
+                                           C.byref(cnt)))
+        return out[:P]
+
+    def tape_begin(self):
+        L.check(self.lib.rod_tape_begin(self.ctx))
+
+    def grad(self, gx=None, gv=None, gq=None, gw=None, want=("m_body", "field", "x0", "v0",
+                                                            "q0", "w0")):
+        """Reverse the recorded steps; returns a dict of gradient tensors."""
+        torch = self.torch
+        cot = L.RodCotangent(_ptr(gx), _ptr(gv), _ptr(gq), _ptr(gw))
+        shapes = dict(m_body=(3, self.n), field=tuple(self.field.shape), x0=(3, self.n),
+                      v0=(3, self.n), q0=(4, self.n), w0=(3, self.n))
+        outs = {k: torch.zeros(shapes[k], dtype=torch.float64, device=self.device) for k in want}
+        g = L.RodGradients(*[_ptr(outs.get(k)) for k in ("m_body", "field", "x0", "v0", "q0",
+                                                         "w0")])
+        L.check(self.lib.rod_grad(self.ctx, C.byref(cot), C.byref(g)))
+        return outs
+
+    def timing(self, enable=True):
+        """Bracket every kernel launch with HIP events (steps run eagerly while on)."""
+        L.check(self.lib.rod_timing(self.ctx, int(bool(enable))))
+
+    def kernel_times(self):
+        """{kernel: (total_ms, launches)} since the last read."""
+        ms = np.zeros(len(L.KERNELS))
+        cnt = np.zeros(len(L.KERNELS), dtype=np.int64)
+        L.check(self.lib.rod_kernel_times(self.ctx, ms.ctypes.data_as(C.c_void_p),
+                                          cnt.ctypes.data_as(C.c_void_p)))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(L.KERNELS)}
+
+    def free(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            L.check(self.lib.rod_free(self.ctx))
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ helpers
+    def state(self):
+        """Host copy of the state in the workload layout (AoS numpy arrays)."""
+        self.torch.cuda.synchronize(self.device)
+        t = lambda a: a.detach().cpu().numpy().T.copy()
+        return dict(x=t(self.x), v=t(self.v), q=t(self.q), w=t(self.om), F=t(self.F),
+                    T=t(self.T), step=self.get_step())
+
+
+# Entry points under the C names, for callers that prefer the flat API.
+def rod_init(w, **kw):
+    return RodSim(w, **kw)
+
+
+def rod_step(sim, n=1):
+    sim.step(n)
+
+
+def rod_energy(sim):
+    return sim.energy()
+
+
+def rod_grad(sim, **kw):
+    return sim.grad(**kw)
+
+
+def rod_free(sim):
+    sim.free()
