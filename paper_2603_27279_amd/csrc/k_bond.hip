@@ -107,11 +107,12 @@ __global__ __launch_bounds__(256) void k_bond(Dev d, int want_energy) {
 }
 
 hipError_t launch_bond(const Dev& d, int precision, int want_energy, hipStream_t s) {
-  dim3 grid((unsigned)((d.n + 255) / 256));
+  const int bs = particle_block(d.n);
+  dim3 grid((unsigned)((d.n + bs - 1) / bs));
   if (precision == 1)
-    hipLaunchKernelGGL(k_bond<float>, grid, dim3(256), 0, s, d, want_energy);
+    hipLaunchKernelGGL(k_bond<float>, grid, dim3(bs), 0, s, d, want_energy);
   else
-    hipLaunchKernelGGL(k_bond<double>, grid, dim3(256), 0, s, d, want_energy);
+    hipLaunchKernelGGL(k_bond<double>, grid, dim3(bs), 0, s, d, want_energy);
   return hipGetLastError();
 }
 

@@ -3,11 +3,16 @@
 // depth (Methods, "Contact", with the normal-only Hookean law of the workloads).
 //
 // Candidates come from the hashed cell list built by the pre kernel (cell side
-// r_c, 27 neighbouring cells, plus the short list of particles whose cell was
-// full). The selection r^2 = (dx dx + dy dy) + dz dz < r_c^2 is evaluated with
-// explicitly rounded FP64 operations (no contraction), so the pair set is
-// exactly that of a brute-force search with the same expression. Each
-// particle's contacts are kept sorted by j and summed in that order.
+// r_c) plus the short list of particles whose cell was full. The search is
+// lane-parallel: half a wavefront serves one particle, lane c (0..26) scans
+// neighbouring cell c, whose count and slots (each slot holds the particle's
+// position and tag) are fetched in a single round trip. Lanes whose hash
+// bucket repeats a lower lane's bucket stand down, so no pair is seen twice.
+// The selection r^2 = (dx dx + dy dy) + dz dz < r_c^2 uses explicitly rounded
+// FP64 operations (no contraction), so the pair set is exactly that of a
+// brute-force search with the same expression. Per-lane sums are kept in
+// 2^-48 fixed point and added across lanes as integers: the result does not
+// depend on the order in which particles were inserted into their cells.
 #include "rod_internal.h"
 #include "rod_math.h"
 
@@ -29,76 +34,91 @@ __device__ __forceinline__ double r2_exact(V3<double> a, V3<double> b) {
   return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
 }
 
-// Visit every candidate j of particle i (duplicates possible when cells share
-// a hash bucket) and keep the accepted ones, sorted and unique, in `list`.
-__device__ __forceinline__ int gather_contacts(const Dev& d, long i, int* list, bool& ovf) {
+constexpr double FIX = 281474976710656.0;  // 2^48
+__device__ __forceinline__ long long to_fix(double v) { return __double2ll_rn(v * FIX); }
+
+// Sum over the 32 lanes of each half wave (integer adds: exact, any order).
+__device__ __forceinline__ long long half_sum(long long v) {
+  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
+  return v;
+}
+
+enum ContactOut { OUT_FORCE = 0, OUT_ENERGY = 1, OUT_PAIRS = 2 };
+
+// One pass of the search; what is produced depends on `OUT`.
+template <int OUT>
+__device__ __forceinline__ void contact_pass(const Dev& d, int* pairs, int cap, int* count) {
   const long N = d.n;
-  const V3<double> xi = ld3(d.x, N, i);
-  const int mem = d.mem[i], rod = d.rod[i];
+  const int lane = threadIdx.x & 31;
+  const long i = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
+  const bool pv = i < N;
+  const long ii = pv ? i : 0;
+  const V3<double> xi = ld3(d.x, N, ii);
+  const int mem = d.mem[ii], rod = d.rod[ii];
+  const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
   const double rc2 = d.rc * d.rc;
   const int cx = cell_coord_c(xi.x, d.inv_cell), cy = cell_coord_c(xi.y, d.inv_cell),
             cz = cell_coord_c(xi.z, d.inv_cell);
-  int cnt = 0;
-  auto consider = [&](int j) {
-    if (j == (int)i || d.mem[j] != mem) return;
-    if (d.rod[j] == rod && abs(j - (int)i) <= d.depth) return;
-    if (!(r2_exact(xi, ld3(d.x, N, j)) < rc2)) return;
-    int p = cnt;
-    while (p > 0 && list[p - 1] > j) --p;
-    if (p > 0 && list[p - 1] == j) return;  // already listed
-    if (cnt == CONTACT_MAX) { ovf = true; return; }
-    for (int s = cnt; s > p; --s) list[s] = list[s - 1];
-    list[p] = j;
-    ++cnt;
-  };
-  for (int oz = -1; oz <= 1; ++oz)
-    for (int oy = -1; oy <= 1; ++oy)
-      for (int ox = -1; ox <= 1; ++ox) {
-        unsigned key = cell_hash_c(cx + ox, cy + oy, cz + oz, mem, d.cell_mask);
-        int nb = min(d.cell_cnt[key], CELL_CAP);
-        const int* slot = d.cell_slot + (long)key * CELL_CAP;
-        for (int s = 0; s < nb; ++s) consider(slot[s]);
+  const int c = lane < 27 ? lane : 0;
+  const unsigned key = cell_hash_c(cx + c % 3 - 1, cy + (c / 3) % 3 - 1, cz + c / 9 - 1, mem,
+                                   d.cell_mask);
+  bool scan = pv && lane < 27;
+  for (int o = 0; o < 26; ++o) {  // stand down if a lower lane has the same bucket
+    unsigned ko = __shfl(key, o, 32);
+    if (o < lane && ko == key) scan = false;
+  }
+  long long fx = 0, fy = 0, fz = 0, fe = 0;
+  auto take = [&](int j, int rj, V3<double> xj) {
+    if (j == (int)i || j < mb || j >= me) return;
+    if (rj == rod && abs(j - (int)i) <= d.depth) return;
+    const double r2 = r2_exact(xi, xj);
+    if (!(r2 < rc2)) return;
+    if (OUT == OUT_PAIRS) {
+      if (j > (int)i) {
+        int p = atomicAdd(count, 1);
+        if (p < cap) { pairs[2 * p] = (int)i; pairs[2 * p + 1] = j; }
       }
-  int no = min(*d.ovf_cnt, OVF_CAP);
-  for (int o = 0; o < no; ++o) consider(d.ovf_list[o]);
-  return cnt;
-}
-
-__global__ __launch_bounds__(256) void k_contact(Dev d, int want_energy) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long N = d.n;
-  if (i >= N) return;
-  int list[CONTACT_MAX];
-  bool ovf = false;
-  const int cnt = gather_contacts(d, i, list, ovf);
-  if (ovf) atomicOr(&d.flags[FLAG_CONTACT_OVF], 1u);
-  const V3<double> xi = ld3(d.x, N, i);
-  V3<double> F{0.0, 0.0, 0.0};
-  double E = 0.0;
-  for (int k = 0; k < cnt; ++k) {
-    const V3<double> dd = xi - ld3(d.x, N, list[k]);
-    const double r = sqrt(r2_exact(xi, ld3(d.x, N, list[k])));
+      return;
+    }
+    const double r = sqrt(r2);
     const double ov = d.rc - r;
-    F = F + ((d.kc * ov) / r) * dd;
-    E += 0.25 * d.kc * ov * ov;  // each pair is seen from both ends
+    const double s = (d.kc * ov) / r;
+    fx += to_fix(s * (xi.x - xj.x));
+    fy += to_fix(s * (xi.y - xj.y));
+    fz += to_fix(s * (xi.z - xj.z));
+    if (OUT == OUT_ENERGY) fe += to_fix(0.25 * d.kc * ov * ov);  // each pair seen from both ends
+  };
+  if (scan) {
+    const CellSlot* sl = d.cell_slot + (long)key * CELL_CAP;
+    const int nb = min(d.cell_cnt[key], CELL_CAP);
+    CellSlot e[CELL_CAP];
+#pragma unroll
+    for (int s = 0; s < CELL_CAP; ++s) e[s] = sl[s];  // slots beyond the count are ignored
+#pragma unroll
+    for (int s = 0; s < CELL_CAP; ++s)
+      if (s < nb) take((int)(e[s].tag & 0xffffffffll), (int)(e[s].tag >> 32),
+                       V3<double>{e[s].x, e[s].y, e[s].z});
   }
-  st3(d.cF, N, i, F);
-  if (want_energy) d.cE[i] = E;
+  if (pv && lane == 27) {  // particles whose cell was full
+    const int no = min(*d.ovf_cnt, OVF_CAP);
+    for (int o = 0; o < no; ++o) {
+      const int j = d.ovf_list[o];
+      take(j, d.rod[j], ld3(d.x, N, j));
+    }
+  }
+  if (OUT == OUT_PAIRS) return;
+  fx = half_sum(fx); fy = half_sum(fy); fz = half_sum(fz);
+  if (OUT == OUT_ENERGY) fe = half_sum(fe);
+  if (pv && lane == 0) {
+    st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
+    if (OUT == OUT_ENERGY) d.cE[i] = (double)fe / FIX;
+  }
 }
 
-// Debug/inspection: append every pair (i < j) found by the cell list.
+__global__ __launch_bounds__(256) void k_contact(Dev d) { contact_pass<OUT_FORCE>(d, nullptr, 0, nullptr); }
+__global__ __launch_bounds__(256) void k_contact_e(Dev d) { contact_pass<OUT_ENERGY>(d, nullptr, 0, nullptr); }
 __global__ __launch_bounds__(256) void k_contact_pairs(Dev d, int* pairs, int cap, int* count) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.n) return;
-  int list[CONTACT_MAX];
-  bool ovf = false;
-  const int cnt = gather_contacts(d, i, list, ovf);
-  if (ovf) atomicOr(&d.flags[FLAG_CONTACT_OVF], 1u);
-  for (int k = 0; k < cnt; ++k) {
-    if (list[k] <= (int)i) continue;
-    int p = atomicAdd(count, 1);
-    if (p < cap) { pairs[2 * p] = (int)i; pairs[2 * p + 1] = list[k]; }
-  }
+  contact_pass<OUT_PAIRS>(d, pairs, cap, count);
 }
 
 // Empty the cell list built by a pre pass that had no particle pass after it.
@@ -114,16 +134,20 @@ hipError_t launch_clear_cells(const Dev& d, hipStream_t s) {
   return hipGetLastError();
 }
 
+static inline unsigned contact_blocks(long n) { return (unsigned)((32 * n + 255) / 256); }
+
 hipError_t launch_contact(const Dev& d, int want_energy, hipStream_t s) {
   if (!d.contact_on) return hipSuccess;
-  hipLaunchKernelGGL(k_contact, dim3((unsigned)((d.n + 255) / 256)), dim3(256), 0, s, d,
-                     want_energy);
+  if (want_energy)
+    hipLaunchKernelGGL(k_contact_e, dim3(contact_blocks(d.n)), dim3(256), 0, s, d);
+  else
+    hipLaunchKernelGGL(k_contact, dim3(contact_blocks(d.n)), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 
 hipError_t launch_contact_pairs(const Dev& d, int* pairs, int cap, int* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_contact_pairs, dim3((unsigned)((d.n + 255) / 256)), dim3(256), 0, s, d,
-                     pairs, cap, count);
+  hipLaunchKernelGGL(k_contact_pairs, dim3(contact_blocks(d.n)), dim3(256), 0, s, d, pairs, cap,
+                     count);
   return hipGetLastError();
 }
 

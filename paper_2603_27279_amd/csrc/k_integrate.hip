@@ -44,9 +44,11 @@ __device__ __forceinline__ unsigned cell_hash(int cx, int cy, int cz, int mem, u
 
 __global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n = d.step[0];
+  const long long lvl = n + (mode == PRE_STEP ? 1 : 0);  // level of the coming force evaluation
+  if (i == 0) d.step[1] = lvl;
   if (i >= d.n) return;
   const long N = d.n;
-  const long long n = *d.step;
   const int b = d.bc[i];
   Q4<double> q = ld4(d.q, N, i);
   if (mode == PRE_STEP) {
@@ -89,7 +91,10 @@ __global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
                              cell_coord(x.z, d.inv_cell), d.mem[i], d.cell_mask);
     int slot = atomicAdd(&d.cell_cnt[key], 1);
     if (slot < CELL_CAP) {
-      d.cell_slot[(long)key * CELL_CAP + slot] = (int)i;
+      CellSlot e;
+      e.x = x.x; e.y = x.y; e.z = x.z;
+      e.tag = (long long)(unsigned)i | ((long long)d.rod[i] << 32);
+      d.cell_slot[(long)key * CELL_CAP + slot] = e;
     } else {
       int o = atomicAdd(d.ovf_cnt, 1);
       if (o < OVF_CAP) d.ovf_list[o] = (int)i;
@@ -107,9 +112,12 @@ __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double*
                                               double* Bo) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long N = d.n;
-  const long long n = *d.step;
+  const long long lvl = d.step[1];  // level of the forces being gathered
+  if (i == 0) {
+    if (mode == POST_KICK) d.step[0] = lvl;
+    *d.ovf_cnt = 0;  // the contact pass that used the overflow list has finished
+  }
   if (i < N) {
-    const long long lvl = n + (mode == POST_KICK ? 1 : 0);
     V3<double> F{0.0, 0.0, 0.0}, T{0.0, 0.0, 0.0};
     const uint8_t bf = d.bflags[i];
     if (mask & 1) {  // bonds: +F, tau_s + tau_bt from bond (i, i+1); -F, tau_s - tau_bt from (i-1, i)
@@ -126,12 +134,23 @@ __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double*
     const int mem = d.mem[i];
     V3<double> Bd{0.0, 0.0, 0.0};
     if ((mask & 2) && d.dipole_on) {  // dipole-dipole: sum of the partial slots, torque m x B_dip
+      // Slots are added in slot order; eight slots are fetched per round trip.
       V3<double> Fd{0.0, 0.0, 0.0};
       const int S = d.mslots[mem];
-      for (int s = 0; s < S; ++s) {
-        const double* p = d.dpart + (long)s * 6 * N;
-        Fd = Fd + V3<double>{p[i], p[N + i], p[2 * N + i]};
-        Bd = Bd + V3<double>{p[3 * N + i], p[4 * N + i], p[5 * N + i]};
+      for (int s0 = 0; s0 < S; s0 += 8) {
+        double v[8][6];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const double* p = d.dpart + (long)(s0 + k) * 6 * N;
+          if (s0 + k < S)
+            for (int c = 0; c < 6; ++c) v[k][c] = p[c * N + i];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (s0 + k < S) {
+            Fd = Fd + V3<double>{v[k][0], v[k][1], v[k][2]};
+            Bd = Bd + V3<double>{v[k][3], v[k][4], v[k][5]};
+          }
       }
       F = F + Fd;
       T = T + cross(m, Bd);
@@ -175,19 +194,6 @@ __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double*
     }
     if (d.contact_on) d.cell_cnt[d.key[i]] = 0;  // empty the cell list for the next build
   }
-  // The last block to finish advances the time level and resets the overflow list;
-  // every other block has read the level before it counted itself done.
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned t = atomicAdd(d.done, 1u);
-    if (t == gridDim.x - 1) {
-      if (mode == POST_KICK) *d.step = n + 1;
-      *d.ovf_cnt = 0;
-      *d.done = 0;
-      __threadfence();
-    }
-  }
 }
 
 // Per-particle energy terms [9][N]: bond terms attributed to the bond's first
@@ -196,7 +202,7 @@ __global__ __launch_bounds__(256) void k_energy_part(Dev d, const double* Bdip, 
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long N = d.n;
   if (i >= N) return;
-  const long long lvl = *d.step;
+  const long long lvl = d.step[1];
   const bool hb = d.bflags[i] & 1;
   for (int t = 0; t < 4; ++t) E[t * N + i] = hb ? d.bE[t * N + i] : 0.0;
   const V3<double> m = ld3(d.mu, N, i);
@@ -238,13 +244,15 @@ __global__ __launch_bounds__(256) void k_energy_reduce(Dev d, const double* E, d
 static inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 hipError_t launch_pre(const Dev& d, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_pre, dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, mode);
+  const int bs = particle_block(d.n);
+  hipLaunchKernelGGL(k_pre, dim3(blocks_for(d.n, bs)), dim3(bs), 0, s, d, mode);
   return hipGetLastError();
 }
 
 hipError_t launch_post(const Dev& d, int mode, int mask, double* Fo, double* To, double* Bo,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_post, dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, mode, mask, Fo, To,
+  const int bs = particle_block(d.n);
+  hipLaunchKernelGGL(k_post, dim3(blocks_for(d.n, bs)), dim3(bs), 0, s, d, mode, mask, Fo, To,
                      Bo);
   return hipGetLastError();
 }

@@ -51,7 +51,6 @@ struct rod_ctx {
   std::vector<void*> allocs;
   DipWork* work = nullptr;
   int nwork = 0, max_slots = 1, dip_chunk = 0;
-  std::vector<int> mslots_h;
   double* epart = nullptr;
   double* eout = nullptr;
   int* pair_count = nullptr;
@@ -188,28 +187,27 @@ static int validate(const rod_desc* d) {
 
 // Dipole work list: blocks of 256 i against j chunks of the same member; the
 // chunk count per member is chosen so the launch holds at least ~2048 work items.
-static int build_dipole_plan(rod_ctx* c, const std::vector<int>& mrange, int chunk_override) {
+static int build_dipole_plan(rod_ctx* c, const std::vector<int>& mrange, int target_wgs) {
   const int M = c->desc.n_members;
+  const long N = c->desc.n_particles;
   long iblocks = 0;
-  for (int m = 0; m < M; ++m) iblocks += (mrange[2 * m + 1] - mrange[2 * m] + 255) / 256;
-  const long target = 2048;
+  for (int m = 0; m < M; ++m) iblocks += (mrange[2 * m + 1] - mrange[2 * m] + 63) / 64;
   std::vector<DipWork> items;
-  c->mslots_h.assign(M, 1);
+  std::vector<int> mslots(M, 1);
   int max_slots = 1;
   for (int m = 0; m < M; ++m) {
     const int b = mrange[2 * m], e = mrange[2 * m + 1], nm = e - b;
-    int S;
-    if (chunk_override > 0) S = (nm + chunk_override - 1) / chunk_override;
-    else S = (int)std::min<long>((target + iblocks - 1) / iblocks, (nm + 255) / 256);
+    // enough j ranges to give the launch ~target_wgs work items, each of at least one tile
+    int S = (int)std::min<long>((target_wgs + iblocks - 1) / iblocks, (nm + 255) / 256);
     S = std::max(S, 1);
     const int len = (nm + S - 1) / S;
     S = (nm + len - 1) / len;
-    c->mslots_h[m] = S;
+    mslots[m] = S;
     max_slots = std::max(max_slots, S);
-    for (int i0 = b; i0 < e; i0 += 256)
+    for (int i0 = b; i0 < e; i0 += 64)
       for (int s = 0; s < S; ++s) {
         DipWork w{};
-        w.i0 = i0; w.i1 = std::min(i0 + 256, e);
+        w.i0 = i0; w.i1 = std::min(i0 + 64, e);
         w.j0 = b + s * len; w.j1 = std::min(e, b + (s + 1) * len);
         w.slot = s;
         items.push_back(w);
@@ -221,9 +219,9 @@ static int build_dipole_plan(rod_ctx* c, const std::vector<int>& mrange, int chu
   HIPC(hipMemcpy(c->work, items.data(), items.size() * sizeof(DipWork), hipMemcpyHostToDevice));
   int* ms = nullptr;
   TRY(dalloc(c, &ms, M));
-  HIPC(hipMemcpy(ms, c->mslots_h.data(), M * sizeof(int), hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ms, mslots.data(), M * sizeof(int), hipMemcpyHostToDevice));
   c->d.mslots = ms;
-  TRY(dalloc(c, &c->d.dpart, (size_t)max_slots * 6 * c->desc.n_particles));
+  TRY(dalloc(c, &c->d.dpart, (size_t)max_slots * 6 * N));
   return ROD_OK;
 }
 
@@ -234,7 +232,7 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
   b += N * (1 + 4 + 4 + 1) + 8 * N * 4 + 8 * N * 4 + 8 * R * 4 + 4 * M * 3;  // topology
   b += 8 * 3 * N + 4 * 3 * N + 8 * 9 * N + 8 * 4 * N;                         // mu, bonds
   b += 8 * (size_t)max_slots * 6 * N + 8 * 4 * N;                               // dipole, contact
-  b += 4 * cells * (1 + CELL_CAP) + 4 * N + 4 * OVF_CAP;                        // cells
+  b += 4 * cells + sizeof(CellSlot) * cells * CELL_CAP + 4 * N + 4 * OVF_CAP;  // cells
   b += 8 * 18 * N + 8 * 9 * M;                                                  // energy
   return b;
 }
@@ -400,7 +398,7 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
       (rc = dalloc(c, &d.cF, 3 * (size_t)N)) || (rc = dalloc(c, &d.cE, (size_t)N)) ||
       (rc = dalloc(c, &d.key, (size_t)N)) || (rc = dalloc(c, &d.ovf_list, (size_t)OVF_CAP)) ||
       (rc = dalloc(c, &d.ovf_cnt, 1)) || (rc = dalloc(c, &d.flags, 4)) ||
-      (rc = dalloc(c, &d.step, 1)) || (rc = dalloc(c, &d.done, 1)) ||
+      (rc = dalloc(c, &d.step, 2)) ||
       (rc = dalloc(c, &c->epart, 18 * (size_t)N)) || (rc = dalloc(c, &c->eout, 9 * (size_t)M)) ||
       (rc = dalloc(c, &c->pair_count, 1)))
     return cleanup(rc);
@@ -420,10 +418,10 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
     for (int k = 0; k < 3; ++k) d.axis[k] = a > 0 ? dsc->drive_axis[k] / a : 0.0;
   }
   d.period = dsc->drive_period > 0 ? dsc->drive_period : 1;
-  long long s0 = dsc->step0;
-  if (hipMemcpy(d.step, &s0, sizeof(s0), hipMemcpyHostToDevice) != hipSuccess)
+  long long s0[2] = {dsc->step0, dsc->step0};
+  if (hipMemcpy(d.step, s0, sizeof(s0), hipMemcpyHostToDevice) != hipSuccess)
     return cleanup(fail(ROD_E_HIP, "upload failed"));
-  if ((rc = build_dipole_plan(c, mrange, 0))) return cleanup(rc);
+  if ((rc = build_dipole_plan(c, mrange, 1024))) return cleanup(rc);
   // descriptor host pointers are not kept
   c->desc.rod_offset = nullptr; c->desc.rod_member = nullptr; c->desc.rod_params = nullptr;
   c->desc.x_ref = nullptr; c->desc.bc = nullptr;
@@ -485,9 +483,8 @@ int rod_sync(rod_ctx* c) {
     unsigned z[4] = {0, 0, 0, 0};
     HIPC(hipMemcpy(c->d.flags, z, sizeof(z), hipMemcpyHostToDevice));
     if (f[FLAG_NONFINITE]) return fail(ROD_E_NONFINITE, "non-finite force, torque or position");
-    return fail(ROD_E_OVERFLOW, "contact search capacity exceeded (%s)",
-                f[FLAG_CONTACT_OVF] ? "more than 32 contacts on a particle"
-                                    : "overflow list of full cells");
+    return fail(ROD_E_OVERFLOW, "contact search capacity exceeded: more than %d particles "
+                "landed in full cells", OVF_CAP);
   }
   return ROD_OK;
 }

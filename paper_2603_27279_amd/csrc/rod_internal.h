@@ -5,6 +5,10 @@
 
 namespace rodmx {
 
+// One entry of the hashed cell list: the particle's position at insertion and
+// a tag holding its index (low 32 bits) and rod (high 32 bits).
+struct alignas(32) CellSlot { double x, y, z; long long tag; };
+
 // Device-side view of one context: every pointer is a device pointer, fixed for
 // the lifetime of the context, so that captured graphs can be replayed.
 struct Dev {
@@ -22,24 +26,25 @@ struct Dev {
   const double* bref;      // [4N]: reference bond vector planes x, y, z and its length r0
   const double* rodK;      // [R][4]: EA, 12EI, GJ, EI
   const int* mrange;       // [2M]: member particle range [begin, end)
-  const int* mslots;       // [M]: dipole partial slots used by the member
   // per-step work buffers
   double* mu;              // [3N] global dipole moments
   float* muf;              // [3N] FP32 copy for the mixed dipole kernel
   double *bF, *bTs, *bTbt; // [3N] per-bond outputs (index = first particle)
   double* bE;              // [4N] per-bond energies (energy evaluation only)
-  double* dpart;           // [S][6][N] dipole partial sums (F then B)
+  double* dpart;           // [S][6][N] dipole partial sums (F then B), one slot per j range
+  const int* mslots;       // [M]: j ranges (partial slots) of each member
   double* cF;              // [3N] contact force
   double* cE;              // [N] contact energy per particle (energy evaluation only)
   int* cell_cnt;           // [cells] particles hashed to each cell
-  int* cell_slot;          // [cells][CELL_CAP] particle indices
+  CellSlot* cell_slot;     // [cells][CELL_CAP] position and tag of each listed particle
   int* key;                // [N] cell of each particle
   int* ovf_list;           // [OVF_CAP] particles whose cell was full
-  int* ovf_cnt;            // [1]
+  int* ovf_cnt;            // [1] entries of the overflow list (reset by the particle kernel)
   unsigned cell_mask;      // cells - 1 (power of two)
-  unsigned* flags;         // [4]: non-finite, contact overflow, overflow-list overflow
-  long long* step;         // time level of the state
-  unsigned* done;          // block counter for the step advance
+  unsigned* flags;         // [4]: [0] non-finite state, [2] overflow list full
+  long long* step;         // [2]: [0] time level of the state (written by the particle
+                           // kernel), [1] level of the force evaluation in flight
+                           // (written by the pre kernel); no kernel writes what it reads
   // parameters
   double dt, damping, C, kc, rc, inv_cell;
   int depth, field_len, dipole_on, contact_on;
@@ -49,15 +54,19 @@ struct Dev {
 
 constexpr int CELL_CAP = 8;
 constexpr int OVF_CAP = 4096;
-constexpr int CONTACT_MAX = 32;  // contacts per particle
-enum { FLAG_NONFINITE = 0, FLAG_CONTACT_OVF = 1, FLAG_LIST_OVF = 2 };
+enum { FLAG_NONFINITE = 0, FLAG_LIST_OVF = 2 };
 
 enum PreMode { PRE_PREPARE = 0, PRE_STEP = 1, PRE_EVAL = 2 };
 enum PostMode { POST_PREPARE = 0, POST_KICK = 1, POST_EVAL = 2 };
 
-// One dipole work item: members' i-block [i0, i0+256) clipped to the member,
-// against j in [j0, j1), written to partial slot `slot`.
+// One dipole work item: an i block [i0, i1) of at most 64 particles of one
+// member against j in [j0, j1) of the same member,
+// written to partial slot `slot`.
 struct DipWork { int i0, i1, j0, j1, slot, pad0, pad1, pad2; };
+
+// Threads per block of the per-particle kernels: small blocks spread small
+// systems over more compute units.
+inline int particle_block(long n) { return n < 65536 ? 64 : 256; }
 
 // Kernel launchers (each enqueues on `s`; return the launch status).
 hipError_t launch_pre(const Dev& d, int mode, hipStream_t s);
