@@ -65,6 +65,50 @@ def cpu_baseline(w, target_s=15.0):
                       f"{dt:.2f} s"}
 
 
+def adjoint_leg():
+    """Adjoint cost on the adjoint-rod workload (N = 256, T = 2000, checkpoints
+    every 100): wall time of rod_grad against the taped forward run that
+    precedes it and against the plain graph-replayed forward run."""
+    import torch
+    import workloads
+    from paper_2603_27279_amd import RodSim
+    w = workloads.make("adjoint_rod")
+    T = w["steps"]
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    plain = RodSim(w, precision="fp64", graph_steps=100)
+    plain.step(100)
+    plain.sync()
+    t_plain = timed(lambda: (plain.step(T), plain.sync()))
+    plain.free()
+    sim = RodSim(w, precision="fp64", tape_every=w["tape_every"], tape_capacity=T)
+    # one untimed pass to warm up every kernel of the reverse pass
+    sim.tape_begin()
+    sim.step(w["tape_every"])
+    sim.grad(gx=torch.zeros((3, w["n"]), dtype=torch.float64, device="cuda"))
+    sim.free()
+    sim = RodSim(w, precision="fp64", tape_every=w["tape_every"], tape_capacity=T)
+    sim.tape_begin()
+    t_fwd = timed(lambda: (sim.step(T), sim.sync()))
+    st = sim.state()
+    gx = np.zeros((w["n"], 3))
+    gx[-1] = 2.0 * (st["x"][-1] - w["target"])
+    gxt = torch.as_tensor(np.ascontiguousarray(gx.T), device="cuda")
+    t_grad = timed(lambda: sim.grad(gx=gxt))
+    sim.free()
+    return {"workload": f"adjoint rod N={w['n']}, T={T} steps, checkpoints every {w['tape_every']}",
+            "forward_ms": 1e3 * t_plain, "forward_taped_ms": 1e3 * t_fwd,
+            "grad_ms": 1e3 * t_grad, "adjoint_over_taped_forward": t_grad / t_fwd,
+            "adjoint_over_forward": t_grad / t_plain,
+            "total_over_forward": (t_fwd + t_grad) / t_plain}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +120,7 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -123,6 +168,8 @@ def main():
                 "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": pairs}
     sim.free()
 
+    adj = None if args.no_adjoint else adjoint_leg()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_seconds)
@@ -147,6 +194,7 @@ def main():
         "pair_evals_per_s": pairs * args.steps / secs if pairs else None,
         "kernel_us": kernels_us,
         "roofline": roof,
+        "adjoint": adj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -115,8 +115,67 @@ __device__ __forceinline__ void contact_pass(const Dev& d, int* pairs, int cap, 
   }
 }
 
+// Variant for large systems: one thread per particle walks the 27 cells, each
+// non-empty cell costing one round trip for the slots it actually holds (far
+// less traffic than 27 lanes fetching whole cells when latency is already
+// hidden by the number of particles). Same selection, same exact sums.
+template <int OUT>
+__device__ __forceinline__ void contact_thread(const Dev& d) {
+  const long N = d.n;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const V3<double> xi = ld3(d.x, N, i);
+  const int mem = d.mem[i], rod = d.rod[i];
+  const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
+  const double rc2 = d.rc * d.rc;
+  const int cx = cell_coord_c(xi.x, d.inv_cell), cy = cell_coord_c(xi.y, d.inv_cell),
+            cz = cell_coord_c(xi.z, d.inv_cell);
+  long long fx = 0, fy = 0, fz = 0, fe = 0;
+  auto take = [&](int j, int rj, V3<double> xj) {
+    if (j == (int)i || j < mb || j >= me) return;
+    if (rj == rod && abs(j - (int)i) <= d.depth) return;
+    const double r2 = r2_exact(xi, xj);
+    if (!(r2 < rc2)) return;
+    const double r = sqrt(r2);
+    const double ov = d.rc - r;
+    const double s = (d.kc * ov) / r;
+    fx += to_fix(s * (xi.x - xj.x));
+    fy += to_fix(s * (xi.y - xj.y));
+    fz += to_fix(s * (xi.z - xj.z));
+    if (OUT == OUT_ENERGY) fe += to_fix(0.25 * d.kc * ov * ov);
+  };
+  unsigned keys[27];
+  int nc[27];
+#pragma unroll
+  for (int c = 0; c < 27; ++c)
+    keys[c] = cell_hash_c(cx + c % 3 - 1, cy + (c / 3) % 3 - 1, cz + c / 9 - 1, mem, d.cell_mask);
+#pragma unroll
+  for (int c = 0; c < 27; ++c) nc[c] = d.cell_cnt[keys[c]];
+  for (int c = 0; c < 27; ++c) {
+    int nb = min(nc[c], CELL_CAP);
+    for (int o = 0; o < c; ++o)
+      if (keys[o] == keys[c]) nb = 0;  // bucket already visited
+    const CellSlot* sl = d.cell_slot + (long)keys[c] * CELL_CAP;
+    for (int s = 0; s < nb; ++s) {
+      const CellSlot e = sl[s];
+      take((int)(e.tag & 0xffffffffll), (int)(e.tag >> 32), V3<double>{e.x, e.y, e.z});
+    }
+  }
+  const int no = min(*d.ovf_cnt, OVF_CAP);
+  for (int o = 0; o < no; ++o) {
+    const int j = d.ovf_list[o];
+    take(j, d.rod[j], ld3(d.x, N, j));
+  }
+  st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
+  if (OUT == OUT_ENERGY) d.cE[i] = (double)fe / FIX;
+}
+
+constexpr long CONTACT_LANES_MAX_N = 65536;  // below: 27 lanes per particle
+
 __global__ __launch_bounds__(256) void k_contact(Dev d) { contact_pass<OUT_FORCE>(d, nullptr, 0, nullptr); }
 __global__ __launch_bounds__(256) void k_contact_e(Dev d) { contact_pass<OUT_ENERGY>(d, nullptr, 0, nullptr); }
+__global__ __launch_bounds__(256) void k_contact_t(Dev d) { contact_thread<OUT_FORCE>(d); }
+__global__ __launch_bounds__(256) void k_contact_te(Dev d) { contact_thread<OUT_ENERGY>(d); }
 __global__ __launch_bounds__(256) void k_contact_pairs(Dev d, int* pairs, int cap, int* count) {
   contact_pass<OUT_PAIRS>(d, pairs, cap, count);
 }
@@ -138,6 +197,12 @@ static inline unsigned contact_blocks(long n) { return (unsigned)((32 * n + 255)
 
 hipError_t launch_contact(const Dev& d, int want_energy, hipStream_t s) {
   if (!d.contact_on) return hipSuccess;
+  if (d.n >= CONTACT_LANES_MAX_N) {
+    const unsigned g = (unsigned)((d.n + 255) / 256);
+    if (want_energy) hipLaunchKernelGGL(k_contact_te, dim3(g), dim3(256), 0, s, d);
+    else hipLaunchKernelGGL(k_contact_t, dim3(g), dim3(256), 0, s, d);
+    return hipGetLastError();
+  }
   if (want_energy)
     hipLaunchKernelGGL(k_contact_e, dim3(contact_blocks(d.n)), dim3(256), 0, s, d);
   else

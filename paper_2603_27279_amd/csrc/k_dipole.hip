@@ -33,33 +33,39 @@ constexpr int JW = 64;    // j entries of a tile handled by one wave
 template <class R>
 struct Acc { R fx, fy, fz, fm, bx, by, bz; };
 
+// Add the contribution of source j (position xj, moment mj) to target i.
+template <class R>
+__device__ __forceinline__ void pair_acc(R dx, R dy, R dz, R mjx, R mjy, R mjz, R mix, R miy,
+                                         R miz, R rinv, Acc<R>& A) {
+  const R rinv2 = rinv * rinv;
+  const R rinv3 = rinv2 * rinv;
+  const R s = (R(3) * rinv3) * rinv2;
+  const R a = fma_(miz, dz, fma_(miy, dy, mix * dx));
+  const R b = fma_(mjz, dz, fma_(mjy, dy, mjx * dx));
+  const R c = fma_(miz, mjz, fma_(miy, mjy, mix * mjx));
+  const R sb = s * b, sa = s * a;
+  const R al = fma_((sb * a) * rinv2, R(-5), s * c);
+  A.fx = fma_(sa, mjx, fma_(al, dx, A.fx));
+  A.fy = fma_(sa, mjy, fma_(al, dy, A.fy));
+  A.fz = fma_(sa, mjz, fma_(al, dz, A.fz));
+  A.fm += sb;
+  A.bx = fma_(-rinv3, mjx, fma_(sb, dx, A.bx));
+  A.by = fma_(-rinv3, mjy, fma_(sb, dy, A.by));
+  A.bz = fma_(-rinv3, mjz, fma_(sb, dz, A.bz));
+}
+
 template <class R, bool SELF>
 __device__ __forceinline__ void tile_pairs(int jb, int je, int jbase, int i, double xi, double yi,
                                            double zi, R mix, R miy, R miz, const double* sx,
                                            const double* sy, const double* sz, const R* smx,
                                            const R* smy, const R* smz, Acc<R>& A) {
-#pragma unroll 4
+#pragma unroll 2
   for (int jj = jb; jj < je; ++jj) {
     const R dx = (R)(xi - sx[jj]), dy = (R)(yi - sy[jj]), dz = (R)(zi - sz[jj]);
-    const R mjx = smx[jj], mjy = smy[jj], mjz = smz[jj];
     const R r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
     R rinv = rsq(r2);
     if (SELF) rinv = (jbase + jj == i) ? R(0) : rinv;   // the pair (i, i) contributes nothing
-    const R rinv2 = rinv * rinv;
-    const R rinv3 = rinv2 * rinv;
-    const R s = (R(3) * rinv3) * rinv2;
-    const R a = fma_(miz, dz, fma_(miy, dy, mix * dx));
-    const R b = fma_(mjz, dz, fma_(mjy, dy, mjx * dx));
-    const R c = fma_(miz, mjz, fma_(miy, mjy, mix * mjx));
-    const R sb = s * b, sa = s * a;
-    const R al = fma_((sb * a) * rinv2, R(-5), s * c);
-    A.fx = fma_(sa, mjx, fma_(al, dx, A.fx));
-    A.fy = fma_(sa, mjy, fma_(al, dy, A.fy));
-    A.fz = fma_(sa, mjz, fma_(al, dz, A.fz));
-    A.fm += sb;
-    A.bx = fma_(-rinv3, mjx, fma_(sb, dx, A.bx));
-    A.by = fma_(-rinv3, mjy, fma_(sb, dy, A.by));
-    A.bz = fma_(-rinv3, mjz, fma_(sb, dz, A.bz));
+    pair_acc(dx, dy, dz, smx[jj], smy[jj], smz[jj], mix, miy, miz, rinv, A);
   }
 }
 
@@ -122,13 +128,69 @@ __global__ __launch_bounds__(256) void k_dipole(Dev d, const DipWork* __restrict
   }
 }
 
+// Layout for small members: a workgroup of 1024 threads serves 16 consecutive
+// i of one member; thread (il, jl) visits j = j0 + jl, j0 + jl + 64, ... of
+// the member, so every member pair is spread over the whole workgroup. The
+// 64 partial sums of each i are added by a fixed LDS tree. One slot.
+template <class R>
+__global__ __launch_bounds__(1024) void k_dipole_small(Dev d, const DipWork* __restrict__ work) {
+  __shared__ double red[7][64][16];
+  const DipWork wk = work[blockIdx.x];
+  const long N = d.n;
+  const int il = threadIdx.x & 15, jl = threadIdx.x >> 4;
+  const int i = wk.i0 + il;
+  const bool act = i < wk.i1;
+  const R* mu;
+  if constexpr (sizeof(R) == 4) mu = (const R*)d.muf;
+  else mu = (const R*)d.mu;
+  double xi = 0, yi = 0, zi = 0;
+  R mix = 0, miy = 0, miz = 0;
+  if (act) {
+    xi = d.x[i]; yi = d.x[N + i]; zi = d.x[2 * N + i];
+    mix = mu[i]; miy = mu[N + i]; miz = mu[2 * N + i];
+  }
+  Acc<R> A{0, 0, 0, 0, 0, 0, 0};
+  for (int j = wk.j0 + jl; j < wk.j1; j += 64) {
+    const R dx = (R)(xi - d.x[j]), dy = (R)(yi - d.x[N + j]), dz = (R)(zi - d.x[2 * N + j]);
+    const R r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
+    const R rinv = (j == i) ? R(0) : rsq(r2);
+    pair_acc(dx, dy, dz, mu[j], mu[N + j], mu[2 * N + j], mix, miy, miz, rinv, A);
+  }
+  const double v[7] = {(double)A.fx, (double)A.fy, (double)A.fz, (double)A.fm,
+                       (double)A.bx, (double)A.by, (double)A.bz};
+  for (int k = 0; k < 7; ++k) red[k][jl][il] = v[k];
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
+    if (jl < w)
+      for (int k = 0; k < 7; ++k) red[k][jl][il] += red[k][jl + w][il];
+    __syncthreads();
+  }
+  if (jl == 0 && act) {
+    const double C = d.C;
+    double* p = d.dpart + (long)wk.slot * 6 * N;
+    const double fm = red[3][0][il];
+    p[i] = C * (red[0][0][il] + fm * (double)mix);
+    p[N + i] = C * (red[1][0][il] + fm * (double)miy);
+    p[2 * N + i] = C * (red[2][0][il] + fm * (double)miz);
+    p[3 * N + i] = C * red[4][0][il];
+    p[4 * N + i] = C * red[5][0][il];
+    p[5 * N + i] = C * red[6][0][il];
+  }
+}
+
 hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int nwork,
                          hipStream_t s) {
   if (nwork <= 0) return hipSuccess;
-  if (precision == 1)
+  if (d.dip_small) {
+    if (precision == 1)
+      hipLaunchKernelGGL(k_dipole_small<float>, dim3(nwork), dim3(1024), 0, s, d, work);
+    else
+      hipLaunchKernelGGL(k_dipole_small<double>, dim3(nwork), dim3(1024), 0, s, d, work);
+  } else if (precision == 1) {
     hipLaunchKernelGGL(k_dipole<float>, dim3(nwork), dim3(256), 0, s, d, work);
-  else
+  } else {
     hipLaunchKernelGGL(k_dipole<double>, dim3(nwork), dim3(256), 0, s, d, work);
+  }
   return hipGetLastError();
 }
 

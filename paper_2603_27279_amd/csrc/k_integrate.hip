@@ -50,21 +50,33 @@ __global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
   if (i >= d.n) return;
   const long N = d.n;
   const int b = d.bc[i];
-  Q4<double> q = ld4(d.q, N, i);
+  // state read in place, or from separate planes (out-of-place step)
+  const double* sx = d.src ? d.src : d.x;
+  const double* sv = d.src ? d.src + 3 * N : d.v;
+  const double* sq = d.src ? d.src + 6 * N : d.q;
+  const double* sw = d.src ? d.src + 10 * N : d.w;
+  const double* sF = d.src ? d.src + 13 * N : d.F;
+  const double* sT = d.src ? d.src + 16 * N : d.T;
+  Q4<double> q = ld4(sq, N, i);
   if (mode == PRE_STEP) {
     if (b == 0) {
       const double h = 0.5 * d.dt;
-      V3<double> v = ld3(d.v, N, i) + (h * d.minv[i]) * ld3(d.F, N, i);
-      V3<double> x = ld3(d.x, N, i) + d.dt * v;
-      V3<double> w = ld3(d.w, N, i) + (h * d.Iinv[i]) * ld3(d.T, N, i);
+      V3<double> v = ld3(sv, N, i) + (h * d.minv[i]) * ld3(sF, N, i);
+      V3<double> x = ld3(sx, N, i) + d.dt * v;
+      V3<double> w = ld3(sw, N, i) + (h * d.Iinv[i]) * ld3(sT, N, i);
       q = richardson(q, w, d.dt);
       st3(d.v, N, i, v);
       st3(d.x, N, i, x);
       st3(d.w, N, i, w);
       st4(d.q, N, i, q);
-    } else if (b == 2) {
-      q = drive_q(d, n + 1);
-      st4(d.q, N, i, q);
+    } else {
+      if (b == 2) q = drive_q(d, n + 1);
+      if (d.src || b == 2) st4(d.q, N, i, q);
+      if (d.src) {  // particles that do not move keep their state
+        st3(d.x, N, i, ld3(sx, N, i));
+        st3(d.v, N, i, ld3(sv, N, i));
+        st3(d.w, N, i, ld3(sw, N, i));
+      }
     }
   } else if (mode == PRE_PREPARE) {
     q = qnormalize(q);

@@ -63,6 +63,7 @@ struct rod_ctx {
   hipGraphExec_t gexec = nullptr;
   int gsteps = 0;
   Tape tape;
+  hipGraphExec_t tgexec = nullptr;  // one checkpoint interval of steps, for taped runs
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -191,12 +192,26 @@ static int build_dipole_plan(rod_ctx* c, const std::vector<int>& mrange, int tar
   const int M = c->desc.n_members;
   const long N = c->desc.n_particles;
   long iblocks = 0;
-  for (int m = 0; m < M; ++m) iblocks += (mrange[2 * m + 1] - mrange[2 * m] + 63) / 64;
+  int max_member = 0;
+  for (int m = 0; m < M; ++m) {
+    iblocks += (mrange[2 * m + 1] - mrange[2 * m] + 63) / 64;
+    max_member = std::max(max_member, mrange[2 * m + 1] - mrange[2 * m]);
+  }
+  // Small systems: spread every member pair over 1024-thread workgroups of 16 i.
+  const bool small = iblocks < 512 && max_member <= 2048;
   std::vector<DipWork> items;
   std::vector<int> mslots(M, 1);
   int max_slots = 1;
   for (int m = 0; m < M; ++m) {
     const int b = mrange[2 * m], e = mrange[2 * m + 1], nm = e - b;
+    if (small) {
+      for (int i0 = b; i0 < e; i0 += 16) {
+        DipWork w{};
+        w.i0 = i0; w.i1 = std::min(i0 + 16, e); w.j0 = b; w.j1 = e; w.slot = 0;
+        items.push_back(w);
+      }
+      continue;
+    }
     // enough j ranges to give the launch ~target_wgs work items, each of at least one tile
     int S = (int)std::min<long>((target_wgs + iblocks - 1) / iblocks, (nm + 255) / 256);
     S = std::max(S, 1);
@@ -213,6 +228,7 @@ static int build_dipole_plan(rod_ctx* c, const std::vector<int>& mrange, int tar
         items.push_back(w);
       }
   }
+  c->d.dip_small = small ? 1 : 0;
   c->max_slots = max_slots;
   c->nwork = (int)items.size();
   TRY(dalloc(c, &c->work, items.size()));
@@ -272,17 +288,22 @@ static int leave(rod_ctx* c) {
   return ROD_OK;
 }
 
-static int capture_graph(rod_ctx* c) {
+static int capture_steps(rod_ctx* c, int nsteps, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIPC(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
   int rc = ROD_OK;
-  for (int k = 0; k < c->desc.graph_steps && rc == ROD_OK; ++k) rc = enqueue_step(c);
+  for (int k = 0; k < nsteps && rc == ROD_OK; ++k) rc = enqueue_step(c);
   hipError_t e = hipStreamEndCapture(c->s, &g);
   if (rc != ROD_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
   if (e != hipSuccess) return fail(ROD_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(ROD_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+  return ROD_OK;
+}
+
+static int capture_graph(rod_ctx* c) {
+  TRY(capture_steps(c, c->desc.graph_steps, &c->gexec));
   c->gsteps = c->desc.graph_steps;
   return ROD_OK;
 }
@@ -454,9 +475,20 @@ int rod_step(rod_ctx* c, int64_t n) {
   if (n == 0) return ROD_OK;
   TRY(enter(c));
   if (c->tape.active) {
-    for (int64_t k = 0; k < n; ++k) {
+    // Checkpoint every tape_every steps; whole checkpoint intervals replay a graph.
+    const int every = c->tape.every;
+    int64_t k = 0;
+    while (k < n) {
+      const int64_t rel = c->h_step + k - c->tape.start_step;
       TRY(tape_before_step(c->tape, c->d, c->s, c->h_step + k));
-      TRY(enqueue_step(c));
+      if (!c->timing && rel % every == 0 && n - k >= every && rel + every <= c->tape.capacity) {
+        if (!c->tgexec) TRY(capture_steps(c, every, &c->tgexec));
+        HIPC(hipGraphLaunch(c->tgexec, c->s));
+        k += every;
+      } else {
+        TRY(enqueue_step(c));
+        k += 1;
+      }
     }
   } else {
     int64_t left = n;
@@ -638,6 +670,8 @@ int rod_free(rod_ctx* c) {
   if (c->s) (void)hipStreamSynchronize(c->s);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->tgexec) (void)hipGraphExecDestroy(c->tgexec);
+  tape_release(c->tape);
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);

@@ -16,6 +16,8 @@ struct Dev {
   int R, M;         // rods, members
   // caller-owned state (SoA planes)
   double *x, *v, *q, *w, *F, *T;
+  const double* src;       // if set, the pre kernel reads the state from these planes
+                           // (x, v, q, w, F, T as in a recorded state) instead of in place
   const double *mb, *field, *extF, *extT;
   // topology and constants
   const uint8_t* bflags;   // bit0: bond (k, k+1); bit1: bond (k-1, k)
@@ -48,6 +50,7 @@ struct Dev {
   // parameters
   double dt, damping, C, kc, rc, inv_cell;
   int depth, field_len, dipole_on, contact_on;
+  int dip_small;           // dipole work items use the small-member layout (16 i per item)
   double axis[3];
   long long period;
 };

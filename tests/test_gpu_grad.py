@@ -1,0 +1,204 @@
+"""Reverse pass (rod_grad) against the oracle's forward-mode JVP and against
+central finite differences of the GPU forward run.
+
+For a loss L(x_T) the adjoint gives g = dL/d(inputs); for any direction u the
+oracle's dual-number run gives the exact directional derivative
+dL[u] = <x-bar_T, dx_T[u]>. The two must agree to roundoff (FP64 path).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from paper_2603_27279_amd import RodSim
+from paper_2603_27279_amd._lib import ROD_E_NOTAPE, RodError
+
+pytestmark = pytest.mark.gpu
+
+BLOCKS = ("m_body", "field", "x0", "v0", "q0", "w0")
+WKEY = {"m_body": "m_body", "field": "field", "x0": "x0", "v0": "v0", "q0": "q0", "w0": "w0"}
+
+
+def soa(a):
+    return torch.as_tensor(np.ascontiguousarray(np.asarray(a, dtype=np.float64).T), device="cuda")
+
+
+def tip_cotangent(w, xT):
+    g = np.zeros_like(xT)
+    g[-1] = 2.0 * (xT[-1] - w["target"])
+    return g
+
+
+def gpu_grad(w, nsteps, every, prec="fp64", cot_fn=tip_cotangent):
+    sim = RodSim(w, precision=prec, tape_every=every, tape_capacity=nsteps)
+    sim.tape_begin()
+    sim.step(nsteps)
+    sim.sync()
+    st = sim.state()
+    gx = cot_fn(w, st["x"])
+    g = sim.grad(gx=soa(gx))
+    out = {k: v.cpu().numpy() for k, v in g.items()}
+    out = {k: (v.T if k != "field" else v) for k, v in out.items()}
+    sim.free()
+    return out, st, gx
+
+
+def jvp_check(w, nsteps, every, rtol=1e-8, seed=0, blocks=BLOCKS):
+    g, st, gx = gpu_grad(w, nsteps, every)
+    rng = np.random.default_rng(seed)
+    free = w["bc"] == 0
+    for blk in blocks + ("all",):
+        names = BLOCKS if blk == "all" else (blk,)
+        tan = {}
+        for k in names:
+            t = rng.normal(size=np.shape(w[WKEY[k]]))
+            tan[WKEY[k]] = t
+        _, dT = oracle.run_jvp(w, nsteps, tan)
+        ref = float(np.sum(gx * dT["x"]))
+        got = float(sum(np.sum(g[k] * tan[WKEY[k]]) for k in names))
+        scale = sum(float(np.sum(np.abs(g[k] * tan[WKEY[k]]))) for k in names) + 1e-300
+        assert abs(got - ref) <= rtol * scale, (blk, got, ref, scale)
+    return g
+
+
+def test_grad_matches_oracle_jvp_clamped_rod():
+    w = workloads.adjoint_rod(n=16)
+    jvp_check(w, 30, 7)
+
+
+def test_grad_field_table_and_gradient_field():
+    w = workloads.adjoint_rod(n=12)
+    L = 5
+    rng = np.random.default_rng(1)
+    f = np.zeros((L, 1, 12))
+    f[:, 0, :3] = rng.normal(0, 0.5, size=(L, 3))
+    f[:, 0, 3:] = rng.normal(0, 0.05, size=(L, 9))
+    w["field"] = f
+    w["v0"] = rng.normal(0, 0.01, size=(12, 3)) * (w["bc"] == 0)[:, None]
+    w["w0"] = rng.normal(0, 0.01, size=(12, 3)) * (w["bc"] == 0)[:, None]
+    jvp_check(w, 23, 4)
+
+
+def test_grad_with_contact_and_driven_end():
+    """Contacts (a tightly wound rod) and a driven end."""
+    n = 40
+    lam = 1.0 / np.hypot(1.5, 0.8 / (2 * np.pi))
+    ph = np.arange(n) * lam
+    x, off, mem = workloads.straight_rods([n], [(0, 0, 0)], (1, 0, 0))
+    bc = np.zeros(n, np.int8)
+    bc[0] = 1
+    bc[-1] = 2
+    w = workloads._base(x, off, mem, [1.0, 1, 1, 0.5], np.tile([0.0, 0.0, 0.04], (n, 1)), bc,
+                        workloads._field_const(1, (0.1, 0.3, -0.2)), contact_on=True,
+                        drive_axis=np.array([0.0, 0.0, 1.0]), drive_period=400)
+    w["x0"] = np.stack([1.5 * np.cos(ph), 1.5 * np.sin(ph), 0.8 * ph / (2 * np.pi)], 1)
+    w["target"] = w["x0"][-2] + 0.5
+    assert len(oracle.contact_pairs(w, w["x0"])) > 10
+
+    def cot(w, xT):
+        g = np.zeros_like(xT)
+        g[-2] = 2.0 * (xT[-2] - w["target"])
+        g[n // 2] = 1.0
+        return g
+    g, st, gx = gpu_grad(w, 25, 6, cot_fn=cot)
+    rng = np.random.default_rng(2)
+    tan = {WKEY[k]: rng.normal(size=np.shape(w[WKEY[k]])) for k in BLOCKS}
+    _, dT = oracle.run_jvp(w, 25, tan)
+    ref = float(np.sum(gx * dT["x"]))
+    got = float(sum(np.sum(g[k] * tan[WKEY[k]]) for k in BLOCKS))
+    assert abs(got - ref) <= 1e-8 * abs(ref), (got, ref)
+
+
+def test_grad_cotangent_of_every_state_block():
+    """Cotangents on x, v, q and w of the final state together."""
+    w = workloads.adjoint_rod(n=10)
+    rng = np.random.default_rng(4)
+    cx, cv = rng.normal(size=(10, 3)), rng.normal(size=(10, 3))
+    cq, cw = rng.normal(size=(10, 4)), rng.normal(size=(10, 3))
+    sim = RodSim(w, precision="fp64", tape_every=5, tape_capacity=20)
+    sim.tape_begin()
+    sim.step(17)
+    g = sim.grad(gx=soa(cx), gv=soa(cv), gq=soa(cq), gw=soa(cw))
+    g = {k: (v.cpu().numpy().T if k != "field" else v.cpu().numpy()) for k, v in g.items()}
+    sim.free()
+    tan = {WKEY[k]: rng.normal(size=np.shape(w[WKEY[k]])) for k in BLOCKS}
+    _, dT = oracle.run_jvp(w, 17, tan)
+    ref = float(np.sum(cx * dT["x"]) + np.sum(cv * dT["v"]) + np.sum(cq * dT["q"]) +
+                np.sum(cw * dT["w"]))
+    got = float(sum(np.sum(g[k] * tan[WKEY[k]]) for k in BLOCKS))
+    assert abs(got - ref) <= 1e-8 * abs(ref), (got, ref)
+
+
+def test_grad_needs_a_tape():
+    w = workloads.adjoint_rod(n=8)
+    sim = RodSim(w, precision="fp64")
+    with pytest.raises(RodError) as e:
+        sim.grad(gx=soa(np.zeros((8, 3))))
+    assert e.value.code == ROD_E_NOTAPE
+    sim.free()
+    sim = RodSim(w, precision="fp64", tape_every=5, tape_capacity=10)
+    sim.tape_begin()
+    with pytest.raises(RodError) as e:
+        sim.grad(gx=soa(np.zeros((8, 3))))
+    assert e.value.code == ROD_E_NOTAPE
+    sim.free()
+
+
+def test_full_adjoint_workload_vs_central_differences():
+    """N = 256, T = 2000 steps, checkpoints every 100: the gradient of
+    |x_tip - target|^2 w.r.t. the body dipoles, the field and the initial
+    state agrees with central differences (h = 1e-6) of the GPU forward run
+    along 8 random directions and on 32 random m_body coordinates to 1e-4."""
+    w = workloads.make("adjoint_rod")
+    T = w["steps"]
+    g, st, gx = gpu_grad(w, T, w["tape_every"])
+    def run_loss(mb, x0):
+        w2 = dict(w)
+        w2["m_body"], w2["x0"] = mb, x0
+        s = RodSim(w2, precision="fp64", graph_steps=100)
+        s.step(T)
+        s.sync()
+        xT = s.state()["x"]
+        s.free()
+        return float(np.sum((xT[-1] - w["target"]) ** 2))
+
+    rng = np.random.default_rng(7)
+    h = 1e-6
+    free = (w["bc"] == 0)[:, None]
+    for _ in range(8):
+        u_mb = rng.normal(size=(w["n"], 3))
+        u_x = rng.normal(size=(w["n"], 3)) * 1e-2 * free
+        fd = (run_loss(w["m_body"] + h * u_mb, w["x0"] + h * u_x) -
+              run_loss(w["m_body"] - h * u_mb, w["x0"] - h * u_x)) / (2 * h)
+        ad = float(np.sum(g["m_body"] * u_mb) + np.sum(g["x0"] * u_x))
+        assert abs(fd - ad) <= 1e-4 * abs(ad), (fd, ad)
+    idx = rng.choice(3 * w["n"], 32, replace=False)
+    for k in idx:
+        p, c = divmod(int(k), 3)
+        e = np.zeros((w["n"], 3))
+        e[p, c] = 1.0
+        fd = (run_loss(w["m_body"] + h * e, w["x0"]) - run_loss(w["m_body"] - h * e, w["x0"])) / (2 * h)
+        ad = g["m_body"][p, c]
+        assert abs(fd - ad) <= 1e-4 * max(abs(ad), 1e-3 * np.max(np.abs(g["m_body"]))), (p, c, fd, ad)
+
+
+def test_taped_forward_matches_plain_run_bitwise():
+    """Recording a tape (checkpoint copies, segment graphs) leaves the
+    trajectory bit-for-bit unchanged, and rod_grad leaves the state alone."""
+    w = workloads.adjoint_rod(n=64)
+    a = RodSim(w, precision="fp64", tape_every=10, tape_capacity=100)
+    a.tape_begin()
+    a.step(37)
+    a.step(40)
+    b = RodSim(w, precision="fp64")
+    b.step(77)
+    sa, sb = a.state(), b.state()
+    for k in ("x", "v", "q", "w", "F", "T"):
+        np.testing.assert_array_equal(sa[k], sb[k])
+    a.grad(gx=soa(np.ones((64, 3))))
+    sa2 = a.state()
+    for k in ("x", "v", "q", "w", "F", "T"):
+        np.testing.assert_array_equal(sa2[k], sb[k])
+    assert sa2["step"] == 77
+    a.free(); b.free()

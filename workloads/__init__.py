@@ -157,9 +157,13 @@ def cilia_carpet(grid=(32, 32), pitch=8.0, len_range=(16, 128), seed=3, m=0.03,
     return _perturb(w, rng, sigma)
 
 
-def adjoint_rod(n=256, seed=4, m_sigma=0.05, B=(0.0, 0.0, 1.0), sigma=1e-3, **kw):
+def adjoint_rod(n=256, seed=4, m_sigma=0.05, B=(0.0, 0.0, 1.0), E=10.0, sigma=1e-3, **kw):
     """Clamped rod along +x with random body-frame dipoles and a random tip target
-    inside the ball of radius 0.5 * (n - 1) around the clamp."""
+    inside the ball of radius 0.5 * (n - 1) around the clamp.
+
+    Young's modulus defaults to 10: with E = 1, dipoles of this spread in a unit
+    field turn neighbouring particles by up to pi relative to each other, where
+    the short-arc central frame of the bond model flips and the run diverges."""
     rng = np.random.default_rng(seed)
     x, off, mem = straight_rods([n], [(0.0, 0.0, 0.0)], (1.0, 0.0, 0.0))
     bc = np.zeros(n, np.int8)
@@ -170,7 +174,7 @@ def adjoint_rod(n=256, seed=4, m_sigma=0.05, B=(0.0, 0.0, 1.0), sigma=1e-3, **kw
         t = rng.uniform(-rad, rad, size=3)
         if np.dot(t, t) <= rad * rad:
             break
-    w = _base(x, off, mem, [1.0, 1.0, 1.0, 0.5], mb, bc, _field_const(1, B),
+    w = _base(x, off, mem, [1.0, 1.0, E, 0.5], mb, bc, _field_const(1, B),
               steps=2000, precision="fp64", name=f"adjoint_rod_n{n}",
               target=t + x[0], tape_every=100)
     w.update(kw)
