@@ -109,6 +109,22 @@ def adjoint_leg():
             "total_over_forward": (t_fwd + t_grad) / t_plain}
 
 
+def copy_calibration():
+    """A plain device copy of a known size (256 MiB read, 256 MiB written, three
+    times), for scaling the FETCH_SIZE and WRITE_SIZE counters to bytes."""
+    import torch
+    n = 256 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_launch": 8 * n,
+                                           "bytes_written_per_launch": 8 * n, "launches": 3}}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,7 +137,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-per-rod", action="store_true",
+                    help="skip the per-rod loop comparison (multi-rod workloads)")
+    ap.add_argument("--per-rod-steps", type=int, default=50)
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON-lines cache of autotuner choices (default: tune every run)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -138,6 +165,10 @@ def main():
     pairs = ordered_pairs(w) if w["dipole_on"] else 0
 
     sim = RodSim(w, precision=prec, graph_steps=args.graph_steps)
+    tune = None
+    if not args.no_autotune:
+        report = sim.autotune(args.tune_cache)
+        tune = report.strip().splitlines()[-1]
     sim.step(args.warmup)
     sim.sync()
     torch.cuda.synchronize()
@@ -166,6 +197,24 @@ def main():
                 "kernel": "k_dipole<float>" if prec == "mixed" else "k_dipole<double>",
                 "pair_evals_per_s": pairs / t_dip,
                 "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": pairs}
+    batching = None
+    n_rods = len(w["rod_offset"]) - 1
+    if n_rods > 1 and not args.no_per_rod:
+        # The same step as a plain per-rod loop (every kernel once per rod, eager).
+        k = max(1, min(args.steps, args.per_rod_steps))
+        sim.launch_mode(per_rod=True)
+        sim.step(2)
+        sim.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(k)
+        sim.sync()
+        torch.cuda.synchronize()
+        ms_rod = 1e3 * (time.perf_counter() - t0) / k
+        sim.launch_mode(per_rod=False)
+        batching = {"n_rods": n_rods, "per_rod_ms_per_step": ms_rod,
+                    "per_rod_steps": k, "batched_ms_per_step": ms_step,
+                    "speedup": ms_rod / ms_step}
     sim.free()
 
     adj = None if args.no_adjoint else adjoint_leg()
@@ -190,10 +239,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "n_particles": n,
                    "ordered_dipole_pairs_per_step": pairs, "precision": prec,
-                   "graph_steps": args.graph_steps},
+                   "graph_steps": args.graph_steps, "dipole_layout": tune},
         "pair_evals_per_s": pairs * args.steps / secs if pairs else None,
         "kernel_us": kernels_us,
         "roofline": roof,
+        "batching": batching,
         "adjoint": adj,
         "cpu_baseline": cpu,
     }

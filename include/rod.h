@@ -194,6 +194,34 @@ enum {
 int rod_timing(rod_ctx* c, int32_t enable);
 int rod_kernel_times(rod_ctx* c, double* ms, int64_t* launches);
 
+/* Autotuner for the work layout of the all-pairs dipole kernel (the dominant
+ * kernel). Candidates: the small-member layout (1024-thread workgroups of 16
+ * targets; members of at most 16384 particles) and the split layout (64
+ * targets per workgroup, each member's sources split into enough ranges to
+ * give the launch 512 ... 32768 work items). Each candidate is timed with HIP
+ * events on the library's stream over repeated force evaluations at the
+ * current state (the state is not changed); the fastest is applied. With a
+ * non-NULL cache_path (a JSON-lines file) the choice is looked up first
+ * (unless force != 0) under a key of GPU architecture, precision and member
+ * sizes, and a new choice is appended. A text report is copied into `report`
+ * (report_len bytes, may be NULL). Invalidates captured graphs; not allowed
+ * while a tape is recorded (ROD_E_STATE). */
+int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, char* report,
+                 int32_t report_len);
+
+/* Launch mode of rod_step. ROD_LAUNCH_BATCHED (default): each kernel serves all
+ * rods and members in one launch (graph-captured when graph_steps > 0).
+ * ROD_LAUNCH_PER_ROD: the plain per-rod loop, every kernel launched once per
+ * rod on that rod's particles, eagerly; kept as the baseline the batched form
+ * is measured against. Both give bitwise identical states. */
+enum { ROD_LAUNCH_BATCHED = 0, ROD_LAUNCH_PER_ROD = 1 };
+int rod_launch_mode(rod_ctx* c, int32_t mode);
+
+/* Set the dipole work layout directly: small = 1 small-member layout (ignored
+ * for members above 16384 particles), 0 split layout aiming at target_wgs
+ * work items, -1 the default rule. Invalidates captured graphs. */
+int rod_dipole_layout(rod_ctx* c, int32_t small, int32_t target_wgs);
+
 /* Release the context and its workspace (synchronises). NULL is accepted. */
 int rod_free(rod_ctx* c);
 

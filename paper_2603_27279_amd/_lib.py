@@ -77,6 +77,9 @@ def load():
         "rod_free": [_P],
         "rod_timing": [_P, i32],
         "rod_kernel_times": [_P, _P, _P],
+        "rod_autotune": [_P, C.c_char_p, i32, C.c_char_p, i32],
+        "rod_dipole_layout": [_P, i32, i32],
+        "rod_launch_mode": [_P, i32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

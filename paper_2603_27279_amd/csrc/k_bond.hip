@@ -19,9 +19,9 @@ namespace rodmx {
 
 template <class R>
 __global__ __launch_bounds__(256) void k_bond(Dev d, int want_energy) {
-  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long k = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long N = d.n;
-  if (k >= N || !(d.bflags[k] & 1)) return;
+  if (k >= d.i_hi || !(d.bflags[k] & 1)) return;
   V3<double> F, Ts, Tbt;
   double e[4];
   bond_one<double, R>(ld3(d.x, N, k), ld3(d.x, N, k + 1), ld4(d.q, N, k), ld4(d.q, N, k + 1),
@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void k_bond(Dev d, int want_energy) {
 
 hipError_t launch_bond(const Dev& d, int precision, int want_energy, hipStream_t s) {
   const int bs = particle_block(d.n);
-  dim3 grid((unsigned)((d.n + bs - 1) / bs));
+  dim3 grid((unsigned)((d.i_hi - d.i_lo + bs - 1) / bs));
   if (precision == 1)
     hipLaunchKernelGGL(k_bond<float>, grid, dim3(bs), 0, s, d, want_energy);
   else

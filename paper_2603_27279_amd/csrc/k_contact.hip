@@ -50,9 +50,9 @@ template <int OUT>
 __device__ __forceinline__ void contact_pass(const Dev& d, int* pairs, int cap, int* count) {
   const long N = d.n;
   const int lane = threadIdx.x & 31;
-  const long i = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
-  const bool pv = i < N;
-  const long ii = pv ? i : 0;
+  const long i = d.i_lo + (((long)blockIdx.x * blockDim.x + threadIdx.x) >> 5);
+  const bool pv = i < d.i_hi;
+  const long ii = pv ? i : d.i_lo;
   const V3<double> xi = ld3(d.x, N, ii);
   const int mem = d.mem[ii], rod = d.rod[ii];
   const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
@@ -122,8 +122,8 @@ __device__ __forceinline__ void contact_pass(const Dev& d, int* pairs, int cap, 
 template <int OUT>
 __device__ __forceinline__ void contact_thread(const Dev& d) {
   const long N = d.n;
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.i_hi) return;
   const V3<double> xi = ld3(d.x, N, i);
   const int mem = d.mem[i], rod = d.rod[i];
   const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
@@ -193,25 +193,27 @@ hipError_t launch_clear_cells(const Dev& d, hipStream_t s) {
   return hipGetLastError();
 }
 
-static inline unsigned contact_blocks(long n) { return (unsigned)((32 * n + 255) / 256); }
+static inline unsigned contact_blocks(const Dev& d) {
+  return (unsigned)((32 * (d.i_hi - d.i_lo) + 255) / 256);
+}
 
 hipError_t launch_contact(const Dev& d, int want_energy, hipStream_t s) {
   if (!d.contact_on) return hipSuccess;
   if (d.n >= CONTACT_LANES_MAX_N) {
-    const unsigned g = (unsigned)((d.n + 255) / 256);
+    const unsigned g = (unsigned)((d.i_hi - d.i_lo + 255) / 256);
     if (want_energy) hipLaunchKernelGGL(k_contact_te, dim3(g), dim3(256), 0, s, d);
     else hipLaunchKernelGGL(k_contact_t, dim3(g), dim3(256), 0, s, d);
     return hipGetLastError();
   }
   if (want_energy)
-    hipLaunchKernelGGL(k_contact_e, dim3(contact_blocks(d.n)), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_contact_e, dim3(contact_blocks(d)), dim3(256), 0, s, d);
   else
-    hipLaunchKernelGGL(k_contact, dim3(contact_blocks(d.n)), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_contact, dim3(contact_blocks(d)), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 
 hipError_t launch_contact_pairs(const Dev& d, int* pairs, int cap, int* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_contact_pairs, dim3(contact_blocks(d.n)), dim3(256), 0, s, d, pairs, cap,
+  hipLaunchKernelGGL(k_contact_pairs, dim3(contact_blocks(d)), dim3(256), 0, s, d, pairs, cap,
                      count);
   return hipGetLastError();
 }

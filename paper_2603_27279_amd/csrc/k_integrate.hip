@@ -43,11 +43,11 @@ __device__ __forceinline__ unsigned cell_hash(int cx, int cy, int cz, int mem, u
 }
 
 __global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long n = d.step[0];
   const long long lvl = n + (mode == PRE_STEP ? 1 : 0);  // level of the coming force evaluation
   if (i == 0) d.step[1] = lvl;
-  if (i >= d.n) return;
+  if (i >= d.i_hi) return;
   const long N = d.n;
   const int b = d.bc[i];
   // state read in place, or from separate planes (out-of-place step)
@@ -122,14 +122,14 @@ __device__ __forceinline__ bool finite3(V3<double> a) {
 
 __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double* Fo, double* To,
                                               double* Bo) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long N = d.n;
   const long long lvl = d.step[1];  // level of the forces being gathered
   if (i == 0) {
     if (mode == POST_KICK) d.step[0] = lvl;
     *d.ovf_cnt = 0;  // the contact pass that used the overflow list has finished
   }
-  if (i < N) {
+  if (i < d.i_hi) {
     V3<double> F{0.0, 0.0, 0.0}, T{0.0, 0.0, 0.0};
     const uint8_t bf = d.bflags[i];
     if (mask & 1) {  // bonds: +F, tau_s + tau_bt from bond (i, i+1); -F, tau_s - tau_bt from (i-1, i)
@@ -257,15 +257,15 @@ static inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 
 
 hipError_t launch_pre(const Dev& d, int mode, hipStream_t s) {
   const int bs = particle_block(d.n);
-  hipLaunchKernelGGL(k_pre, dim3(blocks_for(d.n, bs)), dim3(bs), 0, s, d, mode);
+  hipLaunchKernelGGL(k_pre, dim3(blocks_for(d.i_hi - d.i_lo, bs)), dim3(bs), 0, s, d, mode);
   return hipGetLastError();
 }
 
 hipError_t launch_post(const Dev& d, int mode, int mask, double* Fo, double* To, double* Bo,
                        hipStream_t s) {
   const int bs = particle_block(d.n);
-  hipLaunchKernelGGL(k_post, dim3(blocks_for(d.n, bs)), dim3(bs), 0, s, d, mode, mask, Fo, To,
-                     Bo);
+  hipLaunchKernelGGL(k_post, dim3(blocks_for(d.i_hi - d.i_lo, bs)), dim3(bs), 0, s, d, mode, mask,
+                     Fo, To, Bo);
   return hipGetLastError();
 }
 

@@ -50,11 +50,22 @@ struct rod_ctx {
   Dev d;
   std::vector<void*> allocs;
   DipWork* work = nullptr;
-  int nwork = 0, max_slots = 1, dip_chunk = 0;
+  int nwork = 0, max_slots = 1;
+  std::vector<void*> plan_allocs;   // dipole work list, slot counts, partial slots
+  std::vector<int> mrange_h;        // [2M] member particle ranges
+  int plan_small = -1, plan_target = 1024;  // current dipole layout
+  std::vector<int> mslots_h;        // [M] source ranges per member of the current layout
+  std::vector<int> mlen_h;          // [M] length of those ranges
+  // per-rod launch mode (baseline for the batched form)
+  int launch_mode = ROD_LAUNCH_BATCHED;
+  DipWork* rod_work = nullptr;      // dipole items grouped by rod
+  std::vector<int> rod_work_off;    // [R+1]
+  std::vector<void*> rod_allocs;
   double* epart = nullptr;
   double* eout = nullptr;
   int* pair_count = nullptr;
   std::vector<int> rod_offset;
+  std::vector<int> rod_member_h;
   std::vector<double> bref_h;  // [4N]
   std::vector<double> rodK_h;  // [R][4]
   std::vector<uint8_t> bflags_h;
@@ -115,6 +126,17 @@ static size_t next_pow2(size_t v) {
   size_t p = 1;
   while (p < v) p <<= 1;
   return p;
+}
+
+template <class T>
+static int palloc(rod_ctx* c, T** p, size_t count) {
+  void* q = nullptr;
+  size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+  HIPC(hipMalloc(&q, bytes));
+  c->plan_allocs.push_back(q);
+  HIPC(hipMemset(q, 0, bytes));
+  *p = (T*)q;
+  return ROD_OK;
 }
 
 template <class T>
@@ -188,7 +210,10 @@ static int validate(const rod_desc* d) {
 
 // Dipole work list: blocks of 256 i against j chunks of the same member; the
 // chunk count per member is chosen so the launch holds at least ~2048 work items.
-static int build_dipole_plan(rod_ctx* c, const std::vector<int>& mrange, int target_wgs) {
+// small: -1 = automatic, 0 = 64-i blocks with split j ranges, 1 = small-member
+// layout; target_wgs: work items aimed at by the split layout.
+static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
+  const std::vector<int>& mrange = c->mrange_h;
   const int M = c->desc.n_members;
   const long N = c->desc.n_particles;
   long iblocks = 0;
@@ -198,9 +223,13 @@ static int build_dipole_plan(rod_ctx* c, const std::vector<int>& mrange, int tar
     max_member = std::max(max_member, mrange[2 * m + 1] - mrange[2 * m]);
   }
   // Small systems: spread every member pair over 1024-thread workgroups of 16 i.
-  const bool small = iblocks < 512 && max_member <= 2048;
+  bool small = small_req < 0 ? (iblocks < 512 && max_member <= 2048) : small_req == 1;
+  if (max_member > 16384) small = false;
+  if (!c->plan_allocs.empty()) HIPC(hipStreamSynchronize(c->s));  // old plan may be in use
+  for (void* p : c->plan_allocs) (void)hipFree(p);
+  c->plan_allocs.clear();
   std::vector<DipWork> items;
-  std::vector<int> mslots(M, 1);
+  std::vector<int> mslots(M, 1), mlen(M, 0);
   int max_slots = 1;
   for (int m = 0; m < M; ++m) {
     const int b = mrange[2 * m], e = mrange[2 * m + 1], nm = e - b;
@@ -218,6 +247,7 @@ static int build_dipole_plan(rod_ctx* c, const std::vector<int>& mrange, int tar
     const int len = (nm + S - 1) / S;
     S = (nm + len - 1) / len;
     mslots[m] = S;
+    mlen[m] = len;
     max_slots = std::max(max_slots, S);
     for (int i0 = b; i0 < e; i0 += 64)
       for (int s = 0; s < S; ++s) {
@@ -228,16 +258,20 @@ static int build_dipole_plan(rod_ctx* c, const std::vector<int>& mrange, int tar
         items.push_back(w);
       }
   }
+  c->mslots_h = mslots;
+  c->mlen_h = mlen;
   c->d.dip_small = small ? 1 : 0;
+  c->plan_small = small ? 1 : 0;
+  c->plan_target = target_wgs;
   c->max_slots = max_slots;
   c->nwork = (int)items.size();
-  TRY(dalloc(c, &c->work, items.size()));
+  TRY(palloc(c, &c->work, items.size()));
   HIPC(hipMemcpy(c->work, items.data(), items.size() * sizeof(DipWork), hipMemcpyHostToDevice));
   int* ms = nullptr;
-  TRY(dalloc(c, &ms, M));
+  TRY(palloc(c, &ms, M));
   HIPC(hipMemcpy(ms, mslots.data(), M * sizeof(int), hipMemcpyHostToDevice));
   c->d.mslots = ms;
-  TRY(dalloc(c, &c->d.dpart, (size_t)max_slots * 6 * N));
+  TRY(palloc(c, &c->d.dpart, (size_t)max_slots * 6 * N));
   return ROD_OK;
 }
 
@@ -274,6 +308,66 @@ static int enqueue_prepare(rod_ctx* c) {
   HIPC(launch_pre(c->d, PRE_PREPARE, c->s));
   TRY(force_terms(c, 0));
   HIPC(launch_post(c->d, POST_PREPARE, ROD_TERM_ALL, nullptr, nullptr, nullptr, c->s));
+  return ROD_OK;
+}
+
+// Dipole items of the current layout regrouped by rod: the same source ranges,
+// target blocks cut at rod boundaries (each target's sums are unchanged).
+static int build_rod_work(rod_ctx* c) {
+  if (!c->rod_allocs.empty()) HIPC(hipStreamSynchronize(c->s));
+  for (void* p : c->rod_allocs) (void)hipFree(p);
+  c->rod_allocs.clear();
+  std::vector<DipWork> items;
+  c->rod_work_off.assign(1, 0);
+  const int bs = c->d.dip_small ? 16 : 64;
+  for (int r = 0; r < c->desc.n_rods; ++r) {
+    const int m = c->rod_member_h[r];
+    const int b = c->mrange_h[2 * m], e = c->mrange_h[2 * m + 1];
+    for (int i0 = c->rod_offset[r]; i0 < c->rod_offset[r + 1]; i0 += bs) {
+      const int i1 = std::min(i0 + bs, c->rod_offset[r + 1]);
+      if (c->d.dip_small) {
+        DipWork w{};
+        w.i0 = i0; w.i1 = i1; w.j0 = b; w.j1 = e; w.slot = 0;
+        items.push_back(w);
+      } else {
+        for (int s = 0; s < c->mslots_h[m]; ++s) {
+          DipWork w{};
+          w.i0 = i0; w.i1 = i1;
+          w.j0 = b + s * c->mlen_h[m]; w.j1 = std::min(e, b + (s + 1) * c->mlen_h[m]);
+          w.slot = s;
+          items.push_back(w);
+        }
+      }
+    }
+    c->rod_work_off.push_back((int)items.size());
+  }
+  void* q = nullptr;
+  HIPC(hipMalloc(&q, std::max<size_t>(items.size(), 1) * sizeof(DipWork)));
+  c->rod_allocs.push_back(q);
+  HIPC(hipMemcpy(q, items.data(), items.size() * sizeof(DipWork), hipMemcpyHostToDevice));
+  c->rod_work = (DipWork*)q;
+  return ROD_OK;
+}
+
+// The plain per-rod loop: every kernel launched once per rod on that rod's particles.
+static int enqueue_step_per_rod(rod_ctx* c) {
+  const int R = c->desc.n_rods;
+  auto rod_dev = [&](int r) {
+    Dev dr = c->d;
+    dr.i_lo = c->rod_offset[r];
+    dr.i_hi = c->rod_offset[r + 1];
+    return dr;
+  };
+  for (int r = 0; r < R; ++r) HIPC(launch_pre(rod_dev(r), PRE_STEP, c->s));
+  for (int r = 0; r < R; ++r) HIPC(launch_bond(rod_dev(r), c->desc.precision, 0, c->s));
+  if (c->desc.dipole_on)
+    for (int r = 0; r < R; ++r)
+      HIPC(launch_dipole(rod_dev(r), c->desc.precision, c->rod_work + c->rod_work_off[r],
+                         c->rod_work_off[r + 1] - c->rod_work_off[r], c->s));
+  if (c->desc.contact_on)
+    for (int r = 0; r < R; ++r) HIPC(launch_contact(rod_dev(r), 0, c->s));
+  for (int r = 0; r < R; ++r)
+    HIPC(launch_post(rod_dev(r), POST_KICK, ROD_TERM_ALL, nullptr, nullptr, nullptr, c->s));
   return ROD_OK;
 }
 
@@ -345,6 +439,7 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
 
   // ---- topology and constants (host)
   c->rod_offset.assign(dsc->rod_offset, dsc->rod_offset + R + 1);
+  c->rod_member_h.assign(dsc->rod_member, dsc->rod_member + R);
   std::vector<int> rod(N), mem(N);
   std::vector<uint8_t> bfl(N, 0);
   std::vector<int8_t> bc(dsc->bc, dsc->bc + N);
@@ -389,6 +484,7 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   Dev& d = c->d;
   d = Dev{};
   d.n = N; d.R = R; d.M = M;
+  d.i_lo = 0; d.i_hi = N;
   d.x = b->x; d.v = b->v; d.q = b->q; d.w = b->w; d.F = b->force; d.T = b->torque;
   d.mb = b->m_body; d.field = b->field; d.extF = b->ext_force; d.extT = b->ext_torque;
   uint8_t* bflags; int *rod_d, *mem_d, *mrange_d; int8_t* bc_d;
@@ -442,7 +538,8 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   long long s0[2] = {dsc->step0, dsc->step0};
   if (hipMemcpy(d.step, s0, sizeof(s0), hipMemcpyHostToDevice) != hipSuccess)
     return cleanup(fail(ROD_E_HIP, "upload failed"));
-  if ((rc = build_dipole_plan(c, mrange, 1024))) return cleanup(rc);
+  c->mrange_h = mrange;
+  if ((rc = build_dipole_plan(c, -1, 1024))) return cleanup(rc);
   // descriptor host pointers are not kept
   c->desc.rod_offset = nullptr; c->desc.rod_member = nullptr; c->desc.rod_params = nullptr;
   c->desc.x_ref = nullptr; c->desc.bc = nullptr;
@@ -490,6 +587,8 @@ int rod_step(rod_ctx* c, int64_t n) {
         k += 1;
       }
     }
+  } else if (c->launch_mode == ROD_LAUNCH_PER_ROD) {
+    for (int64_t k = 0; k < n; ++k) TRY(enqueue_step_per_rod(c));
   } else {
     int64_t left = n;
     if (!c->timing && c->desc.graph_steps > 0 && left >= c->desc.graph_steps) {
@@ -665,10 +764,165 @@ int rod_kernel_times(rod_ctx* c, double* ms, int64_t* launches) {
   return ROD_OK;
 }
 
+// ------------------------------------------------------------------ autotuner
+static void drop_graphs(rod_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->tgexec) (void)hipGraphExecDestroy(c->tgexec);
+  c->gexec = c->tgexec = nullptr;
+  c->gsteps = 0;
+  tape_release(c->tape);
+}
+
+// Microseconds per force evaluation (pre, forces, gather) of the current layout.
+static int time_eval(rod_ctx* c, double* us) {
+  double* F = c->epart;  // scratch: [3N] force and [3N] torque
+  double* T = c->epart + 3 * c->d.n;
+  auto eval = [&]() -> int {
+    HIPC(launch_pre(c->d, PRE_EVAL, c->s));
+    TRY(force_terms(c, 0));
+    HIPC(launch_post(c->d, POST_EVAL, ROD_TERM_ALL, F, T, nullptr, c->s));
+    return ROD_OK;
+  };
+  hipEvent_t a, b;
+  HIPC(hipEventCreate(&a));
+  HIPC(hipEventCreate(&b));
+  int rc = ROD_OK;
+  float ms = 0.f;
+  int reps = 3;
+  for (int k = 0; k < 3 && rc == ROD_OK; ++k) rc = eval();  // warm-up
+  for (int round = 0; round < 2 && rc == ROD_OK; ++round) {
+    if (hipEventRecord(a, c->s) != hipSuccess) { rc = fail(ROD_E_HIP, "event record failed"); break; }
+    for (int k = 0; k < reps && rc == ROD_OK; ++k) rc = eval();
+    if (rc != ROD_OK) break;
+    if (hipEventRecord(b, c->s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess) { rc = fail(ROD_E_HIP, "event timing failed"); break; }
+    // aim at ~5 ms of timed work (at most 200 evaluations)
+    const double per = std::max(1e-3, (double)ms / reps);
+    if (round == 0) reps = (int)std::min(200.0, std::max(3.0, 5.0 / per));
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc == ROD_OK) *us = 1e3 * (double)ms / reps;
+  return rc;
+}
+
+static std::string tune_key(rod_ctx* c) {
+  hipDeviceProp_t p;
+  int dev = 0;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+    arch = p.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the member sizes
+  for (size_t k = 0; k + 1 < c->mrange_h.size(); k += 2) {
+    uint64_t v = (uint64_t)(c->mrange_h[k + 1] - c->mrange_h[k]);
+    for (int b = 0; b < 8; ++b) { h ^= (v >> (8 * b)) & 0xff; h *= 1099511628211ull; }
+  }
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s|prec=%d|N=%ld|M=%d|sizes=%016llx", arch.c_str(),
+           c->desc.precision, c->d.n, c->d.M, (unsigned long long)h);
+  return buf;
+}
+
+extern "C" int rod_launch_mode(rod_ctx* c, int32_t mode) {
+  if (!c) return fail(ROD_E_INVALID, "context is NULL");
+  if (mode != ROD_LAUNCH_BATCHED && mode != ROD_LAUNCH_PER_ROD)
+    return fail(ROD_E_INVALID, "mode must be ROD_LAUNCH_BATCHED or ROD_LAUNCH_PER_ROD");
+  if (mode == ROD_LAUNCH_PER_ROD) TRY(build_rod_work(c));
+  c->launch_mode = mode;
+  return ROD_OK;
+}
+
+extern "C" int rod_dipole_layout(rod_ctx* c, int32_t small, int32_t target_wgs) {
+  if (!c) return fail(ROD_E_INVALID, "context is NULL");
+  if (small < -1 || small > 1 || target_wgs < 1)
+    return fail(ROD_E_INVALID, "small must be -1, 0 or 1 and target_wgs >= 1");
+  if (c->tape.active) return fail(ROD_E_STATE, "layout change while a tape is recorded");
+  TRY(enter(c));
+  TRY(build_dipole_plan(c, small, target_wgs));
+  if (c->launch_mode == ROD_LAUNCH_PER_ROD) TRY(build_rod_work(c));
+  drop_graphs(c);
+  TRY(leave(c));
+  return ROD_OK;
+}
+
+extern "C" int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, char* report,
+                            int32_t report_len) {
+  if (!c) return fail(ROD_E_INVALID, "context is NULL");
+  if (c->tape.active) return fail(ROD_E_STATE, "autotune while a tape is recorded");
+  std::string rep, key = tune_key(c);
+  int small = -1, target = 0;
+  double best_us = 0.0;
+  if (cache_path && !force) {  // look the problem up in the cache
+    if (FILE* f = fopen(cache_path, "r")) {
+      char line[512], k[300];
+      while (fgets(line, sizeof(line), f)) {
+        int s_, t_;
+        double u_;
+        if (sscanf(line, "{\"key\": \"%299[^\"]\", \"small\": %d, \"target_wgs\": %d, \"us_per_eval\": %lf",
+                   k, &s_, &t_, &u_) == 4 && key == k) {
+          small = s_; target = t_; best_us = u_;
+        }
+      }
+      fclose(f);
+    }
+  }
+  TRY(enter(c));
+  if (target == 0) {
+    struct Cand { int small, target; };
+    std::vector<Cand> cands;
+    int max_member = 0;
+    for (size_t k = 0; k + 1 < c->mrange_h.size(); k += 2)
+      max_member = std::max(max_member, c->mrange_h[k + 1] - c->mrange_h[k]);
+    if (c->desc.dipole_on) {
+      if (max_member <= 16384) cands.push_back({1, 0});
+      for (int t : {512, 1024, 2048, 4096, 8192, 16384, 32768}) cands.push_back({0, t});
+    } else {
+      cands.push_back({0, 1024});
+    }
+    best_us = 1e300;
+    for (const Cand& cd : cands) {
+      TRY(build_dipole_plan(c, cd.small, cd.target));
+      double us = 0.0;
+      TRY(time_eval(c, &us));
+      char line[160];
+      snprintf(line, sizeof(line), "%s target_wgs=%d work_items=%d slots=%d: %.2f us/eval\n",
+               cd.small ? "small-member layout" : "split layout", cd.target, c->nwork,
+               c->max_slots, us);
+      rep += line;
+      if (us < best_us) { best_us = us; small = cd.small; target = cd.target; }
+    }
+    if (cache_path) {
+      if (FILE* f = fopen(cache_path, "a")) {
+        fprintf(f, "{\"key\": \"%s\", \"small\": %d, \"target_wgs\": %d, \"us_per_eval\": %.3f}\n",
+                key.c_str(), small, target, best_us);
+        fclose(f);
+      }
+    }
+  } else {
+    rep += "cached choice\n";
+  }
+  if (c->plan_small != small || c->plan_target != target) TRY(build_dipole_plan(c, small, target));
+  if (c->launch_mode == ROD_LAUNCH_PER_ROD) TRY(build_rod_work(c));
+  drop_graphs(c);
+  TRY(leave(c));
+  char line[200];
+  snprintf(line, sizeof(line), "chosen: %s target_wgs=%d (%.2f us/eval) key=%s\n",
+           small ? "small-member layout" : "split layout", target, best_us, key.c_str());
+  rep += line;
+  if (report && report_len > 0) {
+    strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  return ROD_OK;
+}
+
 int rod_free(rod_ctx* c) {
   if (!c) return ROD_OK;
   if (c->s) (void)hipStreamSynchronize(c->s);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (void* p : c->plan_allocs) (void)hipFree(p);
+  for (void* p : c->rod_allocs) (void)hipFree(p);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->tgexec) (void)hipGraphExecDestroy(c->tgexec);
   tape_release(c->tape);

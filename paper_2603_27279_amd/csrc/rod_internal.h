@@ -13,6 +13,7 @@ struct alignas(32) CellSlot { double x, y, z; long long tag; };
 // the lifetime of the context, so that captured graphs can be replayed.
 struct Dev {
   long n;           // particles
+  long i_lo, i_hi;  // particle range served by the per-particle kernels (normally 0, n)
   int R, M;         // rods, members
   // caller-owned state (SoA planes)
   double *x, *v, *q, *w, *F, *T;

@@ -167,6 +167,22 @@ class RodSim:
                                           cnt.ctypes.data_as(C.c_void_p)))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(L.KERNELS)}
 
+    def autotune(self, cache_path=None, force=False):
+        """Time the dipole work layouts at the current state and apply the fastest;
+        returns the tuner's report."""
+        buf = C.create_string_buffer(4096)
+        path = None if cache_path is None else str(cache_path).encode()
+        L.check(self.lib.rod_autotune(self.ctx, path, int(bool(force)), buf, len(buf)))
+        return buf.value.decode()
+
+    def launch_mode(self, per_rod=False):
+        """Batched launches (default) or the plain per-rod loop (baseline)."""
+        L.check(self.lib.rod_launch_mode(self.ctx, 1 if per_rod else 0))
+
+    def dipole_layout(self, small=-1, target_wgs=1024):
+        """Choose the dipole work layout explicitly (see rod_dipole_layout)."""
+        L.check(self.lib.rod_dipole_layout(self.ctx, int(small), int(target_wgs)))
+
     def free(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             L.check(self.lib.rod_free(self.ctx))
@@ -206,3 +222,56 @@ def rod_grad(sim, **kw):
 
 def rod_free(sim):
     sim.free()
+
+
+def _rod_trajectory_function():
+    import torch
+
+    class RodTrajectory(torch.autograd.Function):
+        """(m_body, field, x0, v0, q0, w0) -> (x_T, v_T, q_T, w_T) after T steps of the
+        workload's loop; backward runs the checkpointed reverse pass (rod_grad).
+
+        Tensors are device float64 in the binding's SoA layout ([3, N], [4, N],
+        field [L, M, 12])."""
+
+        @staticmethod
+        def forward(ctx, m_body, field, x0, v0, q0, w0, workload, nsteps, every, precision):
+            sim = RodSim(workload, precision=precision, tape_every=every,
+                         tape_capacity=max(int(nsteps), 1))
+            with torch.no_grad():
+                sim.m_body.copy_(m_body.detach())
+                sim.field.copy_(field.detach())
+                sim.x.copy_(x0.detach())
+                sim.v.copy_(v0.detach())
+                sim.q.copy_(q0.detach())
+                sim.om.copy_(w0.detach())
+            sim.tape_begin()
+            sim.step(int(nsteps))
+            ctx.sim = sim
+            return sim.x.clone(), sim.v.clone(), sim.q.clone(), sim.om.clone()
+
+        @staticmethod
+        def backward(ctx, gx, gv, gq, gw):
+            sim = ctx.sim
+            cont = lambda t: None if t is None else t.contiguous()
+            g = sim.grad(gx=cont(gx), gv=cont(gv), gq=cont(gq), gw=cont(gw))
+            sim.free()
+            ctx.sim = None
+            return (g["m_body"], g["field"], g["x0"], g["v0"], g["q0"], g["w0"],
+                    None, None, None, None)
+
+    return RodTrajectory
+
+
+_RT = None
+
+
+def rod_trajectory(m_body, field, x0, v0, q0, w0, workload, nsteps, every=100, precision="fp64"):
+    """Differentiable run of the loop (see RodTrajectory): returns (x_T, v_T, q_T, w_T).
+
+    The tape starts from the given state with tape_begin, so forces of the first
+    level are evaluated from (x0, q0, v0, w0); q0 is normalised first."""
+    global _RT
+    if _RT is None:
+        _RT = _rod_trajectory_function()
+    return _RT.apply(m_body, field, x0, v0, q0, w0, workload, nsteps, every, precision)

@@ -202,3 +202,26 @@ def test_taped_forward_matches_plain_run_bitwise():
         np.testing.assert_array_equal(sa2[k], sb[k])
     assert sa2["step"] == 77
     a.free(); b.free()
+
+
+def test_autograd_function_matches_rod_grad():
+    """torch.autograd through rod_trajectory equals rod_grad and the oracle JVP."""
+    from paper_2603_27279_amd import rod_trajectory
+    w = workloads.adjoint_rod(n=24)
+    T = 40
+    params = {k: soa(w[k]).requires_grad_(True) for k in ("m_body", "x0", "v0", "q0", "w0")}
+    field = torch.as_tensor(w["field"], device="cuda").requires_grad_(True)
+    xT, vT, qT, wT = rod_trajectory(params["m_body"], field, params["x0"], params["v0"],
+                                    params["q0"], params["w0"], w, T, every=9)
+    target = torch.as_tensor(w["target"], device="cuda")
+    loss = torch.sum((xT[:, -1] - target) ** 2) + 0.1 * torch.sum(wT ** 2)
+    loss.backward()
+    rng = np.random.default_rng(11)
+    tan = {k: rng.normal(size=np.shape(w[k])) for k in ("m_body", "x0", "v0", "q0", "w0", "field")}
+    stT, dT = oracle.run_jvp(w, T, tan)
+    gxT = np.zeros_like(stT["x"])
+    gxT[-1] = 2 * (stT["x"][-1] - w["target"])
+    ref = float(np.sum(gxT * dT["x"]) + 0.2 * np.sum(stT["w"] * dT["w"]))
+    got = sum(float(np.sum(params[k].grad.cpu().numpy().T * tan[k])) for k in params)
+    got += float(np.sum(field.grad.cpu().numpy() * tan["field"]))
+    assert abs(got - ref) <= 1e-8 * abs(ref), (got, ref)
