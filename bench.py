@@ -13,8 +13,10 @@ with HIP events on the library's stream, and the FP64 CPU oracle timed on a
 bounded sample of the same workload on the host cores.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -35,6 +37,44 @@ WORKLOADS = {
     "cantilever": "cantilever, 20 particles, FP64",
     "adjoint_rod": "adjoint rod, N=256, FP64",
 }
+
+
+# Sources that make up the dipole kernel; a change to any of them voids the
+# counter figures recorded for it.
+DIPOLE_SOURCES = ("k_dipole.hip", "rod_internal.h", "rod_math.h")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_dipole_counters.md")
+
+
+def dipole_sources_digest():
+    h = hashlib.sha256()
+    for f in DIPOLE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_27279_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def layout_key(tune_line):
+    """'split/1024' or 'small/256' from the autotuner's choice line."""
+    m = re.search(r"(small-member|split) layout target_wgs=\d+ work_items=(\d+)", tune_line or "")
+    return None if m is None else ("small" if m.group(1) == "small-member" else "split") + "/" + m.group(2)
+
+
+def measured_traffic(kernel, workload, precision, layout):
+    """HBM bytes per launch recorded from FETCH_SIZE / WRITE_SIZE counter runs
+    (scaled by a plain copy of known size), or None when no record matches this
+    kernel source, workload, precision and layout."""
+    if layout is None or not os.path.exists(COUNTER_SUMMARY):
+        return None
+    want = {"kernel": kernel, "workload": workload, "precision": precision, "layout": layout,
+            "sources": dipole_sources_digest()}
+    with open(COUNTER_SUMMARY) as fh:
+        for line in fh:
+            if not line.startswith("traffic "):
+                continue
+            rec = dict(kv.split("=", 1) for kv in line.split()[1:])
+            if all(rec.get(k) == v for k, v in want.items()):
+                return float(rec["bytes_per_launch"])
+    return None
 
 
 def ordered_pairs(w):
@@ -192,9 +232,11 @@ def main():
     if pairs and kt["dipole"][1]:
         t_dip = 1e-3 * kt["dipole"][0] / kt["dipole"][1]
         achieved = FLOP_PER_PAIR * pairs / t_dip / 1e12
+        kname = "k_dipole<float>" if prec == "mixed" else "k_dipole<double>"
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                "kernel": "k_dipole<float>" if prec == "mixed" else "k_dipole<double>",
+                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                "traffic": measured_traffic(kname, args.workload, prec, layout_key(tune)),
+                "traffic_unit": "bytes per launch", "kernel": kname,
                 "pair_evals_per_s": pairs / t_dip,
                 "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": pairs}
     batching = None

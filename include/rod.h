@@ -179,7 +179,9 @@ int rod_grad(rod_ctx* c, const rod_cotangent* gy, rod_gradients* gx);
 
 /* Kernel timing with HIP events on the library's own stream.
  * While enabled (enable != 0), rod_step launches every step eagerly (no graph)
- * and brackets each kernel launch with a pair of events. rod_kernel_times
+ * and hands each kernel launch a pair of events that the runtime stamps with
+ * that kernel's own start and end (hipExtLaunchKernel), so launch gaps are
+ * not counted. rod_kernel_times
  * synchronises, adds up the elapsed time of all bracketed launches since the
  * last read per kernel class and resets the sums: ms[ROD_KERNEL_COUNT]
  * (milliseconds) and launches[ROD_KERNEL_COUNT] (host arrays, may be NULL). */

@@ -34,13 +34,14 @@ __global__ __launch_bounds__(256) void k_bond(Dev d, int want_energy) {
     for (int t = 0; t < 4; ++t) d.bE[t * N + k] = e[t];
 }
 
-hipError_t launch_bond(const Dev& d, int precision, int want_energy, hipStream_t s) {
+hipError_t launch_bond(const Dev& d, int precision, int want_energy, hipStream_t s,
+                       const hipEvent_t* ev) {
   const int bs = particle_block(d.n);
   dim3 grid((unsigned)((d.i_hi - d.i_lo + bs - 1) / bs));
   if (precision == 1)
-    hipLaunchKernelGGL(k_bond<float>, grid, dim3(bs), 0, s, d, want_energy);
+    launch_k(ev, k_bond<float>, grid, dim3(bs), s, d, want_energy);
   else
-    hipLaunchKernelGGL(k_bond<double>, grid, dim3(bs), 0, s, d, want_energy);
+    launch_k(ev, k_bond<double>, grid, dim3(bs), s, d, want_energy);
   return hipGetLastError();
 }
 

@@ -197,18 +197,18 @@ static inline unsigned contact_blocks(const Dev& d) {
   return (unsigned)((32 * (d.i_hi - d.i_lo) + 255) / 256);
 }
 
-hipError_t launch_contact(const Dev& d, int want_energy, hipStream_t s) {
+hipError_t launch_contact(const Dev& d, int want_energy, hipStream_t s, const hipEvent_t* ev) {
   if (!d.contact_on) return hipSuccess;
   if (d.n >= CONTACT_LANES_MAX_N) {
     const unsigned g = (unsigned)((d.i_hi - d.i_lo + 255) / 256);
-    if (want_energy) hipLaunchKernelGGL(k_contact_te, dim3(g), dim3(256), 0, s, d);
-    else hipLaunchKernelGGL(k_contact_t, dim3(g), dim3(256), 0, s, d);
+    if (want_energy) launch_k(ev, k_contact_te, dim3(g), dim3(256), s, d);
+    else launch_k(ev, k_contact_t, dim3(g), dim3(256), s, d);
     return hipGetLastError();
   }
   if (want_energy)
-    hipLaunchKernelGGL(k_contact_e, dim3(contact_blocks(d)), dim3(256), 0, s, d);
+    launch_k(ev, k_contact_e, dim3(contact_blocks(d)), dim3(256), s, d);
   else
-    hipLaunchKernelGGL(k_contact, dim3(contact_blocks(d)), dim3(256), 0, s, d);
+    launch_k(ev, k_contact, dim3(contact_blocks(d)), dim3(256), s, d);
   return hipGetLastError();
 }
 

@@ -179,17 +179,17 @@ __global__ __launch_bounds__(1024) void k_dipole_small(Dev d, const DipWork* __r
 }
 
 hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int nwork,
-                         hipStream_t s) {
+                         hipStream_t s, const hipEvent_t* ev) {
   if (nwork <= 0) return hipSuccess;
   if (d.dip_small) {
     if (precision == 1)
-      hipLaunchKernelGGL(k_dipole_small<float>, dim3(nwork), dim3(1024), 0, s, d, work);
+      launch_k(ev, k_dipole_small<float>, dim3(nwork), dim3(1024), s, d, work);
     else
-      hipLaunchKernelGGL(k_dipole_small<double>, dim3(nwork), dim3(1024), 0, s, d, work);
+      launch_k(ev, k_dipole_small<double>, dim3(nwork), dim3(1024), s, d, work);
   } else if (precision == 1) {
-    hipLaunchKernelGGL(k_dipole<float>, dim3(nwork), dim3(256), 0, s, d, work);
+    launch_k(ev, k_dipole<float>, dim3(nwork), dim3(256), s, d, work);
   } else {
-    hipLaunchKernelGGL(k_dipole<double>, dim3(nwork), dim3(256), 0, s, d, work);
+    launch_k(ev, k_dipole<double>, dim3(nwork), dim3(256), s, d, work);
   }
   return hipGetLastError();
 }

@@ -255,17 +255,17 @@ __global__ __launch_bounds__(256) void k_energy_reduce(Dev d, const double* E, d
 
 static inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-hipError_t launch_pre(const Dev& d, int mode, hipStream_t s) {
+hipError_t launch_pre(const Dev& d, int mode, hipStream_t s, const hipEvent_t* ev) {
   const int bs = particle_block(d.n);
-  hipLaunchKernelGGL(k_pre, dim3(blocks_for(d.i_hi - d.i_lo, bs)), dim3(bs), 0, s, d, mode);
+  launch_k(ev, k_pre, dim3(blocks_for(d.i_hi - d.i_lo, bs)), dim3(bs), s, d, mode);
   return hipGetLastError();
 }
 
 hipError_t launch_post(const Dev& d, int mode, int mask, double* Fo, double* To, double* Bo,
-                       hipStream_t s) {
+                       hipStream_t s, const hipEvent_t* ev) {
   const int bs = particle_block(d.n);
-  hipLaunchKernelGGL(k_post, dim3(blocks_for(d.i_hi - d.i_lo, bs)), dim3(bs), 0, s, d, mode, mask,
-                     Fo, To, Bo);
+  launch_k(ev, k_post, dim3(blocks_for(d.i_hi - d.i_lo, bs)), dim3(bs), s, d, mode, mask, Fo, To,
+           Bo);
   return hipGetLastError();
 }
 

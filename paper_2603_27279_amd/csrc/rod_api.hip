@@ -84,7 +84,10 @@ struct rod_ctx {
   int64_t t_cnt[ROD_KERNEL_COUNT] = {0};
 };
 
-static int timing_begin(rod_ctx* c, int kid) {
+// Event pair that the next launch of kernel class `kid` stamps with its own
+// start and end (null when timing is off).
+static int timing_events(rod_ctx* c, int kid, const hipEvent_t** ev) {
+  *ev = nullptr;
   if (!c->timing) return ROD_OK;
   while ((int)c->ev_pool.size() < 2 * (c->ev_used + 1)) {
     hipEvent_t e;
@@ -93,12 +96,7 @@ static int timing_begin(rod_ctx* c, int kid) {
   }
   if ((int)c->ev_kernel.size() < c->ev_used + 1) c->ev_kernel.resize(c->ev_used + 1);
   c->ev_kernel[c->ev_used] = kid;
-  HIPC(hipEventRecord(c->ev_pool[2 * c->ev_used], c->s));
-  return ROD_OK;
-}
-static int timing_end(rod_ctx* c) {
-  if (!c->timing) return ROD_OK;
-  HIPC(hipEventRecord(c->ev_pool[2 * c->ev_used + 1], c->s));
+  *ev = &c->ev_pool[2 * c->ev_used];
   ++c->ev_used;
   return ROD_OK;
 }
@@ -115,11 +113,11 @@ static int timing_collect(rod_ctx* c) {
   return ROD_OK;
 }
 
-#define TIMED(c, kid, expr)        \
-  do {                             \
-    TRY(timing_begin((c), (kid))); \
-    HIPC(expr);                    \
-    TRY(timing_end(c));            \
+#define TIMED(c, kid, launch, ...)                     \
+  do {                                                 \
+    const hipEvent_t* ev_ = nullptr;                   \
+    TRY(timing_events((c), (kid), &ev_));              \
+    HIPC(launch(__VA_ARGS__, ev_));                    \
   } while (0)
 
 static size_t next_pow2(size_t v) {
@@ -208,10 +206,10 @@ static int validate(const rod_desc* d) {
   return ROD_OK;
 }
 
-// Dipole work list: blocks of 256 i against j chunks of the same member; the
-// chunk count per member is chosen so the launch holds at least ~2048 work items.
-// small: -1 = automatic, 0 = 64-i blocks with split j ranges, 1 = small-member
-// layout; target_wgs: work items aimed at by the split layout.
+// Dipole work list. Split layout: blocks of 64 targets against S source ranges
+// of the same member, S chosen so the launch holds about target_wgs work items
+// (each range at least one 256-source tile). Small-member layout: blocks of 16
+// targets against the whole member. small: -1 = automatic, 0 = split, 1 = small.
 static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
   const std::vector<int>& mrange = c->mrange_h;
   const int M = c->desc.n_members;
@@ -289,18 +287,18 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
 
 // ------------------------------------------------------------------ schedule
 static int force_terms(rod_ctx* c, int want_energy) {
-  TIMED(c, ROD_KERNEL_BOND, launch_bond(c->d, c->desc.precision, want_energy, c->s));
+  TIMED(c, ROD_KERNEL_BOND, launch_bond, c->d, c->desc.precision, want_energy, c->s);
   if (c->desc.dipole_on)
-    TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole(c->d, c->desc.precision, c->work, c->nwork, c->s));
-  if (c->desc.contact_on) TIMED(c, ROD_KERNEL_CONTACT, launch_contact(c->d, want_energy, c->s));
+    TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole, c->d, c->desc.precision, c->work, c->nwork, c->s);
+  if (c->desc.contact_on) TIMED(c, ROD_KERNEL_CONTACT, launch_contact, c->d, want_energy, c->s);
   return ROD_OK;
 }
 
 static int enqueue_step(rod_ctx* c) {
-  TIMED(c, ROD_KERNEL_PRE, launch_pre(c->d, PRE_STEP, c->s));
+  TIMED(c, ROD_KERNEL_PRE, launch_pre, c->d, PRE_STEP, c->s);
   TRY(force_terms(c, 0));
-  TIMED(c, ROD_KERNEL_POST,
-        launch_post(c->d, POST_KICK, ROD_TERM_ALL, nullptr, nullptr, nullptr, c->s));
+  TIMED(c, ROD_KERNEL_POST, launch_post, c->d, POST_KICK, ROD_TERM_ALL, nullptr, nullptr, nullptr,
+        c->s);
   return ROD_OK;
 }
 
@@ -881,8 +879,13 @@ extern "C" int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, c
       cands.push_back({0, 1024});
     }
     best_us = 1e300;
+    std::vector<int> seen;  // split targets that give the same work list are timed once
     for (const Cand& cd : cands) {
       TRY(build_dipole_plan(c, cd.small, cd.target));
+      if (!cd.small) {
+        if (std::find(seen.begin(), seen.end(), c->nwork) != seen.end()) continue;
+        seen.push_back(c->nwork);
+      }
       double us = 0.0;
       TRY(time_eval(c, &us));
       char line[160];
@@ -906,9 +909,10 @@ extern "C" int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, c
   if (c->launch_mode == ROD_LAUNCH_PER_ROD) TRY(build_rod_work(c));
   drop_graphs(c);
   TRY(leave(c));
-  char line[200];
-  snprintf(line, sizeof(line), "chosen: %s target_wgs=%d (%.2f us/eval) key=%s\n",
-           small ? "small-member layout" : "split layout", target, best_us, key.c_str());
+  char line[256];
+  snprintf(line, sizeof(line), "chosen: %s target_wgs=%d work_items=%d slots=%d (%.2f us/eval) key=%s\n",
+           small ? "small-member layout" : "split layout", target, c->nwork, c->max_slots,
+           best_us, key.c_str());
   rep += line;
   if (report && report_len > 0) {
     strncpy(report, rep.c_str(), report_len - 1);

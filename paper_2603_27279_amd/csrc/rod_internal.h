@@ -1,6 +1,7 @@
 // Internal declarations shared by the kernels and the host runtime.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstdint>
 
 namespace rodmx {
@@ -73,13 +74,26 @@ struct DipWork { int i0, i1, j0, j1, slot, pad0, pad1, pad2; };
 inline int particle_block(long n) { return n < 65536 ? 64 : 256; }
 
 // Kernel launchers (each enqueues on `s`; return the launch status).
-hipError_t launch_pre(const Dev& d, int mode, hipStream_t s);
-hipError_t launch_bond(const Dev& d, int precision, int want_energy, hipStream_t s);
+// Launch that, given `ev`, has the runtime stamp ev[0] and ev[1] with the
+// kernel's own start and end (timing mode); a plain launch otherwise.
+template <typename... KArgs, typename... Args>
+inline void launch_k(const hipEvent_t* ev, void (*kernel)(KArgs...), dim3 g, dim3 b,
+                     hipStream_t s, Args... args) {
+  if (ev)
+    hipExtLaunchKernelGGL(kernel, g, b, 0u, s, ev[0], ev[1], 0u, static_cast<KArgs>(args)...);
+  else
+    hipLaunchKernelGGL(kernel, g, b, 0, s, static_cast<KArgs>(args)...);
+}
+
+hipError_t launch_pre(const Dev& d, int mode, hipStream_t s, const hipEvent_t* ev = nullptr);
+hipError_t launch_bond(const Dev& d, int precision, int want_energy, hipStream_t s,
+                       const hipEvent_t* ev = nullptr);
 hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int nwork,
-                         hipStream_t s);
-hipError_t launch_contact(const Dev& d, int want_energy, hipStream_t s);
+                         hipStream_t s, const hipEvent_t* ev = nullptr);
+hipError_t launch_contact(const Dev& d, int want_energy, hipStream_t s,
+                          const hipEvent_t* ev = nullptr);
 hipError_t launch_post(const Dev& d, int mode, int mask, double* Fout, double* Tout,
-                       double* Bout, hipStream_t s);
+                       double* Bout, hipStream_t s, const hipEvent_t* ev = nullptr);
 hipError_t launch_energy(const Dev& d, double* Epart, double* out, hipStream_t s);
 hipError_t launch_contact_pairs(const Dev& d, int* pairs, int cap, int* count, hipStream_t s);
 hipError_t launch_clear_cells(const Dev& d, hipStream_t s);
