@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 FLOP_PER_PAIR = 67.0        # algorithmic FP32 flops per ordered dipole pair (FMA = 2)
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector peak (vendor figure)
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector peak (vendor figure)
 METRIC = "particle-steps/s and dipole pair-evals/s (% FP32 peak); adjoint/forward time"
 
 WORKLOADS = {
@@ -39,15 +40,16 @@ WORKLOADS = {
 }
 
 
-# Sources that make up the dipole kernel; a change to any of them voids the
-# counter figures recorded for it.
-DIPOLE_SOURCES = ("k_dipole.hip", "rod_internal.h", "rod_math.h")
-COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_dipole_counters.md")
+# Sources that make up the force kernels; a change to any of them voids the
+# counter figures recorded for them.
+FORCE_SOURCES = ("k_forces.hip", "dipole_body.h", "bond_body.h", "bond_core.h",
+                  "contact_body.h", "k_dipole.hip", "rod_internal.h", "rod_math.h")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "force_kernel_counters.md")
 
 
-def dipole_sources_digest():
+def force_sources_digest():
     h = hashlib.sha256()
-    for f in DIPOLE_SOURCES:
+    for f in FORCE_SOURCES:
         with open(os.path.join(ROOT, "paper_2603_27279_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -66,7 +68,7 @@ def measured_traffic(kernel, workload, precision, layout):
     if layout is None or not os.path.exists(COUNTER_SUMMARY):
         return None
     want = {"kernel": kernel, "workload": workload, "precision": precision, "layout": layout,
-            "sources": dipole_sources_digest()}
+            "sources": force_sources_digest()}
     with open(COUNTER_SUMMARY) as fh:
         for line in fh:
             if not line.startswith("traffic "):
@@ -221,30 +223,50 @@ def main():
     ms_step = 1e3 * secs / args.steps
     value = n * args.steps / secs
 
-    # Kernel durations: HIP events around each launch, on the library's stream.
+    # Kernel durations: every launch stamps a pair of HIP events with its own
+    # start and end, on the library's stream. First the launches the timed steps
+    # make, then the same steps with the three force terms as separate kernels.
     sim.timing(True)
     sim.step(args.timing_steps)
     kt = sim.kernel_times()
     sim.timing(False)
+    sim.launch_mode("separate")
+    sim.timing(True)
+    sim.step(args.timing_steps)
+    kt_sep = sim.kernel_times()
+    sim.timing(False)
+    sim.launch_mode("batched")
     sim.sync()
-    kernels_us = {k: (1e3 * ms / c if c else None) for k, (ms, c) in kt.items()}
+    kernels_us = {k: (1e3 * ms / c if c else None) for k, (ms, c) in kt.items() if c}
+    kernels_sep_us = {k: (1e3 * ms / c if c else None) for k, (ms, c) in kt_sep.items() if c}
     roof = None
-    if pairs and kt["dipole"][1]:
-        t_dip = 1e-3 * kt["dipole"][0] / kt["dipole"][1]
-        achieved = FLOP_PER_PAIR * pairs / t_dip / 1e12
-        kname = "k_dipole<float>" if prec == "mixed" else "k_dipole<double>"
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+    small = "small-member" in (tune or "")
+    if pairs:
+        # dominant kernel of the timed step: the fused force kernel, or the
+        # small-member dipole kernel where that layout is chosen
+        cls = "dipole" if small or not kt["forces"][1] else "forces"
+        t_k = 1e-3 * kt[cls][0] / kt[cls][1]
+        real = "float" if prec == "mixed" else "double"
+        if cls == "forces":
+            kname = f"k_forces<{real}, {'true' if n < 65536 else 'false'}>"
+        else:
+            kname = f"k_dipole_small<{real}>" if small else f"k_dipole<{real}>"
+        peak = FP32_PEAK_TFLOPS if prec == "mixed" else FP64_PEAK_TFLOPS
+        achieved = FLOP_PER_PAIR * pairs / t_k / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": measured_traffic(kname, args.workload, prec, layout_key(tune)),
                 "traffic_unit": "bytes per launch", "kernel": kname,
-                "pair_evals_per_s": pairs / t_dip,
+                "flops_counted": "dipole pair arithmetic only (bond and contact work in the "
+                                 "same launch is not counted)" if cls == "forces" else "dipole pairs",
+                "pair_evals_per_s": pairs / t_k,
                 "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": pairs}
     batching = None
     n_rods = len(w["rod_offset"]) - 1
     if n_rods > 1 and not args.no_per_rod:
         # The same step as a plain per-rod loop (every kernel once per rod, eager).
         k = max(1, min(args.steps, args.per_rod_steps))
-        sim.launch_mode(per_rod=True)
+        sim.launch_mode("per_rod")
         sim.step(2)
         sim.sync()
         torch.cuda.synchronize()
@@ -253,7 +275,7 @@ def main():
         sim.sync()
         torch.cuda.synchronize()
         ms_rod = 1e3 * (time.perf_counter() - t0) / k
-        sim.launch_mode(per_rod=False)
+        sim.launch_mode("batched")
         batching = {"n_rods": n_rods, "per_rod_ms_per_step": ms_rod,
                     "per_rod_steps": k, "batched_ms_per_step": ms_step,
                     "speedup": ms_rod / ms_step}
@@ -284,6 +306,7 @@ def main():
                    "graph_steps": args.graph_steps, "dipole_layout": tune},
         "pair_evals_per_s": pairs * args.steps / secs if pairs else None,
         "kernel_us": kernels_us,
+        "kernel_us_separate_terms": kernels_sep_us,
         "roofline": roof,
         "batching": batching,
         "adjoint": adj,

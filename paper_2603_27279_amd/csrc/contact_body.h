@@ -1,0 +1,187 @@
+// Contact search and force: Hookean normal repulsion k (r_c - r) between particles of the
+// same member that are closer than r_c and not bonded within the exclusion
+// depth (Methods, "Contact", with the normal-only Hookean law of the workloads).
+//
+// Candidates come from the hashed cell list built by the pre kernel (cell side
+// r_c) plus the short list of particles whose cell was full. The search is
+// lane-parallel: half a wavefront serves one particle, lane c (0..26) scans
+// neighbouring cell c, whose count and slots (each slot holds the particle's
+// position and tag) are fetched in a single round trip. Lanes whose hash
+// bucket repeats a lower lane's bucket stand down, so no pair is seen twice.
+// The selection r^2 = (dx dx + dy dy) + dz dz < r_c^2 uses explicitly rounded
+// FP64 operations (no contraction), so the pair set is exactly that of a
+// brute-force search with the same expression. Per-lane sums are kept in
+// 2^-48 fixed point and added across lanes as integers: the result does not
+// depend on the order in which particles were inserted into their cells.
+#pragma once
+#include "rod_internal.h"
+#include "rod_math.h"
+
+namespace rodmx {
+
+__device__ __forceinline__ int cell_coord_c(double x, double inv) {
+  double c = floor(x * inv);
+  c = fmin(fmax(c, -1.0e9), 1.0e9);
+  return (int)c;
+}
+__device__ __forceinline__ unsigned cell_hash_c(int cx, int cy, int cz, int mem, unsigned mask) {
+  unsigned h = (unsigned)cx * 73856093u ^ (unsigned)cy * 19349663u ^ (unsigned)cz * 83492791u ^
+               (unsigned)mem * 2654435761u;
+  return h & mask;
+}
+
+__device__ __forceinline__ double r2_exact(V3<double> a, V3<double> b) {
+  double dx = __dsub_rn(a.x, b.x), dy = __dsub_rn(a.y, b.y), dz = __dsub_rn(a.z, b.z);
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+constexpr double FIX = 281474976710656.0;  // 2^48
+__device__ __forceinline__ long long to_fix(double v) { return __double2ll_rn(v * FIX); }
+
+// Sum over the 32 lanes of each half wave (integer adds: exact, any order).
+__device__ __forceinline__ long long half_sum(long long v) {
+  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
+  return v;
+}
+
+enum ContactOut { OUT_FORCE = 0, OUT_ENERGY = 1, OUT_PAIRS = 2 };
+
+// One pass of the search; what is produced depends on `OUT`.
+template <int OUT>
+__device__ __forceinline__ void contact_pass(const Dev& d, long blk, int* pairs, int cap,
+                                             int* count) {
+  const long N = d.n;
+  const int lane = threadIdx.x & 31;
+  const long i = d.i_lo + ((blk * blockDim.x + threadIdx.x) >> 5);
+  const bool pv = i < d.i_hi;
+  const long ii = pv ? i : d.i_lo;
+  const V3<double> xi = ld3(d.x, N, ii);
+  const int mem = d.mem[ii], rod = d.rod[ii];
+  const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
+  const double rc2 = d.rc * d.rc;
+  const int cx = cell_coord_c(xi.x, d.inv_cell), cy = cell_coord_c(xi.y, d.inv_cell),
+            cz = cell_coord_c(xi.z, d.inv_cell);
+  const int c = lane < 27 ? lane : 0;
+  const unsigned key = cell_hash_c(cx + c % 3 - 1, cy + (c / 3) % 3 - 1, cz + c / 9 - 1, mem,
+                                   d.cell_mask);
+  bool scan = pv && lane < 27;
+  for (int o = 0; o < 26; ++o) {  // stand down if a lower lane has the same bucket
+    unsigned ko = __shfl(key, o, 32);
+    if (o < lane && ko == key) scan = false;
+  }
+  long long fx = 0, fy = 0, fz = 0, fe = 0;
+  auto take = [&](int j, int rj, V3<double> xj) {
+    if (j == (int)i || j < mb || j >= me) return;
+    if (rj == rod && abs(j - (int)i) <= d.depth) return;
+    const double r2 = r2_exact(xi, xj);
+    if (!(r2 < rc2)) return;
+    if (OUT == OUT_PAIRS) {
+      if (j > (int)i) {
+        int p = atomicAdd(count, 1);
+        if (p < cap) { pairs[2 * p] = (int)i; pairs[2 * p + 1] = j; }
+      }
+      return;
+    }
+    const double r = sqrt(r2);
+    const double ov = d.rc - r;
+    const double s = (d.kc * ov) / r;
+    fx += to_fix(s * (xi.x - xj.x));
+    fy += to_fix(s * (xi.y - xj.y));
+    fz += to_fix(s * (xi.z - xj.z));
+    if (OUT == OUT_ENERGY) fe += to_fix(0.25 * d.kc * ov * ov);  // each pair seen from both ends
+  };
+  if (scan) {
+    const CellSlot* sl = d.cell_slot + (long)key * CELL_CAP;
+    const int nb = min(d.cell_cnt[key], CELL_CAP);
+    CellSlot e[CELL_CAP];
+#pragma unroll
+    for (int s = 0; s < CELL_CAP; ++s) e[s] = sl[s];  // slots beyond the count are ignored
+#pragma unroll
+    for (int s = 0; s < CELL_CAP; ++s)
+      if (s < nb) take((int)(e[s].tag & 0xffffffffll), (int)(e[s].tag >> 32),
+                       V3<double>{e[s].x, e[s].y, e[s].z});
+  }
+  if (pv && lane == 27) {  // particles whose cell was full
+    const int no = min(*d.ovf_cnt, OVF_CAP);
+    for (int o = 0; o < no; ++o) {
+      const int j = d.ovf_list[o];
+      take(j, d.rod[j], ld3(d.x, N, j));
+    }
+  }
+  if (OUT == OUT_PAIRS) return;
+  fx = half_sum(fx); fy = half_sum(fy); fz = half_sum(fz);
+  if (OUT == OUT_ENERGY) fe = half_sum(fe);
+  if (pv && lane == 0) {
+    st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
+    if (OUT == OUT_ENERGY) d.cE[i] = (double)fe / FIX;
+  }
+}
+
+// Variant for large systems: one thread per particle walks the 27 cells, each
+// non-empty cell costing one round trip for the slots it actually holds (far
+// less traffic than 27 lanes fetching whole cells when latency is already
+// hidden by the number of particles). Same selection, same exact sums.
+template <int OUT>
+__device__ __forceinline__ void contact_thread(const Dev& d, long blk) {
+  const long N = d.n;
+  const long i = d.i_lo + blk * blockDim.x + threadIdx.x;
+  if (i >= d.i_hi) return;
+  const V3<double> xi = ld3(d.x, N, i);
+  const int mem = d.mem[i], rod = d.rod[i];
+  const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
+  const double rc2 = d.rc * d.rc;
+  const int cx = cell_coord_c(xi.x, d.inv_cell), cy = cell_coord_c(xi.y, d.inv_cell),
+            cz = cell_coord_c(xi.z, d.inv_cell);
+  long long fx = 0, fy = 0, fz = 0, fe = 0;
+  auto take = [&](int j, int rj, V3<double> xj) {
+    if (j == (int)i || j < mb || j >= me) return;
+    if (rj == rod && abs(j - (int)i) <= d.depth) return;
+    const double r2 = r2_exact(xi, xj);
+    if (!(r2 < rc2)) return;
+    const double r = sqrt(r2);
+    const double ov = d.rc - r;
+    const double s = (d.kc * ov) / r;
+    fx += to_fix(s * (xi.x - xj.x));
+    fy += to_fix(s * (xi.y - xj.y));
+    fz += to_fix(s * (xi.z - xj.z));
+    if (OUT == OUT_ENERGY) fe += to_fix(0.25 * d.kc * ov * ov);
+  };
+  unsigned keys[27];
+  int nc[27];
+#pragma unroll
+  for (int c = 0; c < 27; ++c)
+    keys[c] = cell_hash_c(cx + c % 3 - 1, cy + (c / 3) % 3 - 1, cz + c / 9 - 1, mem, d.cell_mask);
+#pragma unroll
+  for (int c = 0; c < 27; ++c) nc[c] = d.cell_cnt[keys[c]];
+  for (int c = 0; c < 27; ++c) {
+    int nb = min(nc[c], CELL_CAP);
+    for (int o = 0; o < c; ++o)
+      if (keys[o] == keys[c]) nb = 0;  // bucket already visited
+    const CellSlot* sl = d.cell_slot + (long)keys[c] * CELL_CAP;
+    for (int s = 0; s < nb; ++s) {
+      const CellSlot e = sl[s];
+      take((int)(e.tag & 0xffffffffll), (int)(e.tag >> 32), V3<double>{e.x, e.y, e.z});
+    }
+  }
+  const int no = min(*d.ovf_cnt, OVF_CAP);
+  for (int o = 0; o < no; ++o) {
+    const int j = d.ovf_list[o];
+    take(j, d.rod[j], ld3(d.x, N, j));
+  }
+  st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
+  if (OUT == OUT_ENERGY) d.cE[i] = (double)fe / FIX;
+}
+
+constexpr long CONTACT_LANES_MAX_N = 65536;  // below: 27 lanes per particle
+
+// Workgroups of 256 threads that a pass over [i_lo, i_hi) takes: lane-parallel
+// (32 lanes per particle), and the variant chosen for this system size.
+inline unsigned contact_lane_blocks(const Dev& d) {
+  return (unsigned)((32 * (d.i_hi - d.i_lo) + 255) / 256);
+}
+inline unsigned contact_blocks(const Dev& d) {
+  return d.n >= CONTACT_LANES_MAX_N ? (unsigned)((d.i_hi - d.i_lo + 255) / 256)
+                                    : contact_lane_blocks(d);
+}
+
+}  // namespace rodmx

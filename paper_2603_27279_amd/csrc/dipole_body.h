@@ -1,0 +1,176 @@
+// All-pairs dipole-dipole sums (Methods, "Magnetic interactions").
+//
+// For every particle i and every other particle j of the same member, with
+// r = x_i - x_j, a = m_i.r, b = m_j.r, c = m_i.m_j and s = 1 / r^5:
+//   F_i += 3 s [ (c - 5 a b / r^2) r + b m_i + a m_j ]        (= -dU_ij/dx_i)
+//   B_i += 3 s b r - m_j / r^3                                (field of j at x_i)
+// and both are scaled by mu0/4pi at the end. The factor 3 is applied once per
+// particle, so the pair sums are kept as F/3 and as the two parts of B; the
+// torque m_i x B_i is formed by the particle kernel. The m_i term of F is
+// accumulated as the scalar sum of s b.
+//
+// Layout. A work item is a block of 64 consecutive i of one member (one i per
+// lane) against a j range of the same member. The four waves of a workgroup
+// split every staged j tile of 256 four ways and are reduced through LDS at
+// the end. Tiles are read from LDS as wavefront-uniform broadcasts. Position
+// differences are taken in FP64 and rounded once; on the mixed path the pair
+// arithmetic and the per-tile sums are FP32 and each tile is flushed into FP64
+// accumulators. When a member's j range is split over several work items,
+// each writes its own FP64 partial slot, and the particle kernel adds the
+// slots in slot order (deterministic, no atomics, no cross-workgroup fences).
+#pragma once
+#include "rod_internal.h"
+#include "rod_math.h"
+
+namespace rodmx {
+
+template <class R> __device__ __forceinline__ R rsq(R a);
+template <> __device__ __forceinline__ float rsq(float a) { return __builtin_amdgcn_rsqf(a); }
+template <> __device__ __forceinline__ double rsq(double a) { return 1.0 / sqrt(a); }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// A value the compiler must treat as held per lane (a vector register). Used
+// for the constant -5, which would otherwise be a literal operand, and for the
+// tile index, so that LDS addresses are formed in vector registers once per
+// unrolled step instead of being copied from scalar registers per read.
+__device__ __forceinline__ int lane_value(int v) {
+  int r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(v));
+  return r;
+}
+__device__ __forceinline__ float lane_value(float v) {
+  float r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(v));
+  return r;
+}
+
+__device__ __forceinline__ float minus5(float) { return lane_value(-5.0f); }
+__device__ __forceinline__ double minus5(double) { return -5.0; }
+
+constexpr int TJ = 256;   // j tile staged per workgroup
+constexpr int JW = 64;    // j entries of a tile handled by one wave
+
+// Pair sums: f = sum s[(c - 5ab/r^2) r + a m_j], fm = sum s b,
+// bs = sum s b r, bm = sum m_j / r^3.
+template <class R>
+struct Acc { R fx, fy, fz, fm, bsx, bsy, bsz, bmx, bmy, bmz; };
+constexpr int NACC = 10;
+
+// Add the contribution of source j (moment mj) at offset (dx, dy, dz) to target i.
+template <class R>
+__device__ __forceinline__ void pair_acc(R dx, R dy, R dz, R mjx, R mjy, R mjz, R mix, R miy,
+                                         R miz, R rinv, R m5, Acc<R>& A) {
+  const R rinv2 = rinv * rinv;
+  const R rinv3 = rinv2 * rinv;
+  const R s = rinv3 * rinv2;
+  const R a = fma_(miz, dz, fma_(miy, dy, mix * dx));
+  const R b = fma_(mjz, dz, fma_(mjy, dy, mjx * dx));
+  const R c = fma_(miz, mjz, fma_(miy, mjy, mix * mjx));
+  const R sb = s * b, sa = s * a;
+  const R al = fma_((sb * a) * rinv2, m5, s * c);
+  A.fx = fma_(sa, mjx, fma_(al, dx, A.fx));
+  A.fy = fma_(sa, mjy, fma_(al, dy, A.fy));
+  A.fz = fma_(sa, mjz, fma_(al, dz, A.fz));
+  A.fm += sb;
+  A.bsx = fma_(sb, dx, A.bsx);
+  A.bsy = fma_(sb, dy, A.bsy);
+  A.bsz = fma_(sb, dz, A.bsz);
+  A.bmx = fma_(rinv3, mjx, A.bmx);
+  A.bmy = fma_(rinv3, mjy, A.bmy);
+  A.bmz = fma_(rinv3, mjz, A.bmz);
+}
+
+// Slot values of one target from its pair sums (FP64): force and field.
+__device__ __forceinline__ void write_slot(double* p, long N, long i, double C, const double* F,
+                                           double mix, double miy, double miz) {
+  const double C3 = 3.0 * C;
+  p[i] = C3 * (F[0] + F[3] * mix);
+  p[N + i] = C3 * (F[1] + F[3] * miy);
+  p[2 * N + i] = C3 * (F[2] + F[3] * miz);
+  p[3 * N + i] = C * (3.0 * F[4] - F[7]);
+  p[4 * N + i] = C * (3.0 * F[5] - F[8]);
+  p[5 * N + i] = C * (3.0 * F[6] - F[9]);
+}
+
+// One staged source: position (FP64) and moment, contiguous so that a single
+// vector-register address with immediate offsets reaches every field.
+template <class R>
+struct alignas(8) Src { double x, y, z; R mx, my, mz; };
+
+template <class R, bool SELF>
+__device__ __forceinline__ void tile_pairs(int jb, int je, int jbase, int i, double xi, double yi,
+                                           double zi, R mix, R miy, R miz, const Src<R>* tile,
+                                           Acc<R>& A) {
+  const R m5 = minus5(R(0));
+  const Src<R>* p = tile + lane_value(jb);  // per-lane address: one increment per step
+#pragma unroll 2
+  for (int k = 0; k < je - jb; ++k) {
+    const Src<R> e = p[k];
+    const R dx = (R)(xi - e.x), dy = (R)(yi - e.y), dz = (R)(zi - e.z);
+    const R r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
+    R rinv = rsq(r2);
+    if (SELF) rinv = (jbase + jb + k == i) ? R(0) : rinv;   // the pair (i, i) contributes nothing
+    pair_acc(dx, dy, dz, e.mx, e.my, e.mz, mix, miy, miz, rinv, m5, A);
+  }
+}
+
+// LDS of one split work item: the staged tile, reused for the final reduction.
+template <class R>
+union DipSmem {
+  Src<R> tile[TJ];
+  double red[4][NACC][64];
+};
+
+// One work item of the split layout (256 threads).
+template <class R>
+__device__ __forceinline__ void dipole_item(const Dev& d, const DipWork& wk, DipSmem<R>& sm) {
+  Src<R>* tile = sm.tile;
+  const long N = d.n;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+  const int i = wk.i0 + lane;
+  const bool act = i < wk.i1;
+  const R* mu;
+  if constexpr (sizeof(R) == 4) mu = (const R*)d.muf;
+  else mu = (const R*)d.mu;
+  double xi = 0, yi = 0, zi = 0;
+  R mix = 0, miy = 0, miz = 0;
+  if (act) {
+    xi = d.x[i]; yi = d.x[N + i]; zi = d.x[2 * N + i];
+    mix = mu[i]; miy = mu[N + i]; miz = mu[2 * N + i];
+  }
+  double F[NACC] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int t0 = wk.j0; t0 < wk.j1; t0 += TJ) {
+    const int jn = min(TJ, wk.j1 - t0);
+    if ((int)threadIdx.x < jn) {
+      const int j = t0 + threadIdx.x;
+      tile[threadIdx.x] = Src<R>{d.x[j], d.x[N + j], d.x[2 * N + j], mu[j], mu[N + j], mu[2 * N + j]};
+    }
+    __syncthreads();
+    const int jb = wave * JW, je = min(jb + JW, jn);
+    if (jb < je) {
+      Acc<R> A{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      const bool self = (t0 + jb < wk.i1) && (t0 + je > wk.i0);  // sub-tile may contain i
+      if (self)
+        tile_pairs<R, true>(jb, je, t0, i, xi, yi, zi, mix, miy, miz, tile, A);
+      else
+        tile_pairs<R, false>(jb, je, t0, i, xi, yi, zi, mix, miy, miz, tile, A);
+      F[0] += A.fx; F[1] += A.fy; F[2] += A.fz; F[3] += A.fm;
+      F[4] += A.bsx; F[5] += A.bsy; F[6] += A.bsz;
+      F[7] += A.bmx; F[8] += A.bmy; F[9] += A.bmz;
+    }
+    __syncthreads();
+  }
+  // Sum the four waves in wave order and write this work item's slot.
+  // (the last tile pass ended with a barrier, so the tile may be overwritten)
+  for (int k = 0; k < NACC; ++k) sm.red[wave][k][lane] = F[k];
+  __syncthreads();
+  if (wave == 0 && act) {
+    for (int k = 0; k < NACC; ++k)
+      F[k] = ((sm.red[0][k][lane] + sm.red[1][k][lane]) + sm.red[2][k][lane]) + sm.red[3][k][lane];
+    write_slot(d.dpart + (long)wk.slot * 6 * N, N, i, d.C, F, mix, miy, miz);
+  }
+}
+
+}  // namespace rodmx

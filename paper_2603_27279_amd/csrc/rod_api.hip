@@ -287,6 +287,12 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
 
 // ------------------------------------------------------------------ schedule
 static int force_terms(rod_ctx* c, int want_energy) {
+  if (!want_energy && c->launch_mode == ROD_LAUNCH_BATCHED) {
+    if (c->desc.dipole_on && c->d.dip_small)
+      TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole, c->d, c->desc.precision, c->work, c->nwork, c->s);
+    TIMED(c, ROD_KERNEL_FORCES, launch_forces, c->d, c->desc.precision, c->work, c->nwork, c->s);
+    return ROD_OK;
+  }
   TIMED(c, ROD_KERNEL_BOND, launch_bond, c->d, c->desc.precision, want_energy, c->s);
   if (c->desc.dipole_on)
     TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole, c->d, c->desc.precision, c->work, c->nwork, c->s);
@@ -824,10 +830,16 @@ static std::string tune_key(rod_ctx* c) {
 
 extern "C" int rod_launch_mode(rod_ctx* c, int32_t mode) {
   if (!c) return fail(ROD_E_INVALID, "context is NULL");
-  if (mode != ROD_LAUNCH_BATCHED && mode != ROD_LAUNCH_PER_ROD)
-    return fail(ROD_E_INVALID, "mode must be ROD_LAUNCH_BATCHED or ROD_LAUNCH_PER_ROD");
+  if (mode != ROD_LAUNCH_BATCHED && mode != ROD_LAUNCH_PER_ROD && mode != ROD_LAUNCH_SEPARATE)
+    return fail(ROD_E_INVALID, "mode must be one of ROD_LAUNCH_BATCHED, _PER_ROD, _SEPARATE");
+  if (c->tape.active) return fail(ROD_E_STATE, "launch mode change while a tape is recorded");
+  if (mode == c->launch_mode) return ROD_OK;
+  TRY(enter(c));
   if (mode == ROD_LAUNCH_PER_ROD) TRY(build_rod_work(c));
+  HIPC(hipStreamSynchronize(c->s));  // captured steps of the old mode may still run
+  drop_graphs(c);
   c->launch_mode = mode;
+  TRY(leave(c));
   return ROD_OK;
 }
 

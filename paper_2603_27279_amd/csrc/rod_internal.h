@@ -92,6 +92,9 @@ hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int n
                          hipStream_t s, const hipEvent_t* ev = nullptr);
 hipError_t launch_contact(const Dev& d, int want_energy, hipStream_t s,
                           const hipEvent_t* ev = nullptr);
+// Dipole (split layout), bond and contact forces of a step in one launch.
+hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int nwork, hipStream_t s,
+                         const hipEvent_t* ev = nullptr);
 hipError_t launch_post(const Dev& d, int mode, int mask, double* Fout, double* Tout,
                        double* Bout, hipStream_t s, const hipEvent_t* ev = nullptr);
 hipError_t launch_energy(const Dev& d, double* Epart, double* out, hipStream_t s);

@@ -175,9 +175,12 @@ class RodSim:
         L.check(self.lib.rod_autotune(self.ctx, path, int(bool(force)), buf, len(buf)))
         return buf.value.decode()
 
-    def launch_mode(self, per_rod=False):
-        """Batched launches (default) or the plain per-rod loop (baseline)."""
-        L.check(self.lib.rod_launch_mode(self.ctx, 1 if per_rod else 0))
+    LAUNCH_MODES = {"batched": 0, "per_rod": 1, "separate": 2}
+
+    def launch_mode(self, mode="batched"):
+        """'batched' (default: all rods per launch, force terms fused), 'separate'
+        (force terms as separate kernels) or 'per_rod' (the plain per-rod loop)."""
+        L.check(self.lib.rod_launch_mode(self.ctx, self.LAUNCH_MODES[mode]))
 
     def dipole_layout(self, small=-1, target_wgs=1024):
         """Choose the dipole work layout explicitly (see rod_dipole_layout)."""

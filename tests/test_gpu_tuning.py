@@ -87,18 +87,19 @@ def _many_rods():
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("layout", [(1, 1024), (0, 64), (0, 4096)])
-def test_per_rod_loop_matches_batched_bitwise(layout, prec):
+def test_launch_modes_match_bitwise(layout, prec):
     w = _many_rods()
     states = []
-    for per_rod in (False, True):
-        sim = RodSim(w, precision=prec, graph_steps=0 if per_rod else 10)
+    for mode in ("batched", "separate", "per_rod"):
+        sim = RodSim(w, precision=prec, graph_steps=0 if mode == "per_rod" else 10)
         sim.dipole_layout(*layout)
-        sim.launch_mode(per_rod=per_rod)
+        sim.launch_mode(mode)
         sim.step(30)
         states.append(sim.state())
         sim.free()
-    for k in ("x", "v", "q", "w", "F", "T"):
-        np.testing.assert_array_equal(states[0][k], states[1][k])
+    for st in states[1:]:
+        for k in ("x", "v", "q", "w", "F", "T"):
+            np.testing.assert_array_equal(states[0][k], st[k])
     o = oracle.run(w, 30)
     motion = np.max(np.abs(o["x"] - w["x0"]))
-    assert np.max(np.abs(states[1]["x"] - o["x"])) / motion <= (1e-9 if prec == "fp64" else 1e-4)
+    assert np.max(np.abs(states[0]["x"] - o["x"])) / motion <= (1e-9 if prec == "fp64" else 1e-4)
