@@ -192,7 +192,8 @@ enum {
   ROD_KERNEL_CONTACT = 3, /* cell-list contact */
   ROD_KERNEL_POST = 4,    /* force gather, Zeeman, damping, second half-kick */
   ROD_KERNEL_FORCES = 5,  /* dipole (split layout), bond and contact in one launch */
-  ROD_KERNEL_COUNT = 6
+  ROD_KERNEL_KICK = 6,    /* post of one step fused with pre of the next */
+  ROD_KERNEL_COUNT = 7
 };
 int rod_timing(rod_ctx* c, int32_t enable);
 int rod_kernel_times(rod_ctx* c, double* ms, int64_t* launches);
@@ -213,10 +214,12 @@ int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, char* report
                  int32_t report_len);
 
 /* Launch mode of rod_step. ROD_LAUNCH_BATCHED (default): each kernel serves all
- * rods and members in one launch (graph-captured when graph_steps > 0), and
- * the dipole, bond and contact forces of a step share one launch.
+ * rods and members in one launch (graph-captured when graph_steps > 0); the
+ * dipole, bond and contact forces of a step share one launch, and between two
+ * consecutive steps of one call the closing half-kick and the next step's
+ * opening half-kick, drift and rotation share one launch.
  * ROD_LAUNCH_SEPARATE: as batched, with the three force terms launched as
- * separate kernels (per-term timing). ROD_LAUNCH_PER_ROD: the plain per-rod
+ * separate kernels and no kick fusion (per-term timing). ROD_LAUNCH_PER_ROD: the plain per-rod
  * loop, every kernel launched once per rod on that rod's particles, eagerly;
  * kept as the baseline the batched form is measured against. All three give
  * bitwise identical states. */

@@ -12,7 +12,7 @@ ROD_FP64, ROD_MIXED = 0, 1
 TERM_BOND, TERM_DIPOLE, TERM_ZEEMAN, TERM_CONTACT, TERM_DAMP, TERM_EXT, TERM_ALL = \
     1, 2, 4, 8, 16, 32, 63
 
-KERNELS = ("pre", "bond", "dipole", "contact", "post", "forces")
+KERNELS = ("pre", "bond", "dipole", "contact", "post", "forces", "kick")
 
 _P = C.c_void_p
 

@@ -64,6 +64,7 @@ __device__ __forceinline__ void contact_pass(const Dev& d, long blk, int* pairs,
   const int c = lane < 27 ? lane : 0;
   const unsigned key = cell_hash_c(cx + c % 3 - 1, cy + (c / 3) % 3 - 1, cz + c / 9 - 1, mem,
                                    d.cell_mask);
+  const CellTab tab = cell_tab(d, d.step[d.lc]);  // cell list of the level being evaluated
   bool scan = pv && lane < 27;
   for (int o = 0; o < 26; ++o) {  // stand down if a lower lane has the same bucket
     unsigned ko = __shfl(key, o, 32);
@@ -91,8 +92,8 @@ __device__ __forceinline__ void contact_pass(const Dev& d, long blk, int* pairs,
     if (OUT == OUT_ENERGY) fe += to_fix(0.25 * d.kc * ov * ov);  // each pair seen from both ends
   };
   if (scan) {
-    const CellSlot* sl = d.cell_slot + (long)key * CELL_CAP;
-    const int nb = min(d.cell_cnt[key], CELL_CAP);
+    const CellSlot* sl = tab.slot + (long)key * CELL_CAP;
+    const int nb = min(tab.cnt[key], CELL_CAP);
     CellSlot e[CELL_CAP];
 #pragma unroll
     for (int s = 0; s < CELL_CAP; ++s) e[s] = sl[s];  // slots beyond the count are ignored
@@ -102,9 +103,9 @@ __device__ __forceinline__ void contact_pass(const Dev& d, long blk, int* pairs,
                        V3<double>{e[s].x, e[s].y, e[s].z});
   }
   if (pv && lane == 27) {  // particles whose cell was full
-    const int no = min(*d.ovf_cnt, OVF_CAP);
+    const int no = min(*tab.ovf_cnt, OVF_CAP);
     for (int o = 0; o < no; ++o) {
-      const int j = d.ovf_list[o];
+      const int j = tab.ovf[o];
       take(j, d.rod[j], ld3(d.x, N, j));
     }
   }
@@ -146,26 +147,27 @@ __device__ __forceinline__ void contact_thread(const Dev& d, long blk) {
     fz += to_fix(s * (xi.z - xj.z));
     if (OUT == OUT_ENERGY) fe += to_fix(0.25 * d.kc * ov * ov);
   };
+  const CellTab tab = cell_tab(d, d.step[d.lc]);
   unsigned keys[27];
   int nc[27];
 #pragma unroll
   for (int c = 0; c < 27; ++c)
     keys[c] = cell_hash_c(cx + c % 3 - 1, cy + (c / 3) % 3 - 1, cz + c / 9 - 1, mem, d.cell_mask);
 #pragma unroll
-  for (int c = 0; c < 27; ++c) nc[c] = d.cell_cnt[keys[c]];
+  for (int c = 0; c < 27; ++c) nc[c] = tab.cnt[keys[c]];
   for (int c = 0; c < 27; ++c) {
     int nb = min(nc[c], CELL_CAP);
     for (int o = 0; o < c; ++o)
       if (keys[o] == keys[c]) nb = 0;  // bucket already visited
-    const CellSlot* sl = d.cell_slot + (long)keys[c] * CELL_CAP;
+    const CellSlot* sl = tab.slot + (long)keys[c] * CELL_CAP;
     for (int s = 0; s < nb; ++s) {
       const CellSlot e = sl[s];
       take((int)(e.tag & 0xffffffffll), (int)(e.tag >> 32), V3<double>{e.x, e.y, e.z});
     }
   }
-  const int no = min(*d.ovf_cnt, OVF_CAP);
+  const int no = min(*tab.ovf_cnt, OVF_CAP);
   for (int o = 0; o < no; ++o) {
-    const int j = d.ovf_list[o];
+    const int j = tab.ovf[o];
     take(j, d.rod[j], ld3(d.x, N, j));
   }
   st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});

@@ -334,18 +334,19 @@ __global__ __launch_bounds__(256) void k_adj_contact(Dev d, Adj a, const double*
     sy += __double2ll_rn(out.y * FIX);
     sz += __double2ll_rn(out.z * FIX);
   };
+  const CellTab tab = cell_tab(d, d.step[d.lc]);
   if (scan) {
-    const CellSlot* sl = d.cell_slot + (long)key * CELL_CAP;
-    const int nb = min(d.cell_cnt[key], CELL_CAP);
+    const CellSlot* sl = tab.slot + (long)key * CELL_CAP;
+    const int nb = min(tab.cnt[key], CELL_CAP);
     for (int s = 0; s < nb; ++s) {
       const CellSlot e = sl[s];
       take((int)(e.tag & 0xffffffffll), (int)(e.tag >> 32), V3<double>{e.x, e.y, e.z});
     }
   }
   if (pv && lane == 27) {
-    const int no = min(*d.ovf_cnt, OVF_CAP);
+    const int no = min(*tab.ovf_cnt, OVF_CAP);
     for (int o = 0; o < no; ++o) {
-      const int j = d.ovf_list[o];
+      const int j = tab.ovf[o];
       take(j, d.rod[j], ldv(S1, N, j));
     }
   }
@@ -509,7 +510,7 @@ int tape_init(Tape& t, const Dev& d, int every, int capacity, std::vector<void*>
   ATRY(adalloc(allocs, &a.mbbar, 3 * N));
   ATRY(adalloc(allocs, &a.fieldbar, (size_t)d.field_len * d.M * 12));
   ATRY(adalloc(allocs, &a.scratch, 6 * N));
-  ATRY(adalloc(allocs, &a.level, 2));
+  ATRY(adalloc(allocs, &a.level, 3));
   ATRY(adalloc(allocs, &a.lbase, 1));
   return ROD_OK;
 }

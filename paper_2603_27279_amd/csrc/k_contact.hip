@@ -20,8 +20,9 @@ __global__ __launch_bounds__(256) void k_contact_pairs(Dev d, int* pairs, int ca
 // Empty the cell list built by a pre pass that had no particle pass after it.
 __global__ __launch_bounds__(256) void k_clear_cells(Dev d) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < d.n) d.cell_cnt[d.key[i]] = 0;
-  if (i == 0) *d.ovf_cnt = 0;
+  const CellTab tab = cell_tab(d, d.step[d.lc]);
+  if (i < d.n) tab.cnt[d.key[i]] = 0;
+  if (i == 0) *tab.ovf_cnt = 0;
 }
 
 hipError_t launch_clear_cells(const Dev& d, hipStream_t s) {

@@ -3,8 +3,13 @@
 // force gather with Zeeman, damping and external terms followed by the second
 // half-kick (post). SI "Equations of motion"; dipoles rotate with the particle
 // (main text, magnetised beams); Zeeman force and torque (Methods).
+#include "rod.h"
 #include "rod_internal.h"
 #include "rod_math.h"
+
+// Contract a*b+c only within one expression, so that the separate and the
+// fused form of a step round identically.
+#pragma clang fp contract(on)
 
 namespace rodmx {
 
@@ -42,11 +47,67 @@ __device__ __forceinline__ unsigned cell_hash(int cx, int cy, int cz, int mem, u
   return h & mask;
 }
 
+// Advance particle i from its state at level lvl - 1 (in registers) to level
+// lvl: half-kick, drift and quaternion update of free particles; the imposed
+// rotation of driven ones. States of particles that do not move are written
+// only when `copy_still` is set (out-of-place step).
+__device__ __forceinline__ void advance(const Dev& d, long i, int b, long long lvl, V3<double>& x,
+                                        V3<double>& v, Q4<double>& q, V3<double>& w,
+                                        V3<double> F, V3<double> T, bool copy_still) {
+  const long N = d.n;
+  if (b == 0) {
+    const double h = 0.5 * d.dt;
+    v = v + (h * d.minv[i]) * F;
+    x = x + d.dt * v;
+    w = w + (h * d.Iinv[i]) * T;
+    q = richardson(q, w, d.dt);
+    st3(d.v, N, i, v);
+    st3(d.x, N, i, x);
+    st3(d.w, N, i, w);
+    st4(d.q, N, i, q);
+  } else {
+    if (b == 2) q = drive_q(d, lvl);
+    if (copy_still || b == 2) st4(d.q, N, i, q);
+    if (copy_still) {
+      st3(d.x, N, i, x);
+      st3(d.v, N, i, v);
+      st3(d.w, N, i, w);
+    }
+  }
+}
+
+// Dipole moment in the global frame, m = q m_body q*, and the particle's entry
+// in the cell list of level lvl.
+__device__ __forceinline__ void moment_and_cell(const Dev& d, long i, Q4<double> q, V3<double> x,
+                                                long long lvl) {
+  const long N = d.n;
+  V3<double> m = qrot(q, ld3(d.mb, N, i));
+  st3(d.mu, N, i, m);
+  if (d.muf) st3(d.muf, N, i, V3<float>{(float)m.x, (float)m.y, (float)m.z});
+  if (d.contact_on) {
+    const CellTab t = cell_tab(d, lvl);
+    unsigned key = cell_hash(cell_coord(x.x, d.inv_cell), cell_coord(x.y, d.inv_cell),
+                             cell_coord(x.z, d.inv_cell), d.mem[i], d.cell_mask);
+    int slot = atomicAdd(&t.cnt[key], 1);
+    if (slot < CELL_CAP) {
+      CellSlot e;
+      e.x = x.x; e.y = x.y; e.z = x.z;
+      e.tag = (long long)(unsigned)i | ((long long)d.rod[i] << 32);
+      t.slot[(long)key * CELL_CAP + slot] = e;
+    } else {
+      int o = atomicAdd(t.ovf_cnt, 1);
+      if (o < OVF_CAP) t.ovf[o] = (int)i;
+      else atomicOr(&d.flags[FLAG_LIST_OVF], 1u);
+    }
+    d.key[i] = (int)key;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
   const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long n = d.step[0];
   const long long lvl = n + (mode == PRE_STEP ? 1 : 0);  // level of the coming force evaluation
-  if (i == 0) d.step[1] = lvl;
+  if (i == 0) d.step[d.lc] = lvl;
   if (i >= d.i_hi) return;
   const long N = d.n;
   const int b = d.bc[i];
@@ -58,26 +119,10 @@ __global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
   const double* sF = d.src ? d.src + 13 * N : d.F;
   const double* sT = d.src ? d.src + 16 * N : d.T;
   Q4<double> q = ld4(sq, N, i);
+  V3<double> x = ld3(sx, N, i);
   if (mode == PRE_STEP) {
-    if (b == 0) {
-      const double h = 0.5 * d.dt;
-      V3<double> v = ld3(sv, N, i) + (h * d.minv[i]) * ld3(sF, N, i);
-      V3<double> x = ld3(sx, N, i) + d.dt * v;
-      V3<double> w = ld3(sw, N, i) + (h * d.Iinv[i]) * ld3(sT, N, i);
-      q = richardson(q, w, d.dt);
-      st3(d.v, N, i, v);
-      st3(d.x, N, i, x);
-      st3(d.w, N, i, w);
-      st4(d.q, N, i, q);
-    } else {
-      if (b == 2) q = drive_q(d, n + 1);
-      if (d.src || b == 2) st4(d.q, N, i, q);
-      if (d.src) {  // particles that do not move keep their state
-        st3(d.x, N, i, ld3(sx, N, i));
-        st3(d.v, N, i, ld3(sv, N, i));
-        st3(d.w, N, i, ld3(sw, N, i));
-      }
-    }
+    V3<double> v = ld3(sv, N, i), w = ld3(sw, N, i);
+    advance(d, i, b, lvl, x, v, q, w, ld3(sF, N, i), ld3(sT, N, i), d.src != nullptr);
   } else if (mode == PRE_PREPARE) {
     q = qnormalize(q);
     if (b != 0) {
@@ -92,120 +137,151 @@ __global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
     }
     st4(d.q, N, i, q);
   }
-  // Dipole moment in the global frame: m = q m_body q*.
-  V3<double> m = qrot(q, ld3(d.mb, N, i));
-  st3(d.mu, N, i, m);
-  if (d.muf) st3(d.muf, N, i, V3<float>{(float)m.x, (float)m.y, (float)m.z});
-  // Hashed cell list insertion for the contact search.
-  if (d.contact_on) {
-    V3<double> x = ld3(d.x, N, i);
-    unsigned key = cell_hash(cell_coord(x.x, d.inv_cell), cell_coord(x.y, d.inv_cell),
-                             cell_coord(x.z, d.inv_cell), d.mem[i], d.cell_mask);
-    int slot = atomicAdd(&d.cell_cnt[key], 1);
-    if (slot < CELL_CAP) {
-      CellSlot e;
-      e.x = x.x; e.y = x.y; e.z = x.z;
-      e.tag = (long long)(unsigned)i | ((long long)d.rod[i] << 32);
-      d.cell_slot[(long)key * CELL_CAP + slot] = e;
-    } else {
-      int o = atomicAdd(d.ovf_cnt, 1);
-      if (o < OVF_CAP) d.ovf_list[o] = (int)i;
-      else atomicOr(&d.flags[FLAG_LIST_OVF], 1u);
-    }
-    d.key[i] = (int)key;
-  }
+  moment_and_cell(d, i, q, x, lvl);
 }
 
 __device__ __forceinline__ bool finite3(V3<double> a) {
   return isfinite(a.x) && isfinite(a.y) && isfinite(a.z);
 }
 
+// Total force and torque on particle i from the terms in `mask` at level lvl
+// (bond, dipole slots, Zeeman, contact, damping, external); the dipole field
+// is written to Bo when given.
+__device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long lvl, double* Bo,
+                                       V3<double>& F, V3<double>& T) {
+  const long N = d.n;
+  F = V3<double>{0.0, 0.0, 0.0};
+  T = V3<double>{0.0, 0.0, 0.0};
+  const uint8_t bf = d.bflags[i];
+  if (mask & 1) {  // bonds: +F, tau_s + tau_bt from bond (i, i+1); -F, tau_s - tau_bt from (i-1, i)
+    if (bf & 1) {
+      F = F + ld3(d.bF, N, i);
+      T = T + ld3(d.bTs, N, i) + ld3(d.bTbt, N, i);
+    }
+    if (bf & 2) {
+      F = F - ld3(d.bF, N, i - 1);
+      T = T + ld3(d.bTs, N, i - 1) - ld3(d.bTbt, N, i - 1);
+    }
+  }
+  const V3<double> m = ld3(d.mu, N, i);
+  const int mem = d.mem[i];
+  V3<double> Bd{0.0, 0.0, 0.0};
+  if ((mask & 2) && d.dipole_on) {  // dipole-dipole: sum of the partial slots, torque m x B_dip
+    // Slots are added in slot order; eight slots are fetched per round trip.
+    V3<double> Fd{0.0, 0.0, 0.0};
+    const int S = d.mslots[mem];
+    for (int s0 = 0; s0 < S; s0 += 8) {
+      double v[8][6];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const double* p = d.dpart + (long)(s0 + k) * 6 * N;
+        if (s0 + k < S)
+          for (int c = 0; c < 6; ++c) v[k][c] = p[c * N + i];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (s0 + k < S) {
+          Fd = Fd + V3<double>{v[k][0], v[k][1], v[k][2]};
+          Bd = Bd + V3<double>{v[k][3], v[k][4], v[k][5]};
+        }
+    }
+    F = F + Fd;
+    T = T + cross(m, Bd);
+  }
+  if (Bo) st3(Bo, N, i, Bd);
+  if (mask & 4) {  // Zeeman: B = B0 + G x, f = G^T m, tau = m x B
+    long long L = d.field_len;
+    long long row = ((lvl % L) + L) % L;
+    const double* f = d.field + (row * d.M + mem) * 12;
+    V3<double> x = ld3(d.x, N, i);
+    V3<double> B{f[0] + f[3] * x.x + f[4] * x.y + f[5] * x.z,
+                 f[1] + f[6] * x.x + f[7] * x.y + f[8] * x.z,
+                 f[2] + f[9] * x.x + f[10] * x.y + f[11] * x.z};
+    F = F + V3<double>{f[3] * m.x + f[6] * m.y + f[9] * m.z,
+                       f[4] * m.x + f[7] * m.y + f[10] * m.z,
+                       f[5] * m.x + f[8] * m.y + f[11] * m.z};
+    T = T + cross(m, B);
+  }
+  if ((mask & 8) && d.contact_on) F = F + ld3(d.cF, N, i);
+  if (mask & 16) {  // global viscous damping with the current (half-step) velocities
+    F = F - (d.damping * d.mass[i]) * ld3(d.v, N, i);
+    T = T - (d.damping * d.inertia[i]) * ld3(d.w, N, i);
+  }
+  if (mask & 32) {
+    if (d.extF) F = F + ld3(d.extF, N, i);
+    if (d.extT) T = T + ld3(d.extT, N, i);
+  }
+}
+
+// Store the forces of the state and apply the second half-kick to free
+// particles; returns the kicked velocities. Flags non-finite values.
+__device__ __forceinline__ void kick(const Dev& d, long i, int b, V3<double> F, V3<double> T,
+                                     V3<double>& v, V3<double>& w) {
+  const long N = d.n;
+  st3(d.F, N, i, F);
+  st3(d.T, N, i, T);
+  v = ld3(d.v, N, i);
+  w = ld3(d.w, N, i);
+  if (b == 0) {
+    const double h = 0.5 * d.dt;
+    v = v + (h * d.minv[i]) * F;
+    w = w + (h * d.Iinv[i]) * T;
+    st3(d.v, N, i, v);
+    st3(d.w, N, i, w);
+  }
+  if (!finite3(F) || !finite3(T) || !finite3(ld3(d.x, N, i)))
+    atomicOr(&d.flags[FLAG_NONFINITE], 1u);
+}
+
 __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double* Fo, double* To,
                                               double* Bo) {
   const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long N = d.n;
-  const long long lvl = d.step[1];  // level of the forces being gathered
+  const long long lvl = d.step[d.lc];  // level of the forces being gathered
   if (i == 0) {
     if (mode == POST_KICK) d.step[0] = lvl;
-    *d.ovf_cnt = 0;  // the contact pass that used the overflow list has finished
+    *cell_tab(d, lvl).ovf_cnt = 0;  // the contact pass that used the overflow list has finished
   }
-  if (i < d.i_hi) {
-    V3<double> F{0.0, 0.0, 0.0}, T{0.0, 0.0, 0.0};
-    const uint8_t bf = d.bflags[i];
-    if (mask & 1) {  // bonds: +F, tau_s + tau_bt from bond (i, i+1); -F, tau_s - tau_bt from (i-1, i)
-      if (bf & 1) {
-        F = F + ld3(d.bF, N, i);
-        T = T + ld3(d.bTs, N, i) + ld3(d.bTbt, N, i);
-      }
-      if (bf & 2) {
-        F = F - ld3(d.bF, N, i - 1);
-        T = T + ld3(d.bTs, N, i - 1) - ld3(d.bTbt, N, i - 1);
-      }
-    }
-    const V3<double> m = ld3(d.mu, N, i);
-    const int mem = d.mem[i];
-    V3<double> Bd{0.0, 0.0, 0.0};
-    if ((mask & 2) && d.dipole_on) {  // dipole-dipole: sum of the partial slots, torque m x B_dip
-      // Slots are added in slot order; eight slots are fetched per round trip.
-      V3<double> Fd{0.0, 0.0, 0.0};
-      const int S = d.mslots[mem];
-      for (int s0 = 0; s0 < S; s0 += 8) {
-        double v[8][6];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const double* p = d.dpart + (long)(s0 + k) * 6 * N;
-          if (s0 + k < S)
-            for (int c = 0; c < 6; ++c) v[k][c] = p[c * N + i];
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-          if (s0 + k < S) {
-            Fd = Fd + V3<double>{v[k][0], v[k][1], v[k][2]};
-            Bd = Bd + V3<double>{v[k][3], v[k][4], v[k][5]};
-          }
-      }
-      F = F + Fd;
-      T = T + cross(m, Bd);
-    }
-    if (Bo) st3(Bo, N, i, Bd);
-    if (mask & 4) {  // Zeeman: B = B0 + G x, f = G^T m, tau = m x B
-      long long L = d.field_len;
-      long long row = ((lvl % L) + L) % L;
-      const double* f = d.field + (row * d.M + mem) * 12;
-      V3<double> x = ld3(d.x, N, i);
-      V3<double> B{f[0] + f[3] * x.x + f[4] * x.y + f[5] * x.z,
-                   f[1] + f[6] * x.x + f[7] * x.y + f[8] * x.z,
-                   f[2] + f[9] * x.x + f[10] * x.y + f[11] * x.z};
-      F = F + V3<double>{f[3] * m.x + f[6] * m.y + f[9] * m.z,
-                         f[4] * m.x + f[7] * m.y + f[10] * m.z,
-                         f[5] * m.x + f[8] * m.y + f[11] * m.z};
-      T = T + cross(m, B);
-    }
-    if ((mask & 8) && d.contact_on) F = F + ld3(d.cF, N, i);
-    if (mask & 16) {  // global viscous damping with the current (half-step) velocities
-      F = F - (d.damping * d.mass[i]) * ld3(d.v, N, i);
-      T = T - (d.damping * d.inertia[i]) * ld3(d.w, N, i);
-    }
-    if (mask & 32) {
-      if (d.extF) F = F + ld3(d.extF, N, i);
-      if (d.extT) T = T + ld3(d.extT, N, i);
-    }
-    if (mode == POST_EVAL) {
-      st3(Fo, N, i, F);
-      st3(To, N, i, T);
-    } else {
-      st3(d.F, N, i, F);
-      st3(d.T, N, i, T);
-      if (mode == POST_KICK && d.bc[i] == 0) {
-        const double h = 0.5 * d.dt;
-        st3(d.v, N, i, ld3(d.v, N, i) + (h * d.minv[i]) * F);
-        st3(d.w, N, i, ld3(d.w, N, i) + (h * d.Iinv[i]) * T);
-      }
-      if (!finite3(F) || !finite3(T) || !finite3(ld3(d.x, N, i)))
-        atomicOr(&d.flags[FLAG_NONFINITE], 1u);
-    }
-    if (d.contact_on) d.cell_cnt[d.key[i]] = 0;  // empty the cell list for the next build
+  if (i >= d.i_hi) return;
+  V3<double> F, T;
+  gather(d, i, mask, lvl, Bo, F, T);
+  if (mode == POST_EVAL) {
+    st3(Fo, N, i, F);
+    st3(To, N, i, T);
+  } else if (mode == POST_KICK) {
+    V3<double> v, w;
+    kick(d, i, d.bc[i], F, T, v, w);
+  } else {  // prepare: forces of the initial state, no kick
+    st3(d.F, N, i, F);
+    st3(d.T, N, i, T);
+    if (!finite3(F) || !finite3(T) || !finite3(ld3(d.x, N, i)))
+      atomicOr(&d.flags[FLAG_NONFINITE], 1u);
   }
+  if (d.contact_on) cell_tab(d, lvl).cnt[d.key[i]] = 0;  // empty the cell list for the next build
+}
+
+// The end of one step and the start of the next in one pass: gather and second
+// half-kick at level L = step[lc], then half-kick, drift, rotation, moments and
+// cell insertion for level L + 1 (written to step[3 - lc]). The cell list and
+// overflow list of level L are emptied while those of level L + 1 are filled.
+__global__ __launch_bounds__(256) void k_kick(Dev d) {
+  const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long N = d.n;
+  const long long L = d.step[d.lc];
+  if (i == 0) {
+    d.step[3 - d.lc] = L + 1;
+    *cell_tab(d, L).ovf_cnt = 0;
+  }
+  if (i >= d.i_hi) return;
+  const int b = d.bc[i];
+  V3<double> F, T, v, w;
+  gather(d, i, ROD_TERM_ALL, L, nullptr, F, T);
+  kick(d, i, b, F, T, v, w);
+  if (d.contact_on) cell_tab(d, L).cnt[d.key[i]] = 0;
+  V3<double> x = ld3(d.x, N, i);
+  Q4<double> q = ld4(d.q, N, i);
+  advance(d, i, b, L + 1, x, v, q, w, F, T, false);
+  moment_and_cell(d, i, q, x, L + 1);
 }
 
 // Per-particle energy terms [9][N]: bond terms attributed to the bond's first
@@ -214,7 +290,7 @@ __global__ __launch_bounds__(256) void k_energy_part(Dev d, const double* Bdip, 
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long N = d.n;
   if (i >= N) return;
-  const long long lvl = d.step[1];
+  const long long lvl = d.step[d.lc];
   const bool hb = d.bflags[i] & 1;
   for (int t = 0; t < 4; ++t) E[t * N + i] = hb ? d.bE[t * N + i] : 0.0;
   const V3<double> m = ld3(d.mu, N, i);
@@ -266,6 +342,12 @@ hipError_t launch_post(const Dev& d, int mode, int mask, double* Fo, double* To,
   const int bs = particle_block(d.n);
   launch_k(ev, k_post, dim3(blocks_for(d.i_hi - d.i_lo, bs)), dim3(bs), s, d, mode, mask, Fo, To,
            Bo);
+  return hipGetLastError();
+}
+
+hipError_t launch_kick(const Dev& d, hipStream_t s, const hipEvent_t* ev) {
+  const int bs = particle_block(d.n);
+  launch_k(ev, k_kick, dim3(blocks_for(d.i_hi - d.i_lo, bs)), dim3(bs), s, d);
   return hipGetLastError();
 }
 

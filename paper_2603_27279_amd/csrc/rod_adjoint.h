@@ -27,7 +27,7 @@ struct Adj {
   double *mbbar;        // [3N] gradient w.r.t. the body dipoles
   double *fieldbar;     // [L][M][12] gradient w.r.t. the field table
   double *scratch;      // [6N] outputs of evaluations whose values are not needed
-  long long* level;     // [2] time-level counters of the recompute view
+  long long* level;     // [3] time-level counters of the recompute view
   long long* lbase;     // [1] first level of the segment being reversed
 };
 

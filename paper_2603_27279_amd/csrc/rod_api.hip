@@ -280,30 +280,51 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
   b += N * (1 + 4 + 4 + 1) + 8 * N * 4 + 8 * N * 4 + 8 * R * 4 + 4 * M * 3;  // topology
   b += 8 * 3 * N + 4 * 3 * N + 8 * 9 * N + 8 * 4 * N;                         // mu, bonds
   b += 8 * (size_t)max_slots * 6 * N + 8 * 4 * N;                               // dipole, contact
-  b += 4 * cells + sizeof(CellSlot) * cells * CELL_CAP + 4 * N + 4 * OVF_CAP;  // cells
+  b += 2 * (4 * cells + sizeof(CellSlot) * cells * CELL_CAP + 4 * OVF_CAP) + 4 * N;  // cells
   b += 8 * 18 * N + 8 * 9 * M;                                                  // energy
   return b;
 }
 
 // ------------------------------------------------------------------ schedule
-static int force_terms(rod_ctx* c, int want_energy) {
+static int force_terms(rod_ctx* c, const Dev& d, int want_energy) {
   if (!want_energy && c->launch_mode == ROD_LAUNCH_BATCHED) {
-    if (c->desc.dipole_on && c->d.dip_small)
-      TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole, c->d, c->desc.precision, c->work, c->nwork, c->s);
-    TIMED(c, ROD_KERNEL_FORCES, launch_forces, c->d, c->desc.precision, c->work, c->nwork, c->s);
+    if (c->desc.dipole_on && d.dip_small)
+      TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole, d, c->desc.precision, c->work, c->nwork, c->s);
+    TIMED(c, ROD_KERNEL_FORCES, launch_forces, d, c->desc.precision, c->work, c->nwork, c->s);
     return ROD_OK;
   }
-  TIMED(c, ROD_KERNEL_BOND, launch_bond, c->d, c->desc.precision, want_energy, c->s);
+  TIMED(c, ROD_KERNEL_BOND, launch_bond, d, c->desc.precision, want_energy, c->s);
   if (c->desc.dipole_on)
-    TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole, c->d, c->desc.precision, c->work, c->nwork, c->s);
-  if (c->desc.contact_on) TIMED(c, ROD_KERNEL_CONTACT, launch_contact, c->d, want_energy, c->s);
+    TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole, d, c->desc.precision, c->work, c->nwork, c->s);
+  if (c->desc.contact_on) TIMED(c, ROD_KERNEL_CONTACT, launch_contact, d, want_energy, c->s);
   return ROD_OK;
 }
+static int force_terms(rod_ctx* c, int want_energy) { return force_terms(c, c->d, want_energy); }
 
-static int enqueue_step(rod_ctx* c) {
-  TIMED(c, ROD_KERNEL_PRE, launch_pre, c->d, PRE_STEP, c->s);
-  TRY(force_terms(c, 0));
-  TIMED(c, ROD_KERNEL_POST, launch_post, c->d, POST_KICK, ROD_TERM_ALL, nullptr, nullptr, nullptr,
+// n consecutive steps. Batched: pre, forces, then (kick, forces) for every
+// further step, and post; the fused kick ends one step and starts the next, and
+// the level counter it reads alternates between step[1] and step[2]. Other
+// modes: pre, forces, post per step.
+static int enqueue_steps(rod_ctx* c, int64_t n) {
+  if (n <= 0) return ROD_OK;
+  if (c->launch_mode != ROD_LAUNCH_BATCHED) {
+    for (int64_t k = 0; k < n; ++k) {
+      TIMED(c, ROD_KERNEL_PRE, launch_pre, c->d, PRE_STEP, c->s);
+      TRY(force_terms(c, 0));
+      TIMED(c, ROD_KERNEL_POST, launch_post, c->d, POST_KICK, ROD_TERM_ALL, nullptr, nullptr,
+            nullptr, c->s);
+    }
+    return ROD_OK;
+  }
+  Dev d = c->d;  // d.lc = 1
+  TIMED(c, ROD_KERNEL_PRE, launch_pre, d, PRE_STEP, c->s);
+  TRY(force_terms(c, d, 0));
+  for (int64_t k = 1; k < n; ++k) {
+    TIMED(c, ROD_KERNEL_KICK, launch_kick, d, c->s);
+    d.lc = 3 - d.lc;
+    TRY(force_terms(c, d, 0));
+  }
+  TIMED(c, ROD_KERNEL_POST, launch_post, d, POST_KICK, ROD_TERM_ALL, nullptr, nullptr, nullptr,
         c->s);
   return ROD_OK;
 }
@@ -390,7 +411,7 @@ static int capture_steps(rod_ctx* c, int nsteps, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIPC(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
   int rc = ROD_OK;
-  for (int k = 0; k < nsteps && rc == ROD_OK; ++k) rc = enqueue_step(c);
+  rc = enqueue_steps(c, nsteps);
   hipError_t e = hipStreamEndCapture(c->s, &g);
   if (rc != ROD_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
   if (e != hipSuccess) return fail(ROD_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
@@ -517,15 +538,16 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
       (rc = dalloc(c, &d.bF, 3 * (size_t)N)) || (rc = dalloc(c, &d.bTs, 3 * (size_t)N)) ||
       (rc = dalloc(c, &d.bTbt, 3 * (size_t)N)) || (rc = dalloc(c, &d.bE, 4 * (size_t)N)) ||
       (rc = dalloc(c, &d.cF, 3 * (size_t)N)) || (rc = dalloc(c, &d.cE, (size_t)N)) ||
-      (rc = dalloc(c, &d.key, (size_t)N)) || (rc = dalloc(c, &d.ovf_list, (size_t)OVF_CAP)) ||
-      (rc = dalloc(c, &d.ovf_cnt, 1)) || (rc = dalloc(c, &d.flags, 4)) ||
-      (rc = dalloc(c, &d.step, 2)) ||
+      (rc = dalloc(c, &d.key, (size_t)N)) || (rc = dalloc(c, &d.ovf_list, 2 * (size_t)OVF_CAP)) ||
+      (rc = dalloc(c, &d.ovf_cnt, 2)) || (rc = dalloc(c, &d.flags, 4)) ||
+      (rc = dalloc(c, &d.step, 3)) ||
       (rc = dalloc(c, &c->epart, 18 * (size_t)N)) || (rc = dalloc(c, &c->eout, 9 * (size_t)M)) ||
       (rc = dalloc(c, &c->pair_count, 1)))
     return cleanup(rc);
   d.muf = dsc->precision == ROD_MIXED ? muf : nullptr;
   size_t cells = dsc->contact_on ? next_pow2(std::max<size_t>(1024, 2 * (size_t)N)) : 1;
-  if ((rc = dalloc(c, &d.cell_cnt, cells)) || (rc = dalloc(c, &d.cell_slot, cells * CELL_CAP)))
+  if ((rc = dalloc(c, &d.cell_cnt, 2 * cells)) ||
+      (rc = dalloc(c, &d.cell_slot, 2 * cells * CELL_CAP)))
     return cleanup(rc);
   d.cell_mask = (unsigned)(cells - 1);
   d.dt = dsc->dt; d.damping = dsc->damping; d.C = dsc->mu0_4pi; d.kc = dsc->k_contact;
@@ -539,7 +561,8 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
     for (int k = 0; k < 3; ++k) d.axis[k] = a > 0 ? dsc->drive_axis[k] / a : 0.0;
   }
   d.period = dsc->drive_period > 0 ? dsc->drive_period : 1;
-  long long s0[2] = {dsc->step0, dsc->step0};
+  d.lc = 1;
+  long long s0[3] = {dsc->step0, dsc->step0, dsc->step0};
   if (hipMemcpy(d.step, s0, sizeof(s0), hipMemcpyHostToDevice) != hipSuccess)
     return cleanup(fail(ROD_E_HIP, "upload failed"));
   c->mrange_h = mrange;
@@ -562,8 +585,8 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   if (forces_valid && d.contact_on) {
     // pre built the cell list without a force pass; empty it again
     if (hipStreamSynchronize(c->s) != hipSuccess) return cleanup(fail(ROD_E_HIP, "sync failed"));
-    if (hipMemset(d.cell_cnt, 0, cells * sizeof(int)) != hipSuccess ||
-        hipMemset(d.ovf_cnt, 0, sizeof(int)) != hipSuccess)
+    if (hipMemset(d.cell_cnt, 0, 2 * cells * sizeof(int)) != hipSuccess ||
+        hipMemset(d.ovf_cnt, 0, 2 * sizeof(int)) != hipSuccess)
       return cleanup(fail(ROD_E_HIP, "memset failed"));
   }
   *out = c;
@@ -587,7 +610,7 @@ int rod_step(rod_ctx* c, int64_t n) {
         HIPC(hipGraphLaunch(c->tgexec, c->s));
         k += every;
       } else {
-        TRY(enqueue_step(c));
+        TRY(enqueue_steps(c, 1));
         k += 1;
       }
     }
@@ -602,7 +625,7 @@ int rod_step(rod_ctx* c, int64_t n) {
         left -= c->gsteps;
       }
     }
-    for (int64_t k = 0; k < left; ++k) TRY(enqueue_step(c));
+    TRY(enqueue_steps(c, left));
   }
   c->h_step += n;
   TRY(leave(c));

@@ -39,16 +39,19 @@ struct Dev {
   const int* mslots;       // [M]: j ranges (partial slots) of each member
   double* cF;              // [3N] contact force
   double* cE;              // [N] contact energy per particle (energy evaluation only)
-  int* cell_cnt;           // [cells] particles hashed to each cell
-  CellSlot* cell_slot;     // [cells][CELL_CAP] position and tag of each listed particle
-  int* key;                // [N] cell of each particle
-  int* ovf_list;           // [OVF_CAP] particles whose cell was full
-  int* ovf_cnt;            // [1] entries of the overflow list (reset by the particle kernel)
+  // Hashed cell lists, one for even and one for odd time levels, so that a
+  // kernel can empty the list of one level while it fills that of the next.
+  int* cell_cnt;           // [2][cells] particles hashed to each cell
+  CellSlot* cell_slot;     // [2][cells][CELL_CAP] position and tag of each listed particle
+  int* key;                // [N] cell of each particle at its last insertion
+  int* ovf_list;           // [2][OVF_CAP] particles whose cell was full
+  int* ovf_cnt;            // [2] entries of the overflow lists (reset by the particle kernel)
   unsigned cell_mask;      // cells - 1 (power of two)
   unsigned* flags;         // [4]: [0] non-finite state, [2] overflow list full
-  long long* step;         // [2]: [0] time level of the state (written by the particle
-                           // kernel), [1] level of the force evaluation in flight
-                           // (written by the pre kernel); no kernel writes what it reads
+  long long* step;         // [3]: [0] time level of the state (written by the particle
+                           // kernel); [1], [2] level of the force evaluation in flight,
+                           // in the entry named by lc. No kernel writes what it reads.
+  int lc;                  // 1 or 2: entry of step[] holding the level of the forces
   // parameters
   double dt, damping, C, kc, rc, inv_cell;
   int depth, field_len, dipole_on, contact_on;
@@ -60,6 +63,15 @@ struct Dev {
 constexpr int CELL_CAP = 8;
 constexpr int OVF_CAP = 4096;
 enum { FLAG_NONFINITE = 0, FLAG_LIST_OVF = 2 };
+
+// Cell list of time level `lvl`.
+struct CellTab { int* cnt; CellSlot* slot; int* ovf; int* ovf_cnt; };
+__device__ __forceinline__ CellTab cell_tab(const Dev& d, long long lvl) {
+  const long p = (long)(lvl & 1);
+  const long cells = (long)d.cell_mask + 1;
+  return {d.cell_cnt + p * cells, d.cell_slot + p * cells * CELL_CAP, d.ovf_list + p * OVF_CAP,
+          d.ovf_cnt + p};
+}
 
 enum PreMode { PRE_PREPARE = 0, PRE_STEP = 1, PRE_EVAL = 2 };
 enum PostMode { POST_PREPARE = 0, POST_KICK = 1, POST_EVAL = 2 };
@@ -97,6 +109,10 @@ hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int n
                          const hipEvent_t* ev = nullptr);
 hipError_t launch_post(const Dev& d, int mode, int mask, double* Fout, double* Tout,
                        double* Bout, hipStream_t s, const hipEvent_t* ev = nullptr);
+// Second half-kick of the step whose forces are in flight (level step[lc]) fused
+// with the first half-kick, drift and rotation of the next step; writes the next
+// level into step[3 - lc].
+hipError_t launch_kick(const Dev& d, hipStream_t s, const hipEvent_t* ev = nullptr);
 hipError_t launch_energy(const Dev& d, double* Epart, double* out, hipStream_t s);
 hipError_t launch_contact_pairs(const Dev& d, int* pairs, int cap, int* count, hipStream_t s);
 hipError_t launch_clear_cells(const Dev& d, hipStream_t s);

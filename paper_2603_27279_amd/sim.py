@@ -156,7 +156,8 @@ class RodSim:
         return outs
 
     def timing(self, enable=True):
-        """Bracket every kernel launch with HIP events (steps run eagerly while on)."""
+        """Have every kernel launch stamp HIP events with its own start and end
+        (steps run eagerly while on)."""
         L.check(self.lib.rod_timing(self.ctx, int(bool(enable))))
 
     def kernel_times(self):

@@ -103,3 +103,50 @@ def test_launch_modes_match_bitwise(layout, prec):
     o = oracle.run(w, 30)
     motion = np.max(np.abs(o["x"] - w["x0"]))
     assert np.max(np.abs(states[0]["x"] - o["x"])) / motion <= (1e-9 if prec == "fp64" else 1e-4)
+
+
+def _twisted_small():
+    w = workloads.twisted_rod(n=300, period=200)
+    rng = np.random.default_rng(9)
+    w["x0"] = w["x0"] + rng.normal(0, 0.05, w["x0"].shape) * (w["bc"] == 0)[:, None]
+    return w
+
+
+@pytest.mark.parametrize("graph_steps", [0, 1, 2, 7])
+def test_fused_step_chains_match_separate_bitwise(graph_steps):
+    """Batched stepping fuses the end of one step with the start of the next and
+    alternates level counters; any chunking and graph size gives the state of
+    unfused separate launches."""
+    w = _twisted_small()
+    a = RodSim(w, precision="mixed", graph_steps=graph_steps)
+    b = RodSim(w, precision="mixed", graph_steps=0)
+    b.launch_mode("separate")
+    for n in (25, 10, 1, 3):
+        a.step(n)
+        b.step(n)
+    sa, sb = a.state(), b.state()
+    assert sa["step"] == sb["step"] == 39
+    for k in ("x", "v", "q", "w", "F", "T"):
+        np.testing.assert_array_equal(sa[k], sb[k])
+    a.free(); b.free()
+
+
+def test_timing_mode_runs_the_same_steps():
+    w = _twisted_small()
+    a = RodSim(w, precision="mixed", graph_steps=5)
+    b = RodSim(w, precision="mixed", graph_steps=5)
+    for s in (a, b):
+        s.dipole_layout(0, 64)  # split layout: dipole work inside the fused force kernel
+    a.timing(True)
+    a.step(13)
+    kt = a.kernel_times()
+    a.timing(False)
+    b.step(13)
+    assert kt["pre"][1] == 1 and kt["post"][1] == 1
+    assert kt["forces"][1] == 13 and kt["kick"][1] == 12
+    assert all(kt[k][1] == 0 for k in ("bond", "dipole", "contact"))
+    assert all(ms > 0 for ms, c in kt.values() if c)
+    sa, sb = a.state(), b.state()
+    for k in ("x", "v", "q", "w", "F", "T"):
+        np.testing.assert_array_equal(sa[k], sb[k])
+    a.free(); b.free()
