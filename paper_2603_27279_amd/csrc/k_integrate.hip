@@ -53,13 +53,14 @@ __device__ __forceinline__ unsigned cell_hash(int cx, int cy, int cz, int mem, u
 // only when `copy_still` is set (out-of-place step).
 __device__ __forceinline__ void advance(const Dev& d, long i, int b, long long lvl, V3<double>& x,
                                         V3<double>& v, Q4<double>& q, V3<double>& w,
-                                        V3<double> F, V3<double> T, bool copy_still) {
+                                        V3<double> F, V3<double> T, double minv, double Iinv,
+                                        bool copy_still) {
   const long N = d.n;
   if (b == 0) {
     const double h = 0.5 * d.dt;
-    v = v + (h * d.minv[i]) * F;
+    v = v + (h * minv) * F;
     x = x + d.dt * v;
-    w = w + (h * d.Iinv[i]) * T;
+    w = w + (h * Iinv) * T;
     q = richardson(q, w, d.dt);
     st3(d.v, N, i, v);
     st3(d.x, N, i, x);
@@ -79,20 +80,20 @@ __device__ __forceinline__ void advance(const Dev& d, long i, int b, long long l
 // Dipole moment in the global frame, m = q m_body q*, and the particle's entry
 // in the cell list of level lvl.
 __device__ __forceinline__ void moment_and_cell(const Dev& d, long i, Q4<double> q, V3<double> x,
-                                                long long lvl) {
+                                                V3<double> mb, int mem, int rod, long long lvl) {
   const long N = d.n;
-  V3<double> m = qrot(q, ld3(d.mb, N, i));
+  V3<double> m = qrot(q, mb);
   st3(d.mu, N, i, m);
   if (d.muf) st3(d.muf, N, i, V3<float>{(float)m.x, (float)m.y, (float)m.z});
   if (d.contact_on) {
     const CellTab t = cell_tab(d, lvl);
     unsigned key = cell_hash(cell_coord(x.x, d.inv_cell), cell_coord(x.y, d.inv_cell),
-                             cell_coord(x.z, d.inv_cell), d.mem[i], d.cell_mask);
+                             cell_coord(x.z, d.inv_cell), mem, d.cell_mask);
     int slot = atomicAdd(&t.cnt[key], 1);
     if (slot < CELL_CAP) {
       CellSlot e;
       e.x = x.x; e.y = x.y; e.z = x.z;
-      e.tag = (long long)(unsigned)i | ((long long)d.rod[i] << 32);
+      e.tag = (long long)(unsigned)i | ((long long)rod << 32);
       t.slot[(long)key * CELL_CAP + slot] = e;
     } else {
       int o = atomicAdd(t.ovf_cnt, 1);
@@ -120,9 +121,12 @@ __global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
   const double* sT = d.src ? d.src + 16 * N : d.T;
   Q4<double> q = ld4(sq, N, i);
   V3<double> x = ld3(sx, N, i);
+  const V3<double> mb = ld3(d.mb, N, i);
+  const int mem = d.mem[i], rod = d.rod[i];
   if (mode == PRE_STEP) {
     V3<double> v = ld3(sv, N, i), w = ld3(sw, N, i);
-    advance(d, i, b, lvl, x, v, q, w, ld3(sF, N, i), ld3(sT, N, i), d.src != nullptr);
+    advance(d, i, b, lvl, x, v, q, w, ld3(sF, N, i), ld3(sT, N, i), d.minv[i], d.Iinv[i],
+            d.src != nullptr);
   } else if (mode == PRE_PREPARE) {
     q = qnormalize(q);
     if (b != 0) {
@@ -137,46 +141,66 @@ __global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
     }
     st4(d.q, N, i, q);
   }
-  moment_and_cell(d, i, q, x, lvl);
+  moment_and_cell(d, i, q, x, mb, mem, rod, lvl);
 }
 
 __device__ __forceinline__ bool finite3(V3<double> a) {
   return isfinite(a.x) && isfinite(a.y) && isfinite(a.z);
 }
 
+// State of one particle as read at the start of a gather: every load that does
+// not depend on another is issued before any arithmetic or store.
+struct PIn {
+  V3<double> x, v, w, m, mb;
+  Q4<double> q;
+  double minv, Iinv;
+  int b, mem, rod;
+};
+__device__ __forceinline__ PIn load_particle(const Dev& d, long i) {
+  const long N = d.n;
+  return {ld3(d.x, N, i), ld3(d.v, N, i), ld3(d.w, N, i), ld3(d.mu, N, i), ld3(d.mb, N, i),
+          ld4(d.q, N, i), d.minv[i], d.Iinv[i], d.bc[i], d.mem[i], d.rod[i]};
+}
+
 // Total force and torque on particle i from the terms in `mask` at level lvl
 // (bond, dipole slots, Zeeman, contact, damping, external); the dipole field
-// is written to Bo when given.
+// is written to Bo when given. Loads are unconditional where the index is
+// valid, so they are all in flight together.
 __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long lvl, double* Bo,
-                                       V3<double>& F, V3<double>& T) {
+                                       const PIn& p, V3<double>& F, V3<double>& T) {
   const long N = d.n;
+  const long im = i > 0 ? i - 1 : 0;
+  const uint8_t bf = d.bflags[i];
+  const V3<double> bF0 = ld3(d.bF, N, i), bTs0 = ld3(d.bTs, N, i), bTb0 = ld3(d.bTbt, N, i);
+  const V3<double> bF1 = ld3(d.bF, N, im), bTs1 = ld3(d.bTs, N, im), bTb1 = ld3(d.bTbt, N, im);
+  const V3<double> cF = d.contact_on ? ld3(d.cF, N, i) : V3<double>{0.0, 0.0, 0.0};
+  const double mass = d.mass[i], inertia = d.inertia[i];
   F = V3<double>{0.0, 0.0, 0.0};
   T = V3<double>{0.0, 0.0, 0.0};
-  const uint8_t bf = d.bflags[i];
   if (mask & 1) {  // bonds: +F, tau_s + tau_bt from bond (i, i+1); -F, tau_s - tau_bt from (i-1, i)
     if (bf & 1) {
-      F = F + ld3(d.bF, N, i);
-      T = T + ld3(d.bTs, N, i) + ld3(d.bTbt, N, i);
+      F = F + bF0;
+      T = T + bTs0 + bTb0;
     }
     if (bf & 2) {
-      F = F - ld3(d.bF, N, i - 1);
-      T = T + ld3(d.bTs, N, i - 1) - ld3(d.bTbt, N, i - 1);
+      F = F - bF1;
+      T = T + bTs1 - bTb1;
     }
   }
-  const V3<double> m = ld3(d.mu, N, i);
-  const int mem = d.mem[i];
+  const V3<double> m = p.m;
   V3<double> Bd{0.0, 0.0, 0.0};
   if ((mask & 2) && d.dipole_on) {  // dipole-dipole: sum of the partial slots, torque m x B_dip
-    // Slots are added in slot order; eight slots are fetched per round trip.
+    // Slots are added in slot order, eight per round trip; slots past the
+    // member's own count hold zeros.
     V3<double> Fd{0.0, 0.0, 0.0};
-    const int S = d.mslots[mem];
+    const int S = d.max_slots;
     for (int s0 = 0; s0 < S; s0 += 8) {
       double v[8][6];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const double* p = d.dpart + (long)(s0 + k) * 6 * N;
+        const double* q = d.dpart + (long)(s0 + k) * 6 * N;
         if (s0 + k < S)
-          for (int c = 0; c < 6; ++c) v[k][c] = p[c * N + i];
+          for (int c = 0; c < 6; ++c) v[k][c] = q[c * N + i];
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k)
@@ -192,8 +216,8 @@ __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long
   if (mask & 4) {  // Zeeman: B = B0 + G x, f = G^T m, tau = m x B
     long long L = d.field_len;
     long long row = ((lvl % L) + L) % L;
-    const double* f = d.field + (row * d.M + mem) * 12;
-    V3<double> x = ld3(d.x, N, i);
+    const double* f = d.field + (row * d.M + p.mem) * 12;
+    const V3<double> x = p.x;
     V3<double> B{f[0] + f[3] * x.x + f[4] * x.y + f[5] * x.z,
                  f[1] + f[6] * x.x + f[7] * x.y + f[8] * x.z,
                  f[2] + f[9] * x.x + f[10] * x.y + f[11] * x.z};
@@ -202,10 +226,10 @@ __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long
                        f[5] * m.x + f[8] * m.y + f[11] * m.z};
     T = T + cross(m, B);
   }
-  if ((mask & 8) && d.contact_on) F = F + ld3(d.cF, N, i);
+  if ((mask & 8) && d.contact_on) F = F + cF;
   if (mask & 16) {  // global viscous damping with the current (half-step) velocities
-    F = F - (d.damping * d.mass[i]) * ld3(d.v, N, i);
-    T = T - (d.damping * d.inertia[i]) * ld3(d.w, N, i);
+    F = F - (d.damping * mass) * p.v;
+    T = T - (d.damping * inertia) * p.w;
   }
   if (mask & 32) {
     if (d.extF) F = F + ld3(d.extF, N, i);
@@ -214,23 +238,19 @@ __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long
 }
 
 // Store the forces of the state and apply the second half-kick to free
-// particles; returns the kicked velocities. Flags non-finite values.
-__device__ __forceinline__ void kick(const Dev& d, long i, int b, V3<double> F, V3<double> T,
-                                     V3<double>& v, V3<double>& w) {
+// particles, updating p.v and p.w. Flags non-finite values.
+__device__ __forceinline__ void kick(const Dev& d, long i, V3<double> F, V3<double> T, PIn& p) {
   const long N = d.n;
   st3(d.F, N, i, F);
   st3(d.T, N, i, T);
-  v = ld3(d.v, N, i);
-  w = ld3(d.w, N, i);
-  if (b == 0) {
+  if (p.b == 0) {
     const double h = 0.5 * d.dt;
-    v = v + (h * d.minv[i]) * F;
-    w = w + (h * d.Iinv[i]) * T;
-    st3(d.v, N, i, v);
-    st3(d.w, N, i, w);
+    p.v = p.v + (h * p.minv) * F;
+    p.w = p.w + (h * p.Iinv) * T;
+    st3(d.v, N, i, p.v);
+    st3(d.w, N, i, p.w);
   }
-  if (!finite3(F) || !finite3(T) || !finite3(ld3(d.x, N, i)))
-    atomicOr(&d.flags[FLAG_NONFINITE], 1u);
+  if (!finite3(F) || !finite3(T) || !finite3(p.x)) atomicOr(&d.flags[FLAG_NONFINITE], 1u);
 }
 
 __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double* Fo, double* To,
@@ -243,21 +263,21 @@ __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double*
     *cell_tab(d, lvl).ovf_cnt = 0;  // the contact pass that used the overflow list has finished
   }
   if (i >= d.i_hi) return;
+  PIn p = load_particle(d, i);
+  const int key = d.contact_on ? d.key[i] : 0;
   V3<double> F, T;
-  gather(d, i, mask, lvl, Bo, F, T);
+  gather(d, i, mask, lvl, Bo, p, F, T);
   if (mode == POST_EVAL) {
     st3(Fo, N, i, F);
     st3(To, N, i, T);
   } else if (mode == POST_KICK) {
-    V3<double> v, w;
-    kick(d, i, d.bc[i], F, T, v, w);
+    kick(d, i, F, T, p);
   } else {  // prepare: forces of the initial state, no kick
     st3(d.F, N, i, F);
     st3(d.T, N, i, T);
-    if (!finite3(F) || !finite3(T) || !finite3(ld3(d.x, N, i)))
-      atomicOr(&d.flags[FLAG_NONFINITE], 1u);
+    if (!finite3(F) || !finite3(T) || !finite3(p.x)) atomicOr(&d.flags[FLAG_NONFINITE], 1u);
   }
-  if (d.contact_on) cell_tab(d, lvl).cnt[d.key[i]] = 0;  // empty the cell list for the next build
+  if (d.contact_on) cell_tab(d, lvl).cnt[key] = 0;  // empty the cell list for the next build
 }
 
 // The end of one step and the start of the next in one pass: gather and second
@@ -266,22 +286,20 @@ __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double*
 // overflow list of level L are emptied while those of level L + 1 are filled.
 __global__ __launch_bounds__(256) void k_kick(Dev d) {
   const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long N = d.n;
   const long long L = d.step[d.lc];
   if (i == 0) {
     d.step[3 - d.lc] = L + 1;
     *cell_tab(d, L).ovf_cnt = 0;
   }
   if (i >= d.i_hi) return;
-  const int b = d.bc[i];
-  V3<double> F, T, v, w;
-  gather(d, i, ROD_TERM_ALL, L, nullptr, F, T);
-  kick(d, i, b, F, T, v, w);
-  if (d.contact_on) cell_tab(d, L).cnt[d.key[i]] = 0;
-  V3<double> x = ld3(d.x, N, i);
-  Q4<double> q = ld4(d.q, N, i);
-  advance(d, i, b, L + 1, x, v, q, w, F, T, false);
-  moment_and_cell(d, i, q, x, L + 1);
+  PIn p = load_particle(d, i);
+  const int key = d.contact_on ? d.key[i] : 0;
+  V3<double> F, T;
+  gather(d, i, ROD_TERM_ALL, L, nullptr, p, F, T);
+  kick(d, i, F, T, p);
+  if (d.contact_on) cell_tab(d, L).cnt[key] = 0;
+  advance(d, i, p.b, L + 1, p.x, p.v, p.q, p.w, F, T, p.minv, p.Iinv, false);
+  moment_and_cell(d, i, p.q, p.x, p.mb, p.mem, p.rod, L + 1);
 }
 
 // Per-particle energy terms [9][N]: bond terms attributed to the bond's first

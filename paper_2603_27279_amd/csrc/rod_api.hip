@@ -262,6 +262,7 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
   c->plan_small = small ? 1 : 0;
   c->plan_target = target_wgs;
   c->max_slots = max_slots;
+  c->d.max_slots = max_slots;
   c->nwork = (int)items.size();
   TRY(palloc(c, &c->work, items.size()));
   HIPC(hipMemcpy(c->work, items.data(), items.size() * sizeof(DipWork), hipMemcpyHostToDevice));

@@ -37,6 +37,7 @@ struct Dev {
   double* bE;              // [4N] per-bond energies (energy evaluation only)
   double* dpart;           // [S][6][N] dipole partial sums (F then B), one slot per j range
   const int* mslots;       // [M]: j ranges (partial slots) of each member
+  int max_slots;           // largest entry of mslots; slots a member does not use stay zero
   double* cF;              // [3N] contact force
   double* cE;              // [N] contact energy per particle (energy evaluation only)
   // Hashed cell lists, one for even and one for odd time levels, so that a
