@@ -67,15 +67,18 @@ def measured_traffic(kernel, workload, precision, layout):
     kernel source, workload, precision and layout."""
     if layout is None or not os.path.exists(COUNTER_SUMMARY):
         return None
-    want = {"kernel": kernel, "workload": workload, "precision": precision, "layout": layout,
-            "sources": force_sources_digest()}
+    want = {"kernel": kernel.replace(" ", ""), "workload": workload, "precision": precision,
+            "layout": layout, "sources": force_sources_digest()}
     with open(COUNTER_SUMMARY) as fh:
         for line in fh:
             if not line.startswith("traffic "):
                 continue
-            rec = dict(kv.split("=", 1) for kv in line.split()[1:])
+            rec = dict(kv.split("=", 1) for kv in line.split()[1:] if "=" in kv)
             if all(rec.get(k) == v for k, v in want.items()):
-                return float(rec["bytes_per_launch"])
+                try:
+                    return float(rec["bytes_per_launch"])
+                except (KeyError, ValueError):
+                    return None
     return None
 
 

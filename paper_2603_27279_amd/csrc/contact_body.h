@@ -1,12 +1,13 @@
-// Contact search and force: Hookean normal repulsion k (r_c - r) between particles of the
-// same member that are closer than r_c and not bonded within the exclusion
-// depth (Methods, "Contact", with the normal-only Hookean law of the workloads).
+// Contact search and force: Hookean normal repulsion k (r_c - r) between
+// particles of the same member that are closer than r_c and not bonded within
+// the exclusion depth (Methods, "Contact", with the normal-only Hookean law of
+// the workloads).
 //
-// Candidates come from the hashed cell list built by the pre kernel (cell side
-// r_c) plus the short list of particles whose cell was full. The search is
+// Candidates come from the hashed cell list of the current time level (cell
+// side r_c) plus the short list of particles whose cell was full. The search is
 // lane-parallel: half a wavefront serves one particle, lane c (0..26) scans
-// neighbouring cell c, whose count and slots (each slot holds the particle's
-// position and tag) are fetched in a single round trip. Lanes whose hash
+// neighbouring cell c, whose count and first slots (each slot holds the
+// particle's position and tag) are fetched in one round trip. Lanes whose hash
 // bucket repeats a lower lane's bucket stand down, so no pair is seen twice.
 // The selection r^2 = (dx dx + dy dy) + dz dz < r_c^2 uses explicitly rounded
 // FP64 operations (no contraction), so the pair set is exactly that of a
@@ -45,6 +46,10 @@ __device__ __forceinline__ long long half_sum(long long v) {
 }
 
 enum ContactOut { OUT_FORCE = 0, OUT_ENERGY = 1, OUT_PAIRS = 2 };
+
+// Cell slots fetched together with the cell count in the lane-parallel search.
+// With cells of side r_c and particles about r_c apart a cell rarely holds more.
+constexpr int CELL_SPEC = 2;
 
 // One pass of the search; what is produced depends on `OUT`.
 template <int OUT>
@@ -92,15 +97,21 @@ __device__ __forceinline__ void contact_pass(const Dev& d, long blk, int* pairs,
     if (OUT == OUT_ENERGY) fe += to_fix(0.25 * d.kc * ov * ov);  // each pair seen from both ends
   };
   if (scan) {
+    // The first CELL_SPEC slots travel with the count (stale entries past the
+    // count are ignored); fuller cells take a second round trip.
     const CellSlot* sl = tab.slot + (long)key * CELL_CAP;
     const int nb = min(tab.cnt[key], CELL_CAP);
-    CellSlot e[CELL_CAP];
+    CellSlot e[CELL_SPEC];
 #pragma unroll
-    for (int s = 0; s < CELL_CAP; ++s) e[s] = sl[s];  // slots beyond the count are ignored
+    for (int s = 0; s < CELL_SPEC; ++s) e[s] = sl[s];
 #pragma unroll
-    for (int s = 0; s < CELL_CAP; ++s)
+    for (int s = 0; s < CELL_SPEC; ++s)
       if (s < nb) take((int)(e[s].tag & 0xffffffffll), (int)(e[s].tag >> 32),
                        V3<double>{e[s].x, e[s].y, e[s].z});
+    for (int s = CELL_SPEC; s < nb; ++s) {
+      const CellSlot f = sl[s];
+      take((int)(f.tag & 0xffffffffll), (int)(f.tag >> 32), V3<double>{f.x, f.y, f.z});
+    }
   }
   if (pv && lane == 27) {  // particles whose cell was full
     const int no = min(*tab.ovf_cnt, OVF_CAP);

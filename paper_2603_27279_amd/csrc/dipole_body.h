@@ -173,4 +173,51 @@ __device__ __forceinline__ void dipole_item(const Dev& d, const DipWork& wk, Dip
   }
 }
 
+// Small-member layout: a work item of up to DIP_SMALL_I consecutive targets of one
+// member, one wave per target; the 64 lanes of the wave stride over the
+// member's sources, four sources in flight per lane, and their sums are
+// combined across lanes by a fixed xor tree. No LDS and no barriers, so these
+// items share launches with any other workgroup.
+template <class R>
+__device__ __forceinline__ void dipole_small_item(const Dev& d, const DipWork& wk) {
+  const long N = d.n;
+  const int lane = threadIdx.x & 63;
+  const int i = wk.i0 + (int)(threadIdx.x >> 6);
+  if (i >= wk.i1) return;  // the whole wave
+  const R* mu;
+  if constexpr (sizeof(R) == 4) mu = (const R*)d.muf;
+  else mu = (const R*)d.mu;
+  const double xi = d.x[i], yi = d.x[N + i], zi = d.x[2 * N + i];
+  const R mix = mu[i], miy = mu[N + i], miz = mu[2 * N + i];
+  Acc<R> A{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const R m5 = minus5(R(0));
+  for (int jb = wk.j0 + lane; jb < wk.j1; jb += 4 * 64) {
+    double sx[4], sy[4], sz[4];
+    R smx[4], smy[4], smz[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {  // loads first; out-of-range entries read source j0
+      const int j = jb + 64 * u < wk.j1 ? jb + 64 * u : wk.j0;
+      sx[u] = d.x[j]; sy[u] = d.x[N + j]; sz[u] = d.x[2 * N + j];
+      smx[u] = mu[j]; smy[u] = mu[N + j]; smz[u] = mu[2 * N + j];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = jb + 64 * u;
+      if (j >= wk.j1) break;
+      const R dx = (R)(xi - sx[u]), dy = (R)(yi - sy[u]), dz = (R)(zi - sz[u]);
+      const R r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
+      const R rinv = (j == i) ? R(0) : rsq(r2);
+      pair_acc(dx, dy, dz, smx[u], smy[u], smz[u], mix, miy, miz, rinv, m5, A);
+    }
+  }
+  double F[NACC] = {(double)A.fx,  (double)A.fy,  (double)A.fz,  (double)A.fm,  (double)A.bsx,
+                    (double)A.bsy, (double)A.bsz, (double)A.bmx, (double)A.bmy, (double)A.bmz};
+#pragma unroll
+  for (int k = 0; k < NACC; ++k)
+    for (int o = 32; o > 0; o >>= 1) F[k] += __shfl_xor(F[k], o);
+  if (lane == 0)
+    write_slot(d.dpart + (long)wk.slot * 6 * N, N, i, d.C, F, (double)mix, (double)miy,
+               (double)miz);
+}
+
 }  // namespace rodmx

@@ -140,9 +140,8 @@ __global__ __launch_bounds__(256) void k_adj_local(Dev d, Adj a, const double* S
 // ---------------------------------------------------------------- bonds
 // One thread per (input direction, bond): column `dir` of the bond's Jacobian
 // by a dual-number evaluation, contracted with the bond cotangent.
-__global__ __launch_bounds__(128) void k_adj_bond(Dev d, Adj a, const double* S1) {
+__device__ __forceinline__ void adj_bond(const Dev& d, const Adj& a, const double* S1, long t) {
   const long N = d.n;
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 11 * N) return;
   const int dir = (int)(t / N);
   const long k = t - (long)dir * N;
@@ -188,11 +187,17 @@ __device__ void phi_grad(V3<double> r, V3<double> am, V3<double> bm, V3<double> 
 
 constexpr int ATJ = 256;
 
-__global__ __launch_bounds__(256) void k_adj_dipole(Dev d, Adj a, const double* S1,
-                                                    const DipWork* __restrict__ work) {
-  __shared__ double sj[12][ATJ];
-  __shared__ double red[4][6][64];
-  const DipWork wk = work[blockIdx.x];
+// LDS of the fused reverse force kernel: a dipole tile and its reduction, or
+// the field-gradient reduction (different workgroups, one union).
+union AdjSmem {
+  double sj[12][ATJ];
+  double red[4][6][64];
+  double fred[12][256];
+};
+
+__device__ __forceinline__ void adj_dipole_item(const Dev& d, const Adj& a, const double* S1,
+                                                const DipWork& wk, AdjSmem& sm) {
+  double(*sj)[ATJ] = sm.sj;
   const long N = d.n;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -229,53 +234,57 @@ __global__ __launch_bounds__(256) void k_adj_dipole(Dev d, Adj a, const double* 
     }
     __syncthreads();
   }
+  // (the last tile pass ended with a barrier, so the tile may be overwritten)
   const double v6[6] = {xb.x, xb.y, xb.z, mb.x, mb.y, mb.z};
-  for (int k = 0; k < 6; ++k) red[wave][k][lane] = v6[k];
+  for (int k = 0; k < 6; ++k) sm.red[wave][k][lane] = v6[k];
   __syncthreads();
   if (wave == 0 && act) {
     double* p = d.dpart + (long)wk.slot * 6 * N;
     for (int k = 0; k < 6; ++k)
-      p[k * N + i] = d.C * (((red[0][k][lane] + red[1][k][lane]) + red[2][k][lane]) + red[3][k][lane]);
+      p[k * N + i] = d.C * (((sm.red[0][k][lane] + sm.red[1][k][lane]) + sm.red[2][k][lane]) +
+                            sm.red[3][k][lane]);
   }
 }
 
-// Small-member layout (as the forward kernel): 16 i per workgroup, 64 j lanes.
-__global__ __launch_bounds__(1024) void k_adj_dipole_small(Dev d, Adj a, const double* S1,
-                                                          const DipWork* __restrict__ work) {
-  __shared__ double red[6][64][16];
-  const DipWork wk = work[blockIdx.x];
+// Small-member layout (as the forward): one wave per target, lanes striding
+// over the member's sources, a fixed xor tree across lanes.
+__device__ __forceinline__ void adj_dipole_small_item(const Dev& d, const Adj& a, const double* S1,
+                                                      const DipWork& wk) {
   const long N = d.n;
-  const int il = threadIdx.x & 15, jl = threadIdx.x >> 4;
-  const int i = wk.i0 + il;
-  const bool act = i < wk.i1;
-  V3<double> xi{0, 0, 0}, mi{0, 0, 0}, gi{0, 0, 0}, hi{0, 0, 0};
-  if (act) {
-    xi = ldv(S1, N, i); mi = ldv(d.mu, N, i); gi = ldv(a.Fe, N, i); hi = ldv(a.h, N, i);
-  }
+  const int lane = threadIdx.x & 63;
+  const int i = wk.i0 + (int)(threadIdx.x >> 6);
+  if (i >= wk.i1) return;  // the whole wave
+  const V3<double> xi = ldv(S1, N, i), mi = ldv(d.mu, N, i), gi = ldv(a.Fe, N, i),
+                   hi = ldv(a.h, N, i);
   V3<double> xb{0, 0, 0}, mb{0, 0, 0};
-  for (int j = wk.j0 + jl; j < wk.j1; j += 64) {
-    if (j == i) continue;
-    const V3<double> xj = ldv(S1, N, j), mj = ldv(d.mu, N, j);
-    const V3<double> gj = ldv(a.Fe, N, j), hj = ldv(a.h, N, j);
-    V3<double> dr, da, db;
-    phi_grad(xi - xj, mi, mj, gi, hi, dr, da, db);  // i as target
-    xb = xb - dr;
-    mb = mb - da;
-    phi_grad(xj - xi, mj, mi, gj, hj, dr, da, db);  // i as source
-    xb = xb + dr;
-    mb = mb - db;
+  for (int jb = wk.j0 + lane; jb < wk.j1; jb += 2 * 64) {
+    V3<double> xj[2], mj[2], gj[2], hj[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {  // loads first; out-of-range entries read source j0
+      const int j = jb + 64 * u < wk.j1 ? jb + 64 * u : wk.j0;
+      xj[u] = ldv(S1, N, j); mj[u] = ldv(d.mu, N, j); gj[u] = ldv(a.Fe, N, j); hj[u] = ldv(a.h, N, j);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int j = jb + 64 * u;
+      if (j >= wk.j1) break;
+      if (j == i) continue;
+      V3<double> dr, da, db;
+      phi_grad(xi - xj[u], mi, mj[u], gi, hi, dr, da, db);  // i as target
+      xb = xb - dr;
+      mb = mb - da;
+      phi_grad(xj[u] - xi, mj[u], mi, gj[u], hj[u], dr, da, db);  // i as source
+      xb = xb + dr;
+      mb = mb - db;
+    }
   }
-  const double v6[6] = {xb.x, xb.y, xb.z, mb.x, mb.y, mb.z};
-  for (int k = 0; k < 6; ++k) red[k][jl][il] = v6[k];
-  __syncthreads();
-  for (int w = 32; w > 0; w >>= 1) {
-    if (jl < w)
-      for (int k = 0; k < 6; ++k) red[k][jl][il] += red[k][jl + w][il];
-    __syncthreads();
-  }
-  if (jl == 0 && act) {
+  double v6[6] = {xb.x, xb.y, xb.z, mb.x, mb.y, mb.z};
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    for (int o = 32; o > 0; o >>= 1) v6[k] += __shfl_xor(v6[k], o);
+  if (lane == 0) {
     double* p = d.dpart + (long)wk.slot * 6 * N;
-    for (int k = 0; k < 6; ++k) p[k * N + i] = d.C * red[k][0][il];
+    for (int k = 0; k < 6; ++k) p[k * N + i] = d.C * v6[k];
   }
 }
 
@@ -298,10 +307,10 @@ __device__ __forceinline__ double r2x(V3<double> p, V3<double> q) {
 // x-bar_i += J(d) (F-bar_i - F-bar_j) over the contacts j of i, with
 // J(d) = k [ (r_c/r - 1) I - r_c d d^T / r^3 ], d = x_i - x_j. Same search
 // as the forward contact kernel (27 lanes per particle, exact sums).
-__global__ __launch_bounds__(256) void k_adj_contact(Dev d, Adj a, const double* S1) {
+__device__ __forceinline__ void adj_contact(const Dev& d, const Adj& a, const double* S1, long blk) {
   const long N = d.n;
   const int lane = threadIdx.x & 31;
-  const long i = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
+  const long i = (blk * blockDim.x + threadIdx.x) >> 5;
   const bool pv = i < N;
   const long ii = pv ? i : 0;
   const V3<double> xi = ldv(S1, N, ii);
@@ -359,10 +368,9 @@ __global__ __launch_bounds__(256) void k_adj_contact(Dev d, Adj a, const double*
 }
 
 // ---------------------------------------------------------------- field gradient
-__global__ __launch_bounds__(256) void k_adj_field(Dev d, Adj a, int koff) {
-  __shared__ double red[12][256];
+__device__ __forceinline__ void adj_field(const Dev& d, const Adj& a, int koff, int mem,
+                                          double (*red)[256]) {
   const long long lvl = *a.lbase + koff;
-  const int mem = blockIdx.x;
   const int b = d.mrange[2 * mem], e = d.mrange[2 * mem + 1];
   const long N = d.n;
   const long long L = d.field_len;
@@ -381,6 +389,34 @@ __global__ __launch_bounds__(256) void k_adj_field(Dev d, Adj a, int koff) {
   if (threadIdx.x < 12) a.fieldbar[(row * d.M + mem) * 12 + threadIdx.x] += red[threadIdx.x][0];
 }
 
+// ---------------------------------------------------------------- fused launch
+// The reverse of the force terms in one launch: dipole work items (either
+// layout), bond Jacobian columns, contact, and the per-member field gradient.
+// Their outputs are disjoint (slots, per-bond columns, contact x-bar, field
+// table), and all read only what the local kernel wrote before.
+__global__ __launch_bounds__(256) void k_adj_forces(Dev d, Adj a, const double* S1,
+                                                    const DipWork* __restrict__ work, int ndip,
+                                                    int nbond, int ncont, int koff) {
+  __shared__ AdjSmem sm;
+  int b = blockIdx.x;
+  if (b < ndip) {
+    if (d.dip_small) adj_dipole_small_item(d, a, S1, work[b]);
+    else adj_dipole_item(d, a, S1, work[b], sm);
+    return;
+  }
+  b -= ndip;
+  if (b < nbond) {
+    adj_bond(d, a, S1, (long)b * blockDim.x + threadIdx.x);
+    return;
+  }
+  b -= nbond;
+  if (b < ncont) {
+    adj_contact(d, a, S1, b);
+    return;
+  }
+  adj_field(d, a, koff, b - ncont, sm.fred);
+}
+
 // ---------------------------------------------------------------- gather
 // Assemble x-bar and q-bar of the level, push m-bar through m = q m_body q*,
 // then reverse the pre kick (ADJ_STEP) or write the initial-state gradients
@@ -389,6 +425,11 @@ __global__ __launch_bounds__(256) void k_adj_gather(Dev d, Adj a, const double* 
                                                     int nslot_max, int mode, rod_gradients gx) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long N = d.n;
+  if (d.contact_on) {  // the contact reverse has finished: empty the level's cell list
+    const CellTab tab = cell_tab(d, d.step[d.lc]);
+    if (i == 0) *tab.ovf_cnt = 0;
+    if (i < N) tab.cnt[d.key[i]] = 0;
+  }
   if (i >= N) return;
   const uint8_t bf = d.bflags[i];
   V3<double> xb = ldv(a.cx, N, i) + ldv(a.xloc, N, i);
@@ -565,23 +606,11 @@ static int reverse_level(Tape& t, const Dev& d, const DipWork* work, int nwork, 
   hipLaunchKernelGGL(k_adj_local, dim3(nblk(N, 256)), dim3(256), 0, s, v, a, S0, (const double*)S1,
                      koff, mode);
   ACHK(hipGetLastError());
-  hipLaunchKernelGGL(k_adj_bond, dim3(nblk(11 * N, 128)), dim3(128), 0, s, v, a, (const double*)S1);
-  ACHK(hipGetLastError());
-  if (d.dipole_on) {
-    if (d.dip_small)
-      hipLaunchKernelGGL(k_adj_dipole_small, dim3(nwork), dim3(1024), 0, s, v, a,
-                         (const double*)S1, work);
-    else
-      hipLaunchKernelGGL(k_adj_dipole, dim3(nwork), dim3(256), 0, s, v, a, (const double*)S1, work);
-    ACHK(hipGetLastError());
-  }
-  if (d.contact_on) {
-    hipLaunchKernelGGL(k_adj_contact, dim3(nblk(32 * N, 256)), dim3(256), 0, s, v, a,
-                       (const double*)S1);
-    ACHK(hipGetLastError());
-  }
-  ACHK(launch_clear_cells(v, s));
-  hipLaunchKernelGGL(k_adj_field, dim3(d.M), dim3(256), 0, s, v, a, koff);
+  const int ndip = d.dipole_on ? nwork : 0;
+  const int nbond = (int)nblk(11 * N, 256);
+  const int ncont = d.contact_on ? (int)nblk(32 * N, 256) : 0;
+  hipLaunchKernelGGL(k_adj_forces, dim3(ndip + nbond + ncont + d.M), dim3(256), 0, s, v, a,
+                     (const double*)S1, work, ndip, nbond, ncont, koff);
   ACHK(hipGetLastError());
   hipLaunchKernelGGL(k_adj_gather, dim3(nblk(N, 256)), dim3(256), 0, s, v, a, S0,
                      (const double*)S1, max_slots, mode, gx);
@@ -600,9 +629,7 @@ static int recompute(Tape& t, const Dev& d, int precision, const DipWork* work, 
     Dev v = view(d, Sk1, t.a.level);
     v.src = Sk;  // the pre kernel reads step k and writes step k+1
     ACHK(launch_pre(v, PRE_STEP, s));
-    ACHK(launch_bond(v, precision, 0, s));
-    if (d.dipole_on) ACHK(launch_dipole(v, precision, work, nwork, s));
-    if (d.contact_on) ACHK(launch_contact(v, 0, s));
+    ACHK(launch_forces(v, precision, work, nwork, s));
     ACHK(launch_post(v, POST_KICK, ROD_TERM_ALL, nullptr, nullptr, Sk1 + 19 * N, s));
   }
   return ROD_OK;
@@ -693,9 +720,7 @@ int adjoint_run(Tape& t, const Dev& d, int precision, const DipWork* work, int n
     ACHK(hipGetLastError());
     Dev v = view(d, S, a.level);
     ACHK(launch_pre(v, PRE_EVAL, s));
-    ACHK(launch_bond(v, precision, 0, s));
-    if (d.dipole_on) ACHK(launch_dipole(v, precision, work, nwork, s));
-    if (d.contact_on) ACHK(launch_contact(v, 0, s));
+    ACHK(launch_forces(v, precision, work, nwork, s));
     ACHK(launch_post(v, POST_EVAL, ROD_TERM_ALL, a.scratch, a.scratch + 3 * N, S + 19 * N, s));
     ATRY(reverse_level(t, d, work, nwork, max_slots, s, S, S, 0, ADJ_PREPARE, *gx));
   }

@@ -1,9 +1,8 @@
-// Force pass of one time step in a single launch: the dipole work items of the
-// split layout first, then the bond threads, then the contact search. The three
+// Force pass of one time step in a single launch: the dipole work items first
+// (either layout), then the bond threads, then the contact search. The three
 // parts read the same drifted state and write disjoint buffers, so their
 // workgroups run side by side and the latency-bound bond and contact work hides
-// under the dipole arithmetic. (The small-member dipole layout uses 1024-thread
-// workgroups and is launched on its own before this kernel.)
+// under the dipole arithmetic.
 #include "dipole_body.h"
 #include "bond_body.h"
 #include "contact_body.h"
@@ -16,7 +15,8 @@ __global__ __launch_bounds__(256) void k_forces(Dev d, const DipWork* __restrict
   __shared__ DipSmem<R> sm;
   const int b = blockIdx.x;
   if (b < ndip) {
-    dipole_item<R>(d, work[b], sm);
+    if (d.dip_small) dipole_small_item<R>(d, work[b]);
+    else dipole_item<R>(d, work[b], sm);
   } else if (b < ndip + nbond) {
     bond_thread<R>(d, d.i_lo + (long)(b - ndip) * 256 + threadIdx.x, 0);
   } else if (LANES) {
@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void k_forces(Dev d, const DipWork* __restrict
 
 hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int nwork, hipStream_t s,
                          const hipEvent_t* ev) {
-  const int ndip = (d.dipole_on && !d.dip_small) ? nwork : 0;
+  const int ndip = d.dipole_on ? nwork : 0;
   const int nbond = (int)((d.i_hi - d.i_lo + 255) / 256);
   const unsigned ncont = d.contact_on ? contact_blocks(d) : 0;
   const dim3 g((unsigned)ndip + (unsigned)nbond + ncont), b(256);

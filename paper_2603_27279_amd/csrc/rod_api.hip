@@ -220,7 +220,7 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
     iblocks += (mrange[2 * m + 1] - mrange[2 * m] + 63) / 64;
     max_member = std::max(max_member, mrange[2 * m + 1] - mrange[2 * m]);
   }
-  // Small systems: spread every member pair over 1024-thread workgroups of 16 i.
+  // Small systems: one wave per target, its lanes striding over the member.
   bool small = small_req < 0 ? (iblocks < 512 && max_member <= 2048) : small_req == 1;
   if (max_member > 16384) small = false;
   if (!c->plan_allocs.empty()) HIPC(hipStreamSynchronize(c->s));  // old plan may be in use
@@ -232,9 +232,9 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
   for (int m = 0; m < M; ++m) {
     const int b = mrange[2 * m], e = mrange[2 * m + 1], nm = e - b;
     if (small) {
-      for (int i0 = b; i0 < e; i0 += 16) {
+      for (int i0 = b; i0 < e; i0 += DIP_SMALL_I) {
         DipWork w{};
-        w.i0 = i0; w.i1 = std::min(i0 + 16, e); w.j0 = b; w.j1 = e; w.slot = 0;
+        w.i0 = i0; w.i1 = std::min(i0 + DIP_SMALL_I, e); w.j0 = b; w.j1 = e; w.slot = 0;
         items.push_back(w);
       }
       continue;
@@ -289,8 +289,6 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
 // ------------------------------------------------------------------ schedule
 static int force_terms(rod_ctx* c, const Dev& d, int want_energy) {
   if (!want_energy && c->launch_mode == ROD_LAUNCH_BATCHED) {
-    if (c->desc.dipole_on && d.dip_small)
-      TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole, d, c->desc.precision, c->work, c->nwork, c->s);
     TIMED(c, ROD_KERNEL_FORCES, launch_forces, d, c->desc.precision, c->work, c->nwork, c->s);
     return ROD_OK;
   }
@@ -345,7 +343,7 @@ static int build_rod_work(rod_ctx* c) {
   c->rod_allocs.clear();
   std::vector<DipWork> items;
   c->rod_work_off.assign(1, 0);
-  const int bs = c->d.dip_small ? 16 : 64;
+  const int bs = c->d.dip_small ? DIP_SMALL_I : 64;
   for (int r = 0; r < c->desc.n_rods; ++r) {
     const int m = c->rod_member_h[r];
     const int b = c->mrange_h[2 * m], e = c->mrange_h[2 * m + 1];

@@ -56,7 +56,7 @@ struct Dev {
   // parameters
   double dt, damping, C, kc, rc, inv_cell;
   int depth, field_len, dipole_on, contact_on;
-  int dip_small;           // dipole work items use the small-member layout (16 i per item)
+  int dip_small;           // dipole work items use the small-member layout (4 i per item)
   double axis[3];
   long long period;
 };
@@ -82,6 +82,10 @@ enum PostMode { POST_PREPARE = 0, POST_KICK = 1, POST_EVAL = 2 };
 // written to partial slot `slot`.
 struct DipWork { int i0, i1, j0, j1, slot, pad0, pad1, pad2; };
 
+// Targets per work item of the small-member layout (one wave of a 256-thread
+// workgroup each).
+constexpr int DIP_SMALL_I = 4;
+
 // Threads per block of the per-particle kernels: small blocks spread small
 // systems over more compute units.
 inline int particle_block(long n) { return n < 65536 ? 64 : 256; }
@@ -105,7 +109,7 @@ hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int n
                          hipStream_t s, const hipEvent_t* ev = nullptr);
 hipError_t launch_contact(const Dev& d, int want_energy, hipStream_t s,
                           const hipEvent_t* ev = nullptr);
-// Dipole (split layout), bond and contact forces of a step in one launch.
+// Dipole, bond and contact forces of a step in one launch.
 hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int nwork, hipStream_t s,
                          const hipEvent_t* ev = nullptr);
 hipError_t launch_post(const Dev& d, int mode, int mask, double* Fout, double* Tout,

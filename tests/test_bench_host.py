@@ -1,0 +1,52 @@
+"""Host logic of bench.py that needs no GPU: the one-GPU guard, the tuner-line
+parser and the counter-record lookup behind the roofline's traffic figure."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("line,key", [
+    ("chosen: split layout target_wgs=1024 work_items=1024 slots=16 (30.78 us/eval) key=x", "split/1024"),
+    ("chosen: small-member layout target_wgs=0 work_items=256 slots=1 (9.1 us/eval) key=x", "small/256"),
+    ("cached choice", None),
+    (None, None),
+])
+def test_layout_key(line, key):
+    assert bench.layout_key(line) == key
+
+
+def test_traffic_record_lookup(tmp_path, monkeypatch):
+    digest = bench.force_sources_digest()
+    f = tmp_path / "counters.md"
+    f.write_text("# summary\n\n```\n"
+                 f"traffic kernel=k_forces<float,true> workload=twisted_rod precision=mixed "
+                 f"layout=split/1024 sources={digest} bytes_per_launch=1234\n"
+                 f"traffic kernel=k_forces<float,true> workload=twisted_rod precision=mixed "
+                 f"layout=split/512 sources=0000000000000000 bytes_per_launch=99\n```\n")
+    monkeypatch.setattr(bench, "COUNTER_SUMMARY", str(f))
+    assert bench.measured_traffic("k_forces<float, true>", "twisted_rod", "mixed", "split/1024") == 1234
+    # other layout, stale sources, other workload or precision: no figure
+    assert bench.measured_traffic("k_forces<float, true>", "twisted_rod", "mixed", "split/512") is None
+    assert bench.measured_traffic("k_forces<float, true>", "ensemble", "mixed", "split/1024") is None
+    assert bench.measured_traffic("k_forces<float, true>", "twisted_rod", "fp64", "split/1024") is None
+    assert bench.measured_traffic("k_forces<float, true>", "twisted_rod", "mixed", None) is None
+
+
+def test_digest_covers_the_force_kernel_sources():
+    csrc = os.path.join(ROOT, "paper_2603_27279_amd", "csrc")
+    for name in bench.FORCE_SOURCES:
+        assert os.path.exists(os.path.join(csrc, name)), name
+    assert "k_forces.hip" in bench.FORCE_SOURCES and "dipole_body.h" in bench.FORCE_SOURCES
