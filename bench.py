@@ -154,6 +154,57 @@ def adjoint_leg():
             "total_over_forward": (t_fwd + t_grad) / t_plain}
 
 
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E (vendor figure)
+
+# Algorithmic bytes per unit of the memory-bound kernels (each datum counted
+# once, however often a kernel re-reads it):
+#   bond (per bond): x, q of one particle (56), reference vector and length (32),
+#     rod id and flags (5), outputs F, tau_s, tau_b+tau_t (72)
+#   contact (per particle): own position (24), cell entry (8), force out (24)
+#   pre (per particle): state x v q w F T and m_body, inverse mass and inertia,
+#     ids (221 in); x v q w, m in FP64 and FP32, cell key and entry (180 out)
+#   kick (per particle): bond outputs of its bond (72), dipole slots (48 each),
+#     contact force, state and constants (318 + 48 S in); F T x v w q, m twice,
+#     cell key and entry (228 out)
+BYTES = {"bond": 165.0, "contact": 56.0, "pre": 401.0}
+
+
+def kick_bytes(slots):
+    return 318.0 + 48.0 * slots + 228.0
+
+
+def hbm_microbench(sizes, steps=10):
+    """Bond, contact and integration kernels of a dipole-free rod array at
+    millions of particles: kernel time from per-launch HIP events, algorithmic
+    bytes per unit as above, achieved GB/s against HBM peak."""
+    import workloads
+    from paper_2603_27279_amd import RodSim
+    out = []
+    for side in sizes:
+        w = workloads.rod_array(grid=(side, side), n_per_rod=1024, dipole_on=False)
+        n, R = w["n"], len(w["rod_offset"]) - 1
+        sim = RodSim(w, precision="mixed", graph_steps=0)
+        res = {"n_particles": n, "n_bonds": n - R}
+        for mode in ("separate", "batched"):
+            sim.launch_mode(mode)
+            sim.step(2)
+            sim.timing(True)
+            sim.step(steps)
+            kt = sim.kernel_times()
+            sim.timing(False)
+            for k, units, b in (("bond", n - R, BYTES["bond"]), ("contact", n, BYTES["contact"]),
+                                ("pre", n, BYTES["pre"]), ("kick", n, kick_bytes(0))):
+                ms, cnt = kt[k]
+                if not cnt or k in res:
+                    continue
+                us = 1e3 * ms / cnt
+                gbs = units * b / (us * 1e-6) / 1e9
+                res[k] = {"us": us, "bytes_per_unit": b, "GB_s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+        sim.free()
+        out.append(res)
+    return out
+
+
 def copy_calibration():
     """A plain device copy of a known size (256 MiB read, 256 MiB written, three
     times), for scaling the FETCH_SIZE and WRITE_SIZE counters to bytes."""
@@ -188,6 +239,11 @@ def main():
     ap.add_argument("--per-rod-steps", type=int, default=50)
     ap.add_argument("--tune-cache", default=None,
                     help="JSON-lines cache of autotuner choices (default: tune every run)")
+    ap.add_argument("--no-microbench", action="store_true",
+                    help="skip the bond/contact/integration kernels at millions of particles")
+    ap.add_argument("--microbench-sizes", default="64",
+                    help="comma-separated grid sides of the dipole-free rod array (x 1024 "
+                         "particles per rod): 64 -> 4.2M particles, 128 -> 16.8M")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -285,6 +341,9 @@ def main():
     sim.free()
 
     adj = None if args.no_adjoint else adjoint_leg()
+    micro = None
+    if not args.no_microbench:
+        micro = hbm_microbench([int(v) for v in args.microbench_sizes.split(",") if v])
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -313,6 +372,7 @@ def main():
         "roofline": roof,
         "batching": batching,
         "adjoint": adj,
+        "hbm_kernels": micro,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

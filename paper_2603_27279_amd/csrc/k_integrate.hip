@@ -238,8 +238,10 @@ __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long
 }
 
 // Store the forces of the state and apply the second half-kick to free
-// particles, updating p.v and p.w. Flags non-finite values.
-__device__ __forceinline__ void kick(const Dev& d, long i, V3<double> F, V3<double> T, PIn& p) {
+// particles, updating p.v and p.w (stored when `store_vw`; the fused kick
+// overwrites them with the next half-kick anyway). Flags non-finite values.
+__device__ __forceinline__ void kick(const Dev& d, long i, V3<double> F, V3<double> T, PIn& p,
+                                     bool store_vw) {
   const long N = d.n;
   st3(d.F, N, i, F);
   st3(d.T, N, i, T);
@@ -247,8 +249,10 @@ __device__ __forceinline__ void kick(const Dev& d, long i, V3<double> F, V3<doub
     const double h = 0.5 * d.dt;
     p.v = p.v + (h * p.minv) * F;
     p.w = p.w + (h * p.Iinv) * T;
-    st3(d.v, N, i, p.v);
-    st3(d.w, N, i, p.w);
+    if (store_vw) {
+      st3(d.v, N, i, p.v);
+      st3(d.w, N, i, p.w);
+    }
   }
   if (!finite3(F) || !finite3(T) || !finite3(p.x)) atomicOr(&d.flags[FLAG_NONFINITE], 1u);
 }
@@ -271,7 +275,7 @@ __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double*
     st3(Fo, N, i, F);
     st3(To, N, i, T);
   } else if (mode == POST_KICK) {
-    kick(d, i, F, T, p);
+    kick(d, i, F, T, p, true);
   } else {  // prepare: forces of the initial state, no kick
     st3(d.F, N, i, F);
     st3(d.T, N, i, T);
@@ -296,7 +300,7 @@ __global__ __launch_bounds__(256) void k_kick(Dev d) {
   const int key = d.contact_on ? d.key[i] : 0;
   V3<double> F, T;
   gather(d, i, ROD_TERM_ALL, L, nullptr, p, F, T);
-  kick(d, i, F, T, p);
+  kick(d, i, F, T, p, false);
   if (d.contact_on) cell_tab(d, L).cnt[key] = 0;
   advance(d, i, p.b, L + 1, p.x, p.v, p.q, p.w, F, T, p.minv, p.Iinv, false);
   moment_and_cell(d, i, p.q, p.x, p.mb, p.mem, p.rod, L + 1);
