@@ -20,16 +20,6 @@
 
 namespace rodmx {
 
-__device__ __forceinline__ int cell_coord_c(double x, double inv) {
-  double c = floor(x * inv);
-  c = fmin(fmax(c, -1.0e9), 1.0e9);
-  return (int)c;
-}
-__device__ __forceinline__ unsigned cell_hash_c(int cx, int cy, int cz, int mem, unsigned mask) {
-  unsigned h = (unsigned)cx * 73856093u ^ (unsigned)cy * 19349663u ^ (unsigned)cz * 83492791u ^
-               (unsigned)mem * 2654435761u;
-  return h & mask;
-}
 
 __device__ __forceinline__ double r2_exact(V3<double> a, V3<double> b) {
   double dx = __dsub_rn(a.x, b.x), dy = __dsub_rn(a.y, b.y), dz = __dsub_rn(a.z, b.z);
@@ -64,10 +54,10 @@ __device__ __forceinline__ void contact_pass(const Dev& d, long blk, int* pairs,
   const int mem = d.mem[ii], rod = d.rod[ii];
   const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
   const double rc2 = d.rc * d.rc;
-  const int cx = cell_coord_c(xi.x, d.inv_cell), cy = cell_coord_c(xi.y, d.inv_cell),
-            cz = cell_coord_c(xi.z, d.inv_cell);
+  const int cx = cell_coord(xi.x, d.inv_cell), cy = cell_coord(xi.y, d.inv_cell),
+            cz = cell_coord(xi.z, d.inv_cell);
   const int c = lane < 27 ? lane : 0;
-  const unsigned key = cell_hash_c(cx + c % 3 - 1, cy + (c / 3) % 3 - 1, cz + c / 9 - 1, mem,
+  const unsigned key = cell_hash(cx + c % 3 - 1, cy + (c / 3) % 3 - 1, cz + c / 9 - 1, mem,
                                    d.cell_mask);
   const CellTab tab = cell_tab(d, d.step[d.lc]);  // cell list of the level being evaluated
   bool scan = pv && lane < 27;
@@ -129,41 +119,19 @@ __device__ __forceinline__ void contact_pass(const Dev& d, long blk, int* pairs,
   }
 }
 
-// Variant for large systems: one thread per particle walks the 27 cells, each
-// non-empty cell costing one round trip for the slots it actually holds (far
-// less traffic than 27 lanes fetching whole cells when latency is already
-// hidden by the number of particles). Same selection, same exact sums.
-template <int OUT>
-__device__ __forceinline__ void contact_thread(const Dev& d, long blk) {
+// Visit every particle listed in the 27 cells around xi (each bucket once) and
+// in the overflow list: take(j, rod of j, position of j).
+template <class Take>
+__device__ __forceinline__ void for_cell_candidates(const Dev& d, const CellTab& tab, V3<double> xi,
+                                                    int mem, Take&& take) {
   const long N = d.n;
-  const long i = d.i_lo + blk * blockDim.x + threadIdx.x;
-  if (i >= d.i_hi) return;
-  const V3<double> xi = ld3(d.x, N, i);
-  const int mem = d.mem[i], rod = d.rod[i];
-  const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
-  const double rc2 = d.rc * d.rc;
-  const int cx = cell_coord_c(xi.x, d.inv_cell), cy = cell_coord_c(xi.y, d.inv_cell),
-            cz = cell_coord_c(xi.z, d.inv_cell);
-  long long fx = 0, fy = 0, fz = 0, fe = 0;
-  auto take = [&](int j, int rj, V3<double> xj) {
-    if (j == (int)i || j < mb || j >= me) return;
-    if (rj == rod && abs(j - (int)i) <= d.depth) return;
-    const double r2 = r2_exact(xi, xj);
-    if (!(r2 < rc2)) return;
-    const double r = sqrt(r2);
-    const double ov = d.rc - r;
-    const double s = (d.kc * ov) / r;
-    fx += to_fix(s * (xi.x - xj.x));
-    fy += to_fix(s * (xi.y - xj.y));
-    fz += to_fix(s * (xi.z - xj.z));
-    if (OUT == OUT_ENERGY) fe += to_fix(0.25 * d.kc * ov * ov);
-  };
-  const CellTab tab = cell_tab(d, d.step[d.lc]);
+  const int cx = cell_coord(xi.x, d.inv_cell), cy = cell_coord(xi.y, d.inv_cell),
+            cz = cell_coord(xi.z, d.inv_cell);
   unsigned keys[27];
   int nc[27];
 #pragma unroll
   for (int c = 0; c < 27; ++c)
-    keys[c] = cell_hash_c(cx + c % 3 - 1, cy + (c / 3) % 3 - 1, cz + c / 9 - 1, mem, d.cell_mask);
+    keys[c] = cell_hash(cx + c % 3 - 1, cy + (c / 3) % 3 - 1, cz + c / 9 - 1, mem, d.cell_mask);
 #pragma unroll
   for (int c = 0; c < 27; ++c) nc[c] = tab.cnt[keys[c]];
   for (int c = 0; c < 27; ++c) {
@@ -181,11 +149,102 @@ __device__ __forceinline__ void contact_thread(const Dev& d, long blk) {
     const int j = tab.ovf[o];
     take(j, d.rod[j], ld3(d.x, N, j));
   }
+}
+
+// Variant for large systems: one thread per particle walks the 27 cells, each
+// non-empty cell costing one round trip for the slots it actually holds. Same
+// selection, same exact sums.
+template <int OUT>
+__device__ __forceinline__ void contact_thread(const Dev& d, long blk) {
+  const long N = d.n;
+  const long i = d.i_lo + blk * blockDim.x + threadIdx.x;
+  if (i >= d.i_hi) return;
+  const V3<double> xi = ld3(d.x, N, i);
+  const int mem = d.mem[i], rod = d.rod[i];
+  const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
+  const double rc2 = d.rc * d.rc;
+  long long fx = 0, fy = 0, fz = 0, fe = 0;
+  for_cell_candidates(d, cell_tab(d, d.step[d.lc]), xi, mem, [&](int j, int rj, V3<double> xj) {
+    if (j == (int)i || j < mb || j >= me) return;
+    if (rj == rod && abs(j - (int)i) <= d.depth) return;
+    const double r2 = r2_exact(xi, xj);
+    if (!(r2 < rc2)) return;
+    const double r = sqrt(r2);
+    const double ov = d.rc - r;
+    const double s = (d.kc * ov) / r;
+    fx += to_fix(s * (xi.x - xj.x));
+    fy += to_fix(s * (xi.y - xj.y));
+    fz += to_fix(s * (xi.z - xj.z));
+    if (OUT == OUT_ENERGY) fe += to_fix(0.25 * d.kc * ov * ov);
+  });
   st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
   if (OUT == OUT_ENERGY) d.cE[i] = (double)fe / FIX;
 }
 
-constexpr long CONTACT_LANES_MAX_N = 65536;  // below: 27 lanes per particle
+// Contact force of a large system from per-particle candidate lists (Verlet
+// lists with a skin). A list holds every non-excluded particle of the member
+// closer than r_c + skin when it was built. It is rebuilt from the cells at the
+// first step of every rod_step call and whenever some particle has moved more
+// than NBR_MOVE * skin since the last build; the displacement check runs where
+// particles move. Between builds every pair closer than r_c is still listed, so
+// the exact selection r^2 < r_c^2 and the fixed-point sums give the cell
+// search's result bit for bit, while a step reads a short contiguous list
+// instead of 27 scattered cells. A particle with more than NBR_CAP candidates
+// searches the cells every step.
+__device__ __forceinline__ void contact_listed(const Dev& d, long blk, bool build) {
+  const long N = d.n;
+  const long i = d.i_lo + blk * blockDim.x + threadIdx.x;
+  if (i >= d.i_hi) return;
+  const V3<double> xi = ld3(d.x, N, i);
+  const int mem = d.mem[i], rod = d.rod[i];
+  const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
+  const double rc2 = d.rc * d.rc;
+  const double rs = d.rc + d.skin, rs2 = rs * rs;
+  long long fx = 0, fy = 0, fz = 0;
+  auto force = [&](V3<double> xj) {
+    const double r2 = r2_exact(xi, xj);
+    if (!(r2 < rc2)) return;
+    const double r = sqrt(r2);
+    const double s = (d.kc * (d.rc - r)) / r;
+    fx += to_fix(s * (xi.x - xj.x));
+    fy += to_fix(s * (xi.y - xj.y));
+    fz += to_fix(s * (xi.z - xj.z));
+  };
+  auto excluded = [&](int j, int rj) {
+    return j == (int)i || j < mb || j >= me || (rj == rod && abs(j - (int)i) <= d.depth);
+  };
+  const CellTab tab = cell_tab(d, d.step[d.lc]);
+  if (build) {
+    int cnt = 0;
+    for_cell_candidates(d, tab, xi, mem, [&](int j, int rj, V3<double> xj) {
+      if (excluded(j, rj)) return;
+      if (r2_exact(xi, xj) < rs2) {
+        if (cnt < NBR_CAP) d.nbr[(long)cnt * N + i] = j;
+        ++cnt;
+      }
+      force(xj);
+    });
+    d.nbr_cnt[i] = cnt <= NBR_CAP ? cnt : -1;
+    st3(d.xb, N, i, xi);
+  } else {
+    const int cnt = d.nbr_cnt[i];
+    if (cnt < 0) {
+      for_cell_candidates(d, tab, xi, mem, [&](int j, int rj, V3<double> xj) {
+        if (!excluded(j, rj)) force(xj);
+      });
+    } else {
+      for (int k = 0; k < cnt; ++k) force(ld3(d.x, N, d.nbr[(long)k * N + i]));
+    }
+  }
+  st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
+}
+
+// Whether the lists must be rebuilt this step: asked by the host, or some
+// particle moved too far since the last build (flag of the level's parity).
+__device__ __forceinline__ bool lists_stale(const Dev& d, int build) {
+  return build || d.rebuild[d.step[d.lc] & 1] != 0u;
+}
+
 
 // Workgroups of 256 threads that a pass over [i_lo, i_hi) takes: lane-parallel
 // (32 lanes per particle), and the variant chosen for this system size.

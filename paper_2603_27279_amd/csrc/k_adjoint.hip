@@ -289,16 +289,6 @@ __device__ __forceinline__ void adj_dipole_small_item(const Dev& d, const Adj& a
 }
 
 // ---------------------------------------------------------------- contact
-__device__ __forceinline__ int ccoord(double x, double inv) {
-  double c = floor(x * inv);
-  c = fmin(fmax(c, -1.0e9), 1.0e9);
-  return (int)c;
-}
-__device__ __forceinline__ unsigned chash(int cx, int cy, int cz, int mem, unsigned mask) {
-  unsigned h = (unsigned)cx * 73856093u ^ (unsigned)cy * 19349663u ^ (unsigned)cz * 83492791u ^
-               (unsigned)mem * 2654435761u;
-  return h & mask;
-}
 __device__ __forceinline__ double r2x(V3<double> p, V3<double> q) {
   double dx = __dsub_rn(p.x, q.x), dy = __dsub_rn(p.y, q.y), dz = __dsub_rn(p.z, q.z);
   return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
@@ -318,9 +308,9 @@ __device__ __forceinline__ void adj_contact(const Dev& d, const Adj& a, const do
   const int mem = d.mem[ii], rod = d.rod[ii];
   const int mlo = d.mrange[2 * mem], mhi = d.mrange[2 * mem + 1];
   const double rc2 = d.rc * d.rc;
-  const int cx = ccoord(xi.x, d.inv_cell), cy = ccoord(xi.y, d.inv_cell), cz = ccoord(xi.z, d.inv_cell);
+  const int cx = cell_coord(xi.x, d.inv_cell), cy = cell_coord(xi.y, d.inv_cell), cz = cell_coord(xi.z, d.inv_cell);
   const int c = lane < 27 ? lane : 0;
-  const unsigned key = chash(cx + c % 3 - 1, cy + (c / 3) % 3 - 1, cz + c / 9 - 1, mem, d.cell_mask);
+  const unsigned key = cell_hash(cx + c % 3 - 1, cy + (c / 3) % 3 - 1, cz + c / 9 - 1, mem, d.cell_mask);
   bool scan = pv && lane < 27;
   for (int o = 0; o < 26; ++o) {
     unsigned ko = __shfl(key, o, 32);
@@ -629,7 +619,7 @@ static int recompute(Tape& t, const Dev& d, int precision, const DipWork* work, 
     Dev v = view(d, Sk1, t.a.level);
     v.src = Sk;  // the pre kernel reads step k and writes step k+1
     ACHK(launch_pre(v, PRE_STEP, s));
-    ACHK(launch_forces(v, precision, work, nwork, s));
+    ACHK(launch_forces(v, precision, work, nwork, 1, s));
     ACHK(launch_post(v, POST_KICK, ROD_TERM_ALL, nullptr, nullptr, Sk1 + 19 * N, s));
   }
   return ROD_OK;
@@ -720,7 +710,7 @@ int adjoint_run(Tape& t, const Dev& d, int precision, const DipWork* work, int n
     ACHK(hipGetLastError());
     Dev v = view(d, S, a.level);
     ACHK(launch_pre(v, PRE_EVAL, s));
-    ACHK(launch_forces(v, precision, work, nwork, s));
+    ACHK(launch_forces(v, precision, work, nwork, 1, s));
     ACHK(launch_post(v, POST_EVAL, ROD_TERM_ALL, a.scratch, a.scratch + 3 * N, S + 19 * N, s));
     ATRY(reverse_level(t, d, work, nwork, max_slots, s, S, S, 0, ADJ_PREPARE, *gx));
   }

@@ -9,7 +9,9 @@ __global__ __launch_bounds__(256) void k_contact(Dev d) {
 __global__ __launch_bounds__(256) void k_contact_e(Dev d) {
   contact_pass<OUT_ENERGY>(d, blockIdx.x, nullptr, 0, nullptr);
 }
-__global__ __launch_bounds__(256) void k_contact_t(Dev d) { contact_thread<OUT_FORCE>(d, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_contact_l(Dev d, int build) {
+  contact_listed(d, blockIdx.x, lists_stale(d, build));
+}
 __global__ __launch_bounds__(256) void k_contact_te(Dev d) {
   contact_thread<OUT_ENERGY>(d, blockIdx.x);
 }
@@ -31,11 +33,12 @@ hipError_t launch_clear_cells(const Dev& d, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_contact(const Dev& d, int want_energy, hipStream_t s, const hipEvent_t* ev) {
+hipError_t launch_contact(const Dev& d, int want_energy, int build, hipStream_t s,
+                          const hipEvent_t* ev) {
   if (!d.contact_on) return hipSuccess;
   if (d.n >= CONTACT_LANES_MAX_N) {
     if (want_energy) launch_k(ev, k_contact_te, dim3(contact_blocks(d)), dim3(256), s, d);
-    else launch_k(ev, k_contact_t, dim3(contact_blocks(d)), dim3(256), s, d);
+    else launch_k(ev, k_contact_l, dim3(contact_blocks(d)), dim3(256), s, d, build);
     return hipGetLastError();
   }
   if (want_energy)

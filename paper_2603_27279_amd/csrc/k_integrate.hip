@@ -35,17 +35,7 @@ __device__ __forceinline__ Q4<double> drive_q(const Dev& d, long long lvl) {
   return {c, s * d.axis[0], s * d.axis[1], s * d.axis[2]};
 }
 
-__device__ __forceinline__ int cell_coord(double x, double inv) {
-  double c = floor(x * inv);
-  c = fmin(fmax(c, -1.0e9), 1.0e9);  // keeps runaway coordinates hashable
-  return (int)c;
-}
 
-__device__ __forceinline__ unsigned cell_hash(int cx, int cy, int cz, int mem, unsigned mask) {
-  unsigned h = (unsigned)cx * 73856093u ^ (unsigned)cy * 19349663u ^ (unsigned)cz * 83492791u ^
-               (unsigned)mem * 2654435761u;
-  return h & mask;
-}
 
 // Advance particle i from its state at level lvl - 1 (in registers) to level
 // lvl: half-kick, drift and quaternion update of free particles; the imposed
@@ -62,6 +52,14 @@ __device__ __forceinline__ void advance(const Dev& d, long i, int b, long long l
     x = x + d.dt * v;
     w = w + (h * Iinv) * T;
     q = richardson(q, w, d.dt);
+    if (d.use_lists) {  // moved too far since the contact lists were built?
+      const V3<double> m = x - ld3(d.xb, N, i);
+      const double lim = NBR_MOVE * d.skin;
+      const bool far = dot(m, m) > lim * lim;
+      const unsigned long long who = __ballot(far);  // one atomic per wave
+      if (far && __lane_id() == (unsigned)(__ffsll((long long)who) - 1))
+        atomicOr(&d.rebuild[lvl & 1], 1u);
+    }
     st3(d.v, N, i, v);
     st3(d.x, N, i, x);
     st3(d.w, N, i, w);
@@ -265,6 +263,7 @@ __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double*
   if (i == 0) {
     if (mode == POST_KICK) d.step[0] = lvl;
     *cell_tab(d, lvl).ovf_cnt = 0;  // the contact pass that used the overflow list has finished
+    if (d.use_lists) d.rebuild[lvl & 1] = 0u;  // and so has the one that read this flag
   }
   if (i >= d.i_hi) return;
   PIn p = load_particle(d, i);
@@ -294,6 +293,7 @@ __global__ __launch_bounds__(256) void k_kick(Dev d) {
   if (i == 0) {
     d.step[3 - d.lc] = L + 1;
     *cell_tab(d, L).ovf_cnt = 0;
+    if (d.use_lists) d.rebuild[L & 1] = 0u;
   }
   if (i >= d.i_hi) return;
   PIn p = load_particle(d, i);

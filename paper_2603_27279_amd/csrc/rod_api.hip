@@ -282,23 +282,27 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
   b += 8 * 3 * N + 4 * 3 * N + 8 * 9 * N + 8 * 4 * N;                         // mu, bonds
   b += 8 * (size_t)max_slots * 6 * N + 8 * 4 * N;                               // dipole, contact
   b += 2 * (4 * cells + sizeof(CellSlot) * cells * CELL_CAP + 4 * OVF_CAP) + 4 * N;  // cells
+  if (d->contact_on && (long)N >= CONTACT_LANES_MAX_N) b += (4 * NBR_CAP + 4 + 24) * N;  // lists
   b += 8 * 18 * N + 8 * 9 * M;                                                  // energy
   return b;
 }
 
 // ------------------------------------------------------------------ schedule
-static int force_terms(rod_ctx* c, const Dev& d, int want_energy) {
+// build: rebuild the contact candidate lists of large systems this step.
+static int force_terms(rod_ctx* c, const Dev& d, int want_energy, int build) {
   if (!want_energy && c->launch_mode == ROD_LAUNCH_BATCHED) {
-    TIMED(c, ROD_KERNEL_FORCES, launch_forces, d, c->desc.precision, c->work, c->nwork, c->s);
+    TIMED(c, ROD_KERNEL_FORCES, launch_forces, d, c->desc.precision, c->work, c->nwork, build,
+          c->s);
     return ROD_OK;
   }
   TIMED(c, ROD_KERNEL_BOND, launch_bond, d, c->desc.precision, want_energy, c->s);
   if (c->desc.dipole_on)
     TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole, d, c->desc.precision, c->work, c->nwork, c->s);
-  if (c->desc.contact_on) TIMED(c, ROD_KERNEL_CONTACT, launch_contact, d, want_energy, c->s);
+  if (c->desc.contact_on)
+    TIMED(c, ROD_KERNEL_CONTACT, launch_contact, d, want_energy, build, c->s);
   return ROD_OK;
 }
-static int force_terms(rod_ctx* c, int want_energy) { return force_terms(c, c->d, want_energy); }
+static int force_terms(rod_ctx* c, int want_energy) { return force_terms(c, c->d, want_energy, 1); }
 
 // n consecutive steps. Batched: pre, forces, then (kick, forces) for every
 // further step, and post; the fused kick ends one step and starts the next, and
@@ -309,7 +313,7 @@ static int enqueue_steps(rod_ctx* c, int64_t n) {
   if (c->launch_mode != ROD_LAUNCH_BATCHED) {
     for (int64_t k = 0; k < n; ++k) {
       TIMED(c, ROD_KERNEL_PRE, launch_pre, c->d, PRE_STEP, c->s);
-      TRY(force_terms(c, 0));
+      TRY(force_terms(c, c->d, 0, k == 0));
       TIMED(c, ROD_KERNEL_POST, launch_post, c->d, POST_KICK, ROD_TERM_ALL, nullptr, nullptr,
             nullptr, c->s);
     }
@@ -317,11 +321,11 @@ static int enqueue_steps(rod_ctx* c, int64_t n) {
   }
   Dev d = c->d;  // d.lc = 1
   TIMED(c, ROD_KERNEL_PRE, launch_pre, d, PRE_STEP, c->s);
-  TRY(force_terms(c, d, 0));
+  TRY(force_terms(c, d, 0, 1));
   for (int64_t k = 1; k < n; ++k) {
     TIMED(c, ROD_KERNEL_KICK, launch_kick, d, c->s);
     d.lc = 3 - d.lc;
-    TRY(force_terms(c, d, 0));
+    TRY(force_terms(c, d, 0, 0));
   }
   TIMED(c, ROD_KERNEL_POST, launch_post, d, POST_KICK, ROD_TERM_ALL, nullptr, nullptr, nullptr,
         c->s);
@@ -389,7 +393,7 @@ static int enqueue_step_per_rod(rod_ctx* c) {
       HIPC(launch_dipole(rod_dev(r), c->desc.precision, c->rod_work + c->rod_work_off[r],
                          c->rod_work_off[r + 1] - c->rod_work_off[r], c->s));
   if (c->desc.contact_on)
-    for (int r = 0; r < R; ++r) HIPC(launch_contact(rod_dev(r), 0, c->s));
+    for (int r = 0; r < R; ++r) HIPC(launch_contact(rod_dev(r), 0, 1, c->s));
   for (int r = 0; r < R; ++r)
     HIPC(launch_post(rod_dev(r), POST_KICK, ROD_TERM_ALL, nullptr, nullptr, nullptr, c->s));
   return ROD_OK;
@@ -552,6 +556,14 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   d.dt = dsc->dt; d.damping = dsc->damping; d.C = dsc->mu0_4pi; d.kc = dsc->k_contact;
   d.rc = dsc->r_contact; d.inv_cell = dsc->contact_on ? 1.0 / dsc->r_contact : 0.0;
   d.depth = dsc->exclude_depth; d.field_len = dsc->field_len;
+  d.use_lists = dsc->contact_on && (long)N >= CONTACT_LANES_MAX_N;
+  d.skin = NBR_SKIN * dsc->r_contact;
+  // with lists the 27 cells around a particle must cover the list cutoff r_c + skin
+  if (d.use_lists) d.inv_cell = 1.0 / (dsc->r_contact + d.skin);
+  if (d.use_lists &&
+      ((rc = dalloc(c, &d.nbr, (size_t)NBR_CAP * N)) || (rc = dalloc(c, &d.nbr_cnt, (size_t)N)) ||
+       (rc = dalloc(c, &d.xb, 3 * (size_t)N)) || (rc = dalloc(c, &d.rebuild, 2))))
+    return cleanup(rc);
   d.dipole_on = dsc->dipole_on != 0; d.contact_on = dsc->contact_on != 0;
   {
     double a = std::sqrt(dsc->drive_axis[0] * dsc->drive_axis[0] +

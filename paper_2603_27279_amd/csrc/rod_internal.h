@@ -48,6 +48,13 @@ struct Dev {
   int* ovf_list;           // [2][OVF_CAP] particles whose cell was full
   int* ovf_cnt;            // [2] entries of the overflow lists (reset by the particle kernel)
   unsigned cell_mask;      // cells - 1 (power of two)
+  // Contact candidate lists of large systems (use_lists): see contact_listed.
+  int use_lists;
+  int* nbr;                // [NBR_CAP][N] candidates of each particle at the last build
+  int* nbr_cnt;            // [N] candidates listed, or -1 when more than NBR_CAP
+  double* xb;              // [3N] positions at the last build
+  unsigned* rebuild;       // [2] per level parity: some particle moved too far since the build
+  double skin;             // list cutoff is r_c + skin
   unsigned* flags;         // [4]: [0] non-finite state, [2] overflow list full
   long long* step;         // [3]: [0] time level of the state (written by the particle
                            // kernel); [1], [2] level of the force evaluation in flight,
@@ -63,7 +70,30 @@ struct Dev {
 
 constexpr int CELL_CAP = 8;
 constexpr int OVF_CAP = 4096;
+constexpr int NBR_CAP = 32;                     // candidates per particle list
+constexpr long CONTACT_LANES_MAX_N = 65536;     // below: lane-parallel cell search, above: lists
+constexpr double NBR_SKIN = 0.25;               // skin as a fraction of r_c
+constexpr double NBR_MOVE = 0.45;               // rebuild past this fraction of the skin
+                                                // (below 1/2, a margin for rounding)
 enum { FLAG_NONFINITE = 0, FLAG_LIST_OVF = 2 };
+
+// Cell of a coordinate (cells of side 1/inv), clamped so runaway coordinates
+// stay hashable.
+__device__ __forceinline__ int cell_coord(double x, double inv) {
+  double c = floor(x * inv);
+  c = fmin(fmax(c, -1.0e9), 1.0e9);
+  return (int)c;
+}
+
+// Bucket of cell (cx, cy, cz) of member `mem`: a row (cy, cz, mem) starts at a
+// hashed base and runs linearly in cx, so that the three cells of a row of a
+// 3x3x3 neighbourhood share cache lines. Distinct cells may share a bucket (the
+// search checks every candidate's distance), which costs only extra checks.
+__device__ __forceinline__ unsigned cell_hash(int cx, int cy, int cz, int mem, unsigned mask) {
+  const unsigned row = (unsigned)cy * 73856093u ^ (unsigned)cz * 19349663u ^
+                       (unsigned)mem * 83492791u;
+  return ((unsigned)cx + row) & mask;
+}
 
 // Cell list of time level `lvl`.
 struct CellTab { int* cnt; CellSlot* slot; int* ovf; int* ovf_cnt; };
@@ -107,11 +137,12 @@ hipError_t launch_bond(const Dev& d, int precision, int want_energy, hipStream_t
                        const hipEvent_t* ev = nullptr);
 hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int nwork,
                          hipStream_t s, const hipEvent_t* ev = nullptr);
-hipError_t launch_contact(const Dev& d, int want_energy, hipStream_t s,
+// build: rebuild contact candidate lists (large systems) regardless of motion.
+hipError_t launch_contact(const Dev& d, int want_energy, int build, hipStream_t s,
                           const hipEvent_t* ev = nullptr);
 // Dipole, bond and contact forces of a step in one launch.
-hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int nwork, hipStream_t s,
-                         const hipEvent_t* ev = nullptr);
+hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int nwork, int build,
+                         hipStream_t s, const hipEvent_t* ev = nullptr);
 hipError_t launch_post(const Dev& d, int mode, int mask, double* Fout, double* Tout,
                        double* Bout, hipStream_t s, const hipEvent_t* ev = nullptr);
 // Second half-kick of the step whose forces are in flight (level step[lc]) fused
