@@ -49,7 +49,6 @@ __device__ __forceinline__ float minus5(float) { return lane_value(-5.0f); }
 __device__ __forceinline__ double minus5(double) { return -5.0; }
 
 constexpr int TJ = 256;   // j tile staged per workgroup
-constexpr int JW = 64;    // j entries of a tile handled by one wave
 
 // Pair sums: f = sum s[(c - 5ab/r^2) r + a m_j], fm = sum s b,
 // bs = sum s b r, bm = sum m_j / r^3.
@@ -148,7 +147,8 @@ __device__ __forceinline__ void dipole_item(const Dev& d, const DipWork& wk, Dip
       tile[threadIdx.x] = Src<R>{d.x[j], d.x[N + j], d.x[2 * N + j], mu[j], mu[N + j], mu[2 * N + j]};
     }
     __syncthreads();
-    const int jb = wave * JW, je = min(jb + JW, jn);
+    const int q = (jn + 3) >> 2;  // the four waves take equal quarters of the staged tile
+    const int jb = min(wave * q, jn), je = min(jb + q, jn);
     if (jb < je) {
       Acc<R> A{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       const bool self = (t0 + jb < wk.i1) && (t0 + je > wk.i0);  // sub-tile may contain i

@@ -208,8 +208,9 @@ static int validate(const rod_desc* d) {
 
 // Dipole work list. Split layout: blocks of 64 targets against S source ranges
 // of the same member, S chosen so the launch holds about target_wgs work items
-// (each range at least one 256-source tile). Small-member layout: blocks of 16
-// targets against the whole member. small: -1 = automatic, 0 = split, 1 = small.
+// (each range at least half a 256-source tile). Small-member layout: blocks of
+// DIP_SMALL_I targets against the whole member. small: -1 = automatic, 0 =
+// split, 1 = small.
 static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
   const std::vector<int>& mrange = c->mrange_h;
   const int M = c->desc.n_members;
@@ -239,8 +240,8 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
       }
       continue;
     }
-    // enough j ranges to give the launch ~target_wgs work items, each of at least one tile
-    int S = (int)std::min<long>((target_wgs + iblocks - 1) / iblocks, (nm + 255) / 256);
+    // enough j ranges to give the launch ~target_wgs work items, each of at least half a tile
+    int S = (int)std::min<long>((target_wgs + iblocks - 1) / iblocks, (nm + 127) / 128);
     S = std::max(S, 1);
     const int len = (nm + S - 1) / S;
     S = (nm + len - 1) / len;
