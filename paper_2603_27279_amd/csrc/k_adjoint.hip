@@ -26,6 +26,7 @@
 #include "rod_adjoint.h"
 #include "bond_core.h"
 #include "dual.h"
+#include "particle_body.h"
 
 #include <algorithm>
 
@@ -78,12 +79,10 @@ __device__ void richardson_vjp(Q4<double> q, V3<double> w, double dt, Q4<double>
 // Post-kick VJP and the per-particle force terms (Zeeman, dipole torque,
 // damping). S1 is the state of the level whose forces are reversed; S0 the
 // state one level earlier (ADJ_STEP only).
-__global__ __launch_bounds__(256) void k_adj_local(Dev d, Adj a, const double* S0,
-                                                   const double* S1, int koff, int mode) {
+__device__ __forceinline__ void adj_local(const Dev& d, const Adj& a, long i, const double* S0,
+                                          const double* S1, int koff, int mode) {
   const long long lvl = *a.lbase + koff;
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long N = d.n;
-  if (i >= N) return;
   const bool free_p = d.bc[i] == 0;
   const double h = 0.5 * d.dt;
   V3<double> Fe{0, 0, 0}, Te{0, 0, 0}, vb{0, 0, 0}, wb{0, 0, 0};
@@ -411,16 +410,10 @@ __global__ __launch_bounds__(256) void k_adj_forces(Dev d, Adj a, const double* 
 // Assemble x-bar and q-bar of the level, push m-bar through m = q m_body q*,
 // then reverse the pre kick (ADJ_STEP) or write the initial-state gradients
 // (ADJ_PREPARE).
-__global__ __launch_bounds__(256) void k_adj_gather(Dev d, Adj a, const double* S0, const double* S1,
-                                                    int nslot_max, int mode, rod_gradients gx) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void adj_gather(const Dev& d, const Adj& a, long i, const double* S0,
+                                           const double* S1, int nslot_max, int mode,
+                                           const rod_gradients& gx) {
   const long N = d.n;
-  if (d.contact_on) {  // the contact reverse has finished: empty the level's cell list
-    const CellTab tab = cell_tab(d, d.step[d.lc]);
-    if (i == 0) *tab.ovf_cnt = 0;
-    if (i < N) tab.cnt[d.key[i]] = 0;
-  }
-  if (i >= N) return;
   const uint8_t bf = d.bflags[i];
   V3<double> xb = ldv(a.cx, N, i) + ldv(a.xloc, N, i);
   Q4<double> qb = ld4(a.cq, N, i);
@@ -485,11 +478,56 @@ __global__ __launch_bounds__(256) void k_adj_gather(Dev d, Adj a, const double* 
   }
 }
 
+// Cell list of level lvl is done with: empty it.
+__device__ __forceinline__ void clear_cells_of(const Dev& d, long i, long long lvl) {
+  if (!d.contact_on) return;
+  const CellTab tab = cell_tab(d, lvl);
+  if (i == 0) *tab.ovf_cnt = 0;
+  if (i < d.n) tab.cnt[d.key[i]] = 0;
+}
+
+// One reverse level in one pass per particle, for the state S1 of level
+// lbase + koff (view v, whose level counter reads that level):
+//  - when S2 (the state one level later) is given, the gather of that later
+//    level, which hands over the cotangents of S1 and empties its cell list;
+//  - the dipole moment and cell-list entry of S1 (the force evaluation being
+//    reversed needs them);
+//  - the local VJPs of level koff (kicks, damping, Zeeman, torques).
+// Everything a particle reads was written by earlier kernels or by its own
+// thread; the cell lists of consecutive levels alternate tables.
+__global__ __launch_bounds__(256) void k_adj_level(Dev v, Adj a, const double* S0, const double* S1,
+                                                   const double* S2, int koff, int mode,
+                                                   int nslot_max) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long N = v.n;
+  const long long lvl = v.step[v.lc];
+  if (S2) {
+    clear_cells_of(v, i, lvl + 1);
+    if (i < N) adj_gather(v, a, i, S1, S2, nslot_max, ADJ_STEP, rod_gradients{});
+  }
+  if (i >= N) return;
+  moment_and_cell(v, i, ld4(S1 + 6 * N, N, i), ldv(S1, N, i), ldv(v.mb, N, i), v.mem[i], v.rod[i],
+                  lvl);
+  adj_local(v, a, i, S0, S1, koff, mode);
+}
+
+// The gather of a level on its own (the last of a segment, and the initial
+// force evaluation).
+__global__ __launch_bounds__(256) void k_adj_gather(Dev v, Adj a, const double* S0, const double* S1,
+                                                    int nslot_max, int mode, rod_gradients gx) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  clear_cells_of(v, i, v.step[v.lc]);
+  if (i < v.n) adj_gather(v, a, i, S0, S1, nslot_max, mode, gx);
+}
+
 __global__ void k_set_level(long long* p, long long v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) { p[0] = v; p[1] = v; }
 }
-__global__ void k_set_base(long long* p, long long v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
+// First level of the segment, and the counters of the reverse views.
+__global__ void k_set_base(long long* p, long long* levels, int nlev, long long v) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) p[0] = v;
+  if (k < nlev) levels[3 * k] = levels[3 * k + 1] = levels[3 * k + 2] = v + k;
 }
 
 // ---------------------------------------------------------------- host side
@@ -543,6 +581,7 @@ int tape_init(Tape& t, const Dev& d, int every, int capacity, std::vector<void*>
   ATRY(adalloc(allocs, &a.scratch, 6 * N));
   ATRY(adalloc(allocs, &a.level, 3));
   ATRY(adalloc(allocs, &a.lbase, 1));
+  ATRY(adalloc(allocs, &a.levels, 3 * (size_t)(every + 1)));
   return ROD_OK;
 }
 
@@ -584,17 +623,19 @@ static Dev view(const Dev& d, double* S, long long* level) {
 static inline unsigned nblk(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // Reverse the force evaluation of state S1 (level lbase + koff) and, in
-// ADJ_STEP mode, the kicks of the step from S0. Only device-side values vary
-// between segments, so a full segment can be captured once and replayed.
+// ADJ_STEP mode, the kicks of the step from S0: one per-particle pass (which
+// first completes the later level S2 when given) and one launch for the force
+// terms. The gather of S1's own level is left to the next call or to
+// reverse_gather. Only device-side values vary between segments, so a full
+// segment can be captured once and replayed.
 static int reverse_level(Tape& t, const Dev& d, const DipWork* work, int nwork, int max_slots,
-                         hipStream_t s, const double* S0, double* S1, int koff, int mode,
-                         const rod_gradients& gx) {
+                         hipStream_t s, const double* S0, double* S1, const double* S2, int koff,
+                         int mode) {
   const long N = d.n;
   Adj& a = t.a;
-  Dev v = view(d, S1, a.level);
-  ACHK(launch_pre(v, PRE_EVAL, s));  // dipole moments of S1 and its cell list
-  hipLaunchKernelGGL(k_adj_local, dim3(nblk(N, 256)), dim3(256), 0, s, v, a, S0, (const double*)S1,
-                     koff, mode);
+  Dev v = view(d, S1, a.levels + 3 * koff);
+  hipLaunchKernelGGL(k_adj_level, dim3(nblk(N, 256)), dim3(256), 0, s, v, a, S0,
+                     (const double*)S1, S2, koff, mode, max_slots);
   ACHK(hipGetLastError());
   const int ndip = d.dipole_on ? nwork : 0;
   const int nbond = (int)nblk(11 * N, 256);
@@ -602,7 +643,15 @@ static int reverse_level(Tape& t, const Dev& d, const DipWork* work, int nwork, 
   hipLaunchKernelGGL(k_adj_forces, dim3(ndip + nbond + ncont + d.M), dim3(256), 0, s, v, a,
                      (const double*)S1, work, ndip, nbond, ncont, koff);
   ACHK(hipGetLastError());
-  hipLaunchKernelGGL(k_adj_gather, dim3(nblk(N, 256)), dim3(256), 0, s, v, a, S0,
+  return ROD_OK;
+}
+
+// The gather of level lbase + koff on its own.
+static int reverse_gather(Tape& t, const Dev& d, int max_slots, hipStream_t s, const double* S0,
+                          double* S1, int koff, int mode, const rod_gradients& gx) {
+  Adj& a = t.a;
+  Dev v = view(d, S1, a.levels + 3 * koff);
+  hipLaunchKernelGGL(k_adj_gather, dim3(nblk(d.n, 256)), dim3(256), 0, s, v, a, S0,
                      (const double*)S1, max_slots, mode, gx);
   ACHK(hipGetLastError());
   return ROD_OK;
@@ -628,15 +677,14 @@ static int recompute(Tape& t, const Dev& d, int precision, const DipWork* work, 
 static int reverse_segment(Tape& t, const Dev& d, const DipWork* work, int nwork, int max_slots,
                            hipStream_t s, int len) {
   const size_t SP = SEG_PLANES * (size_t)d.n;
-  rod_gradients none{};
   for (int k = len - 1; k >= 0; --k) {
     double* Sk = t.seg + k * SP;
-    ATRY(reverse_level(t, d, work, nwork, max_slots, s, Sk, Sk + SP, k + 1, ADJ_STEP, none));
+    const double* S2 = k + 1 < len ? Sk + 2 * SP : nullptr;
+    ATRY(reverse_level(t, d, work, nwork, max_slots, s, Sk, Sk + SP, S2, k + 1, ADJ_STEP));
   }
-  return ROD_OK;
+  return reverse_gather(t, d, max_slots, s, t.seg, t.seg + SP, 1, ADJ_STEP, rod_gradients{});
 }
 
-// Capture `body` on stream s into an executable graph.
 template <class F>
 static int capture(hipStream_t s, hipGraphExec_t* out, F body) {
   hipGraph_t g = nullptr;
@@ -686,7 +734,8 @@ int adjoint_run(Tape& t, const Dev& d, int precision, const DipWork* work, int n
                         STATE_PLANES * N * sizeof(double), hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_set_level, dim3(1), dim3(1), 0, s, a.level, (long long)s0);
     ACHK(hipGetLastError());
-    hipLaunchKernelGGL(k_set_base, dim3(1), dim3(1), 0, s, a.lbase, (long long)s0);
+    hipLaunchKernelGGL(k_set_base, dim3(nblk(t.every + 1, 256)), dim3(256), 0, s, a.lbase,
+                       a.levels, t.every + 1, (long long)s0);
     ACHK(hipGetLastError());
     if (len == t.every) {
       if (!t.g_recompute)
@@ -706,13 +755,15 @@ int adjoint_run(Tape& t, const Dev& d, int precision, const DipWork* work, int n
     ACHK(hipMemcpyAsync(S, t.ckpt, STATE_PLANES * N * sizeof(double), hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_set_level, dim3(1), dim3(1), 0, s, a.level, (long long)t.start_step);
     ACHK(hipGetLastError());
-    hipLaunchKernelGGL(k_set_base, dim3(1), dim3(1), 0, s, a.lbase, (long long)t.start_step);
+    hipLaunchKernelGGL(k_set_base, dim3(nblk(t.every + 1, 256)), dim3(256), 0, s, a.lbase,
+                       a.levels, t.every + 1, (long long)t.start_step);
     ACHK(hipGetLastError());
     Dev v = view(d, S, a.level);
     ACHK(launch_pre(v, PRE_EVAL, s));
     ACHK(launch_forces(v, precision, work, nwork, 1, s));
     ACHK(launch_post(v, POST_EVAL, ROD_TERM_ALL, a.scratch, a.scratch + 3 * N, S + 19 * N, s));
-    ATRY(reverse_level(t, d, work, nwork, max_slots, s, S, S, 0, ADJ_PREPARE, *gx));
+    ATRY(reverse_level(t, d, work, nwork, max_slots, s, S, S, nullptr, 0, ADJ_PREPARE));
+    ATRY(reverse_gather(t, d, max_slots, s, S, S, 0, ADJ_PREPARE, *gx));
   }
   if (gx->m_body) ACHK(hipMemcpyAsync(gx->m_body, a.mbbar, b3, hipMemcpyDeviceToDevice, s));
   if (gx->field)

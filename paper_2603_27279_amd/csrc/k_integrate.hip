@@ -6,6 +6,7 @@
 #include "rod.h"
 #include "rod_internal.h"
 #include "rod_math.h"
+#include "particle_body.h"
 
 // Contract a*b+c only within one expression, so that the separate and the
 // fused form of a step round identically.
@@ -72,33 +73,6 @@ __device__ __forceinline__ void advance(const Dev& d, long i, int b, long long l
       st3(d.v, N, i, v);
       st3(d.w, N, i, w);
     }
-  }
-}
-
-// Dipole moment in the global frame, m = q m_body q*, and the particle's entry
-// in the cell list of level lvl.
-__device__ __forceinline__ void moment_and_cell(const Dev& d, long i, Q4<double> q, V3<double> x,
-                                                V3<double> mb, int mem, int rod, long long lvl) {
-  const long N = d.n;
-  V3<double> m = qrot(q, mb);
-  st3(d.mu, N, i, m);
-  if (d.muf) st3(d.muf, N, i, V3<float>{(float)m.x, (float)m.y, (float)m.z});
-  if (d.contact_on) {
-    const CellTab t = cell_tab(d, lvl);
-    unsigned key = cell_hash(cell_coord(x.x, d.inv_cell), cell_coord(x.y, d.inv_cell),
-                             cell_coord(x.z, d.inv_cell), mem, d.cell_mask);
-    int slot = atomicAdd(&t.cnt[key], 1);
-    if (slot < CELL_CAP) {
-      CellSlot e;
-      e.x = x.x; e.y = x.y; e.z = x.z;
-      e.tag = (long long)(unsigned)i | ((long long)rod << 32);
-      t.slot[(long)key * CELL_CAP + slot] = e;
-    } else {
-      int o = atomicAdd(t.ovf_cnt, 1);
-      if (o < OVF_CAP) t.ovf[o] = (int)i;
-      else atomicOr(&d.flags[FLAG_LIST_OVF], 1u);
-    }
-    d.key[i] = (int)key;
   }
 }
 

@@ -1,0 +1,36 @@
+// Per-particle code shared by the integration kernels and the reverse pass.
+#pragma once
+#include "rod_internal.h"
+#include "rod_math.h"
+
+namespace rodmx {
+
+// Dipole moment in the global frame, m = q m_body q*, and the particle's entry
+// in the cell list of level lvl.
+__device__ __forceinline__ void moment_and_cell(const Dev& d, long i, Q4<double> q, V3<double> x,
+                                                V3<double> mb, int mem, int rod, long long lvl) {
+#pragma clang fp contract(on)  // round alike wherever it is inlined
+  const long N = d.n;
+  V3<double> m = qrot(q, mb);
+  st3(d.mu, N, i, m);
+  if (d.muf) st3(d.muf, N, i, V3<float>{(float)m.x, (float)m.y, (float)m.z});
+  if (d.contact_on) {
+    const CellTab t = cell_tab(d, lvl);
+    unsigned key = cell_hash(cell_coord(x.x, d.inv_cell), cell_coord(x.y, d.inv_cell),
+                             cell_coord(x.z, d.inv_cell), mem, d.cell_mask);
+    int slot = atomicAdd(&t.cnt[key], 1);
+    if (slot < CELL_CAP) {
+      CellSlot e;
+      e.x = x.x; e.y = x.y; e.z = x.z;
+      e.tag = (long long)(unsigned)i | ((long long)rod << 32);
+      t.slot[(long)key * CELL_CAP + slot] = e;
+    } else {
+      int o = atomicAdd(t.ovf_cnt, 1);
+      if (o < OVF_CAP) t.ovf[o] = (int)i;
+      else atomicOr(&d.flags[FLAG_LIST_OVF], 1u);
+    }
+    d.key[i] = (int)key;
+  }
+}
+
+}  // namespace rodmx

@@ -29,6 +29,7 @@ struct Adj {
   double *scratch;      // [6N] outputs of evaluations whose values are not needed
   long long* level;     // [3] time-level counters of the recompute view
   long long* lbase;     // [1] first level of the segment being reversed
+  long long* levels;    // [every + 1][3]: counters of the reverse view of level lbase + k
 };
 
 struct Tape {

@@ -897,6 +897,7 @@ extern "C" int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, c
   if (c->tape.active) return fail(ROD_E_STATE, "autotune while a tape is recorded");
   std::string rep, key = tune_key(c);
   int small = -1, target = 0;
+  bool cached = false;
   double best_us = 0.0;
   if (cache_path && !force) {  // look the problem up in the cache
     if (FILE* f = fopen(cache_path, "r")) {
@@ -907,13 +908,14 @@ extern "C" int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, c
         if (sscanf(line, "{\"key\": \"%299[^\"]\", \"small\": %d, \"target_wgs\": %d, \"us_per_eval\": %lf",
                    k, &s_, &t_, &u_) == 4 && key == k) {
           small = s_; target = t_; best_us = u_;
+          cached = true;
         }
       }
       fclose(f);
     }
   }
   TRY(enter(c));
-  if (target == 0) {
+  if (!cached) {
     struct Cand { int small, target; };
     std::vector<Cand> cands;
     int max_member = 0;

@@ -196,3 +196,20 @@ def test_contact_lists_match_cell_search_bitwise():
     assert np.max(np.abs(sa["x"] - o["x"])) / motion <= 1e-9
     for s in (a, b, c):
         s.free()
+
+
+def test_autotune_cache_holds_small_layout_choice(tmp_path):
+    """A cached small-member choice (whose target_wgs is 0) is taken from the cache."""
+    w = workloads.twisted_rod(n=1500)
+    a = RodSim(w, precision="mixed")
+    key = a.autotune().strip().splitlines()[-1].split("key=")[1].strip()
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text('{"key": "%s", "small": 1, "target_wgs": 0, "us_per_eval": 1.000}\n' % key)
+    rep = a.autotune(cache)
+    assert "cached choice" in rep
+    assert "chosen: small-member layout" in rep
+    a.step(10)
+    o = oracle.run(w, 10)
+    motion = np.max(np.abs(o["x"] - w["x0"]))
+    assert np.max(np.abs(a.state()["x"] - o["x"])) / motion <= 1e-4
+    a.free()
