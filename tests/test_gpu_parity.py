@@ -269,3 +269,57 @@ def test_full_size_sampled_rows(name):
     assert rel_inf(B, Bo) <= TOL["mixed"], (name, rel_inf(B, Bo))
     assert np.max(np.abs(Fc - Fco)) <= 1e-12 * max(1.0, np.max(np.abs(Fco)))
     sim.free()
+
+
+def _check_trajectory(g, o, o0, prec, label):
+    tol = TRAJ_TOL[prec]
+    for k in ("x", "q"):
+        motion = max(np.max(np.abs(o[k] - o0[k])), 1e-300)
+        assert np.max(np.abs(g[k] - o[k])) / motion <= tol, (label, k)
+    for k in ("v", "w", "F", "T"):
+        assert rel_inf(g[k], o[k]) <= tol, (label, k, rel_inf(g[k], o[k]))
+
+
+def test_full_size_twisted_rod_trajectory():
+    """The benchmark's workload as the benchmark runs it (N = 4096, mixed path,
+    autotuned layout, 50-step graphs, fused launches): 100 steps against the
+    oracle's trajectory."""
+    w = workloads.make("twisted_rod")
+    sim = RodSim(w, precision="mixed", graph_steps=50)
+    sim.autotune()
+    sim.step(100)
+    sim.sync()
+    g = sim.state()
+    assert g["step"] == 100
+    _check_trajectory(g, oracle.run(w, 100), oracle.run(w, 0), "mixed", "twisted_rod")
+    sim.free()
+
+
+def _member(w, m):
+    """Member m of a workload as a system of its own (members never interact)."""
+    off = w["rod_offset"]
+    rods = np.nonzero(w["rod_member"] == m)[0]
+    a, b = off[rods[0]], off[rods[-1] + 1]
+    sub = dict(w)
+    sub.update(n=int(b - a), rod_offset=(off[rods[0]:rods[-1] + 2] - a).astype(np.int32),
+               rod_member=np.zeros(len(rods), np.int32), n_members=1,
+               rod_params=w["rod_params"][rods], field=w["field"][:, m:m + 1, :])
+    for k in ("x_ref", "x0", "v0", "w0", "q0", "m_body", "bc"):
+        sub[k] = w[k][a:b]
+    return sub, a, b
+
+
+def test_full_size_ensemble_members_trajectory():
+    """The 64 x 4096 ensemble stepped as one batched launch (20 steps, graphs of
+    5); members 0, 31 and 63 checked against the oracle run on each member alone."""
+    w = workloads.make("ensemble")
+    sim = RodSim(w, precision="mixed", graph_steps=5)
+    sim.autotune()
+    sim.step(20)
+    sim.sync()
+    g = sim.state()
+    for m in (0, 31, 63):
+        sub, a, b = _member(w, m)
+        gm = {k: g[k][a:b] for k in ("x", "q", "v", "w", "F", "T")}
+        _check_trajectory(gm, oracle.run(sub, 20), oracle.run(sub, 0), "mixed", f"member {m}")
+    sim.free()
