@@ -114,17 +114,65 @@ __device__ __forceinline__ void tile_pairs(int jb, int je, int jbase, int i, dou
   }
 }
 
-// LDS of one split work item: the staged tile, reused for the final reduction.
+// Far sub-tiles (mixed path). A sub-tile is far from the wave when every
+// target lies more than three half-diagonals h from the centre o of a box
+// holding the sub-tile's sources (the union of the boxes of the 64-particle
+// chunks it touches, written where positions were set). Then a difference is
+// formed as (x_i - o) - (x_j - o), each offset taken in FP64 and rounded to
+// FP32 once. Since |x_j - o| <= h and |r| > 2h, the error stays below 3 ulp of
+// |r|, the size of the FP32 pair arithmetic's own error, and a pair costs three
+// FP32 subtractions instead of three FP64 subtractions and conversions.
+// Returns false (nothing done) when some target is near; the sub-tile then
+// takes the exact path.
+__device__ __forceinline__ bool far_tile_pairs(const Dev& d, int jg0, int jg1, int jb, int je,
+                                               bool act, double xi, double yi, double zi,
+                                               float mix, float miy, float miz,
+                                               const Src<float>* tile, float4* rel,
+                                               Acc<float>& A) {
+  const int lane = threadIdx.x & 63;
+  const double* b0 = d.cbox + 6 * (jg0 >> 6);
+  const double* b1 = d.cbox + 6 * ((jg1 - 1) >> 6);
+  const double lx = fmin(b0[0], b1[0]), ly = fmin(b0[1], b1[1]), lz = fmin(b0[2], b1[2]);
+  const double hx = fmax(b0[3], b1[3]), hy = fmax(b0[4], b1[4]), hz = fmax(b0[5], b1[5]);
+  const double ox = 0.5 * (lx + hx), oy = 0.5 * (ly + hy), oz = 0.5 * (lz + hz);
+  const double ex = 0.5 * (hx - lx), ey = 0.5 * (hy - ly), ez = 0.5 * (hz - lz);
+  const double h2 = ex * ex + ey * ey + ez * ez;
+  const double tx = xi - ox, ty = yi - oy, tz = zi - oz;
+  if (!__all(!act || tx * tx + ty * ty + tz * tz > 9.0 * h2)) return false;
+  const int n = je - jb;
+  if (lane < n) {
+    const Src<float>& e = tile[jb + lane];
+    rel[lane] = make_float4((float)(e.x - ox), (float)(e.y - oy), (float)(e.z - oz), 0.0f);
+  }
+  const float xr = (float)tx, yr = (float)ty, zr = (float)tz;
+  const float m5 = minus5(0.0f);
+  const float4* pr = rel + lane_value(0);
+  const Src<float>* p = tile + lane_value(jb);
+#pragma unroll 2
+  for (int k = 0; k < n; ++k) {
+    const float4 r = pr[k];
+    const float dx = xr - r.x, dy = yr - r.y, dz = zr - r.z;
+    const float r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
+    pair_acc(dx, dy, dz, p[k].mx, p[k].my, p[k].mz, mix, miy, miz, rsq(r2), m5, A);
+  }
+  return true;
+}
+
+// LDS of one split work item: the staged tile and the per-wave relative source
+// positions of far sub-tiles, reused for the final reduction.
 template <class R>
 union DipSmem {
-  Src<R> tile[TJ];
+  struct {
+    Src<R> tile[TJ];
+    float4 rel[4][64];
+  } st;
   double red[4][NACC][64];
 };
 
 // One work item of the split layout (256 threads).
 template <class R>
 __device__ __forceinline__ void dipole_item(const Dev& d, const DipWork& wk, DipSmem<R>& sm) {
-  Src<R>* tile = sm.tile;
+  Src<R>* tile = sm.st.tile;
   const long N = d.n;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
@@ -151,11 +199,18 @@ __device__ __forceinline__ void dipole_item(const Dev& d, const DipWork& wk, Dip
     const int jb = min(wave * q, jn), je = min(jb + q, jn);
     if (jb < je) {
       Acc<R> A{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      bool far = false;
+      if constexpr (sizeof(R) == 4)
+        if (d.far_ok)
+          far = far_tile_pairs(d, t0 + jb, t0 + je, jb, je, act, xi, yi, zi, mix, miy, miz, tile,
+                               sm.st.rel[wave], A);
       const bool self = (t0 + jb < wk.i1) && (t0 + je > wk.i0);  // sub-tile may contain i
-      if (self)
+      if (far) {
+      } else if (self) {
         tile_pairs<R, true>(jb, je, t0, i, xi, yi, zi, mix, miy, miz, tile, A);
-      else
+      } else {
         tile_pairs<R, false>(jb, je, t0, i, xi, yi, zi, mix, miy, miz, tile, A);
+      }
       F[0] += A.fx; F[1] += A.fy; F[2] += A.fz; F[3] += A.fm;
       F[4] += A.bsx; F[5] += A.bsy; F[6] += A.bsz;
       F[7] += A.bmx; F[8] += A.bmy; F[9] += A.bmz;

@@ -76,12 +76,23 @@ __device__ __forceinline__ void advance(const Dev& d, long i, int b, long long l
   }
 }
 
+__device__ __forceinline__ V3<double> pre_particle(const Dev& d, long i, int mode, long long n,
+                                                   long long lvl);
+
 __global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
   const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long n = d.step[0];
   const long long lvl = n + (mode == PRE_STEP ? 1 : 0);  // level of the coming force evaluation
   if (i == 0) d.step[d.lc] = lvl;
-  if (i >= d.i_hi) return;
+  const bool valid = i < d.i_hi;
+  V3<double> x{0.0, 0.0, 0.0};
+  if (valid) x = pre_particle(d, i, mode, n, lvl);
+  chunk_box(d, i, x, valid);
+}
+
+// The pre kernel's work for particle i; returns its position at level lvl.
+__device__ __forceinline__ V3<double> pre_particle(const Dev& d, long i, int mode, long long n,
+                                                   long long lvl) {
   const long N = d.n;
   const int b = d.bc[i];
   // state read in place, or from separate planes (out-of-place step)
@@ -114,6 +125,7 @@ __global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
     st4(d.q, N, i, q);
   }
   moment_and_cell(d, i, q, x, mb, mem, rod, lvl);
+  return x;
 }
 
 __device__ __forceinline__ bool finite3(V3<double> a) {
@@ -269,15 +281,20 @@ __global__ __launch_bounds__(256) void k_kick(Dev d) {
     *cell_tab(d, L).ovf_cnt = 0;
     if (d.use_lists) d.rebuild[L & 1] = 0u;
   }
-  if (i >= d.i_hi) return;
-  PIn p = load_particle(d, i);
-  const int key = d.contact_on ? d.key[i] : 0;
-  V3<double> F, T;
-  gather(d, i, ROD_TERM_ALL, L, nullptr, p, F, T);
-  kick(d, i, F, T, p, false);
-  if (d.contact_on) cell_tab(d, L).cnt[key] = 0;
-  advance(d, i, p.b, L + 1, p.x, p.v, p.q, p.w, F, T, p.minv, p.Iinv, false);
-  moment_and_cell(d, i, p.q, p.x, p.mb, p.mem, p.rod, L + 1);
+  const bool valid = i < d.i_hi;
+  V3<double> x{0.0, 0.0, 0.0};
+  if (valid) {
+    PIn p = load_particle(d, i);
+    const int key = d.contact_on ? d.key[i] : 0;
+    V3<double> F, T;
+    gather(d, i, ROD_TERM_ALL, L, nullptr, p, F, T);
+    kick(d, i, F, T, p, false);
+    if (d.contact_on) cell_tab(d, L).cnt[key] = 0;
+    advance(d, i, p.b, L + 1, p.x, p.v, p.q, p.w, F, T, p.minv, p.Iinv, false);
+    moment_and_cell(d, i, p.q, p.x, p.mb, p.mem, p.rod, L + 1);
+    x = p.x;
+  }
+  chunk_box(d, i, x, valid);
 }
 
 // Per-particle energy terms [9][N]: bond terms attributed to the bond's first

@@ -33,4 +33,22 @@ __device__ __forceinline__ void moment_and_cell(const Dev& d, long i, Q4<double>
   }
 }
 
+// Bounding box of the wave's 64 particles (a 64-aligned chunk: the
+// per-particle kernels start at particle 0 in blocks of 64 or 256) into
+// d.cbox. Every lane of the wave calls it; `valid` marks lanes with a particle.
+__device__ __forceinline__ void chunk_box(const Dev& d, long i, V3<double> x, bool valid) {
+  if (!d.far_ok) return;
+  double lx = valid ? x.x : 1e300, ly = valid ? x.y : 1e300, lz = valid ? x.z : 1e300;
+  double hx = valid ? x.x : -1e300, hy = valid ? x.y : -1e300, hz = valid ? x.z : -1e300;
+  for (int o = 32; o > 0; o >>= 1) {
+    lx = fmin(lx, __shfl_xor(lx, o)); hx = fmax(hx, __shfl_xor(hx, o));
+    ly = fmin(ly, __shfl_xor(ly, o)); hy = fmax(hy, __shfl_xor(hy, o));
+    lz = fmin(lz, __shfl_xor(lz, o)); hz = fmax(hz, __shfl_xor(hz, o));
+  }
+  if ((threadIdx.x & 63) == 0 && i < d.n) {
+    double* b = d.cbox + 6 * (i >> 6);
+    b[0] = lx; b[1] = ly; b[2] = lz; b[3] = hx; b[4] = hy; b[5] = hz;
+  }
+}
+
 }  // namespace rodmx

@@ -383,6 +383,7 @@ static int enqueue_step_per_rod(rod_ctx* c) {
   const int R = c->desc.n_rods;
   auto rod_dev = [&](int r) {
     Dev dr = c->d;
+    dr.far_ok = 0;  // waves do not start on 64-particle chunk boundaries
     dr.i_lo = c->rod_offset[r];
     dr.i_hi = c->rod_offset[r + 1];
     return dr;
@@ -549,6 +550,10 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
       (rc = dalloc(c, &c->pair_count, 1)))
     return cleanup(rc);
   d.muf = dsc->precision == ROD_MIXED ? muf : nullptr;
+  if (dsc->precision == ROD_MIXED && dsc->dipole_on) {
+    if ((rc = dalloc(c, &d.cbox, 6 * (size_t)((N + 63) / 64)))) return cleanup(rc);
+    d.far_ok = 1;
+  }
   size_t cells = dsc->contact_on ? next_pow2(std::max<size_t>(1024, 2 * (size_t)N)) : 1;
   if ((rc = dalloc(c, &d.cell_cnt, 2 * cells)) ||
       (rc = dalloc(c, &d.cell_slot, 2 * cells * CELL_CAP)))

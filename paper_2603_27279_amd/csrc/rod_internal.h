@@ -64,6 +64,12 @@ struct Dev {
   double dt, damping, C, kc, rc, inv_cell;
   int depth, field_len, dipole_on, contact_on;
   int dip_small;           // dipole work items use the small-member layout (4 i per item)
+  // Bounding boxes of consecutive 64-particle chunks at the level being
+  // evaluated (x, y, z low then high), written where positions are set; the
+  // mixed dipole kernel uses them to pick far sub-tiles (far_ok; off in the
+  // per-rod loop, whose waves do not start on chunk boundaries).
+  double* cbox;            // [(N + 63) / 64][6]
+  int far_ok;
   double axis[3];
   long long period;
 };
