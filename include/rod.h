@@ -221,8 +221,10 @@ int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, char* report
  * ROD_LAUNCH_SEPARATE: as batched, with the three force terms launched as
  * separate kernels and no kick fusion (per-term timing). ROD_LAUNCH_PER_ROD: the plain per-rod
  * loop, every kernel launched once per rod on that rod's particles, eagerly;
- * kept as the baseline the batched form is measured against. All three give
- * bitwise identical states. */
+ * kept as the baseline the batched form is measured against. Batched and
+ * separate give bitwise identical states; so does the per-rod loop in FP64,
+ * while on the mixed path it always takes the exact position differences in
+ * the dipole sum and agrees with the batched launch to rounding. */
 enum { ROD_LAUNCH_BATCHED = 0, ROD_LAUNCH_PER_ROD = 1, ROD_LAUNCH_SEPARATE = 2 };
 int rod_launch_mode(rod_ctx* c, int32_t mode);
 
