@@ -657,20 +657,30 @@ static int reverse_gather(Tape& t, const Dev& d, int max_slots, hipStream_t s, c
   return ROD_OK;
 }
 
-// Recompute steps 0..len-1 of a segment from seg[0] (levels from the view's counter).
+// Recompute steps 0..len-1 of a segment from seg[0] (levels from the view's
+// counters), with the forward's fused chain: pre, forces, then (kick, forces)
+// per further step, and post. Each level's state goes to its own slot; the
+// kick closes slot k (full-step v and w, forces, dipole field) and writes the
+// advanced state into slot k + 1.
 static int recompute(Tape& t, const Dev& d, int precision, const DipWork* work, int nwork,
                      hipStream_t s, int len) {
   const long N = d.n;
   const size_t SP = SEG_PLANES * (size_t)N;
-  for (int k = 0; k < len; ++k) {
+  Dev v = view(d, t.seg + SP, t.a.level);
+  v.src = t.seg;  // the pre kernel reads step 0 and writes step 1
+  ACHK(launch_pre(v, PRE_STEP, s));
+  v.src = nullptr;
+  ACHK(launch_forces(v, precision, work, nwork, 1, s));
+  for (int k = 1; k < len; ++k) {
     double* Sk = t.seg + k * SP;
-    double* Sk1 = Sk + SP;
-    Dev v = view(d, Sk1, t.a.level);
-    v.src = Sk;  // the pre kernel reads step k and writes step k+1
-    ACHK(launch_pre(v, PRE_STEP, s));
+    v.nx = Sk + SP;
+    ACHK(launch_kick(v, Sk + 19 * N, s));
+    Dev w = view(d, Sk + SP, t.a.level);
+    w.lc = 3 - v.lc;
+    v = w;
     ACHK(launch_forces(v, precision, work, nwork, 1, s));
-    ACHK(launch_post(v, POST_KICK, ROD_TERM_ALL, nullptr, nullptr, Sk1 + 19 * N, s));
   }
+  ACHK(launch_post(v, POST_KICK, ROD_TERM_ALL, nullptr, nullptr, t.seg + len * SP + 19 * N, s));
   return ROD_OK;
 }
 

@@ -40,13 +40,19 @@ __device__ __forceinline__ Q4<double> drive_q(const Dev& d, long long lvl) {
 
 // Advance particle i from its state at level lvl - 1 (in registers) to level
 // lvl: half-kick, drift and quaternion update of free particles; the imposed
-// rotation of driven ones. States of particles that do not move are written
-// only when `copy_still` is set (out-of-place step).
+// rotation of driven ones. The result goes to the planes of d.nx when set,
+// else in place; states of particles that do not move are written only when
+// `copy_still` is set (out-of-place step).
 __device__ __forceinline__ void advance(const Dev& d, long i, int b, long long lvl, V3<double>& x,
                                         V3<double>& v, Q4<double>& q, V3<double>& w,
                                         V3<double> F, V3<double> T, double minv, double Iinv,
                                         bool copy_still) {
   const long N = d.n;
+  // output planes: those of the next recorded state, or in place
+  double* const xo = d.nx ? d.nx : d.x;
+  double* const vo = d.nx ? d.nx + 3 * N : d.v;
+  double* const qo = d.nx ? d.nx + 6 * N : d.q;
+  double* const wo = d.nx ? d.nx + 10 * N : d.w;
   if (b == 0) {
     const double h = 0.5 * d.dt;
     v = v + (h * minv) * F;
@@ -61,17 +67,17 @@ __device__ __forceinline__ void advance(const Dev& d, long i, int b, long long l
       if (far && __lane_id() == (unsigned)(__ffsll((long long)who) - 1))
         atomicOr(&d.rebuild[lvl & 1], 1u);
     }
-    st3(d.v, N, i, v);
-    st3(d.x, N, i, x);
-    st3(d.w, N, i, w);
-    st4(d.q, N, i, q);
+    st3(vo, N, i, v);
+    st3(xo, N, i, x);
+    st3(wo, N, i, w);
+    st4(qo, N, i, q);
   } else {
     if (b == 2) q = drive_q(d, lvl);
-    if (copy_still || b == 2) st4(d.q, N, i, q);
+    if (copy_still || b == 2) st4(qo, N, i, q);
     if (copy_still) {
-      st3(d.x, N, i, x);
-      st3(d.v, N, i, v);
-      st3(d.w, N, i, w);
+      st3(xo, N, i, x);
+      st3(vo, N, i, v);
+      st3(wo, N, i, w);
     }
   }
 }
@@ -273,7 +279,7 @@ __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double*
 // half-kick at level L = step[lc], then half-kick, drift, rotation, moments and
 // cell insertion for level L + 1 (written to step[3 - lc]). The cell list and
 // overflow list of level L are emptied while those of level L + 1 are filled.
-__global__ __launch_bounds__(256) void k_kick(Dev d) {
+__global__ __launch_bounds__(256) void k_kick(Dev d, double* Bo) {
   const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long L = d.step[d.lc];
   if (i == 0) {
@@ -287,10 +293,13 @@ __global__ __launch_bounds__(256) void k_kick(Dev d) {
     PIn p = load_particle(d, i);
     const int key = d.contact_on ? d.key[i] : 0;
     V3<double> F, T;
-    gather(d, i, ROD_TERM_ALL, L, nullptr, p, F, T);
-    kick(d, i, F, T, p, false);
+    gather(d, i, ROD_TERM_ALL, L, Bo, p, F, T);
+    // in place, the next half-kick overwrites v and w; out of place (a recorded
+    // state) the full-step v and w stay with level L
+    const bool apart = d.nx != nullptr;
+    kick(d, i, F, T, p, apart);
     if (d.contact_on) cell_tab(d, L).cnt[key] = 0;
-    advance(d, i, p.b, L + 1, p.x, p.v, p.q, p.w, F, T, p.minv, p.Iinv, false);
+    advance(d, i, p.b, L + 1, p.x, p.v, p.q, p.w, F, T, p.minv, p.Iinv, apart);
     moment_and_cell(d, i, p.q, p.x, p.mb, p.mem, p.rod, L + 1);
     x = p.x;
   }
@@ -358,9 +367,9 @@ hipError_t launch_post(const Dev& d, int mode, int mask, double* Fo, double* To,
   return hipGetLastError();
 }
 
-hipError_t launch_kick(const Dev& d, hipStream_t s, const hipEvent_t* ev) {
+hipError_t launch_kick(const Dev& d, double* Bo, hipStream_t s, const hipEvent_t* ev) {
   const int bs = particle_block(d.n);
-  launch_k(ev, k_kick, dim3(blocks_for(d.i_hi - d.i_lo, bs)), dim3(bs), s, d);
+  launch_k(ev, k_kick, dim3(blocks_for(d.i_hi - d.i_lo, bs)), dim3(bs), s, d, Bo);
   return hipGetLastError();
 }
 

@@ -324,7 +324,7 @@ static int enqueue_steps(rod_ctx* c, int64_t n) {
   TIMED(c, ROD_KERNEL_PRE, launch_pre, d, PRE_STEP, c->s);
   TRY(force_terms(c, d, 0, 1));
   for (int64_t k = 1; k < n; ++k) {
-    TIMED(c, ROD_KERNEL_KICK, launch_kick, d, c->s);
+    TIMED(c, ROD_KERNEL_KICK, launch_kick, d, nullptr, c->s);
     d.lc = 3 - d.lc;
     TRY(force_terms(c, d, 0, 0));
   }

@@ -20,6 +20,8 @@ struct Dev {
   double *x, *v, *q, *w, *F, *T;
   const double* src;       // if set, the pre kernel reads the state from these planes
                            // (x, v, q, w, F, T as in a recorded state) instead of in place
+  double* nx;              // if set, the kick kernel writes the next level's x, v, q, w to
+                           // these planes (same layout) instead of in place
   const double *mb, *field, *extF, *extT;
   // topology and constants
   const uint8_t* bflags;   // bit0: bond (k, k+1); bit1: bond (k-1, k)
@@ -154,7 +156,8 @@ hipError_t launch_post(const Dev& d, int mode, int mask, double* Fout, double* T
 // Second half-kick of the step whose forces are in flight (level step[lc]) fused
 // with the first half-kick, drift and rotation of the next step; writes the next
 // level into step[3 - lc].
-hipError_t launch_kick(const Dev& d, hipStream_t s, const hipEvent_t* ev = nullptr);
+// Bo: where to write the dipole field of the gathered level (or nullptr).
+hipError_t launch_kick(const Dev& d, double* Bo, hipStream_t s, const hipEvent_t* ev = nullptr);
 hipError_t launch_energy(const Dev& d, double* Epart, double* out, hipStream_t s);
 hipError_t launch_contact_pairs(const Dev& d, int* pairs, int cap, int* count, hipStream_t s);
 hipError_t launch_clear_cells(const Dev& d, hipStream_t s);
