@@ -17,7 +17,8 @@
  *     (Methods, "Magnetic interactions"), open boundaries, no cutoff;
  *   - Hookean normal contact k (r_c - r) between pairs closer than r_c that
  *     are not bonded within `exclude_depth` (Methods, "Contact"), found with a
- *     hashed cell list;
+ *     hashed cell list (above 65,536 particles through per-particle candidate
+ *     lists built from it; the selected pairs are the same);
  *   - global viscous damping -c m v, -c I w with the half-step velocities;
  *   - optional constant external forces and torques.
  *
@@ -84,7 +85,7 @@ typedef struct rod_desc {
   double damping;             /* global viscous damping c >= 0 */
   double mu0_4pi;             /* dipole prefactor mu0 / 4 pi */
   double k_contact;           /* contact stiffness */
-  double r_contact;           /* contact distance r_c > 0 (also the cell size) */
+  double r_contact;           /* contact distance r_c > 0 (cells of side r_c, or 1.25 r_c with lists) */
   int32_t dipole_on;          /* 0 / 1 */
   int32_t contact_on;         /* 0 / 1 */
   int32_t exclude_depth;      /* same-rod pairs with |i - j| <= depth never contact (>= 0) */
@@ -181,17 +182,17 @@ int rod_grad(rod_ctx* c, const rod_cotangent* gy, rod_gradients* gx);
  * While enabled (enable != 0), rod_step launches every step eagerly (no graph)
  * and hands each kernel launch a pair of events that the runtime stamps with
  * that kernel's own start and end (hipExtLaunchKernel), so launch gaps are
- * not counted. rod_kernel_times
- * synchronises, adds up the elapsed time of all bracketed launches since the
- * last read per kernel class and resets the sums: ms[ROD_KERNEL_COUNT]
- * (milliseconds) and launches[ROD_KERNEL_COUNT] (host arrays, may be NULL). */
+ * not counted. rod_kernel_times synchronises, adds up the elapsed time of all
+ * timed launches since the last read per kernel class and resets the sums:
+ * ms[ROD_KERNEL_COUNT] (milliseconds) and launches[ROD_KERNEL_COUNT] (host
+ * arrays, may be NULL). */
 enum {
   ROD_KERNEL_PRE = 0,     /* half-kick, drift, quaternion update, dipole rotation, cell list */
   ROD_KERNEL_BOND = 1,    /* bond forces and torques */
   ROD_KERNEL_DIPOLE = 2,  /* all-pairs dipole-dipole */
-  ROD_KERNEL_CONTACT = 3, /* cell-list contact */
+  ROD_KERNEL_CONTACT = 3, /* contact (cell list, or candidate lists) */
   ROD_KERNEL_POST = 4,    /* force gather, Zeeman, damping, second half-kick */
-  ROD_KERNEL_FORCES = 5,  /* dipole (split layout), bond and contact in one launch */
+  ROD_KERNEL_FORCES = 5,  /* dipole, bond and contact in one launch */
   ROD_KERNEL_KICK = 6,    /* post of one step fused with pre of the next */
   ROD_KERNEL_COUNT = 7
 };
@@ -199,10 +200,11 @@ int rod_timing(rod_ctx* c, int32_t enable);
 int rod_kernel_times(rod_ctx* c, double* ms, int64_t* launches);
 
 /* Autotuner for the work layout of the all-pairs dipole kernel (the dominant
- * kernel). Candidates: the small-member layout (1024-thread workgroups of 16
- * targets; members of at most 16384 particles) and the split layout (64
- * targets per workgroup, each member's sources split into enough ranges to
- * give the launch 512 ... 32768 work items). Each candidate is timed with HIP
+ * kernel). Candidates: the small-member layout (one wave per target, four
+ * targets per workgroup; members of at most 16384 particles) and the split
+ * layout (64 targets per workgroup, each member's sources split into enough
+ * ranges to give the launch 512 ... 32768 work items; distinct work lists are
+ * timed once). Each candidate is timed with HIP
  * events on the library's stream over repeated force evaluations at the
  * current state (the state is not changed); the fastest is applied. With a
  * non-NULL cache_path (a JSON-lines file) the choice is looked up first
@@ -219,9 +221,10 @@ int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, char* report
  * consecutive steps of one call the closing half-kick and the next step's
  * opening half-kick, drift and rotation share one launch.
  * ROD_LAUNCH_SEPARATE: as batched, with the three force terms launched as
- * separate kernels and no kick fusion (per-term timing). ROD_LAUNCH_PER_ROD: the plain per-rod
- * loop, every kernel launched once per rod on that rod's particles, eagerly;
- * kept as the baseline the batched form is measured against. Batched and
+ * separate kernels and no kick fusion (per-term timing).
+ * ROD_LAUNCH_PER_ROD: the plain per-rod loop, every kernel launched once per
+ * rod on that rod's particles, eagerly; kept as the baseline the batched form
+ * is measured against. Batched and
  * separate give bitwise identical states; so does the per-rod loop in FP64,
  * while on the mixed path it always takes the exact position differences in
  * the dipole sum and agrees with the batched launch to rounding. */

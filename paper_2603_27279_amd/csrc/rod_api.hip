@@ -284,6 +284,7 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
   b += 8 * (size_t)max_slots * 6 * N + 8 * 4 * N;                               // dipole, contact
   b += 2 * (4 * cells + sizeof(CellSlot) * cells * CELL_CAP + 4 * OVF_CAP) + 4 * N;  // cells
   if (d->contact_on && (long)N >= CONTACT_LANES_MAX_N) b += (4 * NBR_CAP + 4 + 24) * N;  // lists
+  if (d->precision == ROD_MIXED && d->dipole_on) b += 48 * ((N + 63) / 64);  // chunk boxes
   b += 8 * 18 * N + 8 * 9 * M;                                                  // energy
   return b;
 }
