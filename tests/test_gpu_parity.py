@@ -323,3 +323,15 @@ def test_full_size_ensemble_members_trajectory():
         gm = {k: g[k][a:b] for k in ("x", "q", "v", "w", "F", "T")}
         _check_trajectory(gm, oracle.run(sub, 20), oracle.run(sub, 0), "mixed", f"member {m}")
     sim.free()
+
+
+def test_cantilever_full_run_fp64():
+    """The plain FP64 configuration as stated: 20-particle cantilever, 1000 steps."""
+    w = workloads.make("cantilever")
+    sim = RodSim(w, precision="fp64", graph_steps=50)
+    sim.step(1000)
+    sim.sync()
+    g = sim.state()
+    assert g["step"] == 1000
+    _check_trajectory(g, oracle.run(w, 1000), oracle.run(w, 0), "fp64", "cantilever")
+    sim.free()
