@@ -314,9 +314,9 @@ def main():
     roof = None
     small = "small-member" in (tune or "")
     if pairs:
-        # dominant kernel of the timed step: the fused force kernel, or the
-        # small-member dipole kernel where that layout is chosen
-        cls = "dipole" if small or not kt["forces"][1] else "forces"
+        # dominant kernel of the timed step: the fused force kernel (it holds
+        # the dipole work of either layout), else the separate dipole kernel
+        cls = "forces" if kt["forces"][1] else "dipole"
         t_k = 1e-3 * kt[cls][0] / kt[cls][1]
         real = "float" if prec == "mixed" else "double"
         if cls == "forces":

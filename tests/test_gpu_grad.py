@@ -30,8 +30,10 @@ def tip_cotangent(w, xT):
     return g
 
 
-def gpu_grad(w, nsteps, every, prec="fp64", cot_fn=tip_cotangent):
+def gpu_grad(w, nsteps, every, prec="fp64", cot_fn=tip_cotangent, layout=None):
     sim = RodSim(w, precision=prec, tape_every=every, tape_capacity=nsteps)
+    if layout is not None:
+        sim.dipole_layout(*layout)
     sim.tape_begin()
     sim.step(nsteps)
     sim.sync()
@@ -44,8 +46,8 @@ def gpu_grad(w, nsteps, every, prec="fp64", cot_fn=tip_cotangent):
     return out, st, gx
 
 
-def jvp_check(w, nsteps, every, rtol=1e-8, seed=0, blocks=BLOCKS):
-    g, st, gx = gpu_grad(w, nsteps, every)
+def jvp_check(w, nsteps, every, rtol=1e-8, seed=0, blocks=BLOCKS, layout=None):
+    g, st, gx = gpu_grad(w, nsteps, every, layout=layout)
     rng = np.random.default_rng(seed)
     free = w["bc"] == 0
     for blk in blocks + ("all",):
@@ -65,6 +67,15 @@ def jvp_check(w, nsteps, every, rtol=1e-8, seed=0, blocks=BLOCKS):
 def test_grad_matches_oracle_jvp_clamped_rod():
     w = workloads.adjoint_rod(n=16)
     jvp_check(w, 30, 7)
+
+
+@pytest.mark.parametrize("layout", [(0, 64), (0, 4096), (1, 1)])
+def test_grad_every_dipole_layout(layout):
+    """1100 particles: the split layouts give several source ranges per target
+    block (partial sums in several slots), the small-member one none."""
+    w = workloads.adjoint_rod(n=1100)
+    w["x0"] = w["x0"] + np.random.default_rng(3).normal(0, 0.05, w["x0"].shape) * (w["bc"] == 0)[:, None]
+    jvp_check(w, 12, 5, blocks=("m_body", "x0"), layout=layout)
 
 
 def test_grad_field_table_and_gradient_field():

@@ -6,7 +6,7 @@ import pytest
 import oracle
 import workloads
 from paper_2603_27279_amd import RodSim, TERM_ALL, TERM_DIPOLE
-from paper_2603_27279_amd._lib import ROD_E_STATE, RodError
+from paper_2603_27279_amd._lib import ROD_E_INVALID, ROD_E_STATE, RodError
 
 pytestmark = pytest.mark.gpu
 
@@ -64,6 +64,17 @@ def test_autotune_keeps_state_and_caches(tmp_path):
     for k in ("x", "v", "q", "w"):
         np.testing.assert_array_equal(runs[0][k], runs[1][k])
     a.free()
+
+
+def test_dipole_layout_arguments_are_checked():
+    w = workloads.twisted_rod(n=300)
+    sim = RodSim(w, precision="mixed")
+    for bad in ((2, 64), (-2, 64), (0, 0)):
+        with pytest.raises(RodError) as e:
+            sim.dipole_layout(*bad)
+        assert e.value.code == ROD_E_INVALID
+    sim.step(3)
+    sim.free()
 
 
 def test_autotune_refused_while_taping():
