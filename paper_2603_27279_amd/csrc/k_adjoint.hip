@@ -670,7 +670,7 @@ static int recompute(Tape& t, const Dev& d, int precision, const DipWork* work, 
   v.src = t.seg;  // the pre kernel reads step 0 and writes step 1
   ACHK(launch_pre(v, PRE_STEP, s));
   v.src = nullptr;
-  ACHK(launch_forces(v, precision, work, nwork, 1, s));
+  ACHK(launch_force_pass(v, precision, work, nwork, 1, s));
   for (int k = 1; k < len; ++k) {
     double* Sk = t.seg + k * SP;
     v.nx = Sk + SP;
@@ -678,7 +678,7 @@ static int recompute(Tape& t, const Dev& d, int precision, const DipWork* work, 
     Dev w = view(d, Sk + SP, t.a.level);
     w.lc = 3 - v.lc;
     v = w;
-    ACHK(launch_forces(v, precision, work, nwork, 1, s));
+    ACHK(launch_force_pass(v, precision, work, nwork, 1, s));
   }
   ACHK(launch_post(v, POST_KICK, ROD_TERM_ALL, nullptr, nullptr, t.seg + len * SP + 19 * N, s));
   return ROD_OK;
@@ -770,7 +770,7 @@ int adjoint_run(Tape& t, const Dev& d, int precision, const DipWork* work, int n
     ACHK(hipGetLastError());
     Dev v = view(d, S, a.level);
     ACHK(launch_pre(v, PRE_EVAL, s));
-    ACHK(launch_forces(v, precision, work, nwork, 1, s));
+    ACHK(launch_force_pass(v, precision, work, nwork, 1, s));
     ACHK(launch_post(v, POST_EVAL, ROD_TERM_ALL, a.scratch, a.scratch + 3 * N, S + 19 * N, s));
     ATRY(reverse_level(t, d, work, nwork, max_slots, s, S, S, nullptr, 0, ADJ_PREPARE));
     ATRY(reverse_gather(t, d, max_slots, s, S, S, 0, ADJ_PREPARE, *gx));

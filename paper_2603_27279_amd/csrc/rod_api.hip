@@ -293,8 +293,9 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
 // build: rebuild the contact candidate lists of large systems this step.
 static int force_terms(rod_ctx* c, const Dev& d, int want_energy, int build) {
   if (!want_energy && c->launch_mode == ROD_LAUNCH_BATCHED) {
-    TIMED(c, ROD_KERNEL_FORCES, launch_forces, d, c->desc.precision, c->work, c->nwork, build,
-          c->s);
+    TIMED(c, ROD_KERNEL_FORCES, launch_forces, d, c->desc.precision, c->work, c->nwork, c->s);
+    if (c->desc.contact_on && !contact_in_forces(d))
+      TIMED(c, ROD_KERNEL_CONTACT, launch_contact, d, 0, build, c->s);
     return ROD_OK;
   }
   TIMED(c, ROD_KERNEL_BOND, launch_bond, d, c->desc.precision, want_energy, c->s);

@@ -149,8 +149,15 @@ hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int n
 hipError_t launch_contact(const Dev& d, int want_energy, int build, hipStream_t s,
                           const hipEvent_t* ev = nullptr);
 // Dipole, bond and contact forces of a step in one launch.
-hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int nwork, int build,
+// Whether the contact search runs inside the fused force launch (lane-parallel
+// cell search of smaller systems) or in a launch of its own (candidate lists).
+inline bool contact_in_forces(const Dev& d) { return d.n < CONTACT_LANES_MAX_N; }
+hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int nwork,
                          hipStream_t s, const hipEvent_t* ev = nullptr);
+// The whole force pass of a level: launch_forces, and for systems whose contact
+// search is not part of it, launch_contact. build: rebuild the candidate lists.
+hipError_t launch_force_pass(const Dev& d, int precision, const DipWork* work, int nwork,
+                             int build, hipStream_t s);
 hipError_t launch_post(const Dev& d, int mode, int mask, double* Fout, double* Tout,
                        double* Bout, hipStream_t s, const hipEvent_t* ev = nullptr);
 // Second half-kick of the step whose forces are in flight (level step[lc]) fused
