@@ -80,6 +80,13 @@ __device__ __forceinline__ void pair_acc(R dx, R dy, R dz, R mjx, R mjy, R mjz, 
   A.bmz = fma_(rinv3, mjz, A.bmz);
 }
 
+template <class R>
+__device__ __forceinline__ void acc_add(Acc<R>& A, const Acc<R>& B) {
+  A.fx += B.fx; A.fy += B.fy; A.fz += B.fz; A.fm += B.fm;
+  A.bsx += B.bsx; A.bsy += B.bsy; A.bsz += B.bsz;
+  A.bmx += B.bmx; A.bmy += B.bmy; A.bmz += B.bmz;
+}
+
 // Slot values of one target from its pair sums (FP64): force and field.
 __device__ __forceinline__ void write_slot(double* p, long N, long i, double C, const double* F,
                                            double mix, double miy, double miz) {
@@ -103,15 +110,30 @@ __device__ __forceinline__ void tile_pairs(int jb, int je, int jbase, int i, dou
                                            Acc<R>& A) {
   const R m5 = minus5(R(0));
   const Src<R>* p = tile + lane_value(jb);  // per-lane address: one increment per step
-#pragma unroll 2
-  for (int k = 0; k < je - jb; ++k) {
-    const Src<R> e = p[k];
+  // even and odd sources go to separate sums, so consecutive pairs do not wait
+  // on each other's accumulation
+  Acc<R> B{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const int n = je - jb;
+  for (int k = 0; k + 1 < n; k += 2) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const Src<R> e = p[k + u];
+      const R dx = (R)(xi - e.x), dy = (R)(yi - e.y), dz = (R)(zi - e.z);
+      const R r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
+      R rinv = rsq(r2);
+      if (SELF) rinv = (jbase + jb + k + u == i) ? R(0) : rinv;  // the pair (i, i) adds nothing
+      pair_acc(dx, dy, dz, e.mx, e.my, e.mz, mix, miy, miz, rinv, m5, u ? B : A);
+    }
+  }
+  if (n & 1) {
+    const Src<R> e = p[n - 1];
     const R dx = (R)(xi - e.x), dy = (R)(yi - e.y), dz = (R)(zi - e.z);
     const R r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
     R rinv = rsq(r2);
-    if (SELF) rinv = (jbase + jb + k == i) ? R(0) : rinv;   // the pair (i, i) contributes nothing
+    if (SELF) rinv = (jbase + je - 1 == i) ? R(0) : rinv;
     pair_acc(dx, dy, dz, e.mx, e.my, e.mz, mix, miy, miz, rinv, m5, A);
   }
+  acc_add(A, B);
 }
 
 // Far sub-tiles (mixed path). A sub-tile is far from the wave when every
@@ -148,13 +170,24 @@ __device__ __forceinline__ bool far_tile_pairs(const Dev& d, int jg0, int jg1, i
   const float m5 = minus5(0.0f);
   const float4* pr = rel + lane_value(0);
   const Src<float>* p = tile + lane_value(jb);
-#pragma unroll 2
-  for (int k = 0; k < n; ++k) {
-    const float4 r = pr[k];
+  Acc<float> B{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // odd sources (see tile_pairs)
+  for (int k = 0; k + 1 < n; k += 2) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const float4 r = pr[k + u];
+      const float dx = xr - r.x, dy = yr - r.y, dz = zr - r.z;
+      const float r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
+      pair_acc(dx, dy, dz, p[k + u].mx, p[k + u].my, p[k + u].mz, mix, miy, miz, rsq(r2), m5,
+               u ? B : A);
+    }
+  }
+  if (n & 1) {
+    const float4 r = pr[n - 1];
     const float dx = xr - r.x, dy = yr - r.y, dz = zr - r.z;
     const float r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
-    pair_acc(dx, dy, dz, p[k].mx, p[k].my, p[k].mz, mix, miy, miz, rsq(r2), m5, A);
+    pair_acc(dx, dy, dz, p[n - 1].mx, p[n - 1].my, p[n - 1].mz, mix, miy, miz, rsq(r2), m5, A);
   }
+  acc_add(A, B);
   return true;
 }
 
