@@ -187,6 +187,7 @@ def hbm_microbench(sizes, steps=10):
         gbs = units * b / (us * 1e-6) / 1e9
         return {"us": us, "bytes_per_unit": b, "GB_s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
 
+    copy = copy_bandwidth()
     for side in sizes:
         w = workloads.rod_array(grid=(side, side), n_per_rod=1024, dipole_on=False)
         n, R = w["n"], len(w["rod_offset"]) - 1
@@ -213,9 +214,35 @@ def hbm_microbench(sizes, steps=10):
         kt = sim.kernel_times()
         sim.timing(False)
         res["kick"] = entry(1e3 * kt["kick"][0] / kt["kick"][1], n, kick_bytes(0))
+        for k in ("bond", "pre", "contact", "kick"):
+            res[k]["frac_copy"] = res[k]["GB_s"] / copy["GB_s"]
+        res["plain_copy"] = copy
         sim.free()
         out.append(res)
     return out
+
+
+def copy_bandwidth(mib=512, reps=20):
+    """What a plain device-to-device copy reaches on this GPU (bytes read plus
+    bytes written per second, median of `reps` launches): the practical ceiling
+    the memory-bound kernels are compared with, besides the vendor peak."""
+    import torch
+    n = mib * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e3)
+    us = sorted(times)[len(times) // 2]
+    gbs = 2 * 8 * n / (us * 1e-6) / 1e9
+    del a, b
+    return {"MiB_each_way": mib, "us": us, "GB_s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
 
 
 def copy_calibration():
