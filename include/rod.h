@@ -192,7 +192,7 @@ enum {
   ROD_KERNEL_DIPOLE = 2,  /* all-pairs dipole-dipole */
   ROD_KERNEL_CONTACT = 3, /* contact (cell list, or candidate lists) */
   ROD_KERNEL_POST = 4,    /* force gather, Zeeman, damping, second half-kick */
-  ROD_KERNEL_FORCES = 5,  /* dipole, bond and contact in one launch */
+  ROD_KERNEL_FORCES = 5,  /* dipole, bond and (below 65536 particles) contact in one launch */
   ROD_KERNEL_KICK = 6,    /* post of one step fused with pre of the next */
   ROD_KERNEL_COUNT = 7
 };
@@ -217,9 +217,11 @@ int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, char* report
 
 /* Launch mode of rod_step. ROD_LAUNCH_BATCHED (default): each kernel serves all
  * rods and members in one launch (graph-captured when graph_steps > 0); the
- * dipole, bond and contact forces of a step share one launch, and between two
- * consecutive steps of one call the closing half-kick and the next step's
- * opening half-kick, drift and rotation share one launch.
+ * dipole and bond forces of a step share one launch, and so does contact below
+ * 65536 particles (above, the candidate-list search is a launch of its own,
+ * timed as ROD_KERNEL_CONTACT); between two consecutive steps of one call the
+ * closing half-kick and the next step's opening half-kick, drift and rotation
+ * share one launch.
  * ROD_LAUNCH_SEPARATE: as batched, with the three force terms launched as
  * separate kernels and no kick fusion (per-term timing).
  * ROD_LAUNCH_PER_ROD: the plain per-rod loop, every kernel launched once per
