@@ -268,7 +268,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="twisted_rod", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
-    ap.add_argument("--graph-steps", type=int, default=50)
+    ap.add_argument("--graph-steps", type=int, default=200)
     ap.add_argument("--timing-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

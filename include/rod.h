@@ -185,7 +185,9 @@ int rod_grad(rod_ctx* c, const rod_cotangent* gy, rod_gradients* gx);
  * not counted. rod_kernel_times synchronises, adds up the elapsed time of all
  * timed launches since the last read per kernel class and resets the sums:
  * ms[ROD_KERNEL_COUNT] (milliseconds) and launches[ROD_KERNEL_COUNT] (host
- * arrays, may be NULL). */
+ * arrays, may be NULL). The library holds at most 4096 pending event pairs;
+ * beyond that a timed launch first synchronises the stream and folds the
+ * pending times into the sums. */
 enum {
   ROD_KERNEL_PRE = 0,     /* half-kick, drift, quaternion update, dipole rotation, cell list */
   ROD_KERNEL_BOND = 1,    /* bond forces and torques */

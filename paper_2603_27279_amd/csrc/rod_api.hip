@@ -84,11 +84,17 @@ struct rod_ctx {
   int64_t t_cnt[ROD_KERNEL_COUNT] = {0};
 };
 
+static int timing_collect(rod_ctx* c);
+constexpr int EV_PAIRS_MAX = 4096;  // pending pairs before they are folded into the sums
+
 // Event pair that the next launch of kernel class `kid` stamps with its own
-// start and end (null when timing is off).
+// start and end (null when timing is off). The pool stays bounded: once
+// EV_PAIRS_MAX pairs are pending, the stream is synchronised and their times
+// are added to the per-class sums.
 static int timing_events(rod_ctx* c, int kid, const hipEvent_t** ev) {
   *ev = nullptr;
   if (!c->timing) return ROD_OK;
+  if (c->ev_used >= EV_PAIRS_MAX) TRY(timing_collect(c));
   while ((int)c->ev_pool.size() < 2 * (c->ev_used + 1)) {
     hipEvent_t e;
     HIPC(hipEventCreate(&e));

@@ -172,6 +172,22 @@ def test_timing_mode_runs_the_same_steps():
     a.free(); b.free()
 
 
+def test_timing_counts_survive_the_event_pool_bound():
+    """More timed launches than the library keeps pending event pairs for: the
+    sums are folded on the way and every launch is still counted."""
+    w = _twisted_small()
+    a = RodSim(w, precision="mixed")
+    a.dipole_layout(0, 64)
+    a.timing(True)
+    a.step(2500)  # 5000 timed launches
+    kt = a.kernel_times()
+    a.timing(False)
+    assert kt["pre"][1] == 1 and kt["post"][1] == 1
+    assert kt["forces"][1] == 2500 and kt["kick"][1] == 2499
+    assert all(ms > 0 for ms, c in kt.values() if c)
+    a.free()
+
+
 def _dense_large(members=70, rods=10, length=100, seed=12):
     """70,000 particles (above the size where contact switches to candidate
     lists): per member ten parallel rods 1.05 apart with random velocities, so
