@@ -26,7 +26,7 @@ namespace rodmx {
 
 template <class R> __device__ __forceinline__ R rsq(R a);
 template <> __device__ __forceinline__ float rsq(float a) { return __builtin_amdgcn_rsqf(a); }
-template <> __device__ __forceinline__ double rsq(double a) { return 1.0 / sqrt(a); }
+template <> __device__ __forceinline__ double rsq(double a) { return rsqrt_nr(a); }
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 

@@ -169,7 +169,7 @@ __device__ __forceinline__ void adj_bond(const Dev& d, const Adj& a, const doubl
 // Gradients of Phi = grad_r U . g + grad_a U . h with respect to r, a and b.
 __device__ void phi_grad(V3<double> r, V3<double> am, V3<double> bm, V3<double> g, V3<double> hv,
                          V3<double>& dr, V3<double>& da, V3<double>& db) {
-  const double u = 1.0 / ::sqrt(dot(r, r));
+  const double u = rsqrt_nr(dot(r, r));
   const double u2 = u * u, u3 = u2 * u, u5 = u3 * u2, u7 = u5 * u2, u9 = u7 * u2;
   const double A = dot(am, bm), P = dot(am, r), Q = dot(bm, r), G = dot(r, g);
   const double Ga = dot(am, g), Gb = dot(bm, g), Hb = dot(bm, hv), Hr = dot(r, hv);

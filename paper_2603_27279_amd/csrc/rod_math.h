@@ -41,6 +41,19 @@ template <class R> __device__ __forceinline__ Q4<R> qadd(Q4<R> a, Q4<R> b) {
 }
 
 __device__ __forceinline__ double rsqrt_ieee(double a) { return 1.0 / sqrt(a); }
+
+// 1/sqrt(a) for a positive normal double: the hardware estimate (v_rsq_f64,
+// about 23 correct bits) refined by two Newton steps y <- y (3/2 - (a/2) y^2),
+// each of which doubles the correct bits; the result is within a few ulp. The
+// quotient of a correctly rounded square root costs about three times as many
+// instructions (scaled square root, then a full division).
+__device__ __forceinline__ double rsqrt_nr(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  const double h = 0.5 * a;
+  y = y * __builtin_fma(-h, y * y, 1.5);
+  y = y * __builtin_fma(-h, y * y, 1.5);
+  return y;
+}
 __device__ __forceinline__ float rsqrt_ieee(float a) { return 1.0f / sqrtf(a); }
 
 template <class R> __device__ __forceinline__ Q4<R> qnormalize(Q4<R> a) {
