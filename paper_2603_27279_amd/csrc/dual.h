@@ -40,7 +40,7 @@ __device__ __forceinline__ DD sqrt(DD a) {
   const double s = ::sqrt(a.v);
   return DD(s, s > 0.0 ? a.d / (2.0 * s) : 0.0);
 }
-__device__ __forceinline__ DD rsqrt_ieee(DD a) { return 1.0 / sqrt(a); }
+__device__ __forceinline__ DD rsqrt_norm(DD a) { return 1.0 / sqrt(a); }
 __device__ __forceinline__ DD atan2(DD y, DD x) {
   const double den = x.v * x.v + y.v * y.v;
   return DD(::atan2(y.v, x.v), den > 0.0 ? (x.v * y.d - y.v * x.d) / den : 0.0);

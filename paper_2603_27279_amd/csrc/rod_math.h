@@ -40,8 +40,6 @@ template <class R> __device__ __forceinline__ Q4<R> qadd(Q4<R> a, Q4<R> b) {
   return {a.w + b.w, a.x + b.x, a.y + b.y, a.z + b.z};
 }
 
-__device__ __forceinline__ double rsqrt_ieee(double a) { return 1.0 / sqrt(a); }
-
 // 1/sqrt(a) for a positive normal double: the hardware estimate (v_rsq_f64,
 // about 23 correct bits) refined by two Newton steps y <- y (3/2 - (a/2) y^2),
 // each of which doubles the correct bits; the result is within a few ulp. The
@@ -54,10 +52,13 @@ __device__ __forceinline__ double rsqrt_nr(double a) {
   y = y * __builtin_fma(-h, y * y, 1.5);
   return y;
 }
-__device__ __forceinline__ float rsqrt_ieee(float a) { return 1.0f / sqrtf(a); }
+__device__ __forceinline__ double rsqrt_norm(double a) { return rsqrt_nr(a); }
+__device__ __forceinline__ float rsqrt_norm(float a) { return 1.0f / sqrtf(a); }
 
+// a / |a|; in FP64 with the refined reciprocal square root (the integrator
+// renormalises four times per step, on the step's critical path).
 template <class R> __device__ __forceinline__ Q4<R> qnormalize(Q4<R> a) {
-  return qscale(rsqrt_ieee(qdot(a, a)), a);
+  return qscale(rsqrt_norm(qdot(a, a)), a);
 }
 
 // q v q* for a unit quaternion: v + 2 w (u x v) + 2 u x (u x v), u = vector part.
