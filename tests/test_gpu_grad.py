@@ -46,7 +46,7 @@ def gpu_grad(w, nsteps, every, prec="fp64", cot_fn=tip_cotangent, layout=None):
     return out, st, gx
 
 
-def jvp_check(w, nsteps, every, rtol=1e-8, seed=0, blocks=BLOCKS, layout=None):
+def jvp_check(w, nsteps, every, rtol=1e-10, seed=0, blocks=BLOCKS, layout=None):
     g, st, gx = gpu_grad(w, nsteps, every, layout=layout)
     rng = np.random.default_rng(seed)
     free = w["bc"] == 0
@@ -118,7 +118,7 @@ def test_grad_with_contact_and_driven_end():
     _, dT = oracle.run_jvp(w, 25, tan)
     ref = float(np.sum(gx * dT["x"]))
     got = float(sum(np.sum(g[k] * tan[WKEY[k]]) for k in BLOCKS))
-    assert abs(got - ref) <= 1e-8 * abs(ref), (got, ref)
+    assert abs(got - ref) <= 1e-10 * abs(ref), (got, ref)
 
 
 def test_grad_cotangent_of_every_state_block():
@@ -138,7 +138,7 @@ def test_grad_cotangent_of_every_state_block():
     ref = float(np.sum(cx * dT["x"]) + np.sum(cv * dT["v"]) + np.sum(cq * dT["q"]) +
                 np.sum(cw * dT["w"]))
     got = float(sum(np.sum(g[k] * tan[WKEY[k]]) for k in BLOCKS))
-    assert abs(got - ref) <= 1e-8 * abs(ref), (got, ref)
+    assert abs(got - ref) <= 1e-10 * abs(ref), (got, ref)
 
 
 def test_grad_needs_a_tape():
@@ -254,4 +254,4 @@ def test_autograd_function_matches_rod_grad():
     ref = float(np.sum(gxT * dT["x"]) + 0.2 * np.sum(stT["w"] * dT["w"]))
     got = sum(float(np.sum(params[k].grad.cpu().numpy().T * tan[k])) for k in params)
     got += float(np.sum(field.grad.cpu().numpy() * tan["field"]))
-    assert abs(got - ref) <= 1e-8 * abs(ref), (got, ref)
+    assert abs(got - ref) <= 1e-10 * abs(ref), (got, ref)
