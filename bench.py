@@ -163,14 +163,14 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E (vendor figure)
 #   contact (per particle): own position (24), list entry (8), force out (24)
 #   pre (per particle): state x v q w F T and m_body, inverse mass and inertia,
 #     ids (221 in); x v q w, m in FP64 and FP32, cell key and entry (180 out)
-#   kick (per particle): bond outputs of its bond (72), dipole slots (48 each),
-#     contact force, state and constants (318 + 48 S in); F T x v w q, m twice,
-#     cell key and entry (228 out)
+#   kick (per particle): bond outputs of its bond (72), dipole slots (24 each on
+#     the mixed path, 48 in FP64), contact force, state and constants (318 + slots
+#     in); F T x v w q, m twice, cell key and entry (228 out)
 BYTES = {"bond": 165.0, "contact": 56.0, "pre": 401.0}
 
 
-def kick_bytes(slots):
-    return 318.0 + 48.0 * slots + 228.0
+def kick_bytes(slots, slot_bytes=24.0):
+    return 318.0 + slot_bytes * slots + 228.0
 
 
 def hbm_microbench(sizes, steps=10):

@@ -87,16 +87,27 @@ __device__ __forceinline__ void acc_add(Acc<R>& A, const Acc<R>& B) {
   A.bmx += B.bmx; A.bmy += B.bmy; A.bmz += B.bmz;
 }
 
-// Slot values of one target from its pair sums (FP64): force and field.
-__device__ __forceinline__ void write_slot(double* p, long N, long i, double C, const double* F,
+// Slot values of one target from its pair sums (FP64): force and field, stored
+// in the work item's slot. The mixed path stores them in FP32: they are sums of
+// FP32 pair terms, and the particle kernel adds the slots in FP64; this halves
+// the bytes and registers of that sum, whose loads then travel in one batch.
+template <class R> __device__ __forceinline__ R* slot_base(const Dev& d, int slot);
+template <> __device__ __forceinline__ float* slot_base(const Dev& d, int slot) {
+  return d.dslotf + (long)slot * 6 * d.n;
+}
+template <> __device__ __forceinline__ double* slot_base(const Dev& d, int slot) {
+  return d.dpart + (long)slot * 6 * d.n;
+}
+template <class T>
+__device__ __forceinline__ void write_slot(T* p, long N, long i, double C, const double* F,
                                            double mix, double miy, double miz) {
   const double C3 = 3.0 * C;
-  p[i] = C3 * (F[0] + F[3] * mix);
-  p[N + i] = C3 * (F[1] + F[3] * miy);
-  p[2 * N + i] = C3 * (F[2] + F[3] * miz);
-  p[3 * N + i] = C * (3.0 * F[4] - F[7]);
-  p[4 * N + i] = C * (3.0 * F[5] - F[8]);
-  p[5 * N + i] = C * (3.0 * F[6] - F[9]);
+  p[i] = (T)(C3 * (F[0] + F[3] * mix));
+  p[N + i] = (T)(C3 * (F[1] + F[3] * miy));
+  p[2 * N + i] = (T)(C3 * (F[2] + F[3] * miz));
+  p[3 * N + i] = (T)(C * (3.0 * F[4] - F[7]));
+  p[4 * N + i] = (T)(C * (3.0 * F[5] - F[8]));
+  p[5 * N + i] = (T)(C * (3.0 * F[6] - F[9]));
 }
 
 // One staged source: position (FP64) and moment, contiguous so that a single
@@ -257,7 +268,7 @@ __device__ __forceinline__ void dipole_item(const Dev& d, const DipWork& wk, Dip
   if (wave == 0 && act) {
     for (int k = 0; k < NACC; ++k)
       F[k] = ((sm.red[0][k][lane] + sm.red[1][k][lane]) + sm.red[2][k][lane]) + sm.red[3][k][lane];
-    write_slot(d.dpart + (long)wk.slot * 6 * N, N, i, d.C, F, mix, miy, miz);
+    write_slot(slot_base<R>(d, wk.slot), N, i, d.C, F, mix, miy, miz);
   }
 }
 
@@ -304,8 +315,7 @@ __device__ __forceinline__ void dipole_small_item(const Dev& d, const DipWork& w
   for (int k = 0; k < NACC; ++k)
     for (int o = 32; o > 0; o >>= 1) F[k] += __shfl_xor(F[k], o);
   if (lane == 0)
-    write_slot(d.dpart + (long)wk.slot * 6 * N, N, i, d.C, F, (double)mix, (double)miy,
-               (double)miz);
+    write_slot(slot_base<R>(d, wk.slot), N, i, d.C, F, (double)mix, (double)miy, (double)miz);
 }
 
 }  // namespace rodmx

@@ -152,12 +152,50 @@ __device__ __forceinline__ PIn load_particle(const Dev& d, long i) {
           ld4(d.q, N, i), d.minv[i], d.Iinv[i], d.bc[i], d.mem[i], d.rod[i]};
 }
 
+// Dipole force and field of particle i: its S slots added in slot order, in
+// FP64, B slots per round trip (FP32 slots of the mixed path: 16; FP64: 8).
+// Slots past the member's own count hold zeros.
+template <class T, int B>
+__device__ __forceinline__ void slot_sum(const T* dp, long N, int S, long i, V3<double>& Fd,
+                                         V3<double>& Bd) {
+  for (int s0 = 0; s0 < S; s0 += B) {
+    T v[B][6];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const T* q = dp + (long)(s0 + k) * 6 * N;
+      if (s0 + k < S)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[k][c] = q[c * N + i];
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if (s0 + k < S) {
+        Fd = Fd + V3<double>{(double)v[k][0], (double)v[k][1], (double)v[k][2]};
+        Bd = Bd + V3<double>{(double)v[k][3], (double)v[k][4], (double)v[k][5]};
+      }
+  }
+}
+
+// The dipole force and field of particle i when `mask` asks for them (zero
+// otherwise). Called first in the particle kernels: the slot loads are the
+// longest chain of the gather, and few other values are live yet.
+__device__ __forceinline__ void dipole_sums(const Dev& d, long i, int mask, V3<double>& Fd,
+                                            V3<double>& Bd) {
+  Fd = V3<double>{0.0, 0.0, 0.0};
+  Bd = V3<double>{0.0, 0.0, 0.0};
+  if (!((mask & 2) && d.dipole_on)) return;
+  if (d.dslotf) slot_sum<float, 8>(d.dslotf, d.n, d.max_slots, i, Fd, Bd);
+  else slot_sum<double, 8>(d.dpart, d.n, d.max_slots, i, Fd, Bd);
+}
+
 // Total force and torque on particle i from the terms in `mask` at level lvl
-// (bond, dipole slots, Zeeman, contact, damping, external); the dipole field
-// is written to Bo when given. Loads are unconditional where the index is
-// valid, so they are all in flight together.
+// (bond, dipole, Zeeman, contact, damping, external), with the dipole force Fd
+// and field Bd from dipole_sums; the dipole field is written to Bo when given.
+// Loads are unconditional where the index is valid, so they are all in flight
+// together.
 __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long lvl, double* Bo,
-                                       const PIn& p, V3<double>& F, V3<double>& T) {
+                                       const PIn& p, V3<double> Fd, V3<double> Bd, V3<double>& F,
+                                       V3<double>& T) {
   const long N = d.n;
   const long im = i > 0 ? i - 1 : 0;
   const uint8_t bf = d.bflags[i];
@@ -178,27 +216,7 @@ __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long
     }
   }
   const V3<double> m = p.m;
-  V3<double> Bd{0.0, 0.0, 0.0};
-  if ((mask & 2) && d.dipole_on) {  // dipole-dipole: sum of the partial slots, torque m x B_dip
-    // Slots are added in slot order, eight per round trip; slots past the
-    // member's own count hold zeros.
-    V3<double> Fd{0.0, 0.0, 0.0};
-    const int S = d.max_slots;
-    for (int s0 = 0; s0 < S; s0 += 8) {
-      double v[8][6];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const double* q = d.dpart + (long)(s0 + k) * 6 * N;
-        if (s0 + k < S)
-          for (int c = 0; c < 6; ++c) v[k][c] = q[c * N + i];
-      }
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (s0 + k < S) {
-          Fd = Fd + V3<double>{v[k][0], v[k][1], v[k][2]};
-          Bd = Bd + V3<double>{v[k][3], v[k][4], v[k][5]};
-        }
-    }
+  if ((mask & 2) && d.dipole_on) {  // dipole-dipole: force and torque m x B_dip
     F = F + Fd;
     T = T + cross(m, Bd);
   }
@@ -260,8 +278,10 @@ __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double*
   if (i >= d.i_hi) return;
   PIn p = load_particle(d, i);
   const int key = d.contact_on ? d.key[i] : 0;
+  V3<double> Fd, Bd;
+  dipole_sums(d, i, mask, Fd, Bd);
   V3<double> F, T;
-  gather(d, i, mask, lvl, Bo, p, F, T);
+  gather(d, i, mask, lvl, Bo, p, Fd, Bd, F, T);
   if (mode == POST_EVAL) {
     st3(Fo, N, i, F);
     st3(To, N, i, T);
@@ -292,8 +312,10 @@ __global__ __launch_bounds__(256) void k_kick(Dev d, double* Bo) {
   if (valid) {
     PIn p = load_particle(d, i);
     const int key = d.contact_on ? d.key[i] : 0;
+    V3<double> Fd, Bd;
+    dipole_sums(d, i, ROD_TERM_ALL, Fd, Bd);
     V3<double> F, T;
-    gather(d, i, ROD_TERM_ALL, L, Bo, p, F, T);
+    gather(d, i, ROD_TERM_ALL, L, Bo, p, Fd, Bd, F, T);
     // in place, the next half-kick overwrites v and w; out of place (a recorded
     // state) the full-step v and w stay with level L
     const bool apart = d.nx != nullptr;

@@ -278,6 +278,9 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
   HIPC(hipMemcpy(ms, mslots.data(), M * sizeof(int), hipMemcpyHostToDevice));
   c->d.mslots = ms;
   TRY(palloc(c, &c->d.dpart, (size_t)max_slots * 6 * N));
+  c->d.dslotf = nullptr;
+  if (c->desc.precision == ROD_MIXED && c->desc.dipole_on)
+    TRY(palloc(c, &c->d.dslotf, (size_t)max_slots * 6 * N));
   return ROD_OK;
 }
 
@@ -288,6 +291,7 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
   b += N * (1 + 4 + 4 + 1) + 8 * N * 4 + 8 * N * 4 + 8 * R * 4 + 4 * M * 3;  // topology
   b += 8 * 3 * N + 4 * 3 * N + 8 * 9 * N + 8 * 4 * N;                         // mu, bonds
   b += 8 * (size_t)max_slots * 6 * N + 8 * 4 * N;                               // dipole, contact
+  if (d->precision == ROD_MIXED && d->dipole_on) b += 4 * (size_t)max_slots * 6 * N;  // FP32 slots
   b += 2 * (4 * cells + sizeof(CellSlot) * cells * CELL_CAP + 4 * OVF_CAP) + 4 * N;  // cells
   if (d->contact_on && (long)N >= CONTACT_LANES_MAX_N) b += (4 * NBR_CAP + 4 + 24) * N;  // lists
   if (d->precision == ROD_MIXED && d->dipole_on) b += 48 * ((N + 63) / 64);  // chunk boxes

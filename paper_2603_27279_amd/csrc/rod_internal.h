@@ -38,6 +38,8 @@ struct Dev {
   double *bF, *bTs, *bTbt; // [3N] per-bond outputs (index = first particle)
   double* bE;              // [4N] per-bond energies (energy evaluation only)
   double* dpart;           // [S][6][N] dipole partial sums (F then B), one slot per j range
+                           // (FP64 path; the reverse pass keeps its cotangent sums here)
+  float* dslotf;           // [S][6][N] the same partial sums on the mixed path (FP32), else null
   const int* mslots;       // [M]: j ranges (partial slots) of each member
   int max_slots;           // largest entry of mslots; slots a member does not use stay zero
   double* cF;              // [3N] contact force
