@@ -310,7 +310,10 @@ def main():
     if not args.no_autotune:
         report = sim.autotune(args.tune_cache)
         tune = report.strip().splitlines()[-1]
-    sim.step(args.warmup)
+    # the warm-up holds at least one whole graph, so that its capture is never
+    # part of the timed steps
+    warmup = max(args.warmup, args.graph_steps)
+    sim.step(warmup)
     sim.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -397,6 +400,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_steps_run": warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
