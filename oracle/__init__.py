@@ -46,6 +46,7 @@ class _System(C.Structure):
         ("dt", C.c_double), ("damping", C.c_double), ("mu0_4pi", C.c_double),
         ("k_contact", C.c_double), ("r_contact", C.c_double),
         ("dipole_on", C.c_int32), ("contact_on", C.c_int32), ("exclude_depth", C.c_int32),
+        ("bond_damping", C.c_void_p),
     ]
 
 
@@ -84,6 +85,7 @@ class System:
             field=_f64(w["field"]),
             ext_force=None if w.get("ext_force") is None else _f64(w["ext_force"]),
             ext_torque=None if w.get("ext_torque") is None else _f64(w["ext_torque"]),
+            bond_damping=None if w.get("bond_damping") is None else _f64(w["bond_damping"]),
         )
         self.keep = keep
         s = _System()
@@ -104,6 +106,7 @@ class System:
         s.k_contact = float(w["k_contact"]); s.r_contact = float(w["r_contact"])
         s.dipole_on = int(bool(w["dipole_on"])); s.contact_on = int(bool(w["contact_on"]))
         s.exclude_depth = int(w["exclude_depth"])
+        s.bond_damping = _p(keep["bond_damping"])
         self.s = s
 
     @property
@@ -146,8 +149,18 @@ def bond_single(x1, x2, q1, q2, rref, K):
     return F, Ts, Tbt, e
 
 
-def forces(w, x, q, v=None, om=None, mbody=None, step=0, mask=ALL, with_field=False):
-    """Force and torque [N,3] of the terms in ``mask`` at the given state."""
+def has_bond_damping(w):
+    g = w.get("bond_damping")
+    return g is not None and bool(np.any(np.asarray(g) != 0))
+
+
+def forces(w, x, q, v=None, om=None, mbody=None, step=0, mask=ALL, with_field=False,
+           hist=None, hist_out=False):
+    """Force and torque [N,3] of the terms in ``mask`` at the given state.
+
+    With bond damping, ``hist`` holds the measures [B, 5] (shear angle, twist,
+    bend vector in C') of the previous level (None: no rates), and
+    ``hist_out=True`` also returns this level's measures."""
     lib = _load()
     sy = System(w)
     n = sy.n
@@ -156,9 +169,16 @@ def forces(w, x, q, v=None, om=None, mbody=None, step=0, mask=ALL, with_field=Fa
     om = np.zeros((n, 3)) if om is None else _f64(om, (n, 3))
     mb = _f64(w["m_body"] if mbody is None else mbody, (n, 3))
     F, T, B = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 3))
+    nb = max(1, n)
+    hin = None if hist is None else _f64(hist)
+    hout = np.zeros((nb, 5))
     lib.orc_forces(sy.ref, _p(x), _p(q), _p(v), _p(om), _p(mb), _p(sy.field),
-                   C.c_int64(step), C.c_int32(mask), _p(F), _p(T), _p(B))
-    return (F, T, B) if with_field else (F, T)
+                   C.c_int64(step), C.c_int32(mask), _p(F), _p(T), _p(B), _p(hin), _p(hout))
+    out = (F, T, B) if with_field else (F, T)
+    if hist_out:
+        nbond = len(bonds(w)[0])
+        out = out + (hout[:nbond].copy(),)
+    return out
 
 
 def energy(w, x, q, v=None, om=None, mbody=None, step=0):
@@ -203,10 +223,12 @@ def run(w, nsteps, state=None, step0=0, mbody=None):
         st = {k: (np.array(v, dtype=np.float64, copy=True) if k != "step" else v)
               for k, v in state.items()}
         prepared = 1
+    if "hist" not in st:  # bond damping measures of the last evaluation
+        st["hist"] = np.zeros((max(1, n), 5))
     mb = _f64(w["m_body"] if mbody is None else mbody, (n, 3))
     lib.orc_run(sy.ref, _p(st["x"]), _p(st["v"]), _p(st["q"]), _p(st["w"]), _p(st["F"]),
                 _p(st["T"]), _p(mb), _p(sy.field), C.c_int64(int(st["step"])),
-                C.c_int64(int(nsteps)), C.c_int32(prepared))
+                C.c_int64(int(nsteps)), C.c_int32(prepared), _p(st["hist"]))
     st["step"] = int(st["step"]) + int(nsteps)
     return st
 
@@ -215,7 +237,10 @@ def run_jvp(w, nsteps, tangent, step0=0):
     """Forward-mode derivative of ``run`` from the raw initial inputs.
 
     ``tangent`` maps any of x0, v0, q0, w0, m_body, field to a direction array.
-    Returns (final state dict, final tangent dict) with keys x, v, q, w."""
+    Returns (final state dict, final tangent dict) with keys x, v, q, w.
+    Bond damping is not differentiated (its rates depend on stored history)."""
+    if has_bond_damping(w):
+        raise NotImplementedError("the forward-mode run does not differentiate bond damping")
     lib = _load()
     sy = System(w)
     n = sy.n

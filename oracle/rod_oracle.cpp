@@ -23,6 +23,9 @@
 //   Zeeman / dipoles  Methods "Magnetic interactions".
 //   contact           Methods "Contact" (Hookean normal law: the workload's
 //                     stated simplification of the paper's Hertz-Mindlin).
+//   bond damping      Methods "Damping": radial term from the relative
+//                     velocity along the bond axis; shear, twist and bend terms
+//                     from finite-difference rates of the stored measures.
 //   integrator        SI "Equations of motion" (velocity Verlet, Richardson
 //                     quaternion update, renormalisation after each substep,
 //                     solid-sphere inertia).
@@ -45,6 +48,7 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#include <type_traits>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -119,6 +123,17 @@ struct Bond {
   int i, j;             // particle 1 = i, particle 2 = j
   V3<double> rref;      // reference bond vector r_i (global = reference C frame)
   double Kr, Ks, Kt, Kb;
+  double gr = 0, gs = 0, gt = 0, gb = 0;  // damping factors (Methods "Damping")
+};
+
+// Bond damping of one evaluation: the deformation measures of the previous
+// time level (gamma, psi, theta-vector in C'; null: no rates yet), where the
+// current ones go, the relative velocity v2 - v1 and the time step.
+struct Damp {
+  const double* hprev;
+  double* hnow;
+  V3<double> dv;
+  double dt;
 };
 
 struct Model {
@@ -135,6 +150,7 @@ struct Model {
   const double* ext_force = nullptr;
   const double* ext_torque = nullptr;
   int field_len = 1;
+  bool bond_damp = false;  // some bond has a non-zero damping factor
 };
 
 }  // namespace orc
@@ -156,6 +172,7 @@ struct orc_system {
   const double* ext_torque;    // [N][3] or NULL
   double dt, damping, mu0_4pi, k_contact, r_contact;
   int32_t dipole_on, contact_on, exclude_depth;
+  const double* bond_damping;  // [R][4] g_r, g_s, g_t, g_b, or NULL
 };
 
 }  // extern "C"
@@ -207,6 +224,11 @@ static Model build_model(const orc_system* s) {
                   s->x_ref[3 * (p + 1) + 1] - s->x_ref[3 * p + 1],
                   s->x_ref[3 * (p + 1) + 2] - s->x_ref[3 * p + 2]};
         spring_constants(d, E, nu, norm(b.rref), b);
+        if (s->bond_damping) {
+          b.gr = s->bond_damping[4 * r + 0]; b.gs = s->bond_damping[4 * r + 1];
+          b.gt = s->bond_damping[4 * r + 2]; b.gb = s->bond_damping[4 * r + 3];
+          m.bond_damp = m.bond_damp || b.gr != 0 || b.gs != 0 || b.gt != 0 || b.gb != 0;
+        }
         m.bonds.push_back(b);
       }
     }
@@ -229,9 +251,11 @@ static Model build_model(const orc_system* s) {
 //   Ts  = tau_s (both particles),
 //   Tbt = tau_b + tau_t acting on particle 1 (particle 2 receives -Tbt),
 //   e   = the four terms of eq:total-energy.
+// With `dmp`, the damping terms of Methods "Damping" are added and the current
+// measures are stored (see Damp).
 template <class T>
 void bond_eval(V3<T> x1, V3<T> x2, Q4<T> q1, Q4<T> q2, const Bond& bd,
-               V3<T>& F, V3<T>& Ts, V3<T>& Tbt, T e[4]) {
+               V3<T>& F, V3<T>& Ts, V3<T>& Tbt, T e[4], const Damp* dmp = nullptr) {
   const T zero(0.0), one(1.0), half(0.5);
   // Bond vectors r_f (current) and r_i (reference), global frame.
   V3<T> rf = x2 - x1;
@@ -247,8 +271,11 @@ void bond_eval(V3<T> x1, V3<T> x2, Q4<T> q1, Q4<T> q2, const Bond& bd,
   T r = norm(rho);
   V3<T> rh = (one / r) * rho;
 
-  // Radial force (eq:bpm-fr), in C.
-  V3<T> fr = (T(bd.Kr) * (r - T(r0))) * rh;
+  // Radial force (eq:bpm-fr), in C; radial damping adds g_r times the relative
+  // velocity along the bond axis, (v2 - v1) . r_f-hat = (q_C* (v2 - v1) q_C) . r-hat.
+  T frad = T(bd.Kr) * (r - T(r0));
+  if (dmp) frad = frad + T(bd.gr) * dot(qrot(qconj(qc), lift<T>(dmp->dv)), rh);
+  V3<T> fr = frad * rh;
 
   // Shear angle gamma between r_i-hat and r_f-hat[C]; t = c/|c|, s = t x r_f-hat.
   // f_s = K_s r gamma s and tau_s = 1/2 K_s r^2 gamma t (eq:bpm-fst, eq:bpm-tst),
@@ -258,8 +285,13 @@ void bond_eval(V3<T> x1, V3<T> x2, Q4<T> q1, Q4<T> q2, const Bond& bd,
   T cg = dot(ri_hat, rh);
   T gamma = atan2(sigma, cg);
   T g = val(sigma) > 0.0 ? gamma / sigma : one / cg;
-  V3<T> fs = (T(bd.Ks) * r * g) * cross(c, rh);
-  V3<T> ts = (half * T(bd.Ks) * r * r * g) * c;
+  // Shear damping: K_s gamma becomes K_s gamma + g_s gamma-dot in f_s and tau_s,
+  // gamma-dot = (gamma^n - gamma^(n-1)) / dt; no term where s-hat is undefined.
+  T ks = T(bd.Ks) * g;
+  if (dmp && dmp->hprev && val(sigma) > 0.0)
+    ks = ks + T(bd.gs) * ((gamma - T(dmp->hprev[0])) / T(dmp->dt)) / sigma;
+  V3<T> fs = (r * ks) * cross(c, rh);
+  V3<T> ts = (half * r * r * ks) * c;
 
   // Quaternion m turning the z-axis of C onto r_f-hat[C] (eq:quat-h, written as
   // the shortest-arc quaternion normalize(1 + z, -y, x, 0)).
@@ -291,6 +323,21 @@ void bond_eval(V3<T> x1, V3<T> x2, Q4<T> q1, Q4<T> q2, const Bond& bd,
 
   // Bending and twisting torques in C' (eq:bpm-tb, eq:bpm-tt).
   V3<T> tbt{T(bd.Kb) * th.x, T(bd.Kb) * th.y, T(bd.Kb) * th.z + T(bd.Kt) * psi};
+  // Twist and bend damping: g_t psi-dot and g_b theta-dot (per component in C'),
+  // the twist change taken modulo 2 pi (psi wraps at +-pi).
+  if (dmp && dmp->hprev) {
+    const double twopi = 6.28318530717958647692;
+    T dpsi = psi - T(dmp->hprev[1]);
+    dpsi = dpsi - T(twopi * std::round(val(dpsi) / twopi));
+    const T idt(1.0 / dmp->dt);
+    tbt = tbt + V3<T>{T(bd.gb) * (th.x - T(dmp->hprev[2])) * idt,
+                      T(bd.gb) * (th.y - T(dmp->hprev[3])) * idt,
+                      T(bd.gb) * (th.z - T(dmp->hprev[4])) * idt + T(bd.gt) * dpsi * idt};
+  }
+  if (dmp && dmp->hnow) {
+    dmp->hnow[0] = val(gamma); dmp->hnow[1] = val(psi);
+    dmp->hnow[2] = val(th.x); dmp->hnow[3] = val(th.y); dmp->hnow[4] = val(th.z);
+  }
 
   // Back to the global frame: v[O] = q_C v[C] q_C*, v[O] = q_C m v[C'] m* q_C*.
   F = qrot(qc, fr + fs);
@@ -348,10 +395,12 @@ void dipoles(const Model& md, const T* q, const T* mbody, std::vector<T>& mu) {
 //   x, q: positions and orientations;  v, w: the velocities used by damping;
 //   mu: global dipole moments; field: external field table; n: time level.
 // Bdip (optional) receives the dipole field at each particle.
+// hprev / hnow: [B][5] bond damping measures of the previous and the current
+// level (see Damp); used when the model has bond damping (FP64 only).
 template <class T>
 void forces(const Model& md, const T* x, const T* q, const T* v, const T* w,
             const T* mu, const T* field, int64_t n, int mask, T* F, T* Tq,
-            T* Bdip = nullptr) {
+            T* Bdip = nullptr, const double* hprev = nullptr, double* hnow = nullptr) {
   const int N = md.n;
   for (int k = 0; k < 3 * N; ++k) { F[k] = T(0.0); Tq[k] = T(0.0); }
 
@@ -363,6 +412,15 @@ void forces(const Model& md, const T* x, const T* q, const T* v, const T* w,
     for (int k = 0; k < B; ++k) {
       const Bond& bd = md.bonds[k];
       T e[4];
+      if constexpr (std::is_same<T, double>::value) {
+        if (md.bond_damp) {
+          Damp dm{hprev ? hprev + 5 * k : nullptr, hnow ? hnow + 5 * k : nullptr,
+                  ld3(v, bd.j) - ld3(v, bd.i), md.dt};
+          bond_eval(ld3(x, bd.i), ld3(x, bd.j), ld4(q, bd.i), ld4(q, bd.j), bd,
+                    bF[k], bTs[k], bTbt[k], e, &dm);
+          continue;
+        }
+      }
       bond_eval(ld3(x, bd.i), ld3(x, bd.j), ld4(q, bd.i), ld4(q, bd.j), bd,
                 bF[k], bTs[k], bTbt[k], e);
     }
@@ -483,6 +541,8 @@ template <class T> Q4<T> drive_q(const Model& md, int64_t n) {
 template <class T> struct State {
   std::vector<T> x, v, q, w, F, Tq;
   int64_t step = 0;
+  std::vector<double> hist;  // [B][5] bond damping measures of the last force evaluation
+  bool hist_valid = false;
 };
 
 // Boundary-condition state of driven particles at time level n.
@@ -498,12 +558,22 @@ template <class T> void apply_drive(const Model& md, State<T>& s, int64_t n) {
   }
 }
 
+// Forces of level n; with bond damping the rates are taken against the
+// measures of the previous evaluation (none yet: no rates), which are then
+// replaced by this level's.
 template <class T>
 void eval_forces(const Model& md, State<T>& s, const T* mbody, const T* field, int64_t n) {
   std::vector<T> mu;
   dipoles(md, s.q.data(), mbody, mu);
+  std::vector<double> hnow(md.bond_damp ? 5 * md.bonds.size() : 0);
   forces(md, s.x.data(), s.q.data(), s.v.data(), s.w.data(), mu.data(), field, n,
-         T_ALL, s.F.data(), s.Tq.data());
+         T_ALL, s.F.data(), s.Tq.data(), (T*)nullptr,
+         md.bond_damp && s.hist_valid ? s.hist.data() : nullptr,
+         md.bond_damp ? hnow.data() : nullptr);
+  if (md.bond_damp) {
+    s.hist.swap(hnow);
+    s.hist_valid = true;
+  }
 }
 
 // One velocity-Verlet step n -> n+1 (SI "Equations of motion").
@@ -546,6 +616,7 @@ void prepare(const Model& md, State<T>& s, const T* mbody, const T* field) {
     }
   }
   apply_drive(md, s, s.step);
+  s.hist_valid = false;  // the first evaluation seeds the bond damping measures
   eval_forces(md, s, mbody, field, s.step);
 }
 
@@ -591,13 +662,16 @@ void orc_bond_single(const double* x1, const double* x2, const double* q1, const
 // Force and torque of the selected terms (bitmask: 1 bond, 2 dipole, 4 Zeeman,
 // 8 contact, 16 damping, 32 external) at the state given, field index n.
 // Bdip (nullable) receives the dipole field at each particle.
+// hprev / hnow (nullable): bond damping measures [B][5] of the previous level
+// and of this one.
 void orc_forces(const orc_system* s, const double* x, const double* q, const double* v,
                 const double* w, const double* mbody, const double* field, int64_t n,
-                int32_t mask, double* F, double* Tq, double* Bdip) {
+                int32_t mask, double* F, double* Tq, double* Bdip, const double* hprev,
+                double* hnow) {
   Model md = build_model(s);
   std::vector<double> mu;
   dipoles(md, q, mbody, mu);
-  forces(md, x, q, v, w, mu.data(), field, n, mask, F, Tq, Bdip);
+  forces(md, x, q, v, w, mu.data(), field, n, mask, F, Tq, Bdip, hprev, hnow);
 }
 
 // Energies per member, 9 terms: stretch, shear, twist, bend (eq:total-energy),
@@ -666,21 +740,29 @@ int orc_contact_pairs(const orc_system* s, const double* x, int32_t* pairs, int 
 // Prepare the initial state (normalise q, boundary conditions, forces of level
 // `step`) and advance it by nsteps. Arrays are AoS and updated in place;
 // F and Tq receive the forces of the final level.
+// hist (nullable, [B][5]): bond damping measures of the last evaluation,
+// read when continuing a prepared state and written at the end.
 void orc_run(const orc_system* s, double* x, double* v, double* q, double* w, double* F,
              double* Tq, const double* mbody, const double* field, int64_t step0,
-             int64_t nsteps, int32_t prepared) {
+             int64_t nsteps, int32_t prepared, double* hist) {
   Model md = build_model(s);
   State<double> st;
   st.x.assign(x, x + 3 * md.n); st.v.assign(v, v + 3 * md.n);
   st.q.assign(q, q + 4 * md.n); st.w.assign(w, w + 3 * md.n);
   st.F.assign(3 * md.n, 0.0); st.Tq.assign(3 * md.n, 0.0);
   st.step = step0;
+  const size_t HB = 5 * md.bonds.size();
   if (prepared) {
     st.F.assign(F, F + 3 * md.n); st.Tq.assign(Tq, Tq + 3 * md.n);
+    if (md.bond_damp && hist) {
+      st.hist.assign(hist, hist + HB);
+      st.hist_valid = true;
+    }
   } else {
     prepare(md, st, mbody, field);
   }
   for (int64_t k = 0; k < nsteps; ++k) step(md, st, mbody, field);
+  if (md.bond_damp && hist && st.hist.size() == HB) std::copy(st.hist.begin(), st.hist.end(), hist);
   std::copy(st.x.begin(), st.x.end(), x); std::copy(st.v.begin(), st.v.end(), v);
   std::copy(st.q.begin(), st.q.end(), q); std::copy(st.w.begin(), st.w.end(), w);
   std::copy(st.F.begin(), st.F.end(), F); std::copy(st.Tq.begin(), st.Tq.end(), Tq);

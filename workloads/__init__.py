@@ -73,7 +73,7 @@ def _base(x_ref, rod_offset, rod_member, rod_params, m_body, bc, field, **kw):
         bc=np.asarray(bc, dtype=np.int8),
         drive_axis=np.array([1.0, 0.0, 0.0]), drive_period=0,
         field=np.ascontiguousarray(field, dtype=np.float64),
-        ext_force=None, ext_torque=None,
+        ext_force=None, ext_torque=None, bond_damping=None,
         dt=0.01, damping=0.1, mu0_4pi=1.0,
         dipole_on=True, contact_on=False, k_contact=10.0, r_contact=1.0,
         exclude_depth=1, steps=100, precision="fp64", name="custom",
