@@ -160,13 +160,15 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E (vendor figure)
 # once, however often a kernel re-reads it):
 #   bond (per bond): x, q of one particle (56), reference vector and length (32),
 #     rod id and flags (5), outputs F, tau_s, tau_b+tau_t (72)
+#   bond with bond damping: the same, plus the velocity of one particle (24) and
+#     the five measures of the previous level read and of this level written (80)
 #   contact (per particle): own position (24), list entry (8), force out (24)
 #   pre (per particle): state x v q w F T and m_body, inverse mass and inertia,
 #     ids (221 in); x v q w, m in FP64 and FP32, cell key and entry (180 out)
 #   kick (per particle): bond outputs of its bond (72), dipole slots (24 each on
 #     the mixed path, 48 in FP64), contact force, state and constants (318 + slots
 #     in); F T x v w q, m twice, cell key and entry (228 out)
-BYTES = {"bond": 165.0, "contact": 56.0, "pre": 401.0}
+BYTES = {"bond": 165.0, "bond_damped": 269.0, "contact": 56.0, "pre": 401.0}
 
 
 def kick_bytes(slots, slot_bytes=24.0):
@@ -214,10 +216,21 @@ def hbm_microbench(sizes, steps=10):
         kt = sim.kernel_times()
         sim.timing(False)
         res["kick"] = entry(1e3 * kt["kick"][0] / kt["kick"][1], n, kick_bytes(0))
-        for k in ("bond", "pre", "contact", "kick"):
+        sim.free()
+        # the bond kernel again with bond damping on every rod
+        wd = dict(w, bond_damping=np.tile([0.1, 0.1, 0.1, 0.1], (R, 1)))
+        sim = RodSim(wd, precision="mixed", graph_steps=0)
+        sim.launch_mode("separate")
+        sim.step(2)
+        sim.timing(True)
+        sim.step(steps)
+        kt = sim.kernel_times()
+        sim.timing(False)
+        sim.free()
+        res["bond_damped"] = entry(1e3 * kt["bond"][0] / kt["bond"][1], n - R, BYTES["bond_damped"])
+        for k in ("bond", "bond_damped", "pre", "contact", "kick"):
             res[k]["frac_copy"] = res[k]["GB_s"] / copy["GB_s"]
         res["plain_copy"] = copy
-        sim.free()
         out.append(res)
     return out
 

@@ -94,6 +94,21 @@ typedef struct rod_desc {
   int32_t graph_steps;        /* steps per captured HIP graph; 0 = launch eagerly */
   int32_t tape_every;         /* checkpoint interval for rod_grad (0 = no gradient support) */
   int32_t tape_capacity;      /* maximum number of steps rod_grad can reverse (0 = no tape) */
+  const double* bond_damping; /* host [R][4] or NULL: bond damping factors g_r, g_s, g_t, g_b >= 0
+                                 of each rod's bonds (Methods, "Damping"). Radial: g_r times the
+                                 relative velocity along the bond axis joins the radial force.
+                                 Shear: K_s gamma becomes K_s gamma + g_s gamma-dot in f_s and
+                                 tau_s. Twist and bend: g_t psi-dot and g_b theta-dot join the
+                                 torques. The rates are differences of these measures between the
+                                 current and the previous force evaluation of the run, over dt
+                                 (the twist change taken modulo 2 pi; the bend vector per component
+                                 in the bond frame). rod_init records the initial state's measures,
+                                 and its evaluation has no rates (with forces_valid the caller's
+                                 forces are kept and only the measures are taken); an evaluation
+                                 at that same level finds zero rates. Velocities are those of the
+                                 force evaluation (half-step while stepping). Factors must be
+                                 finite and >= 0 (else ROD_E_INVALID). Not differentiated: nonzero
+                                 factors with tape_capacity > 0 are refused (ROD_E_INVALID). */
 } rod_desc;
 
 /* Caller-owned device buffers (SoA, float64). */

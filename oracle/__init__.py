@@ -223,12 +223,15 @@ def run(w, nsteps, state=None, step0=0, mbody=None):
         st = {k: (np.array(v, dtype=np.float64, copy=True) if k != "step" else v)
               for k, v in state.items()}
         prepared = 1
-    if "hist" not in st:  # bond damping measures of the last evaluation
+    # bond damping measures of the last evaluation; a continued state without
+    # them has its own recorded before the first step
+    hist_in = int(prepared and "hist" in st)
+    if "hist" not in st:
         st["hist"] = np.zeros((max(1, n), 5))
     mb = _f64(w["m_body"] if mbody is None else mbody, (n, 3))
     lib.orc_run(sy.ref, _p(st["x"]), _p(st["v"]), _p(st["q"]), _p(st["w"]), _p(st["F"]),
                 _p(st["T"]), _p(mb), _p(sy.field), C.c_int64(int(st["step"])),
-                C.c_int64(int(nsteps)), C.c_int32(prepared), _p(st["hist"]))
+                C.c_int64(int(nsteps)), C.c_int32(prepared), _p(st["hist"]), C.c_int32(hist_in))
     st["step"] = int(st["step"]) + int(nsteps)
     return st
 

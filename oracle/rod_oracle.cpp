@@ -576,6 +576,20 @@ void eval_forces(const Model& md, State<T>& s, const T* mbody, const T* field, i
   }
 }
 
+// Bond damping measures of a given state (a continued run that brings none):
+// they are taken from its own configuration, its forces left as they are, so
+// that its first step takes rates against them.
+template <class T>
+void record_measures(const Model& md, State<T>& s, const T* mbody, const T* field, int64_t n) {
+  std::vector<T> mu, Ft(3 * md.n), Tt(3 * md.n);
+  dipoles(md, s.q.data(), mbody, mu);
+  std::vector<double> hnow(5 * md.bonds.size());
+  forces(md, s.x.data(), s.q.data(), s.v.data(), s.w.data(), mu.data(), field, n, T_BOND,
+         Ft.data(), Tt.data(), (T*)nullptr, nullptr, hnow.data());
+  s.hist.swap(hnow);
+  s.hist_valid = true;
+}
+
 // One velocity-Verlet step n -> n+1 (SI "Equations of motion").
 template <class T>
 void step(const Model& md, State<T>& s, const T* mbody, const T* field) {
@@ -741,10 +755,11 @@ int orc_contact_pairs(const orc_system* s, const double* x, int32_t* pairs, int 
 // `step`) and advance it by nsteps. Arrays are AoS and updated in place;
 // F and Tq receive the forces of the final level.
 // hist (nullable, [B][5]): bond damping measures of the last evaluation,
-// read when continuing a prepared state and written at the end.
+// written at the end; read when continuing a prepared state with hist_in set
+// (without it the continued state's own measures are recorded first).
 void orc_run(const orc_system* s, double* x, double* v, double* q, double* w, double* F,
              double* Tq, const double* mbody, const double* field, int64_t step0,
-             int64_t nsteps, int32_t prepared, double* hist) {
+             int64_t nsteps, int32_t prepared, double* hist, int32_t hist_in) {
   Model md = build_model(s);
   State<double> st;
   st.x.assign(x, x + 3 * md.n); st.v.assign(v, v + 3 * md.n);
@@ -754,9 +769,11 @@ void orc_run(const orc_system* s, double* x, double* v, double* q, double* w, do
   const size_t HB = 5 * md.bonds.size();
   if (prepared) {
     st.F.assign(F, F + 3 * md.n); st.Tq.assign(Tq, Tq + 3 * md.n);
-    if (md.bond_damp && hist) {
+    if (md.bond_damp && hist && hist_in) {
       st.hist.assign(hist, hist + HB);
       st.hist_valid = true;
+    } else if (md.bond_damp) {
+      record_measures(md, st, mbody, field, step0);
     }
   } else {
     prepare(md, st, mbody, field);

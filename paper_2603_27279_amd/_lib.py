@@ -27,6 +27,7 @@ class RodDesc(C.Structure):
         ("dipole_on", C.c_int32), ("contact_on", C.c_int32), ("exclude_depth", C.c_int32),
         ("precision", C.c_int32), ("step0", C.c_int64), ("graph_steps", C.c_int32),
         ("tape_every", C.c_int32), ("tape_capacity", C.c_int32),
+        ("bond_damping", _P),
     ]
 
 

@@ -15,10 +15,23 @@ template <class R> __device__ __forceinline__ R sqrt_(R a);
 template <> __device__ __forceinline__ float sqrt_(float a) { return sqrtf(a); }
 template <> __device__ __forceinline__ double sqrt_(double a) { return sqrt(a); }
 
-template <class H, class R>
+// Bond damping of one evaluation (Methods "Damping"): the damping factors,
+// the measures of the previous time level (shear angle, twist, bend vector in
+// C'; null before the first evaluation: no rates), this level's measures
+// (written), the relative velocity v2 - v1 and 1 / dt.
+struct BondDamp {
+  double gr, gs, gt, gb;
+  const double* hprev;
+  double hnow[5];
+  V3<double> dv;
+  double idt;
+};
+
+template <class H, class R, bool DAMP = false>
 __device__ __forceinline__ void bond_one(V3<H> x1, V3<H> x2, Q4<H> q1, Q4<H> q2, V3<double> rref,
                                          double r0, const double* __restrict__ K4, V3<H>& Fo,
-                                         V3<H>& Tso, V3<H>& Tbto, double* e) {
+                                         V3<H>& Tso, V3<H>& Tbto, double* e,
+                                         BondDamp* dm = nullptr) {
   // ---- FP64 head
   const V3<H> rf = x2 - x1;
   if (qdot(q1, q2) < 0.0) q2 = qscale(H(-1.0), q2);     // short arc
@@ -46,8 +59,22 @@ __device__ __forceinline__ void bond_one(V3<H> x1, V3<H> x2, Q4<H> q1, Q4<H> q2,
   const R gamma = atan2_(sigma, cg);                     // shear angle
   const R g = sigma > R(0) ? gamma / sigma : R(1) / cg;  // gamma / |c|, with its limit at 0
   const R rR = (R)r;
-  V3<R> f = (R)(H(Kr) * dr) * rh + (R(Ks) * rR * g) * cross(c, rh);  // f_r + f_s in C
-  const V3<R> ts = (R(0.5) * R(Ks) * rR * rR * g) * c;              // tau_s in C
+  V3<R> f;
+  V3<R> ts;
+  if constexpr (!DAMP) {
+    f = (R)(H(Kr) * dr) * rh + (R(Ks) * rR * g) * cross(c, rh);  // f_r + f_s in C
+    ts = (R(0.5) * R(Ks) * rR * rR * g) * c;                     // tau_s in C
+  } else {
+    // radial: + g_r (v2 - v1) . r_f-hat, the relative velocity seen from C;
+    // shear: K_s gamma becomes K_s gamma + g_s gamma-dot (no term where s-hat is
+    // undefined, sigma = 0)
+    const H frad = H(Kr) * dr + H(dm->gr) * dot(qrot_inv(qc, V3<H>{dm->dv.x, dm->dv.y, dm->dv.z}), rhat);
+    R ks = R(Ks) * g;
+    if (dm->hprev && sigma > R(0))
+      ks = ks + R(dm->gs) * (R)(((double)gamma - dm->hprev[0]) * dm->idt) / sigma;
+    f = (R)frad * rh + (rR * ks) * cross(c, rh);
+    ts = (R(0.5) * rR * rR * ks) * c;
+  }
 
   // u = m* u0 m: same scalar part, vector part rotated by m*.
   const Q4<R> mR = cvtq<R>(m);
@@ -64,7 +91,23 @@ __device__ __forceinline__ void bond_one(V3<H> x1, V3<H> x2, Q4<H> q1, Q4<H> q2,
   const R bn = sqrt_(dot(bv, bv));
   const R theta = R(2) * atan2_(bn, b.w);
   const R fac = bn > R(0) ? theta / bn : R(2) / b.w;
-  const V3<R> tbt{R(Kb) * fac * bv.x, R(Kb) * fac * bv.y, R(Kb) * fac * bv.z + R(Kt) * psi};
+  V3<R> tbt{R(Kb) * fac * bv.x, R(Kb) * fac * bv.y, R(Kb) * fac * bv.z + R(Kt) * psi};
+  if constexpr (DAMP) {
+    // twist and bend: + g_t psi-dot (the change taken modulo 2 pi) and
+    // + g_b theta-dot per component in C'
+    const double th[3] = {(double)(fac * bv.x), (double)(fac * bv.y), (double)(fac * bv.z)};
+    if (dm->hprev) {
+      const double twopi = 6.28318530717958647692;
+      double dpsi = (double)psi - dm->hprev[1];
+      dpsi -= twopi * rint(dpsi / twopi);
+      tbt = tbt + V3<R>{(R)(dm->gb * (th[0] - dm->hprev[2]) * dm->idt),
+                        (R)(dm->gb * (th[1] - dm->hprev[3]) * dm->idt),
+                        (R)(dm->gb * (th[2] - dm->hprev[4]) * dm->idt + dm->gt * dpsi * dm->idt)};
+    }
+    dm->hnow[0] = (double)gamma;
+    dm->hnow[1] = (double)psi;
+    dm->hnow[2] = th[0]; dm->hnow[3] = th[1]; dm->hnow[4] = th[2];
+  }
 
   // Back to the global frame.
   const Q4<R> qcR = cvtq<R>(qc);

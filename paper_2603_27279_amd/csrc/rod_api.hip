@@ -199,6 +199,17 @@ static int validate(const rod_desc* d) {
   if (d->exclude_depth < 0) return fail(ROD_E_INVALID, "exclude_depth must be >= 0");
   if (d->graph_steps < 0 || d->tape_every < 0 || d->tape_capacity < 0)
     return fail(ROD_E_INVALID, "graph_steps, tape_every and tape_capacity must be >= 0");
+  if (d->bond_damping) {
+    bool any = false;
+    for (int k = 0; k < 4 * d->n_rods; ++k) {
+      const double g = d->bond_damping[k];
+      if (!(g >= 0) || !std::isfinite(g))
+        return fail(ROD_E_INVALID, "bond damping factors must be finite and >= 0 (rod %d)", k / 4);
+      any = any || g != 0;
+    }
+    if (any && d->tape_capacity > 0)
+      return fail(ROD_E_INVALID, "bond damping is not differentiated: no tape with bond damping");
+  }
   if (d->tape_capacity > 0 && d->tape_every < 1)
     return fail(ROD_E_INVALID, "a tape needs tape_every >= 1");
   for (int r = 0; r < d->n_rods; ++r)
@@ -295,6 +306,7 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
   b += 2 * (4 * cells + sizeof(CellSlot) * cells * CELL_CAP + 4 * OVF_CAP) + 4 * N;  // cells
   if (d->contact_on && (long)N >= CONTACT_LANES_MAX_N) b += (4 * NBR_CAP + 4 + 24) * N;  // lists
   if (d->precision == ROD_MIXED && d->dipole_on) b += 48 * ((N + 63) / 64);  // chunk boxes
+  if (d->bond_damping) b += 8 * 4 * R + 8 * 2 * 5 * N;                       // bond damping
   b += 8 * 18 * N + 8 * 9 * M;                                                  // energy
   return b;
 }
@@ -583,6 +595,21 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
        (rc = dalloc(c, &d.xb, 3 * (size_t)N)) || (rc = dalloc(c, &d.rebuild, 2))))
     return cleanup(rc);
   d.dipole_on = dsc->dipole_on != 0; d.contact_on = dsc->contact_on != 0;
+  d.bdamp = nullptr;
+  d.hist = nullptr;
+  d.hist_valid = 0;
+  if (dsc->bond_damping) {
+    bool any = false;
+    for (int k = 0; k < 4 * R; ++k) any = any || dsc->bond_damping[k] != 0;
+    if (any) {
+      double* g = nullptr;
+      if ((rc = dalloc(c, &g, 4 * (size_t)R)) || (rc = dalloc(c, &d.hist, 2 * 5 * (size_t)N)))
+        return cleanup(rc);
+      if (hipMemcpy(g, dsc->bond_damping, 32 * (size_t)R, hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(ROD_E_HIP, "upload failed"));
+      d.bdamp = g;
+    }
+  }
   {
     double a = std::sqrt(dsc->drive_axis[0] * dsc->drive_axis[0] +
                          dsc->drive_axis[1] * dsc->drive_axis[1] +
@@ -598,7 +625,7 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   if ((rc = build_dipole_plan(c, -1, 1024))) return cleanup(rc);
   // descriptor host pointers are not kept
   c->desc.rod_offset = nullptr; c->desc.rod_member = nullptr; c->desc.rod_params = nullptr;
-  c->desc.x_ref = nullptr; c->desc.bc = nullptr;
+  c->desc.x_ref = nullptr; c->desc.bc = nullptr; c->desc.bond_damping = nullptr;
   if ((rc = tape_init(c->tape, c->d, dsc->tape_every, dsc->tape_capacity, c->allocs))) {
     return cleanup(fail(rc, "tape allocation failed"));
   }
@@ -607,9 +634,22 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   if ((rc = enter(c))) return cleanup(rc);
   if (forces_valid) {
     if (hipSuccess != launch_pre(c->d, PRE_PREPARE, c->s)) return cleanup(fail(ROD_E_HIP, "launch failed"));
+    // bond damping: record the measures of this level (the forces are the caller's)
+    if (c->d.bdamp && hipSuccess != launch_bond(c->d, dsc->precision, 0, c->s))
+      return cleanup(fail(ROD_E_HIP, "launch failed"));
   } else if ((rc = enqueue_prepare(c))) {
     return cleanup(rc);
   }
+  if (c->d.bdamp) {
+    // both parity planes hold the initial level's measures, so that a further
+    // evaluation of that level finds no rates either
+    const size_t plane = 5 * (size_t)N;
+    const long p0 = (long)(dsc->step0 & 1);
+    if (hipMemcpyAsync(c->d.hist + (1 - p0) * plane, c->d.hist + p0 * plane,
+                       plane * sizeof(double), hipMemcpyDeviceToDevice, c->s) != hipSuccess)
+      return cleanup(fail(ROD_E_HIP, "copy failed"));
+  }
+  c->d.hist_valid = 1;  // later evaluations take rates against the recorded measures
   if ((rc = leave(c))) return cleanup(rc);
   if (forces_valid && d.contact_on) {
     // pre built the cell list without a force pass; empty it again

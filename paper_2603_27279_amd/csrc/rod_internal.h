@@ -40,6 +40,9 @@ struct Dev {
   double* dpart;           // [S][6][N] dipole partial sums (F then B), one slot per j range
                            // (FP64 path; the reverse pass keeps its cotangent sums here)
   float* dslotf;           // [S][6][N] the same partial sums on the mixed path (FP32), else null
+  const double* bdamp;     // [R][4] bond damping factors g_r, g_s, g_t, g_b, or null (none)
+  double* hist;            // [2][5][N] bond damping measures per level parity (bond k at k)
+  int hist_valid;          // the measures of the previous level exist
   const int* mslots;       // [M]: j ranges (partial slots) of each member
   int max_slots;           // largest entry of mslots; slots a member does not use stay zero
   double* cF;              // [3N] contact force

@@ -30,10 +30,13 @@ class RodSim:
     ``precision``: "fp64" or "mixed" (default: the workload's).
     ``graph_steps``: steps per captured HIP graph (0 = eager launches).
     ``tape_every`` / ``tape_capacity``: checkpointing for ``grad``.
+    ``step0``: the time level of the initial state (drive phase, restarts).
+    ``forces``: (F, T) [n, 3] of the initial state, e.g. a saved state's; they
+    are taken as they are (``forces_valid``) instead of being evaluated.
     """
 
     def __init__(self, w, precision=None, graph_steps=0, tape_every=0, tape_capacity=0,
-                 device="cuda", step0=0, stream=None):
+                 device="cuda", step0=0, stream=None, forces=None):
         import torch
         self.torch = torch
         self.lib = L.load()
@@ -46,8 +49,11 @@ class RodSim:
         self.v = _soa(torch, w["v0"], dev)
         self.q = _soa(torch, w["q0"], dev)
         self.om = _soa(torch, w["w0"], dev)
-        self.F = torch.zeros((3, n), dtype=torch.float64, device=dev)
-        self.T = torch.zeros((3, n), dtype=torch.float64, device=dev)
+        if forces is None:
+            self.F = torch.zeros((3, n), dtype=torch.float64, device=dev)
+            self.T = torch.zeros((3, n), dtype=torch.float64, device=dev)
+        else:
+            self.F, self.T = _soa(torch, forces[0], dev), _soa(torch, forces[1], dev)
         self.m_body = _soa(torch, w["m_body"], dev)
         self.field = torch.as_tensor(np.ascontiguousarray(w["field"], dtype=np.float64), device=dev)
         self.ext_force = None if w.get("ext_force") is None else _soa(torch, w["ext_force"], dev)
@@ -60,6 +66,8 @@ class RodSim:
             rod_params=np.ascontiguousarray(w["rod_params"], dtype=np.float64),
             x_ref=np.ascontiguousarray(w["x_ref"], dtype=np.float64),
             bc=np.ascontiguousarray(w["bc"], dtype=np.int8),
+            bond_damping=(None if w.get("bond_damping") is None else
+                          np.ascontiguousarray(w["bond_damping"], dtype=np.float64).reshape(-1, 4)),
         )
         d = L.RodDesc()
         d.n_particles = n
@@ -79,6 +87,8 @@ class RodSim:
         d.graph_steps = int(graph_steps)
         d.tape_every = int(tape_every)
         d.tape_capacity = int(tape_capacity)
+        bd = self._host["bond_damping"]
+        d.bond_damping = None if bd is None else bd.ctypes.data_as(C.c_void_p)
         self.desc = d
         b = L.RodBuffers()
         b.x, b.v, b.q, b.w = _ptr(self.x), _ptr(self.v), _ptr(self.q), _ptr(self.om)
@@ -90,7 +100,7 @@ class RodSim:
         self.stream = s
         ctx = C.c_void_p()
         L.check(self.lib.rod_init(C.byref(ctx), C.byref(d), C.byref(b),
-                                  C.c_void_p(s.cuda_stream), 0))
+                                  C.c_void_p(s.cuda_stream), int(forces is not None)))
         self.ctx = ctx
 
     # ------------------------------------------------------------------ C ABI

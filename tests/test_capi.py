@@ -42,6 +42,9 @@ def _desc(w, **over):
     d.n_members = w["n_members"]
     for k in ("rod_offset", "rod_member", "rod_params", "x_ref", "bc"):
         setattr(d, k, keep[k].ctypes.data_as(C.c_void_p))
+    if "bond_damping" in keep:
+        keep["bond_damping"] = np.ascontiguousarray(keep["bond_damping"], dtype=np.float64)
+        d.bond_damping = keep["bond_damping"].ctypes.data_as(C.c_void_p)
     d.drive_axis = (C.c_double * 3)(*w["drive_axis"])
     d.drive_period = w["drive_period"]
     d.field_len = w["field"].shape[0]
@@ -75,6 +78,11 @@ def test_query_workspace_and_invalid_descriptors():
         (dict(n_members=2), "member 1 has no rod"),
         (dict(exclude_depth=-1), "exclude_depth"),
         (dict(tape_capacity=10, tape_every=0), "tape_every"),
+        (dict(bond_damping=np.array([[0.1, -0.2, 0.0, 0.0]])), "bond damping factors"),
+        (dict(bond_damping=np.array([[0.1, 0.0, np.nan, 0.0]])), "bond damping factors"),
+        (dict(bond_damping=np.array([[0.1, 0.0, np.inf, 0.0]])), "bond damping factors"),
+        (dict(bond_damping=np.array([[0.0, 0.0, 0.0, 0.3]]), tape_capacity=10, tape_every=2),
+         "no tape with bond damping"),
     ]
     for over, msg in cases:
         d, keep = _desc(w, **over)
@@ -83,6 +91,23 @@ def test_query_workspace_and_invalid_descriptors():
         assert rc == L.ROD_E_INVALID, over
         assert ctx.value is None
         assert msg in lib.rod_last_error().decode(), (over, lib.rod_last_error())
+
+
+def test_bond_damping_descriptor():
+    """Bond damping adds its factors and two planes of five measures per
+    particle to the workspace; all-zero factors, with or without a tape, are
+    the undamped model."""
+    lib = L.load()
+    w = workloads.twisted_rod(n=64)
+    nb = C.c_size_t()
+    d, keep = _desc(w)
+    assert lib.rod_query_workspace(C.byref(d), C.byref(nb)) == L.ROD_OK
+    d2, keep2 = _desc(w, bond_damping=np.array([[0.5, 0.3, 0.2, 0.1]]))
+    nb2 = C.c_size_t()
+    assert lib.rod_query_workspace(C.byref(d2), C.byref(nb2)) == L.ROD_OK
+    assert nb2.value - nb.value == 8 * 4 * 1 + 8 * 10 * 64
+    d3, keep3 = _desc(w, bond_damping=np.zeros((1, 4)), tape_capacity=10, tape_every=2)
+    assert lib.rod_query_workspace(C.byref(d3), C.byref(nb2)) == L.ROD_OK
 
 
 def test_null_context_is_rejected():

@@ -763,3 +763,26 @@ def test_bond_damping_dissipates_and_plain_bonds_conserve():
     e = out["damped"]
     assert e[-1] < e[0] * (2.0 / 3.0)
     assert np.all(np.diff(e) <= 1e-3 * e[0])
+
+
+def test_bond_damping_continued_runs():
+    """A damped run cut in two is the uncut run, whether the second part gets
+    the measures the first left or records them from the state it is given
+    (they are that state's own)."""
+    w = single_rod(8, damping=0.0)
+    rng = np.random.default_rng(11)
+    w["x0"] = w["x_ref"] + 0.05 * rng.normal(size=(8, 3)) * (w["bc"] == 0)[:, None]
+    w["q0"] = np.array([qaxis(rng.normal(size=3), 0.2) for _ in range(8)])
+    w["v0"] = 0.1 * rng.normal(size=(8, 3)) * (w["bc"] == 0)[:, None]
+    w["bond_damping"] = np.array([[0.4, 0.3, 0.2, 0.1]])
+    whole = oracle.run(w, 20)
+    half = oracle.run(w, 10)
+    bare = {k: v for k, v in half.items() if k != "hist"}
+    for st in (half, bare):
+        cont = oracle.run(w, 10, state=st)
+        assert cont["step"] == 20
+        for k in ("x", "v", "q", "w", "F", "T"):
+            np.testing.assert_array_equal(cont[k], whole[k])
+    # with measures that are not the state's (all zero) the run differs
+    zero = dict(half, hist=np.zeros_like(half["hist"]))
+    assert np.max(np.abs(oracle.run(w, 10, state=zero)["x"] - whole["x"])) > 1e-6
