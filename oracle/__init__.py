@@ -47,6 +47,7 @@ class _System(C.Structure):
         ("k_contact", C.c_double), ("r_contact", C.c_double),
         ("dipole_on", C.c_int32), ("contact_on", C.c_int32), ("exclude_depth", C.c_int32),
         ("bond_damping", C.c_void_p),
+        ("contact_model", C.c_int32), ("contact_hm", C.c_double * 5),
     ]
 
 
@@ -107,6 +108,9 @@ class System:
         s.dipole_on = int(bool(w["dipole_on"])); s.contact_on = int(bool(w["contact_on"]))
         s.exclude_depth = int(w["exclude_depth"])
         s.bond_damping = _p(keep["bond_damping"])
+        s.contact_model = contact_model(w)
+        if s.contact_model == 1:
+            s.contact_hm = (C.c_double * 5)(*[float(a) for a in w["contact_hm"]])
         self.s = s
 
     @property
@@ -147,6 +151,15 @@ def bond_single(x1, x2, q1, q2, rref, K):
     F, Ts, Tbt, e = np.zeros(3), np.zeros(3), np.zeros(3), np.zeros(4)
     lib.orc_bond_single(*[_p(v) for v in a], _p(F), _p(Ts), _p(Tbt), _p(e))
     return F, Ts, Tbt, e
+
+
+CONTACT_MODELS = {"hookean": 0, "hertz_mindlin": 1}
+
+
+def contact_model(w):
+    """0 for the Hookean normal law, 1 for Hertz-Mindlin (``contact_hm`` =
+    contact modulus E, Poisson ratio nu, friction mu, damping g_n, g_t)."""
+    return CONTACT_MODELS[w.get("contact_model", "hookean")]
 
 
 def has_bond_damping(w):
@@ -244,6 +257,8 @@ def run_jvp(w, nsteps, tangent, step0=0):
     Bond damping is not differentiated (its rates depend on stored history)."""
     if has_bond_damping(w):
         raise NotImplementedError("the forward-mode run does not differentiate bond damping")
+    if w["contact_on"] and contact_model(w) != 0:
+        raise NotImplementedError("the forward-mode run does not differentiate Hertz-Mindlin contact")
     lib = _load()
     sy = System(w)
     n = sy.n

@@ -21,8 +21,10 @@
 //   energy            eq:total-energy.
 //   magnetisation     "Magnetized beams in non-uniform fields": m = R m_body.
 //   Zeeman / dipoles  Methods "Magnetic interactions".
-//   contact           Methods "Contact" (Hookean normal law: the workload's
-//                     stated simplification of the paper's Hertz-Mindlin).
+//   contact           Methods "Contact": the workloads' Hookean normal law, or
+//                     the paper's Hertz-Mindlin law (Hertz normal force,
+//                     Mindlin tangential spring with a Coulomb limit and a
+//                     per-contact tangential displacement history).
 //   bond damping      Methods "Damping": radial term from the relative
 //                     velocity along the bond axis; shear, twist and bend terms
 //                     from finite-difference rates of the stored measures.
@@ -151,7 +153,20 @@ struct Model {
   const double* ext_torque = nullptr;
   int field_len = 1;
   bool bond_damp = false;  // some bond has a non-zero damping factor
+  // Contact law: 0 Hookean normal; 1 Hertz-Mindlin with contact modulus E,
+  // Poisson ratio nu, friction coefficient mu, normal and tangential viscous
+  // damping coefficients gn, gt.
+  int contact_model = 0;
+  double hmE = 0, hmNu = 0, hmMu = 0, hmGn = 0, hmGt = 0;
 };
+
+// Tangential displacement history of Hertz-Mindlin contacts: for particle i,
+// its contacts j at one evaluation and the displacement s of each, seen from i.
+struct CEntry {
+  int j;
+  V3<double> s;
+};
+using CHist = std::vector<std::vector<CEntry>>;
 
 }  // namespace orc
 
@@ -173,6 +188,8 @@ struct orc_system {
   double dt, damping, mu0_4pi, k_contact, r_contact;
   int32_t dipole_on, contact_on, exclude_depth;
   const double* bond_damping;  // [R][4] g_r, g_s, g_t, g_b, or NULL
+  int32_t contact_model;       // 0 Hookean, 1 Hertz-Mindlin
+  double contact_hm[5];        // Hertz-Mindlin: E, nu, mu, g_n, g_t
 };
 
 }  // extern "C"
@@ -241,6 +258,9 @@ static Model build_model(const orc_system* s) {
   m.dipole_on = s->dipole_on; m.contact_on = s->contact_on; m.depth = s->exclude_depth;
   m.ext_force = s->ext_force; m.ext_torque = s->ext_torque;
   m.field_len = s->field_len > 0 ? s->field_len : 1;
+  m.contact_model = s->contact_model;
+  m.hmE = s->contact_hm[0]; m.hmNu = s->contact_hm[1]; m.hmMu = s->contact_hm[2];
+  m.hmGn = s->contact_hm[3]; m.hmGt = s->contact_hm[4];
   return m;
 }
 
@@ -395,12 +415,72 @@ void dipoles(const Model& md, const T* q, const T* mbody, std::vector<T>& mu) {
 //   x, q: positions and orientations;  v, w: the velocities used by damping;
 //   mu: global dipole moments; field: external field table; n: time level.
 // Bdip (optional) receives the dipole field at each particle.
+// ---------------------------------------------------------------- Hertz-Mindlin
+// One Hertz-Mindlin contact seen from particle i, its partner j closer than r_c
+// (Methods, "Contact", which names the law; its constants are the textbook
+// ones for two equal elastic spheres of diameter r_c):
+//   n = (x_i - x_j) / r, overlap delta = r_c - r, R* = r_c / 4,
+//   E* = E / (2 (1 - nu^2)), G* = E / (4 (2 - nu)(1 + nu)), a = sqrt(R* delta);
+//   normal: F_n = max(0, 4/3 E* a delta - g_n v_n), v_n = (v_rel . n);
+//   contact-point velocity of i relative to j: the two centres' velocities plus
+//     w x (branch vector) of each, the branch vectors being -r/2 n and +r/2 n:
+//     v_rel = (v_i - v_j) - r/2 (w_i + w_j) x n, tangential part v_t;
+//   tangential (Mindlin): s, the tangential displacement of the contact, is
+//     turned into the current tangent plane (keeping its length) and advanced
+//     by v_t dt; a contact absent from the previous evaluation starts at s = 0;
+//     F_t = -8 G* a s - g_t v_t, limited to |F_t| <= mu F_n (where the limit
+//     acts, s is reset to the displacement that holds the limited force);
+//   force on i: F_n n + F_t (j receives the opposite); torque on i and on j:
+//     (-r/2 n) x F_t.
+// sprev: s of the previous evaluation, or null for a new contact. Writes the
+// new s to snow and the normal elastic energy 8/15 E* sqrt(R*) delta^(5/2) to e.
+static void hertz_mindlin(const Model& md, V3<double> xi, V3<double> xj, V3<double> vi,
+                          V3<double> vj, V3<double> wi, V3<double> wj, const V3<double>* sprev,
+                          V3<double>& F, V3<double>& Tq, V3<double>& snow, double& e) {
+  const V3<double> d = xi - xj;
+  const double r = std::sqrt((d.x * d.x + d.y * d.y) + d.z * d.z);
+  const V3<double> n = (1.0 / r) * d;
+  const double delta = md.rc - r;
+  const double Rs = 0.25 * md.rc;
+  const double Es = md.hmE / (2.0 * (1.0 - md.hmNu * md.hmNu));
+  const double Gs = md.hmE / (4.0 * (2.0 - md.hmNu) * (1.0 + md.hmNu));
+  const double a = std::sqrt(Rs * delta);
+  const double kn = 4.0 / 3.0 * Es * a, kt = 8.0 * Gs * a;
+
+  const V3<double> vrel = (vi - vj) - (0.5 * r) * cross(wi + wj, n);
+  const double vn = dot(vrel, n);
+  const V3<double> vt = vrel - vn * n;
+  const double Fn = std::max(0.0, kn * delta - md.hmGn * vn);
+
+  V3<double> sv{0.0, 0.0, 0.0};
+  if (sprev) {
+    V3<double> sp = *sprev;
+    V3<double> st = sp - dot(sp, n) * n;  // into the current tangent plane
+    const double lt = norm(st), lp = norm(sp);
+    if (lt > 0.0) st = (lp / lt) * st;
+    sv = st + md.dt * vt;
+  }
+  V3<double> Ft = (-kt) * sv - md.hmGt * vt;
+  const double ft = norm(Ft), fmax = md.hmMu * Fn;
+  if (ft > fmax) {
+    Ft = (fmax / ft) * Ft;
+    sv = (-1.0 / kt) * (Ft + md.hmGt * vt);
+  }
+  F = Fn * n + Ft;
+  Tq = cross((-0.5 * r) * n, Ft);
+  snow = sv;
+  e = 8.0 / 15.0 * Es * std::sqrt(Rs) * delta * delta * std::sqrt(delta);
+}
+
 // hprev / hnow: [B][5] bond damping measures of the previous and the current
 // level (see Damp); used when the model has bond damping (FP64 only).
+// cprev / cnow: Hertz-Mindlin contact histories of the previous evaluation
+// (null: none, every contact is new) and of this one (written when non-null).
 template <class T>
 void forces(const Model& md, const T* x, const T* q, const T* v, const T* w,
             const T* mu, const T* field, int64_t n, int mask, T* F, T* Tq,
-            T* Bdip = nullptr, const double* hprev = nullptr, double* hnow = nullptr) {
+            T* Bdip = nullptr, const double* hprev = nullptr, double* hnow = nullptr,
+            const CHist* cprev = nullptr, CHist* cnow = nullptr) {
   const int N = md.n;
   for (int k = 0; k < 3 * N; ++k) { F[k] = T(0.0); Tq[k] = T(0.0); }
 
@@ -481,9 +561,41 @@ void forces(const Model& md, const T* x, const T* q, const T* v, const T* w,
     }
   }
 
+  // Hertz-Mindlin contact: the same pairs as below, each seen from both ends.
+  if constexpr (std::is_same<T, double>::value) {
+    if ((mask & T_CONTACT) && md.contact_on && md.contact_model == 1) {
+      const double rc2 = md.rc * md.rc;
+      if (cnow) cnow->assign(N, {});
+#pragma omp parallel for schedule(dynamic, 64)
+      for (int i = 0; i < N; ++i) {
+        int mem = md.member_of[i];
+        V3<double> Fi{0.0, 0.0, 0.0}, Ti{0.0, 0.0, 0.0};
+        for (int j = md.member_begin[mem]; j < md.member_end[mem]; ++j) {
+          if (j == i || excluded(md, i, j)) continue;
+          V3<double> d = ld3(x, i) - ld3(x, j);
+          double r2 = (d.x * d.x + d.y * d.y) + d.z * d.z;
+          if (!(r2 < rc2)) continue;
+          const V3<double>* sp = nullptr;
+          if (cprev)
+            for (const CEntry& c : (*cprev)[i])
+              if (c.j == j) sp = &c.s;
+          V3<double> f, t, sn;
+          double e;
+          hertz_mindlin(md, ld3(x, i), ld3(x, j), ld3(v, i), ld3(v, j), ld3(w, i), ld3(w, j),
+                        sp, f, t, sn, e);
+          Fi = Fi + f;
+          Ti = Ti + t;
+          if (cnow) (*cnow)[i].push_back({j, sn});
+        }
+        add3(F, i, Fi);
+        add3(Tq, i, Ti);
+      }
+    }
+  }
+
   // Contact: brute force over all pairs of a member that are not excluded;
   // pairs with r^2 = (dx dx + dy dy) + dz dz < r_c^2 repel with k (r_c - r).
-  if ((mask & T_CONTACT) && md.contact_on) {
+  if ((mask & T_CONTACT) && md.contact_on && md.contact_model == 0) {
     const double rc2 = md.rc * md.rc;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int i = 0; i < N; ++i) {
@@ -543,6 +655,8 @@ template <class T> struct State {
   int64_t step = 0;
   std::vector<double> hist;  // [B][5] bond damping measures of the last force evaluation
   bool hist_valid = false;
+  CHist chist;               // Hertz-Mindlin contacts of the last force evaluation
+  bool chist_valid = false;
 };
 
 // Boundary-condition state of driven particles at time level n.
@@ -560,34 +674,52 @@ template <class T> void apply_drive(const Model& md, State<T>& s, int64_t n) {
 
 // Forces of level n; with bond damping the rates are taken against the
 // measures of the previous evaluation (none yet: no rates), which are then
-// replaced by this level's.
+// replaced by this level's. Hertz-Mindlin contacts likewise continue from the
+// contacts of the previous evaluation (none yet: every contact is new).
 template <class T>
 void eval_forces(const Model& md, State<T>& s, const T* mbody, const T* field, int64_t n) {
   std::vector<T> mu;
   dipoles(md, s.q.data(), mbody, mu);
   std::vector<double> hnow(md.bond_damp ? 5 * md.bonds.size() : 0);
+  const bool hm = md.contact_on && md.contact_model == 1;
+  CHist cnow;
   forces(md, s.x.data(), s.q.data(), s.v.data(), s.w.data(), mu.data(), field, n,
          T_ALL, s.F.data(), s.Tq.data(), (T*)nullptr,
          md.bond_damp && s.hist_valid ? s.hist.data() : nullptr,
-         md.bond_damp ? hnow.data() : nullptr);
+         md.bond_damp ? hnow.data() : nullptr,
+         hm && s.chist_valid ? &s.chist : nullptr, hm ? &cnow : nullptr);
   if (md.bond_damp) {
     s.hist.swap(hnow);
     s.hist_valid = true;
   }
+  if (hm) {
+    s.chist.swap(cnow);
+    s.chist_valid = true;
+  }
 }
 
-// Bond damping measures of a given state (a continued run that brings none):
-// they are taken from its own configuration, its forces left as they are, so
-// that its first step takes rates against them.
+// Bond damping measures and Hertz-Mindlin contacts of a given state (a
+// continued run that brings none): they are taken from its own configuration,
+// as a first evaluation would (no rates; every contact new, s = 0), its forces
+// left as they are, so that its first step continues from them.
 template <class T>
-void record_measures(const Model& md, State<T>& s, const T* mbody, const T* field, int64_t n) {
+void record_measures(const Model& md, State<T>& s, const T* mbody, const T* field, int64_t n,
+                     bool bonds, bool contacts) {
   std::vector<T> mu, Ft(3 * md.n), Tt(3 * md.n);
   dipoles(md, s.q.data(), mbody, mu);
   std::vector<double> hnow(5 * md.bonds.size());
-  forces(md, s.x.data(), s.q.data(), s.v.data(), s.w.data(), mu.data(), field, n, T_BOND,
-         Ft.data(), Tt.data(), (T*)nullptr, nullptr, hnow.data());
-  s.hist.swap(hnow);
-  s.hist_valid = true;
+  CHist cnow;
+  forces(md, s.x.data(), s.q.data(), s.v.data(), s.w.data(), mu.data(), field, n,
+         (bonds ? T_BOND : 0) | (contacts ? T_CONTACT : 0), Ft.data(), Tt.data(), (T*)nullptr,
+         nullptr, bonds ? hnow.data() : nullptr, nullptr, contacts ? &cnow : nullptr);
+  if (bonds) {
+    s.hist.swap(hnow);
+    s.hist_valid = true;
+  }
+  if (contacts) {
+    s.chist.swap(cnow);
+    s.chist_valid = true;
+  }
 }
 
 // One velocity-Verlet step n -> n+1 (SI "Equations of motion").
@@ -630,7 +762,8 @@ void prepare(const Model& md, State<T>& s, const T* mbody, const T* field) {
     }
   }
   apply_drive(md, s, s.step);
-  s.hist_valid = false;  // the first evaluation seeds the bond damping measures
+  s.hist_valid = false;   // the first evaluation seeds the bond damping measures
+  s.chist_valid = false;  // and the Hertz-Mindlin contacts
   eval_forces(md, s, mbody, field, s.step);
 }
 
@@ -689,8 +822,9 @@ void orc_forces(const orc_system* s, const double* x, const double* q, const dou
 }
 
 // Energies per member, 9 terms: stretch, shear, twist, bend (eq:total-energy),
-// Zeeman -m.B, dipole-dipole, contact 1/2 k (r_c - r)^2, translational and
-// rotational kinetic energy.
+// Zeeman -m.B, dipole-dipole, contact (Hookean 1/2 k (r_c - r)^2, or the
+// normal Hertz energy; the tangential springs are not counted), translational
+// and rotational kinetic energy.
 void orc_energy(const orc_system* s, const double* x, const double* q, const double* v,
                 const double* w, const double* mbody, const double* field, int64_t n,
                 double* out) {
@@ -725,7 +859,12 @@ void orc_energy(const orc_system* s, const double* x, const double* q, const dou
         double r2 = (r.x * r.x + r.y * r.y) + r.z * r.z;
         if (r2 < md.rc * md.rc) {
           double ov = md.rc - std::sqrt(r2);
-          out[9 * mem + 6] += 0.5 * md.kc * ov * ov;
+          if (md.contact_model == 1) {  // Hertz: 8/15 E* sqrt(R*) delta^(5/2)
+            const double Es = md.hmE / (2.0 * (1.0 - md.hmNu * md.hmNu));
+            out[9 * mem + 6] += 8.0 / 15.0 * Es * std::sqrt(0.25 * md.rc) * ov * ov * std::sqrt(ov);
+          } else {
+            out[9 * mem + 6] += 0.5 * md.kc * ov * ov;
+          }
         }
       }
     }
@@ -769,12 +908,14 @@ void orc_run(const orc_system* s, double* x, double* v, double* q, double* w, do
   const size_t HB = 5 * md.bonds.size();
   if (prepared) {
     st.F.assign(F, F + 3 * md.n); st.Tq.assign(Tq, Tq + 3 * md.n);
-    if (md.bond_damp && hist && hist_in) {
+    const bool have = md.bond_damp && hist && hist_in;
+    if (have) {
       st.hist.assign(hist, hist + HB);
       st.hist_valid = true;
-    } else if (md.bond_damp) {
-      record_measures(md, st, mbody, field, step0);
     }
+    const bool hm = md.contact_on && md.contact_model == 1;
+    if ((md.bond_damp && !have) || hm)
+      record_measures(md, st, mbody, field, step0, md.bond_damp && !have, hm);
   } else {
     prepare(md, st, mbody, field);
   }

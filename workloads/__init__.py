@@ -29,9 +29,13 @@ ext_torque        float64 [N, 3] or None       constant external torque per part
 dt, damping       float                        time step; global viscous damping coefficient c
 mu0_4pi           float                        dipole prefactor mu0 / (4 pi)
 dipole_on         bool                         all-pairs dipole-dipole interaction within a member
-contact_on        bool                         Hookean normal contact between non-excluded pairs
-k_contact         float                        contact stiffness
+contact_on        bool                         contact between non-excluded pairs
+contact_model     str                          "hookean" (normal, k_contact) or "hertz_mindlin"
+contact_hm        float64 [5] or None          Hertz-Mindlin: contact modulus E, Poisson nu, friction
+                                               mu, normal and tangential damping g_n, g_t
+k_contact         float                        Hookean contact stiffness
 r_contact         float                        contact distance (pairs closer than this interact)
+bond_damping      float64 [R, 4] or None       bond damping factors g_r, g_s, g_t, g_b per rod
 exclude_depth     int                          same-rod pairs with |i-j| <= depth never contact
 steps             int                          run length of the workload
 precision         str                          "fp64" or "mixed" (path the workload is specified for)
@@ -74,6 +78,7 @@ def _base(x_ref, rod_offset, rod_member, rod_params, m_body, bc, field, **kw):
         drive_axis=np.array([1.0, 0.0, 0.0]), drive_period=0,
         field=np.ascontiguousarray(field, dtype=np.float64),
         ext_force=None, ext_torque=None, bond_damping=None,
+        contact_model="hookean", contact_hm=None,
         dt=0.01, damping=0.1, mu0_4pi=1.0,
         dipole_on=True, contact_on=False, k_contact=10.0, r_contact=1.0,
         exclude_depth=1, steps=100, precision="fp64", name="custom",
