@@ -67,6 +67,13 @@ enum {
 /* Boundary condition of a particle. */
 enum { ROD_BC_FREE = 0, ROD_BC_CLAMPED = 1, ROD_BC_DRIVEN = 2 };
 
+/* Contact law (rod_desc.contact_model). */
+enum { ROD_CONTACT_HOOKEAN = 0, ROD_CONTACT_HERTZ_MINDLIN = 1 };
+
+/* Tangential-history capacity of a Hertz-Mindlin particle: contacts it can
+   hold at once (more: ROD_E_OVERFLOW at rod_sync). */
+#define ROD_HM_MAX_CONTACTS 16
+
 /* Host-side description; copied by rod_init (the caller may free it after). */
 typedef struct rod_desc {
   int32_t n_particles;        /* N >= 1 */
@@ -109,6 +116,25 @@ typedef struct rod_desc {
                                  force evaluation (half-step while stepping). Factors must be
                                  finite and >= 0 (else ROD_E_INVALID). Not differentiated: nonzero
                                  factors with tape_capacity > 0 are refused (ROD_E_INVALID). */
+  int32_t contact_model;      /* ROD_CONTACT_HOOKEAN: k_contact (r_c - r) along the line of centres.
+                                 ROD_CONTACT_HERTZ_MINDLIN (Methods, "Contact"), as for two equal
+                                 elastic spheres of diameter r_c: R* = r_c / 4, overlap
+                                 delta = r_c - r, a = sqrt(R* delta), E* = E / (2 (1 - nu^2)),
+                                 G* = E / (4 (2 - nu)(1 + nu)); normal force
+                                 max(0, 4/3 E* a delta - g_n v_n); tangential force
+                                 -8 G* a s - g_t v_t limited to mu times the normal force, with v the
+                                 contact-point velocity of the pair (centre velocities plus spins)
+                                 and s the contact's tangential displacement: zero for a new contact,
+                                 otherwise the previous evaluation's s turned into the current
+                                 tangent plane plus v_t dt (reset to hold the limited force when the
+                                 limit acts). The torque (-r/2 n) x F_t acts on both particles.
+                                 Each particle keeps its contacts of the last two levels (at most
+                                 ROD_HM_MAX_CONTACTS each); as with bond damping, rod_init records
+                                 the initial contacts (all new) and a restart starts them afresh. Not
+                                 differentiated: with tape_capacity > 0 it is refused. */
+  double contact_hm[5];       /* Hertz-Mindlin: contact modulus E > 0, Poisson ratio -1 < nu <= 0.5,
+                                 friction coefficient mu >= 0, normal and tangential viscous damping
+                                 g_n, g_t >= 0 */
 } rod_desc;
 
 /* Caller-owned device buffers (SoA, float64). */

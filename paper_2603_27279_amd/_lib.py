@@ -28,6 +28,7 @@ class RodDesc(C.Structure):
         ("precision", C.c_int32), ("step0", C.c_int64), ("graph_steps", C.c_int32),
         ("tape_every", C.c_int32), ("tape_capacity", C.c_int32),
         ("bond_damping", _P),
+        ("contact_model", C.c_int32), ("contact_hm", C.c_double * 5),
     ]
 
 

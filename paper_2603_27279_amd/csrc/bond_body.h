@@ -20,8 +20,9 @@ namespace rodmx {
 
 // Bond (k, k+1) if particle k has one; energies only when asked.
 // With bond damping (d.bdamp set) the rates are taken against the measures
-// of the previous level, hist[(L - 1) & 1], and this level's go to
-// hist[L & 1], L being the level under evaluation.
+// of the previous level, hist[(L - 1) & 1] (from level hist_from on), and this
+// level's go to hist[L & 1] when the evaluation records them, L being the
+// level under evaluation.
 template <class R>
 __device__ __forceinline__ void bond_thread(const Dev& d, long k, int want_energy) {
   const long N = d.n;
@@ -37,7 +38,7 @@ __device__ __forceinline__ void bond_thread(const Dev& d, long k, int want_energ
     double hp[5];
     const double* hprev = d.hist + (long)((L - 1) & 1) * 5 * N;
     for (int c = 0; c < 5; ++c) hp[c] = hprev[c * N + k];
-    dm.hprev = d.hist_valid ? hp : nullptr;
+    dm.hprev = L >= d.hist_from ? hp : nullptr;
     dm.dv = ld3(d.v, N, k + 1) - ld3(d.v, N, k);
     dm.idt = 1.0 / d.dt;
     bond_one<double, R, true>(ld3(d.x, N, k), ld3(d.x, N, k + 1), ld4(d.q, N, k),
@@ -45,8 +46,10 @@ __device__ __forceinline__ void bond_thread(const Dev& d, long k, int want_energ
                               V3<double>{d.bref[k], d.bref[N + k], d.bref[2 * N + k]},
                               d.bref[3 * N + k], d.rodK + 4 * rod, F, Ts, Tbt,
                               want_energy ? e : nullptr, &dm);
-    double* hnow = d.hist + (long)(L & 1) * 5 * N;
-    for (int c = 0; c < 5; ++c) hnow[c * N + k] = dm.hnow[c];
+    if (d.hist_write) {
+      double* hnow = d.hist + (long)(L & 1) * 5 * N;
+      for (int c = 0; c < 5; ++c) hnow[c * N + k] = dm.hnow[c];
+    }
   } else {
     bond_one<double, R>(ld3(d.x, N, k), ld3(d.x, N, k + 1), ld4(d.q, N, k), ld4(d.q, N, k + 1),
                         V3<double>{d.bref[k], d.bref[N + k], d.bref[2 * N + k]},

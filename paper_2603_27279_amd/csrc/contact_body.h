@@ -249,6 +249,119 @@ __device__ __forceinline__ void contact_listed(const Dev& d, long blk, bool buil
   st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
 }
 
+// ---------------------------------------------------------------- Hertz-Mindlin
+// One Hertz-Mindlin contact of particle i with j (Methods, "Contact"; the
+// constants of two equal elastic spheres of diameter r_c), seen from i, with
+// n = (x_i - x_j) / r, overlap delta = r_c - r and a = sqrt(R* delta):
+//   normal force max(0, 4/3 E* a delta - g_n v_n), v the velocity of i's
+//     contact point relative to j's: (v_i - v_j) - r/2 (w_i + w_j) x n;
+//   tangential displacement s: zero for a new contact (sp null), else the
+//     previous s turned into the current tangent plane at its length, plus
+//     v_t dt; force -8 G* a s - g_t v_t, limited to mu times the normal force
+//     (s then holds the limited force);
+//   force on i F_n n + F_t, torque on i (and on j) (-r/2 n) x F_t.
+// Seen from j every vector changes sign exactly, so the pair's forces cancel.
+struct HmOut {
+  V3<double> F, T, s;
+  double e;  // normal elastic energy 8/15 E* sqrt(R*) delta^(5/2)
+};
+
+__device__ __forceinline__ HmOut hm_pair(const Dev& d, V3<double> xi, V3<double> xj, double r2,
+                                         V3<double> vi, V3<double> vj, V3<double> wi,
+                                         V3<double> wj, const V3<double>* sp) {
+  HmOut o;
+  const V3<double> dx = xi - xj;
+  const double r = sqrt(r2);
+  const V3<double> n = (1.0 / r) * dx;
+  const double delta = d.rc - r;
+  const double a = sqrt(d.hm_Rs * delta);
+  const double kn = 4.0 / 3.0 * d.hm_Es * a, kt = 8.0 * d.hm_Gs * a;
+  const V3<double> vrel = (vi - vj) - (0.5 * r) * cross(wi + wj, n);
+  const double vn = dot(vrel, n);
+  const V3<double> vt = vrel - vn * n;
+  const double Fn = fmax(0.0, kn * delta - d.hm_gn * vn);
+  V3<double> sv{0.0, 0.0, 0.0};
+  if (sp) {
+    const V3<double> p = *sp;
+    V3<double> st = p - dot(p, n) * n;
+    const double lt = sqrt(dot(st, st)), lp = sqrt(dot(p, p));
+    if (lt > 0.0) st = (lp / lt) * st;
+    sv = st + d.dt * vt;
+  }
+  V3<double> Ft = (-kt) * sv - d.hm_gt * vt;
+  const double ft = sqrt(dot(Ft, Ft)), fmx = d.hm_mu * Fn;
+  if (ft > fmx) {
+    Ft = (fmx / ft) * Ft;
+    sv = (-1.0 / kt) * (Ft + d.hm_gt * vt);
+  }
+  o.F = Fn * n + Ft;
+  o.T = cross((-0.5 * r) * n, Ft);
+  o.s = sv;
+  o.e = 8.0 / 15.0 * d.hm_Es * sqrt(d.hm_Rs) * delta * delta * sqrt(delta);
+  return o;
+}
+
+// Hertz-Mindlin contact force and torque of particle i: one thread walks the
+// 27 cells (the selection and exclusions of the Hookean search), looks each
+// contact up among i's contacts of the previous level (plane (L - 1) & 1, from
+// level hist_from on) and, when the evaluation records, writes i's contacts of
+// this level to plane L & 1 in the order found (lookups go by partner, so the
+// order never shows). Sums in fixed point, as in the other searches.
+template <int OUT>
+__device__ __forceinline__ void contact_hm_thread(const Dev& d, long blk) {
+  const long N = d.n;
+  const long i = d.i_lo + blk * blockDim.x + threadIdx.x;
+  if (i >= d.i_hi) return;
+  const V3<double> xi = ld3(d.x, N, i), vi = ld3(d.v, N, i), wi = ld3(d.w, N, i);
+  const int mem = d.mem[i], rod = d.rod[i];
+  const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
+  const double rc2 = d.rc * d.rc;
+  const long long L = d.step[d.lc];
+  const long pp = (long)((L - 1) & 1), pc = (long)(L & 1);
+  const int np = L >= d.hist_from ? min(d.hc_cnt[pp * N + i], HM_CAP) : 0;
+  const int* pj = d.hc_j + pp * HM_CAP * N;
+  const double* ps = d.hc_s + pp * 3 * HM_CAP * N;
+  int* cj = d.hc_j + pc * HM_CAP * N;
+  double* cs = d.hc_s + pc * 3 * HM_CAP * N;
+  long long fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0, fe = 0;
+  int cnt = 0;
+  for_cell_candidates(d, cell_tab(d, L), xi, mem, [&](int j, int rj, V3<double> xj) {
+    if (j == (int)i || j < mb || j >= me) return;
+    if (rj == rod && abs(j - (int)i) <= d.depth) return;
+    const double r2 = r2_exact(xi, xj);
+    if (!(r2 < rc2)) return;
+    V3<double> sprev;
+    bool found = false;
+    for (int k = 0; k < np; ++k)
+      if (pj[(long)k * N + i] == j) {
+        sprev = V3<double>{ps[(long)k * N + i], ps[(long)(HM_CAP + k) * N + i],
+                           ps[(long)(2 * HM_CAP + k) * N + i]};
+        found = true;
+      }
+    const HmOut o = hm_pair(d, xi, xj, r2, vi, ld3(d.v, N, j), wi, ld3(d.w, N, j),
+                            found ? &sprev : nullptr);
+    fx += to_fix(o.F.x); fy += to_fix(o.F.y); fz += to_fix(o.F.z);
+    tx += to_fix(o.T.x); ty += to_fix(o.T.y); tz += to_fix(o.T.z);
+    if (OUT == OUT_ENERGY) fe += to_fix(0.5 * o.e);  // each pair seen from both ends
+    if (d.hist_write) {
+      if (cnt < HM_CAP) {
+        cj[(long)cnt * N + i] = j;
+        cs[(long)cnt * N + i] = o.s.x;
+        cs[(long)(HM_CAP + cnt) * N + i] = o.s.y;
+        cs[(long)(2 * HM_CAP + cnt) * N + i] = o.s.z;
+      }
+      ++cnt;
+    }
+  });
+  if (d.hist_write) {
+    d.hc_cnt[pc * N + i] = min(cnt, HM_CAP);
+    if (cnt > HM_CAP) atomicOr(&d.flags[FLAG_HM_OVF], 1u);
+  }
+  st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
+  st3(d.cT, N, i, V3<double>{(double)tx / FIX, (double)ty / FIX, (double)tz / FIX});
+  if (OUT == OUT_ENERGY) d.cE[i] = (double)fe / FIX;
+}
+
 // Whether the lists must be rebuilt this step: asked by the host, or some
 // particle moved too far since the last build (flag of the level's parity).
 __device__ __forceinline__ bool lists_stale(const Dev& d, int build) {
@@ -262,8 +375,8 @@ inline unsigned contact_lane_blocks(const Dev& d) {
   return (unsigned)((32 * (d.i_hi - d.i_lo) + 255) / 256);
 }
 inline unsigned contact_blocks(const Dev& d) {
-  return d.n >= CONTACT_LANES_MAX_N ? (unsigned)((d.i_hi - d.i_lo + 255) / 256)
-                                    : contact_lane_blocks(d);
+  return d.n >= CONTACT_LANES_MAX_N || d.hm ? (unsigned)((d.i_hi - d.i_lo + 255) / 256)
+                                            : contact_lane_blocks(d);
 }
 
 }  // namespace rodmx

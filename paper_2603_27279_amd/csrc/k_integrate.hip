@@ -202,6 +202,7 @@ __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long
   const V3<double> bF0 = ld3(d.bF, N, i), bTs0 = ld3(d.bTs, N, i), bTb0 = ld3(d.bTbt, N, i);
   const V3<double> bF1 = ld3(d.bF, N, im), bTs1 = ld3(d.bTs, N, im), bTb1 = ld3(d.bTbt, N, im);
   const V3<double> cF = d.contact_on ? ld3(d.cF, N, i) : V3<double>{0.0, 0.0, 0.0};
+  const V3<double> cT = d.hm ? ld3(d.cT, N, i) : V3<double>{0.0, 0.0, 0.0};
   const double mass = d.mass[i], inertia = d.inertia[i];
   F = V3<double>{0.0, 0.0, 0.0};
   T = V3<double>{0.0, 0.0, 0.0};
@@ -234,7 +235,10 @@ __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long
                        f[5] * m.x + f[8] * m.y + f[11] * m.z};
     T = T + cross(m, B);
   }
-  if ((mask & 8) && d.contact_on) F = F + cF;
+  if ((mask & 8) && d.contact_on) {  // contact (Hertz-Mindlin: also its torque)
+    F = F + cF;
+    T = T + cT;
+  }
   if (mask & 16) {  // global viscous damping with the current (half-step) velocities
     F = F - (d.damping * mass) * p.v;
     T = T - (d.damping * inertia) * p.w;

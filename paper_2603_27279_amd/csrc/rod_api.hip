@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+static_assert(rodmx::HM_CAP == ROD_HM_MAX_CONTACTS, "Hertz-Mindlin capacity differs from rod.h");
 using namespace rodmx;
 
 static thread_local std::string g_err;
@@ -210,6 +211,18 @@ static int validate(const rod_desc* d) {
     if (any && d->tape_capacity > 0)
       return fail(ROD_E_INVALID, "bond damping is not differentiated: no tape with bond damping");
   }
+  if (d->contact_model != ROD_CONTACT_HOOKEAN && d->contact_model != ROD_CONTACT_HERTZ_MINDLIN)
+    return fail(ROD_E_INVALID, "contact_model must be ROD_CONTACT_HOOKEAN or _HERTZ_MINDLIN");
+  if (d->contact_on && d->contact_model == ROD_CONTACT_HERTZ_MINDLIN) {
+    const double* h = d->contact_hm;
+    for (int k = 0; k < 5; ++k)
+      if (!std::isfinite(h[k])) return fail(ROD_E_INVALID, "contact_hm must be finite");
+    if (!(h[0] > 0) || !(h[1] > -1.0 && h[1] <= 0.5) || !(h[2] >= 0) || !(h[3] >= 0) ||
+        !(h[4] >= 0))
+      return fail(ROD_E_INVALID, "Hertz-Mindlin needs E > 0, -1 < nu <= 0.5, mu, g_n, g_t >= 0");
+    if (d->tape_capacity > 0)
+      return fail(ROD_E_INVALID, "Hertz-Mindlin contact is not differentiated: no tape with it");
+  }
   if (d->tape_capacity > 0 && d->tape_every < 1)
     return fail(ROD_E_INVALID, "a tape needs tape_every >= 1");
   for (int r = 0; r < d->n_rods; ++r)
@@ -304,7 +317,10 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
   b += 8 * (size_t)max_slots * 6 * N + 8 * 4 * N;                               // dipole, contact
   if (d->precision == ROD_MIXED && d->dipole_on) b += 4 * (size_t)max_slots * 6 * N;  // FP32 slots
   b += 2 * (4 * cells + sizeof(CellSlot) * cells * CELL_CAP + 4 * OVF_CAP) + 4 * N;  // cells
-  if (d->contact_on && (long)N >= CONTACT_LANES_MAX_N) b += (4 * NBR_CAP + 4 + 24) * N;  // lists
+  const bool hm = d->contact_on && d->contact_model == ROD_CONTACT_HERTZ_MINDLIN;
+  if (d->contact_on && !hm && (long)N >= CONTACT_LANES_MAX_N)
+    b += (4 * NBR_CAP + 4 + 24) * N;                                            // lists
+  if (hm) b += (24 + 8 + 2 * HM_CAP * (4 + 24)) * N;                            // torque, contacts
   if (d->precision == ROD_MIXED && d->dipole_on) b += 48 * ((N + 63) / 64);  // chunk boxes
   if (d->bond_damping) b += 8 * 4 * R + 8 * 2 * 5 * N;                       // bond damping
   b += 8 * 18 * N + 8 * 9 * M;                                                  // energy
@@ -328,6 +344,15 @@ static int force_terms(rod_ctx* c, const Dev& d, int want_energy, int build) {
   return ROD_OK;
 }
 static int force_terms(rod_ctx* c, int want_energy) { return force_terms(c, c->d, want_energy, 1); }
+
+// Evaluations outside stepping (inspection, energies, tuning) leave the
+// recorded bond damping measures and Hertz-Mindlin contacts as they are: the
+// velocities they see are not the half-step ones of the step's evaluation.
+struct NoRecord {
+  rod_ctx* c;
+  explicit NoRecord(rod_ctx* ctx) : c(ctx) { c->d.hist_write = 0; }
+  ~NoRecord() { c->d.hist_write = 1; }
+};
 
 // n consecutive steps. Batched: pre, forces, then (kick, forces) for every
 // further step, and post; the fused kick ends one step and starts the next, and
@@ -586,7 +611,8 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   d.dt = dsc->dt; d.damping = dsc->damping; d.C = dsc->mu0_4pi; d.kc = dsc->k_contact;
   d.rc = dsc->r_contact; d.inv_cell = dsc->contact_on ? 1.0 / dsc->r_contact : 0.0;
   d.depth = dsc->exclude_depth; d.field_len = dsc->field_len;
-  d.use_lists = dsc->contact_on && (long)N >= CONTACT_LANES_MAX_N;
+  d.hm = dsc->contact_on && dsc->contact_model == ROD_CONTACT_HERTZ_MINDLIN;
+  d.use_lists = dsc->contact_on && !d.hm && (long)N >= CONTACT_LANES_MAX_N;
   d.skin = NBR_SKIN * dsc->r_contact;
   // with lists the 27 cells around a particle must cover the list cutoff r_c + skin
   if (d.use_lists) d.inv_cell = 1.0 / (dsc->r_contact + d.skin);
@@ -595,9 +621,24 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
        (rc = dalloc(c, &d.xb, 3 * (size_t)N)) || (rc = dalloc(c, &d.rebuild, 2))))
     return cleanup(rc);
   d.dipole_on = dsc->dipole_on != 0; d.contact_on = dsc->contact_on != 0;
+  d.cT = nullptr; d.hc_cnt = nullptr; d.hc_j = nullptr; d.hc_s = nullptr;
+  if (d.hm) {
+    const double E = dsc->contact_hm[0], nu = dsc->contact_hm[1];
+    d.hm_Es = E / (2.0 * (1.0 - nu * nu));
+    d.hm_Gs = E / (4.0 * (2.0 - nu) * (1.0 + nu));
+    d.hm_Rs = 0.25 * dsc->r_contact;
+    d.hm_mu = dsc->contact_hm[2]; d.hm_gn = dsc->contact_hm[3]; d.hm_gt = dsc->contact_hm[4];
+    if ((rc = dalloc(c, &d.cT, 3 * (size_t)N)) || (rc = dalloc(c, &d.hc_cnt, 2 * (size_t)N)) ||
+        (rc = dalloc(c, &d.hc_j, 2 * (size_t)HM_CAP * N)) ||
+        (rc = dalloc(c, &d.hc_s, 6 * (size_t)HM_CAP * N)))
+      return cleanup(rc);
+  }
+  // the first evaluation (at step0) has no previous level; all of stepping's
+  // and rod_init's evaluations record their measures and contacts
+  d.hist_from = dsc->step0 + 1;
+  d.hist_write = 1;
   d.bdamp = nullptr;
   d.hist = nullptr;
-  d.hist_valid = 0;
   if (dsc->bond_damping) {
     bool any = false;
     for (int k = 0; k < 4 * R; ++k) any = any || dsc->bond_damping[k] != 0;
@@ -634,22 +675,15 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   if ((rc = enter(c))) return cleanup(rc);
   if (forces_valid) {
     if (hipSuccess != launch_pre(c->d, PRE_PREPARE, c->s)) return cleanup(fail(ROD_E_HIP, "launch failed"));
-    // bond damping: record the measures of this level (the forces are the caller's)
+    // bond damping and Hertz-Mindlin contact: record the measures and contacts
+    // of this level (the forces are the caller's)
     if (c->d.bdamp && hipSuccess != launch_bond(c->d, dsc->precision, 0, c->s))
+      return cleanup(fail(ROD_E_HIP, "launch failed"));
+    if (c->d.hm && hipSuccess != launch_contact(c->d, 0, 1, c->s))
       return cleanup(fail(ROD_E_HIP, "launch failed"));
   } else if ((rc = enqueue_prepare(c))) {
     return cleanup(rc);
   }
-  if (c->d.bdamp) {
-    // both parity planes hold the initial level's measures, so that a further
-    // evaluation of that level finds no rates either
-    const size_t plane = 5 * (size_t)N;
-    const long p0 = (long)(dsc->step0 & 1);
-    if (hipMemcpyAsync(c->d.hist + (1 - p0) * plane, c->d.hist + p0 * plane,
-                       plane * sizeof(double), hipMemcpyDeviceToDevice, c->s) != hipSuccess)
-      return cleanup(fail(ROD_E_HIP, "copy failed"));
-  }
-  c->d.hist_valid = 1;  // later evaluations take rates against the recorded measures
   if ((rc = leave(c))) return cleanup(rc);
   if (forces_valid && d.contact_on) {
     // pre built the cell list without a force pass; empty it again
@@ -706,10 +740,12 @@ int rod_sync(rod_ctx* c) {
   HIPC(hipStreamSynchronize(c->s));
   unsigned f[4];
   HIPC(hipMemcpy(f, c->d.flags, sizeof(f), hipMemcpyDeviceToHost));
-  if (f[0] | f[1] | f[2]) {
+  if (f[0] | f[1] | f[2] | f[3]) {
     unsigned z[4] = {0, 0, 0, 0};
     HIPC(hipMemcpy(c->d.flags, z, sizeof(z), hipMemcpyHostToDevice));
     if (f[FLAG_NONFINITE]) return fail(ROD_E_NONFINITE, "non-finite force, torque or position");
+    if (f[FLAG_HM_OVF])
+      return fail(ROD_E_OVERFLOW, "a particle had more than %d Hertz-Mindlin contacts", HM_CAP);
     return fail(ROD_E_OVERFLOW, "contact search capacity exceeded: more than %d particles "
                 "landed in full cells", OVF_CAP);
   }
@@ -729,6 +765,7 @@ int rod_get_step(rod_ctx* c, int64_t* step) {
 int rod_eval_forces(rod_ctx* c, int32_t terms, double* F, double* T, double* B) {
   if (!c || !F || !T) return fail(ROD_E_INVALID, "NULL argument");
   if (terms < 0 || terms > ROD_TERM_ALL) return fail(ROD_E_INVALID, "bad term mask %d", terms);
+  NoRecord keep(c);
   TRY(enter(c));
   HIPC(launch_pre(c->d, PRE_EVAL, c->s));
   TRY(force_terms(c, 0));
@@ -739,6 +776,7 @@ int rod_eval_forces(rod_ctx* c, int32_t terms, double* F, double* T, double* B) 
 
 int rod_energy(rod_ctx* c, double* out, int32_t on_device) {
   if (!c || !out) return fail(ROD_E_INVALID, "NULL argument");
+  NoRecord keep(c);
   TRY(enter(c));
   HIPC(launch_pre(c->d, PRE_EVAL, c->s));
   TRY(force_terms(c, 1));
@@ -873,6 +911,7 @@ static void drop_graphs(rod_ctx* c) {
 static int time_eval(rod_ctx* c, double* us) {
   double* F = c->epart;  // scratch: [3N] force and [3N] torque
   double* T = c->epart + 3 * c->d.n;
+  NoRecord keep(c);
   auto eval = [&]() -> int {
     HIPC(launch_pre(c->d, PRE_EVAL, c->s));
     TRY(force_terms(c, 0));

@@ -42,11 +42,24 @@ struct Dev {
   float* dslotf;           // [S][6][N] the same partial sums on the mixed path (FP32), else null
   const double* bdamp;     // [R][4] bond damping factors g_r, g_s, g_t, g_b, or null (none)
   double* hist;            // [2][5][N] bond damping measures per level parity (bond k at k)
-  int hist_valid;          // the measures of the previous level exist
+  // Levels from hist_from on find the previous level's bond damping measures
+  // and Hertz-Mindlin contacts (the first evaluation of a run has none). Only
+  // the evaluations of stepping (and of rod_init) record them (hist_write).
+  long long hist_from;
+  int hist_write;
   const int* mslots;       // [M]: j ranges (partial slots) of each member
   int max_slots;           // largest entry of mslots; slots a member does not use stay zero
   double* cF;              // [3N] contact force
   double* cE;              // [N] contact energy per particle (energy evaluation only)
+  // Hertz-Mindlin contact (hm): E*, G*, R*, friction and dashpot coefficients,
+  // the contact torque, and each particle's contacts per level parity: count,
+  // partner and tangential displacement (seen from the particle).
+  int hm;
+  double hm_Es, hm_Gs, hm_Rs, hm_mu, hm_gn, hm_gt;
+  double* cT;              // [3N] contact torque (hm)
+  int* hc_cnt;             // [2][N]
+  int* hc_j;               // [2][HM_CAP][N]
+  double* hc_s;            // [2][3][HM_CAP][N]
   // Hashed cell lists, one for even and one for odd time levels, so that a
   // kernel can empty the list of one level while it fills that of the next.
   int* cell_cnt;           // [2][cells] particles hashed to each cell
@@ -62,7 +75,8 @@ struct Dev {
   double* xb;              // [3N] positions at the last build
   unsigned* rebuild;       // [2] per level parity: some particle moved too far since the build
   double skin;             // list cutoff is r_c + skin
-  unsigned* flags;         // [4]: [0] non-finite state, [2] overflow list full
+  unsigned* flags;         // [4]: [0] non-finite state, [2] overflow list full,
+                           // [3] a particle had more Hertz-Mindlin contacts than HM_CAP
   long long* step;         // [3]: [0] time level of the state (written by the particle
                            // kernel); [1], [2] level of the force evaluation in flight,
                            // in the entry named by lc. No kernel writes what it reads.
@@ -88,7 +102,8 @@ constexpr long CONTACT_LANES_MAX_N = 65536;     // below: lane-parallel cell sea
 constexpr double NBR_SKIN = 0.25;               // skin as a fraction of r_c
 constexpr double NBR_MOVE = 0.45;               // rebuild past this fraction of the skin
                                                 // (below 1/2, a margin for rounding)
-enum { FLAG_NONFINITE = 0, FLAG_LIST_OVF = 2 };
+constexpr int HM_CAP = 16;                      // Hertz-Mindlin contacts kept per particle
+enum { FLAG_NONFINITE = 0, FLAG_LIST_OVF = 2, FLAG_HM_OVF = 3 };
 
 // Cell of a coordinate (cells of side 1/inv), clamped so runaway coordinates
 // stay hashable.
@@ -155,8 +170,9 @@ hipError_t launch_contact(const Dev& d, int want_energy, int build, hipStream_t 
                           const hipEvent_t* ev = nullptr);
 // Dipole, bond and contact forces of a step in one launch.
 // Whether the contact search runs inside the fused force launch (lane-parallel
-// cell search of smaller systems) or in a launch of its own (candidate lists).
-inline bool contact_in_forces(const Dev& d) { return d.n < CONTACT_LANES_MAX_N; }
+// cell search of smaller systems, Hookean law) or in a launch of its own
+// (candidate lists of large systems, or the Hertz-Mindlin search).
+inline bool contact_in_forces(const Dev& d) { return d.n < CONTACT_LANES_MAX_N && !d.hm; }
 hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int nwork,
                          hipStream_t s, const hipEvent_t* ev = nullptr);
 // The whole force pass of a level: launch_forces, and for systems whose contact

@@ -14,6 +14,7 @@ import numpy as np
 from . import _lib as L
 
 _PRECISION = {"fp64": L.ROD_FP64, "mixed": L.ROD_MIXED}
+_CONTACT_MODEL = {"hookean": 0, "hertz_mindlin": 1}  # ROD_CONTACT_*
 
 
 def _ptr(t):
@@ -89,6 +90,9 @@ class RodSim:
         d.tape_capacity = int(tape_capacity)
         bd = self._host["bond_damping"]
         d.bond_damping = None if bd is None else bd.ctypes.data_as(C.c_void_p)
+        d.contact_model = _CONTACT_MODEL[w.get("contact_model", "hookean")]
+        if w.get("contact_hm") is not None:
+            d.contact_hm = (C.c_double * 5)(*[float(a) for a in w["contact_hm"]])
         self.desc = d
         b = L.RodBuffers()
         b.x, b.v, b.q, b.w = _ptr(self.x), _ptr(self.v), _ptr(self.q), _ptr(self.om)

@@ -83,7 +83,17 @@ def test_query_workspace_and_invalid_descriptors():
         (dict(bond_damping=np.array([[0.1, 0.0, np.inf, 0.0]])), "bond damping factors"),
         (dict(bond_damping=np.array([[0.0, 0.0, 0.0, 0.3]]), tape_capacity=10, tape_every=2),
          "no tape with bond damping"),
+        (dict(contact_model=2), "contact_model"),
     ]
+    hm = lambda *h: (C.c_double * 5)(*h)
+    cases += [
+        (dict(contact_model=1, contact_hm=hm(*h)), "Hertz-Mindlin needs")
+        for h in ((0, 0.3, 0.5, 0, 0), (10, 0.6, 0.5, 0, 0), (10, -1.0, 0.5, 0, 0),
+                  (10, 0.3, -0.1, 0, 0), (10, 0.3, 0.5, -1, 0), (10, 0.3, 0.5, 0, -1))
+    ]
+    cases += [(dict(contact_model=1, contact_hm=hm(10, 0.3, np.nan, 0, 0)), "finite"),
+              (dict(contact_model=1, contact_hm=hm(10, 0.3, 0.5, 0, 0), tape_capacity=10,
+                    tape_every=2), "no tape with it")]
     for over, msg in cases:
         d, keep = _desc(w, **over)
         ctx = C.c_void_p(1)
@@ -107,6 +117,23 @@ def test_bond_damping_descriptor():
     assert lib.rod_query_workspace(C.byref(d2), C.byref(nb2)) == L.ROD_OK
     assert nb2.value - nb.value == 8 * 4 * 1 + 8 * 10 * 64
     d3, keep3 = _desc(w, bond_damping=np.zeros((1, 4)), tape_capacity=10, tape_every=2)
+    assert lib.rod_query_workspace(C.byref(d3), C.byref(nb2)) == L.ROD_OK
+
+
+def test_hertz_mindlin_descriptor():
+    """Hertz-Mindlin adds a contact torque and two planes of 16 contacts per
+    particle (partner and tangential displacement) to the workspace; without
+    contact its parameters are not looked at."""
+    lib = L.load()
+    w = workloads.twisted_rod(n=64)
+    assert w["contact_on"]
+    nb, nb2 = C.c_size_t(), C.c_size_t()
+    d, keep = _desc(w)
+    assert lib.rod_query_workspace(C.byref(d), C.byref(nb)) == L.ROD_OK
+    d2, keep2 = _desc(w, contact_model=1, contact_hm=(C.c_double * 5)(10, 0.3, 0.5, 0.1, 0.1))
+    assert lib.rod_query_workspace(C.byref(d2), C.byref(nb2)) == L.ROD_OK
+    assert nb2.value - nb.value == (24 + 8 + 2 * 16 * (4 + 24)) * 64
+    d3, keep3 = _desc(w, contact_on=0, contact_model=1, tape_capacity=10, tape_every=2)
     assert lib.rod_query_workspace(C.byref(d3), C.byref(nb2)) == L.ROD_OK
 
 
