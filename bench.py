@@ -162,13 +162,17 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E (vendor figure)
 #     rod id and flags (5), outputs F, tau_s, tau_b+tau_t (72)
 #   bond with bond damping: the same, plus the velocity of one particle (24) and
 #     the five measures of the previous level read and of this level written (80)
+#   Hertz-Mindlin contact (per particle): own x, v, w (72), force and torque out
+#     (48), contact counts of the previous and this level (8); per contact, its
+#     previous and new partner and tangential displacement (56)
 #   contact (per particle): own position (24), list entry (8), force out (24)
 #   pre (per particle): state x v q w F T and m_body, inverse mass and inertia,
 #     ids (221 in); x v q w, m in FP64 and FP32, cell key and entry (180 out)
 #   kick (per particle): bond outputs of its bond (72), dipole slots (24 each on
 #     the mixed path, 48 in FP64), contact force, state and constants (318 + slots
 #     in); F T x v w q, m twice, cell key and entry (228 out)
-BYTES = {"bond": 165.0, "bond_damped": 269.0, "contact": 56.0, "pre": 401.0}
+BYTES = {"bond": 165.0, "bond_damped": 269.0, "contact": 56.0, "contact_hm": 128.0,
+         "contact_hm_per_contact": 56.0, "pre": 401.0}
 
 
 def kick_bytes(slots, slot_bytes=24.0):
@@ -228,7 +232,25 @@ def hbm_microbench(sizes, steps=10):
         sim.timing(False)
         sim.free()
         res["bond_damped"] = entry(1e3 * kt["bond"][0] / kt["bond"][1], n - R, BYTES["bond_damped"])
-        for k in ("bond", "bond_damped", "pre", "contact", "kick"):
+        # and the Hertz-Mindlin search, which walks the cells every step
+        wh = dict(w, contact_model="hertz_mindlin", contact_hm=np.array([200.0, 0.3, 0.5, 0.2, 0.2]))
+        sim = RodSim(wh, precision="mixed", graph_steps=0)
+        sim.launch_mode("separate")
+        sim.step(2)
+        timed = {}
+        for k in (1, steps + 1):
+            sim.timing(True)
+            sim.step(k)
+            timed[k] = sim.kernel_times()
+            sim.timing(False)
+        per = 2.0 * len(sim.contact_pairs()) / n
+        sim.free()
+        walk_us = 1e3 * (timed[steps + 1]["contact"][0] - timed[1]["contact"][0]) / steps
+        res["contact_hm"] = entry(walk_us, n,
+                                  BYTES["contact_hm"] + BYTES["contact_hm_per_contact"] * per)
+        res["contact_hm"]["contacts_per_particle"] = per
+        res["contact_hm"]["list_build_us"] = 1e3 * timed[1]["contact"][0]
+        for k in ("bond", "bond_damped", "contact_hm", "pre", "contact", "kick"):
             res[k]["frac_copy"] = res[k]["GB_s"] / copy["GB_s"]
         res["plain_copy"] = copy
         out.append(res)

@@ -301,14 +301,17 @@ __device__ __forceinline__ HmOut hm_pair(const Dev& d, V3<double> xi, V3<double>
   return o;
 }
 
-// Hertz-Mindlin contact force and torque of particle i: one thread walks the
-// 27 cells (the selection and exclusions of the Hookean search), looks each
-// contact up among i's contacts of the previous level (plane (L - 1) & 1, from
-// level hist_from on) and, when the evaluation records, writes i's contacts of
-// this level to plane L & 1 in the order found (lookups go by partner, so the
-// order never shows). Sums in fixed point, as in the other searches.
+// Hertz-Mindlin contact force and torque of particle i, one thread per
+// particle: the candidates are those of the Hookean search (same exact
+// selection and exclusions), from the 27 cells, or in large systems from the
+// particle's candidate list (built from the cells when `build`, see
+// contact_listed). Each contact is looked up among i's contacts of the
+// previous level (plane (L - 1) & 1, from level hist_from on); when the
+// evaluation records, i's contacts of this level go to plane L & 1 in the
+// order found (lookups go by partner, so the order never shows). Force and
+// torque are summed in fixed point, so cells and lists give the same bits.
 template <int OUT>
-__device__ __forceinline__ void contact_hm_thread(const Dev& d, long blk) {
+__device__ __forceinline__ void contact_hm_thread(const Dev& d, long blk, bool build) {
   const long N = d.n;
   const long i = d.i_lo + blk * blockDim.x + threadIdx.x;
   if (i >= d.i_hi) return;
@@ -325,9 +328,10 @@ __device__ __forceinline__ void contact_hm_thread(const Dev& d, long blk) {
   double* cs = d.hc_s + pc * 3 * HM_CAP * N;
   long long fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0, fe = 0;
   int cnt = 0;
-  for_cell_candidates(d, cell_tab(d, L), xi, mem, [&](int j, int rj, V3<double> xj) {
-    if (j == (int)i || j < mb || j >= me) return;
-    if (rj == rod && abs(j - (int)i) <= d.depth) return;
+  auto excluded = [&](int j, int rj) {
+    return j == (int)i || j < mb || j >= me || (rj == rod && abs(j - (int)i) <= d.depth);
+  };
+  auto visit = [&](int j, V3<double> xj) {
     const double r2 = r2_exact(xi, xj);
     if (!(r2 < rc2)) return;
     V3<double> sprev;
@@ -352,7 +356,33 @@ __device__ __forceinline__ void contact_hm_thread(const Dev& d, long blk) {
       }
       ++cnt;
     }
-  });
+  };
+  // one cell walk (which also rebuilds the candidate list when asked) or one
+  // list walk, so that the contact arithmetic is generated twice, not more
+  const bool lists = OUT != OUT_ENERGY && d.use_lists;
+  const int listed = lists && !build ? d.nbr_cnt[i] : -1;
+  if (listed >= 0) {
+    for (int k = 0; k < listed; ++k) {
+      const int j = d.nbr[(long)k * N + i];
+      visit(j, ld3(d.x, N, j));
+    }
+  } else {
+    const bool mk = lists && build;
+    const double rs = d.rc + d.skin, rs2 = rs * rs;
+    int nc = 0;
+    for_cell_candidates(d, cell_tab(d, L), xi, mem, [&](int j, int rj, V3<double> xj) {
+      if (excluded(j, rj)) return;
+      if (mk && r2_exact(xi, xj) < rs2) {
+        if (nc < NBR_CAP) d.nbr[(long)nc * N + i] = j;
+        ++nc;
+      }
+      visit(j, xj);
+    });
+    if (mk) {
+      d.nbr_cnt[i] = nc <= NBR_CAP ? nc : -1;
+      st3(d.xb, N, i, xi);
+    }
+  }
   if (d.hist_write) {
     d.hc_cnt[pc * N + i] = min(cnt, HM_CAP);
     if (cnt > HM_CAP) atomicOr(&d.flags[FLAG_HM_OVF], 1u);

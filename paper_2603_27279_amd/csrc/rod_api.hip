@@ -318,8 +318,7 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
   if (d->precision == ROD_MIXED && d->dipole_on) b += 4 * (size_t)max_slots * 6 * N;  // FP32 slots
   b += 2 * (4 * cells + sizeof(CellSlot) * cells * CELL_CAP + 4 * OVF_CAP) + 4 * N;  // cells
   const bool hm = d->contact_on && d->contact_model == ROD_CONTACT_HERTZ_MINDLIN;
-  if (d->contact_on && !hm && (long)N >= CONTACT_LANES_MAX_N)
-    b += (4 * NBR_CAP + 4 + 24) * N;                                            // lists
+  if (d->contact_on && (long)N >= CONTACT_LANES_MAX_N) b += (4 * NBR_CAP + 4 + 24) * N;  // lists
   if (hm) b += (24 + 8 + 2 * HM_CAP * (4 + 24)) * N;                            // torque, contacts
   if (d->precision == ROD_MIXED && d->dipole_on) b += 48 * ((N + 63) / 64);  // chunk boxes
   if (d->bond_damping) b += 8 * 4 * R + 8 * 2 * 5 * N;                       // bond damping
@@ -612,7 +611,7 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   d.rc = dsc->r_contact; d.inv_cell = dsc->contact_on ? 1.0 / dsc->r_contact : 0.0;
   d.depth = dsc->exclude_depth; d.field_len = dsc->field_len;
   d.hm = dsc->contact_on && dsc->contact_model == ROD_CONTACT_HERTZ_MINDLIN;
-  d.use_lists = dsc->contact_on && !d.hm && (long)N >= CONTACT_LANES_MAX_N;
+  d.use_lists = dsc->contact_on && (long)N >= CONTACT_LANES_MAX_N;
   d.skin = NBR_SKIN * dsc->r_contact;
   // with lists the 27 cells around a particle must cover the list cutoff r_c + skin
   if (d.use_lists) d.inv_cell = 1.0 / (dsc->r_contact + d.skin);
