@@ -35,10 +35,9 @@ __device__ __forceinline__ void bond_thread(const Dev& d, long k, int want_energ
     BondDamp dm;
     dm.gr = d.bdamp[4 * rod]; dm.gs = d.bdamp[4 * rod + 1];
     dm.gt = d.bdamp[4 * rod + 2]; dm.gb = d.bdamp[4 * rod + 3];
-    double hp[5];
     const double* hprev = d.hist + (long)((L - 1) & 1) * 5 * N;
-    for (int c = 0; c < 5; ++c) hp[c] = hprev[c * N + k];
-    dm.hprev = L >= d.hist_from ? hp : nullptr;
+    for (int c = 0; c < 5; ++c) dm.hprev[c] = hprev[c * N + k];
+    dm.rates = L >= d.hist_from;
     dm.dv = ld3(d.v, N, k + 1) - ld3(d.v, N, k);
     dm.idt = 1.0 / d.dt;
     bond_one<double, R, true>(ld3(d.x, N, k), ld3(d.x, N, k + 1), ld4(d.q, N, k),

@@ -17,11 +17,13 @@ template <> __device__ __forceinline__ double sqrt_(double a) { return sqrt(a); 
 
 // Bond damping of one evaluation (Methods "Damping"): the damping factors,
 // the measures of the previous time level (shear angle, twist, bend vector in
-// C'; null before the first evaluation: no rates), this level's measures
-// (written), the relative velocity v2 - v1 and 1 / dt.
+// C'; valid only with `rates`, none before the first evaluation), this level's
+// measures (written), the relative velocity v2 - v1 and 1 / dt. Held by value
+// (no pointers into it), so that it stays in registers.
 struct BondDamp {
   double gr, gs, gt, gb;
-  const double* hprev;
+  bool rates;
+  double hprev[5];
   double hnow[5];
   V3<double> dv;
   double idt;
@@ -70,7 +72,7 @@ __device__ __forceinline__ void bond_one(V3<H> x1, V3<H> x2, Q4<H> q1, Q4<H> q2,
     // undefined, sigma = 0)
     const H frad = H(Kr) * dr + H(dm->gr) * dot(qrot_inv(qc, V3<H>{dm->dv.x, dm->dv.y, dm->dv.z}), rhat);
     R ks = R(Ks) * g;
-    if (dm->hprev && sigma > R(0))
+    if (dm->rates && sigma > R(0))
       ks = ks + R(dm->gs) * (R)(((double)gamma - dm->hprev[0]) * dm->idt) / sigma;
     f = (R)frad * rh + (rR * ks) * cross(c, rh);
     ts = (R(0.5) * rR * rR * ks) * c;
@@ -96,7 +98,7 @@ __device__ __forceinline__ void bond_one(V3<H> x1, V3<H> x2, Q4<H> q1, Q4<H> q2,
     // twist and bend: + g_t psi-dot (the change taken modulo 2 pi) and
     // + g_b theta-dot per component in C'
     const double th[3] = {(double)(fac * bv.x), (double)(fac * bv.y), (double)(fac * bv.z)};
-    if (dm->hprev) {
+    if (dm->rates) {
       const double twopi = 6.28318530717958647692;
       double dpsi = (double)psi - dm->hprev[1];
       dpsi -= twopi * rint(dpsi / twopi);

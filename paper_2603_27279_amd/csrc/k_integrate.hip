@@ -191,8 +191,11 @@ __device__ __forceinline__ void dipole_sums(const Dev& d, long i, int mask, V3<d
 // Total force and torque on particle i from the terms in `mask` at level lvl
 // (bond, dipole, Zeeman, contact, damping, external), with the dipole force Fd
 // and field Bd from dipole_sums; the dipole field is written to Bo when given.
+// HM: the contact law is Hertz-Mindlin, whose contacts also exert a torque (a
+// template argument, so that the Hookean kernels carry no extra load).
 // Loads are unconditional where the index is valid, so they are all in flight
 // together.
+template <bool HM>
 __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long lvl, double* Bo,
                                        const PIn& p, V3<double> Fd, V3<double> Bd, V3<double>& F,
                                        V3<double>& T) {
@@ -202,7 +205,8 @@ __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long
   const V3<double> bF0 = ld3(d.bF, N, i), bTs0 = ld3(d.bTs, N, i), bTb0 = ld3(d.bTbt, N, i);
   const V3<double> bF1 = ld3(d.bF, N, im), bTs1 = ld3(d.bTs, N, im), bTb1 = ld3(d.bTbt, N, im);
   const V3<double> cF = d.contact_on ? ld3(d.cF, N, i) : V3<double>{0.0, 0.0, 0.0};
-  const V3<double> cT = d.hm ? ld3(d.cT, N, i) : V3<double>{0.0, 0.0, 0.0};
+  V3<double> cT{0.0, 0.0, 0.0};  // used only with HM
+  if constexpr (HM) cT = ld3(d.cT, N, i);
   const double mass = d.mass[i], inertia = d.inertia[i];
   F = V3<double>{0.0, 0.0, 0.0};
   T = V3<double>{0.0, 0.0, 0.0};
@@ -237,7 +241,7 @@ __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long
   }
   if ((mask & 8) && d.contact_on) {  // contact (Hertz-Mindlin: also its torque)
     F = F + cF;
-    T = T + cT;
+    if constexpr (HM) T = T + cT;
   }
   if (mask & 16) {  // global viscous damping with the current (half-step) velocities
     F = F - (d.damping * mass) * p.v;
@@ -269,6 +273,7 @@ __device__ __forceinline__ void kick(const Dev& d, long i, V3<double> F, V3<doub
   if (!finite3(F) || !finite3(T) || !finite3(p.x)) atomicOr(&d.flags[FLAG_NONFINITE], 1u);
 }
 
+template <bool HM>
 __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double* Fo, double* To,
                                               double* Bo) {
   const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -285,7 +290,7 @@ __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double*
   V3<double> Fd, Bd;
   dipole_sums(d, i, mask, Fd, Bd);
   V3<double> F, T;
-  gather(d, i, mask, lvl, Bo, p, Fd, Bd, F, T);
+  gather<HM>(d, i, mask, lvl, Bo, p, Fd, Bd, F, T);
   if (mode == POST_EVAL) {
     st3(Fo, N, i, F);
     st3(To, N, i, T);
@@ -303,6 +308,7 @@ __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double*
 // half-kick at level L = step[lc], then half-kick, drift, rotation, moments and
 // cell insertion for level L + 1 (written to step[3 - lc]). The cell list and
 // overflow list of level L are emptied while those of level L + 1 are filled.
+template <bool HM>
 __global__ __launch_bounds__(256) void k_kick(Dev d, double* Bo) {
   const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long L = d.step[d.lc];
@@ -319,7 +325,7 @@ __global__ __launch_bounds__(256) void k_kick(Dev d, double* Bo) {
     V3<double> Fd, Bd;
     dipole_sums(d, i, ROD_TERM_ALL, Fd, Bd);
     V3<double> F, T;
-    gather(d, i, ROD_TERM_ALL, L, Bo, p, Fd, Bd, F, T);
+    gather<HM>(d, i, ROD_TERM_ALL, L, Bo, p, Fd, Bd, F, T);
     // in place, the next half-kick overwrites v and w; out of place (a recorded
     // state) the full-step v and w stay with level L
     const bool apart = d.nx != nullptr;
@@ -388,14 +394,17 @@ hipError_t launch_pre(const Dev& d, int mode, hipStream_t s, const hipEvent_t* e
 hipError_t launch_post(const Dev& d, int mode, int mask, double* Fo, double* To, double* Bo,
                        hipStream_t s, const hipEvent_t* ev) {
   const int bs = particle_block(d.n);
-  launch_k(ev, k_post, dim3(blocks_for(d.i_hi - d.i_lo, bs)), dim3(bs), s, d, mode, mask, Fo, To,
-           Bo);
+  const dim3 g(blocks_for(d.i_hi - d.i_lo, bs)), b(bs);
+  if (d.hm) launch_k(ev, k_post<true>, g, b, s, d, mode, mask, Fo, To, Bo);
+  else launch_k(ev, k_post<false>, g, b, s, d, mode, mask, Fo, To, Bo);
   return hipGetLastError();
 }
 
 hipError_t launch_kick(const Dev& d, double* Bo, hipStream_t s, const hipEvent_t* ev) {
   const int bs = particle_block(d.n);
-  launch_k(ev, k_kick, dim3(blocks_for(d.i_hi - d.i_lo, bs)), dim3(bs), s, d, Bo);
+  const dim3 g(blocks_for(d.i_hi - d.i_lo, bs)), b(bs);
+  if (d.hm) launch_k(ev, k_kick<true>, g, b, s, d, Bo);
+  else launch_k(ev, k_kick<false>, g, b, s, d, Bo);
   return hipGetLastError();
 }
 

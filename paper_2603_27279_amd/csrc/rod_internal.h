@@ -42,24 +42,10 @@ struct Dev {
   float* dslotf;           // [S][6][N] the same partial sums on the mixed path (FP32), else null
   const double* bdamp;     // [R][4] bond damping factors g_r, g_s, g_t, g_b, or null (none)
   double* hist;            // [2][5][N] bond damping measures per level parity (bond k at k)
-  // Levels from hist_from on find the previous level's bond damping measures
-  // and Hertz-Mindlin contacts (the first evaluation of a run has none). Only
-  // the evaluations of stepping (and of rod_init) record them (hist_write).
-  long long hist_from;
-  int hist_write;
   const int* mslots;       // [M]: j ranges (partial slots) of each member
   int max_slots;           // largest entry of mslots; slots a member does not use stay zero
   double* cF;              // [3N] contact force
   double* cE;              // [N] contact energy per particle (energy evaluation only)
-  // Hertz-Mindlin contact (hm): E*, G*, R*, friction and dashpot coefficients,
-  // the contact torque, and each particle's contacts per level parity: count,
-  // partner and tangential displacement (seen from the particle).
-  int hm;
-  double hm_Es, hm_Gs, hm_Rs, hm_mu, hm_gn, hm_gt;
-  double* cT;              // [3N] contact torque (hm)
-  int* hc_cnt;             // [2][N]
-  int* hc_j;               // [2][HM_CAP][N]
-  double* hc_s;            // [2][3][HM_CAP][N]
   // Hashed cell lists, one for even and one for odd time levels, so that a
   // kernel can empty the list of one level while it fills that of the next.
   int* cell_cnt;           // [2][cells] particles hashed to each cell
@@ -93,6 +79,21 @@ struct Dev {
   int far_ok;
   double axis[3];
   long long period;
+  // ---- per-level history (bond damping, Hertz-Mindlin) and Hertz-Mindlin state
+  // Levels from hist_from on find the previous level's bond damping measures
+  // and Hertz-Mindlin contacts (the first evaluation of a run has none). Only
+  // the evaluations of stepping (and of rod_init) record them (hist_write).
+  long long hist_from;
+  int hist_write;
+  // Hertz-Mindlin contact (hm): E*, G*, R*, friction and dashpot coefficients,
+  // the contact torque, and each particle's contacts per level parity: count,
+  // partner and tangential displacement (seen from the particle).
+  int hm;
+  double hm_Es, hm_Gs, hm_Rs, hm_mu, hm_gn, hm_gt;
+  double* cT;              // [3N] contact torque (hm)
+  int* hc_cnt;             // [2][N]
+  int* hc_j;               // [2][HM_CAP][N]
+  double* hc_s;            // [2][3][HM_CAP][N]
 };
 
 constexpr int CELL_CAP = 8;
