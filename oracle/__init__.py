@@ -249,6 +249,42 @@ def run(w, nsteps, state=None, step0=0, mbody=None):
     return st
 
 
+def ramp(w, fields, max_steps, check_every, ke_tol, watch=(), state=None, step0=0):
+    """Quasi-static field ramp: for each field setting ``fields[k]`` ([M, 12],
+    B0 then G per member) step until every member's kinetic energy is at most
+    ``ke_tol`` after a chunk of ``check_every`` steps (at most ``max_steps``;
+    a negative ``ke_tol`` runs every setting for ``max_steps``).
+    ``state`` continues a previous run (prepared, forces of its last field);
+    otherwise the initial state is prepared with the first setting.
+    Returns dict(x_watch [n_inc, n_watch, 3], steps [n_inc], ke [n_inc, M],
+    state)."""
+    lib = _load()
+    sy = System(w)
+    n, M = sy.n, int(w["n_members"])
+    fields = _f64(fields, (-1, M, 12))
+    n_inc = fields.shape[0]
+    if state is None:
+        st = dict(x=_f64(w["x0"]).copy(), v=_f64(w["v0"]).copy(), q=_f64(w["q0"]).copy(),
+                  w=_f64(w["w0"]).copy(), F=np.zeros((n, 3)), T=np.zeros((n, 3)), step=step0)
+        prepared = 0
+    else:
+        st = {k: (np.array(v, dtype=np.float64, copy=True) if k != "step" else v)
+              for k, v in state.items() if k != "hist"}
+        prepared = 1
+    watch = np.ascontiguousarray(watch, dtype=np.int32)
+    xw = np.zeros((n_inc, max(len(watch), 1), 3))
+    steps = np.zeros(n_inc, np.int32)
+    ke = np.zeros((n_inc, M))
+    mb = _f64(w["m_body"], (n, 3))
+    lib.orc_ramp(sy.ref, _p(st["x"]), _p(st["v"]), _p(st["q"]), _p(st["w"]), _p(st["F"]),
+                 _p(st["T"]), _p(mb), _p(fields), C.c_int32(n_inc), C.c_int32(int(max_steps)),
+                 C.c_int32(int(check_every)), C.c_double(float(ke_tol)),
+                 C.c_int64(int(st["step"])), C.c_int32(prepared), _p(watch),
+                 C.c_int32(len(watch)), _p(xw), _p(steps), _p(ke))
+    st["step"] = int(st["step"]) + int(steps.sum())
+    return dict(x_watch=xw[:, :len(watch)], steps=steps, ke=ke, state=st)
+
+
 def run_jvp(w, nsteps, tangent, step0=0):
     """Forward-mode derivative of ``run`` from the raw initial inputs.
 

@@ -998,6 +998,65 @@ void orc_rows(const orc_system* s, const double* x, const double* q, const doubl
   }
 }
 
+// Quasi-static field ramp (the loading protocol of "Magnetized beams in
+// non-uniform fields" and of the helical rods with dipole-dipole interactions):
+// the field takes each of n_inc settings in turn ([n_inc][M][12], B0 and G per
+// member); from the first force evaluation after it is set, the system steps
+// with its damping, in chunks of check_every steps, until the kinetic energy
+// of every member (translational plus rotational, summed in particle order)
+// is at most ke_tol after a chunk, or max_steps have been taken (a negative
+// ke_tol never counts as rest). Then the
+// positions of the watched particles are recorded ([n_inc][n_watch][3]), with
+// the steps taken and the kinetic energies ([n_inc][M]). The state arrays hold
+// a prepared state on entry (its forces evaluated with the field before the
+// ramp) and the final one on return; bond damping measures and Hertz-Mindlin
+// contacts carry over from increment to increment.
+void orc_ramp(const orc_system* s, double* x, double* v, double* q, double* w, double* F,
+              double* Tq, const double* mbody, const double* fields, int32_t n_inc,
+              int32_t max_steps, int32_t check_every, double ke_tol, int64_t step0,
+              int32_t prepared, const int32_t* watch, int32_t n_watch, double* x_watch,
+              int32_t* steps, double* ke) {
+  Model md = build_model(s);
+  const int64_t FM = (int64_t)md.M * 12;
+  std::vector<double> field(fields, fields + FM);  // the setting in force
+  State<double> st;
+  st.x.assign(x, x + 3 * md.n); st.v.assign(v, v + 3 * md.n);
+  st.q.assign(q, q + 4 * md.n); st.w.assign(w, w + 3 * md.n);
+  st.F.assign(3 * md.n, 0.0); st.Tq.assign(3 * md.n, 0.0);
+  st.step = step0;
+  if (prepared) {
+    st.F.assign(F, F + 3 * md.n); st.Tq.assign(Tq, Tq + 3 * md.n);
+    const bool hm = md.contact_on && md.contact_model == 1;
+    if (md.bond_damp || hm) record_measures(md, st, mbody, field.data(), step0, md.bond_damp, hm);
+  } else {
+    prepare(md, st, mbody, field.data());
+  }
+  for (int32_t k = 0; k < n_inc; ++k) {
+    std::copy(fields + k * FM, fields + (k + 1) * FM, field.begin());
+    int32_t taken = 0;
+    std::vector<double> e(md.M, 0.0);
+    while (taken < max_steps) {
+      const int32_t chunk = std::min(check_every, max_steps - taken);
+      for (int32_t t = 0; t < chunk; ++t) step(md, st, mbody, field.data());
+      taken += chunk;
+      std::fill(e.begin(), e.end(), 0.0);
+      for (int p = 0; p < md.n; ++p)
+        e[md.member_of[p]] += 0.5 * md.mass[p] * dot(ld3(st.v.data(), p), ld3(st.v.data(), p)) +
+                              0.5 * md.inertia[p] * dot(ld3(st.w.data(), p), ld3(st.w.data(), p));
+      bool rest = true;
+      for (int m = 0; m < md.M; ++m) rest = rest && e[m] <= ke_tol;
+      if (rest) break;
+    }
+    if (steps) steps[k] = taken;
+    if (ke) std::copy(e.begin(), e.end(), ke + (int64_t)k * md.M);
+    for (int32_t a = 0; a < n_watch; ++a)
+      for (int c = 0; c < 3; ++c) x_watch[((int64_t)k * n_watch + a) * 3 + c] = st.x[3 * watch[a] + c];
+  }
+  std::copy(st.x.begin(), st.x.end(), x); std::copy(st.v.begin(), st.v.end(), v);
+  std::copy(st.q.begin(), st.q.end(), q); std::copy(st.w.begin(), st.w.end(), w);
+  std::copy(st.F.begin(), st.F.end(), F); std::copy(st.Tq.begin(), st.Tq.end(), Tq);
+}
+
 // Threads the OpenMP loops of this library use.
 int orc_threads(void) {
 #ifdef _OPENMP
