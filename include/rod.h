@@ -281,6 +281,32 @@ int rod_launch_mode(rod_ctx* c, int32_t mode);
  * work items, -1 the default rule. Invalidates captured graphs. */
 int rod_dipole_layout(rod_ctx* c, int32_t small, int32_t target_wgs);
 
+/* Quasi-static field ramp: the loading protocol of the magnetised beams in
+ * non-uniform fields and of the helical rods with dipole-dipole interactions
+ * (results sections "Magnetized beams in non-uniform fields" and "Helical rods
+ * with dipole-dipole interactions"): a field parameter is raised (and lowered)
+ * in increments and the damped system comes to rest at each one.
+ * For each of n_inc settings in turn, the context's field table (which must
+ * have field_len = 1; the caller's buffer is overwritten and holds the last
+ * setting on return) takes fields[k] (host [n_inc][M][12]: B0 then G,
+ * row-major, per member). From the first force evaluation after it is set the
+ * system steps (graphs as for rod_step) in chunks of check_every steps until,
+ * after a chunk, the kinetic energy of every member (translational plus
+ * rotational, from the state's velocities) is at most ke_tol, or max_steps
+ * steps have been taken; a negative ke_tol runs every setting for max_steps.
+ * Then the positions of the particles in watch (host [n_watch]) are written to
+ * x_watch (host [n_inc][n_watch][3]), the steps taken to steps (host
+ * [n_inc], nullable) and the members' kinetic energies to ke (host
+ * [n_inc][M], nullable). The ramp synchronises after every chunk.
+ * Errors: ROD_E_INVALID (NULL arguments, n_inc < 1, check_every < 1,
+ * max_steps < 1, ke_tol not a number, field_len != 1, a watch index outside
+ * [0, N)); ROD_E_STATE (a tape is being recorded); ROD_E_NONFINITE and
+ * ROD_E_OVERFLOW as reported by rod_sync after a chunk (the ramp stops there;
+ * outputs of earlier settings are written). */
+int rod_ramp(rod_ctx* c, const double* fields, int32_t n_inc, int32_t max_steps,
+             int32_t check_every, double ke_tol, const int32_t* watch, int32_t n_watch,
+             double* x_watch, int32_t* steps, double* ke);
+
 /* Release the context and its workspace (synchronises). NULL is accepted. */
 int rod_free(rod_ctx* c);
 

@@ -82,6 +82,7 @@ def load():
         "rod_autotune": [_P, C.c_char_p, i32, C.c_char_p, i32],
         "rod_dipole_layout": [_P, i32, i32],
         "rod_launch_mode": [_P, i32],
+        "rod_ramp": [_P, _P, i32, i32, i32, C.c_double, _P, i32, _P, _P, _P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

@@ -408,6 +408,46 @@ hipError_t launch_kick(const Dev& d, double* Bo, hipStream_t s, const hipEvent_t
   return hipGetLastError();
 }
 
+// Kinetic energy, translational plus rotational, of each member from the
+// state's velocities: one block per member, fixed-order tree sum.
+__global__ __launch_bounds__(256) void k_kinetic(Dev d, double* out) {
+  __shared__ double red[256];
+  const int mem = blockIdx.x;
+  const int b = d.mrange[2 * mem], e = d.mrange[2 * mem + 1];
+  const long N = d.n;
+  double s = 0.0;
+  for (int i = b + threadIdx.x; i < e; i += blockDim.x) {
+    const V3<double> v = ld3(d.v, N, i), w = ld3(d.w, N, i);
+    s += 0.5 * d.mass[i] * dot(v, v) + 0.5 * d.inertia[i] * dot(w, w);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[mem] = red[0];
+}
+
+// Positions of the listed particles, [n][3].
+__global__ __launch_bounds__(256) void k_gather_x(Dev d, const int* idx, int n, double* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const V3<double> x = ld3(d.x, d.n, idx[k]);
+  out[3 * k] = x.x; out[3 * k + 1] = x.y; out[3 * k + 2] = x.z;
+}
+
+hipError_t launch_kinetic(const Dev& d, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_kinetic, dim3(d.M), dim3(256), 0, s, d, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_x(const Dev& d, const int* idx, int n, double* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_x, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, idx, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_energy(const Dev& d, double* Epart, double* out, hipStream_t s) {
   // Epart holds [9][N] energy terms, then [3][N] dipole field, [3][N] and [3][N] scratch.
   double* Bd = Epart + 9 * d.n;

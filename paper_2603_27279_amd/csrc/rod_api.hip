@@ -1065,6 +1065,68 @@ extern "C" int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, c
   return ROD_OK;
 }
 
+// ------------------------------------------------------------------ ramp
+namespace {
+struct TmpDev {  // device memory of one call
+  void* p = nullptr;
+  ~TmpDev() { if (p) (void)hipFree(p); }
+};
+}  // namespace
+
+extern "C" int rod_ramp(rod_ctx* c, const double* fields, int32_t n_inc, int32_t max_steps,
+                        int32_t check_every, double ke_tol, const int32_t* watch, int32_t n_watch,
+                        double* x_watch, int32_t* steps, double* ke) {
+  if (!c || !fields) return fail(ROD_E_INVALID, "NULL argument");
+  if (n_inc < 1 || check_every < 1 || max_steps < 1 || n_watch < 0 || std::isnan(ke_tol))
+    return fail(ROD_E_INVALID, "need n_inc, check_every, max_steps >= 1, n_watch >= 0, ke_tol a number");
+  if (c->desc.field_len != 1) return fail(ROD_E_INVALID, "the ramp needs field_len = 1");
+  if (n_watch > 0 && (!watch || !x_watch)) return fail(ROD_E_INVALID, "watch and x_watch are required");
+  for (int32_t a = 0; a < n_watch; ++a)
+    if (watch[a] < 0 || watch[a] >= c->d.n) return fail(ROD_E_INVALID, "watch index %d out of range", watch[a]);
+  if (c->tape.active) return fail(ROD_E_STATE, "ramp while a tape is recorded");
+  const int M = c->d.M;
+  const size_t fbytes = sizeof(double) * 12 * (size_t)M;
+  TmpDev dk, dw, dx;
+  HIPC(hipMalloc(&dk.p, sizeof(double) * M));
+  if (n_watch > 0) {
+    HIPC(hipMalloc(&dw.p, sizeof(int32_t) * n_watch));
+    HIPC(hipMalloc(&dx.p, 3 * sizeof(double) * n_watch));
+    HIPC(hipMemcpy(dw.p, watch, sizeof(int32_t) * n_watch, hipMemcpyHostToDevice));
+  }
+  std::vector<double> e(M);
+  for (int32_t k = 0; k < n_inc; ++k) {
+    TRY(enter(c));
+    HIPC(hipMemcpyAsync(const_cast<double*>(c->d.field), fields + (size_t)k * 12 * M, fbytes,
+                        hipMemcpyHostToDevice, c->s));
+    TRY(leave(c));
+    int32_t taken = 0;
+    while (taken < max_steps) {
+      const int32_t chunk = std::min(check_every, max_steps - taken);
+      TRY(rod_step(c, chunk));
+      taken += chunk;
+      TRY(enter(c));
+      HIPC(launch_kinetic(c->d, (double*)dk.p, c->s));
+      HIPC(hipMemcpyAsync(e.data(), dk.p, sizeof(double) * M, hipMemcpyDeviceToHost, c->s));
+      TRY(leave(c));
+      TRY(rod_sync(c));  // waits for the copy and reports non-finite state or overflow
+      bool rest = true;
+      for (int m = 0; m < M; ++m) rest = rest && e[m] <= ke_tol;
+      if (rest) break;
+    }
+    if (steps) steps[k] = taken;
+    if (ke) std::copy(e.begin(), e.end(), ke + (size_t)k * M);
+    if (n_watch > 0) {
+      TRY(enter(c));
+      HIPC(launch_gather_x(c->d, (const int*)dw.p, n_watch, (double*)dx.p, c->s));
+      HIPC(hipMemcpyAsync(x_watch + (size_t)k * 3 * n_watch, dx.p, 3 * sizeof(double) * n_watch,
+                          hipMemcpyDeviceToHost, c->s));
+      TRY(leave(c));
+      HIPC(hipStreamSynchronize(c->s));
+    }
+  }
+  return ROD_OK;
+}
+
 int rod_free(rod_ctx* c) {
   if (!c) return ROD_OK;
   if (c->s) (void)hipStreamSynchronize(c->s);

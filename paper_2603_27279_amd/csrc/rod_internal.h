@@ -162,6 +162,9 @@ inline void launch_k(const hipEvent_t* ev, void (*kernel)(KArgs...), dim3 g, dim
 }
 
 hipError_t launch_pre(const Dev& d, int mode, hipStream_t s, const hipEvent_t* ev = nullptr);
+// Kinetic energy of each member into out[M]; positions of idx[0..n) into out[n][3].
+hipError_t launch_kinetic(const Dev& d, double* out, hipStream_t s);
+hipError_t launch_gather_x(const Dev& d, const int* idx, int n, double* out, hipStream_t s);
 hipError_t launch_bond(const Dev& d, int precision, int want_energy, hipStream_t s,
                        const hipEvent_t* ev = nullptr);
 hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int nwork,

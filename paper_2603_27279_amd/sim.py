@@ -153,6 +153,25 @@ class RodSim:
                                            C.byref(cnt)))
         return out[:P]
 
+    def ramp(self, fields, max_steps, check_every, ke_tol, watch=()):
+        """Quasi-static field ramp (rod_ramp): ``fields`` [n_inc, M, 12] settings
+        in turn, each held until every member's kinetic energy is at most
+        ``ke_tol`` after a chunk of ``check_every`` steps (at most ``max_steps``;
+        negative ``ke_tol``: always ``max_steps``). Needs a one-row field table.
+        Returns dict(x_watch [n_inc, n_watch, 3], steps [n_inc], ke [n_inc, M])."""
+        M = int(self.w["n_members"])
+        f = np.ascontiguousarray(fields, dtype=np.float64).reshape(-1, M, 12)
+        watch = np.ascontiguousarray(watch, dtype=np.int32).reshape(-1)
+        n_inc, nw = f.shape[0], len(watch)
+        xw = np.zeros((n_inc, max(nw, 1), 3))
+        steps = np.zeros(n_inc, np.int32)
+        ke = np.zeros((n_inc, M))
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        L.check(self.lib.rod_ramp(self.ctx, p(f), n_inc, int(max_steps), int(check_every),
+                                  float(ke_tol), p(watch) if nw else None, nw, p(xw), p(steps),
+                                  p(ke)))
+        return dict(x_watch=xw[:, :nw], steps=steps, ke=ke)
+
     def tape_begin(self):
         L.check(self.lib.rod_tape_begin(self.ctx))
 

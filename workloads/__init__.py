@@ -50,7 +50,8 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["make", "CONFIGS", "straight_rods", "cilia_carpet", "rod_array",
-           "ensemble", "adjoint_rod", "cantilever", "twisted_rod"]
+           "ensemble", "adjoint_rod", "cantilever", "twisted_rod", "magnetic_helix",
+           "helix_ramp_fields"]
 
 
 def _field_const(n_members, b0, g=None, length=1):
@@ -231,6 +232,56 @@ def ensemble(members=64, n=4096, seed=55, E_range=(0.5, 2.0), m_range=(0.01, 0.0
               name=f"ensemble_{members}x{n}")
     w.update(kw)
     return _perturb(w, rng, sigma)
+
+
+def magnetic_helix(gamma=4e-4, n_bonds=103, length=103.0, turns=1.64, pitch_angle=0.96,
+                   d=2.0, E=1.0, nu=0.5, rho=1.0, friction=0.5, damping=2e-3, dt=0.1, **kw):
+    """The helical rod with intra-rod dipole attraction of the paper's results
+    ("Helical rods with dipole-dipole interactions"): arc length ``length`` in
+    ``n_bonds`` bonds, length / (2 pi R) = ``turns``, pitch angle psi =
+    ``pitch_angle`` pi / 2, r(s) = (R cos Ks, R sin Ks, -s cos psi) with
+    K = sin(psi) / R, hanging from the clamped base particle at the origin
+    (z = 0), the screw axis along z. Rod diameter ``d``; each particle stands for
+    a cylindrical segment of the rod and carries the moment M A l along +z, with
+    the magnetisation M from gamma = mu0 M^2 / E. Hertz-Mindlin contact at
+    r_c = d between particles more than three apart along the rod; the field is
+    set by ``helix_ramp_fields``."""
+    R = length / (2.0 * np.pi * turns)
+    psi = pitch_angle * np.pi / 2.0
+    K = np.sin(psi) / R
+    s = np.arange(n_bonds + 1) * (length / n_bonds)
+    x = np.stack([R * np.cos(K * s), R * np.sin(K * s), -s * np.cos(psi)], 1)
+    n = n_bonds + 1
+    mu0 = 4.0 * np.pi  # mu0 / 4 pi = 1
+    M = np.sqrt(gamma * E / mu0)
+    A, l = np.pi * d * d / 4.0, length / n_bonds
+    mb = np.tile([0.0, 0.0, M * A * l], (n, 1))
+    bc = np.zeros(n, np.int8)
+    bc[0] = 1
+    w = _base(x, np.array([0, n], np.int32), np.zeros(1, np.int32), [d, rho, E, nu], mb, bc,
+              _field_const(1, (0, 0, 0)), dipole_on=True, contact_on=True, r_contact=d,
+              exclude_depth=3, contact_model="hertz_mindlin",
+              contact_hm=np.array([E, nu, friction, 0.0, 0.0]), damping=damping, dt=dt,
+              steps=1000, precision="fp64", name=f"magnetic_helix_g{gamma:g}",
+              helix=dict(gamma=gamma, E=E, d=d, length=length, mu0=mu0))
+    w.update(kw)
+    return w
+
+
+def helix_ramp_fields(w, lams):
+    """Field settings [n_inc, 1, 12] of the helix ramp: the potential
+    -(b / mu0) ((x^2 + y^2) / 4 - z^2 / 2) gives B = b (x/2, y/2, -z), a constant
+    gradient b diag(1/2, 1/2, -1) along the screw axis, with the prefactor
+    b = sqrt(mu0 / (gamma E)) (E I / A) (lambda_m / L)^3 for each lambda_m."""
+    h = w["helix"]
+    EI_A = h["E"] * h["d"] ** 2 / 16.0  # I / A = d^2 / 16 for a circular section
+    lams = np.asarray(lams, dtype=np.float64)
+    b = np.sqrt(h["mu0"] / (h["gamma"] * h["E"])) * EI_A * (lams / h["length"]) ** 3
+    f = np.zeros((len(lams), 1, 12))
+    f[:, 0, 3] = 0.5 * b
+    f[:, 0, 7] = 0.5 * b
+    f[:, 0, 11] = -b
+    return f
 
 
 # Full-size workloads (name -> builder with defaults).
