@@ -392,6 +392,104 @@ __device__ __forceinline__ void contact_hm_thread(const Dev& d, long blk, bool b
   if (OUT == OUT_ENERGY) d.cE[i] = (double)fe / FIX;
 }
 
+// The same, lane-parallel for systems below the list size: half a wavefront
+// per particle, lane c (0..26) scanning neighbouring cell c and lane 27 the
+// overflow list, as in contact_pass. A contact's slot in this level's plane is
+// taken with an LDS counter per particle, so slots fill in whatever order the
+// lanes find contacts; lookups go by partner and the sums are fixed point, so
+// nothing depends on that order. Workgroups of 256 threads (8 particles).
+template <int OUT>
+__device__ __forceinline__ void contact_hm_lanes(const Dev& d, long blk) {
+  __shared__ int slots[8];
+  const long N = d.n;
+  const int lane = threadIdx.x & 31, sub = threadIdx.x >> 5;
+  const long i = d.i_lo + ((blk * blockDim.x + threadIdx.x) >> 5);
+  const bool pv = i < d.i_hi;
+  const long ii = pv ? i : d.i_lo;
+  const V3<double> xi = ld3(d.x, N, ii), vi = ld3(d.v, N, ii), wi = ld3(d.w, N, ii);
+  const int mem = d.mem[ii], rod = d.rod[ii];
+  const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
+  const double rc2 = d.rc * d.rc;
+  const long long L = d.step[d.lc];
+  const long pp = (long)((L - 1) & 1), pc = (long)(L & 1);
+  const int np = pv && L >= d.hist_from ? min(d.hc_cnt[pp * N + ii], HM_CAP) : 0;
+  const int* pj = d.hc_j + pp * HM_CAP * N;
+  const double* ps = d.hc_s + pp * 3 * HM_CAP * N;
+  int* cj = d.hc_j + pc * HM_CAP * N;
+  double* cs = d.hc_s + pc * 3 * HM_CAP * N;
+  const int cx = cell_coord(xi.x, d.inv_cell), cy = cell_coord(xi.y, d.inv_cell),
+            cz = cell_coord(xi.z, d.inv_cell);
+  const int c = lane < 27 ? lane : 0;
+  const unsigned key = cell_hash(cx + c % 3 - 1, cy + (c / 3) % 3 - 1, cz + c / 9 - 1, mem,
+                                 d.cell_mask);
+  const CellTab tab = cell_tab(d, L);
+  bool scan = pv && lane < 27;
+  for (int o = 0; o < 26; ++o) {  // stand down if a lower lane has the same bucket
+    unsigned ko = __shfl(key, o, 32);
+    if (o < lane && ko == key) scan = false;
+  }
+  if (lane == 0) slots[sub] = 0;
+  __syncthreads();
+  long long fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0, fe = 0;
+  auto take = [&](int j, int rj, V3<double> xj) {
+    if (j == (int)i || j < mb || j >= me) return;
+    if (rj == rod && abs(j - (int)i) <= d.depth) return;
+    const double r2 = r2_exact(xi, xj);
+    if (!(r2 < rc2)) return;
+    V3<double> sprev;
+    bool found = false;
+    for (int k = 0; k < np; ++k)
+      if (pj[(long)k * N + i] == j) {
+        sprev = V3<double>{ps[(long)k * N + i], ps[(long)(HM_CAP + k) * N + i],
+                           ps[(long)(2 * HM_CAP + k) * N + i]};
+        found = true;
+      }
+    const HmOut o = hm_pair(d, xi, xj, r2, vi, ld3(d.v, N, j), wi, ld3(d.w, N, j),
+                            found ? &sprev : nullptr);
+    fx += to_fix(o.F.x); fy += to_fix(o.F.y); fz += to_fix(o.F.z);
+    tx += to_fix(o.T.x); ty += to_fix(o.T.y); tz += to_fix(o.T.z);
+    if (OUT == OUT_ENERGY) fe += to_fix(0.5 * o.e);
+    if (d.hist_write) {
+      const int k = atomicAdd(&slots[sub], 1);
+      if (k < HM_CAP) {
+        cj[(long)k * N + i] = j;
+        cs[(long)k * N + i] = o.s.x;
+        cs[(long)(HM_CAP + k) * N + i] = o.s.y;
+        cs[(long)(2 * HM_CAP + k) * N + i] = o.s.z;
+      }
+    }
+  };
+  if (scan) {
+    const CellSlot* sl = tab.slot + (long)key * CELL_CAP;
+    const int nb = min(tab.cnt[key], CELL_CAP);
+    for (int q = 0; q < nb; ++q) {
+      const CellSlot e = sl[q];
+      take((int)(e.tag & 0xffffffffll), (int)(e.tag >> 32), V3<double>{e.x, e.y, e.z});
+    }
+  }
+  if (pv && lane == 27) {  // particles whose cell was full
+    const int no = min(*tab.ovf_cnt, OVF_CAP);
+    for (int o = 0; o < no; ++o) {
+      const int j = tab.ovf[o];
+      take(j, d.rod[j], ld3(d.x, N, j));
+    }
+  }
+  __syncthreads();
+  fx = half_sum(fx); fy = half_sum(fy); fz = half_sum(fz);
+  tx = half_sum(tx); ty = half_sum(ty); tz = half_sum(tz);
+  if (OUT == OUT_ENERGY) fe = half_sum(fe);
+  if (pv && lane == 0) {
+    st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
+    st3(d.cT, N, i, V3<double>{(double)tx / FIX, (double)ty / FIX, (double)tz / FIX});
+    if (OUT == OUT_ENERGY) d.cE[i] = (double)fe / FIX;
+    if (d.hist_write) {
+      const int cnt = slots[sub];
+      d.hc_cnt[pc * N + i] = min(cnt, HM_CAP);
+      if (cnt > HM_CAP) atomicOr(&d.flags[FLAG_HM_OVF], 1u);
+    }
+  }
+}
+
 // Whether the lists must be rebuilt this step: asked by the host, or some
 // particle moved too far since the last build (flag of the level's parity).
 __device__ __forceinline__ bool lists_stale(const Dev& d, int build) {
@@ -405,8 +503,8 @@ inline unsigned contact_lane_blocks(const Dev& d) {
   return (unsigned)((32 * (d.i_hi - d.i_lo) + 255) / 256);
 }
 inline unsigned contact_blocks(const Dev& d) {
-  return d.n >= CONTACT_LANES_MAX_N || d.hm ? (unsigned)((d.i_hi - d.i_lo + 255) / 256)
-                                            : contact_lane_blocks(d);
+  return d.n >= CONTACT_LANES_MAX_N ? (unsigned)((d.i_hi - d.i_lo + 255) / 256)
+                                    : contact_lane_blocks(d);
 }
 
 }  // namespace rodmx

@@ -21,6 +21,12 @@ __global__ __launch_bounds__(256) void k_contact_hm(Dev d, int build) {
 __global__ __launch_bounds__(256) void k_contact_hm_e(Dev d) {
   contact_hm_thread<OUT_ENERGY>(d, blockIdx.x, false);
 }
+__global__ __launch_bounds__(256) void k_contact_hm_lanes(Dev d) {
+  contact_hm_lanes<OUT_FORCE>(d, blockIdx.x);
+}
+__global__ __launch_bounds__(256) void k_contact_hm_lanes_e(Dev d) {
+  contact_hm_lanes<OUT_ENERGY>(d, blockIdx.x);
+}
 __global__ __launch_bounds__(256) void k_contact_pairs(Dev d, int* pairs, int cap, int* count) {
   contact_pass<OUT_PAIRS>(d, blockIdx.x, pairs, cap, count);
 }
@@ -43,8 +49,14 @@ hipError_t launch_contact(const Dev& d, int want_energy, int build, hipStream_t 
                           const hipEvent_t* ev) {
   if (!d.contact_on) return hipSuccess;
   if (d.hm) {
-    if (want_energy) launch_k(ev, k_contact_hm_e, dim3(contact_blocks(d)), dim3(256), s, d);
-    else launch_k(ev, k_contact_hm, dim3(contact_blocks(d)), dim3(256), s, d, build);
+    const dim3 g(contact_blocks(d));
+    if (d.n < CONTACT_LANES_MAX_N) {
+      if (want_energy) launch_k(ev, k_contact_hm_lanes_e, g, dim3(256), s, d);
+      else launch_k(ev, k_contact_hm_lanes, g, dim3(256), s, d);
+    } else {
+      if (want_energy) launch_k(ev, k_contact_hm_e, g, dim3(256), s, d);
+      else launch_k(ev, k_contact_hm, g, dim3(256), s, d, build);
+    }
     return hipGetLastError();
   }
   if (d.n >= CONTACT_LANES_MAX_N) {
