@@ -280,6 +280,48 @@ def copy_bandwidth(mib=512, reps=20):
     return {"MiB_each_way": mib, "us": us, "GB_s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
 
 
+def helix_loop(gamma, ke_tol=1e-9, max_steps=200_000, check_every=2000, dlam=0.1, lam_max=3.5,
+               precision="mixed"):
+    """The magnetic helix's loading-unloading cycle (results, "Helical rods with
+    dipole-dipole interactions"): lambda_m from 0 to lam_max and back in steps
+    of dlam, each setting held by the quasi-static ramp (rod_ramp) until the
+    helix is at rest. Reports the distance between the helix ends along the
+    screw axis over L for every setting, the steps each took, and where the
+    largest jumps occur on the way up (detachment) and down (contraction).
+    Prints one progress line per setting to stderr."""
+    import torch
+    import workloads
+    from paper_2603_27279_amd import RodSim
+    up = np.round(np.arange(0.0, lam_max + 1e-9, dlam), 10)
+    lams = np.concatenate([up, up[::-1][1:]])
+    w = workloads.magnetic_helix(gamma=gamma)
+    f = workloads.helix_ramp_fields(w, lams)
+    sim = RodSim(dict(w, field=f[:1]), precision=precision, graph_steps=100)
+    t0 = time.perf_counter()
+    dist, steps = [], []
+    for k in range(len(lams)):
+        r = sim.ramp(f[k:k + 1], max_steps=max_steps, check_every=check_every, ke_tol=ke_tol,
+                     watch=[0, w["n"] - 1])
+        dist.append(float(abs(r["x_watch"][0, 1, 2] - r["x_watch"][0, 0, 2]) / w["helix"]["length"]))
+        steps.append(int(r["steps"][0]))
+        print(f"helix gamma={gamma:g} lambda_m={lams[k]:.2f}: distance/L {dist[-1]:.4f}, "
+              f"{steps[-1]} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.free()
+    n = len(up)
+    d_up, d_down = np.array(dist[:n]), np.array(dist[n - 1:][::-1])
+    jump_up = int(np.argmax(np.diff(d_up))) + 1
+    jump_down = int(np.argmax(-np.diff(d_down[::-1]))) + 1
+    return {"workload": f"magnetic helix, N = {w['n']}, gamma = {gamma:g}, {precision}",
+            "lambda_m": up.tolist(), "distance_up": d_up.tolist(), "distance_down": d_down.tolist(),
+            "steps": steps, "settings_at_step_limit": int(sum(s >= max_steps for s in steps)),
+            "detach_lambda_m": float(up[jump_up]),
+            "contract_lambda_m": float(up[::-1][jump_down]),
+            "total_steps": int(sum(steps)), "wall_s": wall,
+            "us_per_step": 1e6 * wall / max(1, sum(steps))}
+
+
 def copy_calibration():
     """A plain device copy of a known size (256 MiB read, 256 MiB written, three
     times), for scaling the FETCH_SIZE and WRITE_SIZE counters to bytes."""
@@ -321,9 +363,15 @@ def main():
                          "particles per rod): 64 -> 4.2M particles, 128 -> 16.8M")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
+    ap.add_argument("--helix-loop", type=float, default=None, metavar="GAMMA",
+                    help="only run the magnetic helix's quasi-static loading-unloading cycle "
+                         "at this dipole strength (about 3 minutes) and print it as JSON")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.helix_loop is not None:
+        print(json.dumps({"helix_loop": helix_loop(args.helix_loop)}))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
