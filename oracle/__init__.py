@@ -48,6 +48,7 @@ class _System(C.Structure):
         ("dipole_on", C.c_int32), ("contact_on", C.c_int32), ("exclude_depth", C.c_int32),
         ("bond_damping", C.c_void_p),
         ("contact_model", C.c_int32), ("contact_hm", C.c_double * 5),
+        ("dipole_cutoff", C.c_double),
     ]
 
 
@@ -108,6 +109,7 @@ class System:
         s.dipole_on = int(bool(w["dipole_on"])); s.contact_on = int(bool(w["contact_on"]))
         s.exclude_depth = int(w["exclude_depth"])
         s.bond_damping = _p(keep["bond_damping"])
+        s.dipole_cutoff = float(w.get("dipole_cutoff") or 0.0)
         s.contact_model = contact_model(w)
         if s.contact_model == 1:
             s.contact_hm = (C.c_double * 5)(*[float(a) for a in w["contact_hm"]])
@@ -295,6 +297,8 @@ def run_jvp(w, nsteps, tangent, step0=0):
         raise NotImplementedError("the forward-mode run does not differentiate bond damping")
     if w["contact_on"] and contact_model(w) != 0:
         raise NotImplementedError("the forward-mode run does not differentiate Hertz-Mindlin contact")
+    if w.get("dipole_cutoff"):
+        raise NotImplementedError("the forward-mode run does not differentiate the dipole cutoff")
     lib = _load()
     sy = System(w)
     n = sy.n

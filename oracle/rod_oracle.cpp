@@ -158,6 +158,9 @@ struct Model {
   // damping coefficients gn, gt.
   int contact_model = 0;
   double hmE = 0, hmNu = 0, hmMu = 0, hmGn = 0, hmGt = 0;
+  // Dipole-dipole cutoff: 0 for every pair of a member; otherwise only pairs
+  // with r^2 = (dx dx + dy dy) + dz dz < dcut^2 interact.
+  double dcut = 0;
 };
 
 // Tangential displacement history of Hertz-Mindlin contacts: for particle i,
@@ -190,6 +193,7 @@ struct orc_system {
   const double* bond_damping;  // [R][4] g_r, g_s, g_t, g_b, or NULL
   int32_t contact_model;       // 0 Hookean, 1 Hertz-Mindlin
   double contact_hm[5];        // Hertz-Mindlin: E, nu, mu, g_n, g_t
+  double dipole_cutoff;        // 0: all pairs of a member; > 0: pairs closer than this
 };
 
 }  // extern "C"
@@ -261,6 +265,7 @@ static Model build_model(const orc_system* s) {
   m.contact_model = s->contact_model;
   m.hmE = s->contact_hm[0]; m.hmNu = s->contact_hm[1]; m.hmMu = s->contact_hm[2];
   m.hmGn = s->contact_hm[3]; m.hmGt = s->contact_hm[4];
+  m.dcut = s->dipole_cutoff;
   return m;
 }
 
@@ -514,7 +519,9 @@ void forces(const Model& md, const T* x, const T* q, const T* v, const T* w,
   }
 
   // Dipole-dipole, every ordered pair i != j of a member (Methods, "Magnetic
-  // interactions"). With r = x_i - x_j, U = C/r^3 [mi.mj - 3 (mi.r^)(mj.r^)];
+  // interactions"), or with a cutoff only the pairs closer than it (the
+  // truncated pair interaction the paper's simulations use). With
+  // r = x_i - x_j, U = C/r^3 [mi.mj - 3 (mi.r^)(mj.r^)];
   // F_i = -dU/dx_i; the field of j at x_i is C (3 (mj.r) r / r^5 - mj / r^3);
   // the torque is m_i x B_i.
   std::vector<T> Bd(3 * N, T(0.0));
@@ -530,6 +537,7 @@ void forces(const Model& md, const T* x, const T* q, const T* v, const T* w,
         V3<T> mj = ld3(mu, j);
         V3<T> r = xi - ld3(x, j);
         T r2 = dot(r, r);
+        if (md.dcut > 0.0 && !(val(r2) < md.dcut * md.dcut)) continue;
         T rinv = T(1.0) / sqrt(r2);
         T rinv3 = rinv * rinv * rinv;
         T rinv5 = rinv3 * rinv * rinv;
@@ -849,7 +857,7 @@ void orc_energy(const orc_system* s, const double* x, const double* q, const dou
     int mem = md.member_of[i];
     for (int j = i + 1; j < md.member_end[mem]; ++j) {
       V3<double> r = ld3(x, i) - ld3(x, j);
-      if (md.dipole_on) {
+      if (md.dipole_on && (md.dcut == 0.0 || (r.x * r.x + r.y * r.y) + r.z * r.z < md.dcut * md.dcut)) {
         double rr = norm(r);
         V3<double> rh = (1.0 / rr) * r;
         V3<double> mi = ld3(mu.data(), i), mj = ld3(mu.data(), j);
@@ -977,7 +985,7 @@ void orc_rows(const orc_system* s, const double* x, const double* q, const doubl
     for (int j = md.member_begin[mem]; j < md.member_end[mem]; ++j) {
       if (j == i) continue;
       V3<double> r = xi - ld3(x, j);
-      if (md.dipole_on) {
+      if (md.dipole_on && (md.dcut == 0.0 || dot(r, r) < md.dcut * md.dcut)) {
         V3<double> mj = ld3(mu.data(), j);
         double r2 = dot(r, r);
         double rinv = 1.0 / std::sqrt(r2);

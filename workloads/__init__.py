@@ -28,7 +28,8 @@ ext_force         float64 [N, 3] or None       constant external force per parti
 ext_torque        float64 [N, 3] or None       constant external torque per particle
 dt, damping       float                        time step; global viscous damping coefficient c
 mu0_4pi           float                        dipole prefactor mu0 / (4 pi)
-dipole_on         bool                         all-pairs dipole-dipole interaction within a member
+dipole_on         bool                         dipole-dipole interaction within a member
+dipole_cutoff     float                        0: every pair of a member; > 0: pairs closer than this
 contact_on        bool                         contact between non-excluded pairs
 contact_model     str                          "hookean" (normal, k_contact) or "hertz_mindlin"
 contact_hm        float64 [5] or None          Hertz-Mindlin: contact modulus E, Poisson nu, friction
@@ -79,7 +80,7 @@ def _base(x_ref, rod_offset, rod_member, rod_params, m_body, bc, field, **kw):
         drive_axis=np.array([1.0, 0.0, 0.0]), drive_period=0,
         field=np.ascontiguousarray(field, dtype=np.float64),
         ext_force=None, ext_torque=None, bond_damping=None,
-        contact_model="hookean", contact_hm=None,
+        contact_model="hookean", contact_hm=None, dipole_cutoff=0.0,
         dt=0.01, damping=0.1, mu0_4pi=1.0,
         dipole_on=True, contact_on=False, k_contact=10.0, r_contact=1.0,
         exclude_depth=1, steps=100, precision="fp64", name="custom",
