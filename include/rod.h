@@ -135,6 +135,16 @@ typedef struct rod_desc {
   double contact_hm[5];       /* Hertz-Mindlin: contact modulus E > 0, Poisson ratio -1 < nu <= 0.5,
                                  friction coefficient mu >= 0, normal and tangential viscous damping
                                  g_n, g_t >= 0 */
+  double dipole_cutoff;       /* 0: the dipole-dipole sum runs over every pair of a member. > 0: only
+                                 pairs with r^2 = (dx dx + dy dy) + dz dz < cutoff^2 (exact FP64
+                                 selection) interact, through the same pair law (the truncated pair
+                                 interaction of the paper's simulations, for very large systems).
+                                 Needs contact_on: each particle keeps a list of the member's
+                                 particles within cutoff + r_contact / 4, found by walking the
+                                 contact cells and rebuilt with the contact lists; at most 256 per
+                                 particle (more: ROD_E_OVERFLOW at rod_sync). FP64 on both paths;
+                                 sums in list order, so runs agree to rounding, not bit for bit.
+                                 Not differentiated: refused with tape_capacity > 0. */
 } rod_desc;
 
 /* Caller-owned device buffers (SoA, float64). */

@@ -29,6 +29,7 @@ class RodDesc(C.Structure):
         ("tape_every", C.c_int32), ("tape_capacity", C.c_int32),
         ("bond_damping", _P),
         ("contact_model", C.c_int32), ("contact_hm", C.c_double * 5),
+        ("dipole_cutoff", C.c_double),
     ]
 
 

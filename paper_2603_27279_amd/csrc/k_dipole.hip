@@ -1,6 +1,8 @@
 // Dipole kernels (Methods, "Magnetic interactions"); the pair arithmetic and
-// the work items of both layouts are in dipole_body.h.
+// the work items of both layouts are in dipole_body.h, the list walk of the
+// cutoff interaction in dipole_list.h.
 #include "dipole_body.h"
+#include "dipole_list.h"
 
 namespace rodmx {
 
@@ -28,6 +30,16 @@ hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int n
   } else {
     launch_k(ev, k_dipole<double>, dim3(nwork), dim3(256), s, d, work);
   }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_dipole_l(Dev d, int build) {
+  dipole_listed(d, blockIdx.x, lists_stale(d, build));
+}
+
+hipError_t launch_dipole_cut(const Dev& d, int build, hipStream_t s, const hipEvent_t* ev) {
+  const unsigned g = (unsigned)((d.i_hi - d.i_lo + 255) / 256);
+  launch_k(ev, k_dipole_l, dim3(g), dim3(256), s, d, build);
   return hipGetLastError();
 }
 

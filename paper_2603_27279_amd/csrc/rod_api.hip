@@ -223,6 +223,18 @@ static int validate(const rod_desc* d) {
     if (d->tape_capacity > 0)
       return fail(ROD_E_INVALID, "Hertz-Mindlin contact is not differentiated: no tape with it");
   }
+  if (!(d->dipole_cutoff >= 0) || !std::isfinite(d->dipole_cutoff))
+    return fail(ROD_E_INVALID, "dipole_cutoff must be finite and >= 0");
+  if (d->dipole_on && d->dipole_cutoff > 0) {
+    if (!d->contact_on)
+      return fail(ROD_E_INVALID, "a dipole cutoff needs contact_on (it walks the contact cells)");
+    // the list rebuild walks at most 8 cells (of side 1.25 r_contact) each way
+    if (d->dipole_cutoff + NBR_SKIN * d->r_contact > 8.0 * (1.0 + NBR_SKIN) * d->r_contact)
+      return fail(ROD_E_INVALID, "dipole_cutoff above %.2f r_contact: use 0 (all pairs)",
+                  8.0 * (1.0 + NBR_SKIN) - NBR_SKIN);
+    if (d->tape_capacity > 0)
+      return fail(ROD_E_INVALID, "the dipole cutoff is not differentiated: no tape with it");
+  }
   if (d->tape_capacity > 0 && d->tape_every < 1)
     return fail(ROD_E_INVALID, "a tape needs tape_every >= 1");
   for (int r = 0; r < d->n_rods; ++r)
@@ -260,7 +272,8 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
   std::vector<DipWork> items;
   std::vector<int> mslots(M, 1), mlen(M, 0);
   int max_slots = 1;
-  for (int m = 0; m < M; ++m) {
+  // with a dipole cutoff the list walk writes slot 0 and there are no work items
+  for (int m = 0; m < M && c->d.dcut == 0.0; ++m) {
     const int b = mrange[2 * m], e = mrange[2 * m + 1], nm = e - b;
     if (small) {
       for (int i0 = b; i0 < e; i0 += DIP_SMALL_I) {
@@ -295,15 +308,16 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
   c->max_slots = max_slots;
   c->d.max_slots = max_slots;
   c->nwork = (int)items.size();
-  TRY(palloc(c, &c->work, items.size()));
-  HIPC(hipMemcpy(c->work, items.data(), items.size() * sizeof(DipWork), hipMemcpyHostToDevice));
+  TRY(palloc(c, &c->work, std::max<size_t>(1, items.size())));
+  if (!items.empty())
+    HIPC(hipMemcpy(c->work, items.data(), items.size() * sizeof(DipWork), hipMemcpyHostToDevice));
   int* ms = nullptr;
   TRY(palloc(c, &ms, M));
   HIPC(hipMemcpy(ms, mslots.data(), M * sizeof(int), hipMemcpyHostToDevice));
   c->d.mslots = ms;
   TRY(palloc(c, &c->d.dpart, (size_t)max_slots * 6 * N));
   c->d.dslotf = nullptr;
-  if (c->desc.precision == ROD_MIXED && c->desc.dipole_on)
+  if (c->desc.precision == ROD_MIXED && c->desc.dipole_on && c->d.dcut == 0.0)
     TRY(palloc(c, &c->d.dslotf, (size_t)max_slots * 6 * N));
   return ROD_OK;
 }
@@ -318,7 +332,10 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
   if (d->precision == ROD_MIXED && d->dipole_on) b += 4 * (size_t)max_slots * 6 * N;  // FP32 slots
   b += 2 * (4 * cells + sizeof(CellSlot) * cells * CELL_CAP + 4 * OVF_CAP) + 4 * N;  // cells
   const bool hm = d->contact_on && d->contact_model == ROD_CONTACT_HERTZ_MINDLIN;
-  if (d->contact_on && (long)N >= CONTACT_LANES_MAX_N) b += (4 * NBR_CAP + 4 + 24) * N;  // lists
+  const bool dcut = d->dipole_on && d->dipole_cutoff > 0;
+  if (d->contact_on && ((long)N >= CONTACT_LANES_MAX_N || dcut))
+    b += (4 * NBR_CAP + 4 + 24) * N;                                            // lists
+  if (dcut) b += (4 * DNBR_CAP + 4) * N;                                        // dipole lists
   if (hm) b += (24 + 8 + 2 * HM_CAP * (4 + 24)) * N;                            // torque, contacts
   if (d->precision == ROD_MIXED && d->dipole_on) b += 48 * ((N + 63) / 64);  // chunk boxes
   if (d->bond_damping) b += 8 * 4 * R + 8 * 2 * 5 * N;                       // bond damping
@@ -333,10 +350,13 @@ static int force_terms(rod_ctx* c, const Dev& d, int want_energy, int build) {
     TIMED(c, ROD_KERNEL_FORCES, launch_forces, d, c->desc.precision, c->work, c->nwork, c->s);
     if (c->desc.contact_on && !contact_in_forces(d))
       TIMED(c, ROD_KERNEL_CONTACT, launch_contact, d, 0, build, c->s);
+    if (d.dcut > 0) TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole_cut, d, build, c->s);
     return ROD_OK;
   }
   TIMED(c, ROD_KERNEL_BOND, launch_bond, d, c->desc.precision, want_energy, c->s);
-  if (c->desc.dipole_on)
+  if (c->desc.dipole_on && d.dcut > 0)
+    TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole_cut, d, build, c->s);
+  else if (c->desc.dipole_on)
     TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole, d, c->desc.precision, c->work, c->nwork, c->s);
   if (c->desc.contact_on)
     TIMED(c, ROD_KERNEL_CONTACT, launch_contact, d, want_energy, build, c->s);
@@ -438,7 +458,9 @@ static int enqueue_step_per_rod(rod_ctx* c) {
   };
   for (int r = 0; r < R; ++r) HIPC(launch_pre(rod_dev(r), PRE_STEP, c->s));
   for (int r = 0; r < R; ++r) HIPC(launch_bond(rod_dev(r), c->desc.precision, 0, c->s));
-  if (c->desc.dipole_on)
+  if (c->desc.dipole_on && c->d.dcut > 0)
+    for (int r = 0; r < R; ++r) HIPC(launch_dipole_cut(rod_dev(r), 1, c->s));
+  else if (c->desc.dipole_on)
     for (int r = 0; r < R; ++r)
       HIPC(launch_dipole(rod_dev(r), c->desc.precision, c->rod_work + c->rod_work_off[r],
                          c->rod_work_off[r + 1] - c->rod_work_off[r], c->s));
@@ -611,10 +633,19 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   d.rc = dsc->r_contact; d.inv_cell = dsc->contact_on ? 1.0 / dsc->r_contact : 0.0;
   d.depth = dsc->exclude_depth; d.field_len = dsc->field_len;
   d.hm = dsc->contact_on && dsc->contact_model == ROD_CONTACT_HERTZ_MINDLIN;
-  d.use_lists = dsc->contact_on && (long)N >= CONTACT_LANES_MAX_N;
+  d.dcut = dsc->dipole_on && dsc->dipole_cutoff > 0 ? dsc->dipole_cutoff : 0.0;
+  d.use_lists = dsc->contact_on && ((long)N >= CONTACT_LANES_MAX_N || d.dcut > 0);
   d.skin = NBR_SKIN * dsc->r_contact;
   // with lists the 27 cells around a particle must cover the list cutoff r_c + skin
   if (d.use_lists) d.inv_cell = 1.0 / (dsc->r_contact + d.skin);
+  // cells to walk around a particle's own so that the dipole lists reach dcut + skin
+  d.dcell_k = d.dcut > 0 ? (int)std::ceil((d.dcut + d.skin) * d.inv_cell) : 0;
+  d.dnbr = nullptr; d.dnbr_cnt = nullptr;
+  if (d.dcut > 0 && ((rc = dalloc(c, &d.dnbr, (size_t)DNBR_CAP * N)) ||
+                     (rc = dalloc(c, &d.dnbr_cnt, (size_t)N))))
+    return cleanup(rc);
+  if (d.dcut > 0 && hipMemset(d.dnbr_cnt, 0, sizeof(int) * (size_t)N) != hipSuccess)
+    return cleanup(fail(ROD_E_HIP, "memset failed"));
   if (d.use_lists &&
       ((rc = dalloc(c, &d.nbr, (size_t)NBR_CAP * N)) || (rc = dalloc(c, &d.nbr_cnt, (size_t)N)) ||
        (rc = dalloc(c, &d.xb, 3 * (size_t)N)) || (rc = dalloc(c, &d.rebuild, 2))))
@@ -745,6 +776,9 @@ int rod_sync(rod_ctx* c) {
     if (f[FLAG_NONFINITE]) return fail(ROD_E_NONFINITE, "non-finite force, torque or position");
     if (f[FLAG_HM_OVF])
       return fail(ROD_E_OVERFLOW, "a particle had more than %d Hertz-Mindlin contacts", HM_CAP);
+    if (f[FLAG_DIP_OVF])
+      return fail(ROD_E_OVERFLOW, "a particle had more than %d neighbours within the dipole "
+                  "cutoff and skin", DNBR_CAP);
     return fail(ROD_E_OVERFLOW, "contact search capacity exceeded: more than %d particles "
                 "landed in full cells", OVF_CAP);
   }
@@ -1016,7 +1050,7 @@ extern "C" int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, c
     int max_member = 0;
     for (size_t k = 0; k + 1 < c->mrange_h.size(); k += 2)
       max_member = std::max(max_member, c->mrange_h[k + 1] - c->mrange_h[k]);
-    if (c->desc.dipole_on) {
+    if (c->desc.dipole_on && c->d.dcut == 0.0) {  // (a cutoff has no layout to choose)
       if (max_member <= 16384) cands.push_back({1, 0});
       for (int t : {512, 1024, 2048, 4096, 8192, 16384, 32768}) cands.push_back({0, t});
     } else {

@@ -61,7 +61,8 @@ struct Dev {
   double* xb;              // [3N] positions at the last build
   unsigned* rebuild;       // [2] per level parity: some particle moved too far since the build
   double skin;             // list cutoff is r_c + skin
-  unsigned* flags;         // [4]: [0] non-finite state, [2] overflow list full,
+  unsigned* flags;         // [4]: [0] non-finite state, [1] a dipole list was full,
+                           // [2] overflow list full,
                            // [3] a particle had more Hertz-Mindlin contacts than HM_CAP
   long long* step;         // [3]: [0] time level of the state (written by the particle
                            // kernel); [1], [2] level of the force evaluation in flight,
@@ -94,6 +95,13 @@ struct Dev {
   int* hc_cnt;             // [2][N]
   int* hc_j;               // [2][HM_CAP][N]
   double* hc_s;            // [2][3][HM_CAP][N]
+  // Dipole cutoff (dcut > 0; 0: all pairs of a member): each particle's
+  // neighbours within dcut + skin and how many cells around its own to walk
+  // when the list is rebuilt.
+  double dcut;
+  int dcell_k;
+  int* dnbr;               // [DNBR_CAP][N]
+  int* dnbr_cnt;           // [N]
 };
 
 constexpr int CELL_CAP = 8;
@@ -104,7 +112,8 @@ constexpr double NBR_SKIN = 0.25;               // skin as a fraction of r_c
 constexpr double NBR_MOVE = 0.45;               // rebuild past this fraction of the skin
                                                 // (below 1/2, a margin for rounding)
 constexpr int HM_CAP = 16;                      // Hertz-Mindlin contacts kept per particle
-enum { FLAG_NONFINITE = 0, FLAG_LIST_OVF = 2, FLAG_HM_OVF = 3 };
+constexpr int DNBR_CAP = 256;                   // dipole list entries per particle (cutoff)
+enum { FLAG_NONFINITE = 0, FLAG_DIP_OVF = 1, FLAG_LIST_OVF = 2, FLAG_HM_OVF = 3 };
 
 // Cell of a coordinate (cells of side 1/inv), clamped so runaway coordinates
 // stay hashable.
@@ -169,6 +178,10 @@ hipError_t launch_bond(const Dev& d, int precision, int want_energy, hipStream_t
                        const hipEvent_t* ev = nullptr);
 hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int nwork,
                          hipStream_t s, const hipEvent_t* ev = nullptr);
+// Dipole interaction with a cutoff (d.dcut > 0) from the Verlet lists; build:
+// rebuild them regardless of motion.
+hipError_t launch_dipole_cut(const Dev& d, int build, hipStream_t s,
+                             const hipEvent_t* ev = nullptr);
 // build: rebuild contact candidate lists (large systems) regardless of motion.
 hipError_t launch_contact(const Dev& d, int want_energy, int build, hipStream_t s,
                           const hipEvent_t* ev = nullptr);

@@ -91,6 +91,7 @@ class RodSim:
         bd = self._host["bond_damping"]
         d.bond_damping = None if bd is None else bd.ctypes.data_as(C.c_void_p)
         d.contact_model = _CONTACT_MODEL[w.get("contact_model", "hookean")]
+        d.dipole_cutoff = float(w.get("dipole_cutoff") or 0.0)
         if w.get("contact_hm") is not None:
             d.contact_hm = (C.c_double * 5)(*[float(a) for a in w["contact_hm"]])
         self.desc = d

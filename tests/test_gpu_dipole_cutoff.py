@@ -1,0 +1,147 @@
+"""The dipole-dipole interaction with a cutoff on the HIP path against the FP64
+oracle: forces at the initial level, 100-step trajectories (lists rebuilt as
+particles move past the skin), a cutoff wider than the members against the
+all-pairs kernels, every launch form, a system past the lane-parallel contact
+size, and the per-particle list capacity. Sums run in list order, so runs and
+launch forms agree to rounding rather than bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_2603_27279_amd import RodSim, TERM_ALL, TERM_DIPOLE
+from paper_2603_27279_amd._lib import ROD_E_OVERFLOW, RodError
+from test_gpu_parity import TOL, TRAJ_TOL, clump, coil, perturb, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "twisted": lambda: dict(perturb(workloads.twisted_rod(n=300, period=200), 1), dipole_cutoff=3.0),
+    "cilia": lambda: dict(perturb(workloads.cilia_carpet(grid=(4, 4), pitch=3.0, len_range=(5, 40)), 2),
+                          dipole_cutoff=2.5),
+    "coil2": lambda: dict(coil(members=2), dipole_cutoff=4.0),
+    "clump": lambda: dict(clump(), dipole_cutoff=1.7),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_forces_at_the_initial_level(case, prec):
+    w = CASES[case]()
+    sim = RodSim(w, precision=prec)
+    st = oracle.run(w, 0)
+    for mask in (TERM_DIPOLE, TERM_ALL):
+        Fo, To = oracle.forces(w, st["x"], st["q"], st["v"], st["w"], mask=mask)
+        F, T = sim.eval_forces(mask)
+        F, T = F.cpu().numpy().T, T.cpu().numpy().T
+        tol = 1e-12 if mask == TERM_DIPOLE else TOL[prec]
+        assert rel_inf(F, Fo, 1e-300) <= tol, (case, prec, mask, rel_inf(F, Fo))
+        assert rel_inf(T, To, 1e-300) <= tol, (case, prec, mask, rel_inf(T, To))
+    Fa, _ = oracle.forces(dict(w, dipole_cutoff=0.0), st["x"], st["q"], mask=TERM_DIPOLE)
+    assert np.abs(Fa - Fo).max() > 1e-6 * np.abs(Fa).max()  # the cutoff matters here
+    E = sim.energy()
+    Eo = oracle.energy(w, st["x"], st["q"], st["v"], st["w"])
+    assert np.all(np.abs(E[:, 5] - Eo[:, 5]) <= 1e-12 * np.abs(Eo[:, 5]) + 1e-300)
+    sim.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_trajectory_100_steps(case, prec):
+    w = CASES[case]()
+    sim = RodSim(w, precision=prec, graph_steps=25)
+    sim.step(100)
+    sim.sync()
+    g = sim.state()
+    o = oracle.run(w, 100)
+    o0 = oracle.run(w, 0)
+    tol = TRAJ_TOL[prec]
+    for k in ("x", "q"):
+        m = max(np.max(np.abs(o[k] - o0[k])), 1e-300)
+        assert np.max(np.abs(g[k] - o[k])) / m <= tol, (case, prec, k)
+    for k in ("v", "w", "F", "T"):
+        assert rel_inf(g[k], o[k]) <= tol, (case, prec, k, rel_inf(g[k], o[k]))
+    sim.free()
+
+
+def test_wide_cutoff_matches_all_pairs():
+    """A cutoff wider than every member gives the all-pairs kernels' result to
+    rounding (different summation order and reciprocal square root)."""
+    w = perturb(workloads.ensemble(members=3, n=8), 3)
+    a = RodSim(dict(w, dipole_cutoff=9.0), precision="fp64")
+    b = RodSim(w, precision="fp64")
+    Fa, Ta = a.eval_forces(TERM_DIPOLE)
+    Fb, Tb = b.eval_forces(TERM_DIPOLE)
+    assert rel_inf(Fa.cpu().numpy(), Fb.cpu().numpy()) <= 1e-13
+    assert rel_inf(Ta.cpu().numpy(), Tb.cpu().numpy()) <= 1e-13
+    a.step(50); b.step(50)
+    sa, sb = a.state(), b.state()
+    motion = np.max(np.abs(sb["x"] - w["x0"]))
+    assert np.max(np.abs(sa["x"] - sb["x"])) / motion <= 1e-10
+    a.free(); b.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_launch_forms_agree(prec):
+    w = CASES["cilia"]()
+    runs = []
+    for mode, gsteps in (("batched", 0), ("batched", 7), ("separate", 10), ("per_rod", 0)):
+        sim = RodSim(w, precision=prec, graph_steps=gsteps)
+        sim.launch_mode(mode)
+        for n in (13, 10, 1, 6):
+            sim.step(n)
+        runs.append(sim.state())
+        sim.free()
+    motion = np.max(np.abs(runs[0]["x"] - w["x0"]))
+    for r in runs[1:]:
+        assert r["step"] == 30
+        assert np.max(np.abs(r["x"] - runs[0]["x"])) / motion <= 1e-11
+        for k in ("F", "T"):
+            assert rel_inf(r[k], runs[0][k]) <= (1e-10 if prec == "fp64" else 1e-5)
+
+
+def test_large_system():
+    """70,000 particles: contact and dipole lists both in use."""
+    rng = np.random.default_rng(12)
+    members, rods, length = 70, 10, 100
+    lens = [length] * (members * rods)
+    origins = [(0.0, 1.05 * (r % rods), 0.0) for r in range(members * rods)]
+    x, off, mem = workloads.straight_rods(lens, origins, (1, 0, 0),
+                                          member=np.repeat(np.arange(members), rods))
+    n = x.shape[0]
+    w = workloads._base(x, off, mem, np.tile([1.0, 1, 1, 0.5], (members * rods, 1)),
+                        rng.normal(0, 0.05, (n, 3)), np.zeros(n, np.int8),
+                        workloads._field_const(members, (0, 0, 0.5)), contact_on=True,
+                        precision="mixed", name="cutoff_large", dipole_cutoff=3.0)
+    w["x0"] = x + rng.normal(0, 0.05, x.shape)
+    assert n >= 65536
+    sim = RodSim(w, precision="mixed")
+    st = oracle.run(w, 0)
+    Fo, To = oracle.forces(w, st["x"], st["q"], mask=TERM_DIPOLE)
+    F, T = sim.eval_forces(TERM_DIPOLE)
+    assert rel_inf(F.cpu().numpy().T, Fo) <= 1e-12
+    assert rel_inf(T.cpu().numpy().T, To) <= 1e-12
+    sim.step(5)
+    g = sim.state()
+    o = oracle.run(w, 5)
+    motion = np.max(np.abs(o["x"] - st["x"]))
+    assert np.max(np.abs(g["x"] - o["x"])) / motion <= TRAJ_TOL["mixed"]
+    sim.free()
+
+
+def test_list_capacity_is_reported():
+    """400 particles in a box of side 5 with a cutoff of 7: every particle has
+    all 399 others within reach, more than a list holds."""
+    rng = np.random.default_rng(4)
+    n = 400
+    xs = rng.uniform(0, 5, (n, 3))
+    x, off, mem = workloads.straight_rods([1] * n, xs, (1, 0, 0))
+    w = workloads._base(x, off, mem, np.tile([1.0, 1, 1, 0.5], (n, 1)), rng.normal(0, 0.01, (n, 3)),
+                        np.ones(n, np.int8), workloads._field_const(1, (0, 0, 0)), contact_on=True,
+                        precision="fp64", dipole_cutoff=7.0)
+    sim = RodSim(w, precision="fp64")
+    with pytest.raises(RodError) as e:
+        sim.step(2)
+        sim.sync()
+    assert e.value.code == ROD_E_OVERFLOW
+    sim.free()
