@@ -90,6 +90,28 @@ def ordered_pairs(w):
     return int(np.sum(sizes * (sizes - 1)))
 
 
+def cutoff_neighbours(w):
+    """Mean list length of the rod array's dipole lists (cutoff plus the skin
+    r_contact / 4), counted on the reference lattice, which the lists see."""
+    return _lattice_neighbours(w, w["dipole_cutoff"] + 0.25 * w["r_contact"])
+
+
+def cutoff_pairs(w):
+    """Mean number of partners within the cutoff itself (the pairs evaluated)."""
+    return _lattice_neighbours(w, w["dipole_cutoff"])
+
+
+def _lattice_neighbours(w, rad):
+    # the rod array is a lateral grid of straight rods at spacing 1 along z:
+    # count lattice points of one interior particle (i, j, k) within rad
+    pitch = float(np.linalg.norm(w["x_ref"][w["rod_offset"][1]] - w["x_ref"][0]))
+    r = int(np.ceil(rad / min(pitch, 1.0))) + 1
+    g = np.arange(-r, r + 1)
+    X, Y, Z = np.meshgrid(pitch * g, pitch * g, g, indexing="ij")
+    d2 = X * X + Y * Y + Z * Z
+    return float(np.count_nonzero((d2 < rad * rad) & (d2 > 0)))
+
+
 def cpu_baseline(w, target_s=15.0):
     """The FP64 oracle on a bounded number of steps of the same workload."""
     import ctypes
@@ -165,6 +187,9 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E (vendor figure)
 #   Hertz-Mindlin contact (per particle): own x, v, w (72), force and torque out
 #     (48), contact counts of the previous and this level (8); per contact, its
 #     previous and new partner and tangential displacement (56)
+#   dipoles within a cutoff, list walk (per particle): own x and m (48), list
+#     count (4), force and field out (48), and 4 per list entry; the partners'
+#     x and m are other particles' own data
 #   contact (per particle): own position (24), list entry (8), force out (24)
 #   pre (per particle): state x v q w F T and m_body, inverse mass and inertia,
 #     ids (221 in); x v q w, m in FP64 and FP32, cell key and entry (180 out)
@@ -172,7 +197,7 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E (vendor figure)
 #     the mixed path, 48 in FP64), contact force, state and constants (318 + slots
 #     in); F T x v w q, m twice, cell key and entry (228 out)
 BYTES = {"bond": 165.0, "bond_damped": 269.0, "contact": 56.0, "contact_hm": 128.0,
-         "contact_hm_per_contact": 56.0, "pre": 401.0}
+         "contact_hm_per_contact": 56.0, "dipole_cutoff": 100.0, "pre": 401.0}
 
 
 def kick_bytes(slots, slot_bytes=24.0):
@@ -250,7 +275,25 @@ def hbm_microbench(sizes, steps=10):
                                   BYTES["contact_hm"] + BYTES["contact_hm_per_contact"] * per)
         res["contact_hm"]["contacts_per_particle"] = per
         res["contact_hm"]["list_build_us"] = 1e3 * timed[1]["contact"][0]
-        for k in ("bond", "bond_damped", "contact_hm", "pre", "contact", "kick"):
+        # dipoles within a cutoff of 3 from the Verlet lists
+        wc = dict(w, dipole_on=True, dipole_cutoff=3.0)
+        sim = RodSim(wc, precision="mixed", graph_steps=0)
+        sim.launch_mode("separate")
+        sim.step(2)
+        timed = {}
+        for k in (1, steps + 1):
+            sim.timing(True)
+            sim.step(k)
+            timed[k] = sim.kernel_times()
+            sim.timing(False)
+        sim.free()
+        walk_us = 1e3 * (timed[steps + 1]["dipole"][0] - timed[1]["dipole"][0]) / steps
+        per = cutoff_neighbours(wc)
+        res["dipole_cutoff"] = entry(walk_us, n, BYTES["dipole_cutoff"] + 4.0 * per)
+        res["dipole_cutoff"].update(
+            cutoff=3.0, neighbours_in_list=per, list_build_us=1e3 * timed[1]["dipole"][0],
+            pairs_per_s=n * cutoff_pairs(wc) / (walk_us * 1e-6))
+        for k in ("bond", "bond_damped", "contact_hm", "dipole_cutoff", "pre", "contact", "kick"):
             res[k]["frac_copy"] = res[k]["GB_s"] / copy["GB_s"]
         res["plain_copy"] = copy
         out.append(res)
@@ -363,6 +406,9 @@ def main():
                          "particles per rod): 64 -> 4.2M particles, 128 -> 16.8M")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
+    ap.add_argument("--dipole-cutoff", type=float, default=0.0,
+                    help="dipole-dipole interaction only within this distance (0: all pairs; "
+                         "no roofline line then: the pair count is not the all-pairs one)")
     ap.add_argument("--helix-loop", type=float, default=None, metavar="GAMMA",
                     help="only run the magnetic helix's quasi-static loading-unloading cycle "
                          "at this dipole strength (about 3 minutes) and print it as JSON")
@@ -384,9 +430,11 @@ def main():
     from paper_2603_27279_amd import RodSim
 
     w = workloads.make(args.workload)
+    if args.dipole_cutoff > 0:
+        w["dipole_cutoff"] = args.dipole_cutoff
     prec = args.precision or w["precision"]
     n = w["n"]
-    pairs = ordered_pairs(w) if w["dipole_on"] else 0
+    pairs = ordered_pairs(w) if w["dipole_on"] and not args.dipole_cutoff else 0
 
     sim = RodSim(w, precision=prec, graph_steps=args.graph_steps)
     tune = None
@@ -492,7 +540,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "n_particles": n,
                    "ordered_dipole_pairs_per_step": pairs, "precision": prec,
-                   "graph_steps": args.graph_steps, "dipole_layout": tune},
+                   "graph_steps": args.graph_steps, "dipole_layout": tune,
+                   "dipole_cutoff": args.dipole_cutoff or None},
         "pair_evals_per_s": pairs * args.steps / secs if pairs else None,
         "kernel_us": kernels_us,
         "kernel_us_separate_terms": kernels_sep_us,

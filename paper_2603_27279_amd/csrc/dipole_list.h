@@ -14,19 +14,34 @@
 
 namespace rodmx {
 
-// Visit every particle listed in the cells within k cells of xi's cell and in
-// the overflow list: take(j, position of j). A slot counts only when visited
-// from its own cell, so a hash bucket shared by two cells of the walk never
-// yields a particle twice; other members' particles are left to the caller.
+// Squared distance from coordinate x to the cell interval [g h, (g + 1) h),
+// widened by a relative 1e-9 so that rounding never drops a cell.
+__device__ __forceinline__ double gap2(double x, int g, double h) {
+  const double lo = (double)g * h, hi = lo + h, e = 1e-9 * h;
+  const double t = fmax(fmax(lo - e - x, x - hi - e), 0.0);
+  return t * t;
+}
+
+// Visit every particle listed in the cells within k cells of xi's cell that
+// come closer to xi than sqrt(reach2), and in the overflow list: take(j,
+// position of j). A slot counts only when visited from its own cell, so a hash
+// bucket shared by two cells of the walk never yields a particle twice; other
+// members' particles are left to the caller.
 template <class Take>
 __device__ __forceinline__ void for_cells_within(const Dev& d, const CellTab& tab, V3<double> xi,
-                                                 int mem, int k, Take&& take) {
+                                                 int mem, int k, double reach2, Take&& take) {
   const long N = d.n;
+  const double h = 1.0 / d.inv_cell;
   const int cx = cell_coord(xi.x, d.inv_cell), cy = cell_coord(xi.y, d.inv_cell),
             cz = cell_coord(xi.z, d.inv_cell);
-  for (int gz = cz - k; gz <= cz + k; ++gz)
-    for (int gy = cy - k; gy <= cy + k; ++gy)
+  for (int gz = cz - k; gz <= cz + k; ++gz) {
+    const double dz2 = gap2(xi.z, gz, h);
+    if (dz2 > reach2) continue;
+    for (int gy = cy - k; gy <= cy + k; ++gy) {
+      const double dyz2 = dz2 + gap2(xi.y, gy, h);
+      if (dyz2 > reach2) continue;
       for (int gx = cx - k; gx <= cx + k; ++gx) {
+        if (dyz2 + gap2(xi.x, gx, h) > reach2) continue;
         const unsigned key = cell_hash(gx, gy, gz, mem, d.cell_mask);
         const int nb = min(tab.cnt[key], CELL_CAP);
         const CellSlot* sl = tab.slot + (long)key * CELL_CAP;
@@ -38,6 +53,8 @@ __device__ __forceinline__ void for_cells_within(const Dev& d, const CellTab& ta
           take((int)(e.tag & 0xffffffffll), V3<double>{e.x, e.y, e.z});
         }
       }
+    }
+  }
   const int no = min(*tab.ovf_cnt, OVF_CAP);
   for (int o = 0; o < no; ++o) {
     const int j = tab.ovf[o];
@@ -61,7 +78,7 @@ __device__ __forceinline__ void dipole_listed(const Dev& d, long blk, bool build
     if (!(r2 < rd2)) return;
     const V3<double> mj = ld3(d.mu, N, j);
     const V3<double> r = xi - xj;
-    const double rinv = 1.0 / sqrt(r2);
+    const double rinv = rsqrt_nr(r2);  // hardware estimate, two Newton steps
     const double rinv3 = rinv * rinv * rinv, rinv5 = rinv3 * rinv * rinv;
     const double a = dot(mi, r), b = dot(mj, r), cmm = dot(mi, mj);
     F = F + (3.0 * C * rinv5) * ((cmm * r + b * mi + a * mj) - (5.0 * a * b * rinv * rinv) * r);
@@ -70,7 +87,7 @@ __device__ __forceinline__ void dipole_listed(const Dev& d, long blk, bool build
   if (build) {
     const double rs = d.dcut + d.skin, rs2 = rs * rs;
     int nc = 0;
-    for_cells_within(d, cell_tab(d, d.step[d.lc]), xi, mem, d.dcell_k,
+    for_cells_within(d, cell_tab(d, d.step[d.lc]), xi, mem, d.dcell_k, rs2 * (1.0 + 1e-9),
                      [&](int j, V3<double> xj) {
       if (j == (int)i || j < mb || j >= me) return;
       if (r2_exact(xi, xj) < rs2) {
@@ -83,8 +100,20 @@ __device__ __forceinline__ void dipole_listed(const Dev& d, long blk, bool build
     if (nc > DNBR_CAP) atomicOr(&d.flags[FLAG_DIP_OVF], 1u);
     st3(d.xb, N, i, xi);
   } else {
+    // four neighbours' gathers in flight at a time
     const int nc = d.dnbr_cnt[i];
-    for (int k = 0; k < nc; ++k) {
+    int k = 0;
+    for (; k + 4 <= nc; k += 4) {
+      int j[4];
+      V3<double> xj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) j[u] = d.dnbr[(long)(k + u) * N + i];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xj[u] = ld3(d.x, N, j[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pair(j[u], xj[u]);
+    }
+    for (; k < nc; ++k) {
       const int j = d.dnbr[(long)k * N + i];
       pair(j, ld3(d.x, N, j));
     }
