@@ -73,10 +73,15 @@ __device__ __forceinline__ void dipole_listed(const Dev& d, long blk, bool build
   const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
   const double rd2 = d.dcut * d.dcut, C = d.C;
   V3<double> F{0.0, 0.0, 0.0}, B{0.0, 0.0, 0.0};
-  auto pair = [&](int j, V3<double> xj) {
+  // partner j's position and moment from the interleaved copy (one line)
+  auto partner = [&](int j, V3<double>& xj, V3<double>& mj) {
+    const double* p = static_cast<const double*>(__builtin_assume_aligned(d.xm + 8 * (long)j, 64));
+    xj = V3<double>{p[0], p[1], p[2]};
+    mj = V3<double>{p[4], p[5], p[6]};
+  };
+  auto pair = [&](V3<double> xj, V3<double> mj) {
     const double r2 = r2_exact(xi, xj);
     if (!(r2 < rd2)) return;
-    const V3<double> mj = ld3(d.mu, N, j);
     const V3<double> r = xi - xj;
     const double rinv = rsqrt_nr(r2);  // hardware estimate, two Newton steps
     const double rinv3 = rinv * rinv * rinv, rinv5 = rinv3 * rinv * rinv;
@@ -94,7 +99,9 @@ __device__ __forceinline__ void dipole_listed(const Dev& d, long blk, bool build
         if (nc < DNBR_CAP) d.dnbr[(long)nc * N + i] = j;
         ++nc;
       }
-      pair(j, xj);
+      V3<double> xk, mk;
+      partner(j, xk, mk);
+      pair(xk, mk);
     });
     d.dnbr_cnt[i] = min(nc, DNBR_CAP);
     if (nc > DNBR_CAP) atomicOr(&d.flags[FLAG_DIP_OVF], 1u);
@@ -105,17 +112,18 @@ __device__ __forceinline__ void dipole_listed(const Dev& d, long blk, bool build
     int k = 0;
     for (; k + 4 <= nc; k += 4) {
       int j[4];
-      V3<double> xj[4];
+      V3<double> xj[4], mj[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) j[u] = d.dnbr[(long)(k + u) * N + i];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) xj[u] = ld3(d.x, N, j[u]);
+      for (int u = 0; u < 4; ++u) partner(j[u], xj[u], mj[u]);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) pair(j[u], xj[u]);
+      for (int u = 0; u < 4; ++u) pair(xj[u], mj[u]);
     }
     for (; k < nc; ++k) {
-      const int j = d.dnbr[(long)k * N + i];
-      pair(j, ld3(d.x, N, j));
+      V3<double> xj, mj;
+      partner(d.dnbr[(long)k * N + i], xj, mj);
+      pair(xj, mj);
     }
   }
   double* p = d.dpart;

@@ -335,7 +335,7 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
   const bool dcut = d->dipole_on && d->dipole_cutoff > 0;
   if (d->contact_on && ((long)N >= CONTACT_LANES_MAX_N || dcut))
     b += (4 * NBR_CAP + 4 + 24) * N;                                            // lists
-  if (dcut) b += (4 * DNBR_CAP + 4) * N;                                        // dipole lists
+  if (dcut) b += (4 * DNBR_CAP + 4 + 64) * N;                                   // dipole lists
   if (hm) b += (24 + 8 + 2 * HM_CAP * (4 + 24)) * N;                            // torque, contacts
   if (d->precision == ROD_MIXED && d->dipole_on) b += 48 * ((N + 63) / 64);  // chunk boxes
   if (d->bond_damping) b += 8 * 4 * R + 8 * 2 * 5 * N;                       // bond damping
@@ -640,9 +640,10 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   if (d.use_lists) d.inv_cell = 1.0 / (dsc->r_contact + d.skin);
   // cells to walk around a particle's own so that the dipole lists reach dcut + skin
   d.dcell_k = d.dcut > 0 ? (int)std::ceil((d.dcut + d.skin) * d.inv_cell) : 0;
-  d.dnbr = nullptr; d.dnbr_cnt = nullptr;
+  d.dnbr = nullptr; d.dnbr_cnt = nullptr; d.xm = nullptr;
   if (d.dcut > 0 && ((rc = dalloc(c, &d.dnbr, (size_t)DNBR_CAP * N)) ||
-                     (rc = dalloc(c, &d.dnbr_cnt, (size_t)N))))
+                     (rc = dalloc(c, &d.dnbr_cnt, (size_t)N)) ||
+                     (rc = dalloc(c, &d.xm, 8 * (size_t)N))))
     return cleanup(rc);
   if (d.dcut > 0 && hipMemset(d.dnbr_cnt, 0, sizeof(int) * (size_t)N) != hipSuccess)
     return cleanup(fail(ROD_E_HIP, "memset failed"));

@@ -102,6 +102,7 @@ struct Dev {
   int dcell_k;
   int* dnbr;               // [DNBR_CAP][N]
   int* dnbr_cnt;           // [N]
+  double* xm;              // [N][8]: x, y, z, 0, m_x, m_y, m_z, 0 of the level (cutoff), or null
 };
 
 constexpr int CELL_CAP = 8;
