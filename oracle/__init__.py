@@ -196,6 +196,18 @@ def forces(w, x, q, v=None, om=None, mbody=None, step=0, mask=ALL, with_field=Fa
     return out
 
 
+def hm_single(w, xi, xj, vi=(0, 0, 0), vj=(0, 0, 0), wi=(0, 0, 0), wj=(0, 0, 0), sprev=None):
+    """One Hertz-Mindlin contact of a workload's law: (force on i, torque on i,
+    new tangential displacement, normal elastic energy)."""
+    lib = _load()
+    sy = System(w)
+    a = [_f64(v, (3,)) for v in (xi, xj, vi, vj, wi, wj)]
+    sp = None if sprev is None else _f64(sprev, (3,))
+    F, T, sn, e = np.zeros(3), np.zeros(3), np.zeros(3), np.zeros(1)
+    lib.orc_hm_single(sy.ref, *[_p(v) for v in a], _p(sp), _p(F), _p(T), _p(sn), _p(e))
+    return F, T, sn, float(e[0])
+
+
 def energy(w, x, q, v=None, om=None, mbody=None, step=0):
     """Energies [M, 9] (see ENERGY_TERMS)."""
     lib = _load()

@@ -814,6 +814,20 @@ void orc_bond_single(const double* x1, const double* x2, const double* q1, const
   st3(F, 0, f); st3(Ts, 0, ts); st3(Tbt, 0, tbt);
 }
 
+// One Hertz-Mindlin contact in isolation (for closed-form tests): positions,
+// velocities and spins of i and j, the previous tangential displacement (null:
+// a new contact); returns the force and torque on i and the new displacement.
+void orc_hm_single(const orc_system* s, const double* xi, const double* xj, const double* vi,
+                   const double* vj, const double* wi, const double* wj, const double* sprev,
+                   double* F, double* Tq, double* snew, double* e) {
+  Model md = build_model(s);
+  V3<double> f, t, sn, sp;
+  if (sprev) sp = ld3(sprev, 0);
+  hertz_mindlin(md, ld3(xi, 0), ld3(xj, 0), ld3(vi, 0), ld3(vj, 0), ld3(wi, 0), ld3(wj, 0),
+                sprev ? &sp : nullptr, f, t, sn, *e);
+  st3(F, 0, f); st3(Tq, 0, t); st3(snew, 0, sn);
+}
+
 // Force and torque of the selected terms (bitmask: 1 bond, 2 dipole, 4 Zeeman,
 // 8 contact, 16 damping, 32 external) at the state given, field index n.
 // Bdip (nullable) receives the dipole field at each particle.

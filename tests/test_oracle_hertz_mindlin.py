@@ -246,3 +246,27 @@ def test_oblique_impact_keeps_friction_in_the_tangent_plane():
     assert seen >= 5
     assert np.linalg.norm(Ft) > 1e-3 * Fn
     assert np.degrees(np.arccos(np.clip(np.dot(turned[0], turned[-1]), -1, 1))) > 5
+
+
+def test_turned_displacement_keeps_its_length():
+    """A stuck contact whose normal has turned: with no sliding the previous
+    displacement is turned into the new tangent plane at its own length, so
+    the tangential force keeps its magnitude, -k_t |s|, and is normal to n."""
+    E, nu = 10.0, 0.3
+    w = spheres([[0, 0, 0], [0.9, 0, 0]], hm=(E, nu, 10.0, 0.0, 0.0))
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        xi, xj = 0.45 * n, -0.45 * n
+        sp = 1e-3 * rng.normal(size=3)  # a displacement from an earlier tangent plane
+        F, T, sn, e = oracle.hm_single(w, xi, xj, sprev=sp)
+        a = np.sqrt(RS * 0.1)
+        kt = 8.0 * gstar(E, nu) * a
+        assert abs(np.dot(sn, n)) <= 1e-15
+        np.testing.assert_allclose(np.linalg.norm(sn), np.linalg.norm(sp), rtol=1e-13)
+        st = sp - np.dot(sp, n) * n  # the turn is the projection, stretched back
+        np.testing.assert_allclose(sn, st * np.linalg.norm(sp) / np.linalg.norm(st), rtol=1e-12)
+        Ft = F - np.dot(F, n) * n
+        np.testing.assert_allclose(Ft, -kt * sn, rtol=1e-12, atol=1e-18)
+        np.testing.assert_allclose(T, np.cross(-0.45 * n, Ft), rtol=1e-12, atol=1e-18)
