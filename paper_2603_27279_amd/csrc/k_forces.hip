@@ -12,9 +12,11 @@
 
 namespace rodmx {
 
-template <class R, bool LANES>
-__global__ __launch_bounds__(256) void k_forces(Dev d, const DipWork* __restrict__ work, int ndip,
-                                                int nbond) {
+// HM: the lane-parallel search is the Hertz-Mindlin one (a kernel of its own,
+// k_forces_hm, so that the Hookean kernels keep their register budget).
+template <class R, bool LANES, bool HM>
+__device__ __forceinline__ void forces_body(const Dev& d, const DipWork* __restrict__ work,
+                                            int ndip, int nbond) {
   __shared__ DipSmem<R> sm;
   const int b = blockIdx.x;
   if (b < ndip) {
@@ -23,8 +25,21 @@ __global__ __launch_bounds__(256) void k_forces(Dev d, const DipWork* __restrict
   } else if (b < ndip + nbond) {
     bond_thread<R>(d, d.i_lo + (long)(b - ndip) * 256 + threadIdx.x, 0);
   } else if constexpr (LANES) {
-    contact_pass<OUT_FORCE>(d, b - ndip - nbond, nullptr, 0, nullptr);
+    if constexpr (HM) contact_hm_lanes<OUT_FORCE>(d, b - ndip - nbond);
+    else contact_pass<OUT_FORCE>(d, b - ndip - nbond, nullptr, 0, nullptr);
   }
+}
+
+template <class R, bool LANES>
+__global__ __launch_bounds__(256) void k_forces(Dev d, const DipWork* __restrict__ work, int ndip,
+                                                int nbond) {
+  forces_body<R, LANES, false>(d, work, ndip, nbond);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_forces_hm(Dev d, const DipWork* __restrict__ work,
+                                                   int ndip, int nbond) {
+  forces_body<R, true, true>(d, work, ndip, nbond);
 }
 
 hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int nwork,
@@ -34,11 +49,14 @@ hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int n
   const bool lanes = contact_in_forces(d);
   const unsigned ncont = d.contact_on && lanes ? contact_lane_blocks(d) : 0;
   const dim3 g((unsigned)ndip + (unsigned)nbond + ncont), b(256);
+  const bool hm = lanes && d.contact_on && d.hm;
   if (precision == 1) {
-    if (lanes) launch_k(ev, k_forces<float, true>, g, b, s, d, work, ndip, nbond);
+    if (hm) launch_k(ev, k_forces_hm<float>, g, b, s, d, work, ndip, nbond);
+    else if (lanes) launch_k(ev, k_forces<float, true>, g, b, s, d, work, ndip, nbond);
     else launch_k(ev, k_forces<float, false>, g, b, s, d, work, ndip, nbond);
   } else {
-    if (lanes) launch_k(ev, k_forces<double, true>, g, b, s, d, work, ndip, nbond);
+    if (hm) launch_k(ev, k_forces_hm<double>, g, b, s, d, work, ndip, nbond);
+    else if (lanes) launch_k(ev, k_forces<double, true>, g, b, s, d, work, ndip, nbond);
     else launch_k(ev, k_forces<double, false>, g, b, s, d, work, ndip, nbond);
   }
   return hipGetLastError();

@@ -188,9 +188,9 @@ hipError_t launch_contact(const Dev& d, int want_energy, int build, hipStream_t 
                           const hipEvent_t* ev = nullptr);
 // Dipole, bond and contact forces of a step in one launch.
 // Whether the contact search runs inside the fused force launch (lane-parallel
-// cell search of smaller systems, Hookean law) or in a launch of its own
-// (candidate lists of large systems, or the Hertz-Mindlin search).
-inline bool contact_in_forces(const Dev& d) { return d.n < CONTACT_LANES_MAX_N && !d.hm; }
+// cell search of smaller systems, either law) or in a launch of its own
+// (candidate lists of large systems).
+inline bool contact_in_forces(const Dev& d) { return d.n < CONTACT_LANES_MAX_N; }
 hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int nwork,
                          hipStream_t s, const hipEvent_t* ev = nullptr);
 // The whole force pass of a level: launch_forces, and for systems whose contact
