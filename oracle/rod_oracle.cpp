@@ -31,6 +31,12 @@
 //   integrator        SI "Equations of motion" (velocity Verlet, Richardson
 //                     quaternion update, renormalisation after each substep,
 //                     solid-sphere inertia).
+//   dipole cutoff     the truncated pair interaction of the paper's
+//                     simulations (pairs closer than the cutoff only).
+//   field ramp        the quasi-static loading protocol of "Magnetized beams
+//                     in non-uniform fields" and of the helical rods with
+//                     dipole-dipole interactions (settings in turn, each held
+//                     with damped dynamics until the system is at rest).
 //
 // Readings where the paper is silent (each is listed in the design notes):
 //   shortest-arc central frame; gamma via atan2 with the gamma/sigma limit at
@@ -43,7 +49,10 @@
 // Newton's third law, angular momentum), a rotation-matrix re-derivation of the
 // bond, Euler-Bernoulli cantilever limits, closed-form dipole pairs, finite
 // differences of the energies, brute-force contact vs a k-d tree, integrator
-// convergence order, and finite differences of the dual-number JVP.
+// convergence order, finite differences of the dual-number JVP, closed forms of
+// each bond damping mode and the damped oscillator, Hertz contact and impact
+// theory with Mindlin stick-slip, the dipole cutoff's limits and partial sums,
+// and the magnetic cantilever at every increment of a ramp.
 
 #include <cmath>
 #include <cstdint>
