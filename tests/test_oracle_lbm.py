@@ -1,0 +1,86 @@
+"""Pins of the lattice Boltzmann oracle (D3Q19, BGK, Guo forcing; Methods,
+"Lattice Boltzmann method") against closed forms: the equilibrium's moments,
+exact conservation of mass and of momentum plus the applied force, the decay
+rate of a Taylor-Green vortex, nu (kx^2 + ky^2) with nu = (tau - 1/2)/3, and
+force-driven Poiseuille flow between halfway bounce-back walls at the
+relaxation time where that scheme reproduces the parabola exactly."""
+import numpy as np
+import pytest
+
+from oracle import lbm
+
+
+def test_equilibrium_moments():
+    rng = np.random.default_rng(1)
+    rho = 1 + 0.1 * rng.random((3, 4, 5))
+    u = 0.05 * rng.normal(size=(3, 3, 4, 5))
+    f = lbm.equilibrium(rho, u)
+    C = lbm.C.astype(float)
+    np.testing.assert_allclose(f.sum(0), rho, rtol=1e-14)
+    np.testing.assert_allclose(np.einsum("id,i...->d...", C, f), rho * u, rtol=1e-13, atol=1e-16)
+    P = np.einsum("id,ie,i...->de...", C, C, f)
+    want = rho * (np.einsum("d...,e...->de...", u, u) + np.eye(3)[:, :, None, None, None] / 3)
+    np.testing.assert_allclose(P, want, rtol=1e-13, atol=1e-16)
+    assert lbm.W.sum() == pytest.approx(1.0, abs=1e-15)
+    np.testing.assert_array_equal(lbm.C[lbm.OPP], -lbm.C)
+
+
+def test_uniform_equilibrium_is_a_fixed_point():
+    f = lbm.equilibrium(np.full((4, 5, 6), 1.3), np.zeros((3, 4, 5, 6)) + np.array([0.02, -0.01, 0.03]).reshape(3, 1, 1, 1))
+    g = lbm.run(f, 20, tau=0.8)
+    np.testing.assert_allclose(g, f, rtol=1e-14, atol=1e-17)
+
+
+def test_mass_and_momentum_balance():
+    rng = np.random.default_rng(2)
+    shape = (6, 5, 7)
+    f = lbm.equilibrium(1 + 0.05 * rng.random(shape), 0.03 * rng.normal(size=(3,) + shape))
+    f += 1e-4 * rng.random(f.shape)  # off equilibrium
+    g = np.array([1e-5, -2e-5, 3e-5])
+    t = 25
+    out = lbm.run(f, t, tau=0.7, g=g)
+    C = lbm.C.astype(float)
+    ncell = np.prod(shape)
+    assert abs(out.sum() - f.sum()) <= 1e-12 * f.sum()
+    P0 = np.einsum("id,i...->d...", C, f).reshape(3, -1).sum(1)
+    P1 = np.einsum("id,i...->d...", C, out).reshape(3, -1).sum(1)
+    np.testing.assert_allclose(P1 - P0, t * ncell * g, rtol=1e-9, atol=1e-13)
+
+
+def test_taylor_green_decay():
+    n, tau, U = 32, 0.8, 1e-3
+    nu = (tau - 0.5) / 3
+    k = 2 * np.pi / n
+    z, y, x = np.meshgrid(np.arange(2), np.arange(n), np.arange(n), indexing="ij")
+    u = np.zeros((3, 2, n, n))
+    u[0] = U * np.sin(k * x) * np.cos(k * y)
+    u[1] = -U * np.cos(k * x) * np.sin(k * y)
+    f = lbm.equilibrium(np.ones((2, n, n)), u)
+    t = 300
+    out = lbm.run(f, t, tau)
+    _, ut = lbm.moments(out, (0, 0, 0))
+    amp0 = np.sum(u[0] * u[0])
+    amp1 = np.sum(ut[0] * u[0])
+    rate = -np.log(amp1 / amp0) / t
+    assert rate == pytest.approx(2 * nu * k * k, rel=5e-3)
+
+
+def test_poiseuille_between_bounce_back_walls():
+    """Body force g along x, walls at z = -1/2 and nz - 1/2: the steady
+    profile is u(z) = g / (2 nu) (z + 1/2) (nz - 1/2 - z), exactly so with
+    halfway bounce-back at tau = 1/2 + sqrt(3/16)."""
+    nz = 12
+    tau = 0.5 + np.sqrt(3.0 / 16.0)
+    nu = (tau - 0.5) / 3
+    gx = 1e-6
+    f = lbm.equilibrium(np.ones((nz, 2, 2)), np.zeros((3, nz, 2, 2)))
+    out = lbm.run(f, 12000, tau, g=(gx, 0, 0), walls=True)
+    _, u = lbm.moments(out, (gx, 0, 0))
+    zz = np.arange(nz)
+    want = gx / (2 * nu) * (zz + 0.5) * (nz - 0.5 - zz)
+    np.testing.assert_allclose(u[0, :, 0, 0], want, rtol=1e-8)
+    # any other relaxation time moves the effective wall (a slip that grows with tau)
+    out2 = lbm.run(f, 12000, 1.5, g=(gx, 0, 0), walls=True)
+    _, u2 = lbm.moments(out2, (gx, 0, 0))
+    want2 = gx / (2 * (1.0 / 3)) * (zz + 0.5) * (nz - 0.5 - zz)
+    assert np.max(np.abs(u2[0, :, 0, 0] / want2 - 1)) > 1e-3
