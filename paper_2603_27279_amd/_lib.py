@@ -46,6 +46,12 @@ class RodGradients(C.Structure):
     _fields_ = [(k, _P) for k in ("m_body", "field", "x0", "v0", "q0", "w0")]
 
 
+class LbmDesc(C.Structure):
+    """Mirrors lbm_desc of include/lbm.h."""
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double),
+                ("force", C.c_double * 3), ("walls_z", C.c_int32)]
+
+
 class RodError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"rod error {code}: {msg}")
@@ -84,6 +90,11 @@ def load():
         "rod_dipole_layout": [_P, i32, i32],
         "rod_launch_mode": [_P, i32],
         "rod_ramp": [_P, _P, i32, i32, i32, C.c_double, _P, i32, _P, _P, _P],
+        "lbm_init": [C.POINTER(_P), C.POINTER(LbmDesc), _P, _P],
+        "lbm_step": [_P, i64],
+        "lbm_populations": [_P, _P],
+        "lbm_moments": [_P, _P, _P],
+        "lbm_free": [_P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -91,6 +102,8 @@ def load():
         f.restype = C.c_int
     lib.rod_last_error.argtypes = []
     lib.rod_last_error.restype = C.c_char_p
+    lib.lbm_last_error.argtypes = []
+    lib.lbm_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 

@@ -1,0 +1,205 @@
+// Lattice Boltzmann fluid solver (Methods, "Lattice Boltzmann method"): one
+// fused kernel per step. Each thread owns a cell: it reads the cell's 19
+// populations (coalesced, SoA by direction), forms density and velocity (the
+// velocity shifted by half the body force), relaxes towards the second-order
+// equilibrium (BGK), adds Guo's forcing term and pushes every post-collision
+// population to the neighbouring cell along its direction: for each direction
+// consecutive threads write consecutive addresses, so the writes stay as
+// coalesced as the reads. At a bounce-back wall the population comes back
+// reversed at its own cell. 304 bytes move per cell update, 19 doubles in and
+// 19 out; the kernel is bound by HBM bandwidth.
+#include "rod.h"
+#include "lbm.h"
+
+#include <hip/hip_runtime.h>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+namespace lbmx {
+
+// D3Q19 in the order of lbm.h (the loops over i are unrolled, so every lookup
+// is a compile-time constant).
+__device__ __forceinline__ constexpr int CX(int i) {
+  constexpr int v[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  return v[i];
+}
+__device__ __forceinline__ constexpr int CY(int i) {
+  constexpr int v[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  return v[i];
+}
+__device__ __forceinline__ constexpr int CZ(int i) {
+  constexpr int v[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  return v[i];
+}
+__device__ __forceinline__ constexpr int OPP(int i) {
+  constexpr int v[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+  return v[i];
+}
+
+__device__ __forceinline__ double weight(int i) {
+  return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+struct Lattice {
+  int nx, ny, nz, walls;
+  long cells;
+  double tau, gx, gy, gz;
+};
+
+__global__ __launch_bounds__(256) void k_lbm(Lattice L, const double* __restrict__ src,
+                                             double* __restrict__ dst) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= L.cells) return;
+  const int x = (int)(c % L.nx);
+  const long r = c / L.nx;
+  const int y = (int)(r % L.ny), z = (int)(r / L.ny);
+  double f[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) f[i] = src[i * L.cells + c];
+  double rho = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    rho += f[i];
+    mx += CX(i) * f[i]; my += CY(i) * f[i]; mz += CZ(i) * f[i];
+  }
+  const double ux = (mx + 0.5 * L.gx) / rho, uy = (my + 0.5 * L.gy) / rho,
+               uz = (mz + 0.5 * L.gz) / rho;
+  const double uu = ux * ux + uy * uy + uz * uz, ug = ux * L.gx + uy * L.gy + uz * L.gz;
+  const double omega = 1.0 / L.tau, pre = 1.0 - 0.5 / L.tau;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const double cu = CX(i) * ux + CY(i) * uy + CZ(i) * uz;
+    const double cg = CX(i) * L.gx + CY(i) * L.gy + CZ(i) * L.gz;
+    const double w = weight(i);
+    const double feq = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    const double fs = f[i] - omega * (f[i] - feq) + pre * w * (3.0 * (cg - ug) + 9.0 * cu * cg);
+    int zd = z + CZ(i);
+    if (L.walls && (zd < 0 || zd >= L.nz)) {  // halfway bounce-back: reversed, at this cell
+      dst[OPP(i) * L.cells + c] = fs;
+      continue;
+    }
+    zd = (zd + L.nz) % L.nz;
+    const int xd = (x + CX(i) + L.nx) % L.nx, yd = (y + CY(i) + L.ny) % L.ny;
+    dst[i * L.cells + ((long)zd * L.ny + yd) * L.nx + xd] = fs;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lbm_moments(Lattice L, const double* __restrict__ f,
+                                                     double* rho_o, double* u_o) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= L.cells) return;
+  double rho = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const double v = f[i * L.cells + c];
+    rho += v;
+    mx += CX(i) * v; my += CY(i) * v; mz += CZ(i) * v;
+  }
+  rho_o[c] = rho;
+  u_o[c] = (mx + 0.5 * L.gx) / rho;
+  u_o[L.cells + c] = (my + 0.5 * L.gy) / rho;
+  u_o[2 * L.cells + c] = (mz + 0.5 * L.gz) / rho;
+}
+
+}  // namespace lbmx
+
+using namespace lbmx;
+
+struct lbm_ctx {
+  Lattice L;
+  double* f[2] = {nullptr, nullptr};
+  int cur = 0;
+  hipStream_t s = nullptr;
+};
+
+static thread_local std::string g_lbm_err;
+
+static int lfail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_lbm_err = buf;
+  return code;
+}
+
+#define LHIP(x)                                                                     \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) return lfail(ROD_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+static unsigned lblocks(long cells) { return (unsigned)((cells + 255) / 256); }
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_lbm_err.c_str(); }
+
+int lbm_init(lbm_ctx** out, const lbm_desc* d, const double* f0, void* hip_stream) {
+  if (!out || !d || !f0) return lfail(ROD_E_INVALID, "NULL argument");
+  *out = nullptr;
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return lfail(ROD_E_INVALID, "nx, ny, nz must be >= 1");
+  const long cells = (long)d->nx * d->ny * d->nz;
+  if (cells > 2147483647L) return lfail(ROD_E_INVALID, "more than 2^31 - 1 cells");
+  if (!(d->tau > 0.5) || !std::isfinite(d->tau)) return lfail(ROD_E_INVALID, "tau must be > 1/2");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(d->force[k])) return lfail(ROD_E_INVALID, "force must be finite");
+  if (d->walls_z != 0 && d->walls_z != 1) return lfail(ROD_E_INVALID, "walls_z must be 0 or 1");
+  lbm_ctx* c = new lbm_ctx();
+  c->L = Lattice{d->nx, d->ny, d->nz, d->walls_z, cells, d->tau, d->force[0], d->force[1],
+                 d->force[2]};
+  c->s = (hipStream_t)hip_stream;
+  const size_t bytes = 19 * sizeof(double) * (size_t)cells;
+  hipError_t e = hipMalloc(&c->f[0], bytes);
+  if (e == hipSuccess) e = hipMalloc(&c->f[1], bytes);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->f[0], f0, bytes, hipMemcpyDeviceToDevice, c->s);
+  if (e != hipSuccess) {
+    if (c->f[0]) (void)hipFree(c->f[0]);
+    if (c->f[1]) (void)hipFree(c->f[1]);
+    delete c;
+    return lfail(ROD_E_HIP, "allocation or copy failed: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return ROD_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c) return lfail(ROD_E_INVALID, "context is NULL");
+  if (n < 0) return lfail(ROD_E_INVALID, "n must be >= 0");
+  for (int64_t k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(k_lbm, dim3(lblocks(c->L.cells)), dim3(256), 0, c->s, c->L,
+                       (const double*)c->f[c->cur], c->f[1 - c->cur]);
+    LHIP(hipGetLastError());
+    c->cur = 1 - c->cur;
+  }
+  return ROD_OK;
+}
+
+int lbm_populations(lbm_ctx* c, double* f) {
+  if (!c || !f) return lfail(ROD_E_INVALID, "NULL argument");
+  LHIP(hipMemcpyAsync(f, c->f[c->cur], 19 * sizeof(double) * (size_t)c->L.cells,
+                      hipMemcpyDeviceToDevice, c->s));
+  return ROD_OK;
+}
+
+int lbm_moments(lbm_ctx* c, double* rho, double* u) {
+  if (!c || !rho || !u) return lfail(ROD_E_INVALID, "NULL argument");
+  hipLaunchKernelGGL(k_lbm_moments, dim3(lblocks(c->L.cells)), dim3(256), 0, c->s, c->L,
+                     (const double*)c->f[c->cur], rho, u);
+  LHIP(hipGetLastError());
+  return ROD_OK;
+}
+
+int lbm_free(lbm_ctx* c) {
+  if (!c) return ROD_OK;
+  (void)hipStreamSynchronize(c->s);
+  (void)hipFree(c->f[0]);
+  (void)hipFree(c->f[1]);
+  delete c;
+  return ROD_OK;
+}
+
+}  // extern "C"

@@ -14,15 +14,19 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    txt = open(os.path.join(ROOT, "include", "rod.h")).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(rod_[a-z_]+)\s*\(", txt)))
+    names = set()
+    for h in ("rod.h", "lbm.h"):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b((?:rod|lbm)_[a-z_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_exports_every_declared_function():
     lib = L.load()
     names = header_functions()
-    assert {"rod_init", "rod_step", "rod_energy", "rod_grad", "rod_free"} <= set(names)
+    assert {"rod_init", "rod_step", "rod_energy", "rod_grad", "rod_free", "rod_ramp",
+            "lbm_init", "lbm_step", "lbm_free"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
 
@@ -159,3 +163,24 @@ def test_missing_buffers_rejected():
     ctx = C.c_void_p()
     assert lib.rod_init(C.byref(ctx), C.byref(d), C.byref(b), None, 0) == L.ROD_E_INVALID
     assert "buffers are required" in lib.rod_last_error().decode()
+
+
+def test_lbm_descriptor_checks():
+    """lbm_init validates its descriptor before touching the GPU."""
+    lib = L.load()
+    dummy = C.c_void_p(16)  # never dereferenced: validation fails first
+    for over, msg in ((dict(nx=0), "nx"), (dict(tau=0.5), "tau"), (dict(tau=float("nan")), "tau"),
+                      (dict(walls_z=2), "walls_z"), (dict(nx=2048, ny=2048, nz=1024), "2^31")):
+        d = L.LbmDesc()
+        d.nx, d.ny, d.nz, d.tau, d.walls_z = 4, 4, 4, 0.8, 0
+        for k, v in over.items():
+            setattr(d, k, v)
+        ctx = C.c_void_p()
+        assert lib.lbm_init(C.byref(ctx), C.byref(d), dummy, None) == L.ROD_E_INVALID
+        assert msg in lib.lbm_last_error().decode()
+        assert ctx.value is None
+    d = L.LbmDesc()
+    d.nx = d.ny = d.nz = 4
+    d.tau = 0.8
+    d.force = (C.c_double * 3)(0.0, float("inf"), 0.0)
+    assert lib.lbm_init(C.byref(C.c_void_p()), C.byref(d), dummy, None) == L.ROD_E_INVALID
