@@ -300,6 +300,32 @@ def hbm_microbench(sizes, steps=10):
     return out
 
 
+def lbm_leg(n=256, steps=20):
+    """The lattice Boltzmann kernel on an n^3 periodic lattice at rest with a
+    small body force: time per step from HIP events on the stream it runs on,
+    against 304 bytes per cell update (19 populations read and 19 written)."""
+    import torch
+    from paper_2603_27279_amd import Lattice
+    w = torch.tensor([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12, dtype=torch.float64, device="cuda")
+    f0 = w.view(19, 1, 1, 1).expand(19, n, n, n).contiguous()
+    lat = Lattice(f0, tau=0.8, force=(1e-6, 0.0, 0.0))
+    del f0
+    lat.step(2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    lat.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / steps
+    lat.free()
+    cells = n ** 3
+    gbs = cells * 304.0 / (us * 1e-6) / 1e9
+    return {"lattice": f"{n}^3 D3Q19, FP64", "cells": cells, "us_per_step": us,
+            "mlups": cells / us, "bytes_per_cell": 304.0, "GB_s": gbs,
+            "frac_hbm": gbs / HBM_PEAK_GBS}
+
+
 def copy_bandwidth(mib=512, reps=20):
     """What a plain device-to-device copy reaches on this GPU (bytes read plus
     bytes written per second, median of `reps` launches): the practical ceiling
@@ -404,6 +430,8 @@ def main():
     ap.add_argument("--microbench-sizes", default="64",
                     help="comma-separated grid sides of the dipole-free rod array (x 1024 "
                          "particles per rod): 64 -> 4.2M particles, 128 -> 16.8M")
+    ap.add_argument("--no-lbm", action="store_true",
+                    help="skip the lattice Boltzmann kernel on a 256^3 lattice")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
     ap.add_argument("--dipole-cutoff", type=float, default=0.0,
@@ -519,6 +547,12 @@ def main():
     if not args.no_microbench:
         micro = hbm_microbench([int(v) for v in args.microbench_sizes.split(",") if v])
 
+    lbm_res = None
+    if not args.no_lbm:
+        lbm_res = lbm_leg()
+        if micro:
+            lbm_res["frac_copy"] = lbm_res["GB_s"] / micro[0]["plain_copy"]["GB_s"]
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_seconds)
@@ -546,6 +580,7 @@ def main():
         "kernel_us": kernels_us,
         "kernel_us_separate_terms": kernels_sep_us,
         "roofline": roof,
+        "lbm": lbm_res,
         "batching": batching,
         "adjoint": adj,
         "hbm_kernels": micro,
