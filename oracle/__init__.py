@@ -20,6 +20,7 @@ _LIB = os.path.join(_HERE, "librod_oracle.so")
 _lib = None
 
 BOND, DIPOLE, ZEEMAN, CONTACT, DAMP, EXT, ALL = 1, 2, 4, 8, 16, 32, 63
+FLUID = 64  # immersed-boundary penalty force (with a fluid velocity given)
 ENERGY_TERMS = ("stretch", "shear", "twist", "bend", "zeeman", "dipole", "contact",
                 "kinetic", "rotational")
 
@@ -49,6 +50,7 @@ class _System(C.Structure):
         ("bond_damping", C.c_void_p),
         ("contact_model", C.c_int32), ("contact_hm", C.c_double * 5),
         ("dipole_cutoff", C.c_double),
+        ("fluid_u", C.c_void_p), ("fluid_dt", C.c_double), ("fluid_F", C.c_void_p),
     ]
 
 
@@ -110,6 +112,12 @@ class System:
         s.exclude_depth = int(w["exclude_depth"])
         s.bond_damping = _p(keep["bond_damping"])
         s.dipole_cutoff = float(w.get("dipole_cutoff") or 0.0)
+        fu = w.get("fluid_u")
+        keep["fluid_u"] = None if fu is None else _f64(fu, (self.n, 3))
+        keep["fluid_F"] = np.zeros((max(self.n, 1), 3))
+        s.fluid_u = _p(keep["fluid_u"])
+        s.fluid_dt = float(w.get("fluid_dt") or 1.0)
+        s.fluid_F = _p(keep["fluid_F"])
         s.contact_model = contact_model(w)
         if s.contact_model == 1:
             s.contact_hm = (C.c_double * 5)(*[float(a) for a in w["contact_hm"]])
@@ -260,6 +268,8 @@ def run(w, nsteps, state=None, step0=0, mbody=None):
                 _p(st["T"]), _p(mb), _p(sy.field), C.c_int64(int(st["step"])),
                 C.c_int64(int(nsteps)), C.c_int32(prepared), _p(st["hist"]), C.c_int32(hist_in))
     st["step"] = int(st["step"]) + int(nsteps)
+    if w.get("fluid_u") is not None:
+        st["fluid_F"] = sy.keep["fluid_F"][:n].copy()  # penalty forces of the last evaluation
     return st
 
 

@@ -34,12 +34,18 @@ def equilibrium(rho, u):
     return W.reshape((19,) + (1,) * rho.ndim) * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * uu)
 
 
+def _force(g, shape):
+    """A uniform force [3] or a force field [3, nz, ny, nx], as a field."""
+    g = np.asarray(g, float)
+    return g.reshape(3, 1, 1, 1) * np.ones((1,) + shape) if g.ndim == 1 else g
+
+
 def moments(f, g):
     """Density and velocity with the half-force shift: rho u = sum_i f_i c_i + g/2
-    (g: body force density, [3])."""
+    (g: body force density, uniform [3] or a field [3, nz, ny, nx])."""
     rho = f.sum(axis=0)
     mom = np.einsum("id,i...->d...", C.astype(np.float64), f)
-    u = (mom + 0.5 * np.asarray(g, float).reshape(3, 1, 1, 1)) / rho
+    u = (mom + 0.5 * _force(g, f.shape[1:])) / rho
     return rho, u
 
 
@@ -48,10 +54,10 @@ def collide(f, tau, g):
     F_i = (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i . u) c_i] . g."""
     rho, u = moments(f, g)
     feq = equilibrium(rho, u)
-    g = np.asarray(g, float).reshape(3, 1, 1, 1)
+    g = _force(g, f.shape[1:])
     Cf = C.astype(np.float64)
     cu = np.einsum("id,d...->i...", Cf, u)
-    cg = np.einsum("id,d...->i...", Cf, g * np.ones_like(u))
+    cg = np.einsum("id,d...->i...", Cf, g)
     ug = np.sum(u * g, axis=0)
     Fi = (1 - 0.5 / tau) * W.reshape(19, 1, 1, 1) * (3 * (cg - ug) + 9 * cu * cg)
     return f - (f - feq) / tau + Fi
@@ -82,3 +88,83 @@ def run(f, nsteps, tau, g=(0.0, 0.0, 0.0), walls=False):
     for _ in range(nsteps):
         f = stream(collide(f, tau, g), walls)
     return f
+
+
+# ---------------------------------------------------------------- immersed boundary
+# Methods, "Immersed boundary coupling": fluid velocity interpolated at each
+# particle with a smoothed discrete delta, and the reaction force spread back
+# with the same delta. The paper does not name its delta; this is Peskin's
+# four-point function (phi(r) = (3 - 2|r| + sqrt(1 + 4|r| - 4 r^2)) / 8 for
+# |r| <= 1, (5 - 2|r| - sqrt(-7 + 12|r| - 4 r^2)) / 8 for 1 <= |r| <= 2,
+# 0 beyond), a product over the three axes, on a lattice periodic in every
+# axis, with nodes at integer coordinates.
+
+
+def peskin4(r):
+    r = np.abs(np.asarray(r, float))
+    out = np.zeros_like(r)
+    a = r <= 1
+    out[a] = (3 - 2 * r[a] + np.sqrt(1 + 4 * r[a] - 4 * r[a] ** 2)) / 8
+    b = (r > 1) & (r <= 2)
+    out[b] = (5 - 2 * r[b] - np.sqrt(-7 + 12 * r[b] - 4 * r[b] ** 2)) / 8
+    return out
+
+
+def stencil(X, shape):
+    """The 4 x 4 x 4 lattice nodes around position X (x, y, z) and their
+    weights: lists of (iz, iy, ix) index arrays (wrapped) and weights."""
+    nz, ny, nx = shape
+    base = np.floor(np.asarray(X, float)).astype(np.int64) - 1  # x, y, z
+    o = np.arange(4)
+    wx = peskin4(base[0] + o - X[0])
+    wy = peskin4(base[1] + o - X[1])
+    wz = peskin4(base[2] + o - X[2])
+    ix, iy, iz = (base[0] + o) % nx, (base[1] + o) % ny, (base[2] + o) % nz
+    W = wz[:, None, None] * wy[None, :, None] * wx[None, None, :]
+    return np.ix_(iz, iy, ix), W
+
+
+def interpolate(u, X):
+    """U(X) = sum over nodes of u(x) delta(x - X), u [3, nz, ny, nx], X [P, 3]."""
+    shape = u.shape[1:]
+    out = np.zeros((len(X), 3))
+    for p, Xp in enumerate(X):
+        idx, W = stencil(Xp, shape)
+        for d in range(3):
+            out[p, d] = np.sum(u[d][idx] * W)
+    return out
+
+
+def spread(F, X, shape):
+    """Force density field [3, nz, ny, nx] of point forces F [P, 3] at X [P, 3]."""
+    g = np.zeros((3,) + tuple(shape))
+    for p, Xp in enumerate(X):
+        idx, W = stencil(Xp, shape)
+        for d in range(3):
+            np.add.at(g[d], idx, F[p, d] * W)
+    return g
+
+
+def coupled(w, f, ncycles, nsub, tau, g=(0.0, 0.0, 0.0), state=None):
+    """Rods of workload w immersed in the lattice f (Methods, "Immersed boundary
+    coupling"), positions in lattice units, the rods' dt = 1 / nsub of the fluid
+    step. Each cycle: the fluid velocity (with the half-force shift of the
+    uniform force g) is interpolated at every particle once; then nsub rod
+    steps, each evaluation adding the penalty force m_p (U_p - v_p) (fluid time
+    step 1) and each spreading the reaction -F_p / nsub at the particles'
+    positions of that evaluation; then one fluid step with g plus the spread
+    forces. The state before the first cycle carries no penalty force.
+    Returns (rod state, populations)."""
+    import oracle as rod_oracle
+    shape = f.shape[1:]
+    st = rod_oracle.run(w, 0) if state is None else state
+    for _ in range(ncycles):
+        _, u = moments(f, g)
+        U = interpolate(u, st["x"])
+        wf = dict(w, fluid_u=U, fluid_dt=1.0)
+        field = np.zeros((3,) + tuple(shape))
+        for _s in range(nsub):
+            st = rod_oracle.run(wf, 1, state=st)
+            field += spread(-st["fluid_F"] / nsub, st["x"], shape)
+        f = run(f, 1, tau, g=_force(g, shape) + field)
+    return st, f

@@ -170,6 +170,12 @@ struct Model {
   // Dipole-dipole cutoff: 0 for every pair of a member; otherwise only pairs
   // with r^2 = (dx dx + dy dy) + dz dz < dcut^2 interact.
   double dcut = 0;
+  // Immersed-boundary penalty (Methods, "Immersed boundary coupling"): the fluid
+  // velocity interpolated at each particle ([N][3], or null: no coupling), the
+  // fluid time step (kappa_p = m_p / fluid_dt) and where the forces go ([N][3]).
+  const double* fluid_u = nullptr;
+  double fluid_dt = 1.0;
+  double* fluid_F = nullptr;
 };
 
 // Tangential displacement history of Hertz-Mindlin contacts: for particle i,
@@ -203,6 +209,9 @@ struct orc_system {
   int32_t contact_model;       // 0 Hookean, 1 Hertz-Mindlin
   double contact_hm[5];        // Hertz-Mindlin: E, nu, mu, g_n, g_t
   double dipole_cutoff;        // 0: all pairs of a member; > 0: pairs closer than this
+  const double* fluid_u;       // [N][3] fluid velocity at the particles, or NULL
+  double fluid_dt;             // fluid time step (penalty stiffness m_p / fluid_dt)
+  double* fluid_F;             // [N][3] penalty force of the last evaluation, or NULL
 };
 
 }  // extern "C"
@@ -275,6 +284,7 @@ static Model build_model(const orc_system* s) {
   m.hmE = s->contact_hm[0]; m.hmNu = s->contact_hm[1]; m.hmMu = s->contact_hm[2];
   m.hmGn = s->contact_hm[3]; m.hmGt = s->contact_hm[4];
   m.dcut = s->dipole_cutoff;
+  m.fluid_u = s->fluid_u; m.fluid_dt = s->fluid_dt > 0 ? s->fluid_dt : 1.0; m.fluid_F = s->fluid_F;
   return m;
 }
 
@@ -410,7 +420,8 @@ template <class T> V3<T> field_B(const Field<T>& f, V3<T> x) {
           f.B0.z + f.G[6] * x.x + f.G[7] * x.y + f.G[8] * x.z};
 }
 
-enum { T_BOND = 1, T_DIPOLE = 2, T_ZEEMAN = 4, T_CONTACT = 8, T_DAMP = 16, T_EXT = 32, T_ALL = 63 };
+enum { T_BOND = 1, T_DIPOLE = 2, T_ZEEMAN = 4, T_CONTACT = 8, T_DAMP = 16, T_EXT = 32, T_ALL = 63,
+       T_FLUID = 64 };
 
 static bool excluded(const Model& md, int i, int j) {
   if (md.member_of[i] != md.member_of[j]) return true;
@@ -637,6 +648,17 @@ void forces(const Model& md, const T* x, const T* q, const T* v, const T* w,
       add3(Tq, p, T(-md.damping * md.inertia[p]) * ld3(w, p));
     }
   }
+  // Immersed-boundary penalty force kappa_p (U_p - v_p), kappa_p = m_p / fluid_dt,
+  // with the velocities the evaluation sees (half-step ones while stepping).
+  if constexpr (std::is_same<T, double>::value) {
+    if ((mask & T_FLUID) && md.fluid_u) {
+      for (int p = 0; p < N; ++p) {
+        const V3<double> Fp = (md.mass[p] / md.fluid_dt) * (ld3(md.fluid_u, p) - ld3(v, p));
+        add3(F, p, Fp);
+        if (md.fluid_F) st3(md.fluid_F, p, Fp);
+      }
+    }
+  }
   if (mask & T_EXT) {
     for (int p = 0; p < N; ++p) {
       if (md.ext_force) add3(F, p, lift<T>(V3<double>{md.ext_force[3 * p], md.ext_force[3 * p + 1], md.ext_force[3 * p + 2]}));
@@ -701,7 +723,7 @@ void eval_forces(const Model& md, State<T>& s, const T* mbody, const T* field, i
   const bool hm = md.contact_on && md.contact_model == 1;
   CHist cnow;
   forces(md, s.x.data(), s.q.data(), s.v.data(), s.w.data(), mu.data(), field, n,
-         T_ALL, s.F.data(), s.Tq.data(), (T*)nullptr,
+         T_ALL | T_FLUID, s.F.data(), s.Tq.data(), (T*)nullptr,
          md.bond_damp && s.hist_valid ? s.hist.data() : nullptr,
          md.bond_damp ? hnow.data() : nullptr,
          hm && s.chist_valid ? &s.chist : nullptr, hm ? &cnow : nullptr);

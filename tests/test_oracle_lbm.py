@@ -84,3 +84,60 @@ def test_poiseuille_between_bounce_back_walls():
     _, u2 = lbm.moments(out2, (gx, 0, 0))
     want2 = gx / (2 * (1.0 / 3)) * (zz + 0.5) * (nz - 0.5 - zz)
     assert np.max(np.abs(u2[0, :, 0, 0] / want2 - 1)) > 1e-3
+
+
+def test_peskin_delta_moments():
+    """The four-point delta sums to one and has zero first moment at any
+    offset, so a uniform field interpolates exactly and a spread point force
+    keeps its total and its point of application."""
+    rng = np.random.default_rng(3)
+    shape = (9, 8, 10)
+    for X in rng.uniform(0, 8, (6, 3)):
+        idx, W = lbm.stencil(X, shape)
+        assert W.sum() == pytest.approx(1.0, abs=1e-14)
+        o = np.arange(4)
+        base = np.floor(X).astype(int) - 1
+        for d, sh in ((0, (1, 1, 4)), (1, (1, 4, 1)), (2, (4, 1, 1))):  # W is [z, y, x]
+            pos = (base[d] + o).reshape(sh)
+            assert abs(np.sum(W * (pos - X[d]))) <= 1e-14
+        U0 = np.array([0.01, -0.02, 0.03])
+        u = U0.reshape(3, 1, 1, 1) * np.ones((3,) + shape)
+        np.testing.assert_allclose(lbm.interpolate(u, X[None]), U0[None], rtol=1e-14)
+        F = rng.normal(size=(1, 3))
+        gfield = lbm.spread(F, X[None], shape)
+        np.testing.assert_allclose(gfield.reshape(3, -1).sum(1), F[0], rtol=1e-13)
+
+
+def test_coupled_cycle_conserves_momentum():
+    """Free rods in a periodic lattice: bonds and dipoles are internal, the
+    penalty force is paid back to the fluid, so P_rods + P_fluid +
+    (dt/2) sum F_p (the velocity-Verlet share of the last evaluation's penalty
+    force not yet in the rods' velocities) stays constant; the exchange is
+    real (both momenta change)."""
+    import workloads
+    rng = np.random.default_rng(4)
+    n = 6
+    x, off, mem = workloads.straight_rods([n, n], [(3.2, 4.1, 4.3), (3.7, 6.4, 5.1)], (1, 0, 0))
+    nsub = 4
+    w = workloads._base(x, off, mem, np.tile([1.0, 1, 1, 0.5], (2, 1)), np.tile([0, 0, 0.05], (2 * n, 1)),
+                        np.zeros(2 * n, np.int8), workloads._field_const(1, (0, 0, 0.2)),
+                        damping=0.0, dt=1.0 / nsub, precision="fp64")
+    w["v0"] = 0.01 * rng.normal(size=(2 * n, 3))
+    shape = (12, 12, 14)
+    f = lbm.equilibrium(np.ones(shape), 0.005 * rng.normal(size=(3,) + shape))
+    import oracle
+    m, _ = oracle.mass(w)
+    Cf = lbm.C.astype(float)
+
+    def Q(st, f):
+        Pf = np.einsum("id,i...->d...", Cf, f).reshape(3, -1).sum(1)
+        Pr = (m[:, None] * st["v"]).sum(0)
+        Fp = st.get("fluid_F", np.zeros((2 * n, 3))).sum(0)
+        return Pf + Pr + 0.5 * w["dt"] * Fp, Pf, Pr
+
+    st0 = oracle.run(w, 0)
+    q0, pf0, pr0 = Q(st0, f)
+    st, f1 = lbm.coupled(w, f, 3, nsub, tau=0.8, state=st0)
+    q1, pf1, pr1 = Q(st, f1)
+    np.testing.assert_allclose(q1, q0, rtol=0, atol=1e-13 * np.abs(pf0).sum())
+    assert np.max(np.abs(pr1 - pr0)) > 1e-4 * np.max(np.abs(pr0))
