@@ -18,12 +18,13 @@
  *
  * Every call returns ROD_OK (0) or a negative ROD_E_* code (rod.h) and sets
  * the message that lbm_last_error() returns. All work is enqueued on the
- * stream given to lbm_init. The immersed-boundary coupling of rods to the
- * fluid is not part of this interface.
+ * stream given to lbm_init. rod_lbm_cycles couples a rod context to a lattice
+ * (the immersed-boundary method).
  */
 #ifndef LBM_H
 #define LBM_H
 #include <stdint.h>
+#include "rod.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -57,6 +58,32 @@ int lbm_free(lbm_ctx* c);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char* lbm_last_error(void);
+
+/* Rods immersed in the lattice (Methods, "Immersed boundary coupling"), for
+ * n_cycles >= 0 lattice steps with n_sub >= 1 rod steps each. Particle
+ * positions are in lattice units (nodes at integer coordinates); the rod time
+ * step must be 1 / n_sub of the lattice step (|dt n_sub - 1| <= 1e-12), and the
+ * lattice must be periodic in every axis. One cycle:
+ *   1. density and velocity u of the lattice (velocity shifted by half the
+ *      uniform force);
+ *   2. U_p = sum over the 4 x 4 x 4 nodes x around X_p of u(x) delta(x - X_p),
+ *      delta the product over the axes of Peskin's four-point function
+ *      phi(r) = (3 - 2|r| + sqrt(1 + 4|r| - 4r^2)) / 8 for |r| <= 1,
+ *      (5 - 2|r| - sqrt(-7 + 12|r| - 4r^2)) / 8 for 1 < |r| <= 2, 0 beyond
+ *      (indices wrap periodically);
+ *   3. n_sub rod steps; every force evaluation adds the penalty force
+ *      F_p = m_p (U_p - v_p) (lattice step 1) with the half-step velocity, and
+ *      after each step -F_p / n_sub is spread with the same delta at the
+ *      particles' new positions into a force field;
+ *   4. one lattice step with the uniform force plus that field.
+ * The rod state at entry carries no penalty force. Work runs on the rod
+ * context's stream: the lattice's stream is synchronised first, and later work
+ * on it waits for the cycles. The coupling buffers (7 doubles per cell, 6 per
+ * particle) are allocated on first use and freed with their contexts. Errors:
+ * ROD_E_INVALID (arguments, time step, walls), ROD_E_STATE (a tape is being
+ * recorded), ROD_E_HIP; the message is rod_last_error()'s. Non-finite states and
+ * list overflows are reported by the next rod_sync, as for rod_step. */
+int rod_lbm_cycles(rod_ctx* c, lbm_ctx* l, int32_t n_sub, int64_t n_cycles);
 
 #ifdef __cplusplus
 }

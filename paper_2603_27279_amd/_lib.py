@@ -95,6 +95,7 @@ def load():
         "lbm_populations": [_P, _P],
         "lbm_moments": [_P, _P, _P],
         "lbm_free": [_P],
+        "rod_lbm_cycles": [_P, _P, i32, i64],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

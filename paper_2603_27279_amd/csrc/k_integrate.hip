@@ -192,10 +192,12 @@ __device__ __forceinline__ void dipole_sums(const Dev& d, long i, int mask, V3<d
 // (bond, dipole, Zeeman, contact, damping, external), with the dipole force Fd
 // and field Bd from dipole_sums; the dipole field is written to Bo when given.
 // HM: the contact law is Hertz-Mindlin, whose contacts also exert a torque (a
-// template argument, so that the Hookean kernels carry no extra load).
+// template argument, so that the Hookean kernels carry no extra load). FL: the
+// immersed-boundary penalty m_p / dt_fluid (U_p - v_p) with the velocity the
+// evaluation sees, also stored to d.ibm_f (only the unfused post kernel).
 // Loads are unconditional where the index is valid, so they are all in flight
 // together.
-template <bool HM>
+template <bool HM, bool FL = false>
 __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long lvl, double* Bo,
                                        const PIn& p, V3<double> Fd, V3<double> Bd, V3<double>& F,
                                        V3<double>& T) {
@@ -247,6 +249,11 @@ __device__ __forceinline__ void gather(const Dev& d, long i, int mask, long long
     F = F - (d.damping * mass) * p.v;
     T = T - (d.damping * inertia) * p.w;
   }
+  if constexpr (FL) {
+    const V3<double> Fp = (mass * d.ibm_idt) * (ld3(d.ibm_u, N, i) - p.v);
+    F = F + Fp;
+    st3(d.ibm_f, N, i, Fp);
+  }
   if (mask & 32) {
     if (d.extF) F = F + ld3(d.extF, N, i);
     if (d.extT) T = T + ld3(d.extT, N, i);
@@ -273,7 +280,7 @@ __device__ __forceinline__ void kick(const Dev& d, long i, V3<double> F, V3<doub
   if (!finite3(F) || !finite3(T) || !finite3(p.x)) atomicOr(&d.flags[FLAG_NONFINITE], 1u);
 }
 
-template <bool HM>
+template <bool HM, bool FL>
 __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double* Fo, double* To,
                                               double* Bo) {
   const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -290,7 +297,7 @@ __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double*
   V3<double> Fd, Bd;
   dipole_sums(d, i, mask, Fd, Bd);
   V3<double> F, T;
-  gather<HM>(d, i, mask, lvl, Bo, p, Fd, Bd, F, T);
+  gather<HM, FL>(d, i, mask, lvl, Bo, p, Fd, Bd, F, T);
   if (mode == POST_EVAL) {
     st3(Fo, N, i, F);
     st3(To, N, i, T);
@@ -395,8 +402,14 @@ hipError_t launch_post(const Dev& d, int mode, int mask, double* Fo, double* To,
                        hipStream_t s, const hipEvent_t* ev) {
   const int bs = particle_block(d.n);
   const dim3 g(blocks_for(d.i_hi - d.i_lo, bs)), b(bs);
-  if (d.hm) launch_k(ev, k_post<true>, g, b, s, d, mode, mask, Fo, To, Bo);
-  else launch_k(ev, k_post<false>, g, b, s, d, mode, mask, Fo, To, Bo);
+  if (d.ibm_u) {
+    if (d.hm) launch_k(ev, k_post<true, true>, g, b, s, d, mode, mask, Fo, To, Bo);
+    else launch_k(ev, k_post<false, true>, g, b, s, d, mode, mask, Fo, To, Bo);
+  } else if (d.hm) {
+    launch_k(ev, k_post<true, false>, g, b, s, d, mode, mask, Fo, To, Bo);
+  } else {
+    launch_k(ev, k_post<false, false>, g, b, s, d, mode, mask, Fo, To, Bo);
+  }
   return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@
 // 19 out; the kernel is bound by HBM bandwidth.
 #include "rod.h"
 #include "lbm.h"
+#include "lbm_internal.h"
 
 #include <hip/hip_runtime.h>
 #include <cmath>
@@ -42,11 +43,6 @@ __device__ __forceinline__ double weight(int i) {
   return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
-struct Lattice {
-  int nx, ny, nz, walls;
-  long cells;
-  double tau, gx, gy, gz;
-};
 
 __global__ __launch_bounds__(256) void k_lbm(Lattice L, const double* __restrict__ src,
                                              double* __restrict__ dst) {
@@ -64,14 +60,17 @@ __global__ __launch_bounds__(256) void k_lbm(Lattice L, const double* __restrict
     rho += f[i];
     mx += CX(i) * f[i]; my += CY(i) * f[i]; mz += CZ(i) * f[i];
   }
-  const double ux = (mx + 0.5 * L.gx) / rho, uy = (my + 0.5 * L.gy) / rho,
-               uz = (mz + 0.5 * L.gz) / rho;
-  const double uu = ux * ux + uy * uy + uz * uz, ug = ux * L.gx + uy * L.gy + uz * L.gz;
+  double gx = L.gx, gy = L.gy, gz = L.gz;  // uniform force plus the spread field
+  if (L.gfield) {
+    gx += L.gfield[c]; gy += L.gfield[L.cells + c]; gz += L.gfield[2 * L.cells + c];
+  }
+  const double ux = (mx + 0.5 * gx) / rho, uy = (my + 0.5 * gy) / rho, uz = (mz + 0.5 * gz) / rho;
+  const double uu = ux * ux + uy * uy + uz * uz, ug = ux * gx + uy * gy + uz * gz;
   const double omega = 1.0 / L.tau, pre = 1.0 - 0.5 / L.tau;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
     const double cu = CX(i) * ux + CY(i) * uy + CZ(i) * uz;
-    const double cg = CX(i) * L.gx + CY(i) * L.gy + CZ(i) * L.gz;
+    const double cg = CX(i) * gx + CY(i) * gy + CZ(i) * gz;
     const double w = weight(i);
     const double feq = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
     const double fs = f[i] - omega * (f[i] - feq) + pre * w * (3.0 * (cg - ug) + 9.0 * cu * cg);
@@ -103,16 +102,121 @@ __global__ __launch_bounds__(256) void k_lbm_moments(Lattice L, const double* __
   u_o[2 * L.cells + c] = (mz + 0.5 * L.gz) / rho;
 }
 
+// ---------------------------------------------------------------- immersed boundary
+// Peskin's four-point delta along one axis.
+__device__ __forceinline__ double peskin4(double r) {
+  r = fabs(r);
+  if (r <= 1.0) return (3.0 - 2.0 * r + sqrt(1.0 + 4.0 * r - 4.0 * r * r)) * 0.125;
+  if (r <= 2.0) return (5.0 - 2.0 * r - sqrt(-7.0 + 12.0 * r - 4.0 * r * r)) * 0.125;
+  return 0.0;
+}
+
+// Stencil of position (x, y, z): the 4 nodes per axis from floor - 1, their
+// weights and wrapped indices.
+struct Stencil {
+  double wx[4], wy[4], wz[4];
+  int ix[4], iy[4], iz[4];
+};
+
+__device__ __forceinline__ Stencil stencil(const Lattice& L, double x, double y, double z) {
+  Stencil s;
+  const int bx = (int)floor(x) - 1, by = (int)floor(y) - 1, bz = (int)floor(z) - 1;
+#pragma unroll
+  for (int o = 0; o < 4; ++o) {
+    s.wx[o] = peskin4((double)(bx + o) - x);
+    s.wy[o] = peskin4((double)(by + o) - y);
+    s.wz[o] = peskin4((double)(bz + o) - z);
+    s.ix[o] = (((bx + o) % L.nx) + L.nx) % L.nx;
+    s.iy[o] = (((by + o) % L.ny) + L.ny) % L.ny;
+    s.iz[o] = (((bz + o) % L.nz) + L.nz) % L.nz;
+  }
+  return s;
+}
+
+// Fluid velocity at each particle: U(X) = sum over the 64 stencil nodes of
+// u(x) delta(x - X); u [3][cells] (the velocity plane of the moments).
+__global__ __launch_bounds__(256) void k_ibm_interp(Lattice L, const double* __restrict__ u,
+                                                   const double* __restrict__ X, long n,
+                                                   double* U) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const Stencil s = stencil(L, X[p], X[n + p], X[2 * n + p]);
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double w = s.wz[a] * s.wy[b] * s.wx[e];
+        const long c = ((long)s.iz[a] * L.ny + s.iy[b]) * L.nx + s.ix[e];
+        ax += u[c] * w; ay += u[L.cells + c] * w; az += u[2 * L.cells + c] * w;
+      }
+  U[p] = ax; U[n + p] = ay; U[2 * n + p] = az;
+}
+
+// Spread -scale F_p of every particle onto the force field g [3][cells]
+// (FP64 atomics: the sums agree to rounding with any order).
+__global__ __launch_bounds__(256) void k_ibm_spread(Lattice L, const double* __restrict__ X,
+                                                   const double* __restrict__ F, long n,
+                                                   double scale, double* g) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const Stencil s = stencil(L, X[p], X[n + p], X[2 * n + p]);
+  const double fx = -scale * F[p], fy = -scale * F[n + p], fz = -scale * F[2 * n + p];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double w = s.wz[a] * s.wy[b] * s.wx[e];
+        const long c = ((long)s.iz[a] * L.ny + s.iy[b]) * L.nx + s.ix[e];
+        atomicAdd(&g[c], fx * w);
+        atomicAdd(&g[L.cells + c], fy * w);
+        atomicAdd(&g[2 * L.cells + c], fz * w);
+      }
+}
+
+__global__ __launch_bounds__(256) void k_fill0(double* a, long n) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) a[k] = 0.0;
+}
+
 }  // namespace lbmx
 
 using namespace lbmx;
 
-struct lbm_ctx {
-  Lattice L;
-  double* f[2] = {nullptr, nullptr};
-  int cur = 0;
-  hipStream_t s = nullptr;
-};
+namespace lbmx {
+static unsigned blocks_of(long n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_lbm_step(lbm_ctx* c, const double* gfield, hipStream_t s) {
+  Lattice L = c->L;
+  L.gfield = gfield;
+  hipLaunchKernelGGL(k_lbm, dim3(blocks_of(L.cells)), dim3(256), 0, s, L,
+                     (const double*)c->f[c->cur], c->f[1 - c->cur]);
+  c->cur = 1 - c->cur;
+  return hipGetLastError();
+}
+hipError_t launch_lbm_moments(const lbm_ctx* c, double* rho, double* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_lbm_moments, dim3(blocks_of(c->L.cells)), dim3(256), 0, s, c->L,
+                     (const double*)c->f[c->cur], rho, u);
+  return hipGetLastError();
+}
+hipError_t launch_ibm_interp(const lbm_ctx* c, const double* u, const double* X, long n, double* U,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ibm_interp, dim3(blocks_of(n)), dim3(256), 0, s, c->L, u, X, n, U);
+  return hipGetLastError();
+}
+hipError_t launch_ibm_spread(const lbm_ctx* c, const double* X, const double* F, long n,
+                             double scale, double* g, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ibm_spread, dim3(blocks_of(n)), dim3(256), 0, s, c->L, X, F, n, scale, g);
+  return hipGetLastError();
+}
+hipError_t launch_fill0(double* a, long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill0, dim3(blocks_of(n)), dim3(256), 0, s, a, n);
+  return hipGetLastError();
+}
+}  // namespace lbmx
+
 
 static thread_local std::string g_lbm_err;
 
@@ -150,7 +254,7 @@ int lbm_init(lbm_ctx** out, const lbm_desc* d, const double* f0, void* hip_strea
   if (d->walls_z != 0 && d->walls_z != 1) return lfail(ROD_E_INVALID, "walls_z must be 0 or 1");
   lbm_ctx* c = new lbm_ctx();
   c->L = Lattice{d->nx, d->ny, d->nz, d->walls_z, cells, d->tau, d->force[0], d->force[1],
-                 d->force[2]};
+                 d->force[2], nullptr};
   c->s = (hipStream_t)hip_stream;
   const size_t bytes = 19 * sizeof(double) * (size_t)cells;
   hipError_t e = hipMalloc(&c->f[0], bytes);
@@ -196,8 +300,10 @@ int lbm_moments(lbm_ctx* c, double* rho, double* u) {
 int lbm_free(lbm_ctx* c) {
   if (!c) return ROD_OK;
   (void)hipStreamSynchronize(c->s);
+  (void)hipDeviceSynchronize();  // a coupled cycle may have used it on another stream
   (void)hipFree(c->f[0]);
   (void)hipFree(c->f[1]);
+  if (c->work) (void)hipFree(c->work);
   delete c;
   return ROD_OK;
 }

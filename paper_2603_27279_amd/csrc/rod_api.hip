@@ -4,6 +4,8 @@
 // used by the reverse pass.
 #include "rod.h"
 #include "rod_internal.h"
+#include "lbm.h"
+#include "lbm_internal.h"
 #include "rod_adjoint.h"
 
 #include <algorithm>
@@ -50,6 +52,7 @@ struct rod_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   Dev d;
   std::vector<void*> allocs;
+  double* ibm_buf = nullptr;  // coupled cycles: fluid velocity and penalty force [6][N]
   DipWork* work = nullptr;
   int nwork = 0, max_slots = 1;
   std::vector<void*> plan_allocs;   // dipole work list, slot counts, partial slots
@@ -641,6 +644,7 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   // cells to walk around a particle's own so that the dipole lists reach dcut + skin
   d.dcell_k = d.dcut > 0 ? (int)std::ceil((d.dcut + d.skin) * d.inv_cell) : 0;
   d.dnbr = nullptr; d.dnbr_cnt = nullptr; d.xm = nullptr;
+  d.ibm_u = nullptr; d.ibm_f = nullptr; d.ibm_idt = 1.0;
   if (d.dcut > 0 && ((rc = dalloc(c, &d.dnbr, (size_t)DNBR_CAP * N)) ||
                      (rc = dalloc(c, &d.dnbr_cnt, (size_t)N)) ||
                      (rc = dalloc(c, &d.xm, 8 * (size_t)N))))
@@ -1108,6 +1112,52 @@ struct TmpDev {  // device memory of one call
 };
 }  // namespace
 
+// Rods immersed in a lattice (Methods, "Immersed boundary coupling"). Per
+// cycle: moments of the lattice, its velocity interpolated at every particle,
+// then n_sub rod steps whose post kernel adds the penalty force and records it,
+// each followed by the spreading of -F_p / n_sub at the new positions, then one
+// lattice step with that force field. Everything runs on the rod stream; the
+// lattice stream is drained first and made to wait for the result.
+extern "C" int rod_lbm_cycles(rod_ctx* c, lbm_ctx* l, int32_t n_sub, int64_t n_cycles) {
+  if (!c || !l) return fail(ROD_E_INVALID, "NULL argument");
+  if (n_sub < 1 || n_cycles < 0) return fail(ROD_E_INVALID, "need n_sub >= 1 and n_cycles >= 0");
+  if (std::fabs(c->desc.dt * n_sub - 1.0) > 1e-12)
+    return fail(ROD_E_INVALID, "the rod time step times n_sub must be the lattice step 1 (dt = %g)", c->desc.dt);
+  if (l->L.walls) return fail(ROD_E_INVALID, "the coupling needs a lattice periodic in every axis");
+  if (c->tape.active) return fail(ROD_E_STATE, "coupled cycles while a tape is recorded");
+  if (n_cycles == 0) return ROD_OK;
+  const long N = c->d.n, cells = l->L.cells;
+  if (!l->work) HIPC(hipMalloc(&l->work, sizeof(double) * 7 * (size_t)cells));
+  if (!c->ibm_buf) HIPC(hipMalloc(&c->ibm_buf, sizeof(double) * 6 * (size_t)N));
+  double* rho = l->work;
+  double* u = rho + cells;
+  double* g = u + 3 * cells;
+  Dev d = c->d;
+  d.ibm_u = c->ibm_buf;
+  d.ibm_f = c->ibm_buf + 3 * N;
+  d.ibm_idt = 1.0;
+  HIPC(hipStreamSynchronize(l->s));
+  TRY(enter(c));
+  for (int64_t k = 0; k < n_cycles; ++k) {
+    HIPC(lbmx::launch_lbm_moments(l, rho, u, c->s));
+    HIPC(lbmx::launch_ibm_interp(l, u, d.x, N, c->ibm_buf, c->s));
+    HIPC(lbmx::launch_fill0(g, 3 * cells, c->s));
+    for (int32_t sub = 0; sub < n_sub; ++sub) {
+      TIMED(c, ROD_KERNEL_PRE, launch_pre, d, PRE_STEP, c->s);
+      TRY(force_terms(c, d, 0, 1));
+      TIMED(c, ROD_KERNEL_POST, launch_post, d, POST_KICK, ROD_TERM_ALL, nullptr, nullptr, nullptr,
+            c->s);
+      HIPC(lbmx::launch_ibm_spread(l, d.x, d.ibm_f, N, 1.0 / n_sub, g, c->s));
+    }
+    HIPC(lbmx::launch_lbm_step(l, g, c->s));
+  }
+  c->h_step += n_cycles * n_sub;
+  HIPC(hipEventRecord(c->ev_out, c->s));
+  HIPC(hipStreamWaitEvent(l->s, c->ev_out, 0));
+  TRY(leave(c));
+  return ROD_OK;
+}
+
 extern "C" int rod_ramp(rod_ctx* c, const double* fields, int32_t n_inc, int32_t max_steps,
                         int32_t check_every, double ke_tol, const int32_t* watch, int32_t n_watch,
                         double* x_watch, int32_t* steps, double* ke) {
@@ -1172,6 +1222,7 @@ int rod_free(rod_ctx* c) {
   if (c->tgexec) (void)hipGraphExecDestroy(c->tgexec);
   tape_release(c->tape);
   for (void* p : c->allocs) (void)hipFree(p);
+  if (c->ibm_buf) (void)hipFree(c->ibm_buf);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   if (c->s) (void)hipStreamDestroy(c->s);

@@ -103,6 +103,12 @@ struct Dev {
   int* dnbr;               // [DNBR_CAP][N]
   int* dnbr_cnt;           // [N]
   double* xm;              // [N][8]: x, y, z, 0, m_x, m_y, m_z, 0 of the level (cutoff), or null
+  // Immersed-boundary penalty (set only on the copy a coupled cycle launches
+  // with): fluid velocity at the particles [3][N], the penalty force of the
+  // evaluation written to ibm_f [3][N], stiffness m_p * ibm_idt.
+  const double* ibm_u;
+  double* ibm_f;
+  double ibm_idt;
 };
 
 constexpr int CELL_CAP = 8;

@@ -173,6 +173,12 @@ class RodSim:
                                   p(ke)))
         return dict(x_watch=xw[:, :nw], steps=steps, ke=ke)
 
+    def lbm_cycles(self, lattice, n_sub, n_cycles):
+        """Immersed-boundary coupling (rod_lbm_cycles): ``n_cycles`` lattice
+        steps of ``lattice`` (a paper_2603_27279_amd.Lattice), ``n_sub`` rod
+        steps each, rod dt = 1 / n_sub, positions in lattice units."""
+        L.check(self.lib.rod_lbm_cycles(self.ctx, lattice.ctx, int(n_sub), int(n_cycles)))
+
     def tape_begin(self):
         L.check(self.lib.rod_tape_begin(self.ctx))
 
