@@ -326,6 +326,49 @@ def lbm_leg(n=256, steps=20):
             "frac_hbm": gbs / HBM_PEAK_GBS}
 
 
+def ibm_leg(grid=16, nsub=10, cycles=20, shape=(96, 128, 128)):
+    """Cilia immersed in a lattice (rod_lbm_cycles): a grid x grid carpet of
+    clamped rods of 16 to 64 particles at pitch 8, in a rotating field, moved 4
+    lattice units in from x = y = 0 and 2 up from z = 0, in a periodic lattice
+    [nz, ny, nx] = shape at rest, nsub rod steps of dt = 1 / nsub per lattice
+    step (mixed precision rods, FP64 fluid). Time per cycle from HIP events on
+    the calling stream, beside the lattice step alone on the same lattice."""
+    import torch
+    import workloads
+    from paper_2603_27279_amd import Lattice, RodSim
+    w = workloads.cilia_carpet(grid=(grid, grid), pitch=8.0, len_range=(16, 64), dt=1.0 / nsub)
+    for k in ("x0", "x_ref"):
+        w[k] = np.asarray(w[k]) + np.array([4.0, 4.0, 2.0])
+    nz, ny, nx = shape
+    assert np.all(w["x0"].max(0) < np.array([nx, ny, nz]))
+    wt = torch.tensor([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12, dtype=torch.float64, device="cuda")
+    f0 = wt.view(19, 1, 1, 1).expand(19, nz, ny, nx).contiguous()
+    sim = RodSim(w, precision=w["precision"])
+    lat = Lattice(f0, tau=0.8)
+    del f0
+    sim.lbm_cycles(lat, nsub, 2)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return 1e3 * e0.elapsed_time(e1) / cycles
+
+    us = timed(lambda: sim.lbm_cycles(lat, nsub, cycles))
+    us_lat = timed(lambda: lat.step(cycles))
+    sim.sync()  # reports non-finite states or list overflow
+    n, cells = int(w["n"]), nx * ny * nz
+    sim.free()
+    lat.free()
+    return {"workload": f"{grid}x{grid} cilia carpet (16-64 particles) in a {nx}x{ny}x{nz} periodic lattice",
+            "particles": n, "cells": cells, "n_sub": nsub, "us_per_cycle": us,
+            "us_lattice_step": us_lat, "us_rods_and_coupling": us - us_lat,
+            "particle_steps_per_s": n * nsub / (us * 1e-6), "mlups": cells / us}
+
+
 def copy_bandwidth(mib=512, reps=20):
     """What a plain device-to-device copy reaches on this GPU (bytes read plus
     bytes written per second, median of `reps` launches): the practical ceiling
@@ -432,6 +475,10 @@ def main():
                          "particles per rod): 64 -> 4.2M particles, 128 -> 16.8M")
     ap.add_argument("--no-lbm", action="store_true",
                     help="skip the lattice Boltzmann kernel on a 256^3 lattice")
+    ap.add_argument("--no-ibm", action="store_true",
+                    help="skip the cilia carpet immersed in a lattice (rod_lbm_cycles)")
+    ap.add_argument("--ibm", action="store_true",
+                    help="only run the immersed cilia carpet and print it as JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
     ap.add_argument("--dipole-cutoff", type=float, default=0.0,
@@ -446,6 +493,9 @@ def main():
         return
     if args.helix_loop is not None:
         print(json.dumps({"helix_loop": helix_loop(args.helix_loop)}))
+        return
+    if args.ibm:
+        print(json.dumps({"ibm": ibm_leg()}))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -552,6 +602,7 @@ def main():
         lbm_res = lbm_leg()
         if micro:
             lbm_res["frac_copy"] = lbm_res["GB_s"] / micro[0]["plain_copy"]["GB_s"]
+    ibm_res = None if args.no_ibm else ibm_leg()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -581,6 +632,7 @@ def main():
         "kernel_us_separate_terms": kernels_sep_us,
         "roofline": roof,
         "lbm": lbm_res,
+        "ibm": ibm_res,
         "batching": batching,
         "adjoint": adj,
         "hbm_kernels": micro,

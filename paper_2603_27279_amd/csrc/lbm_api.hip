@@ -111,67 +111,62 @@ __device__ __forceinline__ double peskin4(double r) {
   return 0.0;
 }
 
-// Stencil of position (x, y, z): the 4 nodes per axis from floor - 1, their
-// weights and wrapped indices.
-struct Stencil {
-  double wx[4], wy[4], wz[4];
-  int ix[4], iy[4], iz[4];
-};
-
-__device__ __forceinline__ Stencil stencil(const Lattice& L, double x, double y, double z) {
-  Stencil s;
-  const int bx = (int)floor(x) - 1, by = (int)floor(y) - 1, bz = (int)floor(z) - 1;
-#pragma unroll
-  for (int o = 0; o < 4; ++o) {
-    s.wx[o] = peskin4((double)(bx + o) - x);
-    s.wy[o] = peskin4((double)(by + o) - y);
-    s.wz[o] = peskin4((double)(bz + o) - z);
-    s.ix[o] = (((bx + o) % L.nx) + L.nx) % L.nx;
-    s.iy[o] = (((by + o) % L.ny) + L.ny) % L.ny;
-    s.iz[o] = (((bz + o) % L.nz) + L.nz) % L.nz;
-  }
-  return s;
+// One node of the 4 x 4 x 4 stencil of position (x, y, z) per lane: lane k of
+// the particle's wave takes x offset k & 3, y offset (k >> 2) & 3, z offset
+// k >> 4 from floor - 1, so the 64 lanes of a wave touch 64 distinct nodes.
+// Returns the node's cell index (wrapped periodically) and its weight
+// (phi_z phi_y) phi_x.
+__device__ __forceinline__ long stencil_node(const Lattice& L, double x, double y, double z, int k,
+                                             double& w) {
+  const int ox = k & 3, oy = (k >> 2) & 3, oz = k >> 4;
+  const int nx = (int)floor(x) - 1 + ox, ny = (int)floor(y) - 1 + oy, nz = (int)floor(z) - 1 + oz;
+  w = peskin4((double)nz - z) * peskin4((double)ny - y) * peskin4((double)nx - x);
+  const int ix = ((nx % L.nx) + L.nx) % L.nx, iy = ((ny % L.ny) + L.ny) % L.ny,
+            iz = ((nz % L.nz) + L.nz) % L.nz;
+  return ((long)iz * L.ny + iy) * L.nx + ix;
 }
 
 // Fluid velocity at each particle: U(X) = sum over the 64 stencil nodes of
-// u(x) delta(x - X); u [3][cells] (the velocity plane of the moments).
+// u(x) delta(x - X); u [3][cells] (the velocity plane of the moments). One
+// wave per particle, the node terms summed across the wave.
 __global__ __launch_bounds__(256) void k_ibm_interp(Lattice L, const double* __restrict__ u,
                                                    const double* __restrict__ X, long n,
                                                    double* U) {
-  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const Stencil s = stencil(L, X[p], X[n + p], X[2 * n + p]);
-  double ax = 0.0, ay = 0.0, az = 0.0;
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b)
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long p = t >> 6;
+  if (p >= n) return;  // whole waves: 64 divides the block size
+  const int k = (int)(t & 63);
+  double w;
+  const long c = stencil_node(L, X[p], X[n + p], X[2 * n + p], k, w);
+  double ax = u[c] * w, ay = u[L.cells + c] * w, az = u[2 * L.cells + c] * w;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const double w = s.wz[a] * s.wy[b] * s.wx[e];
-        const long c = ((long)s.iz[a] * L.ny + s.iy[b]) * L.nx + s.ix[e];
-        ax += u[c] * w; ay += u[L.cells + c] * w; az += u[2 * L.cells + c] * w;
-      }
-  U[p] = ax; U[n + p] = ay; U[2 * n + p] = az;
+  for (int o = 32; o > 0; o >>= 1) {
+    ax += __shfl_xor(ax, o);
+    ay += __shfl_xor(ay, o);
+    az += __shfl_xor(az, o);
+  }
+  if (k == 0) {
+    U[p] = ax; U[n + p] = ay; U[2 * n + p] = az;
+  }
 }
 
-// Spread -scale F_p of every particle onto the force field g [3][cells]
-// (FP64 atomics: the sums agree to rounding with any order).
+// Spread -scale F_p of every particle onto the force field g [3][cells]: one
+// wave per particle, each lane adding its node's share with a hardware FP64
+// atomic (device memory from hipMalloc is coarse-grained, where these are
+// exact adds; the sums agree to rounding with any order).
 __global__ __launch_bounds__(256) void k_ibm_spread(Lattice L, const double* __restrict__ X,
                                                    const double* __restrict__ F, long n,
                                                    double scale, double* g) {
-  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long p = t >> 6;
   if (p >= n) return;
-  const Stencil s = stencil(L, X[p], X[n + p], X[2 * n + p]);
+  const int k = (int)(t & 63);
+  double w;
+  const long c = stencil_node(L, X[p], X[n + p], X[2 * n + p], k, w);
   const double fx = -scale * F[p], fy = -scale * F[n + p], fz = -scale * F[2 * n + p];
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const double w = s.wz[a] * s.wy[b] * s.wx[e];
-        const long c = ((long)s.iz[a] * L.ny + s.iy[b]) * L.nx + s.ix[e];
-        atomicAdd(&g[c], fx * w);
-        atomicAdd(&g[L.cells + c], fy * w);
-        atomicAdd(&g[2 * L.cells + c], fz * w);
-      }
+  unsafeAtomicAdd(&g[c], fx * w);
+  unsafeAtomicAdd(&g[L.cells + c], fy * w);
+  unsafeAtomicAdd(&g[2 * L.cells + c], fz * w);
 }
 
 __global__ __launch_bounds__(256) void k_fill0(double* a, long n) {
@@ -202,13 +197,13 @@ hipError_t launch_lbm_moments(const lbm_ctx* c, double* rho, double* u, hipStrea
 hipError_t launch_ibm_interp(const lbm_ctx* c, const double* u, const double* X, long n, double* U,
                              hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ibm_interp, dim3(blocks_of(n)), dim3(256), 0, s, c->L, u, X, n, U);
+  hipLaunchKernelGGL(k_ibm_interp, dim3(blocks_of(64 * n)), dim3(256), 0, s, c->L, u, X, n, U);
   return hipGetLastError();
 }
 hipError_t launch_ibm_spread(const lbm_ctx* c, const double* X, const double* F, long n,
                              double scale, double* g, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ibm_spread, dim3(blocks_of(n)), dim3(256), 0, s, c->L, X, F, n, scale, g);
+  hipLaunchKernelGGL(k_ibm_spread, dim3(blocks_of(64 * n)), dim3(256), 0, s, c->L, X, F, n, scale, g);
   return hipGetLastError();
 }
 hipError_t launch_fill0(double* a, long n, hipStream_t s) {
