@@ -21,6 +21,7 @@ _lib = None
 
 BOND, DIPOLE, ZEEMAN, CONTACT, DAMP, EXT, ALL = 1, 2, 4, 8, 16, 32, 63
 FLUID = 64  # immersed-boundary penalty force (with a fluid velocity given)
+HC_CAP = 32  # Hertz-Mindlin contacts per particle a continued state can carry
 ENERGY_TERMS = ("stretch", "shear", "twist", "bend", "zeeman", "dipole", "contact",
                 "kinetic", "rotational")
 
@@ -263,10 +264,21 @@ def run(w, nsteps, state=None, step0=0, mbody=None):
     hist_in = int(prepared and "hist" in st)
     if "hist" not in st:
         st["hist"] = np.zeros((max(1, n), 5))
+    # Hertz-Mindlin contacts of the last evaluation (partner, tangential
+    # displacement), carried by a continued state like the damping measures
+    hc_in = int(prepared and "hc_cnt" in st)
+    hc = (np.ascontiguousarray(st.get("hc_cnt", np.zeros(n)), dtype=np.int32),
+          np.ascontiguousarray(st.get("hc_j", np.zeros((n, HC_CAP))), dtype=np.int32),
+          np.ascontiguousarray(st.get("hc_s", np.zeros((n, HC_CAP, 3))), dtype=np.float64))
     mb = _f64(w["m_body"] if mbody is None else mbody, (n, 3))
-    lib.orc_run(sy.ref, _p(st["x"]), _p(st["v"]), _p(st["q"]), _p(st["w"]), _p(st["F"]),
-                _p(st["T"]), _p(mb), _p(sy.field), C.c_int64(int(st["step"])),
-                C.c_int64(int(nsteps)), C.c_int32(prepared), _p(st["hist"]), C.c_int32(hist_in))
+    rc = lib.orc_run(sy.ref, _p(st["x"]), _p(st["v"]), _p(st["q"]), _p(st["w"]), _p(st["F"]),
+                     _p(st["T"]), _p(mb), _p(sy.field), C.c_int64(int(st["step"])),
+                     C.c_int64(int(nsteps)), C.c_int32(prepared), _p(st["hist"]), C.c_int32(hist_in),
+                     _p(hc[0]), _p(hc[1]), _p(hc[2]), C.c_int32(HC_CAP), C.c_int32(hc_in))
+    if rc != 0:
+        raise RuntimeError(f"a particle has more than {HC_CAP} Hertz-Mindlin contacts")
+    if int(w.get("contact_on", 0)) and contact_model(w) == 1:
+        st["hc_cnt"], st["hc_j"], st["hc_s"] = hc
     st["step"] = int(st["step"]) + int(nsteps)
     if w.get("fluid_u") is not None:
         st["fluid_F"] = sy.keep["fluid_F"][:n].copy()  # penalty forces of the last evaluation
@@ -293,7 +305,7 @@ def ramp(w, fields, max_steps, check_every, ke_tol, watch=(), state=None, step0=
         prepared = 0
     else:
         st = {k: (np.array(v, dtype=np.float64, copy=True) if k != "step" else v)
-              for k, v in state.items() if k != "hist"}
+              for k, v in state.items() if k != "hist" and not k.startswith("hc_")}
         prepared = 1
     watch = np.ascontiguousarray(watch, dtype=np.int32)
     xw = np.zeros((n_inc, max(len(watch), 1), 3))

@@ -949,9 +949,15 @@ int orc_contact_pairs(const orc_system* s, const double* x, int32_t* pairs, int 
 // hist (nullable, [B][5]): bond damping measures of the last evaluation,
 // written at the end; read when continuing a prepared state with hist_in set
 // (without it the continued state's own measures are recorded first).
-void orc_run(const orc_system* s, double* x, double* v, double* q, double* w, double* F,
-             double* Tq, const double* mbody, const double* field, int64_t step0,
-             int64_t nsteps, int32_t prepared, double* hist, int32_t hist_in) {
+// hc_cnt [N], hc_j [N][hc_cap], hc_s [N][hc_cap][3] (nullable): the
+// Hertz-Mindlin contacts of the last evaluation (partner, tangential
+// displacement), written at the end and read when continuing with hc_in set, so
+// that a run cut in pieces keeps its tangential springs. Returns 0, or -1 when a
+// particle has more than hc_cap contacts to write.
+int orc_run(const orc_system* s, double* x, double* v, double* q, double* w, double* F,
+            double* Tq, const double* mbody, const double* field, int64_t step0,
+            int64_t nsteps, int32_t prepared, double* hist, int32_t hist_in, int32_t* hc_cnt,
+            int32_t* hc_j, double* hc_s, int32_t hc_cap, int32_t hc_in) {
   Model md = build_model(s);
   State<double> st;
   st.x.assign(x, x + 3 * md.n); st.v.assign(v, v + 3 * md.n);
@@ -966,7 +972,17 @@ void orc_run(const orc_system* s, double* x, double* v, double* q, double* w, do
       st.hist.assign(hist, hist + HB);
       st.hist_valid = true;
     }
-    const bool hm = md.contact_on && md.contact_model == 1;
+    bool hm = md.contact_on && md.contact_model == 1;
+    if (hm && hc_cnt && hc_in) {  // the contacts as the previous piece left them
+      st.chist.assign(md.n, {});
+      for (int i = 0; i < md.n; ++i)
+        for (int k = 0; k < hc_cnt[i]; ++k) {
+          const int64_t e = (int64_t)i * hc_cap + k;
+          st.chist[i].push_back(CEntry{hc_j[e], V3<double>{hc_s[3 * e], hc_s[3 * e + 1], hc_s[3 * e + 2]}});
+        }
+      st.chist_valid = true;
+      hm = false;
+    }
     if ((md.bond_damp && !have) || hm)
       record_measures(md, st, mbody, field, step0, md.bond_damp && !have, hm);
   } else {
@@ -974,9 +990,21 @@ void orc_run(const orc_system* s, double* x, double* v, double* q, double* w, do
   }
   for (int64_t k = 0; k < nsteps; ++k) step(md, st, mbody, field);
   if (md.bond_damp && hist && st.hist.size() == HB) std::copy(st.hist.begin(), st.hist.end(), hist);
+  if (hc_cnt && st.chist_valid && (int)st.chist.size() == md.n) {
+    for (int i = 0; i < md.n; ++i) {
+      if ((int)st.chist[i].size() > hc_cap) return -1;
+      hc_cnt[i] = (int32_t)st.chist[i].size();
+      for (int k = 0; k < hc_cnt[i]; ++k) {
+        const int64_t e = (int64_t)i * hc_cap + k;
+        hc_j[e] = st.chist[i][k].j;
+        hc_s[3 * e] = st.chist[i][k].s.x; hc_s[3 * e + 1] = st.chist[i][k].s.y; hc_s[3 * e + 2] = st.chist[i][k].s.z;
+      }
+    }
+  }
   std::copy(st.x.begin(), st.x.end(), x); std::copy(st.v.begin(), st.v.end(), v);
   std::copy(st.q.begin(), st.q.end(), q); std::copy(st.w.begin(), st.w.end(), w);
   std::copy(st.F.begin(), st.F.end(), F); std::copy(st.Tq.begin(), st.Tq.end(), Tq);
+  return 0;
 }
 
 // Forward-mode directional derivative of a whole run. Inputs are the raw

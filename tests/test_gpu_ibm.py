@@ -16,14 +16,14 @@ from test_gpu_parity import TRAJ_TOL, rel_inf
 pytestmark = pytest.mark.gpu
 
 
-def rods(lens, origins, nsub, seed, field=(0, 0, 0.2), direction=(1, 0, 0)):
+def rods(lens, origins, nsub, seed, field=(0, 0, 0.2), direction=(1, 0, 0), **kw):
     """Free magnetised rods (lattice units), rod dt = 1 / nsub, no damping."""
     rng = np.random.default_rng(seed)
     x, off, mem = workloads.straight_rods(lens, origins, direction)
     n, R = x.shape[0], len(lens)
     w = workloads._base(x, off, mem, np.tile([1.0, 1, 1, 0.5], (R, 1)), np.tile([0, 0, 0.05], (n, 1)),
                         np.zeros(n, np.int8), workloads._field_const(1, field), damping=0.0,
-                        dt=1.0 / nsub, precision="fp64")
+                        dt=1.0 / nsub, precision="fp64", **kw)
     w["v0"] = 0.01 * rng.normal(size=(n, 3))
     w["x0"] = x + rng.normal(0, 0.02, x.shape)
     return w
@@ -34,8 +34,8 @@ def fluid(shape, seed, amp=0.005):
     return lbm.equilibrium(1 + 0.01 * rng.random(shape), amp * rng.normal(size=(3,) + shape))
 
 
-def run_gpu(w, f0, ncycles, nsub, tau, g=(0.0, 0.0, 0.0), mode="batched"):
-    sim = RodSim(w, precision="fp64")
+def run_gpu(w, f0, ncycles, nsub, tau, g=(0.0, 0.0, 0.0), mode="batched", prec="fp64"):
+    sim = RodSim(w, precision=prec)
     sim.launch_mode(mode)
     lat = Lattice(f0, tau=tau, force=g)
     sim.lbm_cycles(lat, nsub, ncycles)
@@ -46,15 +46,15 @@ def run_gpu(w, f0, ncycles, nsub, tau, g=(0.0, 0.0, 0.0), mode="batched"):
     return st, f
 
 
-def compare(st, f, w, f0, ncycles, nsub, tau, g=(0.0, 0.0, 0.0)):
+def compare(st, f, w, f0, ncycles, nsub, tau, g=(0.0, 0.0, 0.0), prec="fp64", ftol=1e-13):
     ost, of = lbm.coupled(w, f0, ncycles, nsub, tau, g=g)
     assert st["step"] == ncycles * nsub
     motion = np.max(np.abs(ost["x"] - w["x0"]))
-    assert np.max(np.abs(st["x"] - ost["x"])) / motion <= TRAJ_TOL["fp64"]
+    assert np.max(np.abs(st["x"] - ost["x"])) / motion <= TRAJ_TOL[prec]
     for k in ("v", "w", "F", "T"):
-        assert rel_inf(st[k], ost[k]) <= TRAJ_TOL["fp64"], (k, rel_inf(st[k], ost[k]))
+        assert rel_inf(st[k], ost[k]) <= TRAJ_TOL[prec], (k, rel_inf(st[k], ost[k]))
     # populations ~ w_i rho: absolute agreement to rounding of the spread sums
-    assert np.max(np.abs(f - of)) <= 1e-13, np.max(np.abs(f - of))
+    assert np.max(np.abs(f - of)) <= ftol, np.max(np.abs(f - of))
     assert np.max(np.abs(of - lbm.run(f0, ncycles, tau, g=g))) > 1e-9  # the rods moved the fluid
 
 
@@ -65,6 +65,30 @@ def test_two_rods_match_oracle(mode):
     f0 = fluid((12, 12, 14), 2)
     st, f = run_gpu(w, f0, 3, nsub, tau, mode=mode)
     compare(st, f, w, f0, 3, nsub, tau)
+
+
+def test_mixed_precision_rods():
+    """The mixed path's FP32 pair arithmetic feeds the penalty force through
+    the velocities; the fluid sees it at that precision."""
+    nsub, tau = 4, 0.8
+    w = rods([8, 8, 8], [(3.2, 4.1, 4.3), (3.7, 6.4, 5.1), (2.5, 8.8, 7.9)], nsub, 12)
+    f0 = fluid((12, 12, 14), 13)
+    st, f = run_gpu(w, f0, 3, nsub, tau, prec="mixed")
+    compare(st, f, w, f0, 3, nsub, tau, prec="mixed", ftol=1e-8)
+
+
+def test_hertz_mindlin_contacts():
+    """Two rods overlapping by 0.05 with Hertz-Mindlin contact and friction:
+    the contact torques and the penalty force share the post kernel."""
+    nsub, tau = 8, 0.8
+    w = rods([7, 7], [(3.0, 4.0, 5.0), (3.0, 4.95, 5.0)], nsub, 14, contact_on=True,
+             contact_model="hertz_mindlin", contact_hm=np.array([20.0, 0.3, 0.5, 0.0, 0.0]))
+    f0 = fluid((12, 12, 14), 15)
+    ost = oracle.run(w, 0)
+    Fc, Tc = oracle.forces(w, ost["x"], ost["q"], ost["v"], ost["w"], mask=8)
+    assert np.abs(Fc).max() > 0  # the rods touch
+    st, f = run_gpu(w, f0, 2, nsub, tau)
+    compare(st, f, w, f0, 2, nsub, tau)
 
 
 def test_carpet_wraps_around_the_lattice():

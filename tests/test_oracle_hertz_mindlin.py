@@ -270,3 +270,30 @@ def test_turned_displacement_keeps_its_length():
         Ft = F - np.dot(F, n) * n
         np.testing.assert_allclose(Ft, -kt * sn, rtol=1e-12, atol=1e-18)
         np.testing.assert_allclose(T, np.cross(-0.45 * n, Ft), rtol=1e-12, atol=1e-18)
+
+
+def test_continued_runs_keep_the_tangential_springs():
+    """A run cut in pieces carries its contacts and their tangential
+    displacements in the state: the stick phase of the driven sphere keeps
+    growing as k_t L u dt across the cuts (a reset would drop it to g_t u), and
+    a frictional clump run in three pieces is the uncut run."""
+    E, nu, mu, gt = 10.0, 0.3, 0.5, 0.01
+    r, dt, P = 0.95, 0.01, 1000
+    w = spheres([[0, 0, 0], [r, 0, 0]], bc=[2, 1], hm=(E, nu, mu, 0.0, gt), dt=dt,
+                drive_axis=np.array([0.0, 0.0, 1.0]), drive_period=P)
+    st = oracle.run(w, 2)
+    for _ in range(2):
+        st = oracle.run(w, 1, state=st)
+    np.testing.assert_array_equal(st["F"], oracle.run(w, 4)["F"])
+    rng = np.random.default_rng(10)
+    n = 30
+    w = spheres(rng.uniform(0, 2.9, size=(n, 3)), hm=(20.0, 0.3, 0.3, 0.5, 0.5), dt=0.005)
+    w["v0"] = rng.normal(0, 0.5, (n, 3))
+    w["w0"] = rng.normal(0, 2.0, (n, 3))
+    whole = oracle.run(w, 90)
+    st = oracle.run(w, 30)
+    assert st["hc_cnt"].sum() > 10
+    st = oracle.run(w, 30, state=st)
+    st = oracle.run(w, 30, state=st)
+    for k in ("x", "v", "q", "w", "F", "T"):
+        np.testing.assert_array_equal(st[k], whole[k])
