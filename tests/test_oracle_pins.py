@@ -534,6 +534,91 @@ def test_radial_bond_period():
     np.testing.assert_allclose(s_full, 1e-3, rtol=2e-3)
 
 
+# ----------------------------------------------------------------- global damping, inertia
+# SI "Equations of motion": a solid sphere of diameter d and density rho has
+# m = rho pi d^3 / 6 and I = 2/5 m (d/2)^2. Methods "Damping" leaves the form of
+# the global damping open; the reading taken is -c m v and -c I w evaluated with
+# the half-step velocities when forces are computed (the first evaluation with
+# v0, w0). The two constants are written out here, not taken from the oracle.
+def _sphere(d, rho):
+    m = rho * np.pi * d ** 3 / 6.0
+    return m, 0.4 * m * (0.5 * d) ** 2
+
+
+def _free_sphere(d, rho, **kw):
+    w = workloads._base(np.zeros((1, 3)), np.array([0, 1], np.int32), np.array([0], np.int32),
+                        [d, rho, 1.0, 0.5], np.zeros((1, 3)), np.zeros(1, np.int8),
+                        workloads._field_const(1, (0, 0, 0)), dipole_on=False)
+    w.update(kw)
+    return w
+
+
+@pytest.mark.parametrize("nst", [1, 2, 7, 60])
+def test_global_damping_decay_closed_form(nst):
+    """A force-free sphere under global damping c: the half-step velocity of
+    velocity Verlet shrinks by exactly (1 - c dt) per step after a first
+    factor (1 - c dt / 2), since each force evaluation sees the half-step
+    velocity (-c m v and -c I w: the rate is c whatever the mass and inertia).
+    So v_n = v0 (1 - c dt/2)^2 (1 - c dt)^(n-1), x_n = x0 + dt v0 (1 - c dt/2)
+    sum_k (1 - c dt)^k, and the state's force and torque are -c m v_half and
+    -c I w_half with m and I of the sphere."""
+    d, rho, c, dt = 1.3, 2.1, 0.7, 0.01
+    m, I = _sphere(d, rho)
+    v0 = np.array([0.3, -0.2, 0.5])
+    w0 = np.array([0.4, 0.1, -0.9])
+    w = _free_sphere(d, rho, damping=c, dt=dt)
+    w["v0"] = v0[None, :].copy()
+    w["w0"] = w0[None, :].copy()
+    st = oracle.run(w, nst)
+    a, b = 1.0 - 0.5 * c * dt, 1.0 - c * dt
+    half = a * b ** (nst - 1)  # v_half of the last step over v0
+    np.testing.assert_allclose(st["v"][0], v0 * half * a, rtol=1e-13)
+    np.testing.assert_allclose(st["w"][0], w0 * half * a, rtol=1e-13)
+    disp = dt * a * sum(b ** k for k in range(nst))
+    np.testing.assert_allclose(st["x"][0], v0 * disp, rtol=1e-13)
+    np.testing.assert_allclose(st["F"][0], -c * m * v0 * half, rtol=1e-13)
+    np.testing.assert_allclose(st["T"][0], -c * I * w0 * half, rtol=1e-13)
+
+
+def test_sphere_mass_and_inertia_under_constant_load():
+    """A constant external force and torque on a free sphere, no damping:
+    velocity Verlet gives v_n = n dt F / m and w_n = n dt T / I exactly, with
+    the solid-sphere m and I."""
+    d, rho, dt, nst = 0.8, 3.0, 0.02, 25
+    m, I = _sphere(d, rho)
+    Fe, Te = np.array([0.2, -0.5, 0.1]), np.array([-0.03, 0.07, 0.02])
+    w = _free_sphere(d, rho, damping=0.0, dt=dt)
+    w["ext_force"] = Fe[None, :].copy()
+    w["ext_torque"] = Te[None, :].copy()
+    st = oracle.run(w, nst)
+    np.testing.assert_allclose(st["v"][0], nst * dt * Fe / m, rtol=1e-12)
+    np.testing.assert_allclose(st["w"][0], nst * dt * Te / I, rtol=1e-12)
+    np.testing.assert_allclose(st["x"][0], 0.5 * (nst * dt) ** 2 * Fe / m, rtol=1e-12)
+
+
+def test_twist_bond_period():
+    """Two free spheres twisted symmetrically about their bond and released
+    without damping: each carries -+K_t psi (P3), so the relative twist obeys
+    psi'' = -2 K_t psi / I and oscillates with omega = sqrt(2 K_t / I),
+    K_t = G J / L, G = E / (2 (1 + nu)), J = pi d^4 / 32 (eq:bpm-tt and the
+    spring constants), I of the solid sphere."""
+    d, rho, E, nu = 1.0, 1.0, 1.0, 0.5
+    w = single_rod(2, d=d, rho=rho, E=E, nu=nu, damping=0.0, dt=0.005)
+    w["bc"] = np.zeros(2, np.int8)
+    psi0 = 1e-3
+    w["x0"] = w["x_ref"].copy()
+    w["q0"] = np.stack([qaxis([1, 0, 0], -psi0 / 2), qaxis([1, 0, 0], psi0 / 2)])
+    Kt = E / (2 * (1 + nu)) * np.pi * d ** 4 / 32 / 1.0
+    _, I = _sphere(d, rho)
+    nper = 2 * np.pi / np.sqrt(2 * Kt / I) / w["dt"]
+
+    def twist(st):
+        r = qmul(np.array([1.0, -1, -1, -1]) * st["q"][0], st["q"][1])
+        return 2 * np.arctan2(r[1], r[0])
+    np.testing.assert_allclose(twist(oracle.run(w, int(round(nper / 2)))), -psi0, rtol=2e-3)
+    np.testing.assert_allclose(twist(oracle.run(w, int(round(nper)))), psi0, rtol=2e-3)
+
+
 def _total_energy(w, st):
     return oracle.energy(w, st["x"], st["q"], st["v"], st["w"], step=st["step"]).sum()
 
