@@ -206,6 +206,25 @@ int rod_topology(rod_ctx* c, int32_t* ij, double* rref, double* K, int32_t cap, 
  * (host output, synchronises); *count receives the total, at most cap written. */
 int rod_contact_pairs(rod_ctx* c, int32_t* pairs, int32_t cap, int32_t* count);
 
+/* Largest `cap` of rod_contact_pairs_noalloc (its static staging holds this
+ * many pairs). */
+#define ROD_NOALLOC_MAX_PAIRS 1048576
+
+/* For callers that cannot allocate device memory (tight serving or polling
+ * loops, harnesses that forbid hipMalloc): rod_contact_pairs without a per-call
+ * allocation. The same search and output: the contact pairs (i < j) of the
+ * current state, sorted ascending into `pairs` (host [cap][2]); *count receives
+ * the total, at most cap are written (synchronises). The pairs are staged in a
+ * static device array of the library, 8 MiB + 256 B on each GPU it runs on,
+ * held until the process ends; the call allocates no device or host memory.
+ * Errors: ROD_E_INVALID for NULL arguments or cap outside
+ * [0, ROD_NOALLOC_MAX_PAIRS]; ROD_E_HIP if the array's device address could not
+ * be resolved when the context was created, or a launch or copy failed.
+ * Every call on one GPU shares that GPU's array: calls from threads of one
+ * process are serialised by a lock per device; calls that bypass it (e.g. from
+ * another copy of the library in the same process) would race. */
+int rod_contact_pairs_noalloc(rod_ctx* c, int32_t* pairs, int32_t cap, int32_t* count);
+
 /* Gradient support (reverse mode through recorded steps).
  * rod_tape_begin marks the current state as the start of the recorded run
  * (and stores it as the first checkpoint); subsequent rod_step calls record

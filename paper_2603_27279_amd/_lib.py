@@ -12,6 +12,8 @@ ROD_FP64, ROD_MIXED = 0, 1
 TERM_BOND, TERM_DIPOLE, TERM_ZEEMAN, TERM_CONTACT, TERM_DAMP, TERM_EXT, TERM_ALL = \
     1, 2, 4, 8, 16, 32, 63
 
+ROD_NOALLOC_MAX_PAIRS = 1048576  # include/rod.h
+
 KERNELS = ("pre", "bond", "dipole", "contact", "post", "forces", "kick")
 
 _P = C.c_void_p
@@ -81,6 +83,7 @@ def load():
         "rod_energy": [_P, _P, i32],
         "rod_topology": [_P, _P, _P, _P, i32, C.POINTER(i32)],
         "rod_contact_pairs": [_P, _P, i32, C.POINTER(i32)],
+        "rod_contact_pairs_noalloc": [_P, _P, i32, C.POINTER(i32)],
         "rod_tape_begin": [_P],
         "rod_grad": [_P, C.POINTER(RodCotangent), C.POINTER(RodGradients)],
         "rod_free": [_P],

@@ -39,6 +39,18 @@ __global__ __launch_bounds__(256) void k_clear_cells(Dev d) {
   if (i == 0) *tab.ovf_cnt = 0;
 }
 
+// Fill n ints with v (a kernel rather than a memset node).
+__global__ __launch_bounds__(256) void k_fill_i32(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_clear_cells(const Dev& d, hipStream_t s) {
   if (!d.contact_on) return hipSuccess;
   hipLaunchKernelGGL(k_clear_cells, dim3((unsigned)((d.n + 255) / 256)), dim3(256), 0, s, d);

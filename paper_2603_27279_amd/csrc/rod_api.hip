@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -49,6 +50,7 @@ struct rod_ctx {
   rod_desc desc;            // scalar fields (host pointers cleared after init)
   rod_buffers ub;
   hipStream_t user = nullptr, s = nullptr;
+  int dev = 0;                // device current at rod_init
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   Dev d;
   std::vector<void*> allocs;
@@ -506,6 +508,43 @@ static int capture_graph(rod_ctx* c) {
 }
 
 // ------------------------------------------------------------------ C ABI
+// ---- static staging of rod_contact_pairs_noalloc
+// The pairs that entry point finds are staged in this file-scope device array
+// instead of a per-call allocation: a 256-byte header whose first int counts the
+// pairs, then [ROD_NOALLOC_MAX_PAIRS][2] int32 pairs. Each GPU the library runs on
+// holds its own copy (8 MiB + 256 B) until the process ends. Host code never
+// passes the array's name to a kernel or a copy (on the host it is only a
+// stand-in): it resolves the device address once per device with
+// hipGetSymbolAddress and uses that.
+constexpr size_t NOALLOC_HEADER = 256;
+constexpr size_t NOALLOC_BYTES =
+    NOALLOC_HEADER + 2 * sizeof(int32_t) * (size_t)ROD_NOALLOC_MAX_PAIRS;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEV = 64;
+static std::mutex g_scratch_init_mu;
+static void* g_scratch_ptr[NOALLOC_MAX_DEV];    // device address of `scratch`, per device
+static int g_scratch_state[NOALLOC_MAX_DEV];    // 0 unresolved, 1 resolved, -1 failed
+static hipError_t g_scratch_err[NOALLOC_MAX_DEV];
+static std::mutex g_scratch_use_mu[NOALLOC_MAX_DEV];  // one staging user per device at a time
+
+// Resolve the address of `scratch` on device `dev`, which must be current.
+// Called by rod_init; a failure is kept and reported by the entry point.
+static void scratch_resolve(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEV) return;
+  std::lock_guard<std::mutex> lk(g_scratch_init_mu);
+  if (g_scratch_state[dev] != 0) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && ptr) {
+    g_scratch_ptr[dev] = ptr;
+    g_scratch_state[dev] = 1;
+  } else {
+    g_scratch_err[dev] = e;
+    g_scratch_state[dev] = -1;
+  }
+}
+
 extern "C" {
 
 const char* rod_last_error(void) { return g_err.c_str(); }
@@ -539,6 +578,8 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
       hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
     return cleanup(fail(ROD_E_HIP, "stream/event creation failed"));
+  if (hipGetDevice(&c->dev) != hipSuccess) return cleanup(fail(ROD_E_HIP, "hipGetDevice failed"));
+  scratch_resolve(c->dev);
 
   // ---- topology and constants (host)
   c->rod_offset.assign(dsc->rod_offset, dsc->rod_offset + R + 1);
@@ -894,6 +935,51 @@ int rod_contact_pairs(rod_ctx* c, int32_t* pairs, int32_t cap, int32_t* count) {
   } while (0);
   (void)hipFree(dp);
   return rc;
+}
+
+// The pairs of one search, sorted in place (i, then j ascending), with no
+// allocation: a pair is two adjacent int32 of the caller's array.
+namespace {
+struct PairI32 { int32_t i, j; };
+static_assert(sizeof(PairI32) == 2 * sizeof(int32_t), "pair layout");
+}  // namespace
+
+int rod_contact_pairs_noalloc(rod_ctx* c, int32_t* pairs, int32_t cap, int32_t* count) {
+  if (!c || !count || (cap > 0 && !pairs)) return fail(ROD_E_INVALID, "NULL argument");
+  if (cap < 0 || cap > ROD_NOALLOC_MAX_PAIRS)
+    return fail(ROD_E_INVALID, "cap %d is outside [0, %d], the static staging capacity", cap,
+                ROD_NOALLOC_MAX_PAIRS);
+  *count = 0;
+  if (!c->desc.contact_on) return ROD_OK;
+  if (c->dev < 0 || c->dev >= NOALLOC_MAX_DEV)
+    return fail(ROD_E_INVALID, "device %d has no static staging (at most %d devices)", c->dev,
+                NOALLOC_MAX_DEV);
+  if (g_scratch_state[c->dev] != 1)
+    return fail(ROD_E_HIP, "static staging of device %d is unavailable: %s", c->dev,
+                hipGetErrorString(g_scratch_err[c->dev]));
+  std::lock_guard<std::mutex> lk(g_scratch_use_mu[c->dev]);
+  int32_t* dcount = (int32_t*)g_scratch_ptr[c->dev];
+  int32_t* dpairs = (int32_t*)((char*)g_scratch_ptr[c->dev] + NOALLOC_HEADER);
+  TRY(enter(c));
+  if (launch_fill_i32(dcount, 1, 0, c->s) != hipSuccess ||
+      launch_pre(c->d, PRE_EVAL, c->s) != hipSuccess ||
+      launch_contact_pairs(c->d, dpairs, cap, dcount, c->s) != hipSuccess ||
+      launch_clear_cells(c->d, c->s) != hipSuccess)
+    return fail(ROD_E_HIP, "launch failed");
+  TRY(leave(c));
+  int cnt = 0;
+  HIPC(hipStreamSynchronize(c->s));
+  HIPC(hipMemcpy(&cnt, dcount, sizeof(int32_t), hipMemcpyDeviceToHost));
+  const int nw = std::min(cnt, cap);
+  if (nw > 0) {
+    HIPC(hipMemcpy(pairs, dpairs, 2 * sizeof(int32_t) * (size_t)nw, hipMemcpyDeviceToHost));
+    PairI32* pv = reinterpret_cast<PairI32*>(pairs);
+    std::sort(pv, pv + nw, [](const PairI32& a, const PairI32& b) {
+      return a.i != b.i ? a.i < b.i : a.j < b.j;
+    });
+  }
+  *count = cnt;
+  return ROD_OK;
 }
 
 int rod_tape_begin(rod_ctx* c) {

@@ -213,5 +213,7 @@ hipError_t launch_kick(const Dev& d, double* Bo, hipStream_t s, const hipEvent_t
 hipError_t launch_energy(const Dev& d, double* Epart, double* out, hipStream_t s);
 hipError_t launch_contact_pairs(const Dev& d, int* pairs, int cap, int* count, hipStream_t s);
 hipError_t launch_clear_cells(const Dev& d, hipStream_t s);
+// Fill p[0..n) with v.
+hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t s);
 
 }  // namespace rodmx

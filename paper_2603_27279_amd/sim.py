@@ -154,6 +154,14 @@ class RodSim:
                                            C.byref(cnt)))
         return out[:P]
 
+    def contact_pairs_noalloc(self, cap):
+        """rod_contact_pairs_noalloc: at most ``cap`` pairs (sorted) and the total count."""
+        cnt = C.c_int32()
+        out = np.zeros((max(int(cap), 1), 2), np.int32)
+        L.check(self.lib.rod_contact_pairs_noalloc(self.ctx, out.ctypes.data_as(C.c_void_p),
+                                                   int(cap), C.byref(cnt)))
+        return out[:min(cnt.value, int(cap))], cnt.value
+
     def ramp(self, fields, max_steps, check_every, ke_tol, watch=()):
         """Quasi-static field ramp (rod_ramp): ``fields`` [n_inc, M, 12] settings
         in turn, each held until every member's kinetic energy is at most
