@@ -1,11 +1,14 @@
 #!/usr/bin/env python3
 """Benchmark of the rod force-and-integrate loop on one MI355X.
 
-Default workload: the twisted clamped-clamped rod, N = 4096 particles, driven
-end, Hookean contact through the cell list, all-pairs dipoles, mixed path
-(FP32 pair/bond arithmetic, FP64 state and sums), steps replayed from captured
-HIP graphs. A step is one full pass of the loop (integrate, bonds, dipoles,
-contact, gather and kick) over all particles.
+Default workload: the rod array, 512 clamped rods of 512 particles
+(262,144 particles) under a swept field, all-pairs dipoles, Hookean contact
+through candidate lists, mixed path (FP32 pair/bond arithmetic, FP64 state and
+sums), steps replayed from captured HIP graphs whose length divides the timed
+steps. A step is one full pass of the loop (integrate, bonds, dipoles, contact,
+gather and kick) over all particles. Keyed legs run the same array on the
+FP64 path, the twisted rod, the cilia carpet (beside the plain per-rod loop)
+and the ensemble.
 
 Prints one JSON line: throughput in particle-steps/s (inputs resident in HBM),
 dipole pair-evaluations/s, the roofline of the dominant (dipole) kernel timed
@@ -112,12 +115,33 @@ def _lattice_neighbours(w, rad):
     return float(np.count_nonzero((d2 < rad * rad) & (d2 > 0)))
 
 
-def cpu_baseline(w, target_s=15.0):
-    """The FP64 oracle on a bounded number of steps of the same workload."""
-    import ctypes
+ROW_SAMPLE_PAIRS = 2e9  # above this many dipole pairs per step the oracle is sampled by rows
+
+
+def _oracle_rate(w, target_s):
+    """Oracle throughput in particle-steps/s on the threads currently set. A
+    workload whose step exceeds the budget is sampled by rows: the dipole and
+    contact sums of evenly spaced particles (each over its whole member), the
+    work that makes up all but a fraction of a step of such a size; otherwise
+    whole steps from the initial state."""
     import oracle
-    lib = oracle._load()
     n = w["n"]
+    pairs = ordered_pairs(w) if w["dipole_on"] else 0
+    if pairs > ROW_SAMPLE_PAIRS:
+        st = oracle.run(w, 0) if n <= 100_000 else {"x": w["x0"], "q": w["q0"]}
+        rows = np.linspace(0, n - 1, num=min(n, 64)).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.rows(w, st["x"], st["q"], rows)
+        per_row = (time.perf_counter() - t0) / len(rows)
+        k = int(max(16, min(n, target_s / max(per_row, 1e-9))))
+        rows = np.linspace(0, n - 1, num=k).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.rows(w, st["x"], st["q"], rows)
+        dt = time.perf_counter() - t0
+        return k / dt, (f"dipole and contact sums of {k} of the {n} particles (evenly spaced, "
+                        f"each over its member of {n} particles) at the initial state, FP64, "
+                        f"{dt:.2f} s; the bond and integration work of a step (under 0.1% of "
+                        f"it at this size) is not timed")
     t0 = time.perf_counter()
     st = oracle.run(w, 0)                   # prepare (includes one force evaluation)
     t_prep = time.perf_counter() - t0
@@ -125,11 +149,28 @@ def cpu_baseline(w, target_s=15.0):
     t0 = time.perf_counter()
     oracle.run(w, k, state=st)
     dt = time.perf_counter() - t0
+    return n * k / dt, (f"{k} steps of the same workload (N={n}) from its initial state, "
+                        f"FP64, {dt:.2f} s")
+
+
+def cpu_baseline(w, target_s=15.0):
+    """The FP64 oracle on a bounded sample of the same workload: on every thread
+    its OpenMP runtime takes, then on one thread (a smaller sample)."""
+    import ctypes
+    import oracle
+    lib = oracle._load()
     lib.orc_threads.restype = ctypes.c_int
     cores = int(lib.orc_threads())
-    return {"value": n * k / dt, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{k} steps of the same workload (N={n}) from its initial state, FP64, "
-                      f"{dt:.2f} s"}
+    value, sample = _oracle_rate(w, target_s)
+    lib.orc_set_threads(1)
+    try:
+        v1, s1 = _oracle_rate(w, max(2.0, target_s / 3))
+    finally:
+        lib.orc_set_threads(cores)
+    model, ncpu = cpu_model()
+    return {"value": float(value), "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "sample": sample, "one_core": {"value": float(v1), "sample": s1},
+            "cpu_model": model, "logical_cpus": ncpu}
 
 
 def adjoint_leg():
@@ -450,27 +491,192 @@ def copy_calibration():
           flush=True)
 
 
+def cpu_model():
+    """Model name of the host CPU (first entry of /proc/cpuinfo) and the number of
+    logical CPUs the OS reports."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
+def measured_peaks():
+    """Arithmetic ceilings measured on this GPU by rod_probe_fma (independent FMA
+    chains in vector registers, unpacked FP32 as the library's own code; FP64)."""
+    import ctypes
+    import torch
+    from paper_2603_27279_amd import _lib as L
+    lib = L.load()
+    out = {}
+    for key, prec, dt in (("fp32_fma_tflops", L.ROD_MIXED, torch.float32),
+                          ("fp64_fma_tflops", L.ROD_FP64, torch.float64)):
+        sink = torch.zeros(1, dtype=dt, device="cuda")
+        tf = ctypes.c_double()
+        L.check(lib.rod_probe_fma(prec, ctypes.c_void_p(sink.data_ptr()),
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                  ctypes.byref(tf)))
+        out[key] = tf.value
+    return out
+
+
+def graph_plan(graph_steps, steps):
+    """Graph length for a timed call of `steps` steps: at most `steps`, so that
+    the call replays whole graphs (rod_step replays only calls of at least the
+    graph length). Returns (graph length, steps replayed, steps run eagerly)."""
+    gs = max(0, min(int(graph_steps), int(steps)))
+    replayed = (steps // gs) * gs if gs > 0 else 0
+    return gs, replayed, steps - replayed
+
+
+def workload_leg(name, prec, steps, warmup, graph_steps, timing_steps, per_rod_steps,
+                 tune_cache=None, autotune=True, dipole_cutoff=0.0, separate=True, peaks=None):
+    """One workload: whole steps replayed from captured HIP graphs and timed by
+    wall clock between stream synchronisations; then the launches of the same
+    number of steps timed one by one with HIP events on the library's stream
+    (eager), for the dominant kernel's roofline; optionally the plain per-rod
+    loop over a few steps."""
+    import torch
+    import workloads
+    from paper_2603_27279_amd import RodSim
+    w = workloads.make(name)
+    if dipole_cutoff > 0:
+        w["dipole_cutoff"] = dipole_cutoff
+    n = w["n"]
+    pairs = ordered_pairs(w) if w["dipole_on"] and not dipole_cutoff else 0
+    gs, replayed, _ = graph_plan(graph_steps, steps)
+    sim = RodSim(w, precision=prec, graph_steps=gs)
+    tune = None
+    if autotune:
+        tune = sim.autotune(tune_cache).strip().splitlines()[-1]
+    # the warm-up holds at least one whole graph, so that its capture is never
+    # part of the timed steps
+    warm = max(warmup, gs)
+    sim.step(warm)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    ms_step = 1e3 * secs / steps
+
+    # Kernel durations: every launch stamps a pair of HIP events with its own
+    # start and end, on the library's stream (eager launches of the same step).
+    t_steps = max(1, min(timing_steps, steps))
+    sim.timing(True)
+    sim.step(t_steps)
+    kt = sim.kernel_times()
+    sim.timing(False)
+    kt_sep = None
+    if separate:
+        sim.launch_mode("separate")
+        sim.timing(True)
+        sim.step(min(t_steps, 5))
+        kt_sep = sim.kernel_times()
+        sim.timing(False)
+        sim.launch_mode("batched")
+    sim.sync()
+    roof = None
+    if pairs:
+        # dominant kernel of the step: the fused force kernel (it holds the
+        # dipole work of either layout), else the separate dipole kernel
+        cls = "forces" if kt["forces"][1] else "dipole"
+        t_k = 1e-3 * kt[cls][0] / kt[cls][1]
+        real = "float" if prec == "mixed" else "double"
+        small = "small-member" in (tune or "")
+        if cls == "forces":
+            kname = f"k_forces<{real}, {'true' if n < 65536 else 'false'}>"
+        else:
+            kname = f"k_dipole_small<{real}>" if small else f"k_dipole<{real}>"
+        peak = FP32_PEAK_TFLOPS if prec == "mixed" else FP64_PEAK_TFLOPS
+        achieved = FLOP_PER_PAIR * pairs / t_k / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": measured_traffic(kname, name, prec, layout_key(tune)),
+                "traffic_unit": "bytes per launch", "kernel": kname,
+                "kernel_us": 1e6 * t_k, "launches_timed": int(kt[cls][1]),
+                "flops_counted": "dipole pair arithmetic only (bond and contact work in the "
+                                 "same launch is not counted)" if cls == "forces" else "dipole pairs",
+                "pair_evals_per_s": pairs / t_k,
+                "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": pairs}
+        if peaks:
+            mp = peaks["fp32_fma_tflops" if prec == "mixed" else "fp64_fma_tflops"]
+            roof["measured_peak"] = mp
+            roof["frac_measured_peak"] = achieved / mp
+    batching = None
+    n_rods = len(w["rod_offset"]) - 1
+    if n_rods > 1 and per_rod_steps > 0:
+        # the same step as a plain per-rod loop (every kernel once per rod, eager)
+        k = max(1, min(steps, per_rod_steps))
+        sim.launch_mode("per_rod")
+        sim.step(1)
+        sim.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(k)
+        sim.sync()
+        torch.cuda.synchronize()
+        ms_rod = 1e3 * (time.perf_counter() - t0) / k
+        sim.launch_mode("batched")
+        batching = {"n_rods": n_rods, "per_rod_ms_per_step": ms_rod, "per_rod_steps": k,
+                    "batched_ms_per_step": ms_step, "speedup": ms_rod / ms_step}
+    sim.free()
+    return {
+        "w": w, "value": n * steps / secs, "ms_per_step": ms_step, "steps": steps,
+        "warmup_steps_run": warm, "graph_steps": gs, "graph_replayed_steps": replayed,
+        "eager_steps": steps - replayed, "pairs": pairs, "tune": tune,
+        "pair_evals_per_s": pairs * steps / secs if pairs else None,
+        "kernel_us": {k: 1e3 * ms / c for k, (ms, c) in kt.items() if c},
+        "kernel_us_separate_terms": (None if kt_sep is None else
+                                     {k: 1e3 * ms / c for k, (ms, c) in kt_sep.items() if c}),
+        "roofline": roof, "batching": batching,
+    }
+
+
+def leg_summary(name, prec, r):
+    """The keyed form of a workload leg in the bench line."""
+    return {"workload": WORKLOADS[name], "precision": prec, "n_particles": r["w"]["n"],
+            "particle_steps_per_s": r["value"], "ms_per_step": r["ms_per_step"],
+            "steps": r["steps"], "graph_steps": r["graph_steps"],
+            "graph_replayed_steps": r["graph_replayed_steps"],
+            "pair_evals_per_s": r["pair_evals_per_s"], "dipole_layout": r["tune"],
+            "kernel_us": r["kernel_us"], "roofline": r["roofline"], "batching": r["batching"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="twisted_rod", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="rod_array", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
-    ap.add_argument("--graph-steps", type=int, default=200)
-    ap.add_argument("--timing-steps", type=int, default=200)
+    ap.add_argument("--graph-steps", type=int, default=200,
+                    help="steps per captured graph (at most --steps, so that the timed "
+                         "steps replay whole graphs)")
+    ap.add_argument("--timing-steps", type=int, default=200,
+                    help="eager steps timed launch by launch (at most --steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-per-rod", action="store_true",
                     help="skip the per-rod loop comparison (multi-rod workloads)")
-    ap.add_argument("--per-rod-steps", type=int, default=50)
+    ap.add_argument("--per-rod-steps", type=int, default=3)
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the other workloads (FP64 rod array, twisted rod, cilia "
+                         "carpet, ensemble)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON-lines cache of autotuner choices (default: tune every run)")
     ap.add_argument("--no-microbench", action="store_true",
                     help="skip the bond/contact/integration kernels at millions of particles")
-    ap.add_argument("--microbench-sizes", default="64",
+    ap.add_argument("--microbench-sizes", default="64,128",
                     help="comma-separated grid sides of the dipole-free rod array (x 1024 "
                          "particles per rod): 64 -> 4.2M particles, 128 -> 16.8M")
     ap.add_argument("--no-lbm", action="store_true",
@@ -502,100 +708,48 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1:
+        print("--steps must be at least 1", file=sys.stderr)
+        sys.exit(2)
 
-    import torch
     import workloads
-    from paper_2603_27279_amd import RodSim
 
-    w = workloads.make(args.workload)
-    if args.dipole_cutoff > 0:
-        w["dipole_cutoff"] = args.dipole_cutoff
-    prec = args.precision or w["precision"]
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    peaks = measured_peaks()
+    progress(f"measured FMA ceilings {peaks}")
+    prec = args.precision or workloads.make(args.workload)["precision"]
+    head = workload_leg(args.workload, prec, args.steps, args.warmup, args.graph_steps,
+                        args.timing_steps, 0 if args.no_per_rod else args.per_rod_steps,
+                        args.tune_cache, not args.no_autotune, args.dipole_cutoff, peaks=peaks)
+    w = head["w"]
     n = w["n"]
-    pairs = ordered_pairs(w) if w["dipole_on"] and not args.dipole_cutoff else 0
+    progress(f"{args.workload} {prec}: {head['ms_per_step']:.3f} ms per step")
 
-    sim = RodSim(w, precision=prec, graph_steps=args.graph_steps)
-    tune = None
-    if not args.no_autotune:
-        report = sim.autotune(args.tune_cache)
-        tune = report.strip().splitlines()[-1]
-    # the warm-up holds at least one whole graph, so that its capture is never
-    # part of the timed steps
-    warmup = max(args.warmup, args.graph_steps)
-    sim.step(warmup)
-    sim.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    sim.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    secs = t1 - t0
-    ms_step = 1e3 * secs / args.steps
-    value = n * args.steps / secs
-
-    # Kernel durations: every launch stamps a pair of HIP events with its own
-    # start and end, on the library's stream. First the launches the timed steps
-    # make, then the same steps with the three force terms as separate kernels.
-    sim.timing(True)
-    sim.step(args.timing_steps)
-    kt = sim.kernel_times()
-    sim.timing(False)
-    sim.launch_mode("separate")
-    sim.timing(True)
-    sim.step(args.timing_steps)
-    kt_sep = sim.kernel_times()
-    sim.timing(False)
-    sim.launch_mode("batched")
-    sim.sync()
-    kernels_us = {k: (1e3 * ms / c if c else None) for k, (ms, c) in kt.items() if c}
-    kernels_sep_us = {k: (1e3 * ms / c if c else None) for k, (ms, c) in kt_sep.items() if c}
-    roof = None
-    small = "small-member" in (tune or "")
-    if pairs:
-        # dominant kernel of the timed step: the fused force kernel (it holds
-        # the dipole work of either layout), else the separate dipole kernel
-        cls = "forces" if kt["forces"][1] else "dipole"
-        t_k = 1e-3 * kt[cls][0] / kt[cls][1]
-        real = "float" if prec == "mixed" else "double"
-        if cls == "forces":
-            kname = f"k_forces<{real}, {'true' if n < 65536 else 'false'}>"
-        else:
-            kname = f"k_dipole_small<{real}>" if small else f"k_dipole<{real}>"
-        peak = FP32_PEAK_TFLOPS if prec == "mixed" else FP64_PEAK_TFLOPS
-        achieved = FLOP_PER_PAIR * pairs / t_k / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": measured_traffic(kname, args.workload, prec, layout_key(tune)),
-                "traffic_unit": "bytes per launch", "kernel": kname,
-                "flops_counted": "dipole pair arithmetic only (bond and contact work in the "
-                                 "same launch is not counted)" if cls == "forces" else "dipole pairs",
-                "pair_evals_per_s": pairs / t_k,
-                "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": pairs}
-    batching = None
-    n_rods = len(w["rod_offset"]) - 1
-    if n_rods > 1 and not args.no_per_rod:
-        # The same step as a plain per-rod loop (every kernel once per rod, eager).
-        k = max(1, min(args.steps, args.per_rod_steps))
-        sim.launch_mode("per_rod")
-        sim.step(2)
-        sim.sync()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sim.step(k)
-        sim.sync()
-        torch.cuda.synchronize()
-        ms_rod = 1e3 * (time.perf_counter() - t0) / k
-        sim.launch_mode("batched")
-        batching = {"n_rods": n_rods, "per_rod_ms_per_step": ms_rod,
-                    "per_rod_steps": k, "batched_ms_per_step": ms_step,
-                    "speedup": ms_rod / ms_step}
-    sim.free()
+    legs = None
+    if not args.no_legs and args.workload == "rod_array" and not args.dipole_cutoff:
+        legs = {}
+        # the rod array on the FP64 path (the paper's own arithmetic)
+        r = workload_leg("rod_array", "fp64", 5, 2, 5, 5, 0, args.tune_cache,
+                         not args.no_autotune, separate=False, peaks=peaks)
+        legs["rod_array_fp64"] = leg_summary("rod_array", "fp64", r)
+        progress(f"rod_array fp64: {r['ms_per_step']:.3f} ms per step")
+        for name, steps, gsteps, prs in (("twisted_rod", 2000, 200, 0),
+                                         ("cilia_carpet", 100, 50, args.per_rod_steps),
+                                         ("ensemble", 200, 100, 0)):
+            pr = workloads.make(name)["precision"]
+            r = workload_leg(name, pr, steps, gsteps, gsteps, min(steps, 50),
+                             0 if args.no_per_rod else prs, args.tune_cache,
+                             not args.no_autotune, separate=False, peaks=peaks)
+            legs[name] = leg_summary(name, pr, r)
+            progress(f"{name} {pr}: {r['ms_per_step']:.4f} ms per step")
 
     adj = None if args.no_adjoint else adjoint_leg()
     micro = None
     if not args.no_microbench:
         micro = hbm_microbench([int(v) for v in args.microbench_sizes.split(",") if v])
+        progress("memory-bound kernels done")
 
     lbm_res = None
     if not args.no_lbm:
@@ -606,34 +760,38 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
         cpu = cpu_baseline(w, args.cpu_seconds)
-        cpu["value"] = float(cpu["value"])
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "warmup_steps_run": warmup,
-        "ms_per_step": ms_step,
+        "warmup_steps_run": head["warmup_steps_run"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 pair/bond arithmetic, f64 state and sums" if prec == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "n_particles": n,
-                   "ordered_dipole_pairs_per_step": pairs, "precision": prec,
-                   "graph_steps": args.graph_steps, "dipole_layout": tune,
+                   "ordered_dipole_pairs_per_step": head["pairs"], "precision": prec,
+                   "graph_steps": head["graph_steps"],
+                   "graph_replayed_steps": head["graph_replayed_steps"],
+                   "eager_steps": head["eager_steps"], "dipole_layout": head["tune"],
                    "dipole_cutoff": args.dipole_cutoff or None},
-        "pair_evals_per_s": pairs * args.steps / secs if pairs else None,
-        "kernel_us": kernels_us,
-        "kernel_us_separate_terms": kernels_sep_us,
-        "roofline": roof,
+        "pair_evals_per_s": head["pair_evals_per_s"],
+        "kernel_us": head["kernel_us"],
+        "kernel_us_separate_terms": head["kernel_us_separate_terms"],
+        "roofline": head["roofline"],
+        "measured_peaks": peaks,
+        "batching": head["batching"],
+        "legs": legs,
         "lbm": lbm_res,
         "ibm": ibm_res,
-        "batching": batching,
         "adjoint": adj,
         "hbm_kernels": micro,
         "cpu_baseline": cpu,

@@ -336,6 +336,18 @@ int rod_ramp(rod_ctx* c, const double* fields, int32_t n_inc, int32_t max_steps,
              int32_t check_every, double ke_tol, const int32_t* watch, int32_t n_watch,
              double* x_watch, int32_t* steps, double* ke);
 
+/* Measured arithmetic ceiling of the current GPU, for roofline fractions
+ * reported beside the vendor peaks: a launch of 16 workgroups of 256 threads
+ * per compute unit, each thread running 16 independent fused multiply-add
+ * chains for 2048 iterations in vector registers (no memory traffic in the
+ * loop). precision ROD_MIXED times FP32 FMAs (unpacked, as the library's own
+ * arithmetic), ROD_FP64 FP64 FMAs. `sink` is a device buffer of one element of
+ * that type, written only for an impossible result (it keeps the chains live).
+ * Runs on hip_stream (NULL = default), synchronises, and writes the best of
+ * five timed launches to *tflops (2 flops per FMA). Errors: ROD_E_INVALID
+ * (NULL argument, unknown precision), ROD_E_HIP. Needs no context. */
+int rod_probe_fma(int32_t precision, void* sink, void* hip_stream, double* tflops);
+
 /* Release the context and its workspace (synchronises). NULL is accepted. */
 int rod_free(rod_ctx* c);
 

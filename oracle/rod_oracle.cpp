@@ -1139,6 +1139,16 @@ void orc_ramp(const orc_system* s, double* x, double* v, double* q, double* w, d
 }
 
 // Threads the OpenMP loops of this library use.
+// Threads of the parallel loops from now on (n >= 1), for timing the oracle on
+// a given number of host cores.
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int orc_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

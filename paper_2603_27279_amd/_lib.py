@@ -92,6 +92,7 @@ def load():
         "rod_autotune": [_P, C.c_char_p, i32, C.c_char_p, i32],
         "rod_dipole_layout": [_P, i32, i32],
         "rod_launch_mode": [_P, i32],
+        "rod_probe_fma": [i32, _P, _P, C.POINTER(C.c_double)],
         "rod_ramp": [_P, _P, i32, i32, i32, C.c_double, _P, i32, _P, _P, _P],
         "lbm_init": [C.POINTER(_P), C.POINTER(LbmDesc), _P, _P],
         "lbm_step": [_P, i64],

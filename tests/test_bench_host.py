@@ -50,3 +50,23 @@ def test_digest_covers_the_force_kernel_sources():
     for name in bench.FORCE_SOURCES:
         assert os.path.exists(os.path.join(csrc, name)), name
     assert "k_forces.hip" in bench.FORCE_SOURCES and "dipole_body.h" in bench.FORCE_SOURCES
+
+
+@pytest.mark.parametrize("gsteps,steps,plan", [
+    (200, 20, (20, 20, 0)), (200, 2000, (200, 2000, 0)), (100, 250, (100, 200, 50)),
+    (0, 20, (0, 0, 20)), (5, 5, (5, 5, 0))])
+def test_graph_plan_replays_whole_graphs(gsteps, steps, plan):
+    assert bench.graph_plan(gsteps, steps) == plan
+
+
+@pytest.mark.parametrize("rows", [False, True])
+def test_cpu_baseline_reports_cores_model_and_one_core(monkeypatch, rows):
+    import workloads
+    if rows:  # sample by rows, as for the largest workloads
+        monkeypatch.setattr(bench, "ROW_SAMPLE_PAIRS", 0)
+    w = workloads.twisted_rod(n=300)
+    cb = bench.cpu_baseline(w, target_s=0.3)
+    assert cb["kind"] == "oracle" and cb["unit"] == "particle-steps/s"
+    assert cb["value"] > 0 and cb["one_core"]["value"] > 0 and cb["cores"] >= 1
+    assert ("dipole and contact sums" in cb["sample"]) == rows
+    assert "logical_cpus" in cb and "cpu_model" in cb
