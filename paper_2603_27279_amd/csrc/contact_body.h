@@ -11,12 +11,13 @@
 // bucket repeats a lower lane's bucket stand down, so no pair is seen twice.
 // The selection r^2 = (dx dx + dy dy) + dz dz < r_c^2 uses explicitly rounded
 // FP64 operations (no contraction), so the pair set is exactly that of a
-// brute-force search with the same expression. Per-lane sums are kept in
-// 2^-48 fixed point and added across lanes as integers: the result does not
-// depend on the order in which particles were inserted into their cells.
+// brute-force search with the same expression. Pair terms are summed exactly
+// as 128-bit integers (see Fix128): the result does not depend on the order in
+// which particles were inserted into their cells.
 #pragma once
 #include "rod_internal.h"
 #include "rod_math.h"
+#include "fixsum.h"
 
 namespace rodmx {
 
@@ -24,15 +25,6 @@ namespace rodmx {
 __device__ __forceinline__ double r2_exact(V3<double> a, V3<double> b) {
   double dx = __dsub_rn(a.x, b.x), dy = __dsub_rn(a.y, b.y), dz = __dsub_rn(a.z, b.z);
   return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-}
-
-constexpr double FIX = 281474976710656.0;  // 2^48
-__device__ __forceinline__ long long to_fix(double v) { return __double2ll_rn(v * FIX); }
-
-// Sum over the 32 lanes of each half wave (integer adds: exact, any order).
-__device__ __forceinline__ long long half_sum(long long v) {
-  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
-  return v;
 }
 
 enum ContactOut { OUT_FORCE = 0, OUT_ENERGY = 1, OUT_PAIRS = 2 };
@@ -65,7 +57,8 @@ __device__ __forceinline__ void contact_pass(const Dev& d, long blk, int* pairs,
     unsigned ko = __shfl(key, o, 32);
     if (o < lane && ko == key) scan = false;
   }
-  long long fx = 0, fy = 0, fz = 0, fe = 0;
+  Fix3 f{};
+  Fix128 fe{};
   auto take = [&](int j, int rj, V3<double> xj) {
     if (j == (int)i || j < mb || j >= me) return;
     if (rj == rod && abs(j - (int)i) <= d.depth) return;
@@ -81,10 +74,9 @@ __device__ __forceinline__ void contact_pass(const Dev& d, long blk, int* pairs,
     const double r = sqrt(r2);
     const double ov = d.rc - r;
     const double s = (d.kc * ov) / r;
-    fx += to_fix(s * (xi.x - xj.x));
-    fy += to_fix(s * (xi.y - xj.y));
-    fz += to_fix(s * (xi.z - xj.z));
-    if (OUT == OUT_ENERGY) fe += to_fix(0.25 * d.kc * ov * ov);  // each pair seen from both ends
+    fix_add(f, s * (xi - xj), d.fix_scale[0], d.flags + FLAG_CONTACT_RANGE);
+    if (OUT == OUT_ENERGY)  // each pair seen from both ends
+      fix_add(fe, 0.25 * d.kc * ov * ov, d.fix_scale[2], d.flags + FLAG_CONTACT_RANGE);
   };
   if (scan) {
     // The first CELL_SPEC slots travel with the count (stale entries past the
@@ -111,11 +103,11 @@ __device__ __forceinline__ void contact_pass(const Dev& d, long blk, int* pairs,
     }
   }
   if (OUT == OUT_PAIRS) return;
-  fx = half_sum(fx); fy = half_sum(fy); fz = half_sum(fz);
+  f = half_sum(f);
   if (OUT == OUT_ENERGY) fe = half_sum(fe);
   if (pv && lane == 0) {
-    st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
-    if (OUT == OUT_ENERGY) d.cE[i] = (double)fe / FIX;
+    st3(d.cF, N, i, fix_value(f, d.fix_inv[0]));
+    if (OUT == OUT_ENERGY) d.cE[i] = fix_value(fe, d.fix_inv[2]);
   }
 }
 
@@ -173,7 +165,8 @@ __device__ __forceinline__ void contact_thread(const Dev& d, long blk) {
   const int mem = d.mem[i], rod = d.rod[i];
   const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
   const double rc2 = d.rc * d.rc;
-  long long fx = 0, fy = 0, fz = 0, fe = 0;
+  Fix3 f{};
+  Fix128 fe{};
   for_cell_candidates(d, cell_tab(d, d.step[d.lc]), xi, mem, [&](int j, int rj, V3<double> xj) {
     if (j == (int)i || j < mb || j >= me) return;
     if (rj == rod && abs(j - (int)i) <= d.depth) return;
@@ -182,13 +175,12 @@ __device__ __forceinline__ void contact_thread(const Dev& d, long blk) {
     const double r = sqrt(r2);
     const double ov = d.rc - r;
     const double s = (d.kc * ov) / r;
-    fx += to_fix(s * (xi.x - xj.x));
-    fy += to_fix(s * (xi.y - xj.y));
-    fz += to_fix(s * (xi.z - xj.z));
-    if (OUT == OUT_ENERGY) fe += to_fix(0.25 * d.kc * ov * ov);
+    fix_add(f, s * (xi - xj), d.fix_scale[0], d.flags + FLAG_CONTACT_RANGE);
+    if (OUT == OUT_ENERGY)
+      fix_add(fe, 0.25 * d.kc * ov * ov, d.fix_scale[2], d.flags + FLAG_CONTACT_RANGE);
   });
-  st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
-  if (OUT == OUT_ENERGY) d.cE[i] = (double)fe / FIX;
+  st3(d.cF, N, i, fix_value(f, d.fix_inv[0]));
+  if (OUT == OUT_ENERGY) d.cE[i] = fix_value(fe, d.fix_inv[2]);
 }
 
 // Contact force of a large system from per-particle candidate lists (Verlet
@@ -210,15 +202,13 @@ __device__ __forceinline__ void contact_listed(const Dev& d, long blk, bool buil
   const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
   const double rc2 = d.rc * d.rc;
   const double rs = d.rc + d.skin, rs2 = rs * rs;
-  long long fx = 0, fy = 0, fz = 0;
+  Fix3 f{};
   auto force = [&](V3<double> xj) {
     const double r2 = r2_exact(xi, xj);
     if (!(r2 < rc2)) return;
     const double r = sqrt(r2);
     const double s = (d.kc * (d.rc - r)) / r;
-    fx += to_fix(s * (xi.x - xj.x));
-    fy += to_fix(s * (xi.y - xj.y));
-    fz += to_fix(s * (xi.z - xj.z));
+    fix_add(f, s * (xi - xj), d.fix_scale[0], d.flags + FLAG_CONTACT_RANGE);
   };
   auto excluded = [&](int j, int rj) {
     return j == (int)i || j < mb || j >= me || (rj == rod && abs(j - (int)i) <= d.depth);
@@ -246,7 +236,7 @@ __device__ __forceinline__ void contact_listed(const Dev& d, long blk, bool buil
       for (int k = 0; k < cnt; ++k) force(ld3(d.x, N, d.nbr[(long)k * N + i]));
     }
   }
-  st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
+  st3(d.cF, N, i, fix_value(f, d.fix_inv[0]));
 }
 
 // ---------------------------------------------------------------- Hertz-Mindlin
@@ -326,7 +316,8 @@ __device__ __forceinline__ void contact_hm_thread(const Dev& d, long blk, bool b
   const double* ps = d.hc_s + pp * 3 * HM_CAP * N;
   int* cj = d.hc_j + pc * HM_CAP * N;
   double* cs = d.hc_s + pc * 3 * HM_CAP * N;
-  long long fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0, fe = 0;
+  Fix3 f{}, t{};
+  Fix128 fe{};
   int cnt = 0;
   auto excluded = [&](int j, int rj) {
     return j == (int)i || j < mb || j >= me || (rj == rod && abs(j - (int)i) <= d.depth);
@@ -344,9 +335,10 @@ __device__ __forceinline__ void contact_hm_thread(const Dev& d, long blk, bool b
       }
     const HmOut o = hm_pair(d, xi, xj, r2, vi, ld3(d.v, N, j), wi, ld3(d.w, N, j),
                             found ? &sprev : nullptr);
-    fx += to_fix(o.F.x); fy += to_fix(o.F.y); fz += to_fix(o.F.z);
-    tx += to_fix(o.T.x); ty += to_fix(o.T.y); tz += to_fix(o.T.z);
-    if (OUT == OUT_ENERGY) fe += to_fix(0.5 * o.e);  // each pair seen from both ends
+    fix_add(f, o.F, d.fix_scale[0], d.flags + FLAG_CONTACT_RANGE);
+    fix_add(t, o.T, d.fix_scale[1], d.flags + FLAG_CONTACT_RANGE);
+    if (OUT == OUT_ENERGY)  // each pair seen from both ends
+      fix_add(fe, 0.5 * o.e, d.fix_scale[2], d.flags + FLAG_CONTACT_RANGE);
     if (d.hist_write) {
       if (cnt < HM_CAP) {
         cj[(long)cnt * N + i] = j;
@@ -387,9 +379,9 @@ __device__ __forceinline__ void contact_hm_thread(const Dev& d, long blk, bool b
     d.hc_cnt[pc * N + i] = min(cnt, HM_CAP);
     if (cnt > HM_CAP) atomicOr(&d.flags[FLAG_HM_OVF], 1u);
   }
-  st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
-  st3(d.cT, N, i, V3<double>{(double)tx / FIX, (double)ty / FIX, (double)tz / FIX});
-  if (OUT == OUT_ENERGY) d.cE[i] = (double)fe / FIX;
+  st3(d.cF, N, i, fix_value(f, d.fix_inv[0]));
+  st3(d.cT, N, i, fix_value(t, d.fix_inv[1]));
+  if (OUT == OUT_ENERGY) d.cE[i] = fix_value(fe, d.fix_inv[2]);
 }
 
 // The same, lane-parallel for systems below the list size: half a wavefront
@@ -430,7 +422,8 @@ __device__ __forceinline__ void contact_hm_lanes(const Dev& d, long blk) {
   }
   if (lane == 0) slots[sub] = 0;
   __syncthreads();
-  long long fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0, fe = 0;
+  Fix3 f{}, t{};
+  Fix128 fe{};
   auto take = [&](int j, int rj, V3<double> xj) {
     if (j == (int)i || j < mb || j >= me) return;
     if (rj == rod && abs(j - (int)i) <= d.depth) return;
@@ -446,9 +439,10 @@ __device__ __forceinline__ void contact_hm_lanes(const Dev& d, long blk) {
       }
     const HmOut o = hm_pair(d, xi, xj, r2, vi, ld3(d.v, N, j), wi, ld3(d.w, N, j),
                             found ? &sprev : nullptr);
-    fx += to_fix(o.F.x); fy += to_fix(o.F.y); fz += to_fix(o.F.z);
-    tx += to_fix(o.T.x); ty += to_fix(o.T.y); tz += to_fix(o.T.z);
-    if (OUT == OUT_ENERGY) fe += to_fix(0.5 * o.e);
+    fix_add(f, o.F, d.fix_scale[0], d.flags + FLAG_CONTACT_RANGE);
+    fix_add(t, o.T, d.fix_scale[1], d.flags + FLAG_CONTACT_RANGE);
+    if (OUT == OUT_ENERGY)
+      fix_add(fe, 0.5 * o.e, d.fix_scale[2], d.flags + FLAG_CONTACT_RANGE);
     if (d.hist_write) {
       const int k = atomicAdd(&slots[sub], 1);
       if (k < HM_CAP) {
@@ -475,13 +469,13 @@ __device__ __forceinline__ void contact_hm_lanes(const Dev& d, long blk) {
     }
   }
   __syncthreads();
-  fx = half_sum(fx); fy = half_sum(fy); fz = half_sum(fz);
-  tx = half_sum(tx); ty = half_sum(ty); tz = half_sum(tz);
+  f = half_sum(f);
+  t = half_sum(t);
   if (OUT == OUT_ENERGY) fe = half_sum(fe);
   if (pv && lane == 0) {
-    st3(d.cF, N, i, V3<double>{(double)fx / FIX, (double)fy / FIX, (double)fz / FIX});
-    st3(d.cT, N, i, V3<double>{(double)tx / FIX, (double)ty / FIX, (double)tz / FIX});
-    if (OUT == OUT_ENERGY) d.cE[i] = (double)fe / FIX;
+    st3(d.cF, N, i, fix_value(f, d.fix_inv[0]));
+    st3(d.cT, N, i, fix_value(t, d.fix_inv[1]));
+    if (OUT == OUT_ENERGY) d.cE[i] = fix_value(fe, d.fix_inv[2]);
     if (d.hist_write) {
       const int cnt = slots[sub];
       d.hc_cnt[pc * N + i] = min(cnt, HM_CAP);

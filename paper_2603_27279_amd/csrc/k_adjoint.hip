@@ -27,6 +27,7 @@
 #include "bond_core.h"
 #include "dual.h"
 #include "particle_body.h"
+#include "fixsum.h"
 
 #include <algorithm>
 
@@ -315,8 +316,7 @@ __device__ __forceinline__ void adj_contact(const Dev& d, const Adj& a, const do
     unsigned ko = __shfl(key, o, 32);
     if (o < lane && ko == key) scan = false;
   }
-  const double FIX = 281474976710656.0;
-  long long sx = 0, sy = 0, sz = 0;
+  Fix3 sum{};
   auto take = [&](int j, int rj, V3<double> xj) {
     if (j == (int)i || j < mlo || j >= mhi) return;
     if (rj == rod && abs(j - (int)i) <= d.depth) return;
@@ -327,10 +327,7 @@ __device__ __forceinline__ void adj_contact(const Dev& d, const Adj& a, const do
     const V3<double> gv = gi - ldv(a.Fe, N, j);
     const double s1 = d.kc * (d.rc / r - 1.0);
     const double s2 = d.kc * d.rc * dot(dd, gv) / (r * r2);
-    const V3<double> out = s1 * gv - s2 * dd;
-    sx += __double2ll_rn(out.x * FIX);
-    sy += __double2ll_rn(out.y * FIX);
-    sz += __double2ll_rn(out.z * FIX);
+    fix_add(sum, s1 * gv - s2 * dd, d.fix_scale[0], d.flags + FLAG_CONTACT_RANGE);
   };
   const CellTab tab = cell_tab(d, d.step[d.lc]);
   if (scan) {
@@ -348,12 +345,8 @@ __device__ __forceinline__ void adj_contact(const Dev& d, const Adj& a, const do
       take(j, d.rod[j], ldv(S1, N, j));
     }
   }
-  for (int o = 16; o > 0; o >>= 1) {
-    sx += __shfl_xor(sx, o, 32);
-    sy += __shfl_xor(sy, o, 32);
-    sz += __shfl_xor(sz, o, 32);
-  }
-  if (pv && lane == 0) st3(d.cF, N, i, V3<double>{(double)sx / FIX, (double)sy / FIX, (double)sz / FIX});
+  sum = half_sum(sum);
+  if (pv && lane == 0) st3(d.cF, N, i, fix_value(sum, d.fix_inv[0]));
 }
 
 // ---------------------------------------------------------------- field gradient

@@ -160,6 +160,50 @@ static int dalloc(rod_ctx* c, T** p, size_t count) {
   return ROD_OK;
 }
 
+// Bounds on one pair's contribution to the contact sums of force, torque and
+// energy, which set the quanta of those exact sums: for the Hookean law the
+// force k r_c and the energy k r_c^2 / 2 at full overlap (no torque); for
+// Hertz-Mindlin the normal force at an overlap of r_c, times 1 + mu since the
+// tangential force is limited to mu times the normal one, that tangential force
+// on the arm r_c / 2 for the torque, and the normal energy at that overlap. A
+// zero bound (no such term) is taken as 1.
+static void contact_bounds(const rod_desc* d, double b[3]) {
+  const double rc = d->r_contact;
+  if (d->contact_model == ROD_CONTACT_HERTZ_MINDLIN) {
+    const double E = d->contact_hm[0], nu = d->contact_hm[1], mu = d->contact_hm[2];
+    const double Es = E / (2.0 * (1.0 - nu * nu)), Rs = 0.25 * rc;
+    const double fn = 4.0 / 3.0 * Es * std::sqrt(Rs * rc) * rc;
+    b[0] = (1.0 + mu) * fn;
+    b[1] = 0.5 * rc * mu * fn;
+    b[2] = 8.0 / 15.0 * Es * std::sqrt(Rs) * rc * rc * std::sqrt(rc);
+  } else {
+    const double k = std::fabs(d->k_contact);
+    b[0] = k * rc;
+    b[1] = 0.0;
+    b[2] = 0.5 * k * rc * rc;
+  }
+  for (int q = 0; q < 3; ++q)
+    if (b[q] == 0.0) b[q] = 1.0;
+}
+
+// Scale exponents of the exact contact sums; fails when a bound is not finite
+// or so far from 1 that the scale or a term at its bound leaves FP64's range.
+static int contact_scales(const rod_desc* d, int e[3]) {
+  double b[3];
+  contact_bounds(d, b);
+  static const char* what[3] = {"force", "torque", "energy"};
+  for (int q = 0; q < 3; ++q) {
+    if (!std::isfinite(b[q]) || !(b[q] > 0))
+      return fail(ROD_E_INVALID, "the contact law's bound on a pair's %s (%g) is not finite",
+                  what[q], b[q]);
+    e[q] = FIX_BOUND_EXP - std::ilogb(b[q]);
+    if (e[q] < -900 || e[q] > 900)
+      return fail(ROD_E_INVALID, "the contact law's bound on a pair's %s (%g) is outside the "
+                  "range of the exact contact sums (2^-820 to 2^980)", what[q], b[q]);
+  }
+  return ROD_OK;
+}
+
 static int validate(const rod_desc* d) {
   if (!d) return fail(ROD_E_INVALID, "descriptor is NULL");
   if (d->n_particles < 1 || d->n_rods < 1 || d->n_members < 1)
@@ -227,6 +271,11 @@ static int validate(const rod_desc* d) {
       return fail(ROD_E_INVALID, "Hertz-Mindlin needs E > 0, -1 < nu <= 0.5, mu, g_n, g_t >= 0");
     if (d->tape_capacity > 0)
       return fail(ROD_E_INVALID, "Hertz-Mindlin contact is not differentiated: no tape with it");
+  }
+  if (d->contact_on) {
+    if (!std::isfinite(d->k_contact)) return fail(ROD_E_INVALID, "k_contact must be finite");
+    int e[3];
+    TRY(contact_scales(d, e));
   }
   if (!(d->dipole_cutoff >= 0) || !std::isfinite(d->dipole_cutoff))
     return fail(ROD_E_INVALID, "dipole_cutoff must be finite and >= 0");
@@ -658,7 +707,7 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
       (rc = dalloc(c, &d.bTbt, 3 * (size_t)N)) || (rc = dalloc(c, &d.bE, 4 * (size_t)N)) ||
       (rc = dalloc(c, &d.cF, 3 * (size_t)N)) || (rc = dalloc(c, &d.cE, (size_t)N)) ||
       (rc = dalloc(c, &d.key, (size_t)N)) || (rc = dalloc(c, &d.ovf_list, 2 * (size_t)OVF_CAP)) ||
-      (rc = dalloc(c, &d.ovf_cnt, 2)) || (rc = dalloc(c, &d.flags, 4)) ||
+      (rc = dalloc(c, &d.ovf_cnt, 2)) || (rc = dalloc(c, &d.flags, FLAG_COUNT)) ||
       (rc = dalloc(c, &d.step, 3)) ||
       (rc = dalloc(c, &c->epart, 18 * (size_t)N)) || (rc = dalloc(c, &c->eout, 9 * (size_t)M)) ||
       (rc = dalloc(c, &c->pair_count, 1)))
@@ -675,6 +724,15 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   d.cell_mask = (unsigned)(cells - 1);
   d.dt = dsc->dt; d.damping = dsc->damping; d.C = dsc->mu0_4pi; d.kc = dsc->k_contact;
   d.rc = dsc->r_contact; d.inv_cell = dsc->contact_on ? 1.0 / dsc->r_contact : 0.0;
+  for (int q = 0; q < 3; ++q) { d.fix_scale[q] = 1.0; d.fix_inv[q] = 1.0; }
+  if (dsc->contact_on) {
+    int e[3];
+    if ((rc = contact_scales(dsc, e))) return cleanup(rc);
+    for (int q = 0; q < 3; ++q) {
+      d.fix_scale[q] = std::ldexp(1.0, e[q]);
+      d.fix_inv[q] = std::ldexp(1.0, -e[q]);
+    }
+  }
   d.depth = dsc->exclude_depth; d.field_len = dsc->field_len;
   d.hm = dsc->contact_on && dsc->contact_model == ROD_CONTACT_HERTZ_MINDLIN;
   d.dcut = dsc->dipole_on && dsc->dipole_cutoff > 0 ? dsc->dipole_cutoff : 0.0;
@@ -814,12 +872,18 @@ int rod_step(rod_ctx* c, int64_t n) {
 int rod_sync(rod_ctx* c) {
   if (!c) return fail(ROD_E_INVALID, "context is NULL");
   HIPC(hipStreamSynchronize(c->s));
-  unsigned f[4];
+  unsigned f[FLAG_COUNT];
   HIPC(hipMemcpy(f, c->d.flags, sizeof(f), hipMemcpyDeviceToHost));
-  if (f[0] | f[1] | f[2] | f[3]) {
-    unsigned z[4] = {0, 0, 0, 0};
+  unsigned any = 0;
+  for (int k = 0; k < FLAG_COUNT; ++k) any |= f[k];
+  if (any) {
+    unsigned z[FLAG_COUNT] = {};
     HIPC(hipMemcpy(c->d.flags, z, sizeof(z), hipMemcpyHostToDevice));
     if (f[FLAG_NONFINITE]) return fail(ROD_E_NONFINITE, "non-finite force, torque or position");
+    if (f[FLAG_CONTACT_RANGE])
+      return fail(ROD_E_OVERFLOW, "a contact pair's force, torque or energy was non-finite or "
+                  "2^28 times the contact law's bound or more: outside the range of the exact "
+                  "contact sums");
     if (f[FLAG_HM_OVF])
       return fail(ROD_E_OVERFLOW, "a particle had more than %d Hertz-Mindlin contacts", HM_CAP);
     if (f[FLAG_DIP_OVF])

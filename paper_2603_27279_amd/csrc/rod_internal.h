@@ -61,15 +61,20 @@ struct Dev {
   double* xb;              // [3N] positions at the last build
   unsigned* rebuild;       // [2] per level parity: some particle moved too far since the build
   double skin;             // list cutoff is r_c + skin
-  unsigned* flags;         // [4]: [0] non-finite state, [1] a dipole list was full,
+  unsigned* flags;         // [FLAG_COUNT]: [0] non-finite state, [1] a dipole list was full,
                            // [2] overflow list full,
-                           // [3] a particle had more Hertz-Mindlin contacts than HM_CAP
+                           // [3] a particle had more Hertz-Mindlin contacts than HM_CAP,
+                           // [4] a contact sum's term left the range of its exact sum
   long long* step;         // [3]: [0] time level of the state (written by the particle
                            // kernel); [1], [2] level of the force evaluation in flight,
                            // in the entry named by lc. No kernel writes what it reads.
   int lc;                  // 1 or 2: entry of step[] holding the level of the forces
   // parameters
   double dt, damping, C, kc, rc, inv_cell;
+  // Exact contact sums (contact_body.h, Fix128): per quantity (force, torque,
+  // energy) the power of two that maps the contact law's bound on one pair's
+  // term to 2^80, and its inverse.
+  double fix_scale[3], fix_inv[3];
   int depth, field_len, dipole_on, contact_on;
   int dip_small;           // dipole work items use the small-member layout (4 i per item)
   // Bounding boxes of consecutive 64-particle chunks at the level being
@@ -120,7 +125,10 @@ constexpr double NBR_MOVE = 0.45;               // rebuild past this fraction of
                                                 // (below 1/2, a margin for rounding)
 constexpr int HM_CAP = 16;                      // Hertz-Mindlin contacts kept per particle
 constexpr int DNBR_CAP = 256;                   // dipole list entries per particle (cutoff)
-enum { FLAG_NONFINITE = 0, FLAG_DIP_OVF = 1, FLAG_LIST_OVF = 2, FLAG_HM_OVF = 3 };
+enum { FLAG_NONFINITE = 0, FLAG_DIP_OVF = 1, FLAG_LIST_OVF = 2, FLAG_HM_OVF = 3,
+       FLAG_CONTACT_RANGE = 4, FLAG_COUNT = 5 };
+// Exponent that maps a pair-term bound b to 2^80 in the exact contact sums.
+constexpr int FIX_BOUND_EXP = 80;
 
 // Cell of a coordinate (cells of side 1/inv), clamped so runaway coordinates
 // stay hashable.

@@ -100,6 +100,15 @@ def test_query_workspace_and_invalid_descriptors():
         for h in ((0, 0.3, 0.5, 0, 0), (10, 0.6, 0.5, 0, 0), (10, -1.0, 0.5, 0, 0),
                   (10, 0.3, -0.1, 0, 0), (10, 0.3, 0.5, -1, 0), (10, 0.3, 0.5, 0, -1))
     ]
+    # the exact contact sums take their quantum from a bound on one pair's term:
+    # bounds too far from 1 for a representable scale are refused
+    cases += [(dict(k_contact=kc), "outside the range of the exact contact sums")
+              for kc in (1e-300, -1e-300, 1e300)]
+    cases += [(dict(k_contact=float("inf")), "k_contact must be finite"),
+              (dict(contact_model=1, contact_hm=hm(1e-290, 0.3, 0.5, 0, 0)),
+               "outside the range of the exact contact sums"),
+              (dict(contact_model=1, contact_hm=hm(1e300, 0.3, 0.5, 0, 0)),
+               "outside the range of the exact contact sums")]
     cases += [(dict(contact_model=1, contact_hm=hm(10, 0.3, np.nan, 0, 0)), "finite"),
               (dict(contact_model=1, contact_hm=hm(10, 0.3, 0.5, 0, 0), tape_capacity=10,
                     tape_every=2), "no tape with it")]
@@ -144,6 +153,21 @@ def test_hertz_mindlin_descriptor():
     assert nb2.value - nb.value == (24 + 8 + 2 * 16 * (4 + 24)) * 64
     d3, keep3 = _desc(w, contact_on=0, contact_model=1, tape_capacity=10, tape_every=2)
     assert lib.rod_query_workspace(C.byref(d3), C.byref(nb2)) == L.ROD_OK
+
+
+def test_contact_scales_accept_non_unit_laws():
+    """Stiff, soft and unit-system-scaled contact laws are accepted: only the
+    quantum of the exact sums follows the law's bound."""
+    lib = L.load()
+    w = workloads.twisted_rod(n=64)
+    nb = C.c_size_t()
+    hm = lambda *h: (C.c_double * 5)(*h)
+    for over in (dict(k_contact=1e6), dict(k_contact=1e-6), dict(k_contact=0.0),
+                 dict(contact_model=1, contact_hm=hm(1e-3, 0.3, 0.5, 0, 0)),
+                 dict(contact_model=1, contact_hm=hm(1e9, 0.3, 0.0, 1e3, 1e3)),
+                 dict(contact_on=0, k_contact=1e-300)):
+        d, keep = _desc(w, **over)
+        assert lib.rod_query_workspace(C.byref(d), C.byref(nb)) == L.ROD_OK, over
 
 
 def test_null_context_is_rejected():
