@@ -161,8 +161,8 @@ def adjoint_full():
     """The full adjoint workload (N = 256, T = 2000 steps, checkpoints every
     100) and the adjoint gradient of |x_tip - target|^2."""
     w = workloads.make("adjoint_rod")
-    g, _, _ = gpu_grad(w, w["steps"], w["tape_every"])
-    return w, g, _loss_of(w, "x0", 0.0)
+    g, _, gx = gpu_grad(w, w["steps"], w["tape_every"])
+    return w, g, _loss_of(w, "x0", 0.0), gx
 
 
 def _loss_of(w, block, delta):
@@ -190,7 +190,7 @@ def test_full_adjoint_workload_vs_central_differences(adjoint_full, block):
     difference therefore carries an absolute error of about 7e-16 L / h; the
     bound adds 3e-15 L / h to the 1e-4 relative tolerance, which matters only
     for coordinates whose gradient is far below the block's largest."""
-    w, g, L0 = adjoint_full
+    w, g, L0, _ = adjoint_full
     gb = np.asarray(g[block])
     base = np.asarray(w[block], dtype=np.float64)
     rng = np.random.default_rng(7 + BLOCKS.index(block))
@@ -211,6 +211,61 @@ def test_full_adjoint_workload_vs_central_differences(adjoint_full, block):
         fd = (_loss_of(w, block, e) - _loss_of(w, block, -e)) / (2 * h)
         ad = float(gb.reshape(-1)[int(k)])
         assert abs(fd - ad) <= 1e-4 * max(abs(ad), 1e-3 * gmax) + noise, (block, int(k), fd, ad)
+
+
+@pytest.mark.parametrize("block", BLOCKS)
+def test_full_adjoint_workload_vs_oracle_jvp(adjoint_full, block):
+    """The gradient of the full adjoint workload (N = 256, E = 10, T = 2000,
+    checkpoints every 100) against the oracle's dual-number JVP of the same
+    2000 steps, in three random directions per block, to 1e-10 of the sum of
+    the directional terms' magnitudes."""
+    w, g, _, gx = adjoint_full
+    rng = np.random.default_rng(31 + BLOCKS.index(block))
+    gb = np.asarray(g[block])
+    for _ in range(3):
+        u = rng.normal(size=np.shape(w[WKEY[block]]))
+        _, dT = oracle.run_jvp(w, w["steps"], {WKEY[block]: u})
+        ref = float(np.sum(gx * dT["x"]))
+        got = float(np.sum(gb * u))
+        scale = float(np.sum(np.abs(gb * u)))
+        assert abs(got - ref) <= 1e-10 * scale, (block, got, ref, scale)
+
+
+# Longest run of the adjoint rod at the Young's modulus the configuration
+# states (E = 1) before its dipoles turn neighbouring particles by nearly pi
+# relative to each other (the short-arc central frame of the bond model flips
+# there, near step 158): 120 steps, largest neighbour rotation 2.29 rad.
+E1_STEPS = 120
+
+
+def test_adjoint_rod_at_unit_modulus():
+    """The adjoint workload as configured (E = 1; N = 256) over the 120 steps
+    before the central frame nears its flip: rod_grad against the oracle's JVP
+    on every block at 1e-10, and against central differences of the GPU forward
+    run (h = 1e-6) in one random direction per block at 1e-6 (plus the forward's
+    rounding noise over 2h)."""
+    w = workloads.adjoint_rod(E=1.0)
+    st = oracle.run(w, E1_STEPS)
+    d = np.abs(np.sum(st["q"][:-1] * st["q"][1:], axis=1))
+    assert 2.2 < np.max(2 * np.arccos(np.minimum(d, 1.0))) < 2.4
+    g = jvp_check(w, E1_STEPS, 10, seed=5)
+
+    def loss(w2):
+        s = RodSim(w2, precision="fp64")
+        s.step(E1_STEPS)
+        s.sync()
+        xT = s.state()["x"]
+        s.free()
+        return float(np.sum((xT[-1] - w["target"]) ** 2))
+    rng = np.random.default_rng(6)
+    h = 1e-6
+    noise = 3e-15 * loss(w) / h  # the forward's rounding noise over 2h
+    for blk in BLOCKS:
+        u = rng.normal(size=np.shape(w[WKEY[blk]]))
+        fd = (loss(dict(w, **{blk: w[blk] + h * u})) - loss(dict(w, **{blk: w[blk] - h * u}))) / (2 * h)
+        ad = float(np.sum(np.asarray(g[blk]) * u))
+        scale = float(np.sum(np.abs(np.asarray(g[blk]) * u)))
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-2 * scale) + noise, (blk, fd, ad, scale)
 
 
 def test_taped_forward_matches_plain_run_bitwise():
