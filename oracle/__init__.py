@@ -52,6 +52,8 @@ class _System(C.Structure):
         ("contact_model", C.c_int32), ("contact_hm", C.c_double * 5),
         ("dipole_cutoff", C.c_double),
         ("fluid_u", C.c_void_p), ("fluid_dt", C.c_double), ("fluid_F", C.c_void_p),
+        ("box", C.c_double * 3), ("ewald_alpha", C.c_double), ("ewald_rcut", C.c_double),
+        ("ewald_kmax", C.c_int32),
     ]
 
 
@@ -119,6 +121,12 @@ class System:
         s.fluid_u = _p(keep["fluid_u"])
         s.fluid_dt = float(w.get("fluid_dt") or 1.0)
         s.fluid_F = _p(keep["fluid_F"])
+        box = w.get("box")
+        if box is not None:
+            s.box = (C.c_double * 3)(*[float(a) for a in box])
+            s.ewald_alpha = float(w["ewald_alpha"])
+            s.ewald_rcut = float(w["ewald_rcut"])
+            s.ewald_kmax = int(w["ewald_kmax"])
         s.contact_model = contact_model(w)
         if s.contact_model == 1:
             s.contact_hm = (C.c_double * 5)(*[float(a) for a in w["contact_hm"]])
@@ -333,6 +341,8 @@ def run_jvp(w, nsteps, tangent, step0=0):
         raise NotImplementedError("the forward-mode run does not differentiate Hertz-Mindlin contact")
     if w.get("dipole_cutoff"):
         raise NotImplementedError("the forward-mode run does not differentiate the dipole cutoff")
+    if w.get("box") is not None:
+        raise NotImplementedError("the forward-mode run does not differentiate the Ewald sum")
     lib = _load()
     sy = System(w)
     n = sy.n
@@ -351,6 +361,8 @@ def run_jvp(w, nsteps, tangent, step0=0):
 
 def rows(w, x, q, rows, mbody=None):
     """Dipole force, dipole field and contact force [len(rows), 3] of selected particles."""
+    if w.get("box") is not None:
+        raise NotImplementedError("rows are open-boundary sums; a periodic box has no row form")
     lib = _load()
     sy = System(w)
     n = sy.n

@@ -170,6 +170,14 @@ struct Model {
   // Dipole-dipole cutoff: 0 for every pair of a member; otherwise only pairs
   // with r^2 = (dx dx + dy dy) + dz dz < dcut^2 interact.
   double dcut = 0;
+  // Periodic box (all three lengths > 0; else open boundaries): the dipole sum
+  // is the Ewald sum of each member's periodic system, with splitting
+  // parameter alpha, real-space cutoff rcut and reciprocal vectors
+  // k = 2 pi (n_x / L_x, n_y / L_y, n_z / L_z), 0 < |n|^2 <= kmax^2.
+  bool periodic = false;
+  double box[3] = {0, 0, 0};
+  double ew_alpha = 0, ew_rcut = 0;
+  int ew_kmax = 0;
   // Immersed-boundary penalty (Methods, "Immersed boundary coupling"): the fluid
   // velocity interpolated at each particle ([N][3], or null: no coupling), the
   // fluid time step (kappa_p = m_p / fluid_dt) and where the forces go ([N][3]).
@@ -212,6 +220,10 @@ struct orc_system {
   const double* fluid_u;       // [N][3] fluid velocity at the particles, or NULL
   double fluid_dt;             // fluid time step (penalty stiffness m_p / fluid_dt)
   double* fluid_F;             // [N][3] penalty force of the last evaluation, or NULL
+  double box[3];               // periodic box lengths (all > 0), or zeros: open boundaries
+  double ewald_alpha;          // Ewald splitting parameter
+  double ewald_rcut;           // real-space cutoff of the Ewald sum
+  int32_t ewald_kmax;          // reciprocal vectors with 0 < |n|^2 <= kmax^2
 };
 
 }  // extern "C"
@@ -284,6 +296,9 @@ static Model build_model(const orc_system* s) {
   m.hmE = s->contact_hm[0]; m.hmNu = s->contact_hm[1]; m.hmMu = s->contact_hm[2];
   m.hmGn = s->contact_hm[3]; m.hmGt = s->contact_hm[4];
   m.dcut = s->dipole_cutoff;
+  m.periodic = s->box[0] > 0 && s->box[1] > 0 && s->box[2] > 0;
+  for (int a = 0; a < 3; ++a) m.box[a] = s->box[a];
+  m.ew_alpha = s->ewald_alpha; m.ew_rcut = s->ewald_rcut; m.ew_kmax = s->ewald_kmax;
   m.fluid_u = s->fluid_u; m.fluid_dt = s->fluid_dt > 0 ? s->fluid_dt : 1.0; m.fluid_F = s->fluid_F;
   return m;
 }
@@ -440,6 +455,116 @@ void dipoles(const Model& md, const T* q, const T* mbody, std::vector<T>& mu) {
 //   x, q: positions and orientations;  v, w: the velocities used by damping;
 //   mu: global dipole moments; field: external field table; n: time level.
 // Bdip (optional) receives the dipole field at each particle.
+// ---------------------------------------------------------------- Ewald
+// Periodic dipole-dipole interaction by Ewald summation: the long-range
+// solvers the paper's LAMMPS implementation offers beside the truncated pair
+// style (Introduction; SI "Magnetic dipoles"), for a member whose particles
+// repeat in a box L_x x L_y x L_z, with conducting boundaries at infinity (no
+// surface term). With C = mu0/4pi, r = x_i - x_j + n L over every image, the
+// interaction splits at alpha into
+//   real space, pairs (and images of a particle itself) closer than rcut:
+//     U = C sum (mi.mj) B(r) - (mi.r)(mj.r) C(r), with
+//     B = [erfc(a r) + 2 a r/sqrt(pi) e] / r^3,
+//     C = [3 erfc(a r) + 2 a r/sqrt(pi) (3 + 2 a^2 r^2) e] / r^5,
+//     D = [15 erfc(a r) + 2 a r/sqrt(pi) (15 + 10 a^2 r^2 + 4 a^4 r^4) e] / r^7,
+//     e = exp(-a^2 r^2): the screened forms of 1/r^3, 3/r^5, 15/r^7;
+//   reciprocal space, k = 2 pi n / L, n != 0, |n|^2 <= kmax^2:
+//     U = (2 pi C / V) sum_k g(k) |S(k)|^2, g = exp(-k^2 / 4 a^2) / k^2,
+//     S(k) = sum_j (mj.k) exp(i k.x_j);
+//   self: U = -C 2 a^3 / (3 sqrt(pi)) sum |m_i|^2.
+// Force F_i = -dU/dx_i, field B_i = -dU/dm_i (so that U = -1/2 sum m_i.B_i and
+// the torque is m_i x B_i):
+//   real: F_i += C [(mi.mj) C r + C ((mj.r) mi + (mi.r) mj) - (mi.r)(mj.r) D r],
+//         B_i += C [C (mj.r) r - B mj];
+//   reciprocal: F_i += (4 pi C / V) g (mi.k) k Im[exp(i k.x_i) S*(k)],
+//               B_i -= (4 pi C / V) g k Re[exp(i k.x_i) S*(k)];
+//   self: B_i += C 4 a^3 / (3 sqrt(pi)) m_i.
+// Every image within rcut is taken (rcut may exceed half the box); the
+// reciprocal sum runs over all k of the sphere, k and -k alike.
+// F, Bd: [N][3] (added to); U: [M] (added to) or null.
+static void ewald_dipoles(const Model& md, const double* x, const double* mu, double* F,
+                          double* Bd, double* U) {
+  const double pi = 3.14159265358979323846;
+  const double C = md.C, a = md.ew_alpha, rc2 = md.ew_rcut * md.ew_rcut;
+  const double L[3] = {md.box[0], md.box[1], md.box[2]};
+  const double V = L[0] * L[1] * L[2];
+  const double sp = 2.0 * a / std::sqrt(pi);
+  for (int mem = 0; mem < md.M; ++mem) {
+    const int b = md.member_begin[mem], e = md.member_end[mem];
+    double Um = 0.0;
+    // real space
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : Um)
+    for (int i = b; i < e; ++i) {
+      const V3<double> xi = ld3(x, i), mi = ld3(mu, i);
+      V3<double> Fi{0, 0, 0}, Bi{0, 0, 0};
+      for (int j = b; j < e; ++j) {
+        const V3<double> mj = ld3(mu, j);
+        const V3<double> r0 = xi - ld3(x, j);
+        const double r0a[3] = {r0.x, r0.y, r0.z};
+        int lo[3], hi[3];
+        for (int ax = 0; ax < 3; ++ax) {
+          lo[ax] = (int)std::ceil((-md.ew_rcut - r0a[ax]) / L[ax]);
+          hi[ax] = (int)std::floor((md.ew_rcut - r0a[ax]) / L[ax]);
+        }
+        for (int nx = lo[0]; nx <= hi[0]; ++nx)
+          for (int ny = lo[1]; ny <= hi[1]; ++ny)
+            for (int nz = lo[2]; nz <= hi[2]; ++nz) {
+              if (i == j && nx == 0 && ny == 0 && nz == 0) continue;
+              const V3<double> r{r0.x + nx * L[0], r0.y + ny * L[1], r0.z + nz * L[2]};
+              const double r2 = dot(r, r);
+              if (!(r2 < rc2)) continue;
+              const double rr = std::sqrt(r2), ar = a * rr, ex = std::exp(-ar * ar);
+              const double ec = std::erfc(ar);
+              const double Bf = (ec + sp * rr * ex) / (r2 * rr);
+              const double Cf = (3.0 * ec + sp * rr * (3.0 + 2.0 * ar * ar) * ex) / (r2 * r2 * rr);
+              const double Df = (15.0 * ec + sp * rr * (15.0 + 10.0 * ar * ar + 4.0 * ar * ar * ar * ar) * ex) /
+                                (r2 * r2 * r2 * rr);
+              const double dmi = dot(mi, r), dmj = dot(mj, r), mm = dot(mi, mj);
+              Fi = Fi + C * ((mm * Cf) * r + Cf * (dmj * mi + dmi * mj) - (dmi * dmj * Df) * r);
+              Bi = Bi + C * ((Cf * dmj) * r - Bf * mj);
+              Um += 0.5 * C * (mm * Bf - dmi * dmj * Cf);
+            }
+      }
+      add3(F, i, Fi);
+      add3(Bd, i, Bi);
+    }
+    // reciprocal space
+    const int K = md.ew_kmax;
+    for (int nx = -K; nx <= K; ++nx)
+      for (int ny = -K; ny <= K; ++ny)
+        for (int nz = -K; nz <= K; ++nz) {
+          const int n2 = nx * nx + ny * ny + nz * nz;
+          if (n2 == 0 || n2 > K * K) continue;
+          const V3<double> k{2.0 * pi * nx / L[0], 2.0 * pi * ny / L[1], 2.0 * pi * nz / L[2]};
+          const double k2 = dot(k, k);
+          const double g = std::exp(-k2 / (4.0 * a * a)) / k2;
+          double Sr = 0.0, Si = 0.0;
+          for (int j = b; j < e; ++j) {
+            const double mk = dot(ld3(mu, j), k), ph = dot(k, ld3(x, j));
+            Sr += mk * std::cos(ph);
+            Si += mk * std::sin(ph);
+          }
+          Um += 2.0 * pi * C / V * g * (Sr * Sr + Si * Si);
+          const double c = 4.0 * pi * C / V * g;
+          for (int i = b; i < e; ++i) {
+            const double ph = dot(k, ld3(x, i));
+            const double cs = std::cos(ph), sn = std::sin(ph);
+            const double mk = dot(ld3(mu, i), k);
+            add3(F, i, (c * mk * (sn * Sr - cs * Si)) * k);
+            add3(Bd, i, (-c * (cs * Sr + sn * Si)) * k);
+          }
+        }
+    // self
+    const double cs = C * 4.0 * a * a * a / (3.0 * std::sqrt(pi));
+    for (int i = b; i < e; ++i) {
+      const V3<double> mi = ld3(mu, i);
+      add3(Bd, i, cs * mi);
+      Um -= 0.5 * cs * dot(mi, mi);
+    }
+    if (U) U[mem] += Um;
+  }
+}
+
 // ---------------------------------------------------------------- Hertz-Mindlin
 // One Hertz-Mindlin contact seen from particle i, its partner j closer than r_c
 // (Methods, "Contact", which names the law; its constants are the textbook
@@ -545,7 +670,16 @@ void forces(const Model& md, const T* x, const T* q, const T* v, const T* w,
   // F_i = -dU/dx_i; the field of j at x_i is C (3 (mj.r) r / r^5 - mj / r^3);
   // the torque is m_i x B_i.
   std::vector<T> Bd(3 * N, T(0.0));
-  if ((mask & T_DIPOLE) && md.dipole_on) {
+  if ((mask & T_DIPOLE) && md.dipole_on && md.periodic) {
+    if constexpr (std::is_same<T, double>::value) {
+      std::vector<double> Fe(3 * N, 0.0);
+      ewald_dipoles(md, x, mu, Fe.data(), Bd.data(), nullptr);
+      for (int i = 0; i < N; ++i) {
+        add3(F, i, ld3(Fe.data(), i));
+        add3(Tq, i, cross(ld3(mu, i), ld3(Bd.data(), i)));
+      }
+    }
+  } else if ((mask & T_DIPOLE) && md.dipole_on) {
     const T C(md.C);
 #pragma omp parallel for schedule(dynamic, 64)
     for (int i = 0; i < N; ++i) {
@@ -898,11 +1032,17 @@ void orc_energy(const orc_system* s, const double* x, const double* q, const dou
     out[9 * mem + 7] += 0.5 * md.mass[p] * dot(ld3(v, p), ld3(v, p));
     out[9 * mem + 8] += 0.5 * md.inertia[p] * dot(ld3(w, p), ld3(w, p));
   }
+  if (md.dipole_on && md.periodic) {  // Ewald energy of each member's periodic system
+    std::vector<double> Fe(3 * md.n, 0.0), Be(3 * md.n, 0.0), Ue(md.M, 0.0);
+    ewald_dipoles(md, x, mu.data(), Fe.data(), Be.data(), Ue.data());
+    for (int mem = 0; mem < md.M; ++mem) out[9 * mem + 5] += Ue[mem];
+  }
   for (int i = 0; i < md.n; ++i) {
     int mem = md.member_of[i];
     for (int j = i + 1; j < md.member_end[mem]; ++j) {
       V3<double> r = ld3(x, i) - ld3(x, j);
-      if (md.dipole_on && (md.dcut == 0.0 || (r.x * r.x + r.y * r.y) + r.z * r.z < md.dcut * md.dcut)) {
+      if (md.dipole_on && !md.periodic &&
+          (md.dcut == 0.0 || (r.x * r.x + r.y * r.y) + r.z * r.z < md.dcut * md.dcut)) {
         double rr = norm(r);
         V3<double> rh = (1.0 / rr) * r;
         V3<double> mi = ld3(mu.data(), i), mj = ld3(mu.data(), j);

@@ -30,6 +30,11 @@ dt, damping       float                        time step; global viscous damping
 mu0_4pi           float                        dipole prefactor mu0 / (4 pi)
 dipole_on         bool                         dipole-dipole interaction within a member
 dipole_cutoff     float                        0: every pair of a member; > 0: pairs closer than this
+box               float64 [3] or None          periodic box lengths: the dipole sum is then the Ewald
+                                               sum of each member's periodic system (None: open)
+ewald_alpha       float                        Ewald splitting parameter (with a box)
+ewald_rcut        float                        Ewald real-space cutoff (with a box)
+ewald_kmax        int                          Ewald reciprocal vectors 2 pi n / L, 0 < |n|^2 <= kmax^2
 contact_on        bool                         contact between non-excluded pairs
 contact_model     str                          "hookean" (normal, k_contact) or "hertz_mindlin"
 contact_hm        float64 [5] or None          Hertz-Mindlin: contact modulus E, Poisson nu, friction
@@ -81,6 +86,7 @@ def _base(x_ref, rod_offset, rod_member, rod_params, m_body, bc, field, **kw):
         field=np.ascontiguousarray(field, dtype=np.float64),
         ext_force=None, ext_torque=None, bond_damping=None,
         contact_model="hookean", contact_hm=None, dipole_cutoff=0.0,
+        box=None, ewald_alpha=0.0, ewald_rcut=0.0, ewald_kmax=0,
         dt=0.01, damping=0.1, mu0_4pi=1.0,
         dipole_on=True, contact_on=False, k_contact=10.0, r_contact=1.0,
         exclude_depth=1, steps=100, precision="fp64", name="custom",
