@@ -145,6 +145,25 @@ typedef struct rod_desc {
                                  particle (more: ROD_E_OVERFLOW at rod_sync). FP64 on both paths;
                                  sums in list order, so runs agree to rounding, not bit for bit.
                                  Not differentiated: refused with tape_capacity > 0. */
+  double box[3];              /* Periodic box lengths L_x, L_y, L_z, all > 0; or all 0 (open
+                                 boundaries). With a box and dipole_on, the dipole-dipole
+                                 interaction is the Ewald sum of each member's periodic system
+                                 (the long-range solvers offered beside the truncated pair style:
+                                 Introduction; SI "Magnetic dipoles"), with conducting boundaries
+                                 at infinity: real-space pairs by the minimum image closer than
+                                 ewald_rcut, with the erfc-screened dipole terms; reciprocal
+                                 vectors k = 2 pi (n_x/L_x, n_y/L_y, n_z/L_z), 0 < |n|^2 <=
+                                 ewald_kmax^2, weighted by (4 pi C / V) exp(-k^2/4a^2) / k^2 with
+                                 a = ewald_alpha; the self field C 4 a^3 / (3 sqrt(pi)) m_i.
+                                 Positions need not be wrapped into the box. FP64 on both
+                                 paths; sums in a fixed order (deterministic). Needs
+                                 contact_on = 0 (contact is not periodic), dipole_cutoff = 0 and
+                                 no tape (ROD_E_INVALID otherwise). The accuracy is the caller's
+                                 choice of a, ewald_rcut and ewald_kmax: erfc(a rc) and
+                                 exp(-(pi kmax / (a L))^2) bound the two truncations. */
+  double ewald_alpha;         /* Ewald splitting parameter a > 0 (with a box) */
+  double ewald_rcut;          /* real-space cutoff, 0 < rc <= min(L) / 2 (with a box) */
+  int32_t ewald_kmax;         /* reciprocal cutoff, 1 <= kmax <= 64 (with a box) */
 } rod_desc;
 
 /* Caller-owned device buffers (SoA, float64). */
@@ -205,6 +224,26 @@ int rod_topology(rod_ctx* c, int32_t* ij, double* rref, double* K, int32_t cap, 
 /* Contact pairs (i < j, ascending) found by the cell list at the current state
  * (host output, synchronises); *count receives the total, at most cap written. */
 int rod_contact_pairs(rod_ctx* c, int32_t* pairs, int32_t cap, int32_t* count);
+
+/* Hertz-Mindlin contact history of the current time level (Methods, "Contact":
+ * the tangential spring of a contact builds up over the contact's lifetime, so
+ * a run continued from a saved state must carry it to equal the uncut run).
+ * rod_get_contact_history writes, for every particle i, its contact count
+ * count[i] (host [N], at most ROD_HM_MAX_CONTACTS), its partners
+ * partner[i][k] (host [N][ROD_HM_MAX_CONTACTS]) and the tangential
+ * displacement of each contact seen from i, disp[i][k][3] (host
+ * [N][ROD_HM_MAX_CONTACTS][3]); entries past the count are zero. It
+ * synchronises. rod_set_contact_history installs such a history as the current
+ * level's, replacing what the context recorded there (a context created with
+ * forces_valid from a saved state records that state's contacts as new ones):
+ * the next step then continues each listed contact's displacement. Errors:
+ * ROD_E_INVALID (NULL arguments, a count outside [0, ROD_HM_MAX_CONTACTS], a
+ * partner outside [0, N) or equal to its particle, a non-finite
+ * displacement), ROD_E_STATE (the context has no Hertz-Mindlin contact),
+ * ROD_E_HIP. */
+int rod_get_contact_history(rod_ctx* c, int32_t* count, int32_t* partner, double* disp);
+int rod_set_contact_history(rod_ctx* c, const int32_t* count, const int32_t* partner,
+                            const double* disp);
 
 /* Largest `cap` of rod_contact_pairs_noalloc (its static staging holds this
  * many pairs). */

@@ -13,6 +13,7 @@ TERM_BOND, TERM_DIPOLE, TERM_ZEEMAN, TERM_CONTACT, TERM_DAMP, TERM_EXT, TERM_ALL
     1, 2, 4, 8, 16, 32, 63
 
 ROD_NOALLOC_MAX_PAIRS = 1048576  # include/rod.h
+ROD_HM_MAX_CONTACTS = 16  # include/rod.h
 
 KERNELS = ("pre", "bond", "dipole", "contact", "post", "forces", "kick")
 
@@ -32,6 +33,8 @@ class RodDesc(C.Structure):
         ("bond_damping", _P),
         ("contact_model", C.c_int32), ("contact_hm", C.c_double * 5),
         ("dipole_cutoff", C.c_double),
+        ("box", C.c_double * 3), ("ewald_alpha", C.c_double), ("ewald_rcut", C.c_double),
+        ("ewald_kmax", C.c_int32),
     ]
 
 
@@ -51,7 +54,8 @@ class RodGradients(C.Structure):
 class LbmDesc(C.Structure):
     """Mirrors lbm_desc of include/lbm.h."""
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double),
-                ("force", C.c_double * 3), ("walls_z", C.c_int32)]
+                ("force", C.c_double * 3), ("walls_z", C.c_int32),
+                ("lid_velocity", C.c_double * 2)]
 
 
 class RodError(RuntimeError):
@@ -84,6 +88,8 @@ def load():
         "rod_topology": [_P, _P, _P, _P, i32, C.POINTER(i32)],
         "rod_contact_pairs": [_P, _P, i32, C.POINTER(i32)],
         "rod_contact_pairs_noalloc": [_P, _P, i32, C.POINTER(i32)],
+        "rod_get_contact_history": [_P, _P, _P, _P],
+        "rod_set_contact_history": [_P, _P, _P, _P],
         "rod_tape_begin": [_P],
         "rod_grad": [_P, C.POINTER(RodCotangent), C.POINTER(RodGradients)],
         "rod_free": [_P],

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librodmx.so")
 SOURCES = ["rod_api.hip", "k_integrate.hip", "k_bond.hip", "k_dipole.hip", "k_contact.hip",
-           "k_forces.hip", "k_adjoint.hip", "lbm_api.hip", "k_probe.hip"]
+           "k_forces.hip", "k_adjoint.hip", "lbm_api.hip", "k_probe.hip", "k_ewald.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # Packed FP32 arithmetic stays disabled; the compiler emits scalar FP32 ops.

@@ -279,6 +279,30 @@ static int validate(const rod_desc* d) {
   }
   if (!(d->dipole_cutoff >= 0) || !std::isfinite(d->dipole_cutoff))
     return fail(ROD_E_INVALID, "dipole_cutoff must be finite and >= 0");
+  {
+    int nb = 0;
+    for (int a = 0; a < 3; ++a) {
+      if (!std::isfinite(d->box[a]) || d->box[a] < 0)
+        return fail(ROD_E_INVALID, "box lengths must be finite and >= 0");
+      nb += d->box[a] > 0;
+    }
+    if (nb != 0 && nb != 3) return fail(ROD_E_INVALID, "box: all three lengths > 0, or all 0");
+    if (nb == 3 && d->dipole_on) {
+      const double Lmin = std::min(d->box[0], std::min(d->box[1], d->box[2]));
+      if (!(d->ewald_alpha > 0) || !std::isfinite(d->ewald_alpha))
+        return fail(ROD_E_INVALID, "ewald_alpha must be finite and > 0");
+      if (!(d->ewald_rcut > 0) || !(d->ewald_rcut <= 0.5 * Lmin))
+        return fail(ROD_E_INVALID, "ewald_rcut must be in (0, min(box) / 2]");
+      if (d->ewald_kmax < 1 || d->ewald_kmax > 64)
+        return fail(ROD_E_INVALID, "ewald_kmax must be in [1, 64]");
+      if (d->contact_on)
+        return fail(ROD_E_INVALID, "a periodic box needs contact_on = 0 (contact is not periodic)");
+      if (d->dipole_cutoff > 0)
+        return fail(ROD_E_INVALID, "a periodic box takes the Ewald sum: dipole_cutoff must be 0");
+      if (d->tape_capacity > 0)
+        return fail(ROD_E_INVALID, "the Ewald sum is not differentiated: no tape with a box");
+    }
+  }
   if (d->dipole_on && d->dipole_cutoff > 0) {
     if (!d->contact_on)
       return fail(ROD_E_INVALID, "a dipole cutoff needs contact_on (it walks the contact cells)");
@@ -326,8 +350,9 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
   std::vector<DipWork> items;
   std::vector<int> mslots(M, 1), mlen(M, 0);
   int max_slots = 1;
-  // with a dipole cutoff the list walk writes slot 0 and there are no work items
-  for (int m = 0; m < M && c->d.dcut == 0.0; ++m) {
+  // with a dipole cutoff the list walk writes slot 0, and with a periodic box the
+  // Ewald sum does: there are no work items
+  for (int m = 0; m < M && c->d.dcut == 0.0 && !c->d.ew_on; ++m) {
     const int b = mrange[2 * m], e = mrange[2 * m + 1], nm = e - b;
     if (small) {
       for (int i0 = b; i0 < e; i0 += DIP_SMALL_I) {
@@ -371,8 +396,93 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
   c->d.mslots = ms;
   TRY(palloc(c, &c->d.dpart, (size_t)max_slots * 6 * N));
   c->d.dslotf = nullptr;
-  if (c->desc.precision == ROD_MIXED && c->desc.dipole_on && c->d.dcut == 0.0)
+  if (c->desc.precision == ROD_MIXED && c->desc.dipole_on && c->d.dcut == 0.0 && !c->d.ew_on)
     TRY(palloc(c, &c->d.dslotf, (size_t)max_slots * 6 * N));
+  return ROD_OK;
+}
+
+// Ewald sum of a periodic box: cells, reciprocal vectors and their weights,
+// member-aligned particle chunks, structure-factor buffers.
+static void ewald_vectors(const rod_desc* dsc, std::vector<double>* kt) {
+  const double pi = 3.14159265358979323846;
+  const double* L = dsc->box;
+  const double V = L[0] * L[1] * L[2], a = dsc->ewald_alpha;
+  const int K = dsc->ewald_kmax;
+  for (int nx = 0; nx <= K; ++nx)
+    for (int ny = -K; ny <= K; ++ny)
+      for (int nz = -K; nz <= K; ++nz) {
+        const bool half = nx > 0 || (nx == 0 && (ny > 0 || (ny == 0 && nz > 0)));
+        if (!half || nx * nx + ny * ny + nz * nz > K * K) continue;
+        const double kx = 2.0 * pi * nx / L[0], ky = 2.0 * pi * ny / L[1], kz = 2.0 * pi * nz / L[2];
+        const double k2 = kx * kx + ky * ky + kz * kz;
+        if (kt) {
+          kt->push_back(kx); kt->push_back(ky); kt->push_back(kz);
+          kt->push_back(2.0 * 4.0 * pi * dsc->mu0_4pi / V * std::exp(-k2 / (4.0 * a * a)) / k2);
+        }
+      }
+}
+static int ewald_count(const rod_desc* dsc, int nc[3], int* K, int* TC) {
+  for (int a = 0; a < 3; ++a)
+    nc[a] = (int)std::max(1.0, std::min((double)EW_MAX_NC, std::floor(dsc->box[a] / dsc->ewald_rcut)));
+  std::vector<double> kt;
+  ewald_vectors(dsc, &kt);
+  *K = (int)(kt.size() / 4);
+  std::vector<int> msz(dsc->n_members, 0);
+  for (int r = 0; r < dsc->n_rods; ++r)
+    msz[dsc->rod_member[r]] += dsc->rod_offset[r + 1] - dsc->rod_offset[r];
+  int tc = 0;
+  for (int m = 0; m < dsc->n_members; ++m) tc += (msz[m] + EW_CHUNK - 1) / EW_CHUNK;
+  *TC = tc;
+  return ROD_OK;
+}
+static int ewald_setup(rod_ctx* c, const rod_desc* dsc, const std::vector<int>& mrange) {
+  Dev& d = c->d;
+  d.ew_on = dsc->dipole_on && dsc->box[0] > 0 && dsc->box[1] > 0 && dsc->box[2] > 0;
+  if (!d.ew_on) return ROD_OK;
+  const int M = dsc->n_members, N = dsc->n_particles;
+  int K = 0, TC = 0;
+  ewald_count(dsc, d.ew_nc, &K, &TC);
+  for (int a = 0; a < 3; ++a) d.box[a] = dsc->box[a];
+  d.ew_alpha = dsc->ewald_alpha;
+  d.ew_rc = dsc->ewald_rcut;
+  d.ew_self = dsc->mu0_4pi * 4.0 * std::pow(dsc->ewald_alpha, 3) / (3.0 * std::sqrt(3.14159265358979323846));
+  const long ncell = (long)d.ew_nc[0] * d.ew_nc[1] * d.ew_nc[2];
+  if (ncell * M > (1L << 26))
+    return fail(ROD_E_INVALID, "Ewald cells: %ld per member times %d members exceeds 2^26", ncell, M);
+  d.ew_ncell = (int)ncell;
+  d.ew_K = K;
+  d.ew_TC = TC;
+  std::vector<double> kt;
+  ewald_vectors(dsc, &kt);
+  std::vector<int> chunks, coff(M + 1, 0);
+  for (int m = 0; m < M; ++m) {
+    coff[m] = (int)(chunks.size() / 3);
+    for (int b = mrange[2 * m]; b < mrange[2 * m + 1]; b += EW_CHUNK) {
+      chunks.push_back(b);
+      chunks.push_back(std::min(b + EW_CHUNK, mrange[2 * m + 1]));
+      chunks.push_back(m);
+    }
+  }
+  coff[M] = (int)(chunks.size() / 3);
+  double* kdev = nullptr;
+  int *chd = nullptr, *cod = nullptr;
+  TRY(dalloc(c, &d.ew_cnt, (size_t)M * ncell));
+  TRY(dalloc(c, &d.ew_start, (size_t)M * ncell + 1));
+  TRY(dalloc(c, &d.ew_cell, (size_t)N));
+  TRY(dalloc(c, &d.ew_slot, (size_t)N));
+  TRY(dalloc(c, &d.ew_sorted, (size_t)N));
+  TRY(dalloc(c, &d.ew_xm, 8 * (size_t)N));
+  TRY(dalloc(c, &kdev, kt.size()));
+  TRY(dalloc(c, &chd, chunks.size()));
+  TRY(dalloc(c, &cod, coff.size()));
+  TRY(dalloc(c, &d.ew_Sp, 2 * (size_t)TC * K));
+  TRY(dalloc(c, &d.ew_S, 2 * (size_t)M * K));
+  HIPC(hipMemcpy(kdev, kt.data(), kt.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(chd, chunks.data(), chunks.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(cod, coff.data(), coff.size() * sizeof(int), hipMemcpyHostToDevice));
+  d.ew_k = kdev;
+  d.ew_chunks = chd;
+  d.ew_chunk_off = cod;
   return ROD_OK;
 }
 
@@ -391,6 +501,13 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
     b += (4 * NBR_CAP + 4 + 24) * N;                                            // lists
   if (dcut) b += (4 * DNBR_CAP + 4 + 64) * N;                                   // dipole lists
   if (hm) b += (24 + 8 + 2 * HM_CAP * (4 + 24)) * N;                            // torque, contacts
+  if (d->dipole_on && d->box[0] > 0 && d->box[1] > 0 && d->box[2] > 0) {      // Ewald
+    int nc[3], K = 0, TC = 0;
+    ewald_count(d, nc, &K, &TC);
+    const size_t cells = (size_t)nc[0] * nc[1] * nc[2] * M;
+    b += 8 * cells + 4 + (4 * 3 + 64) * N + 32 * (size_t)K + 12 * (size_t)TC + 4 * (M + 1) +
+         16 * ((size_t)TC + M) * K;
+  }
   if (d->precision == ROD_MIXED && d->dipole_on) b += 48 * ((N + 63) / 64);  // chunk boxes
   if (d->bond_damping) b += 8 * 4 * R + 8 * 2 * 5 * N;                       // bond damping
   b += 8 * 18 * N + 8 * 9 * M;                                                  // energy
@@ -405,11 +522,14 @@ static int force_terms(rod_ctx* c, const Dev& d, int want_energy, int build) {
     if (c->desc.contact_on && !contact_in_forces(d))
       TIMED(c, ROD_KERNEL_CONTACT, launch_contact, d, 0, build, c->s);
     if (d.dcut > 0) TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole_cut, d, build, c->s);
+    if (d.ew_on) TIMED(c, ROD_KERNEL_DIPOLE, launch_ewald, d, c->s);
     return ROD_OK;
   }
   TIMED(c, ROD_KERNEL_BOND, launch_bond, d, c->desc.precision, want_energy, c->s);
   if (c->desc.dipole_on && d.dcut > 0)
     TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole_cut, d, build, c->s);
+  else if (d.ew_on)
+    TIMED(c, ROD_KERNEL_DIPOLE, launch_ewald, d, c->s);
   else if (c->desc.dipole_on)
     TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole, d, c->desc.precision, c->work, c->nwork, c->s);
   if (c->desc.contact_on)
@@ -514,6 +634,8 @@ static int enqueue_step_per_rod(rod_ctx* c) {
   for (int r = 0; r < R; ++r) HIPC(launch_bond(rod_dev(r), c->desc.precision, 0, c->s));
   if (c->desc.dipole_on && c->d.dcut > 0)
     for (int r = 0; r < R; ++r) HIPC(launch_dipole_cut(rod_dev(r), 1, c->s));
+  else if (c->d.ew_on)  // one periodic sum over every member (not separable by rod)
+    HIPC(launch_ewald(c->d, c->s));
   else if (c->desc.dipole_on)
     for (int r = 0; r < R; ++r)
       HIPC(launch_dipole(rod_dev(r), c->desc.precision, c->rod_work + c->rod_work_off[r],
@@ -750,6 +872,7 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
     return cleanup(rc);
   if (d.dcut > 0 && hipMemset(d.dnbr_cnt, 0, sizeof(int) * (size_t)N) != hipSuccess)
     return cleanup(fail(ROD_E_HIP, "memset failed"));
+  if ((rc = ewald_setup(c, dsc, mrange))) return cleanup(rc);
   if (d.use_lists &&
       ((rc = dalloc(c, &d.nbr, (size_t)NBR_CAP * N)) || (rc = dalloc(c, &d.nbr_cnt, (size_t)N)) ||
        (rc = dalloc(c, &d.xb, 3 * (size_t)N)) || (rc = dalloc(c, &d.rebuild, 2))))
@@ -1046,6 +1169,67 @@ int rod_contact_pairs_noalloc(rod_ctx* c, int32_t* pairs, int32_t cap, int32_t* 
   return ROD_OK;
 }
 
+// Contact history of the current level: parity h_step & 1 of the per-level
+// planes, which the level's force evaluation wrote and the next step reads.
+int rod_get_contact_history(rod_ctx* c, int32_t* count, int32_t* partner, double* disp) {
+  if (!c || !count || !partner || !disp) return fail(ROD_E_INVALID, "NULL argument");
+  if (!c->d.hm) return fail(ROD_E_STATE, "the context has no Hertz-Mindlin contact");
+  const long N = c->d.n, p = c->h_step & 1;
+  std::vector<int> cnt(N), pj((size_t)HM_CAP * N);
+  std::vector<double> ps((size_t)3 * HM_CAP * N);
+  HIPC(hipStreamSynchronize(c->s));
+  HIPC(hipMemcpy(cnt.data(), c->d.hc_cnt + p * N, sizeof(int) * N, hipMemcpyDeviceToHost));
+  HIPC(hipMemcpy(pj.data(), c->d.hc_j + p * HM_CAP * N, sizeof(int) * HM_CAP * N,
+                 hipMemcpyDeviceToHost));
+  HIPC(hipMemcpy(ps.data(), c->d.hc_s + p * 3 * HM_CAP * N, sizeof(double) * 3 * HM_CAP * N,
+                 hipMemcpyDeviceToHost));
+  for (long i = 0; i < N; ++i) {
+    const int n = std::min(std::max(cnt[i], 0), HM_CAP);
+    count[i] = n;
+    for (int k = 0; k < HM_CAP; ++k) {
+      const bool on = k < n;
+      partner[i * HM_CAP + k] = on ? pj[(size_t)k * N + i] : 0;
+      for (int a = 0; a < 3; ++a)
+        disp[(i * HM_CAP + k) * 3 + a] = on ? ps[((size_t)a * HM_CAP + k) * N + i] : 0.0;
+    }
+  }
+  return ROD_OK;
+}
+
+int rod_set_contact_history(rod_ctx* c, const int32_t* count, const int32_t* partner,
+                            const double* disp) {
+  if (!c || !count || !partner || !disp) return fail(ROD_E_INVALID, "NULL argument");
+  if (!c->d.hm) return fail(ROD_E_STATE, "the context has no Hertz-Mindlin contact");
+  const long N = c->d.n, p = c->h_step & 1;
+  std::vector<int> cnt(N), pj((size_t)HM_CAP * N, 0);
+  std::vector<double> ps((size_t)3 * HM_CAP * N, 0.0);
+  for (long i = 0; i < N; ++i) {
+    const int n = count[i];
+    if (n < 0 || n > HM_CAP)
+      return fail(ROD_E_INVALID, "count[%ld] = %d is outside [0, %d]", i, n, HM_CAP);
+    cnt[i] = n;
+    for (int k = 0; k < n; ++k) {
+      const int j = partner[i * HM_CAP + k];
+      if (j < 0 || j >= N || j == i)
+        return fail(ROD_E_INVALID, "partner[%ld][%d] = %d is not another particle", i, k, j);
+      pj[(size_t)k * N + i] = j;
+      for (int a = 0; a < 3; ++a) {
+        const double v = disp[(i * HM_CAP + k) * 3 + a];
+        if (!std::isfinite(v))
+          return fail(ROD_E_INVALID, "disp[%ld][%d] is not finite", i, k);
+        ps[((size_t)a * HM_CAP + k) * N + i] = v;
+      }
+    }
+  }
+  HIPC(hipStreamSynchronize(c->s));
+  HIPC(hipMemcpy(c->d.hc_cnt + p * N, cnt.data(), sizeof(int) * N, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(c->d.hc_j + p * HM_CAP * N, pj.data(), sizeof(int) * HM_CAP * N,
+                 hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(c->d.hc_s + p * 3 * HM_CAP * N, ps.data(), sizeof(double) * 3 * HM_CAP * N,
+                 hipMemcpyHostToDevice));
+  return ROD_OK;
+}
+
 int rod_tape_begin(rod_ctx* c) {
   if (!c) return fail(ROD_E_INVALID, "context is NULL");
   if (c->tape.capacity <= 0) return fail(ROD_E_NOTAPE, "context was created without a tape");
@@ -1205,7 +1389,7 @@ extern "C" int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, c
     int max_member = 0;
     for (size_t k = 0; k + 1 < c->mrange_h.size(); k += 2)
       max_member = std::max(max_member, c->mrange_h[k + 1] - c->mrange_h[k]);
-    if (c->desc.dipole_on && c->d.dcut == 0.0) {  // (a cutoff has no layout to choose)
+    if (c->desc.dipole_on && c->d.dcut == 0.0 && !c->d.ew_on) {  // (a cutoff or a box: no layout)
       if (max_member <= 16384) cands.push_back({1, 0});
       for (int t : {512, 1024, 2048, 4096, 8192, 16384, 32768}) cands.push_back({0, t});
     } else {
@@ -1273,7 +1457,6 @@ extern "C" int rod_lbm_cycles(rod_ctx* c, lbm_ctx* l, int32_t n_sub, int64_t n_c
   if (n_sub < 1 || n_cycles < 0) return fail(ROD_E_INVALID, "need n_sub >= 1 and n_cycles >= 0");
   if (std::fabs(c->desc.dt * n_sub - 1.0) > 1e-12)
     return fail(ROD_E_INVALID, "the rod time step times n_sub must be the lattice step 1 (dt = %g)", c->desc.dt);
-  if (l->L.walls) return fail(ROD_E_INVALID, "the coupling needs a lattice periodic in every axis");
   if (c->tape.active) return fail(ROD_E_STATE, "coupled cycles while a tape is recorded");
   if (n_cycles == 0) return ROD_OK;
   const long N = c->d.n, cells = l->L.cells;

@@ -108,6 +108,31 @@ struct Dev {
   int* dnbr;               // [DNBR_CAP][N]
   int* dnbr_cnt;           // [N]
   double* xm;              // [N][8]: x, y, z, 0, m_x, m_y, m_z, 0 of the level (cutoff), or null
+  // Periodic box with the Ewald sum of the dipoles (ew_on; k_ewald.hip): box
+  // lengths, splitting parameter, real-space cutoff, the self-field
+  // coefficient C 4 a^3 / (3 sqrt(pi)); member-major cells of side >= ew_rc,
+  // ew_nc per axis; particles sorted by cell with an interleaved copy of their
+  // wrapped positions and moments; the reciprocal vectors of the half space
+  // with their coefficients, particle chunks (sorted ranges of one member) and
+  // the partial and summed structure factors.
+  int ew_on;
+  double box[3];
+  double ew_alpha, ew_rc, ew_self;
+  int ew_nc[3];
+  int ew_ncell;            // cells per member
+  int* ew_cnt;             // [M ncell] particles per cell
+  int* ew_start;           // [M ncell + 1] first sorted position of each cell
+  int* ew_cell;            // [N] cell of each particle
+  int* ew_slot;            // [N] its place in the cell's count
+  int* ew_sorted;          // [N] particles by cell, each cell's in ascending index
+  double* ew_xm;           // [N][8] wrapped x, y, z, 0, m_x, m_y, m_z, 0 in sorted order
+  const double* ew_k;      // [K][4] k_x, k_y, k_z, 2 (4 pi C / V) exp(-k^2 / 4 a^2) / k^2
+  int ew_K;
+  const int* ew_chunks;    // [TC][3] sorted range [begin, end) of at most 256 and the member
+  const int* ew_chunk_off; // [M + 1] first chunk of each member
+  int ew_TC;
+  double* ew_Sp;           // [TC][K][2] structure factor of each chunk
+  double* ew_S;            // [M][K][2] structure factor of each member
   // Immersed-boundary penalty (set only on the copy a coupled cycle launches
   // with): fluid velocity at the particles [3][N], the penalty force of the
   // evaluation written to ibm_f [3][N], stiffness m_p * ibm_idt.
@@ -197,6 +222,11 @@ hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int n
 // rebuild them regardless of motion.
 hipError_t launch_dipole_cut(const Dev& d, int build, hipStream_t s,
                              const hipEvent_t* ev = nullptr);
+// Ewald sum of the dipoles of a periodic box (d.ew_on): writes the dipole
+// force and field to slot 0 of the FP64 partial sums.
+hipError_t launch_ewald(const Dev& d, hipStream_t s, const hipEvent_t* ev = nullptr);
+constexpr int EW_CHUNK = 256;   // particles per structure-factor chunk
+constexpr int EW_MAX_NC = 256;  // cells per box axis at most
 // build: rebuild contact candidate lists (large systems) regardless of motion.
 hipError_t launch_contact(const Dev& d, int want_energy, int build, hipStream_t s,
                           const hipEvent_t* ev = nullptr);

@@ -92,6 +92,11 @@ class RodSim:
         d.bond_damping = None if bd is None else bd.ctypes.data_as(C.c_void_p)
         d.contact_model = _CONTACT_MODEL[w.get("contact_model", "hookean")]
         d.dipole_cutoff = float(w.get("dipole_cutoff") or 0.0)
+        if w.get("box") is not None:
+            d.box = (C.c_double * 3)(*[float(a) for a in w["box"]])
+            d.ewald_alpha = float(w["ewald_alpha"])
+            d.ewald_rcut = float(w["ewald_rcut"])
+            d.ewald_kmax = int(w["ewald_kmax"])
         if w.get("contact_hm") is not None:
             d.contact_hm = (C.c_double * 5)(*[float(a) for a in w["contact_hm"]])
         self.desc = d
@@ -153,6 +158,22 @@ class RodSim:
         L.check(self.lib.rod_contact_pairs(self.ctx, out.ctypes.data_as(C.c_void_p), P,
                                            C.byref(cnt)))
         return out[:P]
+
+    def contact_history(self):
+        """rod_get_contact_history: dict(count [N], partner [N, 16], disp [N, 16, 3])."""
+        n, K = self.n, L.ROD_HM_MAX_CONTACTS
+        h = dict(count=np.zeros(n, np.int32), partner=np.zeros((n, K), np.int32),
+                 disp=np.zeros((n, K, 3)))
+        L.check(self.lib.rod_get_contact_history(self.ctx, *[h[k].ctypes.data_as(C.c_void_p)
+                                                             for k in ("count", "partner", "disp")]))
+        return h
+
+    def set_contact_history(self, h):
+        """rod_set_contact_history from a dict as contact_history returns."""
+        a = [np.ascontiguousarray(h["count"], dtype=np.int32),
+             np.ascontiguousarray(h["partner"], dtype=np.int32),
+             np.ascontiguousarray(h["disp"], dtype=np.float64)]
+        L.check(self.lib.rod_set_contact_history(self.ctx, *[v.ctypes.data_as(C.c_void_p) for v in a]))
 
     def contact_pairs_noalloc(self, cap):
         """rod_contact_pairs_noalloc: at most ``cap`` pairs (sorted) and the total count."""

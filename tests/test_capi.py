@@ -109,6 +109,20 @@ def test_query_workspace_and_invalid_descriptors():
                "outside the range of the exact contact sums"),
               (dict(contact_model=1, contact_hm=hm(1e300, 0.3, 0.5, 0, 0)),
                "outside the range of the exact contact sums")]
+    box = lambda *b: (C.c_double * 3)(*b)
+    cases += [(dict(box=box(10, 0, 10)), "all three lengths"),
+              (dict(box=box(10, -1, 10)), "box lengths"),
+              (dict(box=box(10, np.inf, 10)), "box lengths"),
+              (dict(box=box(10, 10, 10), contact_on=0, ewald_alpha=0.0, ewald_rcut=4.0,
+                    ewald_kmax=8), "ewald_alpha"),
+              (dict(box=box(10, 10, 10), contact_on=0, ewald_alpha=1.0, ewald_rcut=5.5,
+                    ewald_kmax=8), "ewald_rcut"),
+              (dict(box=box(10, 10, 10), contact_on=0, ewald_alpha=1.0, ewald_rcut=4.0,
+                    ewald_kmax=65), "ewald_kmax"),
+              (dict(box=box(10, 10, 10), ewald_alpha=1.0, ewald_rcut=4.0, ewald_kmax=8),
+               "contact is not periodic"),
+              (dict(box=box(10, 10, 10), contact_on=0, ewald_alpha=1.0, ewald_rcut=4.0,
+                    ewald_kmax=8, tape_capacity=10, tape_every=2), "not differentiated")]
     cases += [(dict(contact_model=1, contact_hm=hm(10, 0.3, np.nan, 0, 0)), "finite"),
               (dict(contact_model=1, contact_hm=hm(10, 0.3, 0.5, 0, 0), tape_capacity=10,
                     tape_every=2), "no tape with it")]
@@ -170,6 +184,24 @@ def test_contact_scales_accept_non_unit_laws():
         assert lib.rod_query_workspace(C.byref(d), C.byref(nb)) == L.ROD_OK, over
 
 
+def test_ewald_workspace():
+    """A periodic box adds its cells, sorted copies, reciprocal vectors and
+    structure factors to the workspace; without dipoles the box is not used."""
+    lib = L.load()
+    w = workloads.periodic_rods(n_rods=8, length=16)
+    d, keep = _desc(w, contact_on=0)
+    nb0 = C.c_size_t()
+    assert lib.rod_query_workspace(C.byref(d), C.byref(nb0)) == L.ROD_OK
+    box = (C.c_double * 3)(*w["box"])
+    d2, keep2 = _desc(w, contact_on=0, box=box, ewald_alpha=w["ewald_alpha"],
+                      ewald_rcut=w["ewald_rcut"], ewald_kmax=w["ewald_kmax"])
+    nb = C.c_size_t()
+    assert lib.rod_query_workspace(C.byref(d2), C.byref(nb)) == L.ROD_OK
+    assert nb.value > nb0.value + 64 * w["n"]
+    d3, keep3 = _desc(w, contact_on=0, dipole_on=0, box=box)
+    assert lib.rod_query_workspace(C.byref(d3), C.byref(nb)) == L.ROD_OK
+
+
 def test_null_context_is_rejected():
     lib = L.load()
     assert lib.rod_step(None, 1) == L.ROD_E_INVALID
@@ -194,7 +226,11 @@ def test_lbm_descriptor_checks():
     lib = L.load()
     dummy = C.c_void_p(16)  # never dereferenced: validation fails first
     for over, msg in ((dict(nx=0), "nx"), (dict(tau=0.5), "tau"), (dict(tau=float("nan")), "tau"),
-                      (dict(walls_z=2), "walls_z"), (dict(nx=2048, ny=2048, nz=1024), "2^31")):
+                      (dict(walls_z=3), "walls_z"), (dict(walls_z=-1), "walls_z"),
+                      (dict(lid_velocity=(C.c_double * 2)(0.01, 0.0)), "lid velocity"),
+                      (dict(walls_z=2, lid_velocity=(C.c_double * 2)(0.0, 0.01)), "lid velocity"),
+                      (dict(walls_z=1, lid_velocity=(C.c_double * 2)(np.nan, 0.0)), "lid_velocity"),
+                      (dict(nx=2048, ny=2048, nz=1024), "2^31")):
         d = L.LbmDesc()
         d.nx, d.ny, d.nz, d.tau, d.walls_z = 4, 4, 4, 0.8, 0
         for k, v in over.items():

@@ -57,7 +57,7 @@ import numpy as np
 
 __all__ = ["make", "CONFIGS", "straight_rods", "cilia_carpet", "rod_array",
            "ensemble", "adjoint_rod", "cantilever", "twisted_rod", "magnetic_helix",
-           "helix_ramp_fields"]
+           "helix_ramp_fields", "coiled_rods", "periodic_rods"]
 
 
 def _field_const(n_members, b0, g=None, length=1):
@@ -297,6 +297,73 @@ def helix_ramp_fields(w, lams):
 
 
 # Full-size workloads (name -> builder with defaults).
+def coiled_rods(n=400, members=2, pitch=0.8, radius=1.5, seed=21, m=0.04, sigma=1e-3, **kw):
+    """Clamped rods wound on a tight helix whose turns lie closer than the contact
+    distance, one rod per member: many contacts from the first step."""
+    lam = 1.0 / np.hypot(radius, pitch / (2 * np.pi))
+    ph = np.arange(n) * lam
+    turn = np.stack([radius * np.cos(ph), radius * np.sin(ph), pitch * ph / (2 * np.pi)], 1)
+    x, off, mem = straight_rods([n] * members, [(0.0, 0.0, 0.0)] * members, (1.0, 0.0, 0.0),
+                                member=np.arange(members))
+    x = np.tile(turn, (members, 1))
+    bc = np.zeros(n * members, np.int8)
+    bc[off[:-1]] = 1
+    w = _base(x, off, mem, np.tile([1.0, 1.0, 1.0, 0.5], (members, 1)),
+              np.tile([0.0, 0.0, m], (n * members, 1)), bc,
+              _field_const(members, (0.1, 0.3, -0.2)), contact_on=True, precision="mixed",
+              name=f"coiled_rods_{members}x{n}")
+    w.update(kw)
+    return _perturb(w, np.random.default_rng(seed), sigma)
+
+
+def periodic_rods(n_rods=12, length=20, box=(14.0, 16.0, 18.0), members=1, seed=8, m=0.05,
+                  rcut=None, alpha=None, kmax=None, sigma=1e-3, **kw):
+    """Straight rods of ``length`` particles at random positions and directions
+    in a periodic box (some reaching out of it: positions are not wrapped),
+    dipoles along each rod, ``members`` independent copies' worth of rods per
+    member, no contact. Ewald parameters: rcut half the smallest box length,
+    alpha = 3.6 / rcut and kmax = ceil(3.6 alpha max(L) / pi) unless given
+    (both truncated tails near exp(-13))."""
+    rng = np.random.default_rng(seed)
+    L = np.asarray(box, dtype=np.float64)
+    R = n_rods * members
+    pts, offs, dirs = [], [0], []
+    for r in range(R):
+        # rods of one member are placed at least 1.2 apart (periodic images
+        # included) so that no two particles start overlapping
+        first = (r // n_rods) * n_rods
+        placed = np.concatenate(pts[first:], 0) if r > first else np.zeros((0, 3))
+        for _ in range(1000):
+            o = rng.uniform(0.0, 1.0, 3) * L
+            u = rng.normal(size=3)
+            u /= np.linalg.norm(u)
+            c = o[None, :] + np.arange(length, dtype=np.float64)[:, None] * u[None, :]
+            if not len(placed):
+                break
+            dd = c[:, None, :] - placed[None, :, :]
+            dd -= L * np.rint(dd / L)
+            if np.min(np.sum(dd * dd, -1)) >= 1.44:
+                break
+        else:
+            raise ValueError("periodic_rods: no room for another rod; use a larger box")
+        pts.append(c)
+        dirs.append(u)
+        offs.append(offs[-1] + length)
+    x = np.concatenate(pts, 0)
+    n = x.shape[0]
+    mb = m * np.repeat(np.asarray(dirs), length, axis=0)  # along each rod
+    mem = np.repeat(np.arange(members, dtype=np.int32), n_rods)
+    rc = 0.5 * float(L.min()) if rcut is None else float(rcut)
+    a = 3.6 / rc if alpha is None else float(alpha)
+    km = int(np.ceil(3.6 * a * float(L.max()) / np.pi)) if kmax is None else int(kmax)
+    w = _base(x, np.asarray(offs, np.int32), mem, np.tile([1.0, 1.0, 1.0, 0.5], (R, 1)), mb,
+              np.zeros(n, np.int8), _field_const(members, (0.0, 0.2, 0.1)), contact_on=False,
+              box=L, ewald_alpha=a, ewald_rcut=rc, ewald_kmax=km, precision="fp64",
+              steps=1000, name=f"periodic_rods_{R}x{length}")
+    w.update(kw)
+    return _perturb(w, rng, sigma)
+
+
 CONFIGS = {
     "cantilever": cantilever,       # 20 particles, FP64, 1000 steps
     "twisted_rod": twisted_rod,     # N = 4096, contact + dipoles, 2e4 steps
