@@ -6,8 +6,9 @@
 // population to the neighbouring cell along its direction: for each direction
 // consecutive threads write consecutive addresses, so the writes stay as
 // coalesced as the reads. At a bounce-back wall the population comes back
-// reversed at its own cell. 304 bytes move per cell update, 19 doubles in and
-// 19 out; the kernel is bound by HBM bandwidth.
+// reversed at its own cell (less the moving lid's momentum term), at a
+// free-slip wall with its z component reversed. 304 bytes move per cell update,
+// 19 doubles in and 19 out; the kernel is bound by HBM bandwidth.
 #include "rod.h"
 #include "lbm.h"
 #include "lbm_internal.h"
@@ -36,6 +37,11 @@ __device__ __forceinline__ constexpr int CZ(int i) {
 }
 __device__ __forceinline__ constexpr int OPP(int i) {
   constexpr int v[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+  return v[i];
+}
+// The direction with the z component reversed (specular reflection).
+__device__ __forceinline__ constexpr int FLIPZ(int i) {
+  constexpr int v[19] = {0, 1, 2, 3, 4, 6, 5, 7, 8, 9, 10, 13, 14, 11, 12, 17, 18, 15, 16};
   return v[i];
 }
 
@@ -75,8 +81,13 @@ __global__ __launch_bounds__(256) void k_lbm(Lattice L, const double* __restrict
     const double feq = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
     const double fs = f[i] - omega * (f[i] - feq) + pre * w * (3.0 * (cg - ug) + 9.0 * cu * cg);
     int zd = z + CZ(i);
-    if (L.walls && (zd < 0 || zd >= L.nz)) {  // halfway bounce-back: reversed, at this cell
-      dst[OPP(i) * L.cells + c] = fs;
+    if (L.walls && (zd < 0 || zd >= L.nz)) {
+      if (zd >= L.nz && L.walls == 2) {  // free-slip top: z reversed, at this cell
+        dst[FLIPZ(i) * L.cells + c] = fs;
+      } else {  // halfway bounce-back, less 6 w rho (c . lid) at a moving top wall
+        const double mv = zd >= L.nz ? 6.0 * w * rho * (CX(i) * L.lidx + CY(i) * L.lidy) : 0.0;
+        dst[OPP(i) * L.cells + c] = fs - mv;
+      }
       continue;
     }
     zd = (zd + L.nz) % L.nz;
@@ -115,14 +126,21 @@ __device__ __forceinline__ double peskin4(double r) {
 // the particle's wave takes x offset k & 3, y offset (k >> 2) & 3, z offset
 // k >> 4 from floor - 1, so the 64 lanes of a wave touch 64 distinct nodes.
 // Returns the node's cell index (wrapped periodically) and its weight
-// (phi_z phi_y) phi_x.
+// (phi_z phi_y) phi_x. With walls in z a node beyond them takes no part: its
+// weight is 0 (and its index clamped into the lattice).
 __device__ __forceinline__ long stencil_node(const Lattice& L, double x, double y, double z, int k,
                                              double& w) {
   const int ox = k & 3, oy = (k >> 2) & 3, oz = k >> 4;
   const int nx = (int)floor(x) - 1 + ox, ny = (int)floor(y) - 1 + oy, nz = (int)floor(z) - 1 + oz;
   w = peskin4((double)nz - z) * peskin4((double)ny - y) * peskin4((double)nx - x);
-  const int ix = ((nx % L.nx) + L.nx) % L.nx, iy = ((ny % L.ny) + L.ny) % L.ny,
-            iz = ((nz % L.nz) + L.nz) % L.nz;
+  const int ix = ((nx % L.nx) + L.nx) % L.nx, iy = ((ny % L.ny) + L.ny) % L.ny;
+  int iz;
+  if (L.walls) {
+    if (nz < 0 || nz >= L.nz) w = 0.0;
+    iz = nz < 0 ? 0 : (nz >= L.nz ? L.nz - 1 : nz);
+  } else {
+    iz = ((nz % L.nz) + L.nz) % L.nz;
+  }
   return ((long)iz * L.ny + iy) * L.nx + ix;
 }
 
@@ -163,6 +181,7 @@ __global__ __launch_bounds__(256) void k_ibm_spread(Lattice L, const double* __r
   const int k = (int)(t & 63);
   double w;
   const long c = stencil_node(L, X[p], X[n + p], X[2 * n + p], k, w);
+  if (w == 0.0) return;  // outside the support, or beyond a wall
   const double fx = -scale * F[p], fy = -scale * F[n + p], fz = -scale * F[2 * n + p];
   unsafeAtomicAdd(&g[c], fx * w);
   unsafeAtomicAdd(&g[L.cells + c], fy * w);
@@ -246,10 +265,14 @@ int lbm_init(lbm_ctx** out, const lbm_desc* d, const double* f0, void* hip_strea
   if (!(d->tau > 0.5) || !std::isfinite(d->tau)) return lfail(ROD_E_INVALID, "tau must be > 1/2");
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(d->force[k])) return lfail(ROD_E_INVALID, "force must be finite");
-  if (d->walls_z != 0 && d->walls_z != 1) return lfail(ROD_E_INVALID, "walls_z must be 0 or 1");
+  if (d->walls_z < 0 || d->walls_z > 2) return lfail(ROD_E_INVALID, "walls_z must be 0, 1 or 2");
+  if (!std::isfinite(d->lid_velocity[0]) || !std::isfinite(d->lid_velocity[1]))
+    return lfail(ROD_E_INVALID, "lid_velocity must be finite");
+  if ((d->lid_velocity[0] != 0.0 || d->lid_velocity[1] != 0.0) && d->walls_z != 1)
+    return lfail(ROD_E_INVALID, "a lid velocity needs walls_z = 1 (a no-slip top wall)");
   lbm_ctx* c = new lbm_ctx();
   c->L = Lattice{d->nx, d->ny, d->nz, d->walls_z, cells, d->tau, d->force[0], d->force[1],
-                 d->force[2], nullptr};
+                 d->force[2], nullptr, d->lid_velocity[0], d->lid_velocity[1]};
   c->s = (hipStream_t)hip_stream;
   const size_t bytes = 19 * sizeof(double) * (size_t)cells;
   hipError_t e = hipMalloc(&c->f[0], bytes);

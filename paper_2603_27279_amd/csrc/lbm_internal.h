@@ -6,10 +6,12 @@
 namespace lbmx {
 
 struct Lattice {
-  int nx, ny, nz, walls;
+  int nx, ny, nz;
+  int walls;             // 0 periodic in z; 1 no-slip walls in z; 2 no-slip bottom, free-slip top
   long cells;
   double tau, gx, gy, gz;
   const double* gfield;  // [3][cells] force density added to the uniform one, or null
+  double lidx, lidy;     // velocity of the top wall (walls == 1)
 };
 
 }  // namespace lbmx

@@ -18,9 +18,12 @@ class Lattice:
 
     ``f0``: initial populations [19, nz, ny, nx] (numpy or a device tensor);
     ``tau``: relaxation time; ``force``: uniform body force density;
-    ``walls_z``: halfway bounce-back walls below z = 0 and above nz - 1."""
+    ``walls_z``: 0 (or False) periodic in z; 1 (or True) no-slip walls below
+    z = 0 and above nz - 1; 2 a no-slip bottom and a free-slip top;
+    ``lid``: (u_x, u_y) of a moving top wall (walls_z = 1)."""
 
-    def __init__(self, f0, tau, force=(0.0, 0.0, 0.0), walls_z=False, device="cuda"):
+    def __init__(self, f0, tau, force=(0.0, 0.0, 0.0), walls_z=False, lid=(0.0, 0.0),
+                 device="cuda"):
         import torch
         self.torch = torch
         self.lib = L.load()
@@ -33,7 +36,8 @@ class Lattice:
         d.nx, d.ny, d.nz = nx, ny, nz
         d.tau = float(tau)
         d.force = (C.c_double * 3)(*[float(g) for g in force])
-        d.walls_z = int(bool(walls_z))
+        d.walls_z = int(walls_z)
+        d.lid_velocity = (C.c_double * 2)(*[float(v) for v in lid])
         self.desc = d
         self.device = f0.device
         self.stream = torch.cuda.current_stream(self.device)

@@ -1,8 +1,10 @@
 """Immersed-boundary coupling of rods and lattice (rod_lbm_cycles) against the
 FP64 oracle's coupled driver: rod states and populations after several cycles,
 for both force launch forms, a carpet of rods spanning many blocks with
-positions that wrap around the periodic lattice, conservation of rods' plus
-fluid momentum over many cycles, and the argument checks."""
+positions that wrap around the periodic lattice, a carpet of cilia on
+clamped bases with a driven tip in a turning field (periodic, between no-slip
+walls, one of them moving, and under a free-slip top), conservation of rods'
+plus fluid momentum over many cycles, and the argument checks."""
 import numpy as np
 import pytest
 
@@ -34,10 +36,11 @@ def fluid(shape, seed, amp=0.005):
     return lbm.equilibrium(1 + 0.01 * rng.random(shape), amp * rng.normal(size=(3,) + shape))
 
 
-def run_gpu(w, f0, ncycles, nsub, tau, g=(0.0, 0.0, 0.0), mode="batched", prec="fp64"):
+def run_gpu(w, f0, ncycles, nsub, tau, g=(0.0, 0.0, 0.0), mode="batched", prec="fp64",
+            walls=0, lid=(0.0, 0.0)):
     sim = RodSim(w, precision=prec)
     sim.launch_mode(mode)
-    lat = Lattice(f0, tau=tau, force=g)
+    lat = Lattice(f0, tau=tau, force=g, walls_z=walls, lid=lid)
     sim.lbm_cycles(lat, nsub, ncycles)
     sim.sync()
     st = sim.state()
@@ -46,8 +49,9 @@ def run_gpu(w, f0, ncycles, nsub, tau, g=(0.0, 0.0, 0.0), mode="batched", prec="
     return st, f
 
 
-def compare(st, f, w, f0, ncycles, nsub, tau, g=(0.0, 0.0, 0.0), prec="fp64", ftol=1e-13):
-    ost, of = lbm.coupled(w, f0, ncycles, nsub, tau, g=g)
+def compare(st, f, w, f0, ncycles, nsub, tau, g=(0.0, 0.0, 0.0), prec="fp64", ftol=1e-13,
+            walls=0, lid=(0.0, 0.0)):
+    ost, of = lbm.coupled(w, f0, ncycles, nsub, tau, g=g, walls=walls, lid=lid)
     assert st["step"] == ncycles * nsub
     motion = np.max(np.abs(ost["x"] - w["x0"]))
     assert np.max(np.abs(st["x"] - ost["x"])) / motion <= TRAJ_TOL[prec]
@@ -55,7 +59,8 @@ def compare(st, f, w, f0, ncycles, nsub, tau, g=(0.0, 0.0, 0.0), prec="fp64", ft
         assert rel_inf(st[k], ost[k]) <= TRAJ_TOL[prec], (k, rel_inf(st[k], ost[k]))
     # populations ~ w_i rho: absolute agreement to rounding of the spread sums
     assert np.max(np.abs(f - of)) <= ftol, np.max(np.abs(f - of))
-    assert np.max(np.abs(of - lbm.run(f0, ncycles, tau, g=g))) > 1e-9  # the rods moved the fluid
+    # the rods moved the fluid
+    assert np.max(np.abs(of - lbm.run(f0, ncycles, tau, g=g, walls=walls, lid=lid))) > 1e-9
 
 
 @pytest.mark.parametrize("mode", ["batched", "separate"])
@@ -148,10 +153,57 @@ def test_argument_checks():
     with pytest.raises(RodError) as e:
         sim.lbm_cycles(lat, 0, 1)
     assert e.value.code == ROD_E_INVALID
-    walls = Lattice(f0, tau=0.8, walls_z=True)
-    with pytest.raises(RodError) as e:
-        sim.lbm_cycles(walls, 4, 1)
-    assert e.value.code == ROD_E_INVALID
     sim.lbm_cycles(lat, 4, 0)  # nothing to do
     assert sim.state()["step"] == 0
-    sim.free(); lat.free(); walls.free()
+    sim.free(); lat.free()
+
+
+def carpet(nsub, seed, bottom=1.2):
+    """A 3 x 3 carpet of cilia (6 to 10 particles, lattice units) standing on
+    clamped bases near the bottom wall, the middle one's tip driven (turned
+    about z), with velocities on the fixed particles that the coupling must
+    ignore, in a field turning in the x-z plane (a table of 8 rows)."""
+    rng = np.random.default_rng(seed)
+    lens = list(rng.integers(6, 11, 9))
+    origins = [(3.0 + 2.5 * (r % 3), 3.5 + 2.5 * (r // 3), bottom) for r in range(9)]
+    x, off, mem = workloads.straight_rods(lens, origins, (0, 0, 1))
+    n = x.shape[0]
+    bc = np.zeros(n, np.int8)
+    bc[off[:-1]] = 1
+    bc[off[5] - 1] = 2  # tip of rod 4
+    ph = 2 * np.pi * np.arange(8) / 8
+    field = np.zeros((8, 1, 12))
+    field[:, 0, 0], field[:, 0, 2] = 0.3 * np.cos(ph), 0.3 * np.sin(ph)
+    w = workloads._base(x, off, mem, np.tile([1.0, 1, 1, 0.5], (9, 1)),
+                        np.tile([0, 0, 0.05], (n, 1)), bc, field, damping=0.0, dt=1.0 / nsub,
+                        drive_axis=np.array([0.0, 0.0, 1.0]), drive_period=40, precision="fp64")
+    w["x0"] = x + rng.normal(0, 0.02, x.shape) * (bc == 0)[:, None]
+    w["v0"] = 0.01 * rng.normal(size=(n, 3))  # fixed particles' velocities included
+    return w
+
+
+@pytest.mark.parametrize("walls,lid", [(1, (0.0, 0.0)), (1, (0.002, 0.0)), (2, (0.0, 0.0))])
+def test_carpet_between_walls(walls, lid):
+    """Cilia on clamped bases 1.2 lattice units above a no-slip bottom (their
+    stencils reach past it), a driven tip and a turning field: in a channel
+    with no-slip walls (one of them moving), and under a free-slip top (the
+    paper's cilia pumping box)."""
+    nsub, tau = 4, 0.8
+    w = carpet(nsub, 21)
+    f0 = fluid((12, 12, 14), 22)
+    st, f = run_gpu(w, f0, 3, nsub, tau, walls=walls, lid=lid)
+    fixed = w["bc"] != 0
+    np.testing.assert_array_equal(st["x"][w["bc"] == 1], w["x0"][w["bc"] == 1])
+    assert np.all(st["v"][fixed] == 0)
+    compare(st, f, w, f0, 3, nsub, tau, walls=walls, lid=lid)
+
+
+def test_carpet_in_a_periodic_lattice_with_fixed_particles():
+    """The same carpet in a lattice periodic in every axis (its stencils wrap
+    to the top): clamped and driven particles carry the penalty force of
+    their stored velocity into the fluid as the oracle's coupled run does."""
+    nsub, tau = 4, 0.8
+    w = carpet(nsub, 23, bottom=0.6)
+    f0 = fluid((12, 12, 14), 24)
+    st, f = run_gpu(w, f0, 3, nsub, tau)
+    compare(st, f, w, f0, 3, nsub, tau)

@@ -141,3 +141,80 @@ def test_coupled_cycle_conserves_momentum():
     q1, pf1, pr1 = Q(st, f1)
     np.testing.assert_allclose(q1, q0, rtol=0, atol=1e-13 * np.abs(pf0).sum())
     assert np.max(np.abs(pr1 - pr0)) > 1e-4 * np.max(np.abs(pr0))
+
+
+def test_half_channel_poiseuille_under_a_free_slip_top():
+    """No-slip bottom at z = -1/2, free-slip top at z = nz - 1/2 (walls = 2):
+    specular reflection at the top makes the lattice the lower half of a
+    bounce-back channel of height 2 nz mirrored about z = nz - 1/2, so the
+    steady profile is u(z) = g / (2 nu) (z + 1/2) (2 nz - 1/2 - z), exact at
+    tau = 1/2 + sqrt(3/16) as for the full channel; its shear vanishes at the
+    top plane."""
+    nz = 8
+    tau = 0.5 + np.sqrt(3.0 / 16.0)
+    nu = (tau - 0.5) / 3
+    gx = 1e-6
+    f = lbm.equilibrium(np.ones((nz, 2, 2)), np.zeros((3, nz, 2, 2)))
+    out = lbm.run(f, 20000, tau, g=(gx, 0, 0), walls=2)
+    _, u = lbm.moments(out, (gx, 0, 0))
+    zz = np.arange(nz)
+    want = gx / (2 * nu) * (zz + 0.5) * (2 * nz - 0.5 - zz)
+    np.testing.assert_allclose(u[0, :, 0, 0], want, rtol=1e-8)
+    # the full channel of height 2 nz gives the same lower half, population by population
+    f2 = lbm.equilibrium(np.ones((2 * nz, 2, 2)), np.zeros((3, 2 * nz, 2, 2)))
+    full = lbm.run(f2, 300, tau, g=(gx, 0, 0), walls=1)
+    half = lbm.run(f, 300, tau, g=(gx, 0, 0), walls=2)
+    np.testing.assert_allclose(half, full[:, :nz], rtol=1e-13, atol=1e-19)
+
+
+def test_free_slip_top_keeps_mass():
+    """Both walls of walls = 2 send every population back into the lattice,
+    so mass is exact from a random non-equilibrium state."""
+    rng = np.random.default_rng(6)
+    shape = (6, 4, 5)
+    f = lbm.equilibrium(1 + 0.05 * rng.random(shape), 0.02 * rng.normal(size=(3,) + shape))
+    out = lbm.run(f, 40, tau=0.9, walls=2)
+    assert abs(out.sum() - f.sum()) <= 1e-12 * f.sum()
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.3])
+def test_couette_flow_under_a_moving_lid(tau):
+    """No-slip walls with the top one moving at U along x (walls = 1, lid):
+    the steady profile is linear, u(z) = U (z + 1/2) / nz, for any tau (the
+    moving halfway bounce-back wall reproduces a linear profile exactly)."""
+    nz, U = 10, 1e-3
+    f = lbm.equilibrium(np.ones((nz, 2, 2)), np.zeros((3, nz, 2, 2)))
+    out = lbm.run(f, 12000, tau, walls=1, lid=(U, 0.0))
+    _, u = lbm.moments(out, (0, 0, 0))
+    zz = np.arange(nz)
+    np.testing.assert_allclose(u[0, :, 0, 0], U * (zz + 0.5) / nz, rtol=1e-9)
+    np.testing.assert_allclose(u[2], 0.0, atol=1e-10 * U)
+
+
+def test_stencil_at_walls():
+    """With walls in z the stencil drops the nodes beyond them: away from the
+    walls (z in [2, nz - 3]) interpolation and spreading are the periodic
+    ones; near a wall a uniform field interpolates to itself times the weight
+    left inside, and a spread force keeps that share of its total."""
+    rng = np.random.default_rng(7)
+    shape = (9, 8, 10)
+    U0 = np.array([0.01, -0.02, 0.03])
+    u = U0.reshape(3, 1, 1, 1) * np.ones((3,) + shape)
+    for z in (2.0, 3.7, 5.9):
+        X = np.array([rng.uniform(0, 10), rng.uniform(0, 8), z])
+        F = rng.normal(size=(1, 3))
+        np.testing.assert_array_equal(lbm.spread(F, X[None], shape, walls=1),
+                                      lbm.spread(F, X[None], shape))
+        np.testing.assert_array_equal(lbm.interpolate(u, X[None], walls=1),
+                                      lbm.interpolate(u, X[None]))
+    for z in (-0.3, 0.4, 0.9, 7.5, 8.2):
+        X = np.array([rng.uniform(0, 10), rng.uniform(0, 8), z])
+        _, W = lbm.stencil(X, shape, walls=1)
+        inside = W.sum()
+        zz = np.floor(z) - 1 + np.arange(4)
+        want = np.sum(lbm.peskin4(zz - z) * ((zz >= 0) & (zz < 9)))
+        assert inside == pytest.approx(want, abs=1e-15) and inside < 1.0
+        np.testing.assert_allclose(lbm.interpolate(u, X[None], walls=1), inside * U0[None], rtol=1e-13)
+        F = rng.normal(size=(1, 3))
+        g = lbm.spread(F, X[None], shape, walls=1)
+        np.testing.assert_allclose(g.reshape(3, -1).sum(1), inside * F[0], rtol=1e-12)
