@@ -167,6 +167,54 @@ def test_restart_starts_contacts_afresh():
     a.free(); b.free()
 
 
+def test_restart_carries_the_contact_history():
+    """rod_get_contact_history at step 20 matches the oracle's continued state
+    (partners and tangential displacements); a context started from the saved
+    state with that history installed (rod_set_contact_history) runs 15 more
+    steps as the uncut 35-step run, to the rounding of the quaternion
+    renormalisation rod_init applies (without the history forces differ by
+    about 30% after those steps), and as the oracle's run continued from its
+    own step-20 state."""
+    w = hertz_mindlin(spheres())
+    a = RodSim(w, precision="fp64")
+    a.step(20)
+    s = a.state()
+    h = a.contact_history()
+    o20 = oracle.run(w, 20)
+    assert np.sum(h["count"]) > 10
+    np.testing.assert_array_equal(h["count"], o20["hc_cnt"])
+    scale = max(np.max(np.abs(o20["hc_s"])), 1e-300)
+    for i in range(w["n"]):
+        mine = {int(j): h["disp"][i, k] for k, j in enumerate(h["partner"][i, :h["count"][i]])}
+        theirs = {int(j): o20["hc_s"][i, k] for k, j in enumerate(o20["hc_j"][i, :o20["hc_cnt"][i]])}
+        assert mine.keys() == theirs.keys(), i
+        for j in mine:
+            assert np.max(np.abs(mine[j] - theirs[j])) <= 1e-9 * scale, (i, j)
+    assert np.any(np.abs(h["disp"]) > 0)  # sliding contacts carry a displacement
+    a.step(15)
+    uncut = a.state()
+    w2 = dict(w, x0=s["x"], v0=s["v"], q0=s["q"], w0=s["w"])
+    b = RodSim(w2, precision="fp64", step0=20, forces=(s["F"], s["T"]))
+    b.set_contact_history(h)
+    b.step(15)
+    g = b.state()
+    motion = np.max(np.abs(uncut["x"] - s["x"]))
+    assert np.max(np.abs(g["x"] - uncut["x"])) <= 1e-12 * motion
+    for k in ("v", "q", "w", "F", "T"):
+        assert rel_inf(g[k], uncut[k]) <= 1e-12, (k, rel_inf(g[k], uncut[k]))
+    o = oracle.run(w, 15, state=o20)
+    motion = np.max(np.abs(o["x"] - o20["x"]))
+    assert np.max(np.abs(g["x"] - o["x"])) / motion <= TRAJ_TOL["fp64"]
+    for k in ("v", "w", "F", "T"):
+        assert rel_inf(g[k], o[k]) <= TRAJ_TOL["fp64"], k
+    # bad histories are refused on the host
+    bad = dict(h, count=h["count"].copy())
+    bad["count"][0] = 17
+    with pytest.raises(RodError):
+        b.set_contact_history(bad)
+    a.free(); b.free()
+
+
 def test_large_system_uses_the_cell_walk():
     """Above the lane-parallel search size (70,000 particles) the Hertz-Mindlin
     search walks the cells in its own launch: forces at the initial level and
