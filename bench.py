@@ -410,6 +410,52 @@ def ibm_leg(grid=16, nsub=10, cycles=20, shape=(96, 128, 128)):
             "particle_steps_per_s": n * nsub / (us * 1e-6), "mlups": cells / us}
 
 
+def ewald_leg(grid=32, length=32, box=(64.0, 64.0, 40.0), rcut=16.0, steps=20):
+    """Rods in a periodic box with the Ewald sum of their dipoles: the rod array
+    at 32 x 32 rods of 32 particles (32,768) at pitch 2, without contact, in a
+    64 x 64 x 40 box (the lateral pitch continues across the boundary), real-
+    space cutoff 16 (4 cells per axis in x and y), alpha = 3.6 / rcut and kmax
+    = ceil(3.6 alpha max(L) / pi) (both truncated tails near exp(-13)). Whole
+    steps replayed from a graph, and the Ewald part of a step (its ten
+    launches, bracketed by events) on its own."""
+    import torch
+    import workloads
+    from paper_2603_27279_amd import RodSim
+    w = workloads.rod_array(grid=(grid, grid), n_per_rod=length, pitch=2.0, contact_on=False)
+    alpha = 3.6 / rcut
+    w.update(box=np.asarray(box, float), ewald_rcut=rcut, ewald_alpha=alpha,
+             ewald_kmax=int(np.ceil(3.6 * alpha * max(box) / np.pi)))
+    n = w["n"]
+    sim = RodSim(w, precision="mixed", graph_steps=steps)
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    sim.timing(True)
+    sim.step(5)
+    kt = sim.kernel_times()
+    sim.timing(False)
+    sim.free()
+    ew_ms = kt["dipole"][0] / kt["dipole"][1]
+    rho = n / float(np.prod(box))
+    kmax = w["ewald_kmax"]
+    nk = sum(1 for a in range(0, kmax + 1) for b in range(-kmax, kmax + 1)
+             for c in range(-kmax, kmax + 1)
+             if (a > 0 or (a == 0 and (b > 0 or (b == 0 and c > 0)))) and a * a + b * b + c * c <= kmax * kmax)
+    return {"workload": f"{grid}x{grid} rods x {length} particles in a periodic "
+                        f"{box[0]:g} x {box[1]:g} x {box[2]:g} box, Ewald sum (rcut {rcut:g}, "
+                        f"alpha {alpha:.4f}, kmax {kmax}), mixed precision rods",
+            "particles": n, "ms_per_step": ms, "particle_steps_per_s": n / (ms * 1e-3),
+            "ewald_ms_per_evaluation": ew_ms,
+            "real_space_pairs_per_particle": 4.0 / 3.0 * np.pi * rcut ** 3 * rho,
+            "reciprocal_vectors_half_space": nk,
+            "reciprocal_terms_per_s": 2.0 * nk * n / (ew_ms * 1e-3)}
+
+
 def copy_bandwidth(mib=512, reps=20):
     """What a plain device-to-device copy reaches on this GPU (bytes read plus
     bytes written per second, median of `reps` launches): the practical ceiling
@@ -473,6 +519,80 @@ def helix_loop(gamma, ke_tol=1e-9, max_steps=200_000, check_every=2000, dlam=0.1
             "contract_lambda_m": float(up[::-1][jump_down]),
             "total_steps": int(sum(steps)), "wall_s": wall,
             "us_per_step": 1e6 * wall / max(1, sum(steps))}
+
+
+TERMS = (("bond", 1), ("dipole", 2), ("zeeman", 4), ("contact", 8), ("damping", 16),
+         ("total", 63))
+
+
+def _member0(w):
+    """The first member of an ensemble workload as a workload of its own (its
+    rods, particles and field column; no arithmetic)."""
+    off = np.asarray(w["rod_offset"])
+    mem = np.asarray(w["rod_member"])
+    R = int(np.count_nonzero(mem == 0))
+    n = int(off[R])
+    v = dict(w)
+    v.update(n=n, rod_offset=off[:R + 1].copy(), rod_member=mem[:R].copy(), n_members=1,
+             rod_params=np.asarray(w["rod_params"])[:R].copy(),
+             field=np.ascontiguousarray(np.asarray(w["field"])[:, :1, :]))
+    for k in ("x_ref", "x0", "v0", "w0", "q0", "m_body", "bc"):
+        v[k] = np.asarray(w[k])[:n].copy()
+    v["name"] = w["name"] + "_member0"
+    return v
+
+
+def error_table(steps=100):
+    """Error of the GPU path against the FP64 oracle per quantity, on both
+    paths: ||dF||_inf / ||F||_inf and ||dT||_inf / ||T||_inf of each force term
+    alone and of their sum, at the initial level and at the GPU's state after
+    `steps` steps (both sides evaluating the same state); and after `steps`
+    steps of each side, x relative to the motion ||x_T - x_0||_inf, q relative
+    to its change ||q_T - q_0||_inf, and v, w, F, T relative to their own
+    ||.||_inf. Terms whose reference is zero are reported as null."""
+    import workloads
+    from paper_2603_27279_amd import RodSim
+    import oracle
+
+    def rel(a, b):
+        den = float(np.max(np.abs(b))) if b.size else 0.0
+        return None if den == 0.0 else float(np.max(np.abs(a - b))) / den
+
+    cases = [("cantilever", workloads.cantilever()),
+             ("twisted_rod", workloads.twisted_rod()),
+             ("adjoint_rod", workloads.adjoint_rod()),
+             ("cilia_carpet_2x2", workloads.cilia_carpet(grid=(2, 2))),
+             ("ensemble_member0", _member0(workloads.ensemble())),
+             ("coiled_rods", workloads.coiled_rods()),
+             ("periodic_rods", workloads.periodic_rods(n_rods=8, length=16))]
+    out = {}
+
+    def per_term(sim, w, g, row, tag):
+        # each force term alone at the given state (the GPU's own), both sides
+        for term, mask in TERMS:
+            Fo, To = oracle.forces(w, g["x"], g["q"], g["v"], g["w"], mask=mask, step=g["step"])
+            F, T = sim.eval_forces(mask)
+            row[f"{tag}F_{term}"] = rel(F.cpu().numpy().T, Fo)
+            row[f"{tag}T_{term}"] = rel(T.cpu().numpy().T, To)
+
+    for name, w in cases:
+        stT = oracle.run(w, steps)
+        for prec in ("fp64", "mixed"):
+            sim = RodSim(w, precision=prec)
+            row = {"n_particles": int(w["n"])}
+            per_term(sim, w, sim.state(), row, "")
+            sim.step(steps)
+            sim.sync()
+            g = sim.state()
+            per_term(sim, w, g, row, f"step{steps}_")
+            sim.free()
+            row["x"] = rel(g["x"] - w["x0"], stT["x"] - w["x0"])
+            row["q"] = rel(g["q"] - w["q0"], stT["q"] - w["q0"])
+            for k in ("v", "w", "F", "T"):
+                row[k] = rel(g[k], stT[k])
+            out[f"{name}/{prec}"] = row
+            print(f"[error-table] {name} {prec}", file=sys.stderr, flush=True)
+    return {"steps": steps, "rows": out}
 
 
 def copy_calibration():
@@ -683,8 +803,13 @@ def main():
                     help="skip the lattice Boltzmann kernel on a 256^3 lattice")
     ap.add_argument("--no-ibm", action="store_true",
                     help="skip the cilia carpet immersed in a lattice (rod_lbm_cycles)")
+    ap.add_argument("--no-ewald", action="store_true",
+                    help="skip the rods in a periodic box with the Ewald dipole sum")
     ap.add_argument("--ibm", action="store_true",
                     help="only run the immersed cilia carpet and print it as JSON")
+    ap.add_argument("--error-table", action="store_true",
+                    help="only measure the per-quantity error against the FP64 oracle (initial "
+                         "forces per term, 100-step state) on both paths and print it as JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
     ap.add_argument("--dipole-cutoff", type=float, default=0.0,
@@ -696,6 +821,9 @@ def main():
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.error_table:
+        print(json.dumps({"error_table": error_table()}))
         return
     if args.helix_loop is not None:
         print(json.dumps({"helix_loop": helix_loop(args.helix_loop)}))
@@ -757,6 +885,7 @@ def main():
         if micro:
             lbm_res["frac_copy"] = lbm_res["GB_s"] / micro[0]["plain_copy"]["GB_s"]
     ibm_res = None if args.no_ibm else ibm_leg()
+    ewald_res = None if args.no_ewald else ewald_leg()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -792,6 +921,7 @@ def main():
         "legs": legs,
         "lbm": lbm_res,
         "ibm": ibm_res,
+        "ewald": ewald_res,
         "adjoint": adj,
         "hbm_kernels": micro,
         "cpu_baseline": cpu,

@@ -15,18 +15,21 @@
 // The torque is m_i x B_i (in the particle kernels' gather) and the energy
 // -1/2 sum m_i.B_i. FP64 on both precision paths.
 //
-// Data flow of one evaluation (all on one stream, no atomics in any sum):
+// Data flow of one evaluation (all on one stream, no atomics in any sum; ten
+// launches):
 //   bin:     each particle's cell (side >= rc, member-major numbering) and its
 //            place in the cell (an atomic count);
 //   scan:    first sorted position of every cell (one workgroup);
-//   scatter: particles sorted by cell; order: each cell's particles by index
-//            (so the sums below run in a fixed order) and an interleaved copy
-//            of wrapped position and moment in sorted order;
-//   real:    one thread per sorted position walks the 27 (or fewer, in boxes
-//            under three cells wide) neighbouring cells, writes F, B;
+//   scatter: particles grouped by cell; rank: each cell's particles by index
+//            (so the sums below run in a fixed order); pack: an interleaved
+//            copy of wrapped position and moment in sorted order;
+//   real:    eight lanes per sorted position walk the 27 (or fewer, in boxes
+//            under three cells wide) neighbouring cells, their sums added by a
+//            fixed xor tree; writes F, B;
 //   sk:      partial structure factors of 256-particle chunks, one thread per k;
 //   sreduce: S(k) of each member, its chunks added in order;
-//   kspace:  one thread per sorted position sums over k, adds to F, B.
+//   kspace:  eight threads per sorted position share the k vectors, their
+//            partial sums added in a fixed order, and add to F, B.
 #include "rod.h"
 #include "rod_internal.h"
 #include "rod_math.h"
@@ -86,42 +89,41 @@ __global__ __launch_bounds__(1024) void k_ew_scan(const int* cnt, int* start, in
   if (t == 1023) start[total] = part[1023];
 }
 
+// Particles grouped by cell, in the arbitrary order of the counting slots.
 __global__ __launch_bounds__(EW_BLOCK) void k_ew_scatter(Dev d) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
-  d.ew_sorted[d.ew_start[d.ew_cell[i]] + d.ew_slot[i]] = (int)i;
+  d.ew_tmp[d.ew_start[d.ew_cell[i]] + d.ew_slot[i]] = (int)i;
 }
 
-// One thread per cell: its particles in ascending index (insertion sort; cells
-// hold tens of particles), then their wrapped positions and moments in sorted
-// order, one 64-byte record each.
-__global__ __launch_bounds__(EW_BLOCK) void k_ew_order(Dev d, int total) {
-  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= total) return;
+// Each cell's particles in ascending index: a particle's place in its cell is
+// the number of the cell's particles with a smaller index (one thread per
+// particle reads its cell's group, which its neighbours read too).
+__global__ __launch_bounds__(EW_BLOCK) void k_ew_rank(Dev d) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const int c = d.ew_cell[i];
   const int b = d.ew_start[c], e = d.ew_start[c + 1];
-  int* s = d.ew_sorted;
-  for (int p = b + 1; p < e; ++p) {
-    const int v = s[p];
-    int q = p - 1;
-    while (q >= b && s[q] > v) {
-      s[q + 1] = s[q];
-      --q;
-    }
-    s[q + 1] = v;
-  }
+  int r = 0;
+  for (int q = b; q < e; ++q) r += d.ew_tmp[q] < (int)i;
+  d.ew_sorted[b + r] = (int)i;
+}
+
+// Wrapped positions and moments in sorted order, one 64-byte record each.
+__global__ __launch_bounds__(EW_BLOCK) void k_ew_pack(Dev d) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= d.n) return;
   const long N = d.n;
-  for (int p = b; p < e; ++p) {
-    const long i = s[p];
-    double* o = d.ew_xm + 8 * (long)p;
-    o[0] = ew_wrap(d.x[i], d.box[0]);
-    o[1] = ew_wrap(d.x[N + i], d.box[1]);
-    o[2] = ew_wrap(d.x[2 * N + i], d.box[2]);
-    o[3] = 0.0;
-    o[4] = d.mu[i];
-    o[5] = d.mu[N + i];
-    o[6] = d.mu[2 * N + i];
-    o[7] = 0.0;
-  }
+  const long i = d.ew_sorted[p];
+  double* o = d.ew_xm + 8 * p;
+  o[0] = ew_wrap(d.x[i], d.box[0]);
+  o[1] = ew_wrap(d.x[N + i], d.box[1]);
+  o[2] = ew_wrap(d.x[2 * N + i], d.box[2]);
+  o[3] = 0.0;
+  o[4] = d.mu[i];
+  o[5] = d.mu[N + i];
+  o[6] = d.mu[2 * N + i];
+  o[7] = 0.0;
 }
 
 // Neighbouring cell offsets along an axis of nc cells: -1, 0, 1, or fewer when
@@ -131,19 +133,30 @@ __device__ __forceinline__ void ew_offsets(int nc, int& lo, int& hi) {
   hi = nc >= 2 ? 1 : 0;
 }
 
+// Real-space force and field: EW_RL lanes per sorted position, lane l taking
+// every EW_RL-th particle of each neighbouring cell; the lanes' sums are added
+// by a fixed xor tree, so the result does not depend on scheduling.
+constexpr int EW_RL = 8;
 __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
-  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= d.n) return;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long p = t / EW_RL;
+  const int sub = (int)(t % EW_RL);
+  const bool pv = p < d.n;
   const long N = d.n;
-  const double* rec = d.ew_xm + 8 * p;
+  const long pp = pv ? p : 0;
+  const double* rec = d.ew_xm + 8 * pp;
   const V3<double> xi{rec[0], rec[1], rec[2]}, mi{rec[4], rec[5], rec[6]};
-  const int i = d.ew_sorted[p];
+  const int i = d.ew_sorted[pp];
   const int cell = d.ew_cell[i];
   const int nx = d.ew_nc[0], ny = d.ew_nc[1], nz = d.ew_nc[2];
   const int mem = cell / d.ew_ncell;
   const int loc = cell - mem * d.ew_ncell;
   const int cx = loc % nx, cy = (loc / nx) % ny, cz = loc / (nx * ny);
   const double Lx = d.box[0], Ly = d.box[1], Lz = d.box[2];
+  // minimum image by the reciprocal lengths: a shift that rounding could make
+  // differ from that of a division only for |r_a| near L_a / 2, where the
+  // distance is at least rc and the pair is left out either way
+  const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
   const double a = d.ew_alpha, rc2 = d.ew_rc * d.ew_rc, C = d.C;
   const double sp = 2.0 * a * 0.56418958354775628695;  // 2 a / sqrt(pi)
   V3<double> F{0.0, 0.0, 0.0}, B{0.0, 0.0, 0.0};
@@ -151,7 +164,7 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
   ew_offsets(nx, lx, hx);
   ew_offsets(ny, ly, hy);
   ew_offsets(nz, lz, hz);
-  for (int oz = lz; oz <= hz; ++oz) {
+  for (int oz = lz; oz <= hz && pv; ++oz) {
     const int gz = (cz + oz + nz) % nz;
     for (int oy = ly; oy <= hy; ++oy) {
       const int gy = (cy + oy + ny) % ny;
@@ -159,23 +172,23 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
         const int gx = (cx + ox + nx) % nx;
         const int cc = mem * d.ew_ncell + (gz * ny + gy) * nx + gx;
         const int qe = d.ew_start[cc + 1];
-        for (int q = d.ew_start[cc]; q < qe; ++q) {
+        for (int q = d.ew_start[cc] + sub; q < qe; q += EW_RL) {
           if (q == p) continue;
           const double* rj = d.ew_xm + 8 * (long)q;
           V3<double> r{xi.x - rj[0], xi.y - rj[1], xi.z - rj[2]};
-          r.x -= Lx * rint(r.x / Lx);  // minimum image
-          r.y -= Ly * rint(r.y / Ly);
-          r.z -= Lz * rint(r.z / Lz);
+          r.x -= Lx * rint(r.x * iLx);  // minimum image
+          r.y -= Ly * rint(r.y * iLy);
+          r.z -= Lz * rint(r.z * iLz);
           const double r2 = dot(r, r);
           if (!(r2 < rc2)) continue;
           const V3<double> mj{rj[4], rj[5], rj[6]};
           const double rr = sqrt(r2), ar = a * rr, ar2 = ar * ar;
           const double ex = exp(-ar2), ec = erfc(ar);
-          const double r3 = r2 * rr, r5 = r3 * r2;
-          const double Bf = (ec + sp * rr * ex) / r3;
-          const double Cf = (3.0 * ec + sp * rr * (3.0 + 2.0 * ar2) * ex) / r5;
-          const double Df = (15.0 * ec + sp * rr * (15.0 + 10.0 * ar2 + 4.0 * ar2 * ar2) * ex) /
-                            (r5 * r2);
+          const double ri = 1.0 / rr, ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2;
+          const double Bf = (ec + sp * rr * ex) * ri3;
+          const double Cf = (3.0 * ec + sp * rr * (3.0 + 2.0 * ar2) * ex) * ri5;
+          const double Df = (15.0 * ec + sp * rr * (15.0 + 10.0 * ar2 + 4.0 * ar2 * ar2) * ex) *
+                            (ri5 * ri2);
           const double dmi = dot(mi, r), dmj = dot(mj, r), mm = dot(mi, mj);
           F = F + C * ((mm * Cf) * r + Cf * (dmj * mi + dmi * mj) - (dmi * dmj * Df) * r);
           B = B + C * ((Cf * dmj) * r - Bf * mj);
@@ -183,6 +196,12 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
       }
     }
   }
+#pragma unroll
+  for (int o = EW_RL / 2; o > 0; o >>= 1) {
+    F.x += __shfl_xor(F.x, o); F.y += __shfl_xor(F.y, o); F.z += __shfl_xor(F.z, o);
+    B.x += __shfl_xor(B.x, o); B.y += __shfl_xor(B.y, o); B.z += __shfl_xor(B.z, o);
+  }
+  if (!pv || sub != 0) return;
   B = B + d.ew_self * mi;
   double* o = d.dpart;
   o[i] = F.x; o[N + i] = F.y; o[2 * N + i] = F.z;
@@ -242,15 +261,22 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_sreduce(Dev d) {
   d.ew_S[2 * t + 1] = Si;
 }
 
-// Reciprocal-space force and field: block = one chunk (one member), thread = one
-// sorted position; k vectors, coefficients and the member's S(k) staged in LDS.
+// Reciprocal-space force and field. Block = 32 sorted positions of one chunk
+// (blockIdx.y picks which 32 of its 256) x 8 k lanes: thread (pl, kl) sums over
+// every 8th k vector of each tile of 256 (k vectors, coefficients and the
+// member's S(k) staged in LDS), then the 8 partial sums of a particle are added
+// in lane order through LDS. 8 blocks per chunk fill the GPU at moderate sizes.
+constexpr int EW_KP = 32;  // particles per kspace block
+constexpr int EW_KL = 8;   // k lanes per particle
 __global__ __launch_bounds__(EW_BLOCK) void k_ew_kspace(Dev d) {
   __shared__ double sk[6 * EW_BLOCK];
+  __shared__ double red[6 * EW_BLOCK];
   const long N = d.n;
   const int K = d.ew_K;
   const int ch = blockIdx.x;
   const int b = d.ew_chunks[3 * ch], e = d.ew_chunks[3 * ch + 1], mem = d.ew_chunks[3 * ch + 2];
-  const int p = b + threadIdx.x;
+  const int pl = threadIdx.x & (EW_KP - 1), kl = threadIdx.x / EW_KP;
+  const int p = b + (int)blockIdx.y * EW_KP + pl;
   const bool pv = p < e;
   V3<double> xi{0.0, 0.0, 0.0}, mi{0.0, 0.0, 0.0};
   if (pv) {
@@ -271,7 +297,7 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_kspace(Dev d) {
     }
     __syncthreads();
     const int nk = min(EW_BLOCK, K - k0);
-    for (int q = 0; q < nk; ++q) {
+    for (int q = kl; q < nk; q += EW_KL) {
       const double* r = sk + 6 * q;
       const V3<double> k{r[0], r[1], r[2]};
       const double ph = dot(k, xi), mk = dot(mi, k);
@@ -282,11 +308,17 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_kspace(Dev d) {
       B = B - (c * (cs * r[4] + sn * r[5])) * k;
     }
   }
-  if (!pv) return;
+  double* o6 = red + 6 * threadIdx.x;
+  o6[0] = F.x; o6[1] = F.y; o6[2] = F.z; o6[3] = B.x; o6[4] = B.y; o6[5] = B.z;
+  __syncthreads();
+  if (kl != 0 || !pv) return;
+  double t[6] = {0, 0, 0, 0, 0, 0};
+  for (int l = 0; l < EW_KL; ++l)
+    for (int c = 0; c < 6; ++c) t[c] += red[6 * (l * EW_KP + pl) + c];
   const int i = d.ew_sorted[p];
   double* o = d.dpart;
-  o[i] += F.x; o[N + i] += F.y; o[2 * N + i] += F.z;
-  o[3 * N + i] += B.x; o[4 * N + i] += B.y; o[5 * N + i] += B.z;
+  o[i] += t[0]; o[N + i] += t[1]; o[2 * N + i] += t[2];
+  o[3 * N + i] += t[3]; o[4 * N + i] += t[4]; o[5 * N + i] += t[5];
 }
 
 hipError_t launch_ewald(const Dev& d, hipStream_t s, const hipEvent_t* ev) {
@@ -299,14 +331,16 @@ hipError_t launch_ewald(const Dev& d, hipStream_t s, const hipEvent_t* ev) {
   hipLaunchKernelGGL(k_ew_bin, dim3(pg), dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_scan, dim3(1), dim3(1024), 0, s, (const int*)d.ew_cnt, d.ew_start, total);
   hipLaunchKernelGGL(k_ew_scatter, dim3(pg), dim3(EW_BLOCK), 0, s, d);
-  hipLaunchKernelGGL(k_ew_order, dim3((unsigned)((total + EW_BLOCK - 1) / EW_BLOCK)), dim3(EW_BLOCK),
-                     0, s, d, total);
-  hipLaunchKernelGGL(k_ew_real, dim3(pg), dim3(EW_BLOCK), 0, s, d);
+  hipLaunchKernelGGL(k_ew_rank, dim3(pg), dim3(EW_BLOCK), 0, s, d);
+  hipLaunchKernelGGL(k_ew_pack, dim3(pg), dim3(EW_BLOCK), 0, s, d);
+  hipLaunchKernelGGL(k_ew_real, dim3((unsigned)((EW_RL * d.n + EW_BLOCK - 1) / EW_BLOCK)),
+                     dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_sk, dim3((unsigned)((d.ew_K + EW_BLOCK - 1) / EW_BLOCK), (unsigned)d.ew_TC),
                      dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_sreduce, dim3((unsigned)(((long)d.M * d.ew_K + EW_BLOCK - 1) / EW_BLOCK)),
                      dim3(EW_BLOCK), 0, s, d);
-  hipLaunchKernelGGL(k_ew_kspace, dim3((unsigned)d.ew_TC), dim3(EW_BLOCK), 0, s, d);
+  static_assert(EW_KP * EW_KL == EW_BLOCK && EW_CHUNK % EW_KP == 0, "kspace block shape");
+  hipLaunchKernelGGL(k_ew_kspace, dim3((unsigned)d.ew_TC, EW_CHUNK / EW_KP), dim3(EW_BLOCK), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev) return hipEventRecord(ev[1], s);
   return hipSuccess;

@@ -470,6 +470,7 @@ static int ewald_setup(rod_ctx* c, const rod_desc* dsc, const std::vector<int>& 
   TRY(dalloc(c, &d.ew_start, (size_t)M * ncell + 1));
   TRY(dalloc(c, &d.ew_cell, (size_t)N));
   TRY(dalloc(c, &d.ew_slot, (size_t)N));
+  TRY(dalloc(c, &d.ew_tmp, (size_t)N));
   TRY(dalloc(c, &d.ew_sorted, (size_t)N));
   TRY(dalloc(c, &d.ew_xm, 8 * (size_t)N));
   TRY(dalloc(c, &kdev, kt.size()));
@@ -505,7 +506,7 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
     int nc[3], K = 0, TC = 0;
     ewald_count(d, nc, &K, &TC);
     const size_t cells = (size_t)nc[0] * nc[1] * nc[2] * M;
-    b += 8 * cells + 4 + (4 * 3 + 64) * N + 32 * (size_t)K + 12 * (size_t)TC + 4 * (M + 1) +
+    b += 8 * cells + 4 + (4 * 4 + 64) * N + 32 * (size_t)K + 12 * (size_t)TC + 4 * (M + 1) +
          16 * ((size_t)TC + M) * K;
   }
   if (d->precision == ROD_MIXED && d->dipole_on) b += 48 * ((N + 63) / 64);  // chunk boxes

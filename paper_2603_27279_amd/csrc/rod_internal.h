@@ -124,6 +124,7 @@ struct Dev {
   int* ew_start;           // [M ncell + 1] first sorted position of each cell
   int* ew_cell;            // [N] cell of each particle
   int* ew_slot;            // [N] its place in the cell's count
+  int* ew_tmp;             // [N] particles grouped by cell in counting-slot order
   int* ew_sorted;          // [N] particles by cell, each cell's in ascending index
   double* ew_xm;           // [N][8] wrapped x, y, z, 0, m_x, m_y, m_z, 0 in sorted order
   const double* ew_k;      // [K][4] k_x, k_y, k_z, 2 (4 pi C / V) exp(-k^2 / 4 a^2) / k^2
