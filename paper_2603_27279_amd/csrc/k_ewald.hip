@@ -26,9 +26,10 @@
 //   real:    eight lanes per sorted position walk the 27 (or fewer, in boxes
 //            under three cells wide) neighbouring cells, their sums added by a
 //            fixed xor tree; writes F, B;
-//   sk:      partial structure factors of 256-particle chunks, one thread per k;
+//   sk:      partial structure factors of 256-particle chunks, one thread per
+//            segment of up to 8 k vectors along a row;
 //   sreduce: S(k) of each member, its chunks added in order;
-//   kspace:  eight threads per sorted position share the k vectors, their
+//   kspace:  eight threads per sorted position share the k segments, their
 //            partial sums added in a fixed order, and add to F, B.
 #include "rod.h"
 #include "rod_internal.h"
@@ -208,41 +209,67 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
   o[3 * N + i] = B.x; o[4 * N + i] = B.y; o[5 * N + i] = B.z;
 }
 
-// Partial structure factors: block (k block, chunk); thread = one k vector; the
-// chunk's particles (at most EW_BLOCK sorted positions of one member) staged in
-// LDS and read as broadcasts.
+// The k vectors come in segments of at most EW_SEG consecutive vectors of one
+// row (fixed n_x, n_y; n_z rising by one), so that exp(i k.x) along a segment
+// follows from its first value by repeated rotation through exp(i dkz z),
+// dkz = 2 pi / L_z: one sincos per segment instead of per vector (the rotation
+// adds an error of a few ulp per step).
+constexpr int EW_SEG = 8;
+
+// Partial structure factors: block (segment block, chunk); thread = one
+// segment; the chunk's particles (at most EW_BLOCK sorted positions of one
+// member) with their rotation exp(i dkz z) staged in LDS and read as
+// broadcasts.
 __global__ __launch_bounds__(EW_BLOCK) void k_ew_sk(Dev d) {
-  __shared__ double sx[6 * EW_BLOCK];
+  __shared__ double sx[8 * EW_BLOCK];
   const int K = d.ew_K;
-  const int kk = blockIdx.x * EW_BLOCK + threadIdx.x;
+  const int sg = blockIdx.x * EW_BLOCK + threadIdx.x;
   const int ch = blockIdx.y;
   const int b = d.ew_chunks[3 * ch], e = d.ew_chunks[3 * ch + 1];
   const int p = b + threadIdx.x;
   if (p < e) {
     const double* rec = d.ew_xm + 8 * (long)p;
+    double* o = sx + 8 * threadIdx.x;
     for (int c = 0; c < 3; ++c) {
-      sx[6 * threadIdx.x + c] = rec[c];
-      sx[6 * threadIdx.x + 3 + c] = rec[4 + c];
+      o[c] = rec[c];
+      o[3 + c] = rec[4 + c];
     }
+    sincos(d.ew_dkz * rec[2], &o[7], &o[6]);  // cos, sin of dkz z
   }
   __syncthreads();
-  if (kk >= K) return;
-  const double* kv = d.ew_k + 4 * (long)kk;
-  const double kx = kv[0], ky = kv[1], kz = kv[2];
-  double Sr = 0.0, Si = 0.0;
+  if (sg >= d.ew_SEG) return;
+  const int k0 = d.ew_seg[2 * sg], nk = d.ew_seg[2 * sg + 1];
+  const double* kv = d.ew_k + 4 * (long)k0;
+  const double kx = kv[0], ky = kv[1], kz = kv[2], dkz = d.ew_dkz;
+  double Sr[EW_SEG], Si[EW_SEG];
+#pragma unroll
+  for (int m = 0; m < EW_SEG; ++m) Sr[m] = Si[m] = 0.0;
   const int n = e - b;
   for (int q = 0; q < n; ++q) {
-    const double* r = sx + 6 * q;
-    const double ph = kx * r[0] + ky * r[1] + kz * r[2];
-    const double mk = kx * r[3] + ky * r[4] + kz * r[5];
+    const double* r = sx + 8 * q;
     double sn, cs;
-    sincos(ph, &sn, &cs);
-    Sr += mk * cs;
-    Si += mk * sn;
+    sincos(kx * r[0] + ky * r[1] + kz * r[2], &sn, &cs);
+    double mk = kx * r[3] + ky * r[4] + kz * r[5];
+    const double dm = dkz * r[5], rc = r[6], rs = r[7];
+#pragma unroll
+    for (int m = 0; m < EW_SEG; ++m) {
+      if (m < nk) {
+        Sr[m] += mk * cs;
+        Si[m] += mk * sn;
+      }
+      const double c2 = cs * rc - sn * rs;
+      sn = sn * rc + cs * rs;
+      cs = c2;
+      mk += dm;
+    }
   }
-  double* o = d.ew_Sp + 2 * ((long)ch * K + kk);
-  o[0] = Sr;
-  o[1] = Si;
+  double* o = d.ew_Sp + 2 * ((long)ch * K + k0);
+#pragma unroll
+  for (int m = 0; m < EW_SEG; ++m)
+    if (m < nk) {
+      o[2 * m] = Sr[m];
+      o[2 * m + 1] = Si[m];
+    }
 }
 
 // S(k) of every member: its chunks added in chunk order.
@@ -262,14 +289,13 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_sreduce(Dev d) {
 }
 
 // Reciprocal-space force and field. Block = 32 sorted positions of one chunk
-// (blockIdx.y picks which 32 of its 256) x 8 k lanes: thread (pl, kl) sums over
-// every 8th k vector of each tile of 256 (k vectors, coefficients and the
-// member's S(k) staged in LDS), then the 8 partial sums of a particle are added
-// in lane order through LDS. 8 blocks per chunk fill the GPU at moderate sizes.
+// (blockIdx.y picks which 32 of its 256) x 8 k lanes: thread (pl, kl) takes
+// every 8th segment, its k vectors, weights and the member's S(k) read as
+// broadcasts, exp(i k.x) rotated along the segment; the 8 partial sums of a
+// particle are then added in lane order through LDS.
 constexpr int EW_KP = 32;  // particles per kspace block
 constexpr int EW_KL = 8;   // k lanes per particle
 __global__ __launch_bounds__(EW_BLOCK) void k_ew_kspace(Dev d) {
-  __shared__ double sk[6 * EW_BLOCK];
   __shared__ double red[6 * EW_BLOCK];
   const long N = d.n;
   const int K = d.ew_K;
@@ -284,28 +310,25 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_kspace(Dev d) {
     xi = V3<double>{rec[0], rec[1], rec[2]};
     mi = V3<double>{rec[4], rec[5], rec[6]};
   }
+  double rs, rc;
+  sincos(d.ew_dkz * xi.z, &rs, &rc);
   V3<double> F{0.0, 0.0, 0.0}, B{0.0, 0.0, 0.0};
   const double* S = d.ew_S + 2 * (long)mem * K;
-  for (int k0 = 0; k0 < K; k0 += EW_BLOCK) {
-    __syncthreads();
-    const int kk = k0 + threadIdx.x;
-    if (kk < K) {
-      const double* kv = d.ew_k + 4 * (long)kk;
-      for (int c = 0; c < 4; ++c) sk[6 * threadIdx.x + c] = kv[c];
-      sk[6 * threadIdx.x + 4] = S[2 * kk];
-      sk[6 * threadIdx.x + 5] = S[2 * kk + 1];
-    }
-    __syncthreads();
-    const int nk = min(EW_BLOCK, K - k0);
-    for (int q = kl; q < nk; q += EW_KL) {
-      const double* r = sk + 6 * q;
-      const V3<double> k{r[0], r[1], r[2]};
-      const double ph = dot(k, xi), mk = dot(mi, k);
-      double sn, cs;
-      sincos(ph, &sn, &cs);
-      const double c = r[3];
-      F = F + (c * mk * (sn * r[4] - cs * r[5])) * k;
-      B = B - (c * (cs * r[4] + sn * r[5])) * k;
+  for (int sg = kl; sg < d.ew_SEG; sg += EW_KL) {
+    const int k0 = d.ew_seg[2 * sg], nk = d.ew_seg[2 * sg + 1];
+    const double* kv = d.ew_k + 4 * (long)k0;
+    V3<double> k{kv[0], kv[1], kv[2]};
+    double sn, cs;
+    sincos(dot(k, xi), &sn, &cs);
+    for (int m = 0; m < nk; ++m) {
+      const double c = kv[4 * m + 3], Sr = S[2 * (k0 + m)], Si = S[2 * (k0 + m) + 1];
+      const double mk = dot(mi, k);
+      F = F + (c * mk * (sn * Sr - cs * Si)) * k;
+      B = B - (c * (cs * Sr + sn * Si)) * k;
+      const double c2 = cs * rc - sn * rs;
+      sn = sn * rc + cs * rs;
+      cs = c2;
+      k.z += d.ew_dkz;
     }
   }
   double* o6 = red + 6 * threadIdx.x;
@@ -335,7 +358,7 @@ hipError_t launch_ewald(const Dev& d, hipStream_t s, const hipEvent_t* ev) {
   hipLaunchKernelGGL(k_ew_pack, dim3(pg), dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_real, dim3((unsigned)((EW_RL * d.n + EW_BLOCK - 1) / EW_BLOCK)),
                      dim3(EW_BLOCK), 0, s, d);
-  hipLaunchKernelGGL(k_ew_sk, dim3((unsigned)((d.ew_K + EW_BLOCK - 1) / EW_BLOCK), (unsigned)d.ew_TC),
+  hipLaunchKernelGGL(k_ew_sk, dim3((unsigned)((d.ew_SEG + EW_BLOCK - 1) / EW_BLOCK), (unsigned)d.ew_TC),
                      dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_sreduce, dim3((unsigned)(((long)d.M * d.ew_K + EW_BLOCK - 1) / EW_BLOCK)),
                      dim3(EW_BLOCK), 0, s, d);

@@ -403,7 +403,11 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
 
 // Ewald sum of a periodic box: cells, reciprocal vectors and their weights,
 // member-aligned particle chunks, structure-factor buffers.
-static void ewald_vectors(const rod_desc* dsc, std::vector<double>* kt) {
+// k vectors of the half space 0 < |n|^2 <= kmax^2 in rows of fixed (n_x, n_y)
+// with n_z rising, and the rows cut into segments of at most 8 vectors
+// ([first, count] pairs in *seg).
+static void ewald_vectors(const rod_desc* dsc, std::vector<double>* kt,
+                          std::vector<int>* seg = nullptr) {
   const double pi = 3.14159265358979323846;
   const double* L = dsc->box;
   const double V = L[0] * L[1] * L[2], a = dsc->ewald_alpha;
@@ -415,9 +419,18 @@ static void ewald_vectors(const rod_desc* dsc, std::vector<double>* kt) {
         if (!half || nx * nx + ny * ny + nz * nz > K * K) continue;
         const double kx = 2.0 * pi * nx / L[0], ky = 2.0 * pi * ny / L[1], kz = 2.0 * pi * nz / L[2];
         const double k2 = kx * kx + ky * ky + kz * kz;
-        if (kt) {
-          kt->push_back(kx); kt->push_back(ky); kt->push_back(kz);
-          kt->push_back(2.0 * 4.0 * pi * dsc->mu0_4pi / V * std::exp(-k2 / (4.0 * a * a)) / k2);
+        const int idx = (int)(kt->size() / 4);
+        kt->push_back(kx); kt->push_back(ky); kt->push_back(kz);
+        kt->push_back(2.0 * 4.0 * pi * dsc->mu0_4pi / V * std::exp(-k2 / (4.0 * a * a)) / k2);
+        if (seg) {  // a new segment at the start of a row or after 8 vectors
+          const bool row_start = seg->empty() || nz == -K ||
+                                 (*kt)[4 * (idx - 1)] != kx || (*kt)[4 * (idx - 1) + 1] != ky;
+          if (row_start || seg->back() == 8) {
+            seg->push_back(idx);
+            seg->push_back(1);
+          } else {
+            seg->back() += 1;
+          }
         }
       }
 }
@@ -453,7 +466,8 @@ static int ewald_setup(rod_ctx* c, const rod_desc* dsc, const std::vector<int>& 
   d.ew_K = K;
   d.ew_TC = TC;
   std::vector<double> kt;
-  ewald_vectors(dsc, &kt);
+  std::vector<int> seg;
+  ewald_vectors(dsc, &kt, &seg);
   std::vector<int> chunks, coff(M + 1, 0);
   for (int m = 0; m < M; ++m) {
     coff[m] = (int)(chunks.size() / 3);
@@ -465,7 +479,7 @@ static int ewald_setup(rod_ctx* c, const rod_desc* dsc, const std::vector<int>& 
   }
   coff[M] = (int)(chunks.size() / 3);
   double* kdev = nullptr;
-  int *chd = nullptr, *cod = nullptr;
+  int *chd = nullptr, *cod = nullptr, *sgd = nullptr;
   TRY(dalloc(c, &d.ew_cnt, (size_t)M * ncell));
   TRY(dalloc(c, &d.ew_start, (size_t)M * ncell + 1));
   TRY(dalloc(c, &d.ew_cell, (size_t)N));
@@ -476,11 +490,16 @@ static int ewald_setup(rod_ctx* c, const rod_desc* dsc, const std::vector<int>& 
   TRY(dalloc(c, &kdev, kt.size()));
   TRY(dalloc(c, &chd, chunks.size()));
   TRY(dalloc(c, &cod, coff.size()));
+  TRY(dalloc(c, &sgd, seg.size()));
   TRY(dalloc(c, &d.ew_Sp, 2 * (size_t)TC * K));
   TRY(dalloc(c, &d.ew_S, 2 * (size_t)M * K));
   HIPC(hipMemcpy(kdev, kt.data(), kt.size() * sizeof(double), hipMemcpyHostToDevice));
   HIPC(hipMemcpy(chd, chunks.data(), chunks.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPC(hipMemcpy(cod, coff.data(), coff.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(sgd, seg.data(), seg.size() * sizeof(int), hipMemcpyHostToDevice));
+  d.ew_seg = sgd;
+  d.ew_SEG = (int)(seg.size() / 2);
+  d.ew_dkz = 2.0 * 3.14159265358979323846 / dsc->box[2];
   d.ew_k = kdev;
   d.ew_chunks = chd;
   d.ew_chunk_off = cod;

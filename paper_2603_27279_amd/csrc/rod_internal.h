@@ -129,6 +129,9 @@ struct Dev {
   double* ew_xm;           // [N][8] wrapped x, y, z, 0, m_x, m_y, m_z, 0 in sorted order
   const double* ew_k;      // [K][4] k_x, k_y, k_z, 2 (4 pi C / V) exp(-k^2 / 4 a^2) / k^2
   int ew_K;
+  const int* ew_seg;       // [SEG][2] first vector and count (<= 8) of runs along k_z
+  int ew_SEG;
+  double ew_dkz;           // 2 pi / L_z, the k_z step along a run
   const int* ew_chunks;    // [TC][3] sorted range [begin, end) of at most 256 and the member
   const int* ew_chunk_off; // [M + 1] first chunk of each member
   int ew_TC;
