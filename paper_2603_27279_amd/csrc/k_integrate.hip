@@ -156,36 +156,77 @@ __device__ __forceinline__ PIn load_particle(const Dev& d, long i) {
 // FP64, B slots per round trip (FP32 slots of the mixed path: 16; FP64: 8).
 // Slots past the member's own count hold zeros.
 template <class T, int B>
-__device__ __forceinline__ void slot_sum(const T* dp, long N, int S, long i, V3<double>& Fd,
-                                         V3<double>& Bd) {
-  for (int s0 = 0; s0 < S; s0 += B) {
+__device__ __forceinline__ void slot_sum(const T* dp, long N, int s_begin, int s_end, long i,
+                                         V3<double>& Fd, V3<double>& Bd) {
+  for (int s0 = s_begin; s0 < s_end; s0 += B) {
     T v[B][6];
 #pragma unroll
     for (int k = 0; k < B; ++k) {
       const T* q = dp + (long)(s0 + k) * 6 * N;
-      if (s0 + k < S)
+      if (s0 + k < s_end)
 #pragma unroll
         for (int c = 0; c < 6; ++c) v[k][c] = q[c * N + i];
     }
 #pragma unroll
     for (int k = 0; k < B; ++k)
-      if (s0 + k < S) {
+      if (s0 + k < s_end) {
         Fd = Fd + V3<double>{(double)v[k][0], (double)v[k][1], (double)v[k][2]};
         Bd = Bd + V3<double>{(double)v[k][3], (double)v[k][4], (double)v[k][5]};
       }
   }
 }
 
-// The dipole force and field of particle i when `mask` asks for them (zero
-// otherwise). Called first in the particle kernels: the slot loads are the
-// longest chain of the gather, and few other values are live yet.
+// The dipole force and field of particle i from slots [s_begin, s_end) when
+// `mask` asks for them (zero otherwise). Called first in the particle
+// kernels: the slot loads are the longest chain of the gather, and few other
+// values are live yet.
 __device__ __forceinline__ void dipole_sums(const Dev& d, long i, int mask, V3<double>& Fd,
-                                            V3<double>& Bd) {
+                                            V3<double>& Bd, int s_begin, int s_end) {
   Fd = V3<double>{0.0, 0.0, 0.0};
   Bd = V3<double>{0.0, 0.0, 0.0};
   if (!((mask & 2) && d.dipole_on)) return;
-  if (d.dslotf) slot_sum<float, 8>(d.dslotf, d.n, d.max_slots, i, Fd, Bd);
-  else slot_sum<double, 8>(d.dpart, d.n, d.max_slots, i, Fd, Bd);
+  if (d.dslotf) slot_sum<float, 8>(d.dslotf, d.n, s_begin, s_end, i, Fd, Bd);
+  else slot_sum<double, 8>(d.dpart, d.n, s_begin, s_end, i, Fd, Bd);
+}
+
+// Systems below 65,536 particles spread the gather over four waves per 64
+// particles (a quarter of the workgroups a particle per thread would give):
+// wave w adds the slots [w G, (w + 1) G), G = ceil(S / 4), of each of the 64
+// particles, the four partial sums meet in LDS, and wave 0 adds them in wave
+// order and completes the kernel alone. Every gather of such a system (fused
+// kick and unfused post) sums in this order, so launch forms stay bitwise
+// equal; larger systems add the slots one after another.
+constexpr int SPLIT_WAVES = 4;
+inline bool particle_split(long n) { return n < 65536; }
+
+// Slot sums of particle i in the kernel's layout: all slots (SPLIT false), or
+// this wave's group, combined through `part` ([SPLIT_WAVES][64][6]); returns
+// false on waves other than the first, which then leave the kernel.
+template <bool SPLIT>
+__device__ __forceinline__ bool dipole_sums_of(const Dev& d, long i, bool valid, int mask,
+                                               V3<double>& Fd, V3<double>& Bd, double* part) {
+  if constexpr (!SPLIT) {
+    if (valid) dipole_sums(d, i, mask, Fd, Bd, 0, d.max_slots);
+    return true;
+  } else {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int G = (d.max_slots + SPLIT_WAVES - 1) / SPLIT_WAVES;
+    const int sb = min(w * G, d.max_slots), se = min(sb + G, d.max_slots);
+    V3<double> f{0.0, 0.0, 0.0}, b{0.0, 0.0, 0.0};
+    if (valid) dipole_sums(d, i, mask, f, b, sb, se);
+    double* o = part + 6 * (w * 64 + lane);
+    o[0] = f.x; o[1] = f.y; o[2] = f.z; o[3] = b.x; o[4] = b.y; o[5] = b.z;
+    __syncthreads();
+    if (w != 0) return false;
+    Fd = V3<double>{0.0, 0.0, 0.0};
+    Bd = V3<double>{0.0, 0.0, 0.0};
+    for (int u = 0; u < SPLIT_WAVES; ++u) {
+      const double* q = part + 6 * (u * 64 + lane);
+      Fd = Fd + V3<double>{q[0], q[1], q[2]};
+      Bd = Bd + V3<double>{q[3], q[4], q[5]};
+    }
+    return true;
+  }
 }
 
 // Total force and torque on particle i from the terms in `mask` at level lvl
@@ -280,22 +321,24 @@ __device__ __forceinline__ void kick(const Dev& d, long i, V3<double> F, V3<doub
   if (!finite3(F) || !finite3(T) || !finite3(p.x)) atomicOr(&d.flags[FLAG_NONFINITE], 1u);
 }
 
-template <bool HM, bool FL>
+template <bool HM, bool FL, bool SPLIT>
 __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double* Fo, double* To,
                                               double* Bo) {
-  const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double part[SPLIT ? 6 * 64 * SPLIT_WAVES : 1];
+  const long i = d.i_lo + (SPLIT ? (long)blockIdx.x * 64 + (threadIdx.x & 63)
+                                 : (long)blockIdx.x * blockDim.x + threadIdx.x);
   const long N = d.n;
   const long long lvl = d.step[d.lc];  // level of the forces being gathered
-  if (i == 0) {
+  if (i == 0 && (!SPLIT || threadIdx.x < 64)) {
     if (mode == POST_KICK) d.step[0] = lvl;
     *cell_tab(d, lvl).ovf_cnt = 0;  // the contact pass that used the overflow list has finished
     if (d.use_lists) d.rebuild[lvl & 1] = 0u;  // and so has the one that read this flag
   }
+  V3<double> Fd, Bd;
+  if (!dipole_sums_of<SPLIT>(d, i, i < d.i_hi, mask, Fd, Bd, part)) return;
   if (i >= d.i_hi) return;
   PIn p = load_particle(d, i);
   const int key = d.contact_on ? d.key[i] : 0;
-  V3<double> Fd, Bd;
-  dipole_sums(d, i, mask, Fd, Bd);
   V3<double> F, T;
   gather<HM, FL>(d, i, mask, lvl, Bo, p, Fd, Bd, F, T);
   if (mode == POST_EVAL) {
@@ -315,22 +358,24 @@ __global__ __launch_bounds__(256) void k_post(Dev d, int mode, int mask, double*
 // half-kick at level L = step[lc], then half-kick, drift, rotation, moments and
 // cell insertion for level L + 1 (written to step[3 - lc]). The cell list and
 // overflow list of level L are emptied while those of level L + 1 are filled.
-template <bool HM>
+template <bool HM, bool SPLIT>
 __global__ __launch_bounds__(256) void k_kick(Dev d, double* Bo) {
-  const long i = d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double part[SPLIT ? 6 * 64 * SPLIT_WAVES : 1];
+  const long i = d.i_lo + (SPLIT ? (long)blockIdx.x * 64 + (threadIdx.x & 63)
+                                 : (long)blockIdx.x * blockDim.x + threadIdx.x);
   const long long L = d.step[d.lc];
-  if (i == 0) {
+  if (i == 0 && (!SPLIT || threadIdx.x < 64)) {
     d.step[3 - d.lc] = L + 1;
     *cell_tab(d, L).ovf_cnt = 0;
     if (d.use_lists) d.rebuild[L & 1] = 0u;
   }
   const bool valid = i < d.i_hi;
   V3<double> x{0.0, 0.0, 0.0};
+  V3<double> Fd, Bd;
+  if (!dipole_sums_of<SPLIT>(d, i, valid, ROD_TERM_ALL, Fd, Bd, part)) return;
   if (valid) {
     PIn p = load_particle(d, i);
     const int key = d.contact_on ? d.key[i] : 0;
-    V3<double> Fd, Bd;
-    dipole_sums(d, i, ROD_TERM_ALL, Fd, Bd);
     V3<double> F, T;
     gather<HM>(d, i, ROD_TERM_ALL, L, Bo, p, Fd, Bd, F, T);
     // in place, the next half-kick overwrites v and w; out of place (a recorded
@@ -398,26 +443,43 @@ hipError_t launch_pre(const Dev& d, int mode, hipStream_t s, const hipEvent_t* e
   return hipGetLastError();
 }
 
+template <bool SPLIT>
+static void post_variant(const Dev& d, int mode, int mask, double* Fo, double* To, double* Bo,
+                         hipStream_t s, const hipEvent_t* ev, dim3 g, dim3 b) {
+  if (d.ibm_u) {
+    if (d.hm) launch_k(ev, k_post<true, true, SPLIT>, g, b, s, d, mode, mask, Fo, To, Bo);
+    else launch_k(ev, k_post<false, true, SPLIT>, g, b, s, d, mode, mask, Fo, To, Bo);
+  } else if (d.hm) {
+    launch_k(ev, k_post<true, false, SPLIT>, g, b, s, d, mode, mask, Fo, To, Bo);
+  } else {
+    launch_k(ev, k_post<false, false, SPLIT>, g, b, s, d, mode, mask, Fo, To, Bo);
+  }
+}
+
 hipError_t launch_post(const Dev& d, int mode, int mask, double* Fo, double* To, double* Bo,
                        hipStream_t s, const hipEvent_t* ev) {
-  const int bs = particle_block(d.n);
-  const dim3 g(blocks_for(d.i_hi - d.i_lo, bs)), b(bs);
-  if (d.ibm_u) {
-    if (d.hm) launch_k(ev, k_post<true, true>, g, b, s, d, mode, mask, Fo, To, Bo);
-    else launch_k(ev, k_post<false, true>, g, b, s, d, mode, mask, Fo, To, Bo);
-  } else if (d.hm) {
-    launch_k(ev, k_post<true, false>, g, b, s, d, mode, mask, Fo, To, Bo);
+  if (particle_split(d.n)) {  // four waves per 64 particles
+    post_variant<true>(d, mode, mask, Fo, To, Bo, s, ev, dim3(blocks_for(d.i_hi - d.i_lo, 64)),
+                       dim3(64 * SPLIT_WAVES));
   } else {
-    launch_k(ev, k_post<false, false>, g, b, s, d, mode, mask, Fo, To, Bo);
+    const int bs = particle_block(d.n);
+    post_variant<false>(d, mode, mask, Fo, To, Bo, s, ev, dim3(blocks_for(d.i_hi - d.i_lo, bs)),
+                        dim3(bs));
   }
   return hipGetLastError();
 }
 
 hipError_t launch_kick(const Dev& d, double* Bo, hipStream_t s, const hipEvent_t* ev) {
-  const int bs = particle_block(d.n);
-  const dim3 g(blocks_for(d.i_hi - d.i_lo, bs)), b(bs);
-  if (d.hm) launch_k(ev, k_kick<true>, g, b, s, d, Bo);
-  else launch_k(ev, k_kick<false>, g, b, s, d, Bo);
+  if (particle_split(d.n)) {
+    const dim3 g(blocks_for(d.i_hi - d.i_lo, 64)), b(64 * SPLIT_WAVES);
+    if (d.hm) launch_k(ev, k_kick<true, true>, g, b, s, d, Bo);
+    else launch_k(ev, k_kick<false, true>, g, b, s, d, Bo);
+  } else {
+    const int bs = particle_block(d.n);
+    const dim3 g(blocks_for(d.i_hi - d.i_lo, bs)), b(bs);
+    if (d.hm) launch_k(ev, k_kick<true, false>, g, b, s, d, Bo);
+    else launch_k(ev, k_kick<false, false>, g, b, s, d, Bo);
+  }
   return hipGetLastError();
 }
 
