@@ -17,15 +17,15 @@
 //
 // Data flow of one evaluation (all on one stream, no atomics in any sum; ten
 // launches):
-//   bin:     each particle's cell (side >= rc, member-major numbering) and its
-//            place in the cell (an atomic count);
+//   bin:     each particle's cell (side >= rc / 2, member-major numbering) and
+//            its place in the cell (an atomic count);
 //   scan:    first sorted position of every cell (one workgroup);
 //   scatter: particles grouped by cell; rank: each cell's particles by index
 //            (so the sums below run in a fixed order); pack: an interleaved
 //            copy of wrapped position and moment in sorted order;
-//   real:    eight lanes per sorted position walk the 27 (or fewer, in boxes
-//            under three cells wide) neighbouring cells, their sums added by a
-//            fixed xor tree; writes F, B;
+//   real:    eight lanes per sorted position walk the 5 x 5 x 5 neighbouring
+//            cells (every cell of an axis under five cells wide), their sums
+//            added by a fixed xor tree; writes F, B;
 //   sk:      partial structure factors of 256-particle chunks, one thread per
 //            segment of up to 8 k vectors along a row;
 //   sreduce: S(k) of each member, its chunks added in order;
@@ -127,11 +127,18 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_pack(Dev d) {
   o[7] = 0.0;
 }
 
-// Neighbouring cell offsets along an axis of nc cells: -1, 0, 1, or fewer when
-// the box is under three cells wide (so that no cell is visited twice).
+// Neighbouring cell offsets along an axis of nc cells of side >= rc / EW_REACH:
+// -EW_REACH .. EW_REACH, or every cell of the axis once when it has fewer than
+// 2 EW_REACH + 1 of them.
+constexpr int EW_REACH = 2;
 __device__ __forceinline__ void ew_offsets(int nc, int& lo, int& hi) {
-  lo = nc >= 3 ? -1 : 0;
-  hi = nc >= 2 ? 1 : 0;
+  if (nc >= 2 * EW_REACH + 1) {
+    lo = -EW_REACH;
+    hi = EW_REACH;
+  } else {
+    lo = 0;
+    hi = nc - 1;
+  }
 }
 
 // Real-space force and field: EW_RL lanes per sorted position, lane l taking

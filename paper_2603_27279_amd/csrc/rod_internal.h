@@ -110,7 +110,7 @@ struct Dev {
   double* xm;              // [N][8]: x, y, z, 0, m_x, m_y, m_z, 0 of the level (cutoff), or null
   // Periodic box with the Ewald sum of the dipoles (ew_on; k_ewald.hip): box
   // lengths, splitting parameter, real-space cutoff, the self-field
-  // coefficient C 4 a^3 / (3 sqrt(pi)); member-major cells of side >= ew_rc,
+  // coefficient C 4 a^3 / (3 sqrt(pi)); member-major cells of side >= ew_rc / 2,
   // ew_nc per axis; particles sorted by cell with an interleaved copy of their
   // wrapped positions and moments; the reciprocal vectors of the half space
   // with their coefficients, particle chunks (sorted ranges of one member) and

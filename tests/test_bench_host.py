@@ -70,3 +70,14 @@ def test_cpu_baseline_reports_cores_model_and_one_core(monkeypatch, rows):
     assert cb["value"] > 0 and cb["one_core"]["value"] > 0 and cb["cores"] >= 1
     assert ("dipole and contact sums" in cb["sample"]) == rows
     assert "logical_cpus" in cb and "cpu_model" in cb
+
+
+def test_member0_slices_the_first_ensemble_member():
+    import numpy as np
+    import workloads
+    w = workloads.ensemble(members=3, n=50)
+    v = bench._member0(w)
+    assert v["n"] == 50 and v["n_members"] == 1 and list(v["rod_offset"]) == [0, 50]
+    assert v["field"].shape == (w["field"].shape[0], 1, 12)
+    np.testing.assert_array_equal(v["x0"], w["x0"][:50])
+    np.testing.assert_array_equal(v["rod_params"], w["rod_params"][:1])
