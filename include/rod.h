@@ -72,7 +72,7 @@ enum { ROD_CONTACT_HOOKEAN = 0, ROD_CONTACT_HERTZ_MINDLIN = 1 };
 
 /* Tangential-history capacity of a Hertz-Mindlin particle: contacts it can
    hold at once (more: ROD_E_OVERFLOW at rod_sync). */
-#define ROD_HM_MAX_CONTACTS 16
+#define ROD_HM_MAX_CONTACTS 32
 
 /* Host-side description; copied by rod_init (the caller may free it after). */
 typedef struct rod_desc {

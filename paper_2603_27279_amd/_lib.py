@@ -13,7 +13,7 @@ TERM_BOND, TERM_DIPOLE, TERM_ZEEMAN, TERM_CONTACT, TERM_DAMP, TERM_EXT, TERM_ALL
     1, 2, 4, 8, 16, 32, 63
 
 ROD_NOALLOC_MAX_PAIRS = 1048576  # include/rod.h
-ROD_HM_MAX_CONTACTS = 16  # include/rod.h
+ROD_HM_MAX_CONTACTS = 32  # include/rod.h
 
 KERNELS = ("pre", "bond", "dipole", "contact", "post", "forces", "kick")
 

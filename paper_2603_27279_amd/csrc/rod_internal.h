@@ -152,7 +152,7 @@ constexpr long CONTACT_LANES_MAX_N = 65536;     // below: lane-parallel cell sea
 constexpr double NBR_SKIN = 0.25;               // skin as a fraction of r_c
 constexpr double NBR_MOVE = 0.45;               // rebuild past this fraction of the skin
                                                 // (below 1/2, a margin for rounding)
-constexpr int HM_CAP = 16;                      // Hertz-Mindlin contacts kept per particle
+constexpr int HM_CAP = 32;                      // Hertz-Mindlin contacts kept per particle
 constexpr int DNBR_CAP = 256;                   // dipole list entries per particle (cutoff)
 enum { FLAG_NONFINITE = 0, FLAG_DIP_OVF = 1, FLAG_LIST_OVF = 2, FLAG_HM_OVF = 3,
        FLAG_CONTACT_RANGE = 4, FLAG_COUNT = 5 };

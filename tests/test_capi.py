@@ -153,7 +153,7 @@ def test_bond_damping_descriptor():
 
 
 def test_hertz_mindlin_descriptor():
-    """Hertz-Mindlin adds a contact torque and two planes of 16 contacts per
+    """Hertz-Mindlin adds a contact torque and two planes of 32 contacts per
     particle (partner and tangential displacement) to the workspace; without
     contact its parameters are not looked at."""
     lib = L.load()
@@ -164,7 +164,7 @@ def test_hertz_mindlin_descriptor():
     assert lib.rod_query_workspace(C.byref(d), C.byref(nb)) == L.ROD_OK
     d2, keep2 = _desc(w, contact_model=1, contact_hm=(C.c_double * 5)(10, 0.3, 0.5, 0.1, 0.1))
     assert lib.rod_query_workspace(C.byref(d2), C.byref(nb2)) == L.ROD_OK
-    assert nb2.value - nb.value == (24 + 8 + 2 * 16 * (4 + 24)) * 64
+    assert nb2.value - nb.value == (24 + 8 + 2 * 32 * (4 + 24)) * 64
     d3, keep3 = _desc(w, contact_on=0, contact_model=1, tape_capacity=10, tape_every=2)
     assert lib.rod_query_workspace(C.byref(d3), C.byref(nb2)) == L.ROD_OK
 

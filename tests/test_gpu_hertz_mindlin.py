@@ -16,7 +16,7 @@ from test_gpu_parity import TOL, TRAJ_TOL, clump, coil, perturb, rel_inf
 pytestmark = pytest.mark.gpu
 
 # E, nu, mu, g_n, g_t: stiff enough that the dipole-laden clump below keeps
-# at most 14 contacts per particle (under the capacity of 16)
+# at most 14 contacts per particle (well under the capacity of 32)
 HM = (200.0, 0.3, 0.5, 0.2, 0.2)
 
 
@@ -251,9 +251,9 @@ def test_large_system_uses_the_cell_walk():
 
 
 def test_contact_capacity_is_reported():
-    """A particle buried among 18 overlapping neighbours has more contacts than
-    a particle keeps: rod_sync reports ROD_E_OVERFLOW; 12 neighbours fit."""
-    for k, fits in ((12, True), (18, False)):
+    """A particle buried among 40 overlapping neighbours has more contacts than
+    a particle keeps (32): rod_sync reports ROD_E_OVERFLOW; 24 neighbours fit."""
+    for k, fits in ((24, True), (40, False)):
         # neighbours on a sphere of radius 0.8 around the origin (Fibonacci points)
         i = np.arange(k) + 0.5
         phi = np.arccos(1 - 2 * i / k)
