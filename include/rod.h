@@ -140,10 +140,11 @@ typedef struct rod_desc {
                                  selection) interact, through the same pair law (the truncated pair
                                  interaction of the paper's simulations, for very large systems).
                                  Needs contact_on: each particle keeps a list of the member's
-                                 particles within cutoff + r_contact / 4, found by walking the
-                                 contact cells and rebuilt with the contact lists; at most 256 per
-                                 particle (more: ROD_E_OVERFLOW at rod_sync). FP64 on both paths;
-                                 sums in list order, so runs agree to rounding, not bit for bit.
+                                 particles within cutoff + r_contact / 4, rebuilt with the contact
+                                 lists from the particles sorted by cell (cells of that side); at
+                                 most 256 per particle (more: ROD_E_OVERFLOW at rod_sync). FP64 on
+                                 both paths; the sort fixes the list order and the sums, so a run
+                                 repeated gives the same bits.
                                  Not differentiated: refused with tape_capacity > 0. */
   double box[3];              /* Periodic box lengths L_x, L_y, L_z, all > 0; or all 0 (open
                                  boundaries). With a box and dipole_on, the dipole-dipole

@@ -16,8 +16,8 @@ __device__ __forceinline__ void moment_and_cell(const Dev& d, long i, Q4<double>
   if (d.muf) st3(d.muf, N, i, V3<float>{(float)m.x, (float)m.y, (float)m.z});
   if (d.xm) {  // interleaved copy for the cutoff list walk: one line per partner
     double* p = d.xm + 8 * i;
-    p[0] = x.x; p[1] = x.y; p[2] = x.z; p[3] = 0.0;
-    p[4] = m.x; p[5] = m.y; p[6] = m.z; p[7] = 0.0;
+    p[0] = x.x; p[1] = x.y; p[2] = x.z;
+    p[3] = m.x; p[4] = m.y; p[5] = m.z; p[6] = 0.0; p[7] = 0.0;
   }
   if (d.contact_on) {
     const CellTab t = cell_tab(d, lvl);

@@ -306,10 +306,6 @@ static int validate(const rod_desc* d) {
   if (d->dipole_on && d->dipole_cutoff > 0) {
     if (!d->contact_on)
       return fail(ROD_E_INVALID, "a dipole cutoff needs contact_on (it walks the contact cells)");
-    // the list rebuild walks at most 8 cells (of side 1.25 r_contact) each way
-    if (d->dipole_cutoff + NBR_SKIN * d->r_contact > 8.0 * (1.0 + NBR_SKIN) * d->r_contact)
-      return fail(ROD_E_INVALID, "dipole_cutoff above %.2f r_contact: use 0 (all pairs)",
-                  8.0 * (1.0 + NBR_SKIN) - NBR_SKIN);
     if (d->tape_capacity > 0)
       return fail(ROD_E_INVALID, "the dipole cutoff is not differentiated: no tape with it");
   }
@@ -508,6 +504,49 @@ static int ewald_setup(rod_ctx* c, const rod_desc* dsc, const std::vector<int>& 
   return ROD_OK;
 }
 
+// Cells of the cutoff sort (dipole_list.h): side dcut + skin, from the lower
+// corner of the reference lattice less one cell. Each axis gets the key bits
+// its extent needs (plus a cell either side), the member field ceil(log2 M);
+// keys have at most ceil(log2 N) + 1 bits (the widest axis gives up bits
+// first: its cells then share buckets) and at least log2 DL_SCAN.
+struct DlGeo { double inv, org[3]; int bits[3]; unsigned axis[3]; int mshift, nb; };
+static int ceil_log2(double v) {
+  int b = 0;
+  while (b < 31 && std::ldexp(1.0, b) < v) ++b;
+  return b;
+}
+static DlGeo dl_geometry(const rod_desc* d) {
+  DlGeo g{};
+  const double side = d->dipole_cutoff + NBR_SKIN * d->r_contact;
+  g.inv = 1.0 / side;
+  const int N = d->n_particles;
+  for (int a = 0; a < 3; ++a) {
+    double lo = d->x_ref[a], hi = d->x_ref[a];
+    for (int k = 1; k < N; ++k) {
+      lo = std::min(lo, d->x_ref[3 * k + a]);
+      hi = std::max(hi, d->x_ref[3 * k + a]);
+    }
+    g.org[a] = lo - side;
+    g.bits[a] = ceil_log2(std::min(std::floor((hi - g.org[a]) * g.inv) + 2.0, 1048576.0));
+  }
+  const int mbits = ceil_log2((double)d->n_members);
+  const int max_bits = std::max(ceil_log2((double)DL_SCAN), ceil_log2((double)N) + 1);
+  while (g.bits[0] + g.bits[1] + g.bits[2] + mbits > max_bits) {
+    int w = 0;
+    for (int a = 1; a < 3; ++a)
+      if (g.bits[a] > g.bits[w]) w = a;
+    if (g.bits[w] == 0) break;
+    --g.bits[w];
+  }
+  int pos = 0;  // bit l of each axis in turn, lowest first
+  for (int l = 0; l < 21; ++l)
+    for (int a = 0; a < 3; ++a)
+      if (l < g.bits[a]) g.axis[a] |= 1u << pos++;
+  g.mshift = pos;
+  g.nb = std::max(DL_SCAN, 1 << (pos + mbits));
+  return g;
+}
+
 static size_t workspace_bytes(const rod_desc* d, int max_slots) {
   size_t N = d->n_particles, R = d->n_rods, M = d->n_members;
   size_t cells = d->contact_on ? next_pow2(std::max<size_t>(1024, 2 * N)) : 1;
@@ -522,6 +561,10 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
   if (d->contact_on && ((long)N >= CONTACT_LANES_MAX_N || dcut))
     b += (4 * NBR_CAP + 4 + 24) * N;                                            // lists
   if (dcut) b += (4 * DNBR_CAP + 4 + 64) * N;                                   // dipole lists
+  if (dcut) {                                                                   // cutoff sort
+    const DlGeo g = dl_geometry(d);
+    b += 4 * (2 * (size_t)g.nb + 1 + g.nb / DL_SCAN) + (4 * 5 + sizeof(DlRec)) * N;
+  }
   if (hm) b += (24 + 8 + 2 * HM_CAP * (4 + 24)) * N;                            // torque, contacts
   if (d->dipole_on && d->box[0] > 0 && d->box[1] > 0 && d->box[2] > 0) {      // Ewald
     int nc[3], K = 0, TC = 0;
@@ -654,8 +697,10 @@ static int enqueue_step_per_rod(rod_ctx* c) {
   };
   for (int r = 0; r < R; ++r) HIPC(launch_pre(rod_dev(r), PRE_STEP, c->s));
   for (int r = 0; r < R; ++r) HIPC(launch_bond(rod_dev(r), c->desc.precision, 0, c->s));
-  if (c->desc.dipole_on && c->d.dcut > 0)
+  if (c->desc.dipole_on && c->d.dcut > 0) {
+    HIPC(launch_dipole_sort(c->d, 1, c->s));  // one sort of the whole system
     for (int r = 0; r < R; ++r) HIPC(launch_dipole_cut(rod_dev(r), 1, c->s));
+  }
   else if (c->d.ew_on)  // one periodic sum over every member (not separable by rod)
     HIPC(launch_ewald(c->d, c->s));
   else if (c->desc.dipole_on)
@@ -884,9 +929,25 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   d.skin = NBR_SKIN * dsc->r_contact;
   // with lists the 27 cells around a particle must cover the list cutoff r_c + skin
   if (d.use_lists) d.inv_cell = 1.0 / (dsc->r_contact + d.skin);
-  // cells to walk around a particle's own so that the dipole lists reach dcut + skin
-  d.dcell_k = d.dcut > 0 ? (int)std::ceil((d.dcut + d.skin) * d.inv_cell) : 0;
   d.dnbr = nullptr; d.dnbr_cnt = nullptr; d.xm = nullptr;
+  d.dl_cnt = d.dl_aux = d.dl_start = d.dl_bkt = d.dl_slot = d.dl_tmp = d.dl_sorted = d.dl_pos = nullptr;
+  d.dl_rec = nullptr;
+  d.dl_nb = 0;
+  if (d.dcut > 0) {
+    const DlGeo g = dl_geometry(dsc);
+    d.dl_inv = g.inv;
+    for (int a = 0; a < 3; ++a) {
+      d.dl_org[a] = g.org[a]; d.dl_bits[a] = g.bits[a]; d.dl_axis[a] = g.axis[a];
+    }
+    d.dl_mshift = g.mshift;
+    d.dl_nb = g.nb;
+    if ((rc = dalloc(c, &d.dl_cnt, (size_t)g.nb)) || (rc = dalloc(c, &d.dl_aux, (size_t)g.nb / DL_SCAN)) ||
+        (rc = dalloc(c, &d.dl_start, (size_t)g.nb + 1)) || (rc = dalloc(c, &d.dl_bkt, (size_t)N)) ||
+        (rc = dalloc(c, &d.dl_slot, (size_t)N)) || (rc = dalloc(c, &d.dl_tmp, (size_t)N)) ||
+        (rc = dalloc(c, &d.dl_sorted, (size_t)N)) || (rc = dalloc(c, &d.dl_pos, (size_t)N)) ||
+        (rc = dalloc(c, &d.dl_rec, (size_t)N)))
+      return cleanup(rc);
+  }
   d.ibm_u = nullptr; d.ibm_f = nullptr; d.ibm_idt = 1.0;
   if (d.dcut > 0 && ((rc = dalloc(c, &d.dnbr, (size_t)DNBR_CAP * N)) ||
                      (rc = dalloc(c, &d.dnbr_cnt, (size_t)N)) ||

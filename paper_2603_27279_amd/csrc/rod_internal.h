@@ -10,6 +10,10 @@ namespace rodmx {
 // a tag holding its index (low 32 bits) and rod (high 32 bits).
 struct alignas(32) CellSlot { double x, y, z; long long tag; };
 
+// A particle of the cutoff sort at its sorted position: position, index and
+// the high bits of its cell's coordinates.
+struct alignas(32) DlRec { double x, y, z; int i; unsigned tag; };
+
 // Device-side view of one context: every pointer is a device pointer, fixed for
 // the lifetime of the context, so that captured graphs can be replayed.
 struct Dev {
@@ -101,13 +105,29 @@ struct Dev {
   int* hc_j;               // [2][HM_CAP][N]
   double* hc_s;            // [2][3][HM_CAP][N]
   // Dipole cutoff (dcut > 0; 0: all pairs of a member): each particle's
-  // neighbours within dcut + skin and how many cells around its own to walk
-  // when the list is rebuilt.
+  // neighbours within dcut + skin, found at a rebuild from the particles
+  // sorted by cell (dipole_list.h). Cells of side 1 / dl_inv >= dcut + skin
+  // from the origin dl_org; a bucket is the member shifted by dl_mshift above
+  // the coordinates' low dl_bits[a] bits, deposited at the bits of dl_axis[a].
   double dcut;
-  int dcell_k;
-  int* dnbr;               // [DNBR_CAP][N]
-  int* dnbr_cnt;           // [N]
-  double* xm;              // [N][8]: x, y, z, 0, m_x, m_y, m_z, 0 of the level (cutoff), or null
+  double dl_inv;
+  double dl_org[3];
+  int dl_bits[3];
+  unsigned dl_axis[3];
+  int dl_mshift;
+  int dl_nb;               // buckets (a power of two, a multiple of DL_SCAN)
+  int* dl_cnt;             // [nb] particles per bucket (zero between rebuilds)
+  int* dl_aux;             // [nb / DL_SCAN] count of each scan block
+  int* dl_start;           // [nb + 1] first sorted position of each bucket
+  int* dl_bkt;             // [N] bucket of each particle
+  int* dl_slot;            // [N] its counting slot in the bucket
+  int* dl_tmp;             // [N] particles by bucket in counting order
+  int* dl_sorted;          // [N] particle at each sorted position
+  int* dl_pos;             // [N] sorted position of each particle
+  DlRec* dl_rec;            // [N] position, index and cell tag at each sorted position
+  int* dnbr;               // [DNBR_CAP][N] by sorted position
+  int* dnbr_cnt;           // [N] by sorted position
+  double* xm;              // [N][8]: x, y, z, m_x, m_y, m_z, 0, 0 of the level (cutoff), or null
   // Periodic box with the Ewald sum of the dipoles (ew_on; k_ewald.hip): box
   // lengths, splitting parameter, real-space cutoff, the self-field
   // coefficient C 4 a^3 / (3 sqrt(pi)); member-major cells of side >= ew_rc / 2,
@@ -154,6 +174,7 @@ constexpr double NBR_MOVE = 0.45;               // rebuild past this fraction of
                                                 // (below 1/2, a margin for rounding)
 constexpr int HM_CAP = 32;                      // Hertz-Mindlin contacts kept per particle
 constexpr int DNBR_CAP = 256;                   // dipole list entries per particle (cutoff)
+constexpr int DL_SCAN = 2048;                   // buckets per block of the cutoff sort's sums
 enum { FLAG_NONFINITE = 0, FLAG_DIP_OVF = 1, FLAG_LIST_OVF = 2, FLAG_HM_OVF = 3,
        FLAG_CONTACT_RANGE = 4, FLAG_COUNT = 5 };
 // Exponent that maps a pair-term bound b to 2^80 in the exact contact sums.
@@ -194,6 +215,7 @@ enum PostMode { POST_PREPARE = 0, POST_KICK = 1, POST_EVAL = 2 };
 // written to partial slot `slot`.
 struct DipWork { int i0, i1, j0, j1, slot, pad0, pad1, pad2; };
 
+
 // Targets per work item of the small-member layout (one wave of a 256-thread
 // workgroup each).
 constexpr int DIP_SMALL_I = 4;
@@ -226,6 +248,9 @@ hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int n
 // rebuild them regardless of motion.
 hipError_t launch_dipole_cut(const Dev& d, int build, hipStream_t s,
                              const hipEvent_t* ev = nullptr);
+// The cutoff sort alone (when the lists are stale or `build`), over the whole
+// system: launched once before the per-rod loop's list walks.
+hipError_t launch_dipole_sort(const Dev& d, int build, hipStream_t s);
 // Ewald sum of the dipoles of a periodic box (d.ew_on): writes the dipole
 // force and field to slot 0 of the FP64 partial sums.
 hipError_t launch_ewald(const Dev& d, hipStream_t s, const hipEvent_t* ev = nullptr);

@@ -2,8 +2,9 @@
 oracle: forces at the initial level, 100-step trajectories (lists rebuilt as
 particles move past the skin), a cutoff wider than the members against the
 all-pairs kernels, every launch form, a system past the lane-parallel contact
-size, and the per-particle list capacity. Sums run in list order, so runs and
-launch forms agree to rounding rather than bit for bit."""
+size, cells that share a sort bucket, and the per-particle list capacity. Sums
+run in list order, fixed by the cell sort: a run repeated gives the same bits;
+launch forms whose lists are rebuilt at other steps agree to rounding."""
 import numpy as np
 import pytest
 
@@ -145,3 +146,57 @@ def test_list_capacity_is_reported():
         sim.sync()
     assert e.value.code == ROD_E_OVERFLOW
     sim.free()
+
+
+def _bundle(stretch=1.0, shift=(0.0, 0.0, 0.0), seed=21):
+    """A 3 x 3 bundle of rods of 100 particles along z on a unit reference
+    lattice (pitch 1.1); the state is that lattice stretched along z and
+    shifted, so that the cell sort's key bits, chosen for the reference
+    lattice, no longer cover it."""
+    rng = np.random.default_rng(seed)
+    origins = [(1.1 * (r % 3), 1.1 * (r // 3), 0.0) for r in range(9)]
+    x, off, mem = workloads.straight_rods([100] * 9, origins, (0, 0, 1))
+    n = x.shape[0]
+    w = workloads._base(x, off, mem, np.tile([1.0, 1, 1, 0.5], (9, 1)), rng.normal(0, 0.05, (n, 3)),
+                        np.zeros(n, np.int8), workloads._field_const(1, (0, 0, 0.5)), contact_on=True,
+                        precision="fp64", name="cutoff_bundle", dipole_cutoff=3.0)
+    x0 = x.copy()
+    x0[:, 2] *= stretch
+    w["x0"] = x0 + np.asarray(shift) + rng.normal(0, 0.05, x.shape)
+    return w
+
+
+@pytest.mark.parametrize("stretch,shift", [(1.0, (0.0, 0.0, 0.0)), (2.5, (0.0, 0.0, 0.0)),
+                                           (1.0, (1.0e4, 0.0, -3.0e3))])
+def test_cells_sharing_a_bucket(stretch, shift):
+    """The sort's key keeps 6 bits of the cell coordinate along the bundle (64
+    cells of side 3.25, enough for the reference lattice). Stretched 2.5 times,
+    cells 64 apart share buckets; shifted by 10^4, the high bits of every
+    cell's coordinates leave the tag's range and cells are told apart by their
+    coordinates. The dipole forces and fields match the oracle in each case."""
+    w = _bundle(stretch, shift)
+    sim = RodSim(w, precision="fp64")
+    st = oracle.run(w, 0)
+    Fo, To = oracle.forces(w, st["x"], st["q"], mask=TERM_DIPOLE)
+    F, T = sim.eval_forces(TERM_DIPOLE)
+    assert rel_inf(F.cpu().numpy().T, Fo, 1e-300) <= 1e-12
+    assert rel_inf(T.cpu().numpy().T, To, 1e-300) <= 1e-12
+    assert np.abs(Fo).max() > 0
+    sim.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_runs_repeat_bit_for_bit(prec):
+    """The same run twice (graphs of 7 steps, lists rebuilt as particles move)
+    ends in the same state, bit for bit."""
+    w = CASES["cilia"]()
+    runs = []
+    for _ in range(2):
+        sim = RodSim(w, precision=prec, graph_steps=7)
+        for n in (13, 10, 1, 6):
+            sim.step(n)
+        runs.append(sim.state())
+        sim.free()
+    for k in ("x", "v", "q", "w", "F", "T"):
+        np.testing.assert_array_equal(runs[0][k], runs[1][k], err_msg=k)
+
