@@ -143,7 +143,9 @@ __device__ __forceinline__ void ew_offsets(int nc, int& lo, int& hi) {
 
 // Real-space force and field: EW_RL lanes per sorted position, lane l taking
 // every EW_RL-th particle of each neighbouring cell; the lanes' sums are added
-// by a fixed xor tree, so the result does not depend on scheduling.
+// by a fixed xor tree, so the result does not depend on scheduling. 1/r from
+// the refined reciprocal square root, r = r^2 / r (no FP64 square root or
+// division per pair).
 constexpr int EW_RL = 8;
 __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -172,27 +174,37 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
   ew_offsets(nx, lx, hx);
   ew_offsets(ny, ly, hy);
   ew_offsets(nz, lz, hz);
+  // Along an axis of at least five cells each neighbouring cell is visited
+  // once, at offset o from the particle's own: its particles' image nearest
+  // the particle is shifted by a whole box length when cell + o leaves the box
+  // (a pair closer than rc <= L/2 has no other image that close). Narrower
+  // axes take the minimum image of each pair.
+  const bool wx = nx < 2 * EW_REACH + 1, wy = ny < 2 * EW_REACH + 1, wz = nz < 2 * EW_REACH + 1;
   for (int oz = lz; oz <= hz && pv; ++oz) {
-    const int gz = (cz + oz + nz) % nz;
+    const int uz = cz + oz, gz = (uz + nz) % nz;
+    const double sz = wz ? 0.0 : (uz < 0 ? Lz : (uz >= nz ? -Lz : 0.0));
     for (int oy = ly; oy <= hy; ++oy) {
-      const int gy = (cy + oy + ny) % ny;
+      const int uy = cy + oy, gy = (uy + ny) % ny;
+      const double sy = wy ? 0.0 : (uy < 0 ? Ly : (uy >= ny ? -Ly : 0.0));
       for (int ox = lx; ox <= hx; ++ox) {
-        const int gx = (cx + ox + nx) % nx;
+        const int ux = cx + ox, gx = (ux + nx) % nx;
+        const double sx = wx ? 0.0 : (ux < 0 ? Lx : (ux >= nx ? -Lx : 0.0));
         const int cc = mem * d.ew_ncell + (gz * ny + gy) * nx + gx;
         const int qe = d.ew_start[cc + 1];
         for (int q = d.ew_start[cc] + sub; q < qe; q += EW_RL) {
           if (q == p) continue;
           const double* rj = d.ew_xm + 8 * (long)q;
-          V3<double> r{xi.x - rj[0], xi.y - rj[1], xi.z - rj[2]};
-          r.x -= Lx * rint(r.x * iLx);  // minimum image
-          r.y -= Ly * rint(r.y * iLy);
-          r.z -= Lz * rint(r.z * iLz);
+          V3<double> r{(xi.x - rj[0]) + sx, (xi.y - rj[1]) + sy, (xi.z - rj[2]) + sz};
+          if (wx) r.x -= Lx * rint(r.x * iLx);  // minimum image
+          if (wy) r.y -= Ly * rint(r.y * iLy);
+          if (wz) r.z -= Lz * rint(r.z * iLz);
           const double r2 = dot(r, r);
           if (!(r2 < rc2)) continue;
           const V3<double> mj{rj[4], rj[5], rj[6]};
-          const double rr = sqrt(r2), ar = a * rr, ar2 = ar * ar;
+          const double ri = rsqrt_nr(r2);  // hardware estimate, two Newton steps
+          const double rr = r2 * ri, ar = a * rr, ar2 = ar * ar;
           const double ex = exp(-ar2), ec = erfc(ar);
-          const double ri = 1.0 / rr, ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2;
+          const double ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2;
           const double Bf = (ec + sp * rr * ex) * ri3;
           const double Cf = (3.0 * ec + sp * rr * (3.0 + 2.0 * ar2) * ex) * ri5;
           const double Df = (15.0 * ec + sp * rr * (15.0 + 10.0 * ar2 + 4.0 * ar2 * ar2) * ex) *
