@@ -23,7 +23,7 @@
 //   scatter: particles grouped by cell; rank: each cell's particles by index
 //            (so the sums below run in a fixed order); pack: an interleaved
 //            copy of wrapped position and moment in sorted order;
-//   real:    eight lanes per sorted position walk the 5 x 5 x 5 neighbouring
+//   real:    16 lanes per sorted position walk the 5 x 5 x 5 neighbouring
 //            cells (every cell of an axis under five cells wide), their sums
 //            added by a fixed xor tree; writes F, B;
 //   sk:      partial structure factors of 256-particle chunks, one thread per
@@ -146,7 +146,7 @@ __device__ __forceinline__ void ew_offsets(int nc, int& lo, int& hi) {
 // by a fixed xor tree, so the result does not depend on scheduling. 1/r from
 // the refined reciprocal square root, r = r^2 / r (no FP64 square root or
 // division per pair).
-constexpr int EW_RL = 8;
+constexpr int EW_RL = 16;
 __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long p = t / EW_RL;
