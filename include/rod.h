@@ -144,8 +144,10 @@ typedef struct rod_desc {
                                  lists from the particles sorted by cell (cells of that side); at
                                  most 256 per particle (more: ROD_E_OVERFLOW at rod_sync). FP64 on
                                  both paths; the sort fixes the list order and the sums, so a run
-                                 repeated gives the same bits.
-                                 Not differentiated: refused with tape_capacity > 0. */
+                                 repeated gives the same bits. With a tape, rod_grad
+                                 differentiates the truncated sum (pairs selected by the
+                                 recorded distances); its reverse pass visits every pair of a
+                                 member (one slot) and tests each against the cutoff. */
   double box[3];              /* Periodic box lengths L_x, L_y, L_z, all > 0; or all 0 (open
                                  boundaries). With a box and dipole_on, the dipole-dipole
                                  interaction is the Ewald sum of each member's periodic system

@@ -334,13 +334,13 @@ def run_jvp(w, nsteps, tangent, step0=0):
 
     ``tangent`` maps any of x0, v0, q0, w0, m_body, field to a direction array.
     Returns (final state dict, final tangent dict) with keys x, v, q, w.
-    Bond damping is not differentiated (its rates depend on stored history)."""
+    Bond damping is not differentiated (its rates depend on stored history). With a
+    dipole cutoff the selection of pairs is taken from the primal distances (the
+    derivative of the truncated sum away from the cutoff)."""
     if has_bond_damping(w):
         raise NotImplementedError("the forward-mode run does not differentiate bond damping")
     if w["contact_on"] and contact_model(w) != 0:
         raise NotImplementedError("the forward-mode run does not differentiate Hertz-Mindlin contact")
-    if w.get("dipole_cutoff"):
-        raise NotImplementedError("the forward-mode run does not differentiate the dipole cutoff")
     if w.get("box") is not None:
         raise NotImplementedError("the forward-mode run does not differentiate the Ewald sum")
     lib = _load()

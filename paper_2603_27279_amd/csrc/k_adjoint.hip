@@ -167,6 +167,18 @@ __device__ __forceinline__ void adj_bond(const Dev& d, const Adj& a, const doubl
 }
 
 // ---------------------------------------------------------------- dipoles
+// Squared distance with explicitly rounded operations: the exact selection of
+// the contact search and of the dipole cutoff.
+__device__ __forceinline__ double r2x(V3<double> p, V3<double> q) {
+  double dx = __dsub_rn(p.x, q.x), dy = __dsub_rn(p.y, q.y), dz = __dsub_rn(p.z, q.z);
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+// Whether pair (i, j) interacts: every pair of a member, or with a cutoff the
+// pairs the forward list walk selects.
+__device__ __forceinline__ bool dip_pair_on(const Dev& d, V3<double> xi, V3<double> xj) {
+  return d.dcut == 0.0 || r2x(xi, xj) < d.dcut * d.dcut;
+}
+
 // Gradients of Phi = grad_r U . g + grad_a U . h with respect to r, a and b.
 __device__ void phi_grad(V3<double> r, V3<double> am, V3<double> bm, V3<double> g, V3<double> hv,
                          V3<double>& dr, V3<double>& da, V3<double>& db) {
@@ -221,6 +233,7 @@ __device__ __forceinline__ void adj_dipole_item(const Dev& d, const Adj& a, cons
     for (int jj = jb; jj < je; ++jj) {
       if (t0 + jj == i) continue;
       const V3<double> xj{sj[0][jj], sj[1][jj], sj[2][jj]};
+      if (!dip_pair_on(d, xi, xj)) continue;
       const V3<double> mj{sj[3][jj], sj[4][jj], sj[5][jj]};
       const V3<double> gj{sj[6][jj], sj[7][jj], sj[8][jj]};
       const V3<double> hj{sj[9][jj], sj[10][jj], sj[11][jj]};
@@ -268,7 +281,7 @@ __device__ __forceinline__ void adj_dipole_small_item(const Dev& d, const Adj& a
     for (int u = 0; u < 2; ++u) {
       const int j = jb + 64 * u;
       if (j >= wk.j1) break;
-      if (j == i) continue;
+      if (j == i || !dip_pair_on(d, xi, xj[u])) continue;
       V3<double> dr, da, db;
       phi_grad(xi - xj[u], mi, mj[u], gi, hi, dr, da, db);  // i as target
       xb = xb - dr;
@@ -289,10 +302,6 @@ __device__ __forceinline__ void adj_dipole_small_item(const Dev& d, const Adj& a
 }
 
 // ---------------------------------------------------------------- contact
-__device__ __forceinline__ double r2x(V3<double> p, V3<double> q) {
-  double dx = __dsub_rn(p.x, q.x), dy = __dsub_rn(p.y, q.y), dz = __dsub_rn(p.z, q.z);
-  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-}
 
 // x-bar_i += J(d) (F-bar_i - F-bar_j) over the contacts j of i, with
 // J(d) = k [ (r_c/r - 1) I - r_c d d^T / r^3 ], d = x_i - x_j. Same search

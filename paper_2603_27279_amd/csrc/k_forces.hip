@@ -64,8 +64,11 @@ hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int n
 
 hipError_t launch_force_pass(const Dev& d, int precision, const DipWork* work, int nwork,
                              int build, hipStream_t s) {
-  hipError_t e = launch_forces(d, precision, work, nwork, s);
+  // with a dipole cutoff the items (if any) are the reverse pass's; the
+  // forward walks the lists
+  hipError_t e = launch_forces(d, precision, work, d.dcut > 0.0 ? 0 : nwork, s);
   if (e == hipSuccess && d.contact_on && !contact_in_forces(d)) e = launch_contact(d, 0, build, s);
+  if (e == hipSuccess && d.dipole_on && d.dcut > 0.0) e = launch_dipole_cut(d, build, s);
   return e;
 }
 

@@ -57,6 +57,10 @@ struct rod_ctx {
   double* ibm_buf = nullptr;  // coupled cycles: fluid velocity and penalty force [6][N]
   DipWork* work = nullptr;
   int nwork = 0, max_slots = 1;
+  // with a dipole cutoff and a tape: all-pairs items of one slot for the
+  // reverse pass (it tests each pair against the cutoff)
+  DipWork* adj_work = nullptr;
+  int adj_nwork = 0;
   std::vector<void*> plan_allocs;   // dipole work list, slot counts, partial slots
   std::vector<int> mrange_h;        // [2M] member particle ranges
   int plan_small = -1, plan_target = 1024;  // current dipole layout
@@ -306,8 +310,6 @@ static int validate(const rod_desc* d) {
   if (d->dipole_on && d->dipole_cutoff > 0) {
     if (!d->contact_on)
       return fail(ROD_E_INVALID, "a dipole cutoff needs contact_on (it walks the contact cells)");
-    if (d->tape_capacity > 0)
-      return fail(ROD_E_INVALID, "the dipole cutoff is not differentiated: no tape with it");
   }
   if (d->tape_capacity > 0 && d->tape_every < 1)
     return fail(ROD_E_INVALID, "a tape needs tape_every >= 1");
@@ -374,6 +376,24 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
         w.slot = s;
         items.push_back(w);
       }
+  }
+  // the reverse pass of a dipole cutoff: every pair of a member in one slot,
+  // each tested against the cutoff (the forward walks its lists instead)
+  std::vector<DipWork> adj;
+  for (int m = 0; m < M && c->d.dcut > 0.0 && c->desc.tape_capacity > 0; ++m) {
+    const int b = mrange[2 * m], e = mrange[2 * m + 1];
+    const int bs = small ? DIP_SMALL_I : 64;
+    for (int i0 = b; i0 < e; i0 += bs) {
+      DipWork w{};
+      w.i0 = i0; w.i1 = std::min(i0 + bs, e); w.j0 = b; w.j1 = e; w.slot = 0;
+      adj.push_back(w);
+    }
+  }
+  c->adj_nwork = (int)adj.size();
+  c->adj_work = nullptr;
+  if (!adj.empty()) {
+    TRY(palloc(c, &c->adj_work, adj.size()));
+    HIPC(hipMemcpy(c->adj_work, adj.data(), adj.size() * sizeof(DipWork), hipMemcpyHostToDevice));
   }
   c->mslots_h = mslots;
   c->mlen_h = mlen;
@@ -1328,7 +1348,9 @@ int rod_grad(rod_ctx* c, const rod_cotangent* gy, rod_gradients* gx) {
   if (!c->tape.active || c->h_step == c->tape.start_step)
     return fail(ROD_E_NOTAPE, "no recorded steps: call rod_tape_begin, then rod_step");
   TRY(enter(c));
-  TRY(adjoint_run(c->tape, c->d, c->desc.precision, c->work, c->nwork, c->s, c->h_step, gy, gx));
+  const bool cut = c->d.dcut > 0.0;
+  TRY(adjoint_run(c->tape, c->d, c->desc.precision, cut ? c->adj_work : c->work,
+                  cut ? c->adj_nwork : c->nwork, c->s, c->h_step, gy, gx));
   TRY(leave(c));
   return ROD_OK;
 }

@@ -91,7 +91,6 @@ def test_query_workspace_and_invalid_descriptors():
         (dict(dipole_cutoff=-1.0), "dipole_cutoff"),
         (dict(dipole_cutoff=float("inf")), "dipole_cutoff"),
         (dict(dipole_cutoff=3.0, contact_on=0), "needs contact_on"),
-        (dict(dipole_cutoff=3.0, tape_capacity=10, tape_every=2), "not differentiated"),
     ]
     hm = lambda *h: (C.c_double * 5)(*h)
     cases += [

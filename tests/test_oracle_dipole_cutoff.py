@@ -2,8 +2,9 @@
 of the paper's simulations): a cutoff wider than the member is the all-pairs
 sum, a pair just inside the cutoff has the closed-form coaxial force and
 energy and one just outside none, an on-axis chain's field is the partial
-sum of 2 C m / k^3 over the neighbours inside the cutoff, and the truncated
-interaction still balances force and angular momentum."""
+sum of 2 C m / k^3 over the neighbours inside the cutoff, the truncated
+interaction still balances force and angular momentum, and the dual-number run
+through a cutoff is the derivative of the run."""
 import numpy as np
 import pytest
 
@@ -84,3 +85,35 @@ def test_truncated_interaction_balances():
     assert np.abs((np.cross(x, F) + T).sum(0)).max() <= 1e-13 * scale
     Fa, _ = oracle.forces(dict(w, dipole_cutoff=0.0), x, q, mask=oracle.DIPOLE)
     assert np.abs(Fa - F).max() > 1e-3 * np.abs(Fa).max()  # the cutoff does cut
+
+
+def test_jvp_through_the_cutoff_matches_central_differences():
+    """A rod of 10 with a cutoff of 2.5: pairs up to two neighbours apart (about
+    1 and 2 apart) interact, the next (about 3 apart) do not, and no distance
+    comes near 2.5 over the run. The dual-number run (pairs selected by the
+    primal distances) equals central differences of the run, and differs from
+    the all-pairs one."""
+    from test_oracle_pins import rel
+    w = workloads.adjoint_rod(n=10, steps=30, dipole_cutoff=2.5)
+    rng = np.random.default_rng(8)
+    tan = {k: rng.normal(size=np.shape(w[k])) for k in ("x0", "v0", "q0", "w0", "m_body")}
+    tan["field"] = rng.normal(size=w["field"].shape)
+    for k in ("x0", "v0", "q0", "w0"):
+        tan[k][0] = 0.0
+    nst = 30
+    st, dT = oracle.run_jvp(w, nst, tan)
+    d = np.linalg.norm(st["x"][:, None, :] - st["x"][None, :, :], axis=-1)
+    assert np.all(np.abs(d - 2.5) > 0.2)
+    h = 1e-6
+
+    def shifted(sgn):
+        w2 = dict(w)
+        for k in ("x0", "v0", "q0", "w0", "m_body", "field"):
+            w2[k] = w[k] + sgn * h * tan[k]
+        return oracle.run(w2, nst)
+    sp, sm = shifted(1), shifted(-1)
+    for k in ("x", "v", "q", "w"):
+        fd = (sp[k] - sm[k]) / (2 * h)
+        assert rel(dT[k], fd) < 1e-6, k
+    _, dA = oracle.run_jvp(dict(w, dipole_cutoff=0.0), nst, tan)
+    assert rel(dA["x"], dT["x"]) > 1e-6  # the cutoff matters
