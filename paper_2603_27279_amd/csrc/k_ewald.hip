@@ -17,15 +17,15 @@
 //
 // Data flow of one evaluation (all on one stream, no atomics in any sum; ten
 // launches):
-//   bin:     each particle's cell (side >= rc / 2, member-major numbering) and
+//   bin:     each particle's cell (side >= rc / 3, member-major numbering) and
 //            its place in the cell (an atomic count);
 //   scan:    first sorted position of every cell (one workgroup);
 //   scatter: particles grouped by cell; rank: each cell's particles by index
 //            (so the sums below run in a fixed order); pack: an interleaved
 //            copy of wrapped position and moment in sorted order;
-//   real:    16 lanes per sorted position walk the 5 x 5 x 5 neighbouring
-//            cells (every cell of an axis under five cells wide), their sums
-//            added by a fixed xor tree; writes F, B;
+//   real:    16 lanes per sorted position walk the 7 x 7 x 7 neighbouring
+//            cells that come within rc (every cell of an axis under seven
+//            cells wide), their sums added by a fixed xor tree; writes F, B;
 //   sk:      partial structure factors of 256-particle chunks, one thread per
 //            segment of up to 8 k vectors along a row;
 //   sreduce: S(k) of each member, its chunks added in order;
@@ -130,7 +130,6 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_pack(Dev d) {
 // Neighbouring cell offsets along an axis of nc cells of side >= rc / EW_REACH:
 // -EW_REACH .. EW_REACH, or every cell of the axis once when it has fewer than
 // 2 EW_REACH + 1 of them.
-constexpr int EW_REACH = 2;
 __device__ __forceinline__ void ew_offsets(int nc, int& lo, int& hi) {
   if (nc >= 2 * EW_REACH + 1) {
     lo = -EW_REACH;
@@ -174,20 +173,32 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
   ew_offsets(nx, lx, hx);
   ew_offsets(ny, ly, hy);
   ew_offsets(nz, lz, hz);
-  // Along an axis of at least five cells each neighbouring cell is visited
-  // once, at offset o from the particle's own: its particles' image nearest
-  // the particle is shifted by a whole box length when cell + o leaves the box
-  // (a pair closer than rc <= L/2 has no other image that close). Narrower
-  // axes take the minimum image of each pair.
+  // Along an axis of at least 2 EW_REACH + 1 cells each neighbouring cell is
+  // visited once, at offset o from the particle's own: its particles' image
+  // nearest the particle is shifted by a whole box length when cell + o leaves
+  // the box (a pair closer than rc <= L/2 has no other image that close), and a
+  // cell whose slab lies farther than rc from the particle is skipped. Narrower
+  // axes take the minimum image of each pair and skip nothing.
   const bool wx = nx < 2 * EW_REACH + 1, wy = ny < 2 * EW_REACH + 1, wz = nz < 2 * EW_REACH + 1;
+  const double hxs = Lx / nx, hys = Ly / ny, hzs = Lz / nz;
+  const double reach2 = rc2 * (1.0 + 1e-9);  // widened so that rounding never drops a cell
+  auto gap = [](double x, int u, double h, bool w) {
+    const double g = w ? 0.0 : fmax(fmax((double)u * h - x, x - (double)(u + 1) * h), 0.0);
+    return g * g;
+  };
   for (int oz = lz; oz <= hz && pv; ++oz) {
     const int uz = cz + oz, gz = (uz + nz) % nz;
+    const double gz2 = gap(xi.z, uz, hzs, wz);
+    if (gz2 > reach2) continue;
     const double sz = wz ? 0.0 : (uz < 0 ? Lz : (uz >= nz ? -Lz : 0.0));
     for (int oy = ly; oy <= hy; ++oy) {
       const int uy = cy + oy, gy = (uy + ny) % ny;
+      const double gyz2 = gz2 + gap(xi.y, uy, hys, wy);
+      if (gyz2 > reach2) continue;
       const double sy = wy ? 0.0 : (uy < 0 ? Ly : (uy >= ny ? -Ly : 0.0));
       for (int ox = lx; ox <= hx; ++ox) {
         const int ux = cx + ox, gx = (ux + nx) % nx;
+        if (gyz2 + gap(xi.x, ux, hxs, wx) > reach2) continue;
         const double sx = wx ? 0.0 : (ux < 0 ? Lx : (ux >= nx ? -Lx : 0.0));
         const int cc = mem * d.ew_ncell + (gz * ny + gy) * nx + gx;
         const int qe = d.ew_start[cc + 1];

@@ -451,10 +451,10 @@ static void ewald_vectors(const rod_desc* dsc, std::vector<double>* kt,
       }
 }
 static int ewald_count(const rod_desc* dsc, int nc[3], int* K, int* TC) {
-  // cells of side >= rcut / 2: the real-space walk reaches two cells each way
+  // cells of side >= rcut / EW_REACH: the real-space walk reaches EW_REACH cells each way
   for (int a = 0; a < 3; ++a)
     nc[a] = (int)std::max(1.0, std::min((double)EW_MAX_NC,
-                                        std::floor(2.0 * dsc->box[a] / dsc->ewald_rcut)));
+                                        std::floor(EW_REACH * dsc->box[a] / dsc->ewald_rcut)));
   std::vector<double> kt;
   ewald_vectors(dsc, &kt);
   *K = (int)(kt.size() / 4);

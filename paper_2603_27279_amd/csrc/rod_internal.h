@@ -130,7 +130,7 @@ struct Dev {
   double* xm;              // [N][8]: x, y, z, m_x, m_y, m_z, 0, 0 of the level (cutoff), or null
   // Periodic box with the Ewald sum of the dipoles (ew_on; k_ewald.hip): box
   // lengths, splitting parameter, real-space cutoff, the self-field
-  // coefficient C 4 a^3 / (3 sqrt(pi)); member-major cells of side >= ew_rc / 2,
+  // coefficient C 4 a^3 / (3 sqrt(pi)); member-major cells of side >= ew_rc / EW_REACH,
   // ew_nc per axis; particles sorted by cell with an interleaved copy of their
   // wrapped positions and moments; the reciprocal vectors of the half space
   // with their coefficients, particle chunks (sorted ranges of one member) and
@@ -256,6 +256,7 @@ hipError_t launch_dipole_sort(const Dev& d, int build, hipStream_t s);
 hipError_t launch_ewald(const Dev& d, hipStream_t s, const hipEvent_t* ev = nullptr);
 constexpr int EW_CHUNK = 256;   // particles per structure-factor chunk
 constexpr int EW_MAX_NC = 256;  // cells per box axis at most
+constexpr int EW_REACH = 3;     // real-space cells of side >= rc / EW_REACH
 // build: rebuild contact candidate lists (large systems) regardless of motion.
 hipError_t launch_contact(const Dev& d, int want_energy, int build, hipStream_t s,
                           const hipEvent_t* ev = nullptr);
