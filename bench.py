@@ -233,16 +233,18 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E (vendor figure)
 #     x and m are other particles' own data
 #   contact (per particle): own position (24), list entry (8), force out (24)
 #   pre (per particle): state x v q w F T and m_body, inverse mass and inertia,
-#     ids (221 in); x v q w, m in FP64 and FP32, cell key and entry (180 out)
+#     ids (221 in); x v q w, m in FP64 and FP32 (140 out). With contact lists
+#     (these systems) the cell-list entry (key, slot, count: 40 more) is written
+#     only at list rebuilds, by the contact launch
 #   kick (per particle): bond outputs of its bond (72), dipole slots (24 each on
 #     the mixed path, 48 in FP64), contact force, state and constants (318 + slots
-#     in); F T x v w q, m twice, cell key and entry (228 out)
+#     in); F T x v w q, m twice (188 out; the cell-list entry as for pre)
 BYTES = {"bond": 165.0, "bond_damped": 269.0, "contact": 56.0, "contact_hm": 128.0,
-         "contact_hm_per_contact": 56.0, "dipole_cutoff": 100.0, "pre": 401.0}
+         "contact_hm_per_contact": 56.0, "dipole_cutoff": 100.0, "pre": 361.0}
 
 
 def kick_bytes(slots, slot_bytes=24.0):
-    return 318.0 + slot_bytes * slots + 228.0
+    return 318.0 + slot_bytes * slots + 188.0
 
 
 def hbm_microbench(sizes, steps=10):

@@ -96,6 +96,21 @@ __global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
   chunk_box(d, i, x, valid);
 }
 
+// Cell-list entries of the level being evaluated, when its contact lists are
+// rebuilt (lazy_cells: the particle kernels left the list empty).
+__global__ __launch_bounds__(256) void k_cell_insert(Dev d, int build) {
+  if (!build && d.rebuild[d.step[d.lc] & 1] == 0u) return;  // the lists stay
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const long N = d.n;
+  cell_insert(d, i, ld3(d.x, N, i), d.mem[i], d.rod[i], d.step[d.lc]);
+}
+
+hipError_t launch_cell_insert(const Dev& d, int build, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_insert, dim3((unsigned)((d.n + 255) / 256)), dim3(256), 0, s, d, build);
+  return hipGetLastError();
+}
+
 // The pre kernel's work for particle i; returns its position at level lvl.
 __device__ __forceinline__ V3<double> pre_particle(const Dev& d, long i, int mode, long long n,
                                                    long long lvl) {
@@ -130,7 +145,7 @@ __device__ __forceinline__ V3<double> pre_particle(const Dev& d, long i, int mod
     }
     st4(d.q, N, i, q);
   }
-  moment_and_cell(d, i, q, x, mb, mem, rod, lvl);
+  moment_and_cell(d, i, q, x, mb, mem, rod, lvl, !(d.lazy_cells && mode == PRE_STEP));
   return x;
 }
 
@@ -384,7 +399,7 @@ __global__ __launch_bounds__(256) void k_kick(Dev d, double* Bo) {
     kick(d, i, F, T, p, apart);
     if (d.contact_on) cell_tab(d, L).cnt[key] = 0;
     advance(d, i, p.b, L + 1, p.x, p.v, p.q, p.w, F, T, p.minv, p.Iinv, apart);
-    moment_and_cell(d, i, p.q, p.x, p.mb, p.mem, p.rod, L + 1);
+    moment_and_cell(d, i, p.q, p.x, p.mb, p.mem, p.rod, L + 1, !d.lazy_cells);
     x = p.x;
   }
   chunk_box(d, i, x, valid);

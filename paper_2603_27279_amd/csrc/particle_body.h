@@ -5,10 +5,31 @@
 
 namespace rodmx {
 
-// Dipole moment in the global frame, m = q m_body q*, and the particle's entry
-// in the cell list of level lvl.
+// The particle's entry in the cell list of level lvl.
+__device__ __forceinline__ void cell_insert(const Dev& d, long i, V3<double> x, int mem, int rod,
+                                            long long lvl) {
+  const CellTab t = cell_tab(d, lvl);
+  unsigned key = cell_hash(cell_coord(x.x, d.inv_cell), cell_coord(x.y, d.inv_cell),
+                           cell_coord(x.z, d.inv_cell), mem, d.cell_mask);
+  int slot = atomicAdd(&t.cnt[key], 1);
+  if (slot < CELL_CAP) {
+    CellSlot e;
+    e.x = x.x; e.y = x.y; e.z = x.z;
+    e.tag = (long long)(unsigned)i | ((long long)rod << 32);
+    t.slot[(long)key * CELL_CAP + slot] = e;
+  } else {
+    int o = atomicAdd(t.ovf_cnt, 1);
+    if (o < OVF_CAP) t.ovf[o] = (int)i;
+    else atomicOr(&d.flags[FLAG_LIST_OVF], 1u);
+  }
+  d.key[i] = (int)key;
+}
+
+// Dipole moment in the global frame, m = q m_body q*, and (insert) the
+// particle's entry in the cell list of level lvl.
 __device__ __forceinline__ void moment_and_cell(const Dev& d, long i, Q4<double> q, V3<double> x,
-                                                V3<double> mb, int mem, int rod, long long lvl) {
+                                                V3<double> mb, int mem, int rod, long long lvl,
+                                                bool insert = true) {
 #pragma clang fp contract(on)  // round alike wherever it is inlined
   const long N = d.n;
   V3<double> m = qrot(q, mb);
@@ -19,23 +40,7 @@ __device__ __forceinline__ void moment_and_cell(const Dev& d, long i, Q4<double>
     p[0] = x.x; p[1] = x.y; p[2] = x.z;
     p[3] = m.x; p[4] = m.y; p[5] = m.z; p[6] = 0.0; p[7] = 0.0;
   }
-  if (d.contact_on) {
-    const CellTab t = cell_tab(d, lvl);
-    unsigned key = cell_hash(cell_coord(x.x, d.inv_cell), cell_coord(x.y, d.inv_cell),
-                             cell_coord(x.z, d.inv_cell), mem, d.cell_mask);
-    int slot = atomicAdd(&t.cnt[key], 1);
-    if (slot < CELL_CAP) {
-      CellSlot e;
-      e.x = x.x; e.y = x.y; e.z = x.z;
-      e.tag = (long long)(unsigned)i | ((long long)rod << 32);
-      t.slot[(long)key * CELL_CAP + slot] = e;
-    } else {
-      int o = atomicAdd(t.ovf_cnt, 1);
-      if (o < OVF_CAP) t.ovf[o] = (int)i;
-      else atomicOr(&d.flags[FLAG_LIST_OVF], 1u);
-    }
-    d.key[i] = (int)key;
-  }
+  if (d.contact_on && insert) cell_insert(d, i, x, mem, rod, lvl);
 }
 
 // Bounding box of the wave's 64 particles (a 64-aligned chunk: the

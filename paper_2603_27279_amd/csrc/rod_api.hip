@@ -638,16 +638,23 @@ struct NoRecord {
 // modes: pre, forces, post per step.
 static int enqueue_steps(rod_ctx* c, int64_t n) {
   if (n <= 0) return ROD_OK;
+  // contact by candidate lists: the particle kernels of the stepping chain leave
+  // the cell list empty, and the contact launch fills it when the lists are
+  // rebuilt (the cell list serves nothing else between rebuilds)
+  const int lazy = c->d.contact_on && c->d.use_lists && !contact_in_forces(c->d);
   if (c->launch_mode != ROD_LAUNCH_BATCHED) {
+    Dev d = c->d;
+    d.lazy_cells = lazy;
     for (int64_t k = 0; k < n; ++k) {
-      TIMED(c, ROD_KERNEL_PRE, launch_pre, c->d, PRE_STEP, c->s);
-      TRY(force_terms(c, c->d, 0, k == 0));
-      TIMED(c, ROD_KERNEL_POST, launch_post, c->d, POST_KICK, ROD_TERM_ALL, nullptr, nullptr,
+      TIMED(c, ROD_KERNEL_PRE, launch_pre, d, PRE_STEP, c->s);
+      TRY(force_terms(c, d, 0, k == 0));
+      TIMED(c, ROD_KERNEL_POST, launch_post, d, POST_KICK, ROD_TERM_ALL, nullptr, nullptr,
             nullptr, c->s);
     }
     return ROD_OK;
   }
   Dev d = c->d;  // d.lc = 1
+  d.lazy_cells = lazy;
   TIMED(c, ROD_KERNEL_PRE, launch_pre, d, PRE_STEP, c->s);
   TRY(force_terms(c, d, 0, 1));
   for (int64_t k = 1; k < n; ++k) {
@@ -946,6 +953,7 @@ int rod_init(rod_ctx** out, const rod_desc* dsc, const rod_buffers* b, void* hip
   d.hm = dsc->contact_on && dsc->contact_model == ROD_CONTACT_HERTZ_MINDLIN;
   d.dcut = dsc->dipole_on && dsc->dipole_cutoff > 0 ? dsc->dipole_cutoff : 0.0;
   d.use_lists = dsc->contact_on && ((long)N >= CONTACT_LANES_MAX_N || d.dcut > 0);
+  d.lazy_cells = 0;  // set in the stepping chain's copy
   d.skin = NBR_SKIN * dsc->r_contact;
   // with lists the 27 cells around a particle must cover the list cutoff r_c + skin
   if (d.use_lists) d.inv_cell = 1.0 / (dsc->r_contact + d.skin);

@@ -60,6 +60,10 @@ struct Dev {
   unsigned cell_mask;      // cells - 1 (power of two)
   // Contact candidate lists of large systems (use_lists): see contact_listed.
   int use_lists;
+  // Stepping of a system whose contact search walks candidate lists: the
+  // particle kernels leave the cell list empty and k_cell_insert fills it
+  // only when the lists are rebuilt (set in the stepping chain's copy only).
+  int lazy_cells;
   int* nbr;                // [NBR_CAP][N] candidates of each particle at the last build
   int* nbr_cnt;            // [N] candidates listed, or -1 when more than NBR_CAP
   double* xb;              // [3N] positions at the last build
@@ -237,6 +241,10 @@ inline void launch_k(const hipEvent_t* ev, void (*kernel)(KArgs...), dim3 g, dim
 }
 
 hipError_t launch_pre(const Dev& d, int mode, hipStream_t s, const hipEvent_t* ev = nullptr);
+// Cell-list entries of the current level for a rebuild of the contact lists
+// (nothing unless the lists are stale or `build`); the stepping chain of a
+// system with lazy_cells.
+hipError_t launch_cell_insert(const Dev& d, int build, hipStream_t s);
 // Kinetic energy of each member into out[M]; positions of idx[0..n) into out[n][3].
 hipError_t launch_kinetic(const Dev& d, double* out, hipStream_t s);
 hipError_t launch_gather_x(const Dev& d, const int* idx, int n, double* out, hipStream_t s);
