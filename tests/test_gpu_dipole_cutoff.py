@@ -200,3 +200,27 @@ def test_runs_repeat_bit_for_bit(prec):
     for k in ("x", "v", "q", "w", "F", "T"):
         np.testing.assert_array_equal(runs[0][k], runs[1][k], err_msg=k)
 
+
+@pytest.mark.parametrize("grid,npr", [((32, 16), 512), ((64, 64), 1024)])
+def test_full_size_sampled_rows(grid, npr):
+    """The rod array at the benchmark's sizes with a cutoff of 3 (262,144
+    particles, and the 4.2M-particle array of the memory-bound legs), mixed
+    path, graphs of 10: after 20 steps (lists rebuilt at the call's first step
+    and whenever a particle passes 0.45 of the skin), the dipole force and field
+    of 48 sampled particles match the oracle's truncated sums at the GPU's
+    state."""
+    w = workloads.rod_array(grid=grid, n_per_rod=npr, dipole_on=True, dipole_cutoff=3.0)
+    sim = RodSim(w, precision="mixed", graph_steps=10)
+    sim.step(20)
+    sim.sync()
+    g = sim.state()
+    rows = np.sort(np.random.default_rng(1).choice(w["n"], 48, replace=False))
+    rows[0] = 0
+    rows[-1] = w["n"] - 1
+    F, T, B = sim.eval_forces(TERM_DIPOLE, with_field=True)
+    Fo, Bo, _ = oracle.rows(w, g["x"], g["q"], rows)
+    F, B = F.cpu().numpy().T[rows], B.cpu().numpy().T[rows]
+    assert rel_inf(F, Fo) <= 1e-12, rel_inf(F, Fo)
+    assert rel_inf(B, Bo) <= 1e-12, rel_inf(B, Bo)
+    sim.free()
+
