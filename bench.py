@@ -99,6 +99,15 @@ def cutoff_neighbours(w):
     return _lattice_neighbours(w, w["dipole_cutoff"] + 0.25 * w["r_contact"])
 
 
+def contact_list_len(w):
+    """Mean contact list length of the rod array: partners within r_contact plus
+    the skin r_contact / 4 that are not bonded neighbours of the same rod
+    (|i - j| <= exclude_depth along the rod)."""
+    rad = 1.25 * w["r_contact"]
+    same_rod = sum(1 for k in range(1, int(w["exclude_depth"]) + 1) if k < rad)
+    return _lattice_neighbours(w, rad) - 2.0 * same_rod
+
+
 def cutoff_pairs(w):
     """Mean number of partners within the cutoff itself (the pairs evaluated)."""
     return _lattice_neighbours(w, w["dipole_cutoff"])
@@ -231,7 +240,9 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E (vendor figure)
 #   dipoles within a cutoff, list walk (per particle): own x and m (48), list
 #     count (4), force and field out (48), and 4 per list entry; the partners'
 #     x and m are other particles' own data
-#   contact (per particle): own position (24), list entry (8), force out (24)
+#   contact list walk (per particle): own position (24), list length (4), force
+#     out (24), and 4 per list entry (the member range and rod id are read only
+#     by a cell search)
 #   pre (per particle): state x v q w F T and m_body, inverse mass and inertia,
 #     ids (221 in); x v q w, m in FP64 and FP32 (140 out). With contact lists
 #     (these systems) the cell-list entry (key, slot, count: 40 more) is written
@@ -239,7 +250,7 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E (vendor figure)
 #   kick (per particle): bond outputs of its bond (72), dipole slots (24 each on
 #     the mixed path, 48 in FP64), contact force, state and constants (318 + slots
 #     in); F T x v w q, m twice (188 out; the cell-list entry as for pre)
-BYTES = {"bond": 165.0, "bond_damped": 269.0, "contact": 56.0, "contact_hm": 128.0,
+BYTES = {"bond": 165.0, "bond_damped": 269.0, "contact": 52.0, "contact_hm": 128.0,
          "contact_hm_per_contact": 56.0, "dipole_cutoff": 100.0, "pre": 361.0}
 
 
@@ -278,10 +289,16 @@ def hbm_microbench(sizes, steps=10):
         kt = timed[steps + 1]
         res["bond"] = entry(1e3 * kt["bond"][0] / kt["bond"][1], n - R, BYTES["bond"])
         res["pre"] = entry(1e3 * kt["pre"][0] / kt["pre"][1], n, BYTES["pre"])
-        build_us = 1e3 * timed[1]["contact"][0]
+        # a rebuild step: the cell-list fill and the contact launch that builds
+        # the lists; other steps: the walk, after a fill launch that finds the
+        # lists current and does nothing (reported as cell_gate_us)
+        build_us = 1e3 * (timed[1]["contact"][0] + timed[1]["cells"][0])
         walk_us = 1e3 * (kt["contact"][0] - timed[1]["contact"][0]) / steps
-        res["contact"] = entry(walk_us, n, BYTES["contact"])
+        listed = contact_list_len(w)
+        res["contact"] = entry(walk_us, n, BYTES["contact"] + 4.0 * listed)
+        res["contact"]["list_entries"] = listed
         res["contact"]["list_build_us"] = build_us
+        res["contact"]["cell_gate_us"] = 1e3 * (kt["cells"][0] - timed[1]["cells"][0]) / steps
         sim.launch_mode("batched")
         sim.timing(True)
         sim.step(steps + 1)
@@ -317,7 +334,9 @@ def hbm_microbench(sizes, steps=10):
         res["contact_hm"] = entry(walk_us, n,
                                   BYTES["contact_hm"] + BYTES["contact_hm_per_contact"] * per)
         res["contact_hm"]["contacts_per_particle"] = per
-        res["contact_hm"]["list_build_us"] = 1e3 * timed[1]["contact"][0]
+        res["contact_hm"]["list_build_us"] = 1e3 * (timed[1]["contact"][0] + timed[1]["cells"][0])
+        res["contact_hm"]["cell_gate_us"] = 1e3 * (timed[steps + 1]["cells"][0]
+                                                   - timed[1]["cells"][0]) / steps
         # dipoles within a cutoff of 3 from the Verlet lists
         wc = dict(w, dipole_on=True, dipole_cutoff=3.0)
         sim = RodSim(wc, precision="mixed", graph_steps=0)

@@ -308,7 +308,9 @@ enum {
   ROD_KERNEL_POST = 4,    /* force gather, Zeeman, damping, second half-kick */
   ROD_KERNEL_FORCES = 5,  /* dipole, bond and (below 65536 particles) contact in one launch */
   ROD_KERNEL_KICK = 6,    /* post of one step fused with pre of the next */
-  ROD_KERNEL_COUNT = 7
+  ROD_KERNEL_CELLS = 7,   /* cell-list fill before the contact launch when stepping with
+                             candidate lists (empty unless the lists are rebuilt) */
+  ROD_KERNEL_COUNT = 8
 };
 int rod_timing(rod_ctx* c, int32_t enable);
 int rod_kernel_times(rod_ctx* c, double* ms, int64_t* launches);

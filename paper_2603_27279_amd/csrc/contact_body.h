@@ -198,10 +198,8 @@ __device__ __forceinline__ void contact_listed(const Dev& d, long blk, bool buil
   const long i = d.i_lo + blk * blockDim.x + threadIdx.x;
   if (i >= d.i_hi) return;
   const V3<double> xi = ld3(d.x, N, i);
-  const int mem = d.mem[i], rod = d.rod[i];
-  const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
+  const int cnt = build ? -1 : d.nbr_cnt[i];
   const double rc2 = d.rc * d.rc;
-  const double rs = d.rc + d.skin, rs2 = rs * rs;
   Fix3 f{};
   auto force = [&](V3<double> xj) {
     const double r2 = r2_exact(xi, xj);
@@ -210,30 +208,34 @@ __device__ __forceinline__ void contact_listed(const Dev& d, long blk, bool buil
     const double s = (d.kc * (d.rc - r)) / r;
     fix_add(f, s * (xi - xj), d.fix_scale[0], d.flags + FLAG_CONTACT_RANGE);
   };
-  auto excluded = [&](int j, int rj) {
-    return j == (int)i || j < mb || j >= me || (rj == rod && abs(j - (int)i) <= d.depth);
-  };
-  const CellTab tab = cell_tab(d, d.step[d.lc]);
-  if (build) {
-    int cnt = 0;
-    for_cell_candidates(d, tab, xi, mem, [&](int j, int rj, V3<double> xj) {
-      if (excluded(j, rj)) return;
-      if (r2_exact(xi, xj) < rs2) {
-        if (cnt < NBR_CAP) d.nbr[(long)cnt * N + i] = j;
-        ++cnt;
-      }
-      force(xj);
-    });
-    d.nbr_cnt[i] = cnt <= NBR_CAP ? cnt : -1;
-    st3(d.xb, N, i, xi);
+  if (cnt >= 0) {  // the list: its entries passed the exclusions when it was built
+    for (int k = 0; k < cnt; ++k) force(ld3(d.x, N, d.nbr[(long)k * N + i]));
   } else {
-    const int cnt = d.nbr_cnt[i];
-    if (cnt < 0) {
+    // a rebuild, or a list that overflowed: search the cells (the member range
+    // and rod id are read only here, so that a walk is one round trip)
+    const int mem = d.mem[i], rod = d.rod[i];
+    const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
+    auto excluded = [&](int j, int rj) {
+      return j == (int)i || j < mb || j >= me || (rj == rod && abs(j - (int)i) <= d.depth);
+    };
+    const CellTab tab = cell_tab(d, d.step[d.lc]);
+    if (build) {
+      const double rs = d.rc + d.skin, rs2 = rs * rs;
+      int nc = 0;
+      for_cell_candidates(d, tab, xi, mem, [&](int j, int rj, V3<double> xj) {
+        if (excluded(j, rj)) return;
+        if (r2_exact(xi, xj) < rs2) {
+          if (nc < NBR_CAP) d.nbr[(long)nc * N + i] = j;
+          ++nc;
+        }
+        force(xj);
+      });
+      d.nbr_cnt[i] = nc <= NBR_CAP ? nc : -1;
+      st3(d.xb, N, i, xi);
+    } else {
       for_cell_candidates(d, tab, xi, mem, [&](int j, int rj, V3<double> xj) {
         if (!excluded(j, rj)) force(xj);
       });
-    } else {
-      for (int k = 0; k < cnt; ++k) force(ld3(d.x, N, d.nbr[(long)k * N + i]));
     }
   }
   st3(d.cF, N, i, fix_value(f, d.fix_inv[0]));
@@ -306,8 +308,6 @@ __device__ __forceinline__ void contact_hm_thread(const Dev& d, long blk, bool b
   const long i = d.i_lo + blk * blockDim.x + threadIdx.x;
   if (i >= d.i_hi) return;
   const V3<double> xi = ld3(d.x, N, i), vi = ld3(d.v, N, i), wi = ld3(d.w, N, i);
-  const int mem = d.mem[i], rod = d.rod[i];
-  const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
   const double rc2 = d.rc * d.rc;
   const long long L = d.step[d.lc];
   const long pp = (long)((L - 1) & 1), pc = (long)(L & 1);
@@ -319,9 +319,6 @@ __device__ __forceinline__ void contact_hm_thread(const Dev& d, long blk, bool b
   Fix3 f{}, t{};
   Fix128 fe{};
   int cnt = 0;
-  auto excluded = [&](int j, int rj) {
-    return j == (int)i || j < mb || j >= me || (rj == rod && abs(j - (int)i) <= d.depth);
-  };
   auto visit = [&](int j, V3<double> xj) {
     const double r2 = r2_exact(xi, xj);
     if (!(r2 < rc2)) return;
@@ -359,6 +356,12 @@ __device__ __forceinline__ void contact_hm_thread(const Dev& d, long blk, bool b
       visit(j, ld3(d.x, N, j));
     }
   } else {
+    // the cell search (member range and rod id read only here)
+    const int mem = d.mem[i], rod = d.rod[i];
+    const int mb = d.mrange[2 * mem], me = d.mrange[2 * mem + 1];
+    auto excluded = [&](int j, int rj) {
+      return j == (int)i || j < mb || j >= me || (rj == rod && abs(j - (int)i) <= d.depth);
+    };
     const bool mk = lists && build;
     const double rs = d.rc + d.skin, rs2 = rs * rs;
     int nc = 0;

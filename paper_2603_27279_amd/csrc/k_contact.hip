@@ -63,17 +63,6 @@ hipError_t launch_clear_cells(const Dev& d, hipStream_t s) {
 hipError_t launch_contact(const Dev& d, int want_energy, int build, hipStream_t s,
                           const hipEvent_t* ev) {
   if (!d.contact_on) return hipSuccess;
-  if (d.lazy_cells && !want_energy && d.n >= CONTACT_LANES_MAX_N) {
-    // stepping with lists: the cell list is filled only for a rebuild; the
-    // event pair (timing mode) brackets both launches
-    Dev e = d;
-    e.lazy_cells = 0;
-    hipError_t r;
-    if (ev && (r = hipEventRecord(ev[0], s)) != hipSuccess) return r;
-    if ((r = launch_cell_insert(d, build, s)) != hipSuccess) return r;
-    if ((r = launch_contact(e, 0, build, s, nullptr)) != hipSuccess) return r;
-    return ev ? hipEventRecord(ev[1], s) : hipSuccess;
-  }
   if (d.hm) {
     const dim3 g(contact_blocks(d));
     if (d.n < CONTACT_LANES_MAX_N) {

@@ -97,17 +97,43 @@ __global__ __launch_bounds__(256) void k_pre(Dev d, int mode) {
 }
 
 // Cell-list entries of the level being evaluated, when its contact lists are
-// rebuilt (lazy_cells: the particle kernels left the list empty).
+// rebuilt (lazy_cells: the particle kernels left the list empty). Most steps
+// keep their lists, and then every workgroup only reads the flag: the grid is
+// capped at CELL_INSERT_WGS workgroups (a few per compute unit), each thread
+// striding over the particles CELL_INSERT_ILP at a time, so that their loads
+// and slot claims are in flight together.
+constexpr int CELL_INSERT_WGS = 1024;
+constexpr int CELL_INSERT_ILP = 4;
 __global__ __launch_bounds__(256) void k_cell_insert(Dev d, int build) {
-  if (!build && d.rebuild[d.step[d.lc] & 1] == 0u) return;  // the lists stay
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.n) return;
+  const long long lvl = d.step[d.lc];
+  if (!build && d.rebuild[lvl & 1] == 0u) return;  // the lists stay
   const long N = d.n;
-  cell_insert(d, i, ld3(d.x, N, i), d.mem[i], d.rod[i], d.step[d.lc]);
+  const long G = (long)gridDim.x * blockDim.x;
+  const CellTab t = cell_tab(d, lvl);
+  for (long i0 = (long)blockIdx.x * blockDim.x + threadIdx.x; i0 < N; i0 += CELL_INSERT_ILP * G) {
+    V3<double> x[CELL_INSERT_ILP];
+    int rod[CELL_INSERT_ILP], slot[CELL_INSERT_ILP];
+    unsigned key[CELL_INSERT_ILP];
+#pragma unroll
+    for (int u = 0; u < CELL_INSERT_ILP; ++u) {
+      const long i = i0 + u * G < N ? i0 + u * G : i0;
+      x[u] = ld3(d.x, N, i);
+      rod[u] = d.rod[i];
+      key[u] = cell_key(d, x[u], d.mem[i]);
+    }
+#pragma unroll
+    for (int u = 0; u < CELL_INSERT_ILP; ++u)  // the claims, all in flight
+      slot[u] = i0 + u * G < N ? atomicAdd(&t.cnt[key[u]], 1) : 0;
+#pragma unroll
+    for (int u = 0; u < CELL_INSERT_ILP; ++u)
+      if (i0 + u * G < N) cell_place(d, t, i0 + u * G, x[u], rod[u], key[u], slot[u]);
+  }
 }
 
-hipError_t launch_cell_insert(const Dev& d, int build, hipStream_t s) {
-  hipLaunchKernelGGL(k_cell_insert, dim3((unsigned)((d.n + 255) / 256)), dim3(256), 0, s, d, build);
+hipError_t launch_cell_insert(const Dev& d, int build, hipStream_t s, const hipEvent_t* ev) {
+  const long blocks = (d.n + 255) / 256;
+  launch_k(ev, k_cell_insert, dim3((unsigned)(blocks < CELL_INSERT_WGS ? blocks : CELL_INSERT_WGS)), dim3(256),
+           s, d, build);
   return hipGetLastError();
 }
 

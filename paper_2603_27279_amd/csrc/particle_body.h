@@ -5,13 +5,16 @@
 
 namespace rodmx {
 
-// The particle's entry in the cell list of level lvl.
-__device__ __forceinline__ void cell_insert(const Dev& d, long i, V3<double> x, int mem, int rod,
-                                            long long lvl) {
-  const CellTab t = cell_tab(d, lvl);
-  unsigned key = cell_hash(cell_coord(x.x, d.inv_cell), cell_coord(x.y, d.inv_cell),
-                           cell_coord(x.z, d.inv_cell), mem, d.cell_mask);
-  int slot = atomicAdd(&t.cnt[key], 1);
+// Cell-list key of a particle at x in member mem.
+__device__ __forceinline__ unsigned cell_key(const Dev& d, V3<double> x, int mem) {
+  return cell_hash(cell_coord(x.x, d.inv_cell), cell_coord(x.y, d.inv_cell),
+                   cell_coord(x.z, d.inv_cell), mem, d.cell_mask);
+}
+
+// Store particle i in the slot it claimed in cell `key` of table t (the
+// overflow list past CELL_CAP entries), and its key.
+__device__ __forceinline__ void cell_place(const Dev& d, const CellTab& t, long i, V3<double> x,
+                                           int rod, unsigned key, int slot) {
   if (slot < CELL_CAP) {
     CellSlot e;
     e.x = x.x; e.y = x.y; e.z = x.z;
@@ -23,6 +26,14 @@ __device__ __forceinline__ void cell_insert(const Dev& d, long i, V3<double> x, 
     else atomicOr(&d.flags[FLAG_LIST_OVF], 1u);
   }
   d.key[i] = (int)key;
+}
+
+// The particle's entry in the cell list of level lvl.
+__device__ __forceinline__ void cell_insert(const Dev& d, long i, V3<double> x, int mem, int rod,
+                                            long long lvl) {
+  const CellTab t = cell_tab(d, lvl);
+  const unsigned key = cell_key(d, x, mem);
+  cell_place(d, t, i, x, rod, key, atomicAdd(&t.cnt[key], 1));
 }
 
 // Dipole moment in the global frame, m = q m_body q*, and (insert) the

@@ -600,12 +600,21 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
 }
 
 // ------------------------------------------------------------------ schedule
+// Contact of one level. Stepping with candidate lists (lazy_cells), the cell
+// list is filled first, by a launch that does nothing unless the lists are
+// rebuilt (timed as a class of its own, so that the contact time is the walk's).
+static int contact_term(rod_ctx* c, const Dev& d, int want_energy, int build) {
+  if (d.lazy_cells && !want_energy && !contact_in_forces(d))
+    TIMED(c, ROD_KERNEL_CELLS, launch_cell_insert, d, build, c->s);
+  TIMED(c, ROD_KERNEL_CONTACT, launch_contact, d, want_energy, build, c->s);
+  return ROD_OK;
+}
+
 // build: rebuild the contact candidate lists of large systems this step.
 static int force_terms(rod_ctx* c, const Dev& d, int want_energy, int build) {
   if (!want_energy && c->launch_mode == ROD_LAUNCH_BATCHED) {
     TIMED(c, ROD_KERNEL_FORCES, launch_forces, d, c->desc.precision, c->work, c->nwork, c->s);
-    if (c->desc.contact_on && !contact_in_forces(d))
-      TIMED(c, ROD_KERNEL_CONTACT, launch_contact, d, 0, build, c->s);
+    if (c->desc.contact_on && !contact_in_forces(d)) TRY(contact_term(c, d, 0, build));
     if (d.dcut > 0) TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole_cut, d, build, c->s);
     if (d.ew_on) TIMED(c, ROD_KERNEL_DIPOLE, launch_ewald, d, c->s);
     return ROD_OK;
@@ -617,8 +626,7 @@ static int force_terms(rod_ctx* c, const Dev& d, int want_energy, int build) {
     TIMED(c, ROD_KERNEL_DIPOLE, launch_ewald, d, c->s);
   else if (c->desc.dipole_on)
     TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole, d, c->desc.precision, c->work, c->nwork, c->s);
-  if (c->desc.contact_on)
-    TIMED(c, ROD_KERNEL_CONTACT, launch_contact, d, want_energy, build, c->s);
+  if (c->desc.contact_on) TRY(contact_term(c, d, want_energy, build));
   return ROD_OK;
 }
 static int force_terms(rod_ctx* c, int want_energy) { return force_terms(c, c->d, want_energy, 1); }

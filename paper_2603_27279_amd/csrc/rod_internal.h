@@ -244,7 +244,8 @@ hipError_t launch_pre(const Dev& d, int mode, hipStream_t s, const hipEvent_t* e
 // Cell-list entries of the current level for a rebuild of the contact lists
 // (nothing unless the lists are stale or `build`); the stepping chain of a
 // system with lazy_cells.
-hipError_t launch_cell_insert(const Dev& d, int build, hipStream_t s);
+hipError_t launch_cell_insert(const Dev& d, int build, hipStream_t s,
+                              const hipEvent_t* ev = nullptr);
 // Kinetic energy of each member into out[M]; positions of idx[0..n) into out[n][3].
 hipError_t launch_kinetic(const Dev& d, double* out, hipStream_t s);
 hipError_t launch_gather_x(const Dev& d, const int* idx, int n, double* out, hipStream_t s);
