@@ -351,7 +351,12 @@ int rod_launch_mode(rod_ctx* c, int32_t mode);
 
 /* Set the dipole work layout directly: small = 1 small-member layout (ignored
  * for members above 16384 particles), 0 split layout aiming at target_wgs
- * work items, -1 the default rule. Invalidates captured graphs. */
+ * work items, 2 the split layout over each member's particles taken in a
+ * space-filling-curve (Morton) order of their positions at this call (on the
+ * mixed path more of its 64-source sub-tiles are far from their targets and
+ * take the cheaper position differences; sums are as deterministic as in
+ * particle order, but rounded in another order), -1 the default rule.
+ * Invalidates captured graphs. */
 int rod_dipole_layout(rod_ctx* c, int32_t small, int32_t target_wgs);
 
 /* Quasi-static field ramp: the loading protocol of the magnetised beams in

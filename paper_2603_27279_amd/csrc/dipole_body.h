@@ -163,8 +163,9 @@ __device__ __forceinline__ bool far_tile_pairs(const Dev& d, int jg0, int jg1, i
                                                const Src<float>* tile, float4* rel,
                                                Acc<float>& A) {
   const int lane = threadIdx.x & 63;
-  const double* b0 = d.cbox + 6 * (jg0 >> 6);
-  const double* b1 = d.cbox + 6 * ((jg1 - 1) >> 6);
+  const double* boxes = d.dperm ? d.sbox : d.cbox;  // chunks of positions
+  const double* b0 = boxes + 6 * (jg0 >> 6);
+  const double* b1 = boxes + 6 * ((jg1 - 1) >> 6);
   const double lx = fmin(b0[0], b1[0]), ly = fmin(b0[1], b1[1]), lz = fmin(b0[2], b1[2]);
   const double hx = fmax(b0[3], b1[3]), hy = fmax(b0[4], b1[4]), hz = fmax(b0[5], b1[5]);
   const double ox = 0.5 * (lx + hx), oy = 0.5 * (ly + hy), oz = 0.5 * (lz + hz);
@@ -213,15 +214,17 @@ union DipSmem {
   double red[4][NACC][64];
 };
 
-// One work item of the split layout (256 threads).
+// One work item of the split layout (256 threads). Its ranges are positions:
+// particles themselves, or places in the spatial order (d.dperm).
 template <class R>
 __device__ __forceinline__ void dipole_item(const Dev& d, const DipWork& wk, DipSmem<R>& sm) {
   Src<R>* tile = sm.st.tile;
   const long N = d.n;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
-  const int i = wk.i0 + lane;
-  const bool act = i < wk.i1;
+  const int ip = wk.i0 + lane;  // target position
+  const bool act = ip < wk.i1;
+  const int i = act && d.dperm ? d.dperm[ip] : ip;  // target particle
   const R* mu;
   if constexpr (sizeof(R) == 4) mu = (const R*)d.muf;
   else mu = (const R*)d.mu;
@@ -235,7 +238,7 @@ __device__ __forceinline__ void dipole_item(const Dev& d, const DipWork& wk, Dip
   for (int t0 = wk.j0; t0 < wk.j1; t0 += TJ) {
     const int jn = min(TJ, wk.j1 - t0);
     if ((int)threadIdx.x < jn) {
-      const int j = t0 + threadIdx.x;
+      const int j = d.dperm ? d.dperm[t0 + threadIdx.x] : t0 + threadIdx.x;
       tile[threadIdx.x] = Src<R>{d.x[j], d.x[N + j], d.x[2 * N + j], mu[j], mu[N + j], mu[2 * N + j]};
     }
     __syncthreads();
@@ -250,10 +253,10 @@ __device__ __forceinline__ void dipole_item(const Dev& d, const DipWork& wk, Dip
                                sm.st.rel[wave], A);
       const bool self = (t0 + jb < wk.i1) && (t0 + je > wk.i0);  // sub-tile may contain i
       if (far) {
-      } else if (self) {
-        tile_pairs<R, true>(jb, je, t0, i, xi, yi, zi, mix, miy, miz, tile, A);
+      } else if (self) {  // (the pair of a position with itself adds nothing)
+        tile_pairs<R, true>(jb, je, t0, ip, xi, yi, zi, mix, miy, miz, tile, A);
       } else {
-        tile_pairs<R, false>(jb, je, t0, i, xi, yi, zi, mix, miy, miz, tile, A);
+        tile_pairs<R, false>(jb, je, t0, ip, xi, yi, zi, mix, miy, miz, tile, A);
       }
       F[0] += A.fx; F[1] += A.fy; F[2] += A.fz; F[3] += A.fm;
       F[4] += A.bsx; F[5] += A.bsy; F[6] += A.bsz;

@@ -3,6 +3,7 @@
 // cutoff interaction in dipole_list.h.
 #include "dipole_body.h"
 #include "dipole_list.h"
+#include "particle_body.h"
 
 namespace rodmx {
 
@@ -17,9 +18,24 @@ __global__ __launch_bounds__(256) void k_dipole_small(Dev d, const DipWork* __re
   dipole_small_item<R>(d, work[blockIdx.x]);
 }
 
-hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int nwork,
+// Boxes of the 64-position chunks of the spatial order, one wave per chunk
+// (the far test of the mixed split layout reads them).
+__global__ __launch_bounds__(256) void k_spatial_box(Dev d) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = p < d.n;
+  V3<double> x{0.0, 0.0, 0.0};
+  if (valid) x = ld3(d.x, d.n, d.dperm[p]);
+  wave_box(d.sbox + 6 * (p >> 6), x, valid, p < d.n);
+}
+
+hipError_t launch_spatial_boxes(const Dev& d, hipStream_t s) {
+  if (!d.dperm || !d.far_ok) return hipSuccess;
+  hipLaunchKernelGGL(k_spatial_box, dim3((unsigned)((d.n + 255) / 256)), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+static void dipole_items(const Dev& d, int precision, const DipWork* work, int nwork,
                          hipStream_t s, const hipEvent_t* ev) {
-  if (nwork <= 0) return hipSuccess;
   if (d.dip_small) {
     if (precision == 1)
       launch_k(ev, k_dipole_small<float>, dim3(nwork), dim3(256), s, d, work);
@@ -30,6 +46,21 @@ hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int n
   } else {
     launch_k(ev, k_dipole<double>, dim3(nwork), dim3(256), s, d, work);
   }
+}
+
+hipError_t launch_dipole(const Dev& d, int precision, const DipWork* work, int nwork,
+                         hipStream_t s, const hipEvent_t* ev) {
+  if (nwork <= 0) return hipSuccess;
+  if (d.dperm && precision == 1 && d.far_ok) {
+    // the chunk boxes of the spatial order first; a timed launch brackets both
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+    if ((e = launch_spatial_boxes(d, s)) != hipSuccess) return e;
+    dipole_items(d, precision, work, nwork, s, nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return ev ? hipEventRecord(ev[1], s) : hipSuccess;
+  }
+  dipole_items(d, precision, work, nwork, s, ev);
   return hipGetLastError();
 }
 

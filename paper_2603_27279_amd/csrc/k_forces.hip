@@ -42,9 +42,27 @@ __global__ __launch_bounds__(256) void k_forces_hm(Dev d, const DipWork* __restr
   forces_body<R, true, true>(d, work, ndip, nbond);
 }
 
+static void forces_kernel(const Dev& d, int precision, const DipWork* work, int ndip,
+                          hipStream_t s, const hipEvent_t* ev);
+
 hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int nwork,
                          hipStream_t s, const hipEvent_t* ev) {
   const int ndip = d.dipole_on ? nwork : 0;
+  if (ndip > 0 && d.dperm && precision == 1 && d.far_ok) {
+    // the chunk boxes of the spatial order first; a timed launch brackets both
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+    if ((e = launch_spatial_boxes(d, s)) != hipSuccess) return e;
+    forces_kernel(d, precision, work, ndip, s, nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return ev ? hipEventRecord(ev[1], s) : hipSuccess;
+  }
+  forces_kernel(d, precision, work, ndip, s, ev);
+  return hipGetLastError();
+}
+
+static void forces_kernel(const Dev& d, int precision, const DipWork* work, int ndip,
+                          hipStream_t s, const hipEvent_t* ev) {
   const int nbond = (int)((d.i_hi - d.i_lo + 255) / 256);
   const bool lanes = contact_in_forces(d);
   const unsigned ncont = d.contact_on && lanes ? contact_lane_blocks(d) : 0;
@@ -59,7 +77,6 @@ hipError_t launch_forces(const Dev& d, int precision, const DipWork* work, int n
     else if (lanes) launch_k(ev, k_forces<double, true>, g, b, s, d, work, ndip, nbond);
     else launch_k(ev, k_forces<double, false>, g, b, s, d, work, ndip, nbond);
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_force_pass(const Dev& d, int precision, const DipWork* work, int nwork,

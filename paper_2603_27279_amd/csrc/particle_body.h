@@ -54,11 +54,9 @@ __device__ __forceinline__ void moment_and_cell(const Dev& d, long i, Q4<double>
   if (d.contact_on && insert) cell_insert(d, i, x, mem, rod, lvl);
 }
 
-// Bounding box of the wave's 64 particles (a 64-aligned chunk: the
-// per-particle kernels start at particle 0 in blocks of 64 or 256) into
-// d.cbox. Every lane of the wave calls it; `valid` marks lanes with a particle.
-__device__ __forceinline__ void chunk_box(const Dev& d, long i, V3<double> x, bool valid) {
-  if (!d.far_ok) return;
+// Bounding box of the x of the wave's lanes into out[0..6) (low then high;
+// `valid` marks lanes with a particle), written by lane 0 when `write`.
+__device__ __forceinline__ void wave_box(double* out, V3<double> x, bool valid, bool write) {
   double lx = valid ? x.x : 1e300, ly = valid ? x.y : 1e300, lz = valid ? x.z : 1e300;
   double hx = valid ? x.x : -1e300, hy = valid ? x.y : -1e300, hz = valid ? x.z : -1e300;
   for (int o = 32; o > 0; o >>= 1) {
@@ -66,10 +64,17 @@ __device__ __forceinline__ void chunk_box(const Dev& d, long i, V3<double> x, bo
     ly = fmin(ly, __shfl_xor(ly, o)); hy = fmax(hy, __shfl_xor(hy, o));
     lz = fmin(lz, __shfl_xor(lz, o)); hz = fmax(hz, __shfl_xor(hz, o));
   }
-  if ((threadIdx.x & 63) == 0 && i < d.n) {
-    double* b = d.cbox + 6 * (i >> 6);
-    b[0] = lx; b[1] = ly; b[2] = lz; b[3] = hx; b[4] = hy; b[5] = hz;
+  if ((threadIdx.x & 63) == 0 && write) {
+    out[0] = lx; out[1] = ly; out[2] = lz; out[3] = hx; out[4] = hy; out[5] = hz;
   }
+}
+
+// Bounding box of the wave's 64 particles (a 64-aligned chunk: the
+// per-particle kernels start at particle 0 in blocks of 64 or 256) into
+// d.cbox. Every lane of the wave calls it; `valid` marks lanes with a particle.
+__device__ __forceinline__ void chunk_box(const Dev& d, long i, V3<double> x, bool valid) {
+  if (!d.far_ok) return;
+  wave_box(d.cbox + 6 * (i >> 6), x, valid, i < d.n);
 }
 
 }  // namespace rodmx

@@ -324,11 +324,44 @@ static int validate(const rod_desc* d) {
   return ROD_OK;
 }
 
+// Spatial order of the particles of member [b, e) into perm[b, e): by the
+// Morton code of positions quantised to 2^21 levels over the member's largest
+// extent, ties in particle order, so that consecutive entries are close in space.
+static void spatial_order(const std::vector<double>& x, long N, int b, int e, int* perm) {
+  double lo[3] = {1e300, 1e300, 1e300}, ext = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    double hi = -1e300;
+    for (int i = b; i < e; ++i) {
+      lo[a] = std::min(lo[a], x[a * N + i]);
+      hi = std::max(hi, x[a * N + i]);
+    }
+    ext = std::max(ext, hi - lo[a]);
+  }
+  const double scale = ext > 0.0 ? 2097151.0 / ext : 0.0;
+  auto spread = [](uint64_t v) {  // bit k of v to bit 3k
+    uint64_t r = 0;
+    for (int k = 0; k < 21; ++k) r |= ((v >> k) & 1ull) << (3 * k);
+    return r;
+  };
+  std::vector<std::pair<uint64_t, int>> key((size_t)(e - b));
+  for (int i = b; i < e; ++i) {
+    uint64_t code = 0;
+    for (int a = 0; a < 3; ++a) {
+      const double t = std::min(2097151.0, std::max(0.0, (x[a * N + i] - lo[a]) * scale));
+      code |= spread((uint64_t)t) << a;
+    }
+    key[i - b] = {code, i};
+  }
+  std::sort(key.begin(), key.end());
+  for (int i = b; i < e; ++i) perm[i] = key[i - b].second;
+}
+
 // Dipole work list. Split layout: blocks of 64 targets against S source ranges
 // of the same member, S chosen so the launch holds about target_wgs work items
 // (each range at least half a 256-source tile). Small-member layout: blocks of
 // DIP_SMALL_I targets against the whole member. small: -1 = automatic, 0 =
-// split, 1 = small.
+// split, 1 = small, 2 = split in the spatial order of the current positions
+// (the ranges are then places in that order; see Dev::dperm).
 static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
   const std::vector<int>& mrange = c->mrange_h;
   const int M = c->desc.n_members;
@@ -342,6 +375,7 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
   // Small systems: one wave per target, its lanes striding over the member.
   bool small = small_req < 0 ? (iblocks < 512 && max_member <= 2048) : small_req == 1;
   if (max_member > 16384) small = false;
+  const bool spatial = small_req == 2;
   if (!c->plan_allocs.empty()) HIPC(hipStreamSynchronize(c->s));  // old plan may be in use
   for (void* p : c->plan_allocs) (void)hipFree(p);
   c->plan_allocs.clear();
@@ -398,7 +432,22 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
   c->mslots_h = mslots;
   c->mlen_h = mlen;
   c->d.dip_small = small ? 1 : 0;
-  c->plan_small = small ? 1 : 0;
+  c->plan_small = spatial ? 2 : small ? 1 : 0;
+  c->d.dperm = nullptr;
+  c->d.sbox = nullptr;
+  if (spatial && !items.empty()) {  // the order of the positions the plan is built at
+    std::vector<double> xh(3 * (size_t)N);
+    HIPC(hipStreamSynchronize(c->s));
+    HIPC(hipMemcpy(xh.data(), c->d.x, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<int> perm((size_t)N);
+    for (long i = 0; i < N; ++i) perm[i] = (int)i;
+    for (int m = 0; m < M; ++m) spatial_order(xh, N, mrange[2 * m], mrange[2 * m + 1], perm.data());
+    int* dp = nullptr;
+    TRY(palloc(c, &dp, (size_t)N));
+    HIPC(hipMemcpy(dp, perm.data(), (size_t)N * sizeof(int), hipMemcpyHostToDevice));
+    c->d.dperm = dp;
+    TRY(palloc(c, &c->d.sbox, 6 * (size_t)((N + 63) / 64)));
+  }
   c->plan_target = target_wgs;
   c->max_slots = max_slots;
   c->d.max_slots = max_slots;
@@ -594,6 +643,7 @@ static size_t workspace_bytes(const rod_desc* d, int max_slots) {
          16 * ((size_t)TC + M) * K;
   }
   if (d->precision == ROD_MIXED && d->dipole_on) b += 48 * ((N + 63) / 64);  // chunk boxes
+  if (d->dipole_on) b += 4 * N + 48 * ((N + 63) / 64);  // spatial order and its chunk boxes
   if (d->bond_damping) b += 8 * 4 * R + 8 * 2 * 5 * N;                       // bond damping
   b += 8 * 18 * N + 8 * 9 * M;                                                  // energy
   return b;
@@ -726,6 +776,8 @@ static int enqueue_step_per_rod(rod_ctx* c) {
   auto rod_dev = [&](int r) {
     Dev dr = c->d;
     dr.far_ok = 0;  // waves do not start on 64-particle chunk boundaries
+    dr.dperm = nullptr;  // per-rod work items are particle ranges
+    dr.sbox = nullptr;
     dr.i_lo = c->rod_offset[r];
     dr.i_hi = c->rod_offset[r + 1];
     return dr;
@@ -1469,8 +1521,8 @@ extern "C" int rod_launch_mode(rod_ctx* c, int32_t mode) {
 
 extern "C" int rod_dipole_layout(rod_ctx* c, int32_t small, int32_t target_wgs) {
   if (!c) return fail(ROD_E_INVALID, "context is NULL");
-  if (small < -1 || small > 1 || target_wgs < 1)
-    return fail(ROD_E_INVALID, "small must be -1, 0 or 1 and target_wgs >= 1");
+  if (small < -1 || small > 2 || target_wgs < 1)
+    return fail(ROD_E_INVALID, "small must be -1, 0, 1 or 2 and target_wgs >= 1");
   if (c->tape.active) return fail(ROD_E_STATE, "layout change while a tape is recorded");
   TRY(enter(c));
   TRY(build_dipole_plan(c, small, target_wgs));
@@ -1478,6 +1530,10 @@ extern "C" int rod_dipole_layout(rod_ctx* c, int32_t small, int32_t target_wgs) 
   drop_graphs(c);
   TRY(leave(c));
   return ROD_OK;
+}
+
+static const char* layout_name(int small) {
+  return small == 1 ? "small-member layout" : small == 2 ? "spatial split layout" : "split layout";
 }
 
 extern "C" int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, char* report,
@@ -1512,24 +1568,26 @@ extern "C" int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, c
       max_member = std::max(max_member, c->mrange_h[k + 1] - c->mrange_h[k]);
     if (c->desc.dipole_on && c->d.dcut == 0.0 && !c->d.ew_on) {  // (a cutoff or a box: no layout)
       if (max_member <= 16384) cands.push_back({1, 0});
-      for (int t : {512, 1024, 2048, 4096, 8192, 16384, 32768}) cands.push_back({0, t});
+      for (int sp : {0, 2})  // particle order, spatial order
+        for (int t : {512, 1024, 2048, 4096, 8192, 16384, 32768}) cands.push_back({sp, t});
     } else {
       cands.push_back({0, 1024});
     }
     best_us = 1e300;
-    std::vector<int> seen;  // split targets that give the same work list are timed once
+    // split targets that give the same work list (in the same order) are timed once
+    std::vector<std::pair<int, int>> seen;
     for (const Cand& cd : cands) {
       TRY(build_dipole_plan(c, cd.small, cd.target));
-      if (!cd.small) {
-        if (std::find(seen.begin(), seen.end(), c->nwork) != seen.end()) continue;
-        seen.push_back(c->nwork);
+      if (cd.small != 1) {
+        const std::pair<int, int> k{cd.small, c->nwork};
+        if (std::find(seen.begin(), seen.end(), k) != seen.end()) continue;
+        seen.push_back(k);
       }
       double us = 0.0;
       TRY(time_eval(c, &us));
       char line[160];
       snprintf(line, sizeof(line), "%s target_wgs=%d work_items=%d slots=%d: %.2f us/eval\n",
-               cd.small ? "small-member layout" : "split layout", cd.target, c->nwork,
-               c->max_slots, us);
+               layout_name(cd.small), cd.target, c->nwork, c->max_slots, us);
       rep += line;
       if (us < best_us) { best_us = us; small = cd.small; target = cd.target; }
     }
@@ -1549,8 +1607,7 @@ extern "C" int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, c
   TRY(leave(c));
   char line[256];
   snprintf(line, sizeof(line), "chosen: %s target_wgs=%d work_items=%d slots=%d (%.2f us/eval) key=%s\n",
-           small ? "small-member layout" : "split layout", target, c->nwork, c->max_slots,
-           best_us, key.c_str());
+           layout_name(small), target, c->nwork, c->max_slots, best_us, key.c_str());
   rep += line;
   if (report && report_len > 0) {
     strncpy(report, rep.c_str(), report_len - 1);

@@ -91,6 +91,14 @@ struct Dev {
   // per-rod loop, whose waves do not start on chunk boundaries).
   double* cbox;            // [(N + 63) / 64][6]
   int far_ok;
+  // Split layout in spatial order (rod_dipole_layout with small = 2): the
+  // work items' target and source ranges are positions in a space-filling-curve
+  // order of each member's particles, dperm[position] = particle, so that 64
+  // consecutive positions are close in space and most sub-tiles pass the far
+  // test; sbox holds the boxes of consecutive 64-position chunks, written before
+  // each launch of the dipole work items. Both null: positions are particles.
+  const int* dperm;        // [N]
+  double* sbox;            // [(N + 63) / 64][6]
   double axis[3];
   long long period;
   // ---- per-level history (bond damping, Hertz-Mindlin) and Hertz-Mindlin state
@@ -260,6 +268,9 @@ hipError_t launch_dipole_cut(const Dev& d, int build, hipStream_t s,
 // The cutoff sort alone (when the lists are stale or `build`), over the whole
 // system: launched once before the per-rod loop's list walks.
 hipError_t launch_dipole_sort(const Dev& d, int build, hipStream_t s);
+// Boxes of the 64-position chunks of the spatial order (d.dperm) into d.sbox;
+// nothing without a spatial order.
+hipError_t launch_spatial_boxes(const Dev& d, hipStream_t s);
 // Ewald sum of the dipoles of a periodic box (d.ew_on): writes the dipole
 // force and field to slot 0 of the FP64 partial sums.
 hipError_t launch_ewald(const Dev& d, hipStream_t s, const hipEvent_t* ev = nullptr);

@@ -69,10 +69,12 @@ def test_grad_matches_oracle_jvp_clamped_rod():
     jvp_check(w, 30, 7)
 
 
-@pytest.mark.parametrize("layout", [(0, 64), (0, 4096), (1, 1)])
+@pytest.mark.parametrize("layout", [(0, 64), (0, 4096), (1, 1), (2, 64), (2, 4096)])
 def test_grad_every_dipole_layout(layout):
     """1100 particles: the split layouts give several source ranges per target
-    block (partial sums in several slots), the small-member one none."""
+    block (partial sums in several slots), the small-member one none; in the
+    spatial order (2) the forward recomputation walks places in that order
+    while the reverse pass takes the same ranges as particle ranges."""
     w = workloads.adjoint_rod(n=1100)
     w["x0"] = w["x0"] + np.random.default_rng(3).normal(0, 0.05, w["x0"].shape) * (w["bc"] == 0)[:, None]
     jvp_check(w, 12, 5, blocks=("m_body", "x0"), layout=layout)

@@ -16,7 +16,8 @@ def rel_inf(a, ref):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
-@pytest.mark.parametrize("layout", [(1, 1024), (0, 64), (0, 1024), (0, 8192), (0, 65536)])
+@pytest.mark.parametrize("layout", [(1, 1024), (0, 64), (0, 1024), (0, 8192), (0, 65536), (2, 64),
+                                    (2, 1024)])
 def test_every_layout_matches_oracle(layout, prec, tol):
     w = workloads.ensemble(members=3, n=700)
     w["x0"] = w["x0"] + np.random.default_rng(1).normal(0, 0.05, w["x0"].shape) * (w["bc"] == 0)[:, None]
@@ -69,7 +70,7 @@ def test_autotune_keeps_state_and_caches(tmp_path):
 def test_dipole_layout_arguments_are_checked():
     w = workloads.twisted_rod(n=300)
     sim = RodSim(w, precision="mixed")
-    for bad in ((2, 64), (-2, 64), (0, 0)):
+    for bad in ((3, 64), (-2, 64), (0, 0)):
         with pytest.raises(RodError) as e:
             sim.dipole_layout(*bad)
         assert e.value.code == ROD_E_INVALID
@@ -122,6 +123,30 @@ def test_launch_modes_match(layout, prec):
         assert np.max(np.abs(states[2]["x"] - states[0]["x"])) / motion <= 1e-5
         for k in ("F", "T"):
             assert rel_inf(states[2][k], states[0][k]) <= 1e-5
+    assert np.max(np.abs(states[0]["x"] - o["x"])) / motion <= (1e-9 if prec == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("target", [64, 4096])
+def test_spatial_layout_launch_modes(prec, target):
+    """The split layout over the spatial order of the particles: batched and
+    separate launches bitwise equal, the trajectory within the oracle's bound,
+    and the state of the particle-order layout to rounding (the sums are the
+    same terms added in another order)."""
+    w = _many_rods()
+    states = []
+    for small, mode in ((2, "batched"), (2, "separate"), (0, "batched")):
+        sim = RodSim(w, precision=prec, graph_steps=10)
+        sim.dipole_layout(small, target)
+        sim.launch_mode(mode)
+        sim.step(30)
+        states.append(sim.state())
+        sim.free()
+    o = oracle.run(w, 30)
+    motion = np.max(np.abs(o["x"] - w["x0"]))
+    for k in ("x", "v", "q", "w", "F", "T"):
+        np.testing.assert_array_equal(states[0][k], states[1][k])
+    assert np.max(np.abs(states[0]["x"] - states[2]["x"])) / motion <= (1e-12 if prec == "fp64" else 1e-5)
     assert np.max(np.abs(states[0]["x"] - o["x"])) / motion <= (1e-9 if prec == "fp64" else 1e-4)
 
 
