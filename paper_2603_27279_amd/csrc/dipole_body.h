@@ -11,7 +11,7 @@
 //
 // Layout. A work item is a block of 64 consecutive i of one member (one i per
 // lane) against a j range of the same member. The four waves of a workgroup
-// split every staged j tile of 256 four ways and are reduced through LDS at
+// split every staged j tile of TJ sources four ways and are reduced through LDS at
 // the end. Tiles are read from LDS as wavefront-uniform broadcasts. Position
 // differences are taken in FP64 and rounded once; on the mixed path the pair
 // arithmetic and the per-tile sums are FP32 and each tile is flushed into FP64
@@ -48,7 +48,7 @@ __device__ __forceinline__ float lane_value(float v) {
 __device__ __forceinline__ float minus5(float) { return lane_value(-5.0f); }
 __device__ __forceinline__ double minus5(double) { return -5.0; }
 
-constexpr int TJ = 256;   // j tile staged per workgroup
+constexpr int TJ = 512;   // j tile staged per workgroup (a quarter per wave)
 
 // Pair sums: f = sum s[(c - 5ab/r^2) r + a m_j], fm = sum s b,
 // bs = sum s b r, bm = sum m_j / r^3.
@@ -164,19 +164,21 @@ __device__ __forceinline__ bool far_tile_pairs(const Dev& d, int jg0, int jg1, i
                                                Acc<float>& A) {
   const int lane = threadIdx.x & 63;
   const double* boxes = d.dperm ? d.sbox : d.cbox;  // chunks of positions
-  const double* b0 = boxes + 6 * (jg0 >> 6);
-  const double* b1 = boxes + 6 * ((jg1 - 1) >> 6);
-  const double lx = fmin(b0[0], b1[0]), ly = fmin(b0[1], b1[1]), lz = fmin(b0[2], b1[2]);
-  const double hx = fmax(b0[3], b1[3]), hy = fmax(b0[4], b1[4]), hz = fmax(b0[5], b1[5]);
+  double lx = 1e300, ly = 1e300, lz = 1e300, hx = -1e300, hy = -1e300, hz = -1e300;
+  for (int c = jg0 >> 6; c <= (jg1 - 1) >> 6; ++c) {  // every chunk the sub-tile touches
+    const double* b = boxes + 6 * c;
+    lx = fmin(lx, b[0]); ly = fmin(ly, b[1]); lz = fmin(lz, b[2]);
+    hx = fmax(hx, b[3]); hy = fmax(hy, b[4]); hz = fmax(hz, b[5]);
+  }
   const double ox = 0.5 * (lx + hx), oy = 0.5 * (ly + hy), oz = 0.5 * (lz + hz);
   const double ex = 0.5 * (hx - lx), ey = 0.5 * (hy - ly), ez = 0.5 * (hz - lz);
   const double h2 = ex * ex + ey * ey + ez * ez;
   const double tx = xi - ox, ty = yi - oy, tz = zi - oz;
   if (!__all(!act || tx * tx + ty * ty + tz * tz > 9.0 * h2)) return false;
   const int n = je - jb;
-  if (lane < n) {
-    const Src<float>& e = tile[jb + lane];
-    rel[lane] = make_float4((float)(e.x - ox), (float)(e.y - oy), (float)(e.z - oz), 0.0f);
+  for (int k = lane; k < n; k += 64) {
+    const Src<float>& e = tile[jb + k];
+    rel[k] = make_float4((float)(e.x - ox), (float)(e.y - oy), (float)(e.z - oz), 0.0f);
   }
   const float xr = (float)tx, yr = (float)ty, zr = (float)tz;
   const float m5 = minus5(0.0f);
@@ -209,7 +211,7 @@ template <class R>
 union DipSmem {
   struct {
     Src<R> tile[TJ];
-    float4 rel[4][64];
+    float4 rel[4][TJ / 4];
   } st;
   double red[4][NACC][64];
 };
@@ -237,9 +239,9 @@ __device__ __forceinline__ void dipole_item(const Dev& d, const DipWork& wk, Dip
   double F[NACC] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int t0 = wk.j0; t0 < wk.j1; t0 += TJ) {
     const int jn = min(TJ, wk.j1 - t0);
-    if ((int)threadIdx.x < jn) {
-      const int j = d.dperm ? d.dperm[t0 + threadIdx.x] : t0 + threadIdx.x;
-      tile[threadIdx.x] = Src<R>{d.x[j], d.x[N + j], d.x[2 * N + j], mu[j], mu[N + j], mu[2 * N + j]};
+    for (int t = threadIdx.x; t < jn; t += blockDim.x) {
+      const int j = d.dperm ? d.dperm[t0 + t] : t0 + t;
+      tile[t] = Src<R>{d.x[j], d.x[N + j], d.x[2 * N + j], mu[j], mu[N + j], mu[2 * N + j]};
     }
     __syncthreads();
     const int q = (jn + 3) >> 2;  // the four waves take equal quarters of the staged tile
