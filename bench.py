@@ -59,9 +59,13 @@ def force_sources_digest():
 
 
 def layout_key(tune_line):
-    """'split/1024' or 'small/256' from the autotuner's choice line."""
-    m = re.search(r"(small-member|split) layout target_wgs=\d+ work_items=(\d+)", tune_line or "")
-    return None if m is None else ("small" if m.group(1) == "small-member" else "split") + "/" + m.group(2)
+    """'split/1024', 'spatial/32768' or 'small/256' from the autotuner's choice line."""
+    m = re.search(r"(small-member|spatial split|split) layout target_wgs=\d+ work_items=(\d+)",
+                  tune_line or "")
+    if m is None:
+        return None
+    kind = {"small-member": "small", "spatial split": "spatial", "split": "split"}[m.group(1)]
+    return kind + "/" + m.group(2)
 
 
 def measured_traffic(kernel, workload, precision, layout):
@@ -743,6 +747,9 @@ def workload_leg(name, prec, steps, warmup, graph_steps, timing_steps, per_rod_s
                 "traffic": measured_traffic(kname, name, prec, layout_key(tune)),
                 "traffic_unit": "bytes per launch", "kernel": kname,
                 "kernel_us": 1e6 * t_k, "launches_timed": int(kt[cls][1]),
+                "kernel_us_covers": "the launch's own events; with the spatial layout they also "
+                                    "bracket the chunk-box kernel launched just before it"
+                                    if "spatial" in (tune or "") else "the launch's own events",
                 "flops_counted": "dipole pair arithmetic only (bond and contact work in the "
                                  "same launch is not counted)" if cls == "forces" else "dipole pairs",
                 "pair_evals_per_s": pairs / t_k,

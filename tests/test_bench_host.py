@@ -21,6 +21,8 @@ def test_more_than_one_gpu_is_refused():
 @pytest.mark.parametrize("line,key", [
     ("chosen: split layout target_wgs=1024 work_items=1024 slots=16 (30.78 us/eval) key=x", "split/1024"),
     ("chosen: small-member layout target_wgs=0 work_items=256 slots=1 (9.1 us/eval) key=x", "small/256"),
+    ("chosen: spatial split layout target_wgs=32768 work_items=32768 slots=8 (49.8 us/eval) key=x",
+     "spatial/32768"),
     ("cached choice", None),
     (None, None),
 ])
