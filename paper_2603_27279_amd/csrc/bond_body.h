@@ -23,10 +23,19 @@ namespace rodmx {
 // of the previous level, hist[(L - 1) & 1] (from level hist_from on), and this
 // level's go to hist[L & 1] when the evaluation records them, L being the
 // level under evaluation.
-template <class R>
+// ALL: every particle below i_hi is evaluated with its successor, whether or
+// not the two are bonded, so that no load waits for the bond flag (the
+// standalone bond kernel); the particle kernels read a bond's outputs only
+// where the flag is set, and what the last particle of a rod stores (its
+// partner is the next rod's first, or itself at the end of the system) is never
+// read. Without ALL the flag is tested first: the fused force kernel keeps the
+// registers of its dipole work items that way.
+template <class R, bool ALL = false>
 __device__ __forceinline__ void bond_thread(const Dev& d, long k, int want_energy) {
   const long N = d.n;
-  if (k >= d.i_hi || !(d.bflags[k] & 1)) return;
+  if (k >= d.i_hi) return;
+  if (!ALL && !(d.bflags[k] & 1)) return;
+  const long k2 = ALL && k + 1 >= N ? k : k + 1;
   V3<double> F, Ts, Tbt;
   double e[4];
   if (d.bdamp) {
@@ -38,10 +47,9 @@ __device__ __forceinline__ void bond_thread(const Dev& d, long k, int want_energ
     const double* hprev = d.hist + (long)((L - 1) & 1) * 5 * N;
     for (int c = 0; c < 5; ++c) dm.hprev[c] = hprev[c * N + k];
     dm.rates = L >= d.hist_from;
-    dm.dv = ld3(d.v, N, k + 1) - ld3(d.v, N, k);
+    dm.dv = ld3(d.v, N, k2) - ld3(d.v, N, k);
     dm.idt = 1.0 / d.dt;
-    bond_one<double, R, true>(ld3(d.x, N, k), ld3(d.x, N, k + 1), ld4(d.q, N, k),
-                              ld4(d.q, N, k + 1),
+    bond_one<double, R, true>(ld3(d.x, N, k), ld3(d.x, N, k2), ld4(d.q, N, k), ld4(d.q, N, k2),
                               V3<double>{d.bref[k], d.bref[N + k], d.bref[2 * N + k]},
                               d.bref[3 * N + k], d.rodK + 4 * rod, F, Ts, Tbt,
                               want_energy ? e : nullptr, &dm);
@@ -50,7 +58,7 @@ __device__ __forceinline__ void bond_thread(const Dev& d, long k, int want_energ
       for (int c = 0; c < 5; ++c) hnow[c * N + k] = dm.hnow[c];
     }
   } else {
-    bond_one<double, R>(ld3(d.x, N, k), ld3(d.x, N, k + 1), ld4(d.q, N, k), ld4(d.q, N, k + 1),
+    bond_one<double, R>(ld3(d.x, N, k), ld3(d.x, N, k2), ld4(d.q, N, k), ld4(d.q, N, k2),
                         V3<double>{d.bref[k], d.bref[N + k], d.bref[2 * N + k]},
                         d.bref[3 * N + k], d.rodK + 4 * d.rod[k], F, Ts, Tbt,
                         want_energy ? e : nullptr);

@@ -6,7 +6,7 @@ namespace rodmx {
 
 template <class R>
 __global__ __launch_bounds__(256) void k_bond(Dev d, int want_energy) {
-  bond_thread<R>(d, d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x, want_energy);
+  bond_thread<R, true>(d, d.i_lo + (long)blockIdx.x * blockDim.x + threadIdx.x, want_energy);
 }
 
 hipError_t launch_bond(const Dev& d, int precision, int want_energy, hipStream_t s,
