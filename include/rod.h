@@ -353,7 +353,7 @@ int rod_launch_mode(rod_ctx* c, int32_t mode);
  * for members above 16384 particles), 0 split layout aiming at target_wgs
  * work items, 2 the split layout over each member's particles taken in a
  * space-filling-curve (Morton) order of their positions at this call (on the
- * mixed path more of its 64-source sub-tiles are far from their targets and
+ * mixed path more of its sub-tiles of sources are far from their targets and
  * take the cheaper position differences; sums are as deterministic as in
  * particle order, but rounded in another order), -1 the default rule.
  * Invalidates captured graphs. */

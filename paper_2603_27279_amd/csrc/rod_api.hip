@@ -358,7 +358,7 @@ static void spatial_order(const std::vector<double>& x, long N, int b, int e, in
 
 // Dipole work list. Split layout: blocks of 64 targets against S source ranges
 // of the same member, S chosen so the launch holds about target_wgs work items
-// (each range at least half a 256-source tile). Small-member layout: blocks of
+// (each range at least 128 sources). Small-member layout: blocks of
 // DIP_SMALL_I targets against the whole member. small: -1 = automatic, 0 =
 // split, 1 = small, 2 = split in the spatial order of the current positions
 // (the ranges are then places in that order; see Dev::dperm).
