@@ -439,7 +439,8 @@ def ewald_leg(grid=32, length=32, box=(64.0, 64.0, 40.0), rcut=16.0, steps=20):
     """Rods in a periodic box with the Ewald sum of their dipoles: the rod array
     at 32 x 32 rods of 32 particles (32,768) at pitch 2, without contact, in a
     64 x 64 x 40 box (the lateral pitch continues across the boundary), real-
-    space cutoff 16 (4 cells per axis in x and y), alpha = 3.6 / rcut and kmax
+    space cutoff 16 (cells of a third of it: 12 per axis in x and y, 7 in z),
+    alpha = 3.6 / rcut and kmax
     = ceil(3.6 alpha max(L) / pi) (both truncated tails near exp(-13)). Whole
     steps replayed from a graph, and the Ewald part of a step (its ten
     launches, bracketed by events) on its own."""
