@@ -134,20 +134,41 @@ def test_spatial_layout_launch_modes(prec, target):
     and the state of the particle-order layout to rounding (the sums are the
     same terms added in another order)."""
     w = _many_rods()
-    states = []
-    for small, mode in ((2, "batched"), (2, "separate"), (0, "batched")):
-        sim = RodSim(w, precision=prec, graph_steps=10)
+    states, energies = [], []
+    for small, mode in ((2, "batched"), (2, "separate"), (0, "batched"), (2, "per_rod")):
+        sim = RodSim(w, precision=prec, graph_steps=0 if mode == "per_rod" else 10)
         sim.dipole_layout(small, target)
         sim.launch_mode(mode)
         sim.step(30)
         states.append(sim.state())
+        energies.append(sim.energy())
         sim.free()
     o = oracle.run(w, 30)
     motion = np.max(np.abs(o["x"] - w["x0"]))
     for k in ("x", "v", "q", "w", "F", "T"):
         np.testing.assert_array_equal(states[0][k], states[1][k])
-    assert np.max(np.abs(states[0]["x"] - states[2]["x"])) / motion <= (1e-12 if prec == "fp64" else 1e-5)
+    np.testing.assert_array_equal(energies[0], energies[1])
+    # particle order, and the per-rod loop (whose work items are particle ranges)
+    for other in (states[2], states[3]):
+        assert np.max(np.abs(states[0]["x"] - other["x"])) / motion <= (1e-12 if prec == "fp64" else 1e-5)
+    np.testing.assert_allclose(energies[0], energies[2], rtol=1e-12 if prec == "fp64" else 1e-5,
+                               atol=1e-12 * np.max(np.abs(energies[2])))
     assert np.max(np.abs(states[0]["x"] - o["x"])) / motion <= (1e-9 if prec == "fp64" else 1e-4)
+
+
+def test_spatial_layout_without_work_items():
+    """A dipole cutoff walks lists and holds no work items: asking for the
+    spatial order changes nothing."""
+    w = dict(_many_rods(), dipole_cutoff=3.0)
+    runs = []
+    for layout in ((0, 1024), (2, 1024)):
+        sim = RodSim(w, precision="mixed", graph_steps=10)
+        sim.dipole_layout(*layout)
+        sim.step(12)
+        runs.append(sim.state())
+        sim.free()
+    for k in ("x", "v", "q", "w", "F", "T"):
+        np.testing.assert_array_equal(runs[0][k], runs[1][k])
 
 
 def _twisted_small():
