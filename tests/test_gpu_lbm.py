@@ -19,12 +19,16 @@ def start(shape, seed):
     return f + 1e-3 * rng.random(f.shape) * lbm.W.reshape(19, 1, 1, 1)
 
 
-@pytest.mark.parametrize("walls,lid", [(0, (0.0, 0.0)), (1, (0.0, 0.0)), (1, (0.02, -0.01)),
-                                       (2, (0.0, 0.0))])
-@pytest.mark.parametrize("shape", [(7, 6, 9), (20, 33, 47), (5, 1, 1), (1, 3, 2)])
+# every lattice shape with periodic z; the walled variants (no-slip bottom and
+# top, a moving lid, a free-slip top) on shapes with cells between the walls
+CASES = [(shape, walls, lid)
+         for walls, lid in [(0, (0.0, 0.0)), (1, (0.0, 0.0)), (1, (0.02, -0.01)), (2, (0.0, 0.0))]
+         for shape in [(7, 6, 9), (20, 33, 47), (5, 1, 1), (1, 3, 2)]
+         if not (walls and shape[0] < 2)]
+
+
+@pytest.mark.parametrize("shape,walls,lid", CASES)
 def test_populations_match_oracle(shape, walls, lid):
-    if walls and shape[0] < 2:
-        pytest.skip("a walled box needs cells between the walls in z")
     f0 = start(shape, sum(shape))
     g = (2e-5, -1e-5, 3e-5)
     lat = Lattice(f0, tau=0.7, force=g, walls_z=walls, lid=lid)
