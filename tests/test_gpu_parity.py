@@ -241,14 +241,23 @@ FULL = {
 }
 
 
-@pytest.mark.parametrize("name", list(FULL))
-def test_full_size_sampled_rows(name):
+# the dipole layouts the autotuner picks for these workloads on this GPU (None:
+# the default rule)
+BENCH_LAYOUT = {"twisted_rod": (0, 1024), "cilia_carpet": (2, 32768), "rod_array": (2, 32768),
+                "ensemble": (0, 16384)}
+
+
+@pytest.mark.parametrize("name,layout", [(n, None) for n in FULL] + list(BENCH_LAYOUT.items()))
+def test_full_size_sampled_rows(name, layout):
     """Full-size workloads in the launch configuration of the benchmark (mixed
-    path, graph replay): after 20 steps, bond, Zeeman and damping forces of
-    every particle, and dipole force/field and contact force of 48 sampled
-    particles, match the oracle at the GPU's state."""
+    path, graph replay, the default layout and the one the autotuner picks):
+    after 20 steps, bond, Zeeman and damping forces of every particle, and
+    dipole force/field and contact force of 48 sampled particles, match the
+    oracle at the GPU's state."""
     w = FULL[name]()
     sim = RodSim(w, precision="mixed", graph_steps=10)
+    if layout is not None:
+        sim.dipole_layout(*layout)
     sim.step(20)
     sim.sync()
     g = sim.state()
