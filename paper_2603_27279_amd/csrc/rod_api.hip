@@ -337,7 +337,7 @@ static void spatial_order(const std::vector<double>& x, long N, int b, int e, in
     }
     ext = std::max(ext, hi - lo[a]);
   }
-  const double scale = ext > 0.0 ? 2097151.0 / ext : 0.0;
+  const double scale = ext > 0.0 && std::isfinite(ext) ? 2097151.0 / ext : 0.0;
   auto spread = [](uint64_t v) {  // bit k of v to bit 3k
     uint64_t r = 0;
     for (int k = 0; k < 21; ++k) r |= ((v >> k) & 1ull) << (3 * k);
@@ -347,7 +347,8 @@ static void spatial_order(const std::vector<double>& x, long N, int b, int e, in
   for (int i = b; i < e; ++i) {
     uint64_t code = 0;
     for (int a = 0; a < 3; ++a) {
-      const double t = std::min(2097151.0, std::max(0.0, (x[a * N + i] - lo[a]) * scale));
+      double t = (x[a * N + i] - lo[a]) * scale;
+      t = std::isfinite(t) ? std::min(2097151.0, std::max(0.0, t)) : 0.0;  // (a non-finite state)
       code |= spread((uint64_t)t) << a;
     }
     key[i - b] = {code, i};
