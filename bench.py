@@ -392,13 +392,14 @@ def lbm_leg(n=256, steps=20):
             "frac_hbm": gbs / HBM_PEAK_GBS}
 
 
-def ibm_leg(grid=16, nsub=10, cycles=20, shape=(96, 128, 128)):
+def ibm_leg(grid=16, nsub=10, cycles=20, shape=(96, 128, 128), autotune=True):
     """Cilia immersed in a lattice (rod_lbm_cycles): a grid x grid carpet of
     clamped rods of 16 to 64 particles at pitch 8, in a rotating field, moved 4
     lattice units in from x = y = 0 and 2 up from z = 0, in a periodic lattice
     [nz, ny, nx] = shape at rest, nsub rod steps of dt = 1 / nsub per lattice
-    step (mixed precision rods, FP64 fluid). Time per cycle from HIP events on
-    the calling stream, beside the lattice step alone on the same lattice."""
+    step (mixed precision rods, FP64 fluid), the rods' dipole layout autotuned
+    first. Time per cycle from HIP events on the calling stream, beside the
+    lattice step alone on the same lattice."""
     import torch
     import workloads
     from paper_2603_27279_amd import Lattice, RodSim
@@ -410,6 +411,7 @@ def ibm_leg(grid=16, nsub=10, cycles=20, shape=(96, 128, 128)):
     wt = torch.tensor([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12, dtype=torch.float64, device="cuda")
     f0 = wt.view(19, 1, 1, 1).expand(19, nz, ny, nx).contiguous()
     sim = RodSim(w, precision=w["precision"])
+    tune = sim.autotune(None).strip().splitlines()[-1] if autotune else None
     lat = Lattice(f0, tau=0.8)
     del f0
     sim.lbm_cycles(lat, nsub, 2)
@@ -432,7 +434,8 @@ def ibm_leg(grid=16, nsub=10, cycles=20, shape=(96, 128, 128)):
     return {"workload": f"{grid}x{grid} cilia carpet (16-64 particles) in a {nx}x{ny}x{nz} periodic lattice",
             "particles": n, "cells": cells, "n_sub": nsub, "us_per_cycle": us,
             "us_lattice_step": us_lat, "us_rods_and_coupling": us - us_lat,
-            "particle_steps_per_s": n * nsub / (us * 1e-6), "mlups": cells / us}
+            "particle_steps_per_s": n * nsub / (us * 1e-6), "mlups": cells / us,
+            "dipole_layout": tune}
 
 
 def ewald_leg(grid=32, length=32, box=(64.0, 64.0, 40.0), rcut=16.0, steps=20):
