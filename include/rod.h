@@ -158,8 +158,10 @@ typedef struct rod_desc {
                                  vectors k = 2 pi (n_x/L_x, n_y/L_y, n_z/L_z), 0 < |n|^2 <=
                                  ewald_kmax^2, weighted by (4 pi C / V) exp(-k^2/4a^2) / k^2 with
                                  a = ewald_alpha; the self field C 4 a^3 / (3 sqrt(pi)) m_i.
-                                 Positions need not be wrapped into the box. FP64 on both
-                                 paths; sums in a fixed order (deterministic). Needs
+                                 Positions need not be wrapped into the box. The real-space
+                                 pair law is FP32 on the mixed path (separations, cutoff test,
+                                 reciprocal sum and self field FP64 on both paths); sums in a
+                                 fixed order (deterministic). Needs
                                  contact_on = 0 (contact is not periodic), dipole_cutoff = 0 and
                                  no tape (ROD_E_INVALID otherwise). The accuracy is the caller's
                                  choice of a, ewald_rcut and ewald_kmax: erfc(a rc) and

@@ -13,7 +13,8 @@
 //     B_i -= 2 (4 pi C / V) g(k) k Re[exp(i k.x_i) S*(k)],  g = exp(-k^2/4a^2)/k^2;
 //   self: B_i += C 4 a^3 / (3 sqrt(pi)) m_i.
 // The torque is m_i x B_i (in the particle kernels' gather) and the energy
-// -1/2 sum m_i.B_i. FP64 on both precision paths.
+// -1/2 sum m_i.B_i. FP64, except the real-space pair law of the mixed path
+// (FP32, as that path's other pair arithmetic).
 //
 // Data flow of one evaluation (all on one stream, no atomics in any sum; ten
 // launches):
@@ -142,10 +143,45 @@ __device__ __forceinline__ void ew_offsets(int nc, int& lo, int& hi) {
 
 // Real-space force and field: EW_RL lanes per sorted position, lane l taking
 // every EW_RL-th particle of each neighbouring cell; the lanes' sums are added
-// by a fixed xor tree, so the result does not depend on scheduling. 1/r from
-// the refined reciprocal square root, r = r^2 / r (no FP64 square root or
-// division per pair).
+// by a fixed xor tree, so the result does not depend on scheduling. The image
+// shift, the separation and the cutoff test are FP64 on both paths. The pair
+// law runs in R: FP64 with 1/r from the refined reciprocal square root, r =
+// r^2 / r (no FP64 square root or division per pair); on the mixed path FP32
+// from the separation rounded once (the pair arithmetic of that path), each
+// lane's sums in FP32 and their tree in FP64.
 constexpr int EW_RL = 16;
+
+// The screened pair law: C (mm Cf r + Cf (dmj mi + dmi mj) - dmi dmj Df r) to
+// F and C (Cf dmj r - Bf mj) to B, with Bf, Cf, Df the erfc-screened 1/r^3,
+// 3/r^5, 15/r^7 (file header).
+template <class R>
+__device__ __forceinline__ void ew_pair(V3<R> r, R r2, V3<R> mi, V3<R> mj, R a, R sp, R C,
+                                        V3<R>& F, V3<R>& B) {
+  R ri, ex, ec;
+  if constexpr (sizeof(R) == 8) {
+    ri = rsqrt_nr(r2);  // hardware estimate, two Newton steps
+  } else {
+    ri = __builtin_amdgcn_rsqf(r2);
+  }
+  const R rr = r2 * ri, ar = a * rr, ar2 = ar * ar;
+  if constexpr (sizeof(R) == 8) {
+    ex = exp(-ar2);
+    ec = erfc(ar);
+  } else {
+    ex = expf(-ar2);
+    ec = erfcf(ar);
+  }
+  const R ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2;
+  const R Bf = (ec + sp * rr * ex) * ri3;
+  const R Cf = (R(3) * ec + sp * rr * (R(3) + R(2) * ar2) * ex) * ri5;
+  const R Df = (R(15) * ec + sp * rr * (R(15) + R(10) * ar2 + R(4) * ar2 * ar2) * ex) *
+               (ri5 * ri2);
+  const R dmi = dot(mi, r), dmj = dot(mj, r), mm = dot(mi, mj);
+  F = F + C * ((mm * Cf) * r + Cf * (dmj * mi + dmi * mj) - (dmi * dmj * Df) * r);
+  B = B + C * ((Cf * dmj) * r - Bf * mj);
+}
+
+template <class R>
 __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long p = t / EW_RL;
@@ -168,7 +204,9 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
   const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
   const double a = d.ew_alpha, rc2 = d.ew_rc * d.ew_rc, C = d.C;
   const double sp = 2.0 * a * 0.56418958354775628695;  // 2 a / sqrt(pi)
-  V3<double> F{0.0, 0.0, 0.0}, B{0.0, 0.0, 0.0};
+  const R aR = (R)a, spR = (R)sp, CR = (R)C;
+  const V3<R> miR = cvt<R>(mi);
+  V3<R> FR{R(0), R(0), R(0)}, BR{R(0), R(0), R(0)};
   int lx, hx, ly, hy, lz, hz;
   ew_offsets(nx, lx, hx);
   ew_offsets(ny, ly, hy);
@@ -212,21 +250,12 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
           const double r2 = dot(r, r);
           if (!(r2 < rc2)) continue;
           const V3<double> mj{rj[4], rj[5], rj[6]};
-          const double ri = rsqrt_nr(r2);  // hardware estimate, two Newton steps
-          const double rr = r2 * ri, ar = a * rr, ar2 = ar * ar;
-          const double ex = exp(-ar2), ec = erfc(ar);
-          const double ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2;
-          const double Bf = (ec + sp * rr * ex) * ri3;
-          const double Cf = (3.0 * ec + sp * rr * (3.0 + 2.0 * ar2) * ex) * ri5;
-          const double Df = (15.0 * ec + sp * rr * (15.0 + 10.0 * ar2 + 4.0 * ar2 * ar2) * ex) *
-                            (ri5 * ri2);
-          const double dmi = dot(mi, r), dmj = dot(mj, r), mm = dot(mi, mj);
-          F = F + C * ((mm * Cf) * r + Cf * (dmj * mi + dmi * mj) - (dmi * dmj * Df) * r);
-          B = B + C * ((Cf * dmj) * r - Bf * mj);
+          ew_pair<R>(cvt<R>(r), (R)r2, miR, cvt<R>(mj), aR, spR, CR, FR, BR);
         }
       }
     }
   }
+  V3<double> F = cvt<double>(FR), B = cvt<double>(BR);
 #pragma unroll
   for (int o = EW_RL / 2; o > 0; o >>= 1) {
     F.x += __shfl_xor(F.x, o); F.y += __shfl_xor(F.y, o); F.z += __shfl_xor(F.z, o);
@@ -386,8 +415,11 @@ hipError_t launch_ewald(const Dev& d, hipStream_t s, const hipEvent_t* ev) {
   hipLaunchKernelGGL(k_ew_scatter, dim3(pg), dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_rank, dim3(pg), dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_pack, dim3(pg), dim3(EW_BLOCK), 0, s, d);
-  hipLaunchKernelGGL(k_ew_real, dim3((unsigned)((EW_RL * d.n + EW_BLOCK - 1) / EW_BLOCK)),
-                     dim3(EW_BLOCK), 0, s, d);
+  const dim3 rg((unsigned)((EW_RL * d.n + EW_BLOCK - 1) / EW_BLOCK));
+  if (d.muf)  // the mixed path
+    hipLaunchKernelGGL(k_ew_real<float>, rg, dim3(EW_BLOCK), 0, s, d);
+  else
+    hipLaunchKernelGGL(k_ew_real<double>, rg, dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_sk, dim3((unsigned)((d.ew_SEG + EW_BLOCK - 1) / EW_BLOCK), (unsigned)d.ew_TC),
                      dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_sreduce, dim3((unsigned)(((long)d.M * d.ew_K + EW_BLOCK - 1) / EW_BLOCK)),
