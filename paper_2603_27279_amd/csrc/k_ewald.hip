@@ -273,7 +273,6 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
 // follows from its first value by repeated rotation through exp(i dkz z),
 // dkz = 2 pi / L_z: one sincos per segment instead of per vector (the rotation
 // adds an error of a few ulp per step).
-constexpr int EW_SEG = 8;
 
 // Partial structure factors: block (segment block, chunk); thread = one
 // segment; the chunk's particles (at most EW_BLOCK sorted positions of one
@@ -331,7 +330,8 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_sk(Dev d) {
     }
 }
 
-// S(k) of every member: its chunks added in chunk order.
+// S(k) of every member: its chunks added in chunk order, times the vector's
+// weight (the only use of S(k) is weighted).
 __global__ __launch_bounds__(EW_BLOCK) void k_ew_sreduce(Dev d) {
   const int K = d.ew_K;
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -343,24 +343,30 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_sreduce(Dev d) {
     Sr += s[0];
     Si += s[1];
   }
-  d.ew_S[2 * t] = Sr;
-  d.ew_S[2 * t + 1] = Si;
+  const double c = d.ew_k[4 * (long)kk + 3];
+  d.ew_S[2 * t] = c * Sr;
+  d.ew_S[2 * t + 1] = c * Si;
 }
 
-// Reciprocal-space force and field. Block = 32 sorted positions of one chunk
-// (blockIdx.y picks which 32 of its 256) x 8 k lanes: thread (pl, kl) takes
-// every 8th segment, its k vectors, weights and the member's S(k) read as
-// broadcasts, exp(i k.x) rotated along the segment; the 8 partial sums of a
-// particle are then added in lane order through LDS.
-constexpr int EW_KP = 32;  // particles per kspace block
-constexpr int EW_KL = 8;   // k lanes per particle
-__global__ __launch_bounds__(EW_BLOCK) void k_ew_kspace(Dev d) {
-  __shared__ double red[6 * EW_BLOCK];
+// Reciprocal-space force and field. Block = 64 sorted positions of one chunk
+// (one per lane; blockIdx.y picks which 64 of its 256) x 8 waves: wave w takes
+// every 8th row of k vectors (fixed n_x, n_y), so that a row's vectors and the
+// member's weighted S(k) are the same for the whole wave (scalar loads), and
+// exp(i k.x) follows along each run of EW_SEG vectors from one sincos by
+// rotation through exp(i dkz z). Along a row only k_z changes, so the k_x and
+// k_y parts of the sums are taken once per row. The 8 partial sums of a particle are then added
+// in wave order through LDS.
+constexpr int EW_KP = 64;  // particles per kspace block, one per lane
+constexpr int EW_KL = 8;   // waves per kspace block, each its own rows
+constexpr int EW_KBLOCK = EW_KP * EW_KL;
+__global__ __launch_bounds__(EW_KBLOCK) void k_ew_kspace(Dev d) {
+  __shared__ double red[6 * EW_KBLOCK];
   const long N = d.n;
   const int K = d.ew_K;
   const int ch = blockIdx.x;
   const int b = d.ew_chunks[3 * ch], e = d.ew_chunks[3 * ch + 1], mem = d.ew_chunks[3 * ch + 2];
-  const int pl = threadIdx.x & (EW_KP - 1), kl = threadIdx.x / EW_KP;
+  const int pl = threadIdx.x % EW_KP;
+  const int kl = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / EW_KP));
   const int p = b + (int)blockIdx.y * EW_KP + pl;
   const bool pv = p < e;
   V3<double> xi{0.0, 0.0, 0.0}, mi{0.0, 0.0, 0.0};
@@ -371,24 +377,43 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_kspace(Dev d) {
   }
   double rs, rc;
   sincos(d.ew_dkz * xi.z, &rs, &rc);
+  const double mdz = mi.z * d.ew_dkz;
   V3<double> F{0.0, 0.0, 0.0}, B{0.0, 0.0, 0.0};
   const double* S = d.ew_S + 2 * (long)mem * K;
-  for (int sg = kl; sg < d.ew_SEG; sg += EW_KL) {
-    const int k0 = d.ew_seg[2 * sg], nk = d.ew_seg[2 * sg + 1];
+  for (int rw = kl; rw < d.ew_ROWS; rw += EW_KL) {
+    const int k0 = d.ew_row[2 * rw], nk = d.ew_row[2 * rw + 1];
     const double* kv = d.ew_k + 4 * (long)k0;
-    V3<double> k{kv[0], kv[1], kv[2]};
-    double sn, cs;
-    sincos(dot(k, xi), &sn, &cs);
+    const double* sk = S + 2 * (long)k0;
+    const double kx = kv[0], ky = kv[1];
+    double mk = mi.x * kx + mi.y * ky + mi.z * kv[2];
+    double sn = 0.0, cs = 1.0;
+    // sums along the row: a = m.k Im(conj(S) e^{ikx}) and g = Re(conj(S) e^{ikx}),
+    // each also weighted by k_z
+    double A = 0.0, Az = 0.0, G = 0.0, Gz = 0.0;
     for (int m = 0; m < nk; ++m) {
-      const double c = kv[4 * m + 3], Sr = S[2 * (k0 + m)], Si = S[2 * (k0 + m) + 1];
-      const double mk = dot(mi, k);
-      F = F + (c * mk * (sn * Sr - cs * Si)) * k;
-      B = B - (c * (cs * Sr + sn * Si)) * k;
+      const double Sr = sk[2 * m], Si = sk[2 * m + 1], kzm = kv[4 * m + 2];
+      // the phase restarts where the structure factors' runs of EW_SEG start
+      // (every EW_SEG vectors of a row), with the same operations, so that a
+      // particle's own part of S(k) meets the same bits of exp(i k.x) and its
+      // self term cancels to rounding
+      if (m % EW_SEG == 0) sincos(kx * xi.x + ky * xi.y + kzm * xi.z, &sn, &cs);
+      const double a = mk * (sn * Sr - cs * Si);
+      const double g = cs * Sr + sn * Si;
+      A += a;
+      Az += a * kzm;
+      G += g;
+      Gz += g * kzm;
       const double c2 = cs * rc - sn * rs;
       sn = sn * rc + cs * rs;
       cs = c2;
-      k.z += d.ew_dkz;
+      mk += mdz;
     }
+    F.x += kx * A;
+    F.y += ky * A;
+    F.z += Az;
+    B.x -= kx * G;
+    B.y -= ky * G;
+    B.z -= Gz;
   }
   double* o6 = red + 6 * threadIdx.x;
   o6[0] = F.x; o6[1] = F.y; o6[2] = F.z; o6[3] = B.x; o6[4] = B.y; o6[5] = B.z;
@@ -424,8 +449,8 @@ hipError_t launch_ewald(const Dev& d, hipStream_t s, const hipEvent_t* ev) {
                      dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_sreduce, dim3((unsigned)(((long)d.M * d.ew_K + EW_BLOCK - 1) / EW_BLOCK)),
                      dim3(EW_BLOCK), 0, s, d);
-  static_assert(EW_KP * EW_KL == EW_BLOCK && EW_CHUNK % EW_KP == 0, "kspace block shape");
-  hipLaunchKernelGGL(k_ew_kspace, dim3((unsigned)d.ew_TC, EW_CHUNK / EW_KP), dim3(EW_BLOCK), 0, s, d);
+  static_assert(EW_CHUNK % EW_KP == 0, "kspace block shape");
+  hipLaunchKernelGGL(k_ew_kspace, dim3((unsigned)d.ew_TC, EW_CHUNK / EW_KP), dim3(EW_KBLOCK), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev) return hipEventRecord(ev[1], s);
   return hipSuccess;

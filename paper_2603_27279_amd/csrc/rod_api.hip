@@ -473,7 +473,7 @@ static int build_dipole_plan(rod_ctx* c, int small_req, int target_wgs) {
 // with n_z rising, and the rows cut into segments of at most 8 vectors
 // ([first, count] pairs in *seg).
 static void ewald_vectors(const rod_desc* dsc, std::vector<double>* kt,
-                          std::vector<int>* seg = nullptr) {
+                          std::vector<int>* seg = nullptr, std::vector<int>* rows = nullptr) {
   const double pi = 3.14159265358979323846;
   const double* L = dsc->box;
   const double V = L[0] * L[1] * L[2], a = dsc->ewald_alpha;
@@ -488,14 +488,22 @@ static void ewald_vectors(const rod_desc* dsc, std::vector<double>* kt,
         const int idx = (int)(kt->size() / 4);
         kt->push_back(kx); kt->push_back(ky); kt->push_back(kz);
         kt->push_back(2.0 * 4.0 * pi * dsc->mu0_4pi / V * std::exp(-k2 / (4.0 * a * a)) / k2);
-        if (seg) {  // a new segment at the start of a row or after 8 vectors
-          const bool row_start = seg->empty() || nz == -K ||
-                                 (*kt)[4 * (idx - 1)] != kx || (*kt)[4 * (idx - 1) + 1] != ky;
-          if (row_start || seg->back() == 8) {
+        const bool row_start = idx == 0 || nz == -K ||
+                               (*kt)[4 * (idx - 1)] != kx || (*kt)[4 * (idx - 1) + 1] != ky;
+        if (seg) {  // a new segment at the start of a row or after EW_SEG vectors
+          if (row_start || seg->back() == EW_SEG) {
             seg->push_back(idx);
             seg->push_back(1);
           } else {
             seg->back() += 1;
+          }
+        }
+        if (rows) {
+          if (row_start) {
+            rows->push_back(idx);
+            rows->push_back(1);
+          } else {
+            rows->back() += 1;
           }
         }
       }
@@ -534,8 +542,8 @@ static int ewald_setup(rod_ctx* c, const rod_desc* dsc, const std::vector<int>& 
   d.ew_K = K;
   d.ew_TC = TC;
   std::vector<double> kt;
-  std::vector<int> seg;
-  ewald_vectors(dsc, &kt, &seg);
+  std::vector<int> seg, rows;
+  ewald_vectors(dsc, &kt, &seg, &rows);
   std::vector<int> chunks, coff(M + 1, 0);
   for (int m = 0; m < M; ++m) {
     coff[m] = (int)(chunks.size() / 3);
@@ -547,7 +555,7 @@ static int ewald_setup(rod_ctx* c, const rod_desc* dsc, const std::vector<int>& 
   }
   coff[M] = (int)(chunks.size() / 3);
   double* kdev = nullptr;
-  int *chd = nullptr, *cod = nullptr, *sgd = nullptr;
+  int *chd = nullptr, *cod = nullptr, *sgd = nullptr, *rwd = nullptr;
   TRY(dalloc(c, &d.ew_cnt, (size_t)M * ncell));
   TRY(dalloc(c, &d.ew_start, (size_t)M * ncell + 1));
   TRY(dalloc(c, &d.ew_cell, (size_t)N));
@@ -559,14 +567,18 @@ static int ewald_setup(rod_ctx* c, const rod_desc* dsc, const std::vector<int>& 
   TRY(dalloc(c, &chd, chunks.size()));
   TRY(dalloc(c, &cod, coff.size()));
   TRY(dalloc(c, &sgd, seg.size()));
+  TRY(dalloc(c, &rwd, rows.size()));
   TRY(dalloc(c, &d.ew_Sp, 2 * (size_t)TC * K));
   TRY(dalloc(c, &d.ew_S, 2 * (size_t)M * K));
   HIPC(hipMemcpy(kdev, kt.data(), kt.size() * sizeof(double), hipMemcpyHostToDevice));
   HIPC(hipMemcpy(chd, chunks.data(), chunks.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPC(hipMemcpy(cod, coff.data(), coff.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPC(hipMemcpy(sgd, seg.data(), seg.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(rwd, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice));
   d.ew_seg = sgd;
   d.ew_SEG = (int)(seg.size() / 2);
+  d.ew_row = rwd;
+  d.ew_ROWS = (int)(rows.size() / 2);
   d.ew_dkz = 2.0 * 3.14159265358979323846 / dsc->box[2];
   d.ew_k = kdev;
   d.ew_chunks = chd;

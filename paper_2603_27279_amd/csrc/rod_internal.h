@@ -161,14 +161,16 @@ struct Dev {
   double* ew_xm;           // [N][8] wrapped x, y, z, 0, m_x, m_y, m_z, 0 in sorted order
   const double* ew_k;      // [K][4] k_x, k_y, k_z, 2 (4 pi C / V) exp(-k^2 / 4 a^2) / k^2
   int ew_K;
-  const int* ew_seg;       // [SEG][2] first vector and count (<= 8) of runs along k_z
+  const int* ew_seg;       // [SEG][2] first vector and count (<= EW_SEG) of runs along k_z
   int ew_SEG;
+  const int* ew_row;       // [ROWS][2] first vector and count of each row (fixed n_x, n_y)
+  int ew_ROWS;
   double ew_dkz;           // 2 pi / L_z, the k_z step along a run
   const int* ew_chunks;    // [TC][3] sorted range [begin, end) of at most 256 and the member
   const int* ew_chunk_off; // [M + 1] first chunk of each member
   int ew_TC;
   double* ew_Sp;           // [TC][K][2] structure factor of each chunk
-  double* ew_S;            // [M][K][2] structure factor of each member
+  double* ew_S;            // [M][K][2] structure factor of each member times the k weight
   // Immersed-boundary penalty (set only on the copy a coupled cycle launches
   // with): fluid velocity at the particles [3][N], the penalty force of the
   // evaluation written to ibm_f [3][N], stiffness m_p * ibm_idt.
@@ -275,6 +277,7 @@ hipError_t launch_spatial_boxes(const Dev& d, hipStream_t s);
 // force and field to slot 0 of the FP64 partial sums.
 hipError_t launch_ewald(const Dev& d, hipStream_t s, const hipEvent_t* ev = nullptr);
 constexpr int EW_CHUNK = 256;   // particles per structure-factor chunk
+constexpr int EW_SEG = 8;       // k vectors per run of one row (one sincos per run)
 constexpr int EW_MAX_NC = 256;  // cells per box axis at most
 constexpr int EW_REACH = 3;     // real-space cells of side >= rc / EW_REACH
 // build: rebuild contact candidate lists (large systems) regardless of motion.
