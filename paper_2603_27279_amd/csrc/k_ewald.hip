@@ -30,8 +30,10 @@
 //   sk:      partial structure factors of 256-particle chunks, one thread per
 //            segment of up to 8 k vectors along a row;
 //   sreduce: S(k) of each member, its chunks added in order;
-//   kspace:  eight threads per sorted position share the k segments, their
-//            partial sums added in a fixed order, and add to F, B.
+//   kspace:  eight waves per 64 sorted positions, each wave its own rows of
+//            k vectors, their partial sums added in a fixed order; add to F, B.
+#include <type_traits>
+
 #include "rod.h"
 #include "rod_internal.h"
 #include "rod_math.h"
@@ -151,25 +153,55 @@ __device__ __forceinline__ void ew_offsets(int nc, int& lo, int& hi) {
 // lane's sums in FP32 and their tree in FP64.
 constexpr int EW_RL = 16;
 
+// erfc(x), x >= 0, on the mixed path: the Chebyshev-fitted form of Numerical
+// Recipes' erfcc, erfc(x) = t exp(-x^2 + P(t)) with t = 1 / (1 + x/2) and P of
+// degree 9, whose fractional error stays below 1.2e-7 for every x >= 0. exp(-x^2)
+// is the pair law's own factor ex, so only exp(P) (-1.3 < P <= 0) is taken
+// here, as a base-2 exponential with the coefficients prescaled by log2(e).
+constexpr double EW_LOG2E = 1.4426950408889634;
+__device__ __forceinline__ float erfc_fit(float x, float ex) {
+  constexpr float c0 = (float)(-1.26551223 * EW_LOG2E), c1 = (float)(1.00002368 * EW_LOG2E),
+                  c2 = (float)(0.37409196 * EW_LOG2E), c3 = (float)(0.09678418 * EW_LOG2E),
+                  c4 = (float)(-0.18628806 * EW_LOG2E), c5 = (float)(0.27886807 * EW_LOG2E),
+                  c6 = (float)(-1.13520398 * EW_LOG2E), c7 = (float)(1.48851587 * EW_LOG2E),
+                  c8 = (float)(-0.82215223 * EW_LOG2E), c9 = (float)(0.17087277 * EW_LOG2E);
+  const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.5f, x, 1.0f));
+  float q = __builtin_fmaf(c9, t, c8);
+  q = __builtin_fmaf(q, t, c7);
+  q = __builtin_fmaf(q, t, c6);
+  q = __builtin_fmaf(q, t, c5);
+  q = __builtin_fmaf(q, t, c4);
+  q = __builtin_fmaf(q, t, c3);
+  q = __builtin_fmaf(q, t, c2);
+  q = __builtin_fmaf(q, t, c1);
+  q = __builtin_fmaf(q, t, c0);
+  return (t * ex) * __builtin_amdgcn_exp2f(q);
+}
+
 // The screened pair law: C (mm Cf r + Cf (dmj mi + dmi mj) - dmi dmj Df r) to
 // F and C (Cf dmj r - Bf mj) to B, with Bf, Cf, Df the erfc-screened 1/r^3,
-// 3/r^5, 15/r^7 (file header).
+// 3/r^5, 15/r^7 (file header). The FP32 form takes exp(-(a r)^2) with the
+// rounding of (a r)^2 put back to first order (its exact low part from an FMA),
+// and erfc from the fit above.
 template <class R>
 __device__ __forceinline__ void ew_pair(V3<R> r, R r2, V3<R> mi, V3<R> mj, R a, R sp, R C,
                                         V3<R>& F, V3<R>& B) {
-  R ri, ex, ec;
+  R ri, ex, ec, ar2;
   if constexpr (sizeof(R) == 8) {
     ri = rsqrt_nr(r2);  // hardware estimate, two Newton steps
   } else {
     ri = __builtin_amdgcn_rsqf(r2);
   }
-  const R rr = r2 * ri, ar = a * rr, ar2 = ar * ar;
+  const R rr = r2 * ri, ar = a * rr;
+  ar2 = ar * ar;
   if constexpr (sizeof(R) == 8) {
     ex = exp(-ar2);
     ec = erfc(ar);
   } else {
+    const float lo = __builtin_fmaf(ar, ar, -ar2);
     ex = expf(-ar2);
-    ec = erfcf(ar);
+    ex = __builtin_fmaf(-lo, ex, ex);
+    ec = erfc_fit(ar, ex);
   }
   const R ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2;
   const R Bf = (ec + sp * rr * ex) * ri3;
@@ -224,37 +256,48 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
     const double g = w ? 0.0 : fmax(fmax((double)u * h - x, x - (double)(u + 1) * h), 0.0);
     return g * g;
   };
-  for (int oz = lz; oz <= hz && pv; ++oz) {
-    const int uz = cz + oz, gz = (uz + nz) % nz;
-    const double gz2 = gap(xi.z, uz, hzs, wz);
-    if (gz2 > reach2) continue;
-    const double sz = wz ? 0.0 : (uz < 0 ? Lz : (uz >= nz ? -Lz : 0.0));
-    for (int oy = ly; oy <= hy; ++oy) {
-      const int uy = cy + oy, gy = (uy + ny) % ny;
-      const double gyz2 = gz2 + gap(xi.y, uy, hys, wy);
-      if (gyz2 > reach2) continue;
-      const double sy = wy ? 0.0 : (uy < 0 ? Ly : (uy >= ny ? -Ly : 0.0));
-      for (int ox = lx; ox <= hx; ++ox) {
-        const int ux = cx + ox, gx = (ux + nx) % nx;
-        if (gyz2 + gap(xi.x, ux, hxs, wx) > reach2) continue;
-        const double sx = wx ? 0.0 : (ux < 0 ? Lx : (ux >= nx ? -Lx : 0.0));
-        const int cc = mem * d.ew_ncell + (gz * ny + gy) * nx + gx;
-        const int qe = d.ew_start[cc + 1];
-        for (int q = d.ew_start[cc] + sub; q < qe; q += EW_RL) {
-          if (q == p) continue;
-          const double* rj = d.ew_xm + 8 * (long)q;
-          V3<double> r{(xi.x - rj[0]) + sx, (xi.y - rj[1]) + sy, (xi.z - rj[2]) + sz};
-          if (wx) r.x -= Lx * rint(r.x * iLx);  // minimum image
-          if (wy) r.y -= Ly * rint(r.y * iLy);
-          if (wz) r.z -= Lz * rint(r.z * iLz);
-          const double r2 = dot(r, r);
-          if (!(r2 < rc2)) continue;
-          const V3<double> mj{rj[4], rj[5], rj[6]};
-          ew_pair<R>(cvt<R>(r), (R)r2, miR, cvt<R>(mj), aR, spR, CR, FR, BR);
+  // the walk, compiled once without the minimum image (every axis wide enough)
+  // and once with it, so the common case carries no per-pair selects
+  auto walk = [&](auto narrow) {
+    constexpr bool NW = decltype(narrow)::value;
+    for (int oz = lz; oz <= hz && pv; ++oz) {
+      const int uz = cz + oz, gz = (uz + nz) % nz;
+      const double gz2 = gap(xi.z, uz, hzs, NW && wz);
+      if (gz2 > reach2) continue;
+      const double sz = NW && wz ? 0.0 : (uz < 0 ? Lz : (uz >= nz ? -Lz : 0.0));
+      for (int oy = ly; oy <= hy; ++oy) {
+        const int uy = cy + oy, gy = (uy + ny) % ny;
+        const double gyz2 = gz2 + gap(xi.y, uy, hys, NW && wy);
+        if (gyz2 > reach2) continue;
+        const double sy = NW && wy ? 0.0 : (uy < 0 ? Ly : (uy >= ny ? -Ly : 0.0));
+        for (int ox = lx; ox <= hx; ++ox) {
+          const int ux = cx + ox, gx = (ux + nx) % nx;
+          if (gyz2 + gap(xi.x, ux, hxs, NW && wx) > reach2) continue;
+          const double sx = NW && wx ? 0.0 : (ux < 0 ? Lx : (ux >= nx ? -Lx : 0.0));
+          const int cc = mem * d.ew_ncell + (gz * ny + gy) * nx + gx;
+          const int qe = d.ew_start[cc + 1];
+          for (int q = d.ew_start[cc] + sub; q < qe; q += EW_RL) {
+            if (q == p) continue;
+            const double* rj = d.ew_xm + 8 * (long)q;
+            V3<double> r{(xi.x - rj[0]) + sx, (xi.y - rj[1]) + sy, (xi.z - rj[2]) + sz};
+            if constexpr (NW) {
+              if (wx) r.x -= Lx * rint(r.x * iLx);  // minimum image
+              if (wy) r.y -= Ly * rint(r.y * iLy);
+              if (wz) r.z -= Lz * rint(r.z * iLz);
+            }
+            const double r2 = dot(r, r);
+            if (!(r2 < rc2)) continue;
+            const V3<double> mj{rj[4], rj[5], rj[6]};
+            ew_pair<R>(cvt<R>(r), (R)r2, miR, cvt<R>(mj), aR, spR, CR, FR, BR);
+          }
         }
       }
     }
-  }
+  };
+  if (wx || wy || wz)
+    walk(std::true_type{});
+  else
+    walk(std::false_type{});
   V3<double> F = cvt<double>(FR), B = cvt<double>(BR);
 #pragma unroll
   for (int o = EW_RL / 2; o > 0; o >>= 1) {
