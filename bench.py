@@ -31,6 +31,12 @@ sys.path.insert(0, ROOT)
 FLOP_PER_PAIR = 67.0        # algorithmic FP32 flops per ordered dipole pair (FMA = 2)
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector peak (vendor figure)
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector peak (vendor figure)
+# Algorithmic flops of one ordered real-space pair of the Ewald sum (FMA = 2; the
+# square root, exp and erfc one each): 1/r, r, a r, (a r)^2, exp, erfc (6); 1/r^2,
+# 1/r^3, 1/r^5, 1/r^7 (4); the shared sp r exp factor (2); the screened B, C, D
+# factors (2 + 6 + 9); three dot products (15); the force (33) and field (16)
+# terms with C and their accumulation.
+EWALD_PAIR_FLOPS = 93.0
 METRIC = "particle-steps/s and dipole pair-evals/s (% FP32 peak); adjoint/forward time"
 
 WORKLOADS = {
@@ -468,9 +474,16 @@ def ewald_leg(grid=32, length=32, box=(64.0, 64.0, 40.0), rcut=16.0, steps=20):
     sim.step(5)
     kt = sim.kernel_times()
     sim.timing(False)
+    x_end = np.asarray(sim.state()["x"], dtype=np.float64)
     sim.free()
     ew_ms = kt["dipole"][0] / kt["dipole"][1]
-    rho = n / float(np.prod(box))
+    real_ms = kt["ewald_real"][0] / kt["ewald_real"][1]
+    # real-space pairs (i, j) closer than rcut by the minimum image, each
+    # evaluated once per particle of the pair (ordered pairs)
+    from scipy.spatial import cKDTree
+    bx = np.asarray(box, float)
+    tree = cKDTree(np.mod(x_end, bx), boxsize=bx)
+    ordered = int(tree.count_neighbors(tree, rcut)) - n
     kmax = w["ewald_kmax"]
     nk = sum(1 for a in range(0, kmax + 1) for b in range(-kmax, kmax + 1)
              for c in range(-kmax, kmax + 1)
@@ -480,7 +493,14 @@ def ewald_leg(grid=32, length=32, box=(64.0, 64.0, 40.0), rcut=16.0, steps=20):
                         f"alpha {alpha:.4f}, kmax {kmax}), mixed precision rods",
             "particles": n, "ms_per_step": ms, "particle_steps_per_s": n / (ms * 1e-3),
             "ewald_ms_per_evaluation": ew_ms,
-            "real_space_pairs_per_particle": 4.0 / 3.0 * np.pi * rcut ** 3 * rho,
+            "real_space_ms_per_evaluation": real_ms,
+            "real_space_pairs_per_particle": ordered / n,
+            "roofline": {"bound": "alu", "kernel": "k_ew_real<float>",
+                         "achieved": ordered * EWALD_PAIR_FLOPS / (real_ms * 1e-3) / 1e12,
+                         "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": ordered * EWALD_PAIR_FLOPS / (real_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                         "flops_per_pair": EWALD_PAIR_FLOPS, "ordered_pairs": ordered,
+                         "traffic": None},
             "reciprocal_vectors_half_space": nk,
             "reciprocal_terms_per_s": 2.0 * nk * n / (ew_ms * 1e-3)}
 

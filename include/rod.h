@@ -312,7 +312,9 @@ enum {
   ROD_KERNEL_KICK = 6,    /* post of one step fused with pre of the next */
   ROD_KERNEL_CELLS = 7,   /* cell-list fill before the contact launch when stepping with
                              candidate lists (empty unless the lists are rebuilt) */
-  ROD_KERNEL_COUNT = 8
+  ROD_KERNEL_EWALD_REAL = 8, /* the Ewald sum's real-space walk alone (with a box; its time is
+                                also part of ROD_KERNEL_DIPOLE, which covers the whole sum) */
+  ROD_KERNEL_COUNT = 9
 };
 int rod_timing(rod_ctx* c, int32_t enable);
 int rod_kernel_times(rod_ctx* c, double* ms, int64_t* launches);

@@ -15,7 +15,7 @@ TERM_BOND, TERM_DIPOLE, TERM_ZEEMAN, TERM_CONTACT, TERM_DAMP, TERM_EXT, TERM_ALL
 ROD_NOALLOC_MAX_PAIRS = 1048576  # include/rod.h
 ROD_HM_MAX_CONTACTS = 32  # include/rod.h
 
-KERNELS = ("pre", "bond", "dipole", "contact", "post", "forces", "kick", "cells")
+KERNELS = ("pre", "bond", "dipole", "contact", "post", "forces", "kick", "cells", "ewald_real")
 
 _P = C.c_void_p
 

@@ -471,7 +471,7 @@ __global__ __launch_bounds__(EW_KBLOCK) void k_ew_kspace(Dev d) {
   o[3 * N + i] += t[3]; o[4 * N + i] += t[4]; o[5 * N + i] += t[5];
 }
 
-hipError_t launch_ewald(const Dev& d, hipStream_t s, const hipEvent_t* ev) {
+hipError_t launch_ewald(const Dev& d, const hipEvent_t* ev_real, hipStream_t s, const hipEvent_t* ev) {
   const int total = d.M * d.ew_ncell;
   const unsigned pg = (unsigned)((d.n + EW_BLOCK - 1) / EW_BLOCK);
   hipError_t e = launch_fill_i32(d.ew_cnt, total, 0, s);
@@ -485,9 +485,9 @@ hipError_t launch_ewald(const Dev& d, hipStream_t s, const hipEvent_t* ev) {
   hipLaunchKernelGGL(k_ew_pack, dim3(pg), dim3(EW_BLOCK), 0, s, d);
   const dim3 rg((unsigned)((EW_RL * d.n + EW_BLOCK - 1) / EW_BLOCK));
   if (d.muf)  // the mixed path
-    hipLaunchKernelGGL(k_ew_real<float>, rg, dim3(EW_BLOCK), 0, s, d);
+    launch_k(ev_real, k_ew_real<float>, rg, dim3(EW_BLOCK), s, d);
   else
-    hipLaunchKernelGGL(k_ew_real<double>, rg, dim3(EW_BLOCK), 0, s, d);
+    launch_k(ev_real, k_ew_real<double>, rg, dim3(EW_BLOCK), s, d);
   hipLaunchKernelGGL(k_ew_sk, dim3((unsigned)((d.ew_SEG + EW_BLOCK - 1) / EW_BLOCK), (unsigned)d.ew_TC),
                      dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_sreduce, dim3((unsigned)(((long)d.M * d.ew_K + EW_BLOCK - 1) / EW_BLOCK)),

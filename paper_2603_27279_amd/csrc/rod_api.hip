@@ -673,20 +673,28 @@ static int contact_term(rod_ctx* c, const Dev& d, int want_energy, int build) {
   return ROD_OK;
 }
 
+// The Ewald sum, timed as a whole (dipole class) and its real-space walk alone.
+static int ewald_term(rod_ctx* c, const Dev& d) {
+  const hipEvent_t* evr = nullptr;
+  TRY(timing_events(c, ROD_KERNEL_EWALD_REAL, &evr));
+  TIMED(c, ROD_KERNEL_DIPOLE, launch_ewald, d, evr, c->s);
+  return ROD_OK;
+}
+
 // build: rebuild the contact candidate lists of large systems this step.
 static int force_terms(rod_ctx* c, const Dev& d, int want_energy, int build) {
   if (!want_energy && c->launch_mode == ROD_LAUNCH_BATCHED) {
     TIMED(c, ROD_KERNEL_FORCES, launch_forces, d, c->desc.precision, c->work, c->nwork, c->s);
     if (c->desc.contact_on && !contact_in_forces(d)) TRY(contact_term(c, d, 0, build));
     if (d.dcut > 0) TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole_cut, d, build, c->s);
-    if (d.ew_on) TIMED(c, ROD_KERNEL_DIPOLE, launch_ewald, d, c->s);
+    if (d.ew_on) TRY(ewald_term(c, d));
     return ROD_OK;
   }
   TIMED(c, ROD_KERNEL_BOND, launch_bond, d, c->desc.precision, want_energy, c->s);
   if (c->desc.dipole_on && d.dcut > 0)
     TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole_cut, d, build, c->s);
   else if (d.ew_on)
-    TIMED(c, ROD_KERNEL_DIPOLE, launch_ewald, d, c->s);
+    TRY(ewald_term(c, d));
   else if (c->desc.dipole_on)
     TIMED(c, ROD_KERNEL_DIPOLE, launch_dipole, d, c->desc.precision, c->work, c->nwork, c->s);
   if (c->desc.contact_on) TRY(contact_term(c, d, want_energy, build));
@@ -802,7 +810,7 @@ static int enqueue_step_per_rod(rod_ctx* c) {
     for (int r = 0; r < R; ++r) HIPC(launch_dipole_cut(rod_dev(r), 1, c->s));
   }
   else if (c->d.ew_on)  // one periodic sum over every member (not separable by rod)
-    HIPC(launch_ewald(c->d, c->s));
+    HIPC(launch_ewald(c->d, nullptr, c->s));
   else if (c->desc.dipole_on)
     for (int r = 0; r < R; ++r)
       HIPC(launch_dipole(rod_dev(r), c->desc.precision, c->rod_work + c->rod_work_off[r],

@@ -275,7 +275,10 @@ hipError_t launch_dipole_sort(const Dev& d, int build, hipStream_t s);
 hipError_t launch_spatial_boxes(const Dev& d, hipStream_t s);
 // Ewald sum of the dipoles of a periodic box (d.ew_on): writes the dipole
 // force and field to slot 0 of the FP64 partial sums.
-hipError_t launch_ewald(const Dev& d, hipStream_t s, const hipEvent_t* ev = nullptr);
+// ev_real (timing mode, else NULL): the runtime stamps the real-space walk's own
+// start and end on it; ev brackets the whole sum.
+hipError_t launch_ewald(const Dev& d, const hipEvent_t* ev_real, hipStream_t s,
+                        const hipEvent_t* ev = nullptr);
 constexpr int EW_CHUNK = 256;   // particles per structure-factor chunk
 constexpr int EW_SEG = 8;       // k vectors per run of one row (one sincos per run)
 constexpr int EW_MAX_NC = 256;  // cells per box axis at most

@@ -146,6 +146,30 @@ def test_mixed_path_graphs_launch_forms_and_repeats_bitwise():
             np.testing.assert_array_equal(r[k], runs[0][k])
 
 
+@pytest.mark.parametrize("mode", ["batched", "separate"])
+def test_timing_classes_of_the_sum(mode):
+    """In timing mode the whole sum is timed as the dipole class and its
+    real-space walk alone as its own class, once per force evaluation, the walk
+    taking part of the sum's time; timing leaves the results unchanged."""
+    w = CASES["many_cells"]()
+    ref = RodSim(w, precision="mixed")
+    ref.step(6)
+    st_ref = ref.state()
+    ref.free()
+    s = RodSim(w, precision="mixed")
+    s.launch_mode(mode)
+    s.timing(True)
+    s.step(6)
+    kt = s.kernel_times()
+    s.timing(False)
+    st = s.state()
+    s.free()
+    assert kt["ewald_real"][1] == kt["dipole"][1] >= 6
+    assert 0 < kt["ewald_real"][0] < kt["dipole"][0]
+    for k in ("x", "v", "q", "w"):
+        np.testing.assert_array_equal(st[k], st_ref[k])
+
+
 def test_descriptor_checks():
     """Box and Ewald parameters are validated before any device work."""
     from paper_2603_27279_amd._lib import ROD_E_INVALID, RodError
