@@ -321,12 +321,14 @@ int rod_kernel_times(rod_ctx* c, double* ms, int64_t* launches);
 
 /* Autotuner for the work layout of the all-pairs dipole kernel (the dominant
  * kernel). Candidates: the small-member layout (one wave per target, four
- * targets per workgroup; members of at most 16384 particles) and the split
- * layout (64 targets per workgroup, each member's sources split into enough
- * ranges to give the launch 512 ... 32768 work items; distinct work lists are
- * timed once). Each candidate is timed with HIP
- * events on the library's stream over repeated force evaluations at the
- * current state (the state is not changed); the fastest is applied. With a
+ * targets per workgroup; members of at most 16384 particles), then the split
+ * layout in particle order and in spatial order (64 targets per workgroup,
+ * each member's sources split into enough ranges to give the launch 512 ...
+ * 32768 work items; distinct work lists are timed once). Each candidate is
+ * timed with HIP events on the library's stream over repeated force
+ * evaluations at the current state (the state is not changed); the fastest is
+ * applied, candidates within 1% of it counting as equal (the first of them in
+ * the order above wins, so that timing noise does not flip the choice). With a
  * non-NULL cache_path (a JSON-lines file) the choice is looked up first
  * (unless force != 0) under a key of GPU architecture, precision and member
  * sizes, and a new choice is appended. A text report is copied into `report`

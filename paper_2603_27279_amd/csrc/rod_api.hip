@@ -1597,6 +1597,8 @@ extern "C" int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, c
     best_us = 1e300;
     // split targets that give the same work list (in the same order) are timed once
     std::vector<std::pair<int, int>> seen;
+    struct Timed { int small, target; double us; };
+    std::vector<Timed> timed;
     for (const Cand& cd : cands) {
       TRY(build_dipole_plan(c, cd.small, cd.target));
       if (cd.small != 1) {
@@ -1610,8 +1612,17 @@ extern "C" int rod_autotune(rod_ctx* c, const char* cache_path, int32_t force, c
       snprintf(line, sizeof(line), "%s target_wgs=%d work_items=%d slots=%d: %.2f us/eval\n",
                layout_name(cd.small), cd.target, c->nwork, c->max_slots, us);
       rep += line;
-      if (us < best_us) { best_us = us; small = cd.small; target = cd.target; }
+      timed.push_back({cd.small, cd.target, us});
+      best_us = std::min(best_us, us);
     }
+    // Candidates within 1% of the fastest are taken as equal, and the first of
+    // them in the candidate order wins, so that timing noise between runs does
+    // not flip the choice between near-equal layouts.
+    for (const Timed& t : timed)
+      if (t.us <= 1.01 * best_us) {
+        small = t.small; target = t.target; best_us = t.us;
+        break;
+      }
     if (cache_path) {
       if (FILE* f = fopen(cache_path, "a")) {
         fprintf(f, "{\"key\": \"%s\", \"small\": %d, \"target_wgs\": %d, \"us_per_eval\": %.3f}\n",
