@@ -722,7 +722,10 @@ def workload_leg(name, prec, steps, warmup, graph_steps, timing_steps, per_rod_s
     sim = RodSim(w, precision=prec, graph_steps=gs)
     tune = None
     if autotune:
-        tune = sim.autotune(tune_cache).strip().splitlines()[-1]
+        report = sim.autotune(tune_cache).strip().splitlines()
+        for line in report[:-1]:  # the candidates' timings (none for a cached choice)
+            print(f"[bench] {name} {prec} autotune: {line}", file=sys.stderr, flush=True)
+        tune = report[-1]
     # the warm-up holds at least one whole graph, so that its capture is never
     # part of the timed steps
     warm = max(warmup, gs)
