@@ -625,6 +625,7 @@ def error_table(steps=100):
             row[f"{tag}T_{term}"] = rel(T.cpu().numpy().T, To)
 
     for name, w in cases:
+        print(f"[error-table] {name}: oracle, {steps} steps", file=sys.stderr, flush=True)
         stT = oracle.run(w, steps)
         for prec in ("fp64", "mixed"):
             sim = RodSim(w, precision=prec)
