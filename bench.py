@@ -192,6 +192,59 @@ def cpu_baseline(w, target_s=15.0):
             "cpu_model": model, "logical_cpus": ncpu}
 
 
+def oracle_timings():
+    """The FP64 oracle timed on the host cores, per workload, from its prepared
+    initial state: whole runs of the cantilever (1000 steps), the adjoint rod
+    (2000) and the twisted rod (20,000), and windows of the cilia carpet (10
+    steps) and the rod array (2 steps); then on one thread, with shorter
+    windows (the rod array left out). Steps run in chunks with a progress line
+    each. Reports seconds, particle-steps/s and ordered dipole pair evaluations
+    per second, with the thread count and the CPU model."""
+    import ctypes
+    import oracle
+    import workloads
+    lib = oracle._load()
+    lib.orc_threads.restype = ctypes.c_int
+    cores = int(lib.orc_threads())
+    plan = (("cantilever", 1000, 1000), ("adjoint_rod", 2000, 2000), ("twisted_rod", 20000, 200),
+            ("cilia_carpet", 10, 1), ("rod_array", 2, 0))
+    rows = []
+    try:
+        for threads in (cores, 1):
+            lib.orc_set_threads(threads)
+            for name, n_all, n_one in plan:
+                steps = n_all if threads == cores else n_one
+                if steps == 0:
+                    continue
+                w = workloads.make(name)
+                n = int(w["n"])
+                pairs = ordered_pairs(w) if w["dipole_on"] else 0
+                print(f"[oracle-timings] {name}: {threads} threads, preparing", file=sys.stderr,
+                      flush=True)
+                st = oracle.run(w, 0)
+                done, secs = 0, 0.0
+                chunk = 1
+                while done < steps:
+                    k = min(chunk, steps - done)
+                    t0 = time.perf_counter()
+                    st = oracle.run(w, k, state=st)
+                    dt = time.perf_counter() - t0
+                    done += k
+                    secs += dt
+                    # chunks of about 20 s between progress lines
+                    chunk = max(1, int(k * 20.0 / max(dt, 1e-6)))
+                    print(f"[oracle-timings] {name}: {done}/{steps} steps, {secs:.1f} s",
+                          file=sys.stderr, flush=True)
+                rows.append({"workload": name, "n_particles": n, "threads": threads,
+                             "steps": steps, "seconds": secs,
+                             "particle_steps_per_s": n * steps / secs,
+                             "dipole_pair_evals_per_s": pairs * steps / secs if pairs else None})
+    finally:
+        lib.orc_set_threads(cores)
+    model, ncpu = cpu_model()
+    return {"cpu_model": model, "logical_cpus": ncpu, "threads": cores, "rows": rows}
+
+
 def adjoint_leg():
     """Adjoint cost on the adjoint-rod workload (N = 256, T = 2000, checkpoints
     every 100): wall time of rod_grad against the taped forward run that
@@ -842,6 +895,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--oracle-timings", action="store_true",
+                    help="only time the FP64 oracle per workload on the host cores")
     ap.add_argument("--no-per-rod", action="store_true",
                     help="skip the per-rod loop comparison (multi-rod workloads)")
     ap.add_argument("--per-rod-steps", type=int, default=3)
@@ -877,6 +932,9 @@ def main():
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.oracle_timings:
+        print(json.dumps({"oracle_timings": oracle_timings()}))
         return
     if args.error_table:
         print(json.dumps({"error_table": error_table()}))
