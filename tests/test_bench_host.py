@@ -83,3 +83,27 @@ def test_member0_slices_the_first_ensemble_member():
     assert v["field"].shape == (w["field"].shape[0], 1, 12)
     np.testing.assert_array_equal(v["x0"], w["x0"][:50])
     np.testing.assert_array_equal(v["rod_params"], w["rod_params"][:1])
+
+
+def test_oracle_timings_rows_and_thread_restore(monkeypatch):
+    """--oracle-timings: one row per workload and thread count (the rod array on
+    all threads only), rates from the steps timed, and the oracle's thread count
+    set back afterwards. Every workload is replaced by the 20-particle
+    cantilever so that the test runs in seconds."""
+    import ctypes
+    import oracle
+    import workloads
+    monkeypatch.setattr(workloads, "make", lambda name, **kw: workloads.cantilever())
+    lib = oracle._load()
+    lib.orc_threads.restype = ctypes.c_int
+    before = int(lib.orc_threads())
+    r = bench.oracle_timings()
+    assert int(lib.orc_threads()) == before == r["threads"]
+    names = [(x["workload"], x["threads"]) for x in r["rows"]]
+    assert names[:5] == [(n, before) for n in ("cantilever", "adjoint_rod", "twisted_rod",
+                                               "cilia_carpet", "rod_array")]
+    assert ("rod_array", 1) not in names and len(names) == 9
+    for x in r["rows"]:
+        assert x["seconds"] > 0
+        assert x["particle_steps_per_s"] == pytest.approx(20 * x["steps"] / x["seconds"])
+        assert x["dipole_pair_evals_per_s"] == pytest.approx(380 * x["steps"] / x["seconds"])
