@@ -803,6 +803,8 @@ def workload_leg(name, prec, steps, warmup, graph_steps, timing_steps, per_rod_s
     kt_sep = None
     if separate:
         sim.launch_mode("separate")
+        sim.step(1)  # untimed: the separate kernels' first launch loads their code
+        sim.sync()
         sim.timing(True)
         sim.step(min(t_steps, 5))
         kt_sep = sim.kernel_times()
