@@ -55,6 +55,24 @@ def test_initial_level_per_term(case, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("kmax", [1, 2, 9])
+def test_short_reciprocal_rows(kmax, prec):
+    """Reciprocal tables whose rows of k vectors hold one to three vectors
+    (kmax 1 and 2: a few rows, fewer than the force pass's waves per block) and
+    rows just past one run of eight (kmax 9: up to 19 vectors) against the
+    oracle with the same truncation, per term and the field."""
+    w = workloads.periodic_rods(n_rods=8, length=16, kmax=kmax, seed=12)
+    sim = RodSim(w, precision=prec)
+    st = oracle.run(w, 0)
+    Fo, To, Bo = oracle.forces(w, st["x"], st["q"], st["v"], st["w"], mask=TERM_DIPOLE,
+                               with_field=True)
+    F, T, B = (a.cpu().numpy().T for a in sim.eval_forces(TERM_DIPOLE, with_field=True))
+    sim.free()
+    for a, b, name in ((F, Fo, "F"), (T, To, "T"), (B, Bo, "B")):
+        assert rel_inf(a, b) <= TOL[prec], (kmax, prec, name, rel_inf(a, b))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_trajectory_100_steps(prec):
     w = CASES["one_member"]()
     sim = RodSim(w, precision=prec, graph_steps=25)
