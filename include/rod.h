@@ -159,8 +159,10 @@ typedef struct rod_desc {
                                  ewald_kmax^2, weighted by (4 pi C / V) exp(-k^2/4a^2) / k^2 with
                                  a = ewald_alpha; the self field C 4 a^3 / (3 sqrt(pi)) m_i.
                                  Positions need not be wrapped into the box. The real-space
-                                 pair law is FP32 on the mixed path (separations, cutoff test,
-                                 reciprocal sum and self field FP64 on both paths); sums in a
+                                 pair law, the reciprocal phases (from FP64 arguments reduced
+                                 modulo 2 pi) and their per-thread sums are FP32 on the mixed
+                                 path (separations, cutoff test, the sums across lanes, chunks
+                                 and rows and the self field FP64 on both paths); sums in a
                                  fixed order (deterministic). Needs
                                  contact_on = 0 (contact is not periodic), dipole_cutoff = 0 and
                                  no tape (ROD_E_INVALID otherwise). The accuracy is the caller's

@@ -13,8 +13,10 @@
 //     B_i -= 2 (4 pi C / V) g(k) k Re[exp(i k.x_i) S*(k)],  g = exp(-k^2/4a^2)/k^2;
 //   self: B_i += C 4 a^3 / (3 sqrt(pi)) m_i.
 // The torque is m_i x B_i (in the particle kernels' gather) and the energy
-// -1/2 sum m_i.B_i. FP64, except the real-space pair law of the mixed path
-// (FP32, as that path's other pair arithmetic).
+// -1/2 sum m_i.B_i. FP64, except on the mixed path, which takes the real-space
+// pair law and the reciprocal phases and per-thread sums in FP32 (as that
+// path's other pair arithmetic), from FP64 separations and phase arguments,
+// with FP64 sums across lanes, chunks and rows.
 //
 // Data flow of one evaluation (all on one stream, no atomics in any sum; ten
 // launches):
@@ -321,6 +323,20 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
 // segment; the chunk's particles (at most EW_BLOCK sorted positions of one
 // member) with their rotation exp(i dkz z) staged in LDS and read as
 // broadcasts.
+// exp(i ph) as R: FP64 directly; FP32 from the argument reduced modulo 2 pi in
+// FP64 (|k.x| reaches a few hundred radians, where an FP32 argument alone
+// would lose 1e-5 of the phase).
+template <class R>
+__device__ __forceinline__ void ew_phase(double ph, R& sn, R& cs) {
+  if constexpr (sizeof(R) == 8) {
+    sincos(ph, &sn, &cs);
+  } else {
+    constexpr double two_pi = 6.283185307179586477, inv_two_pi = 0.15915494309189533577;
+    sincosf((float)(ph - two_pi * rint(ph * inv_two_pi)), &sn, &cs);
+  }
+}
+
+template <class R>
 __global__ __launch_bounds__(EW_BLOCK) void k_ew_sk(Dev d) {
   __shared__ double sx[8 * EW_BLOCK];
   const int K = d.ew_K;
@@ -342,23 +358,23 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_sk(Dev d) {
   const int k0 = d.ew_seg[2 * sg], nk = d.ew_seg[2 * sg + 1];
   const double* kv = d.ew_k + 4 * (long)k0;
   const double kx = kv[0], ky = kv[1], kz = kv[2], dkz = d.ew_dkz;
-  double Sr[EW_SEG], Si[EW_SEG];
+  R Sr[EW_SEG], Si[EW_SEG];
 #pragma unroll
-  for (int m = 0; m < EW_SEG; ++m) Sr[m] = Si[m] = 0.0;
+  for (int m = 0; m < EW_SEG; ++m) Sr[m] = Si[m] = R(0);
   const int n = e - b;
   for (int q = 0; q < n; ++q) {
     const double* r = sx + 8 * q;
-    double sn, cs;
-    sincos(kx * r[0] + ky * r[1] + kz * r[2], &sn, &cs);
-    double mk = kx * r[3] + ky * r[4] + kz * r[5];
-    const double dm = dkz * r[5], rc = r[6], rs = r[7];
+    R sn, cs;
+    ew_phase<R>(kx * r[0] + ky * r[1] + kz * r[2], sn, cs);
+    R mk = (R)(kx * r[3] + ky * r[4] + kz * r[5]);
+    const R dm = (R)(dkz * r[5]), rc = (R)r[6], rs = (R)r[7];
 #pragma unroll
     for (int m = 0; m < EW_SEG; ++m) {
       if (m < nk) {
         Sr[m] += mk * cs;
         Si[m] += mk * sn;
       }
-      const double c2 = cs * rc - sn * rs;
+      const R c2 = cs * rc - sn * rs;
       sn = sn * rc + cs * rs;
       cs = c2;
       mk += dm;
@@ -368,8 +384,8 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_sk(Dev d) {
 #pragma unroll
   for (int m = 0; m < EW_SEG; ++m)
     if (m < nk) {
-      o[2 * m] = Sr[m];
-      o[2 * m + 1] = Si[m];
+      o[2 * m] = (double)Sr[m];
+      o[2 * m + 1] = (double)Si[m];
     }
 }
 
@@ -402,6 +418,7 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_sreduce(Dev d) {
 constexpr int EW_KP = 64;  // particles per kspace block, one per lane
 constexpr int EW_KL = 8;   // waves per kspace block, each its own rows
 constexpr int EW_KBLOCK = EW_KP * EW_KL;
+template <class R>
 __global__ __launch_bounds__(EW_KBLOCK) void k_ew_kspace(Dev d) {
   __shared__ double red[6 * EW_KBLOCK];
   const long N = d.n;
@@ -418,9 +435,10 @@ __global__ __launch_bounds__(EW_KBLOCK) void k_ew_kspace(Dev d) {
     xi = V3<double>{rec[0], rec[1], rec[2]};
     mi = V3<double>{rec[4], rec[5], rec[6]};
   }
-  double rs, rc;
-  sincos(d.ew_dkz * xi.z, &rs, &rc);
-  const double mdz = mi.z * d.ew_dkz;
+  double rs_, rc_;
+  sincos(d.ew_dkz * xi.z, &rs_, &rc_);
+  const R rs = (R)rs_, rc = (R)rc_;
+  const R mdz = (R)(mi.z * d.ew_dkz);
   V3<double> F{0.0, 0.0, 0.0}, B{0.0, 0.0, 0.0};
   const double* S = d.ew_S + 2 * (long)mem * K;
   for (int rw = kl; rw < d.ew_ROWS; rw += EW_KL) {
@@ -428,35 +446,37 @@ __global__ __launch_bounds__(EW_KBLOCK) void k_ew_kspace(Dev d) {
     const double* kv = d.ew_k + 4 * (long)k0;
     const double* sk = S + 2 * (long)k0;
     const double kx = kv[0], ky = kv[1];
-    double mk = mi.x * kx + mi.y * ky + mi.z * kv[2];
-    double sn = 0.0, cs = 1.0;
+    R mk = (R)(mi.x * kx + mi.y * ky + mi.z * kv[2]);
+    R sn = R(0), cs = R(1);
     // sums along the row: a = m.k Im(conj(S) e^{ikx}) and g = Re(conj(S) e^{ikx}),
     // each also weighted by k_z
-    double A = 0.0, Az = 0.0, G = 0.0, Gz = 0.0;
+    R A = R(0), Az = R(0), G = R(0), Gz = R(0);
     for (int m = 0; m < nk; ++m) {
-      const double Sr = sk[2 * m], Si = sk[2 * m + 1], kzm = kv[4 * m + 2];
+      const R Sr = (R)sk[2 * m], Si = (R)sk[2 * m + 1];
+      const double kzd = kv[4 * m + 2];
+      const R kzm = (R)kzd;
       // the phase restarts where the structure factors' runs of EW_SEG start
       // (every EW_SEG vectors of a row), with the same operations, so that a
       // particle's own part of S(k) meets the same bits of exp(i k.x) and its
       // self term cancels to rounding
-      if (m % EW_SEG == 0) sincos(kx * xi.x + ky * xi.y + kzm * xi.z, &sn, &cs);
-      const double a = mk * (sn * Sr - cs * Si);
-      const double g = cs * Sr + sn * Si;
+      if (m % EW_SEG == 0) ew_phase<R>(kx * xi.x + ky * xi.y + kzd * xi.z, sn, cs);
+      const R a = mk * (sn * Sr - cs * Si);
+      const R g = cs * Sr + sn * Si;
       A += a;
       Az += a * kzm;
       G += g;
       Gz += g * kzm;
-      const double c2 = cs * rc - sn * rs;
+      const R c2 = cs * rc - sn * rs;
       sn = sn * rc + cs * rs;
       cs = c2;
       mk += mdz;
     }
-    F.x += kx * A;
-    F.y += ky * A;
-    F.z += Az;
-    B.x -= kx * G;
-    B.y -= ky * G;
-    B.z -= Gz;
+    F.x += kx * (double)A;
+    F.y += ky * (double)A;
+    F.z += (double)Az;
+    B.x -= kx * (double)G;
+    B.y -= ky * (double)G;
+    B.z -= (double)Gz;
   }
   double* o6 = red + 6 * threadIdx.x;
   o6[0] = F.x; o6[1] = F.y; o6[2] = F.z; o6[3] = B.x; o6[4] = B.y; o6[5] = B.z;
@@ -488,12 +508,19 @@ hipError_t launch_ewald(const Dev& d, const hipEvent_t* ev_real, hipStream_t s, 
     launch_k(ev_real, k_ew_real<float>, rg, dim3(EW_BLOCK), s, d);
   else
     launch_k(ev_real, k_ew_real<double>, rg, dim3(EW_BLOCK), s, d);
-  hipLaunchKernelGGL(k_ew_sk, dim3((unsigned)((d.ew_SEG + EW_BLOCK - 1) / EW_BLOCK), (unsigned)d.ew_TC),
-                     dim3(EW_BLOCK), 0, s, d);
+  const dim3 skg((unsigned)((d.ew_SEG + EW_BLOCK - 1) / EW_BLOCK), (unsigned)d.ew_TC);
+  if (d.muf)  // the mixed path: phases and per-thread sums in FP32
+    hipLaunchKernelGGL(k_ew_sk<float>, skg, dim3(EW_BLOCK), 0, s, d);
+  else
+    hipLaunchKernelGGL(k_ew_sk<double>, skg, dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_sreduce, dim3((unsigned)(((long)d.M * d.ew_K + EW_BLOCK - 1) / EW_BLOCK)),
                      dim3(EW_BLOCK), 0, s, d);
   static_assert(EW_CHUNK % EW_KP == 0, "kspace block shape");
-  hipLaunchKernelGGL(k_ew_kspace, dim3((unsigned)d.ew_TC, EW_CHUNK / EW_KP), dim3(EW_KBLOCK), 0, s, d);
+  const dim3 kg((unsigned)d.ew_TC, EW_CHUNK / EW_KP);
+  if (d.muf)
+    hipLaunchKernelGGL(k_ew_kspace<float>, kg, dim3(EW_KBLOCK), 0, s, d);
+  else
+    hipLaunchKernelGGL(k_ew_kspace<double>, kg, dim3(EW_KBLOCK), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev) return hipEventRecord(ev[1], s);
   return hipSuccess;

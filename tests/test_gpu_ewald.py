@@ -34,8 +34,8 @@ def test_initial_level_per_term(case, prec):
     assert np.any(w["x0"] < 0) or np.any(w["x0"] > w["box"])  # unwrapped positions
     sim = RodSim(w, precision=prec)
     st = oracle.run(w, 0)
-    # the real-space pair law is FP32 on the mixed path (the reciprocal sum and
-    # the self term FP64 on both)
+    # the real-space pair law and the reciprocal phases are FP32 on the mixed
+    # path (the sums across lanes, chunks and rows and the self term FP64 on both)
     Fo, To, Bo = oracle.forces(w, st["x"], st["q"], st["v"], st["w"], mask=TERM_DIPOLE,
                                with_field=True)
     F, T, B = sim.eval_forces(TERM_DIPOLE, with_field=True)
