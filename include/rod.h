@@ -161,9 +161,11 @@ typedef struct rod_desc {
                                  Positions need not be wrapped into the box. The real-space
                                  pair law, the reciprocal phases (from FP64 arguments reduced
                                  modulo 2 pi) and their per-thread sums are FP32 on the mixed
-                                 path (separations, cutoff test, the sums across lanes, chunks
-                                 and rows and the self field FP64 on both paths); sums in a
-                                 fixed order (deterministic). Needs
+                                 path, and so are its separations and cutoff test when every
+                                 axis holds at least seven cells of side >= rcut / 3 (taken
+                                 from the positions' offsets to their cells' centres); the
+                                 sums across lanes, chunks and rows and the self field are FP64
+                                 on both paths; sums in a fixed order (deterministic). Needs
                                  contact_on = 0 (contact is not periodic), dipole_cutoff = 0 and
                                  no tape (ROD_E_INVALID otherwise). The accuracy is the caller's
                                  choice of a, ewald_rcut and ewald_kmax: erfc(a rc) and

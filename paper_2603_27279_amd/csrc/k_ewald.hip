@@ -15,8 +15,10 @@
 // The torque is m_i x B_i (in the particle kernels' gather) and the energy
 // -1/2 sum m_i.B_i. FP64, except on the mixed path, which takes the real-space
 // pair law and the reciprocal phases and per-thread sums in FP32 (as that
-// path's other pair arithmetic), from FP64 separations and phase arguments,
-// with FP64 sums across lanes, chunks and rows.
+// path's other pair arithmetic), from FP64 phase arguments, with FP64 sums
+// across lanes, chunks and rows; its real-space separations and cutoff test
+// are FP32 from the positions' offsets to their cells' centres when every
+// axis is at least seven cells wide (FP64 by the minimum image otherwise).
 //
 // Data flow of one evaluation (all on one stream, no atomics in any sum; ten
 // launches):
@@ -130,6 +132,17 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_pack(Dev d) {
   o[5] = d.mu[N + i];
   o[6] = d.mu[2 * N + i];
   o[7] = 0.0;
+  if (d.ew_xf) {  // the mixed path's record: offset from the cell's centre, FP32
+    const int loc = d.ew_cell[i] % d.ew_ncell;
+    const int nx = d.ew_nc[0], ny = d.ew_nc[1];
+    const int cc[3] = {loc % nx, (loc / nx) % ny, loc / (nx * ny)};
+    float* f = d.ew_xf + 8 * p;
+    for (int a = 0; a < 3; ++a)
+      f[a] = (float)(o[a] - ((double)cc[a] + 0.5) * (d.box[a] / d.ew_nc[a]));
+    f[3] = 0.0f;
+    for (int a = 0; a < 3; ++a) f[4 + a] = d.muf[a * N + i];
+    f[7] = 0.0f;
+  }
 }
 
 // Neighbouring cell offsets along an axis of nc cells of side >= rc / EW_REACH:
@@ -148,7 +161,8 @@ __device__ __forceinline__ void ew_offsets(int nc, int& lo, int& hi) {
 // Real-space force and field: EW_RL lanes per sorted position, lane l taking
 // every EW_RL-th particle of each neighbouring cell; the lanes' sums are added
 // by a fixed xor tree, so the result does not depend on scheduling. The image
-// shift, the separation and the cutoff test are FP64 on both paths. The pair
+// shift, the separation and the cutoff test are FP64, except on the mixed path
+// with every axis wide (FP32 from cell offsets, below). The pair
 // law runs in R: FP64 with 1/r from the refined reciprocal square root, r =
 // r^2 / r (no FP64 square root or division per pair); on the mixed path FP32
 // from the separation rounded once (the pair arithmetic of that path), each
@@ -260,6 +274,48 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
   };
   // the walk, compiled once without the minimum image (every axis wide enough)
   // and once with it, so the common case carries no per-pair selects
+  // Mixed path, every axis wide: separations in FP32 from the offsets of the
+  // positions to their cells' centres, r = (o_i - o_j) - (cell offset) h, the
+  // cell part taken once per neighbouring cell (it holds the image shift).
+  // Each term is at most |r| + h and rounded once, so r carries a few ulp of
+  // |r| + h, the size of the FP32 pair arithmetic's own error; the cutoff test
+  // is then FP32 too.
+  if constexpr (sizeof(R) == 4) {
+    if (!(wx || wy || wz)) {
+      const float4 fi = pv ? *reinterpret_cast<const float4*>(d.ew_xf + 8 * pp)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float rc2f = (float)rc2;
+      for (int oz = lz; oz <= hz && pv; ++oz) {
+        const int uz = cz + oz, gz = (uz + nz) % nz;
+        const double gz2 = gap(xi.z, uz, hzs, false);
+        if (gz2 > reach2) continue;
+        const float dz = fi.z - (float)((double)oz * hzs);
+        for (int oy = ly; oy <= hy; ++oy) {
+          const int uy = cy + oy, gy = (uy + ny) % ny;
+          const double gyz2 = gz2 + gap(xi.y, uy, hys, false);
+          if (gyz2 > reach2) continue;
+          const float dy = fi.y - (float)((double)oy * hys);
+          for (int ox = lx; ox <= hx; ++ox) {
+            const int ux = cx + ox, gx = (ux + nx) % nx;
+            if (gyz2 + gap(xi.x, ux, hxs, false) > reach2) continue;
+            const float dx = fi.x - (float)((double)ox * hxs);
+            const int cc = mem * d.ew_ncell + (gz * ny + gy) * nx + gx;
+            const int qe = d.ew_start[cc + 1];
+            for (int q = d.ew_start[cc] + sub; q < qe; q += EW_RL) {
+              if (q == p) continue;
+              const float* rj = d.ew_xf + 8 * (long)q;
+              const float4 oj = *reinterpret_cast<const float4*>(rj);
+              const V3<float> r{dx - oj.x, dy - oj.y, dz - oj.z};
+              const float r2 = __builtin_fmaf(r.z, r.z, __builtin_fmaf(r.y, r.y, r.x * r.x));
+              if (!(r2 < rc2f)) continue;
+              const float4 mj = *reinterpret_cast<const float4*>(rj + 4);
+              ew_pair<float>(r, r2, miR, V3<float>{mj.x, mj.y, mj.z}, aR, spR, CR, FR, BR);
+            }
+          }
+        }
+      }
+    }
+  }
   auto walk = [&](auto narrow) {
     constexpr bool NW = decltype(narrow)::value;
     for (int oz = lz; oz <= hz && pv; ++oz) {
@@ -298,7 +354,7 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
   };
   if (wx || wy || wz)
     walk(std::true_type{});
-  else
+  else if constexpr (sizeof(R) == 8)
     walk(std::false_type{});
   V3<double> F = cvt<double>(FR), B = cvt<double>(BR);
 #pragma unroll

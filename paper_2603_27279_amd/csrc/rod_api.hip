@@ -563,6 +563,8 @@ static int ewald_setup(rod_ctx* c, const rod_desc* dsc, const std::vector<int>& 
   TRY(dalloc(c, &d.ew_tmp, (size_t)N));
   TRY(dalloc(c, &d.ew_sorted, (size_t)N));
   TRY(dalloc(c, &d.ew_xm, 8 * (size_t)N));
+  d.ew_xf = nullptr;
+  if (dsc->precision == ROD_MIXED) TRY(dalloc(c, &d.ew_xf, 8 * (size_t)N));
   TRY(dalloc(c, &kdev, kt.size()));
   TRY(dalloc(c, &chd, chunks.size()));
   TRY(dalloc(c, &cod, coff.size()));

@@ -159,6 +159,8 @@ struct Dev {
   int* ew_tmp;             // [N] particles grouped by cell in counting-slot order
   int* ew_sorted;          // [N] particles by cell, each cell's in ascending index
   double* ew_xm;           // [N][8] wrapped x, y, z, 0, m_x, m_y, m_z, 0 in sorted order
+  float* ew_xf;            // [N][8] mixed path: the position's offset from the centre of its
+                           // cell, 0, m_x, m_y, m_z, 0 (FP32) in sorted order; else NULL
   const double* ew_k;      // [K][4] k_x, k_y, k_z, 2 (4 pi C / V) exp(-k^2 / 4 a^2) / k^2
   int ew_K;
   const int* ew_seg;       // [SEG][2] first vector and count (<= EW_SEG) of runs along k_z

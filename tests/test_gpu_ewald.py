@@ -24,6 +24,10 @@ CASES = {
     "two_members": lambda: workloads.periodic_rods(n_rods=6, length=12, members=2, seed=9),
     # rcut = 3 in 14 x 16 x 18: 4 x 5 x 6 cells; rods reach out of the box
     "many_cells": lambda: workloads.periodic_rods(n_rods=10, length=14, rcut=3.0, seed=10),
+    # every axis at least seven cells wide (the walk without minimum images,
+    # FP32 separations from cell offsets on the mixed path), two members
+    "wide_two_members": lambda: workloads.periodic_rods(n_rods=6, length=12, members=2,
+                                                        rcut=3.0, seed=11),
 }
 
 
@@ -70,6 +74,48 @@ def test_short_reciprocal_rows(kmax, prec):
     sim.free()
     for a, b, name in ((F, Fo, "F"), (T, To, "T"), (B, Bo, "B")):
         assert rel_inf(a, b) <= TOL[prec], (kmax, prec, name, rel_inf(a, b))
+
+
+@pytest.fixture(scope="module")
+def bench_leg_reference():
+    """The periodic rods of the bench leg at full size (32 x 32 rods of 32
+    particles in a 64 x 64 x 40 box, rcut 16, 12 x 12 x 7 cells, 10,239
+    reciprocal vectors), with the parameters the leg uses, and the oracle's
+    dipole force, torque and field at the initial level (one evaluation, about
+    half a minute on the host)."""
+    import bench
+    w = workloads.rod_array(grid=(32, 32), n_per_rod=32, pitch=2.0, contact_on=False)
+    box, rcut = (64.0, 64.0, 40.0), 16.0
+    alpha = 3.6 / rcut
+    w.update(box=np.asarray(box, float), ewald_rcut=rcut, ewald_alpha=alpha,
+             ewald_kmax=int(np.ceil(3.6 * alpha * max(box) / np.pi)))
+    assert w["n"] == 32768 and bench.ewald_leg.__defaults__[:4] == (32, 32, box, rcut)
+    # the initial level as the library prepares it: unit quaternions; the
+    # dipole term reads only positions and orientations
+    q = np.asarray(w["q0"], dtype=np.float64)
+    q = q / np.linalg.norm(q, axis=1, keepdims=True)
+    x = np.asarray(w["x0"], dtype=np.float64)
+    z = np.zeros_like(x)
+    return w, oracle.forces(w, x, q, z, z, mask=TERM_DIPOLE, with_field=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_bench_leg_workload_full_size(prec, bench_leg_reference):
+    """The bench leg's workload at full size against the oracle: the dipole
+    force, torque and field of every particle, on the launch configuration the
+    leg times (wide cells: on the mixed path the FP32 cell-offset walk)."""
+    w, (Fo, To, Bo) = bench_leg_reference
+    sim = RodSim(w, precision=prec)
+    F, T, B = (a.cpu().numpy().T for a in sim.eval_forces(TERM_DIPOLE, with_field=True))
+    sim.free()
+    for a, b, name in ((F, Fo, "F"), (B, Bo, "B")):
+        assert rel_inf(a, b) <= TOL[prec], (prec, name, rel_inf(a, b))
+    # T = m x B: the rods' moments lie nearly along their own field, so the
+    # torque is a small part of |m| |B| and carries B's rounding at that scale;
+    # it is held to the bar relative to max(|T|, |m| |B|)
+    mB = np.max(np.linalg.norm(w["m_body"], axis=1)) * np.max(np.linalg.norm(Bo, axis=1))
+    assert rel_inf(T, To, mB) <= TOL[prec], (prec, "T", rel_inf(T, To, mB),
+                                             np.max(np.abs(To)) / mB)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
