@@ -33,7 +33,7 @@
 //            cells wide), their sums added by a fixed xor tree; writes F, B;
 //   sk:      partial structure factors of 256-particle chunks, one thread per
 //            segment of up to 8 k vectors along a row;
-//   sreduce: S(k) of each member, its chunks added in order;
+//   sreduce: S(k) of each member, its chunks added in a fixed order;
 //   kspace:  eight waves per 64 sorted positions, each wave its own rows of
 //            k vectors, their partial sums added in a fixed order; add to F, B.
 #include <type_traits>
@@ -445,22 +445,34 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_sk(Dev d) {
     }
 }
 
-// S(k) of every member: its chunks added in chunk order, times the vector's
-// weight (the only use of S(k) is weighted).
+// S(k) of every member from its chunks' partial sums, times the vector's
+// weight (the only use of S(k) is weighted): EW_SR lanes per (member, k), lane
+// l adding every EW_SR-th chunk in order, their sums added by a fixed xor tree.
+constexpr int EW_SR = 8;
 __global__ __launch_bounds__(EW_BLOCK) void k_ew_sreduce(Dev d) {
   const int K = d.ew_K;
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long)d.M * K) return;
-  const int m = (int)(t / K), kk = (int)(t % K);
+  const long u = t / EW_SR;
+  const int l = (int)(t % EW_SR);
+  const bool valid = u < (long)d.M * K;
+  const long uu = valid ? u : 0;
+  const int m = (int)(uu / K), kk = (int)(uu % K);
   double Sr = 0.0, Si = 0.0;
-  for (int ch = d.ew_chunk_off[m]; ch < d.ew_chunk_off[m + 1]; ++ch) {
-    const double* s = d.ew_Sp + 2 * ((long)ch * K + kk);
-    Sr += s[0];
-    Si += s[1];
+  if (valid)
+    for (int ch = d.ew_chunk_off[m] + l; ch < d.ew_chunk_off[m + 1]; ch += EW_SR) {
+      const double* s = d.ew_Sp + 2 * ((long)ch * K + kk);
+      Sr += s[0];
+      Si += s[1];
+    }
+#pragma unroll
+  for (int o = EW_SR / 2; o > 0; o >>= 1) {
+    Sr += __shfl_xor(Sr, o);
+    Si += __shfl_xor(Si, o);
   }
+  if (!valid || l != 0) return;
   const double c = d.ew_k[4 * (long)kk + 3];
-  d.ew_S[2 * t] = c * Sr;
-  d.ew_S[2 * t + 1] = c * Si;
+  d.ew_S[2 * uu] = c * Sr;
+  d.ew_S[2 * uu + 1] = c * Si;
 }
 
 // Reciprocal-space force and field. Block = 64 sorted positions of one chunk
@@ -569,7 +581,9 @@ hipError_t launch_ewald(const Dev& d, const hipEvent_t* ev_real, hipStream_t s, 
     hipLaunchKernelGGL(k_ew_sk<float>, skg, dim3(EW_BLOCK), 0, s, d);
   else
     hipLaunchKernelGGL(k_ew_sk<double>, skg, dim3(EW_BLOCK), 0, s, d);
-  hipLaunchKernelGGL(k_ew_sreduce, dim3((unsigned)(((long)d.M * d.ew_K + EW_BLOCK - 1) / EW_BLOCK)),
+  static_assert(EW_BLOCK % EW_SR == 0, "sreduce lane groups within a wave");
+  hipLaunchKernelGGL(k_ew_sreduce,
+                     dim3((unsigned)(((long)d.M * d.ew_K * EW_SR + EW_BLOCK - 1) / EW_BLOCK)),
                      dim3(EW_BLOCK), 0, s, d);
   static_assert(EW_CHUNK % EW_KP == 0, "kspace block shape");
   const dim3 kg((unsigned)d.ew_TC, EW_CHUNK / EW_KP);
