@@ -162,8 +162,9 @@ typedef struct rod_desc {
                                  pair law, the reciprocal phases (from FP64 arguments reduced
                                  modulo 2 pi) and their per-thread sums are FP32 on the mixed
                                  path, and so are its separations and cutoff test when every
-                                 axis holds at least seven cells of side >= rcut / 3 (taken
-                                 from the positions' offsets to their cells' centres); the
+                                 axis holds at least seven cells, of side rcut / 3 to rcut
+                                 (taken from the positions' offsets to their cells' centres);
+                                 the
                                  sums across lanes, chunks and rows and the self field are FP64
                                  on both paths; sums in a fixed order (deterministic). Needs
                                  contact_on = 0 (contact is not periodic), dipole_cutoff = 0 and

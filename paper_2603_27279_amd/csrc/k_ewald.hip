@@ -18,7 +18,8 @@
 // path's other pair arithmetic), from FP64 phase arguments, with FP64 sums
 // across lanes, chunks and rows; its real-space separations and cutoff test
 // are FP32 from the positions' offsets to their cells' centres when every
-// axis is at least seven cells wide (FP64 by the minimum image otherwise).
+// axis is at least seven cells wide and no cell is wider than rc (FP64
+// otherwise).
 //
 // Data flow of one evaluation (all on one stream, no atomics in any sum; ten
 // launches):
@@ -280,8 +281,14 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
   // Each term is at most |r| + h and rounded once, so r carries a few ulp of
   // |r| + h, the size of the FP32 pair arithmetic's own error; the cutoff test
   // is then FP32 too.
+  // (cells no wider than rc, as they are unless the per-axis cell count is
+  // capped in a box far larger than rc: the error then stays within a few ulp
+  // of |r| + 2 rc)
+  const double rc_ = d.ew_rc;
+  const bool f32walk = sizeof(R) == 4 && !(wx || wy || wz) && hxs <= rc_ && hys <= rc_ &&
+                       hzs <= rc_;
   if constexpr (sizeof(R) == 4) {
-    if (!(wx || wy || wz)) {
+    if (f32walk) {
       const float4 fi = pv ? *reinterpret_cast<const float4*>(d.ew_xf + 8 * pp)
                            : make_float4(0.f, 0.f, 0.f, 0.f);
       const float rc2f = (float)rc2;
@@ -354,7 +361,7 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
   };
   if (wx || wy || wz)
     walk(std::true_type{});
-  else if constexpr (sizeof(R) == 8)
+  else if (!f32walk)
     walk(std::false_type{});
   V3<double> F = cvt<double>(FR), B = cvt<double>(BR);
 #pragma unroll
