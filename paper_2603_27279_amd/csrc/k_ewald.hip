@@ -29,7 +29,7 @@
 //   scatter: particles grouped by cell; rank: each cell's particles by index
 //            (so the sums below run in a fixed order); pack: an interleaved
 //            copy of wrapped position and moment in sorted order;
-//   real:    16 lanes per sorted position walk the 7 x 7 x 7 neighbouring
+//   real:    8 (FP64: 16) lanes per sorted position walk the 7 x 7 x 7 neighbouring
 //            cells that come within rc (every cell of an axis under seven
 //            cells wide), their sums added by a fixed xor tree; writes F, B;
 //   sk:      partial structure factors of 256-particle chunks, one thread per
@@ -168,7 +168,10 @@ __device__ __forceinline__ void ew_offsets(int nc, int& lo, int& hi) {
 // r^2 / r (no FP64 square root or division per pair); on the mixed path FP32
 // from the separation rounded once (the pair arithmetic of that path), each
 // lane's sums in FP32 and their tree in FP64.
-constexpr int EW_RL = 16;
+// lanes per sorted position: 8 on the mixed path (FP32 walk; 16 lanes took
+// 0.75 ms per walk where 8 take 0.70), 16 on the FP64 path (2.82 against 2.95
+// ms per evaluation)
+template <class R> constexpr int ew_rl() { return sizeof(R) == 4 ? 8 : 16; }
 
 // erfc(x), x >= 0, on the mixed path: the Chebyshev-fitted form of Numerical
 // Recipes' erfcc, erfc(x) = t exp(-x^2 + P(t)) with t = 1 / (1 + x/2) and P of
@@ -232,6 +235,7 @@ __device__ __forceinline__ void ew_pair(V3<R> r, R r2, V3<R> mi, V3<R> mj, R a, 
 
 template <class R>
 __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
+  constexpr int EW_RL = ew_rl<R>();
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long p = t / EW_RL;
   const int sub = (int)(t % EW_RL);
@@ -578,11 +582,12 @@ hipError_t launch_ewald(const Dev& d, const hipEvent_t* ev_real, hipStream_t s, 
   hipLaunchKernelGGL(k_ew_scatter, dim3(pg), dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_rank, dim3(pg), dim3(EW_BLOCK), 0, s, d);
   hipLaunchKernelGGL(k_ew_pack, dim3(pg), dim3(EW_BLOCK), 0, s, d);
-  const dim3 rg((unsigned)((EW_RL * d.n + EW_BLOCK - 1) / EW_BLOCK));
   if (d.muf)  // the mixed path
-    launch_k(ev_real, k_ew_real<float>, rg, dim3(EW_BLOCK), s, d);
+    launch_k(ev_real, k_ew_real<float>,
+             dim3((unsigned)((ew_rl<float>() * d.n + EW_BLOCK - 1) / EW_BLOCK)), dim3(EW_BLOCK), s, d);
   else
-    launch_k(ev_real, k_ew_real<double>, rg, dim3(EW_BLOCK), s, d);
+    launch_k(ev_real, k_ew_real<double>,
+             dim3((unsigned)((ew_rl<double>() * d.n + EW_BLOCK - 1) / EW_BLOCK)), dim3(EW_BLOCK), s, d);
   const dim3 skg((unsigned)((d.ew_SEG + EW_BLOCK - 1) / EW_BLOCK), (unsigned)d.ew_TC);
   if (d.muf)  // the mixed path: phases and per-thread sums in FP32
     hipLaunchKernelGGL(k_ew_sk<float>, skg, dim3(EW_BLOCK), 0, s, d);
