@@ -277,8 +277,6 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
     const double g = w ? 0.0 : fmax(fmax((double)u * h - x, x - (double)(u + 1) * h), 0.0);
     return g * g;
   };
-  // the walk, compiled once without the minimum image (every axis wide enough)
-  // and once with it, so the common case carries no per-pair selects
   // Mixed path, every axis wide: separations in FP32 from the offsets of the
   // positions to their cells' centres, r = (o_i - o_j) - (cell offset) h, the
   // cell part taken once per neighbouring cell (it holds the image shift).
@@ -327,6 +325,8 @@ __global__ __launch_bounds__(EW_BLOCK) void k_ew_real(Dev d) {
       }
     }
   }
+  // The FP64 walk, compiled once without the minimum image (every axis wide
+  // enough) and once with it, so the common case carries no per-pair selects.
   auto walk = [&](auto narrow) {
     constexpr bool NW = decltype(narrow)::value;
     for (int oz = lz; oz <= hz && pv; ++oz) {
